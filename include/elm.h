@@ -1,0 +1,206 @@
+/*
+ * elm.h -- C ABI of libelm, an MI355X (gfx950) implementation of the training
+ * path of the rank-based pseudoinverse Extreme Learning Machine of Ragala &
+ * Kumar, "Rank Based Pseudoinverse Computation in Extreme Learning Machine
+ * for large Datasets" (arXiv 2011.02436).
+ *
+ * Problem (Section 2.1): N samples (x_i, t_i) in R^d x R^m, L hidden nodes with
+ * random weights w_j and biases b_j, hidden matrix H[i][j] = g(w_j . x_i + b_j)
+ * with g the logistic sigmoid (eqs. 1 and 4; Section 4 names the sigmoid),
+ * output weights beta = H^+ T (eqs. 3 and 5), prediction H beta (step 3 of
+ * the three-step ELM).  The rank step follows Section 3 (eq. 6, algorithm
+ * steps 3-4): a permutation P putting r = rank(H) independent columns first,
+ * H P = [H1 H2].  With H2 = H1 K the pseudoinverse is assembled from the
+ * full-rank factorisation H = F G, F = H1, G = [I K] P^T:
+ *   H^+ = G^T (G G^T)^-1 (F^T F)^-1 F^T,  F^T F = R11^T R11,  G G^T = I + K K^T,
+ * where R = [R11 R12] comes from a diagonally pivoted Cholesky of the Gram
+ * (eq. 8; H H^T instead of H^T H when N < L, as stated just before eq. 8).
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless the argument says "host".  The caller
+ *    owns every buffer passed in; the library owns handles, factors and its
+ *    internal workspace (allocated with hipMalloc, released by the matching
+ *    destroy call).
+ *  - Matrices are row-major with an explicit leading dimension (elements
+ *    between consecutive rows).  "Sample-major" H is N x L (row i = sample i,
+ *    ld >= L); "node-major" H is its transpose, L x N (row j = node j,
+ *    ld >= N).
+ *  - Work is enqueued on the handle's HIP stream and is asynchronous unless an
+ *    argument says the call synchronises.
+ *  - Arguments are validated before any device work; an invalid call returns
+ *    an error code and enqueues nothing.  Errors are reported only through the
+ *    return value (and elm_last_error for a message); nothing is thrown.
+ *  - Calls on one handle must not overlap from several host threads.
+ */
+#ifndef ELM_H
+#define ELM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ELM_OK = 0,
+    ELM_ERR_INVALID_ARG = 1,    /* null pointer, size <= 0, unknown enum, tolerance out of range */
+    ELM_ERR_SHAPE = 2,          /* leading dimension too small, or shapes that do not match */
+    ELM_ERR_ALLOC = 3,          /* device workspace allocation failed */
+    ELM_ERR_HIP = 4,            /* a HIP runtime call (launch, copy, synchronise) failed */
+    ELM_ERR_NOT_PSD = 5,        /* the Gram had a NaN/Inf diagonal (non-finite input) */
+    ELM_ERR_NO_CONVERGENCE = 6, /* refinement stopped above the requested residual */
+    ELM_ERR_UNSUPPORTED = 7     /* valid but not implemented combination of dtypes/layouts */
+} elm_status;
+
+typedef enum {
+    ELM_F64 = 0,
+    ELM_F32 = 1,
+    ELM_BF16 = 2,
+    ELM_F16 = 3
+} elm_dtype;
+
+typedef enum {
+    ELM_SAMPLE_MAJOR = 0, /* H is N x L, row = sample */
+    ELM_NODE_MAJOR = 1    /* H is L x N, row = hidden node */
+} elm_layout;
+
+typedef struct elm_handle elm_handle;
+typedef struct elm_factor elm_factor;
+
+/* Per-solve report (host struct, filled by elm_pinv_solve). */
+typedef struct {
+    int64_t rank;              /* r */
+    int32_t transposed;        /* 1 if the rank step used H H^T (N < L) */
+    int32_t iterations;        /* refinement corrections applied */
+    double ne_residual;        /* final ||H^T (T - H beta)||_F / ||H^T T||_F (FP64), -1 if not computed */
+    double ne_history[32];     /* residual before each correction (first `iterations`+1 entries) */
+} elm_solve_info;
+
+/* ------------------------------------------------------------------------ */
+/* Handle                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Create a handle bound to `stream` (a hipStream_t; NULL = the default
+ * stream) on the current HIP device.  *out receives a library-owned handle.
+ * Errors: INVALID_ARG if out is NULL; HIP if the device cannot be queried. */
+elm_status elm_create(elm_handle** out, void* stream);
+
+/* Destroy a handle and free its workspace (synchronises its stream).
+ * NULL is accepted and ignored. */
+elm_status elm_destroy(elm_handle* h);
+
+/* Rebind the handle to another stream (no synchronisation). */
+elm_status elm_set_stream(elm_handle* h, void* stream);
+
+/* Static description of a status code. */
+const char* elm_status_string(elm_status s);
+
+/* Message describing the last error returned on this handle ("" if none).
+ * The string stays valid until the next call on the handle. */
+const char* elm_last_error(const elm_handle* h);
+
+/* ------------------------------------------------------------------------ */
+/* Step 2 of the RBP-ELM algorithm: the hidden-layer matrix, eqs. (1), (4).   */
+/* ------------------------------------------------------------------------ */
+
+/* H[i][j] = 1 / (1 + exp(-(sum_k X[i][k] W[k][j] + b[j]))).
+ *
+ * X: N x d, ld ldx >= d.  W: d x L, ld ldw >= L.  b: L.  All of dtype `dt`,
+ * which is ELM_F64 or ELM_F32; the products are accumulated in `dt` and the
+ * sigmoid is evaluated in `dt`.
+ * H (optional, may be NULL): sample-major N x L of dtype `dt`, ld ldh >= L.
+ * Hlp (optional, may be NULL): node-major L x N copy, ld ldlp >= N, of dtype
+ *   lp_dt (ELM_BF16, ELM_F16 or ELM_F32), rounded to nearest even from the
+ *   same `dt` value written to H.  It feeds the low-precision Gram.
+ * At least one of H and Hlp must be non-NULL.  N, d, L >= 1. */
+elm_status elm_hidden(elm_handle* h, int64_t N, int64_t d, int64_t L,
+                      const void* X, int64_t ldx, const void* W, int64_t ldw,
+                      const void* b, elm_dtype dt,
+                      void* H, int64_t ldh,
+                      void* Hlp, int64_t ldlp, elm_dtype lp_dt);
+
+/* ------------------------------------------------------------------------ */
+/* Steps 3-4: permutation P and rank r (eq. 6), and the full-rank factor.     */
+/* ------------------------------------------------------------------------ */
+
+/* Factor the Gram of H: M = H^T H when N >= L, M = H H^T when N < L (n x n
+ * with n = min(N, L)).  Accepted inputs (dtype, layout):
+ *   (F64, SAMPLE_MAJOR)   FP64 Gram on FP64 MFMA (both orientations);
+ *   (F32, NODE_MAJOR)     FP32 Gram on FP32 MFMA, N >= L only;
+ *   (BF16|F16, NODE_MAJOR) 16-bit Gram on MFMA with FP32 accumulation, N >= L.
+ * The Gram is accumulated in a fixed order per element, so bitwise-equal
+ * columns of H give bitwise-equal Gram rows.  It is then widened to FP64 and
+ * factored in FP64 by a greedy diagonally pivoted Cholesky: at each step the
+ * pivot is the remaining index with the largest Schur-complement diagonal
+ * (lowest original index on exact ties); the factorisation stops when that
+ * diagonal is <= tau, tau = tau_rel * max_j M_jj, or n * 2^-53 * max_j M_jj
+ * when tau_rel <= 0 (tau_rel must be < 1).  Then K = R11^-1 R12 and the
+ * Cholesky factor of I + K K^T (or of I + K^T K when n - r < r, used through
+ * the Woodbury identity) are formed, all in FP64.
+ *
+ * *out receives a library-owned factor (free with elm_factor_destroy).
+ * rank (host, may be NULL) receives r.  This call synchronises the stream
+ * once (the rank sizes the later steps).
+ * Errors: INVALID_ARG / SHAPE / UNSUPPORTED as above; NOT_PSD if the Gram has
+ * a non-finite diagonal; ALLOC; HIP. */
+elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L,
+                           const void* H, int64_t ldh, elm_dtype h_dt, elm_layout layout,
+                           double tau_rel, elm_factor** out, int64_t* rank);
+
+/* r of a factor (host read, no synchronisation needed). */
+elm_status elm_factor_rank(const elm_factor* f, int64_t* rank);
+
+/* Copy the pivot order (original index at each pivoted position, first r
+ * entries independent) into host array piv_host[n]; n = min(N, L).
+ * Synchronises the handle's stream. */
+elm_status elm_factor_pivots(elm_handle* h, const elm_factor* f, int32_t* piv_host);
+
+/* Free a factor.  NULL is accepted. */
+elm_status elm_factor_destroy(elm_factor* f);
+
+/* ------------------------------------------------------------------------ */
+/* Steps 5-9: beta = H^+ T (eqs. 5, 7) from the factor, with optional FP64   */
+/* refinement on the normal-equation residual.                               */
+/* ------------------------------------------------------------------------ */
+
+/* T: N x m sample-major FP64 targets, ld ldt >= m (one-hot rows for
+ * classification).  H64: the FP64 sample-major hidden matrix (N x L, ld
+ * ldh64 >= L) that beta is the least-squares solution for; it supplies
+ * H^T T and the refinement residuals.  beta: L x m FP64 output, ld ldbeta
+ * >= m.  1 <= m <= 64.
+ *
+ * beta_0 = H^+ T through the factor; then, while the relative normal-equation
+ * residual ||H^T (T - H beta)||_F / ||H^T T||_F exceeds ir_tol and fewer
+ * than ir_max_iter corrections were made, beta += H^+ (T - H beta) with H^+
+ * applied through the (possibly low-precision-derived) factor.  ir_max_iter
+ * = 0 gives beta_0 and skips the residual.  ir_tol must be in [0, 1).
+ * info (host, may be NULL) receives rank, iterations and residuals.
+ * Synchronises once per refinement iteration.
+ * Errors: NO_CONVERGENCE if ir_max_iter > 0 and the final residual is above
+ * ir_tol (beta then holds the last iterate); INVALID_ARG; SHAPE; ALLOC; HIP. */
+elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m,
+                          const double* T, int64_t ldt,
+                          const double* H64, int64_t ldh64,
+                          double ir_tol, int32_t ir_max_iter,
+                          double* beta, int64_t ldbeta, elm_solve_info* info);
+
+/* ------------------------------------------------------------------------ */
+/* Step 3 of the three-step ELM: prediction Y = H beta, label = argmax.      */
+/* ------------------------------------------------------------------------ */
+
+/* Y = sigma(X W + b) beta without storing H.  X, W, b as for elm_hidden
+ * (dtype dt, F64 or F32); beta: L x m FP64, ld ldbeta >= m (converted to dt).
+ * Y (optional): N x m of dtype dt, ld ldy >= m.  labels (optional): N int32,
+ * index of the largest output of each row (lowest index on ties).  At least
+ * one of Y and labels must be non-NULL.  1 <= m <= 64. */
+elm_status elm_predict(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m,
+                       const void* X, int64_t ldx, const void* W, int64_t ldw,
+                       const void* b, elm_dtype dt,
+                       const double* beta, int64_t ldbeta,
+                       void* Y, int64_t ldy, int32_t* labels);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELM_H */

@@ -1,0 +1,362 @@
+// C entry points of libelm (declared and documented in include/elm.h):
+// argument validation, workspace, stream handling and the refinement loop.
+// All device work is in the kernels of the other translation units.
+#include "elm_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+
+namespace elm {
+
+void* Workspace::get(const std::string& name, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    for (auto& kv : bufs) {
+        if (kv.first == name) {
+            if (kv.second.bytes >= bytes) return kv.second.ptr;
+            // grow: hipFree waits for pending work on the buffer
+            ELM_HIP_TRY(hipFree(kv.second.ptr));
+            kv.second.ptr = nullptr;
+            kv.second.bytes = 0;
+            void* p = nullptr;
+            if (hipMalloc(&p, bytes) != hipSuccess)
+                throw Error{ELM_ERR_ALLOC, "workspace '" + name + "': hipMalloc of " +
+                                               std::to_string(bytes) + " bytes failed"};
+            kv.second.ptr = p;
+            kv.second.bytes = bytes;
+            return p;
+        }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess)
+        throw Error{ELM_ERR_ALLOC,
+                    "workspace '" + name + "': hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    bufs.push_back({name, Buffer{p, bytes}});
+    return p;
+}
+
+void Workspace::release() {
+    for (auto& kv : bufs)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    bufs.clear();
+}
+
+namespace {
+
+thread_local std::string g_create_error;
+
+elm_status fail(elm_handle* h, elm_status st, const std::string& msg) {
+    if (h) h->last_error = msg;
+    return st;
+}
+
+// Runs `body` and turns exceptions into status codes.  Bodies validate every
+// argument first (pure host checks) and call use_device() before any HIP call.
+template <typename F>
+elm_status guarded(elm_handle* h, F&& body) {
+    try {
+        if (h) h->last_error.clear();
+        body();
+        return ELM_OK;
+    } catch (const Error& e) {
+        return fail(h, e.st, e.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(h, ELM_ERR_ALLOC, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(h, ELM_ERR_HIP, e.what());
+    }
+}
+
+void use_device(elm_handle* h) { ELM_HIP_TRY(hipSetDevice(h->device)); }
+
+#define REQUIRE(cond, st, msg) \
+    do {                       \
+        if (!(cond)) throw ::elm::Error{st, msg}; \
+    } while (0)
+
+size_t dtype_size(elm_dtype dt) {
+    switch (dt) {
+        case ELM_F64: return 8;
+        case ELM_F32: return 4;
+        case ELM_BF16: return 2;
+        case ELM_F16: return 2;
+    }
+    return 0;
+}
+
+void free_factor_buffers(elm_factor* f) {
+    if (!f) return;
+    if (f->piv) (void)hipFree(f->piv);
+    if (f->R) (void)hipFree(f->R);
+    if (f->Rinv) (void)hipFree(f->Rinv);
+    if (f->K) (void)hipFree(f->K);
+    if (f->Usinv) (void)hipFree(f->Usinv);
+    f->piv = nullptr;
+    f->R = f->Rinv = f->K = f->Usinv = nullptr;
+}
+
+}  // namespace
+}  // namespace elm
+
+using elm::Error;
+
+extern "C" {
+
+elm_status elm_create(elm_handle** out, void* stream) {
+    if (!out) return ELM_ERR_INVALID_ARG;
+    *out = nullptr;
+    elm_handle* h = nullptr;
+    try {
+        h = new elm_handle();
+        h->stream = (hipStream_t)stream;
+        if (hipGetDevice(&h->device) != hipSuccess) {
+            delete h;
+            return ELM_ERR_HIP;
+        }
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+            cu > 0)
+            h->num_cu = cu;
+    } catch (...) {
+        delete h;
+        return ELM_ERR_ALLOC;
+    }
+    *out = h;
+    return ELM_OK;
+}
+
+elm_status elm_destroy(elm_handle* h) {
+    if (!h) return ELM_OK;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    h->ws.release();
+    delete h;
+    return ELM_OK;
+}
+
+elm_status elm_set_stream(elm_handle* h, void* stream) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    h->stream = (hipStream_t)stream;
+    return ELM_OK;
+}
+
+const char* elm_status_string(elm_status s) {
+    switch (s) {
+        case ELM_OK: return "ok";
+        case ELM_ERR_INVALID_ARG: return "invalid argument";
+        case ELM_ERR_SHAPE: return "inconsistent shape or leading dimension";
+        case ELM_ERR_ALLOC: return "device allocation failed";
+        case ELM_ERR_HIP: return "HIP runtime error";
+        case ELM_ERR_NOT_PSD: return "Gram matrix not positive semidefinite (non-finite input)";
+        case ELM_ERR_NO_CONVERGENCE: return "refinement did not reach the requested residual";
+        case ELM_ERR_UNSUPPORTED: return "unsupported dtype/layout combination";
+    }
+    return "unknown status";
+}
+
+const char* elm_last_error(const elm_handle* h) { return h ? h->last_error.c_str() : ""; }
+
+elm_status elm_hidden(elm_handle* h, int64_t N, int64_t d, int64_t L, const void* X, int64_t ldx,
+                      const void* W, int64_t ldw, const void* b, elm_dtype dt, void* H, int64_t ldh,
+                      void* Hlp, int64_t ldlp, elm_dtype lp_dt) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(N >= 1 && d >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N, d and L must be >= 1");
+        REQUIRE(X && W && b, ELM_ERR_INVALID_ARG, "X, W and b must be non-null");
+        REQUIRE(dt == ELM_F64 || dt == ELM_F32, ELM_ERR_UNSUPPORTED, "dt must be ELM_F64 or ELM_F32");
+        REQUIRE(H || Hlp, ELM_ERR_INVALID_ARG, "at least one of H and Hlp must be non-null");
+        REQUIRE(ldx >= d, ELM_ERR_SHAPE, "ldx < d");
+        REQUIRE(ldw >= L, ELM_ERR_SHAPE, "ldw < L");
+        if (H) REQUIRE(ldh >= L, ELM_ERR_SHAPE, "ldh < L");
+        if (Hlp) {
+            REQUIRE(lp_dt == ELM_BF16 || lp_dt == ELM_F16 || lp_dt == ELM_F32, ELM_ERR_UNSUPPORTED,
+                    "lp_dt must be ELM_BF16, ELM_F16 or ELM_F32");
+            REQUIRE(ldlp >= N, ELM_ERR_SHAPE, "ldlp < N");
+        }
+        elm::use_device(h);
+        elm::launch_hidden(h->stream, dt, N, d, L, X, ldx, W, ldw, b, H, ldh, Hlp, ldlp, lp_dt);
+    });
+}
+
+elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
+                           elm_dtype h_dt, elm_layout layout, double tau_rel, elm_factor** out,
+                           int64_t* rank) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    elm_factor* f = nullptr;
+    elm_status st = elm::guarded(h, [&] {
+        REQUIRE(out, ELM_ERR_INVALID_ARG, "out must be non-null");
+        *out = nullptr;
+        REQUIRE(N >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N and L must be >= 1");
+        REQUIRE(H, ELM_ERR_INVALID_ARG, "H must be non-null");
+        REQUIRE(tau_rel < 1.0 && !std::isnan(tau_rel), ELM_ERR_INVALID_ARG, "tau_rel must be < 1");
+        REQUIRE(layout == ELM_SAMPLE_MAJOR || layout == ELM_NODE_MAJOR, ELM_ERR_INVALID_ARG,
+                "unknown layout");
+        REQUIRE(h_dt == ELM_F64 || h_dt == ELM_F32 || h_dt == ELM_BF16 || h_dt == ELM_F16,
+                ELM_ERR_INVALID_ARG, "unknown dtype");
+        REQUIRE(ldh >= (layout == ELM_SAMPLE_MAJOR ? L : N), ELM_ERR_SHAPE,
+                "ldh smaller than the row length");
+        const bool transposed = N < L;
+        if (h_dt == ELM_F64)
+            REQUIRE(layout == ELM_SAMPLE_MAJOR, ELM_ERR_UNSUPPORTED, "FP64 H must be sample-major");
+        else
+            REQUIRE(layout == ELM_NODE_MAJOR && !transposed, ELM_ERR_UNSUPPORTED,
+                    "low-precision H must be node-major, with N >= L");
+        const int64_t n = transposed ? N : L;
+        elm::use_device(h);
+        f = new elm_factor();
+        f->N = N;
+        f->L = L;
+        f->n = n;
+        f->transposed = transposed;
+        f->device = h->device;
+        double* M = (double*)h->ws.get("gram_M", (size_t)n * n * sizeof(double));
+        if (h_dt == ELM_F64) {
+            if (transposed)
+                elm::launch_gram_f64_rows(h->stream, N, L, (const double*)H, ldh, M, n, h->ws);
+            else
+                elm::launch_gram_f64_cols(h->stream, N, L, (const double*)H, ldh, M, n, h->ws);
+        } else {
+            elm::launch_gram_lp_nodes(h->stream, h_dt, N, L, H, ldh, M, n, h->ws);
+        }
+        // tau from the largest diagonal entry (read back once)
+        double* dmax = (double*)h->ws.get("gram_dmax", sizeof(double));
+        elm::launch_diag_max(h->stream, n, M, n, dmax);
+        double hdmax = 0;
+        ELM_HIP_TRY(hipMemcpyAsync(&hdmax, dmax, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        ELM_HIP_TRY(hipStreamSynchronize(h->stream));
+        if (!std::isfinite(hdmax)) throw Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
+        f->tau = (tau_rel > 0 ? tau_rel : (double)n * std::ldexp(1.0, -53)) * hdmax;
+        ELM_HIP_TRY(hipMalloc(&f->piv, (size_t)n * sizeof(int32_t)));
+        f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, h->ws);
+        elm::build_factor_tail(h->stream, f, h->ws);
+        if (rank) *rank = f->r;
+        *out = f;
+    });
+    if (st != ELM_OK && f) {
+        elm::free_factor_buffers(f);
+        delete f;
+    }
+    return st;
+}
+
+elm_status elm_factor_rank(const elm_factor* f, int64_t* rank) {
+    if (!f || !rank) return ELM_ERR_INVALID_ARG;
+    *rank = f->r;
+    return ELM_OK;
+}
+
+elm_status elm_factor_pivots(elm_handle* h, const elm_factor* f, int32_t* piv_host) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(f && piv_host, ELM_ERR_INVALID_ARG, "factor and piv_host must be non-null");
+        elm::use_device(h);
+        ELM_HIP_TRY(hipMemcpyAsync(piv_host, f->piv, (size_t)f->n * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, h->stream));
+        ELM_HIP_TRY(hipStreamSynchronize(h->stream));
+    });
+}
+
+elm_status elm_factor_destroy(elm_factor* f) {
+    if (!f) return ELM_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(f->device);
+    (void)hipDeviceSynchronize();
+    elm::free_factor_buffers(f);
+    (void)hipSetDevice(cur);
+    delete f;
+    return ELM_OK;
+}
+
+elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const double* T, int64_t ldt,
+                          const double* H64, int64_t ldh64, double ir_tol, int32_t ir_max_iter,
+                          double* beta, int64_t ldbeta, elm_solve_info* info) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    elm_status result = ELM_OK;
+    elm_status st = elm::guarded(h, [&] {
+        REQUIRE(f, ELM_ERR_INVALID_ARG, "factor must be non-null");
+        REQUIRE(m >= 1 && m <= 64, ELM_ERR_INVALID_ARG, "m must be in [1, 64]");
+        REQUIRE(T && H64 && beta, ELM_ERR_INVALID_ARG, "T, H64 and beta must be non-null");
+        REQUIRE(ldt >= m && ldbeta >= m, ELM_ERR_SHAPE, "ldt or ldbeta smaller than m");
+        REQUIRE(ldh64 >= f->L, ELM_ERR_SHAPE, "ldh64 < L");
+        REQUIRE(ir_tol >= 0.0 && ir_tol < 1.0, ELM_ERR_INVALID_ARG, "ir_tol must be in [0, 1)");
+        REQUIRE(ir_max_iter >= 0 && ir_max_iter <= 31, ELM_ERR_INVALID_ARG,
+                "ir_max_iter must be in [0, 31]");
+        const int64_t N = f->N, L = f->L;
+        elm::use_device(h);
+        hipStream_t s = h->stream;
+        elm::Workspace& ws = h->ws;
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->rank = f->r;
+            info->transposed = f->transposed ? 1 : 0;
+            info->ne_residual = -1.0;
+        }
+        double* Z = (double*)ws.get("ps_Z", (size_t)L * m * sizeof(double));
+        double* nrm = (double*)ws.get("ps_nrm", 2 * sizeof(double));
+        // beta_0 = H^+ T
+        if (!f->transposed) {
+            elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);   // H^T T, eq. (8)
+            elm::apply_pinv(s, f, m, Z, m, H64, ldh64, beta, ldbeta, ws);
+        } else {
+            elm::apply_pinv(s, f, m, T, ldt, H64, ldh64, beta, ldbeta, ws);
+        }
+        if (ir_max_iter == 0) {
+            ELM_HIP_TRY(hipStreamSynchronize(s));
+            return;
+        }
+        if (f->transposed) elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);
+        double z2 = 0;
+        ELM_HIP_TRY(hipMemcpyAsync(&z2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+        double* E = (double*)ws.get("ps_E", (size_t)N * m * sizeof(double));
+        double* G = (double*)ws.get("ps_G", (size_t)L * m * sizeof(double));
+        double* D = (double*)ws.get("ps_D", (size_t)L * m * sizeof(double));
+        double res = 0;
+        int it = 0;
+        for (;;) {
+            elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m);   // T - H beta
+            elm::launch_ht_times(s, N, L, m, H64, ldh64, E, m, G, m, nrm + 1, ws);     // H^T (T - H beta)
+            double g2 = 0;
+            ELM_HIP_TRY(hipMemcpyAsync(&g2, nrm + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+            ELM_HIP_TRY(hipStreamSynchronize(s));
+            res = z2 > 0 ? std::sqrt(g2 / z2) : std::sqrt(g2);
+            if (info && it < 32) info->ne_history[it] = res;
+            if (!(res > ir_tol) || it >= ir_max_iter) break;
+            if (!f->transposed)
+                elm::apply_pinv(s, f, m, G, m, H64, ldh64, D, m, ws);
+            else
+                elm::apply_pinv(s, f, m, E, m, H64, ldh64, D, m, ws);
+            elm::launch_axpy_mat(s, L, m, D, m, beta, ldbeta);
+            ++it;
+        }
+        if (info) {
+            info->iterations = it;
+            info->ne_residual = res;
+        }
+        if (res > ir_tol) result = ELM_ERR_NO_CONVERGENCE;
+    });
+    if (st != ELM_OK) return st;
+    if (result != ELM_OK) h->last_error = "refinement stopped above ir_tol";
+    return result;
+}
+
+elm_status elm_predict(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, const void* X,
+                       int64_t ldx, const void* W, int64_t ldw, const void* b, elm_dtype dt,
+                       const double* beta, int64_t ldbeta, void* Y, int64_t ldy, int32_t* labels) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(N >= 1 && d >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N, d and L must be >= 1");
+        REQUIRE(m >= 1 && m <= 64, ELM_ERR_INVALID_ARG, "m must be in [1, 64]");
+        REQUIRE(X && W && b && beta, ELM_ERR_INVALID_ARG, "X, W, b and beta must be non-null");
+        REQUIRE(Y || labels, ELM_ERR_INVALID_ARG, "at least one of Y and labels must be non-null");
+        REQUIRE(dt == ELM_F64 || dt == ELM_F32, ELM_ERR_UNSUPPORTED, "dt must be ELM_F64 or ELM_F32");
+        REQUIRE(ldx >= d && ldw >= L && ldbeta >= m, ELM_ERR_SHAPE, "leading dimension too small");
+        if (Y) REQUIRE(ldy >= m, ELM_ERR_SHAPE, "ldy < m");
+        elm::use_device(h);
+        elm::launch_predict(h->stream, dt, N, d, L, m, X, ldx, W, ldw, b, beta, ldbeta, Y, ldy,
+                            labels, h->ws);
+    });
+}
+
+}  // extern "C"

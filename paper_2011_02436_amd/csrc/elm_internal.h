@@ -1,0 +1,165 @@
+// Internal declarations shared by the libelm translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/elm.h"
+
+namespace elm {
+
+// ---------------------------------------------------------------------------
+// vector types used by the MFMA builtins
+// ---------------------------------------------------------------------------
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// 16 x 16 x 4 MFMA with one element per lane for A (16 x 4) and B (4 x 16):
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].  The 16 x 16 result
+// sits in 4 registers per lane; row(l, v) is the row of register v of lane l,
+// the column is l % 16.  The FP64 and FP32 instructions place rows
+// differently (measured on gfx950).
+// ---------------------------------------------------------------------------
+template <typename T> struct Mfma16;
+template <> struct Mfma16<double> {
+    typedef d4v acc_t;
+    static __device__ inline acc_t op(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <> struct Mfma16<float> {
+    typedef f4v acc_t;
+    static __device__ inline acc_t op(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+struct Error {
+    elm_status st;
+    std::string msg;
+};
+
+#define ELM_HIP_TRY(expr)                                                             \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            throw ::elm::Error{ELM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define ELM_LAUNCH_CHECK() ELM_HIP_TRY(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// workspace arena: grow-only named device buffers owned by a handle
+// ---------------------------------------------------------------------------
+struct Buffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Workspace {
+    std::vector<std::pair<std::string, Buffer>> bufs;
+    void* get(const std::string& name, size_t bytes);
+    void release();
+};
+
+}  // namespace elm
+
+struct elm_handle {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int num_cu = 256;
+    elm::Workspace ws;
+    std::string last_error;
+};
+
+struct elm_factor {
+    int64_t N = 0, L = 0;     // shape of H
+    int64_t n = 0;            // order of the Gram: min(N, L)
+    int64_t r = 0;            // rank
+    bool transposed = false;  // the Gram is H H^T (N < L)
+    double tau = 0;           // absolute stopping threshold of the pivoted Cholesky
+    // device buffers owned by the factor (hipMalloc'd)
+    int32_t* piv = nullptr;   // n: original index at each pivoted position
+    double* R = nullptr;      // r x n, pivot order, ld n: [R11 R12]
+    double* Rinv = nullptr;   // r x r, ld r: R11^-1 (upper triangular)
+    double* K = nullptr;      // r x (n - r), ld n - r: K = R11^-1 R12
+    double* Usinv = nullptr;  // q x q, ld q: Us^-1 where Us^T Us = I + K K^T (q = r)
+                              // or I + K^T K (q = n - r, woodbury)
+    int64_t q = 0;
+    bool woodbury = false;
+    int device = 0;
+};
+
+namespace elm {
+
+// ---------------------------------------------------------------------------
+// kernel launchers (each .hip file owns its kernels)
+// ---------------------------------------------------------------------------
+
+// hidden.hip: H = sigmoid(X W + b), sample-major H and/or node-major low-precision copy
+void launch_hidden(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L,
+                   const void* X, int64_t ldx, const void* W, int64_t ldw, const void* b,
+                   void* H, int64_t ldh, void* Hlp, int64_t ldlp, elm_dtype lp_dt);
+
+// gram.hip: M (n x n FP64, full symmetric, ld = ldm)
+//   column Gram  M = H^T H  of sample-major FP64 H (N x L)
+void launch_gram_f64_cols(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
+                          double* M, int64_t ldm, Workspace& ws);
+//   row Gram     M = H H^T  of sample-major FP64 H (N x L, N < L)
+void launch_gram_f64_rows(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
+                          double* M, int64_t ldm, Workspace& ws);
+//   column Gram of a node-major low-precision copy (L x N): M = Hn Hn^T
+void launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
+                          int64_t ldn, double* M, int64_t ldm, Workspace& ws);
+//   *out = max_i M[i][i]  (NaN if any diagonal entry is NaN)
+void launch_diag_max(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
+
+// pchol.hip: greedy pivoted Cholesky of M (n x n FP64, full symmetric, ld = ldm).
+// Writes piv (n), allocates *R_out = R (r x n in pivot order, ld n, hipMalloc'd,
+// NULL when r = 0) and returns r (synchronises the stream once).
+int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double tau,
+                         int32_t* piv, double** R_out, Workspace& ws);
+void launch_fill(hipStream_t s, double* p, int64_t count, double v);
+
+// solve.hip: dense FP64 helpers for the factor and the pseudoinverse apply
+void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws);
+void apply_pinv(hipStream_t s, const elm_factor* f, int64_t m, const double* rhs, int64_t ldr,
+                const double* H64, int64_t ldh64, double* out, int64_t ldo, Workspace& ws);
+
+// refine.hip: streaming FP64 passes over sample-major H
+//   E = T - H beta  (N x m)
+void launch_residual(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
+                     const double* T, int64_t ldt, const double* beta, int64_t ldb, double* E,
+                     int64_t lde);
+//   G = H^T E  (L x m), deterministic two-stage reduction; also writes ||G||_F^2 to *nrm2
+void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
+                     const double* E, int64_t lde, double* G, int64_t ldg, double* nrm2,
+                     Workspace& ws);
+//   beta += delta, elementwise over L x m
+void launch_axpy_mat(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx,
+                     double* Y, int64_t ldy);
+
+// predict.hip
+void launch_predict(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L, int64_t m,
+                    const void* X, int64_t ldx, const void* W, int64_t ldw, const void* b,
+                    const double* beta, int64_t ldbeta, void* Y, int64_t ldy, int32_t* labels,
+                    Workspace& ws);
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace elm

@@ -1,0 +1,313 @@
+// Gram of the hidden matrix for the normal equations, eq. (8):
+//   M = H^T H (L x L) when N >= L, M = H H^T (N x N) when N < L (the two
+//   pseudoinverse forms stated before eq. 8).  Only the upper block triangle
+//   is computed; each value is written to both (i, j) and (j, i), so M is
+//   exactly symmetric.
+//
+// Every element is accumulated in one fixed order (tile k-loop, then a
+// fixed-order FP64 sum over split-K chunks; no atomics), so bitwise-equal
+// columns of H give bitwise-equal rows of M.  The pivoted Cholesky relies on
+// that to send the Schur diagonal of a duplicated hidden node to ~0.
+//
+// Kernels:
+//   gram16_kernel<T, KCONTIG>  FP64 or FP32, 16x16x4 MFMA, 128 x 128 tiles.
+//     KCONTIG=false: operand element (row, k) at base[k*ld + row] (columns of
+//       a sample-major H: the column Gram H^T H).
+//     KCONTIG=true:  element (row, k) at base[row*ld + k] (rows of a
+//       sample-major H for H H^T, or a node-major copy for H^T H).
+//   gram_lp_kernel<HT>  BF16 or FP16 node-major copy, 32x32x16 MFMA with FP32
+//     accumulation, 128 x 128 tiles.
+//   gram_reduce_kernel  sums the split-K partial tiles in FP64 and mirrors.
+#include "elm_internal.h"
+
+#include <cmath>
+
+namespace elm {
+namespace {
+
+constexpr int TILE = 128;
+constexpr int NT = 256;  // 4 waves in a 2 x 2 grid of 64 x 64 sub-tiles
+
+// upper-triangular tile index t -> (bi, bj), bi <= bj, column-major over bj
+__device__ inline void tile_coords(int64_t t, int& bi, int& bj) {
+    int64_t c = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (c * (c + 1) / 2 > t) --c;
+    while ((c + 1) * (c + 2) / 2 <= t) ++c;
+    bj = (int)c;
+    bi = (int)(t - c * (c + 1) / 2);
+}
+
+template <typename T, bool KCONTIG>
+__global__ __launch_bounds__(NT) void gram16_kernel(int64_t n, int64_t K, int64_t kc_len,
+                                                    const T* __restrict__ A, int64_t ld,
+                                                    T* __restrict__ part, int64_t ntile) {
+    constexpr int BK = 16;
+    __shared__ T As[BK][TILE + 1];
+    __shared__ T Bs[BK][TILE + 1];
+
+    int bi, bj;
+    tile_coords(blockIdx.x, bi, bj);
+    const int64_t r0 = (int64_t)bi * TILE, c0 = (int64_t)bj * TILE;
+    const int64_t kbeg = (int64_t)blockIdx.y * kc_len;
+    const int64_t kend = min(K, kbeg + kc_len);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    typename Mfma16<T>::acc_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = typename Mfma16<T>::acc_t{};
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+        for (int it = 0; it < (BK * TILE) / NT; ++it) {
+            const int e = tid + it * NT;
+            int row, k;
+            if (KCONTIG) { row = e / BK; k = e % BK; }
+            else         { k = e / TILE; row = e % TILE; }
+            const int64_t gk = k0 + k;
+            const int64_t ga = r0 + row, gb = c0 + row;
+            T va = T(0), vb = T(0);
+            if (gk < kend) {
+                if (ga < n) va = KCONTIG ? A[ga * ld + gk] : A[gk * ld + ga];
+                if (gb < n) vb = KCONTIG ? A[gb * ld + gk] : A[gk * ld + gb];
+            }
+            As[k][row] = va;
+            Bs[k][row] = vb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int k = kk + (lane >> 4);
+            T a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = As[k][wm * 64 + q * 16 + (lane & 15)];
+                b[q] = Bs[k][wn * 64 + q * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = Mfma16<T>::op(a[x], b[y], acc[x][y]);
+        }
+        __syncthreads();
+    }
+
+    T* out = part + ((int64_t)blockIdx.y * ntile + blockIdx.x) * (TILE * TILE);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = wm * 64 + x * 16 + Mfma16<T>::row(lane, v);
+                const int col = wn * 64 + y * 16 + (lane & 15);
+                out[row * TILE + col] = acc[x][y][v];
+            }
+}
+
+template <typename HT> struct Mfma32;
+template <> struct Mfma32<__bf16> {
+    typedef bf8v vec_t;
+    static __device__ inline f16v op(vec_t a, vec_t b, f16v c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma32<_Float16> {
+    typedef h8v vec_t;
+    static __device__ inline f16v op(vec_t a, vec_t b, f16v c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// 16-bit node-major Gram.  32x32x16 MFMA: lane l holds A[l % 32][8 (l / 32) + e],
+// e = 0..7, and B likewise by column; result row of register v is
+// 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32 (measured on gfx950).
+template <typename HT>
+__global__ __launch_bounds__(NT) void gram_lp_kernel(int64_t n, int64_t K, int64_t kc_len,
+                                                     const HT* __restrict__ A, int64_t ld,
+                                                     float* __restrict__ part, int64_t ntile) {
+    constexpr int BK = 32;
+    constexpr int LDK = BK + 8;  // row pitch in elements (80 B)
+    typedef typename Mfma32<HT>::vec_t vec_t;
+    __shared__ __attribute__((aligned(16))) HT As[TILE * LDK];
+    __shared__ __attribute__((aligned(16))) HT Bs[TILE * LDK];
+
+    int bi, bj;
+    tile_coords(blockIdx.x, bi, bj);
+    const int64_t r0 = (int64_t)bi * TILE, c0 = (int64_t)bj * TILE;
+    const int64_t kbeg = (int64_t)blockIdx.y * kc_len;
+    const int64_t kend = min(K, kbeg + kc_len);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const bool vec_ok = ((ld & 7) == 0) && ((((uintptr_t)A) & 15) == 0);
+
+    f16v acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f16v{};
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+        // 128 rows x 32 k per operand = 512 vectors of 8 elements
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int vix = tid + it * NT;
+            const int row = vix >> 2, seg = vix & 3;
+            const int64_t gk = k0 + seg * 8;
+#pragma unroll
+            for (int opnd = 0; opnd < 2; ++opnd) {
+                const int64_t grow = (opnd == 0 ? r0 : c0) + row;
+                HT* dst = (opnd == 0 ? As : Bs) + row * LDK + seg * 8;
+                if (grow < n && vec_ok && gk + 8 <= kend) {
+                    *(uint4*)dst = *(const uint4*)(A + grow * ld + gk);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        dst[e] = (grow < n && gk + e < kend) ? A[grow * ld + gk + e] : HT(0);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            vec_t a[2], b[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                a[q] = *(const vec_t*)(As + (wm * 64 + q * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5));
+                b[q] = *(const vec_t*)(Bs + (wn * 64 + q * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5));
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) acc[x][y] = Mfma32<HT>::op(a[x], b[y], acc[x][y]);
+        }
+        __syncthreads();
+    }
+
+    float* out = part + ((int64_t)blockIdx.y * ntile + blockIdx.x) * (TILE * TILE);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = wm * 64 + x * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int col = wn * 64 + y * 32 + (lane & 31);
+                out[row * TILE + col] = acc[x][y][v];
+            }
+}
+
+// M[i][j] = M[j][i] = sum over chunks (in chunk order, FP64) of the partial tiles
+template <typename PT>
+__global__ __launch_bounds__(NT) void gram_reduce_kernel(int64_t n, const PT* __restrict__ part,
+                                                         int64_t ntile, int nchunk,
+                                                         double* __restrict__ M, int64_t ldm) {
+    int bi, bj;
+    tile_coords(blockIdx.x, bi, bj);
+    const int64_t r0 = (int64_t)bi * TILE, c0 = (int64_t)bj * TILE;
+    for (int e = threadIdx.x; e < TILE * TILE; e += NT) {
+        const int row = e / TILE, col = e % TILE;
+        const int64_t gi = r0 + row, gj = c0 + col;
+        if (gi >= n || gj >= n || gi > gj) continue;
+        double s = 0.0;
+        for (int c = 0; c < nchunk; ++c)
+            s += (double)part[((int64_t)c * ntile + blockIdx.x) * (TILE * TILE) + e];
+        M[gi * ldm + gj] = s;
+        M[gj * ldm + gi] = s;
+    }
+}
+
+// Split the reduction length K into chunks so the grid has enough blocks.
+void plan_chunks(int64_t ntile, int64_t K, int64_t quantum, int64_t& kc_len, int& nchunk) {
+    const int64_t want_blocks = 1024;
+    int64_t nc = (want_blocks + ntile - 1) / ntile;
+    int64_t max_nc = (K + 1023) / 1024;  // keep chunks at least ~1024 long
+    if (nc > max_nc) nc = max_nc;
+    if (nc > 64) nc = 64;
+    if (nc < 1) nc = 1;
+    kc_len = cdiv(cdiv(K, nc), quantum) * quantum;
+    nchunk = (int)cdiv(K, kc_len);
+}
+
+template <typename T, bool KCONTIG>
+void run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, double* M,
+                int64_t ldm, Workspace& ws) {
+    const int64_t nt = cdiv(n, TILE);
+    const int64_t ntile = nt * (nt + 1) / 2;
+    int64_t kc_len;
+    int nchunk;
+    plan_chunks(ntile, K, 16, kc_len, nchunk);
+    T* part = (T*)ws.get("gram_part", (size_t)ntile * nchunk * TILE * TILE * sizeof(T));
+    gram16_kernel<T, KCONTIG><<<dim3((unsigned)ntile, (unsigned)nchunk), NT, 0, s>>>(
+        n, K, kc_len, A, ld, part, ntile);
+    ELM_LAUNCH_CHECK();
+    gram_reduce_kernel<T><<<(unsigned)ntile, NT, 0, s>>>(n, part, ntile, nchunk, M, ldm);
+    ELM_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(NT) void diag_max_kernel(int64_t n, const double* __restrict__ M,
+                                                      int64_t ldm, double* __restrict__ out) {
+    __shared__ double red[NT];
+    double m = 0.0;
+    bool nan = false;
+    for (int64_t i = threadIdx.x; i < n; i += NT) {
+        const double x = M[i * ldm + i];
+        if (x != x || isinf(x)) nan = true;
+        m = fmax(m, x);
+    }
+    red[threadIdx.x] = nan ? NAN : m;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double a = red[threadIdx.x], b = red[threadIdx.x + w];
+            red[threadIdx.x] = (a != a || b != b) ? NAN : fmax(a, b);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+}  // namespace
+
+void launch_diag_max(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out) {
+    diag_max_kernel<<<1, NT, 0, s>>>(n, M, ldm, out);
+    ELM_LAUNCH_CHECK();
+}
+
+void launch_gram_f64_cols(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
+                          double* M, int64_t ldm, Workspace& ws) {
+    run_gram16<double, false>(s, L, N, H, ldh, M, ldm, ws);
+}
+
+void launch_gram_f64_rows(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
+                          double* M, int64_t ldm, Workspace& ws) {
+    run_gram16<double, true>(s, N, L, H, ldh, M, ldm, ws);
+}
+
+void launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
+                          int64_t ldn, double* M, int64_t ldm, Workspace& ws) {
+    if (dt == ELM_F32) {
+        run_gram16<float, true>(s, L, N, (const float*)Hn, ldn, M, ldm, ws);
+        return;
+    }
+    const int64_t nt = cdiv(L, TILE);
+    const int64_t ntile = nt * (nt + 1) / 2;
+    int64_t kc_len;
+    int nchunk;
+    plan_chunks(ntile, N, 32, kc_len, nchunk);
+    float* part = (float*)ws.get("gram_part", (size_t)ntile * nchunk * TILE * TILE * sizeof(float));
+    dim3 grid((unsigned)ntile, (unsigned)nchunk);
+    if (dt == ELM_BF16)
+        gram_lp_kernel<__bf16><<<grid, NT, 0, s>>>(L, N, kc_len, (const __bf16*)Hn, ldn, part, ntile);
+    else
+        gram_lp_kernel<_Float16><<<grid, NT, 0, s>>>(L, N, kc_len, (const _Float16*)Hn, ldn, part, ntile);
+    ELM_LAUNCH_CHECK();
+    gram_reduce_kernel<float><<<(unsigned)ntile, NT, 0, s>>>(L, part, ntile, nchunk, M, ldm);
+    ELM_LAUNCH_CHECK();
+}
+
+}  // namespace elm

@@ -1,0 +1,261 @@
+// From the rank step to beta (Section 3; eq. 7 and step 9 of the algorithm).
+//
+// With the pivoted factor P^T M P = R^T R, R = [R11 R12] (r x n):
+//   F = H1 = H P[:, :r]  (the r independent columns),  F^T F = R11^T R11,
+//   K = R11^-1 R12,  G = [I K] P^T,  G G^T = I + K K^T,
+//   H^+ = G^T (G G^T)^-1 (F^T F)^-1 F^T.
+// When N < L the same factorisation is taken of H^T (Gram H H^T) and
+//   H^+ = F' (F'^T F')^-1 (G' G'^T)^-1 G'  with F' = H[piv[:r], :]^T.
+//
+// The factor keeps explicit inverses of the triangular factors (R11^-1 and
+// the inverse Cholesky factor of I + K K^T, or of I + K^T K used through the
+// Woodbury identity when n - r < r), so each application of H^+ is a short
+// chain of matrix products on the FP64 MFMA.  The triangular inverse is built
+// by recursive doubling of diagonal blocks:
+//   [A B; 0 C]^-1 = [A^-1, -A^-1 B C^-1; 0, C^-1].
+#include "elm_internal.h"
+
+namespace elm {
+
+void gemm_f64(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+              int64_t a_rs, int64_t a_cs, const double* B, int64_t b_rs, int64_t b_cs, double beta,
+              double* C, int64_t ldc);
+
+namespace {
+
+constexpr int LB = 64;  // leaf block of the triangular inverse
+
+// invert the LB x LB (or smaller, last) diagonal blocks of upper-triangular U
+__global__ __launch_bounds__(LB) void trtri_leaf_kernel(int64_t r, const double* __restrict__ U,
+                                                        int64_t ldu, double* __restrict__ X,
+                                                        int64_t ldx) {
+    __shared__ double Us[LB][LB + 1];
+    __shared__ double Xs[LB][LB + 1];
+    const int64_t b0 = (int64_t)blockIdx.x * LB;
+    const int nb = (int)((r - b0) < LB ? (r - b0) : LB);
+    const int j = threadIdx.x;
+    for (int i = 0; i < nb; ++i)
+        if (j < nb) Us[i][j] = U[(b0 + i) * ldu + b0 + j];
+    __syncthreads();
+    if (j < nb) {
+        // column j of the inverse: X[j][j] = 1/U[j][j], back substitution upward
+        for (int i = 0; i < nb; ++i) Xs[i][j] = 0.0;
+        Xs[j][j] = 1.0 / Us[j][j];
+        for (int i = j - 1; i >= 0; --i) {
+            double s = 0.0;
+            for (int k = i + 1; k <= j; ++k) s += Us[i][k] * Xs[k][j];
+            Xs[i][j] = -s / Us[i][i];
+        }
+    }
+    __syncthreads();
+    for (int i = 0; i < nb; ++i)
+        if (j < nb) X[(b0 + i) * ldx + b0 + j] = Xs[i][j];
+}
+
+// in-place upper Cholesky A = U^T U of a small SPD matrix, one block;
+// the strict lower triangle is zeroed.  flag[0] = 1 if a pivot is not positive.
+__global__ __launch_bounds__(1024) void chol_small_kernel(int64_t q, double* __restrict__ A,
+                                                          int64_t lda, int* flag) {
+    __shared__ double piv;
+    for (int64_t k = 0; k < q; ++k) {
+        if (threadIdx.x == 0) {
+            const double a = A[k * lda + k];
+            if (!(a > 0.0)) flag[0] = 1;
+            piv = sqrt(a > 0.0 ? a : 1.0);
+            A[k * lda + k] = piv;
+        }
+        __syncthreads();
+        for (int64_t j = k + 1 + threadIdx.x; j < q; j += blockDim.x) A[k * lda + j] /= piv;
+        __syncthreads();
+        const int64_t w = q - k - 1;
+        for (int64_t e = threadIdx.x; e < w * w; e += blockDim.x) {
+            const int64_t i = k + 1 + e / w, j = k + 1 + e % w;
+            if (j >= i) A[i * lda + j] -= A[k * lda + i] * A[k * lda + j];
+        }
+        __syncthreads();
+    }
+    for (int64_t e = threadIdx.x; e < q * q; e += blockDim.x) {
+        const int64_t i = e / q, j = e % q;
+        if (j < i) A[i * lda + j] = 0.0;
+    }
+}
+
+__global__ void add_identity_kernel(int64_t q, double* A, int64_t lda) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < q) A[i * lda + i] += 1.0;
+}
+
+// dst[i][c] = src[idx[i]][c]
+__global__ void gather_rows_kernel(int64_t rows, int64_t cols, const double* __restrict__ src,
+                                   int64_t lds, const int32_t* __restrict__ idx,
+                                   double* __restrict__ dst, int64_t ldd) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.y;
+    if (c < cols && i < rows) dst[i * ldd + c] = src[(int64_t)idx[i] * lds + c];
+}
+
+// dst[idx[i]][c] = src[i][c]
+__global__ void scatter_rows_kernel(int64_t rows, int64_t cols, const double* __restrict__ src,
+                                    int64_t lds, const int32_t* __restrict__ idx,
+                                    double* __restrict__ dst, int64_t ldd) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.y;
+    if (c < cols && i < rows) dst[(int64_t)idx[i] * ldd + c] = src[i * lds + c];
+}
+
+__global__ void zero_mat_kernel(int64_t rows, int64_t cols, double* __restrict__ A, int64_t lda) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.y;
+    if (c < cols && i < rows) A[i * lda + c] = 0.0;
+}
+
+void gather_rows(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds,
+                 const int32_t* idx, double* dst, int64_t ldd) {
+    if (rows <= 0 || cols <= 0) return;
+    gather_rows_kernel<<<dim3((unsigned)cdiv(cols, 256), (unsigned)rows), 256, 0, s>>>(
+        rows, cols, src, lds, idx, dst, ldd);
+    ELM_LAUNCH_CHECK();
+}
+
+void scatter_rows(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds,
+                  const int32_t* idx, double* dst, int64_t ldd) {
+    if (rows <= 0 || cols <= 0) return;
+    scatter_rows_kernel<<<dim3((unsigned)cdiv(cols, 256), (unsigned)rows), 256, 0, s>>>(
+        rows, cols, src, lds, idx, dst, ldd);
+    ELM_LAUNCH_CHECK();
+}
+
+void zero_mat(hipStream_t s, int64_t rows, int64_t cols, double* A, int64_t lda) {
+    if (rows <= 0 || cols <= 0) return;
+    zero_mat_kernel<<<dim3((unsigned)cdiv(cols, 256), (unsigned)rows), 256, 0, s>>>(rows, cols, A,
+                                                                                   lda);
+    ELM_LAUNCH_CHECK();
+}
+
+// X = U^-1 for upper-triangular U (r x r); X must not alias U.
+void trtri_upper(hipStream_t s, int64_t r, const double* U, int64_t ldu, double* X, int64_t ldx,
+                 Workspace& ws) {
+    zero_mat(s, r, r, X, ldx);
+    trtri_leaf_kernel<<<(unsigned)cdiv(r, LB), LB, 0, s>>>(r, U, ldu, X, ldx);
+    ELM_LAUNCH_CHECK();
+    int64_t szmax = 0;
+    for (int64_t sz = LB; sz < r; sz *= 2) szmax = sz;
+    double* T1 = szmax ? (double*)ws.get("trtri_T1", (size_t)szmax * szmax * sizeof(double)) : nullptr;
+    for (int64_t sz = LB; sz < r; sz *= 2) {
+        for (int64_t a0 = 0; a0 < r; a0 += 2 * sz) {
+            const int64_t c0 = a0 + sz;
+            if (c0 >= r) continue;
+            const int64_t na = sz, nc = (r - c0) < sz ? (r - c0) : sz;
+            // T1 = U[a, c] * X[c, c];  X[a, c] = -X[a, a] * T1
+            gemm_f64(s, na, nc, nc, 1.0, U + a0 * ldu + c0, ldu, 1, X + c0 * ldx + c0, ldx, 1, 0.0,
+                     T1, nc);
+            gemm_f64(s, na, nc, na, -1.0, X + a0 * ldx + a0, ldx, 1, T1, nc, 1, 0.0,
+                     X + a0 * ldx + c0, ldx);
+        }
+    }
+}
+
+// Y (q x m, ld m) <- S^-1 Y with S^-1 = Usinv Usinv^T (S = Us^T Us)
+void apply_s_inv(hipStream_t s, const elm_factor* f, int64_t m, double* Y, Workspace& ws) {
+    const int64_t q = f->q;
+    double* t = (double*)ws.get("ap_sinv", (size_t)q * m * sizeof(double));
+    gemm_f64(s, q, m, q, 1.0, f->Usinv, 1, q, Y, m, 1, 0.0, t, m);       // t = Usinv^T Y
+    gemm_f64(s, q, m, q, 1.0, f->Usinv, q, 1, t, m, 1, 0.0, Y, m);       // Y = Usinv t
+}
+
+// u (r x m) <- (G G^T)^-1 u = (I + K K^T)^-1 u
+void apply_g_gram_inv(hipStream_t s, const elm_factor* f, int64_t m, double* u, Workspace& ws) {
+    const int64_t r = f->r, c = f->n - f->r;
+    if (f->q == 0) return;
+    if (f->woodbury) {
+        // (I + K K^T)^-1 = I - K (I + K^T K)^-1 K^T
+        double* w = (double*)ws.get("ap_w", (size_t)c * m * sizeof(double));
+        gemm_f64(s, c, m, r, 1.0, f->K, 1, c, u, m, 1, 0.0, w, m);        // w = K^T u
+        apply_s_inv(s, f, m, w, ws);                                      // w = S'^-1 w
+        gemm_f64(s, r, m, c, -1.0, f->K, c, 1, w, m, 1, 1.0, u, m);       // u -= K w
+    } else {
+        apply_s_inv(s, f, m, u, ws);
+    }
+}
+
+// y (r x m) <- (F^T F)^-1 y = R11^-1 R11^-T y
+void apply_f_gram_inv(hipStream_t s, const elm_factor* f, int64_t m, double* y, Workspace& ws) {
+    const int64_t r = f->r;
+    double* t = (double*)ws.get("ap_finv", (size_t)r * m * sizeof(double));
+    gemm_f64(s, r, m, r, 1.0, f->Rinv, 1, r, y, m, 1, 0.0, t, m);        // t = Rinv^T y
+    gemm_f64(s, r, m, r, 1.0, f->Rinv, r, 1, t, m, 1, 0.0, y, m);        // y = Rinv t
+}
+
+}  // namespace
+
+void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws) {
+    const int64_t r = f->r, n = f->n, c = n - r;
+    if (r == 0) return;
+    ELM_HIP_TRY(hipMalloc(&f->Rinv, (size_t)r * r * sizeof(double)));
+    trtri_upper(s, r, f->R, n, f->Rinv, r, ws);
+    if (c > 0) {
+        ELM_HIP_TRY(hipMalloc(&f->K, (size_t)r * c * sizeof(double)));
+        gemm_f64(s, r, c, r, 1.0, f->Rinv, r, 1, f->R + r, n, 1, 0.0, f->K, c);   // K = R11^-1 R12
+    }
+    const int64_t q = r < c ? r : c;
+    f->q = q;
+    f->woodbury = (c < r);
+    if (q == 0) return;
+    double* S = (double*)ws.get("ft_S", (size_t)q * q * sizeof(double));
+    if (f->woodbury)
+        gemm_f64(s, c, c, r, 1.0, f->K, 1, c, f->K, c, 1, 0.0, S, c);   // K^T K
+    else
+        gemm_f64(s, r, r, c, 1.0, f->K, c, 1, f->K, 1, c, 0.0, S, r);   // K K^T
+    add_identity_kernel<<<(unsigned)cdiv(q, 256), 256, 0, s>>>(q, S, q);
+    ELM_LAUNCH_CHECK();
+    int* flag = (int*)ws.get("ft_flag", sizeof(int));
+    ELM_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+    chol_small_kernel<<<1, 1024, 0, s>>>(q, S, q, flag);
+    ELM_LAUNCH_CHECK();
+    ELM_HIP_TRY(hipMalloc(&f->Usinv, (size_t)q * q * sizeof(double)));
+    trtri_upper(s, q, S, q, f->Usinv, q, ws);
+    int hflag = 0;
+    ELM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipStreamSynchronize(s));
+    if (hflag) throw Error{ELM_ERR_NOT_PSD, "Gram of G is not positive definite"};
+}
+
+// out (L x m) = H^+ (.) through the factor.
+//   N >= L: rhs is H^T (.)  (L x m, ld ldr).
+//   N <  L: rhs is (.) itself (N x m, ld ldr); H64 (N x L sample-major) supplies F'.
+void apply_pinv(hipStream_t s, const elm_factor* f, int64_t m, const double* rhs, int64_t ldr,
+                const double* H64, int64_t ldh64, double* out, int64_t ldo, Workspace& ws) {
+    const int64_t r = f->r, n = f->n, c = n - r, L = f->L;
+    if (r == 0) {
+        zero_mat(s, L, m, out, ldo);
+        return;
+    }
+    double* u = (double*)ws.get("ap_u", (size_t)r * m * sizeof(double));
+    if (!f->transposed) {
+        gather_rows(s, r, m, rhs, ldr, f->piv, u, m);     // F^T (.) = rows piv[:r] of H^T (.)
+        apply_f_gram_inv(s, f, m, u, ws);                 // (F^T F)^-1
+        apply_g_gram_inv(s, f, m, u, ws);                 // (G G^T)^-1
+        // beta[piv] = [u; K^T u]  (eq. 7 block order)
+        scatter_rows(s, r, m, u, m, f->piv, out, ldo);
+        if (c > 0) {
+            double* bd = (double*)ws.get("ap_bd", (size_t)c * m * sizeof(double));
+            gemm_f64(s, c, m, r, 1.0, f->K, 1, c, u, m, 1, 0.0, bd, m);
+            scatter_rows(s, c, m, bd, m, f->piv + r, out, ldo);
+        }
+        return;
+    }
+    // N < L: w = G' rhs = rhs[piv[:r]] + K rhs[piv[r:]]
+    gather_rows(s, r, m, rhs, ldr, f->piv, u, m);
+    if (c > 0) {
+        double* t2 = (double*)ws.get("ap_t2", (size_t)c * m * sizeof(double));
+        gather_rows(s, c, m, rhs, ldr, f->piv + r, t2, m);
+        gemm_f64(s, r, m, c, 1.0, f->K, c, 1, t2, m, 1, 1.0, u, m);
+    }
+    apply_g_gram_inv(s, f, m, u, ws);                     // (G' G'^T)^-1
+    apply_f_gram_inv(s, f, m, u, ws);                     // (F'^T F')^-1
+    double* G1 = (double*)ws.get("ap_G1", (size_t)r * L * sizeof(double));
+    gather_rows(s, r, L, H64, ldh64, f->piv, G1, L);      // F'^T = H[piv[:r], :]
+    gemm_f64(s, L, m, r, 1.0, G1, 1, L, u, m, 1, 0.0, out, ldo);
+}
+
+}  // namespace elm

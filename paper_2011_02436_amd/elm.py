@@ -1,0 +1,315 @@
+"""Python binding of libelm (ctypes over the C ABI in include/elm.h).
+
+Argument marshalling only: tensors are torch device tensors, passed to the
+library as raw device pointers with their leading dimension, on the current
+torch stream.  Every step of the training path runs in the library's HIP
+kernels; there is no CPU fallback, and importing this module fails loudly if
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libelm.so")
+
+ELM_OK = 0
+ELM_ERR_NO_CONVERGENCE = 6
+ELM_F64, ELM_F32, ELM_BF16, ELM_F16 = 0, 1, 2, 3
+ELM_SAMPLE_MAJOR, ELM_NODE_MAJOR = 0, 1
+
+_DT = {torch.float64: ELM_F64, torch.float32: ELM_F32, torch.bfloat16: ELM_BF16,
+       torch.float16: ELM_F16}
+_LP = {"bf16": torch.bfloat16, "fp16": torch.float16, "fp32": torch.float32}
+
+
+class ElmError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status} ({_status_string(status)}): {message}")
+        self.status = status
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int64), ("transposed", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("ne_residual", ctypes.c_double),
+                ("ne_history", ctypes.c_double * 32)]
+
+    def as_dict(self):
+        n = self.iterations + 1 if self.ne_residual >= 0 else 0
+        return {"rank": int(self.rank), "transposed": bool(self.transposed),
+                "iterations": int(self.iterations), "ne_residual": float(self.ne_residual),
+                "ne_history": [float(self.ne_history[i]) for i in range(min(n, 32))]}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2011_02436_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "elm_create": ([ctypes.POINTER(vp), vp], i32),
+        "elm_destroy": ([vp], i32),
+        "elm_set_stream": ([vp, vp], i32),
+        "elm_status_string": ([i32], ctypes.c_char_p),
+        "elm_last_error": ([vp], ctypes.c_char_p),
+        "elm_hidden": ([vp, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, i32], i32),
+        "elm_rank_factor": ([vp, i64, i64, vp, i64, i32, i32, dbl, ctypes.POINTER(vp),
+                             ctypes.POINTER(i64)], i32),
+        "elm_factor_rank": ([vp, ctypes.POINTER(i64)], i32),
+        "elm_factor_pivots": ([vp, vp, ctypes.POINTER(i32)], i32),
+        "elm_factor_destroy": ([vp], i32),
+        "elm_pinv_solve": ([vp, vp, i64, vp, i64, vp, i64, dbl, i32, vp, i64,
+                            ctypes.POINTER(SolveInfo)], i32),
+        "elm_predict": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, vp],
+                        i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", "elm_last_error",
+            "elm_hidden", "elm_rank_factor", "elm_factor_rank", "elm_factor_pivots",
+            "elm_factor_destroy", "elm_pinv_solve", "elm_predict"]
+
+
+def _status_string(st: int) -> str:
+    return _lib.elm_status_string(st).decode()
+
+
+# ----------------------------------------------------------------------------
+# handle: one per (device, stream)
+# ----------------------------------------------------------------------------
+class Handle:
+    def __init__(self, device: Optional[int] = None):
+        dev = torch.cuda.current_device() if device is None else device
+        self.device = dev
+        with torch.cuda.device(dev):
+            h = ctypes.c_void_p()
+            st = _lib.elm_create(ctypes.byref(h), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            if st != ELM_OK:
+                raise ElmError(st, "elm_create", "")
+        self.ptr = h
+
+    def bind_current_stream(self):
+        _lib.elm_set_stream(self.ptr, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def check(self, st: int, where: str):
+        if st != ELM_OK:
+            raise ElmError(st, where, _lib.elm_last_error(self.ptr).decode())
+
+    def __del__(self):
+        try:
+            if getattr(self, "ptr", None):
+                _lib.elm_destroy(self.ptr)
+                self.ptr = None
+        except Exception:
+            pass
+
+
+_handles = {}
+
+
+def handle() -> Handle:
+    dev = torch.cuda.current_device()
+    h = _handles.get(dev)
+    if h is None:
+        h = Handle(dev)
+        _handles[dev] = h
+    h.bind_current_stream()
+    return h
+
+
+def _mat(t: torch.Tensor, name: str):
+    """(pointer, leading dimension) of a row-major 2-D device tensor."""
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    rows, cols = t.shape
+    if cols > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit stride along rows")
+    ld = t.stride(0) if rows > 1 else cols
+    if ld < cols:
+        raise ValueError(f"{name}: row stride smaller than the row length")
+    return ctypes.c_void_p(t.data_ptr()), max(ld, 1)
+
+
+def _vec(t: torch.Tensor, name: str):
+    if not t.is_cuda or t.dim() != 1 or t.stride(0) != 1:
+        raise ValueError(f"{name} must be a contiguous 1-D device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------------------------
+# entry points
+# ----------------------------------------------------------------------------
+def elm_hidden(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor,
+               H: Optional[torch.Tensor] = None, Hlp: Optional[torch.Tensor] = None) -> None:
+    """H = sigmoid(X W + b) into H (N x L, dtype of X) and/or Hlp (L x N)."""
+    h = handle()
+    N, d = X.shape
+    L = W.shape[1]
+    if X.dtype not in (torch.float64, torch.float32) or W.dtype != X.dtype or b.dtype != X.dtype:
+        raise ValueError("X, W, b must share dtype float64 or float32")
+    xp, ldx = _mat(X, "X")
+    wp, ldw = _mat(W, "W")
+    bp = _vec(b, "b")
+    hp, ldh = (ctypes.c_void_p(), 0) if H is None else _mat(H, "H")
+    if H is not None and (H.dtype != X.dtype or tuple(H.shape) != (N, L)):
+        raise ValueError("H must be N x L with the dtype of X")
+    if Hlp is not None:
+        if tuple(Hlp.shape) != (L, N) or Hlp.dtype not in (torch.bfloat16, torch.float16, torch.float32):
+            raise ValueError("Hlp must be L x N in bfloat16, float16 or float32")
+        lp, ldlp = _mat(Hlp, "Hlp")
+        lpdt = _DT[Hlp.dtype]
+    else:
+        lp, ldlp, lpdt = ctypes.c_void_p(), 0, ELM_BF16
+    h.check(_lib.elm_hidden(h.ptr, N, d, L, xp, ldx, wp, ldw, bp, _DT[X.dtype], hp, ldh, lp, ldlp,
+                            lpdt), "elm_hidden")
+
+
+class Factor:
+    """Library-owned rank factor (permutation, rank, full-rank factorisation)."""
+
+    def __init__(self, ptr: ctypes.c_void_p, N: int, L: int, rank: int):
+        self.ptr = ptr
+        self.N, self.L, self.rank = N, L, rank
+
+    @property
+    def n(self) -> int:
+        return min(self.N, self.L)
+
+    def pivots(self):
+        import numpy as np
+        out = np.empty(self.n, dtype=np.int32)
+        h = handle()
+        h.check(_lib.elm_factor_pivots(h.ptr, self.ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+                "elm_factor_pivots")
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "ptr", None):
+                _lib.elm_factor_destroy(self.ptr)
+                self.ptr = None
+        except Exception:
+            pass
+
+
+def elm_rank_factor(H: torch.Tensor, layout: str = "sample", tau_rel: float = 0.0) -> Factor:
+    """Rank step on H: FP64 sample-major (N x L), or a node-major (L x N)
+    low-precision copy from elm_hidden."""
+    h = handle()
+    if layout == "sample":
+        N, L = H.shape
+        lay = ELM_SAMPLE_MAJOR
+    elif layout == "node":
+        L, N = H.shape
+        lay = ELM_NODE_MAJOR
+    else:
+        raise ValueError("layout must be 'sample' or 'node'")
+    hp, ldh = _mat(H, "H")
+    f = ctypes.c_void_p()
+    r = ctypes.c_int64()
+    h.check(_lib.elm_rank_factor(h.ptr, N, L, hp, ldh, _DT[H.dtype], lay, float(tau_rel), ctypes.byref(f),
+                                 ctypes.byref(r)), "elm_rank_factor")
+    return Factor(f, N, L, int(r.value))
+
+
+def elm_pinv_solve(factor: Factor, T: torch.Tensor, H64: torch.Tensor, ir_tol: float = 1e-10,
+                   ir_max_iter: int = 0, beta: Optional[torch.Tensor] = None,
+                   check_convergence: bool = True):
+    """beta = H^+ T through the factor, with optional FP64 refinement.
+    Returns (beta, info dict)."""
+    h = handle()
+    N, m = T.shape
+    L = factor.L
+    if T.dtype != torch.float64 or H64.dtype != torch.float64:
+        raise ValueError("T and H64 must be float64")
+    if tuple(H64.shape) != (factor.N, factor.L) or N != factor.N:
+        raise ValueError("T / H64 shapes do not match the factor")
+    if beta is None:
+        beta = torch.empty((L, m), dtype=torch.float64, device=T.device)
+    tp, ldt = _mat(T, "T")
+    hp, ldh = _mat(H64, "H64")
+    bp, ldb = _mat(beta, "beta")
+    info = SolveInfo()
+    st = _lib.elm_pinv_solve(h.ptr, factor.ptr, m, tp, ldt, hp, ldh, float(ir_tol), int(ir_max_iter),
+                             bp, ldb, ctypes.byref(info))
+    if st == ELM_ERR_NO_CONVERGENCE and not check_convergence:
+        st = ELM_OK
+    h.check(st, "elm_pinv_solve")
+    return beta, info.as_dict()
+
+
+def elm_predict(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, beta: torch.Tensor,
+                want_Y: bool = True, want_labels: bool = True):
+    """Y = sigmoid(X W + b) beta (dtype of X) and arg-max labels (int32)."""
+    h = handle()
+    N, d = X.shape
+    L = W.shape[1]
+    m = beta.shape[1]
+    xp, ldx = _mat(X, "X")
+    wp, ldw = _mat(W, "W")
+    bp = _vec(b, "b")
+    betap, ldbeta = _mat(beta, "beta")
+    if beta.dtype != torch.float64:
+        raise ValueError("beta must be float64")
+    Y = torch.empty((N, m), dtype=X.dtype, device=X.device) if want_Y else None
+    labels = torch.empty(N, dtype=torch.int32, device=X.device) if want_labels else None
+    yp, ldy = (ctypes.c_void_p(), 0) if Y is None else _mat(Y, "Y")
+    lp = ctypes.c_void_p() if labels is None else ctypes.c_void_p(labels.data_ptr())
+    h.check(_lib.elm_predict(h.ptr, N, d, L, m, xp, ldx, wp, ldw, bp, _DT[X.dtype], betap, ldbeta, yp, ldy,
+                             lp), "elm_predict")
+    return Y, labels
+
+
+# ----------------------------------------------------------------------------
+# the whole training path as one call (composition of the entry points)
+# ----------------------------------------------------------------------------
+@dataclass
+class TrainResult:
+    beta: torch.Tensor
+    rank: int
+    info: dict
+    factor: Factor = field(repr=False, default=None)
+
+
+def train(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, T: torch.Tensor, precision: str = "fp64",
+          ir_tol: float = 1e-10, ir_max_iter: Optional[int] = None, tau_rel: float = 0.0,
+          H64: Optional[torch.Tensor] = None, Hlp: Optional[torch.Tensor] = None,
+          check_convergence: bool = True) -> TrainResult:
+    """H = g(XW + b) -> rank factor -> beta = H^+ T (+ FP64 refinement).
+
+    precision: 'fp64' (FP64 Gram), or 'fp32' / 'bf16' / 'fp16' (Gram of a
+    node-major low-precision copy; the rank decision and the refinement
+    residual stay in FP64).  X, W, b must be float64; H64/Hlp may be passed
+    preallocated to keep allocation out of timed regions."""
+    N, d = X.shape
+    L = W.shape[1]
+    if H64 is None:
+        H64 = torch.empty((N, L), dtype=torch.float64, device=X.device)
+    if precision == "fp64":
+        elm_hidden(X, W, b, H=H64)
+        factor = elm_rank_factor(H64, "sample", tau_rel)
+        its = 2 if ir_max_iter is None else ir_max_iter
+    else:
+        dt = _LP[precision]
+        if N < L:
+            raise ValueError("low-precision Gram requires N >= L; use precision='fp64'")
+        if Hlp is None:
+            Hlp = torch.empty((L, N), dtype=dt, device=X.device)
+        elm_hidden(X, W, b, H=H64, Hlp=Hlp)
+        factor = elm_rank_factor(Hlp, "node", tau_rel)
+        its = 30 if ir_max_iter is None else ir_max_iter
+    beta, info = elm_pinv_solve(factor, T, H64, ir_tol, its, check_convergence=check_convergence)
+    return TrainResult(beta, factor.rank, info, factor)

@@ -1,0 +1,37 @@
+"""Helpers for the GPU parity tests (host side only)."""
+import numpy as np
+import torch
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=dev(), dtype=dtype)
+
+
+def round_to_format(x: np.ndarray, sig_bits: int, min_normal_exp: int) -> np.ndarray:
+    """Round float64 values to nearest-even in a binary format with `sig_bits`
+    significant bits (8 for BF16, 11 for FP16) and smallest normal exponent
+    `min_normal_exp` (-126 for BF16, -14 for FP16), denormals included.
+    Exact: the scaled value x / ulp is an integer-spaced float64, and np.rint
+    rounds half to even.  Inputs here are finite and far from overflow."""
+    x = np.asarray(x, dtype=np.float64)
+    ax = np.abs(x)
+    with np.errstate(divide="ignore"):
+        e = np.floor(np.log2(np.where(ax > 0, ax, 1.0)))
+    # guard log2 rounding at exact powers of two
+    e = np.where(np.ldexp(1.0, e.astype(np.int64)) > ax, e - 1, e)
+    e = np.where(np.ldexp(1.0, (e + 1).astype(np.int64)) <= ax, e + 1, e)
+    e = np.maximum(e, min_normal_exp)
+    ulp = np.ldexp(1.0, (e - (sig_bits - 1)).astype(np.int64))
+    return np.where(ax > 0, np.rint(x / ulp) * ulp, x)
+
+
+def bf16_rne(x):
+    return round_to_format(x, 8, -126)
+
+
+def fp16_rne(x):
+    return round_to_format(x, 11, -14)
