@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark: ELM trainings/s of the precision form (BF16 Gram + FP64 pivoted
+Cholesky + FP64 refinement) against the plain FP64 GPU form at equal
+normal-equation residual, on the regression workload N=500000, d=128,
+L=10000, m=4 (synthetic, seeded).
+
+One step = the whole path on resident inputs: hidden layer (FP64 with a
+node-major BF16 copy), BF16 Gram, FP64 pivoted Cholesky and factor, beta with
+refinement to a relative normal-equation residual of 1e-10, and the
+training-set prediction (arg-max / outputs).
+
+Prints ONE JSON line.  Extra keys: the FP64 form's time and the speedup at
+equal residual, per-stage times, the Gram kernel's roofline, and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ELM trainings/sec + Gram TFLOP/s, BF16+refine vs FP64 GPU at equal residual"
+PEAK_BF16_TFLOPS = 2516.6   # MI355X dense BF16 MFMA
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--N", type=int, default=500000)
+    ap.add_argument("--L", type=int, default=10000)
+    ap.add_argument("--fp64-steps", type=int, default=2, help="timed FP64-form trainings (0 = skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=4000, help="oracle sample: rows at full L")
+    ap.add_argument("--cpu-nodes", type=int, default=3000, help="oracle sample: nodes for the factor")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, rows, nodes):
+    """The FP64 oracle on a bounded sample of the workload, scaled to
+    trainings/s of the full workload:
+      rows part   - hidden layer, Gram and two refinement residual passes on
+                    the first `rows` samples at full L (work proportional to N),
+                    scaled by N / rows;
+      factor part - rank step and beta assembly on the Gram of the first
+                    `nodes` hidden nodes (work ~ L^3), scaled by (L / nodes)^3."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    N, L = prob.N, prob.L
+    Xs, Ts = prob.X[:rows], prob.T[:rows]
+    t0 = time.perf_counter()
+    M, Z = O.gram_streamed(Xs, prob.W, prob.b, Ts, chunk_rows=2000)
+    beta0 = np.zeros((L, prob.m))
+    for _ in range(2):
+        O.ne_gradient_streamed(Xs, prob.W, prob.b, Ts, beta0, chunk_rows=2000)
+    t_rows = time.perf_counter() - t0
+    Ms = np.ascontiguousarray(M[:nodes, :nodes])
+    t1 = time.perf_counter()
+    F = O.rank_factor(O.ShapeOnly(rows, nodes), M=Ms)
+    for _ in range(3):
+        O.apply_pinv(F, None, None, Z=Z[:nodes])
+    t_factor = time.perf_counter() - t1
+    t_full = t_rows * (N / rows) + t_factor * (L / nodes) ** 3
+    return {
+        "value": 1.0 / t_full, "unit": "trainings/s", "cores": int(cores), "kind": "oracle",
+        "sample": (f"FP64 oracle on the first {rows} of {N} rows at full L={L} (hidden, Gram, 2 residual "
+                   f"passes: {t_rows:.2f} s, scaled x{N / rows:.0f}) plus its rank step and beta "
+                   f"assembly at {nodes} nodes ({t_factor:.2f} s, scaled x(L/{nodes})^3); "
+                   f"extrapolated full training {t_full:.0f} s"),
+    }
+
+
+def traffic_from_profiles(kernel_src):
+    """HBM traffic per launch of the Gram kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "gram_bf16_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src_hash = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for ln in open(path):
+        if ":" in ln and not ln.startswith("#"):
+            k, v = ln.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != src_hash:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the N-sharded design is described in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import elm_workloads as wl
+    from paper_2011_02436_amd import elm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    prob = wl.smooth_regression(N=args.N, L=args.L)
+    log(f"generated workload N={prob.N} d={prob.d} L={prob.L} m={prob.m} in {time.perf_counter() - t0:.1f} s")
+    X = torch.from_numpy(prob.X).to(dev)
+    W = torch.from_numpy(prob.W).to(dev)
+    b = torch.from_numpy(prob.b).to(dev)
+    T = torch.from_numpy(prob.T).to(dev)
+    N, L, m = prob.N, prob.L, prob.m
+    lp_dtype = {"bf16": torch.bfloat16, "fp16": torch.float16, "fp32": torch.float32}[args.precision]
+    H64 = torch.empty((N, L), dtype=torch.float64, device=dev)
+    Hlp = torch.empty((L, N), dtype=lp_dtype, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        res = elm.train(X, W, b, T, precision=args.precision, ir_tol=1e-10, H64=H64, Hlp=Hlp,
+                        check_convergence=False)
+        _, labels = elm.elm_predict(X, W, b, res.beta, want_Y=True, want_labels=True)
+        return res
+
+    for i in range(args.warmup):
+        res = step()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: rank {res.rank}, NE residual {res.info['ne_residual']:.2e}, "
+            f"iterations {res.info['iterations']}")
+
+    elm.profile_enable(True)
+    torch.cuda.synchronize()
+    times = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        res = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        log(f"step {i}: {times[-1] * 1e3:.1f} ms, rank {res.rank}, NE residual {res.info['ne_residual']:.2e}, "
+            f"its {res.info['iterations']}")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    stages = elm.profile_read()
+    elm.profile_enable(False)
+    ms_per_step = t_total / args.steps * 1e3
+    beta_lp = res.beta.clone()
+    info_lp = res.info
+    rank_lp = res.rank
+
+    # roofline of the Gram kernel: N L (L + 1) flops per launch (symmetric product)
+    gram_ms, gram_n = stages["gram"]
+    gram_avg_ms = gram_ms / max(gram_n, 1)
+    gram_flops = float(N) * L * (L + 1)
+    gram_tflops = gram_flops / (gram_avg_ms * 1e-3) / 1e12 if gram_n else None
+    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_2011_02436_amd", "csrc", "gram.hip"))
+    stage_ms_per_step = {k: round(v[0] / args.steps, 3) for k, v in stages.items()}
+
+    # FP64 form at equal residual
+    fp64 = None
+    if args.fp64_steps > 0:
+        del Hlp
+        torch.cuda.empty_cache()
+        r64 = elm.train(X, W, b, T, precision="fp64", ir_tol=1e-10, ir_max_iter=8, H64=H64,
+                        check_convergence=False)
+        torch.cuda.synchronize()
+        ft = []
+        for i in range(args.fp64_steps):
+            ts = time.perf_counter()
+            r64 = elm.train(X, W, b, T, precision="fp64", ir_tol=1e-10, ir_max_iter=8, H64=H64,
+                            check_convergence=False)
+            elm.elm_predict(X, W, b, r64.beta)
+            torch.cuda.synchronize()
+            ft.append(time.perf_counter() - ts)
+            log(f"fp64 step {i}: {ft[-1] * 1e3:.1f} ms, rank {r64.rank}, NE residual "
+                f"{r64.info['ne_residual']:.2e}, its {r64.info['iterations']}")
+        fp64_ms = sum(ft) / len(ft) * 1e3
+        diff = (torch.linalg.norm(beta_lp - r64.beta) / torch.linalg.norm(r64.beta)).item()
+        fp64 = {"ms_per_step": round(fp64_ms, 2), "trainings_per_s": round(1e3 / fp64_ms, 4),
+                "rank": r64.rank, "ne_residual": r64.info["ne_residual"],
+                "iterations": r64.info["iterations"],
+                "speedup_of_mixed": round(fp64_ms / ms_per_step, 3),
+                "beta_rel_diff_mixed_vs_fp64": diff}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(prob, min(args.cpu_rows, N), min(args.cpu_nodes, L))
+        log(f"cpu baseline {time.perf_counter() - t0:.1f} s: {cpu['sample']}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(1e3 / ms_per_step, 4),
+        "unit": "trainings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{args.precision}+f64",
+        "data": "synthetic",
+        "config": {"workload": f"smooth_regression N={N} d={prob.d} L={L} m={m}, {args.precision} Gram "
+                               f"+ FP64 pivoted Cholesky + FP64 refinement to NE residual 1e-10, "
+                               f"plus training-set predict",
+                   "N": N, "d": prob.d, "L": L, "m": m, "precision": args.precision},
+        "rank": rank_lp,
+        "ne_residual": info_lp["ne_residual"],
+        "refine_iterations": info_lp["iterations"],
+        "gram_tflops": round(gram_tflops, 2) if gram_tflops else None,
+        "roofline": {
+            "kernel": "gram_lp_kernel" if args.precision != "fp32" else "gram16_kernel<float>",
+            "bound": "mfma",
+            "achieved": round(gram_tflops, 2) if gram_tflops else None,
+            "peak": PEAK_BF16_TFLOPS if args.precision != "fp32" else 157.3,
+            "unit": "TFLOP/s",
+            "frac": round(gram_tflops / (PEAK_BF16_TFLOPS if args.precision != "fp32" else 157.3), 4)
+            if gram_tflops else None,
+            "traffic": traffic,
+            "avg_launch_ms": round(gram_avg_ms, 3),
+            "algorithmic_flops_per_launch": gram_flops,
+        },
+        "stage_ms_per_step": stage_ms_per_step,
+        "fp64_form": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

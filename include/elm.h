@@ -199,6 +199,37 @@ elm_status elm_predict(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m
                        const double* beta, int64_t ldbeta,
                        void* Y, int64_t ldy, int32_t* labels);
 
+/* ------------------------------------------------------------------------ */
+/* Stage timers (not part of the method; for measurement).                   */
+/* ------------------------------------------------------------------------ */
+
+typedef enum {
+    ELM_STAGE_HIDDEN = 0,       /* elm_hidden kernel */
+    ELM_STAGE_GRAM = 1,         /* Gram kernel (split-K partial tiles) */
+    ELM_STAGE_GRAM_REDUCE = 2,  /* fixed-order FP64 sum of the Gram partials */
+    ELM_STAGE_RANK = 3,         /* pivoted Cholesky (all its launches) */
+    ELM_STAGE_FACTOR = 4,       /* triangular inverses, K, Cholesky of G G^T */
+    ELM_STAGE_SOLVE = 5,        /* applications of H^+ through the factor */
+    ELM_STAGE_RHS = 6,          /* H^T T and H^T (T - H beta) passes over H */
+    ELM_STAGE_RESIDUAL = 7,     /* T - H beta passes over H */
+    ELM_STAGE_PREDICT = 8,      /* elm_predict kernel */
+    ELM_STAGE_COUNT = 9
+} elm_stage;
+
+typedef struct {
+    double ms[ELM_STAGE_COUNT];    /* summed device time between HIP events recorded on the
+                                      handle's stream around each stage */
+    int64_t count[ELM_STAGE_COUNT]; /* number of timed intervals per stage */
+} elm_stage_times;
+
+/* enable != 0 starts recording HIP events around every stage on the handle's
+ * stream and clears the accumulated times; enable == 0 stops recording. */
+elm_status elm_profile_enable(elm_handle* h, int enable);
+
+/* Accumulated stage times since the last elm_profile_enable(h, 1)
+ * (host struct out).  Synchronises the handle's stream. */
+elm_status elm_profile_read(elm_handle* h, elm_stage_times* out);
+
 #ifdef __cplusplus
 }
 #endif

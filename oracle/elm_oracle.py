@@ -264,7 +264,7 @@ def train(X, W, b, T, refine_steps: int = 2, tau: Optional[float] = None,
     t0 = time.perf_counter()
     M, Z = gram_streamed(X, W, b, T, chunk_rows)
     t1 = time.perf_counter()
-    F = rank_factor(_Shape(N, L), tau, M=M)
+    F = rank_factor(ShapeOnly(N, L), tau, M=M)
     beta = apply_pinv(F, None, None, Z=Z)
     t2 = time.perf_counter()
     t["rows"] += t1 - t0
@@ -279,7 +279,7 @@ def train(X, W, b, T, refine_steps: int = 2, tau: Optional[float] = None,
     return beta, F.r
 
 
-class _Shape:
+class ShapeOnly:
     """Stand-in carrying only the shape of H (streamed N >= L route)."""
 
     def __init__(self, N, L):

@@ -42,9 +42,59 @@ void Workspace::release() {
     bufs.clear();
 }
 
-namespace {
+hipEvent_t Profiler::take() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    ELM_HIP_TRY(hipEventCreate(&e));
+    return e;
+}
 
-thread_local std::string g_create_error;
+void Profiler::resolve() {
+    for (auto& pe : pending) {
+        ELM_HIP_TRY(hipEventSynchronize(pe.b));
+        float t = 0;
+        ELM_HIP_TRY(hipEventElapsedTime(&t, pe.a, pe.b));
+        ms[pe.stage] += t;
+        cnt[pe.stage] += 1;
+        pool.push_back(pe.a);
+        pool.push_back(pe.b);
+    }
+    pending.clear();
+}
+
+void Profiler::release() {
+    for (auto& pe : pending) {
+        (void)hipEventDestroy(pe.a);
+        (void)hipEventDestroy(pe.b);
+    }
+    pending.clear();
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+}
+
+StageScope::StageScope(Profiler* prof, int st, hipStream_t stream) : p(prof), stage(st), s(stream) {
+    if (p && p->on) {
+        a = p->take();
+        ELM_HIP_TRY(hipEventRecord(a, s));
+    }
+}
+
+StageScope::~StageScope() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    try {
+        b = p->take();
+    } catch (...) {
+        return;
+    }
+    if (hipEventRecord(b, s) == hipSuccess) p->pending.push_back({stage, a, b});
+}
+
+namespace {
 
 elm_status fail(elm_handle* h, elm_status st, const std::string& msg) {
     if (h) h->last_error = msg;
@@ -109,6 +159,7 @@ elm_status elm_create(elm_handle** out, void* stream) {
     elm_handle* h = nullptr;
     try {
         h = new elm_handle();
+        h->ws.prof = &h->prof;
         h->stream = (hipStream_t)stream;
         if (hipGetDevice(&h->device) != hipSuccess) {
             delete h;
@@ -130,6 +181,7 @@ elm_status elm_destroy(elm_handle* h) {
     if (!h) return ELM_OK;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
+    h->prof.release();
     h->ws.release();
     delete h;
     return ELM_OK;
@@ -175,6 +227,7 @@ elm_status elm_hidden(elm_handle* h, int64_t N, int64_t d, int64_t L, const void
             REQUIRE(ldlp >= N, ELM_ERR_SHAPE, "ldlp < N");
         }
         elm::use_device(h);
+        elm::StageScope sc(&h->prof, ELM_STAGE_HIDDEN, h->stream);
         elm::launch_hidden(h->stream, dt, N, d, L, X, ldx, W, ldw, b, H, ldh, Hlp, ldlp, lp_dt);
     });
 }
@@ -228,8 +281,14 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, i
         if (!std::isfinite(hdmax)) throw Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
         f->tau = (tau_rel > 0 ? tau_rel : (double)n * std::ldexp(1.0, -53)) * hdmax;
         ELM_HIP_TRY(hipMalloc(&f->piv, (size_t)n * sizeof(int32_t)));
-        f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, h->ws);
-        elm::build_factor_tail(h->stream, f, h->ws);
+        {
+            elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
+            f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, h->ws);
+        }
+        {
+            elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
+            elm::build_factor_tail(h->stream, f, h->ws);
+        }
         if (rank) *rank = f->r;
         *out = f;
     });
@@ -296,17 +355,26 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
         double* Z = (double*)ws.get("ps_Z", (size_t)L * m * sizeof(double));
         double* nrm = (double*)ws.get("ps_nrm", 2 * sizeof(double));
         // beta_0 = H^+ T
+        elm::Profiler* pr = &h->prof;
         if (!f->transposed) {
-            elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);   // H^T T, eq. (8)
+            {
+                elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+                elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);   // H^T T, eq. (8)
+            }
+            elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
             elm::apply_pinv(s, f, m, Z, m, H64, ldh64, beta, ldbeta, ws);
         } else {
+            elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
             elm::apply_pinv(s, f, m, T, ldt, H64, ldh64, beta, ldbeta, ws);
         }
         if (ir_max_iter == 0) {
             ELM_HIP_TRY(hipStreamSynchronize(s));
             return;
         }
-        if (f->transposed) elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);
+        if (f->transposed) {
+            elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+            elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);
+        }
         double z2 = 0;
         ELM_HIP_TRY(hipMemcpyAsync(&z2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
         double* E = (double*)ws.get("ps_E", (size_t)N * m * sizeof(double));
@@ -315,18 +383,27 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
         double res = 0;
         int it = 0;
         for (;;) {
-            elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m);   // T - H beta
-            elm::launch_ht_times(s, N, L, m, H64, ldh64, E, m, G, m, nrm + 1, ws);     // H^T (T - H beta)
+            {
+                elm::StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
+                elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m);  // T - H beta
+            }
+            {
+                elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+                elm::launch_ht_times(s, N, L, m, H64, ldh64, E, m, G, m, nrm + 1, ws);    // H^T (T - H beta)
+            }
             double g2 = 0;
             ELM_HIP_TRY(hipMemcpyAsync(&g2, nrm + 1, sizeof(double), hipMemcpyDeviceToHost, s));
             ELM_HIP_TRY(hipStreamSynchronize(s));
             res = z2 > 0 ? std::sqrt(g2 / z2) : std::sqrt(g2);
             if (info && it < 32) info->ne_history[it] = res;
             if (!(res > ir_tol) || it >= ir_max_iter) break;
-            if (!f->transposed)
-                elm::apply_pinv(s, f, m, G, m, H64, ldh64, D, m, ws);
-            else
-                elm::apply_pinv(s, f, m, E, m, H64, ldh64, D, m, ws);
+            {
+                elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
+                if (!f->transposed)
+                    elm::apply_pinv(s, f, m, G, m, H64, ldh64, D, m, ws);
+                else
+                    elm::apply_pinv(s, f, m, E, m, H64, ldh64, D, m, ws);
+            }
             elm::launch_axpy_mat(s, L, m, D, m, beta, ldbeta);
             ++it;
         }
@@ -354,8 +431,37 @@ elm_status elm_predict(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m
         REQUIRE(ldx >= d && ldw >= L && ldbeta >= m, ELM_ERR_SHAPE, "leading dimension too small");
         if (Y) REQUIRE(ldy >= m, ELM_ERR_SHAPE, "ldy < m");
         elm::use_device(h);
+        elm::StageScope sc(&h->prof, ELM_STAGE_PREDICT, h->stream);
         elm::launch_predict(h->stream, dt, N, d, L, m, X, ldx, W, ldw, b, beta, ldbeta, Y, ldy,
                             labels, h->ws);
+    });
+}
+
+elm_status elm_profile_enable(elm_handle* h, int enable) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        elm::use_device(h);
+        if (enable) {
+            h->prof.resolve();
+            for (int i = 0; i < ELM_STAGE_COUNT; ++i) {
+                h->prof.ms[i] = 0;
+                h->prof.cnt[i] = 0;
+            }
+        }
+        h->prof.on = enable != 0;
+    });
+}
+
+elm_status elm_profile_read(elm_handle* h, elm_stage_times* out) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(out, ELM_ERR_INVALID_ARG, "out must be non-null");
+        elm::use_device(h);
+        h->prof.resolve();
+        for (int i = 0; i < ELM_STAGE_COUNT; ++i) {
+            out->ms[i] = h->prof.ms[i];
+            out->count[i] = h->prof.cnt[i];
+        }
     });
 }
 

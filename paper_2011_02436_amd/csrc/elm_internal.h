@@ -71,8 +71,34 @@ struct Buffer {
     size_t bytes = 0;
 };
 
+// HIP-event stage timers on the handle's stream (off unless enabled)
+struct Profiler {
+    bool on = false;
+    double ms[ELM_STAGE_COUNT] = {};
+    int64_t cnt[ELM_STAGE_COUNT] = {};
+    struct Pending {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t take();
+    void resolve();  // synchronises on the recorded events
+    void release();
+};
+
+struct StageScope {
+    Profiler* p;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    StageScope(Profiler* prof, int st, hipStream_t stream);
+    ~StageScope();
+};
+
 struct Workspace {
     std::vector<std::pair<std::string, Buffer>> bufs;
+    Profiler* prof = nullptr;
     void* get(const std::string& name, size_t bytes);
     void release();
 };
@@ -84,6 +110,7 @@ struct elm_handle {
     int device = 0;
     int num_cu = 256;
     elm::Workspace ws;
+    elm::Profiler prof;
     std::string last_error;
 };
 

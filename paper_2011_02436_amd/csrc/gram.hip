@@ -242,9 +242,13 @@ void run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, dou
     int nchunk;
     plan_chunks(ntile, K, 16, kc_len, nchunk);
     T* part = (T*)ws.get("gram_part", (size_t)ntile * nchunk * TILE * TILE * sizeof(T));
-    gram16_kernel<T, KCONTIG><<<dim3((unsigned)ntile, (unsigned)nchunk), NT, 0, s>>>(
-        n, K, kc_len, A, ld, part, ntile);
-    ELM_LAUNCH_CHECK();
+    {
+        StageScope sc(ws.prof, ELM_STAGE_GRAM, s);
+        gram16_kernel<T, KCONTIG><<<dim3((unsigned)ntile, (unsigned)nchunk), NT, 0, s>>>(
+            n, K, kc_len, A, ld, part, ntile);
+        ELM_LAUNCH_CHECK();
+    }
+    StageScope sc(ws.prof, ELM_STAGE_GRAM_REDUCE, s);
     gram_reduce_kernel<T><<<(unsigned)ntile, NT, 0, s>>>(n, part, ntile, nchunk, M, ldm);
     ELM_LAUNCH_CHECK();
 }
@@ -301,11 +305,16 @@ void launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, con
     plan_chunks(ntile, N, 32, kc_len, nchunk);
     float* part = (float*)ws.get("gram_part", (size_t)ntile * nchunk * TILE * TILE * sizeof(float));
     dim3 grid((unsigned)ntile, (unsigned)nchunk);
-    if (dt == ELM_BF16)
-        gram_lp_kernel<__bf16><<<grid, NT, 0, s>>>(L, N, kc_len, (const __bf16*)Hn, ldn, part, ntile);
-    else
-        gram_lp_kernel<_Float16><<<grid, NT, 0, s>>>(L, N, kc_len, (const _Float16*)Hn, ldn, part, ntile);
-    ELM_LAUNCH_CHECK();
+    {
+        StageScope sc(ws.prof, ELM_STAGE_GRAM, s);
+        if (dt == ELM_BF16)
+            gram_lp_kernel<__bf16><<<grid, NT, 0, s>>>(L, N, kc_len, (const __bf16*)Hn, ldn, part, ntile);
+        else
+            gram_lp_kernel<_Float16><<<grid, NT, 0, s>>>(L, N, kc_len, (const _Float16*)Hn, ldn, part,
+                                                         ntile);
+        ELM_LAUNCH_CHECK();
+    }
+    StageScope sc(ws.prof, ELM_STAGE_GRAM_REDUCE, s);
     gram_reduce_kernel<float><<<(unsigned)ntile, NT, 0, s>>>(L, part, ntile, nchunk, M, ldm);
     ELM_LAUNCH_CHECK();
 }

@@ -46,6 +46,13 @@ class SolveInfo(ctypes.Structure):
                 "ne_history": [float(self.ne_history[i]) for i in range(min(n, 32))]}
 
 
+STAGES = ["hidden", "gram", "gram_reduce", "rank", "factor", "solve", "rhs", "residual", "predict"]
+
+
+class StageTimes(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 9), ("count", ctypes.c_int64 * 9)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2011_02436_amd.build.build()")
@@ -67,6 +74,8 @@ def _load():
                             ctypes.POINTER(SolveInfo)], i32),
         "elm_predict": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, vp],
                         i32),
+        "elm_profile_enable": ([vp, i32], i32),
+        "elm_profile_read": ([vp, ctypes.POINTER(StageTimes)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -78,7 +87,8 @@ def _load():
 _lib = _load()
 EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", "elm_last_error",
             "elm_hidden", "elm_rank_factor", "elm_factor_rank", "elm_factor_pivots",
-            "elm_factor_destroy", "elm_pinv_solve", "elm_predict"]
+            "elm_factor_destroy", "elm_pinv_solve", "elm_predict", "elm_profile_enable",
+            "elm_profile_read"]
 
 
 def _status_string(st: int) -> str:
@@ -271,6 +281,20 @@ def elm_predict(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, beta: torch.T
     h.check(_lib.elm_predict(h.ptr, N, d, L, m, xp, ldx, wp, ldw, bp, _DT[X.dtype], betap, ldbeta, yp, ldy,
                              lp), "elm_predict")
     return Y, labels
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (and reset) or stop the library's HIP-event stage timers."""
+    h = handle()
+    h.check(_lib.elm_profile_enable(h.ptr, 1 if on else 0), "elm_profile_enable")
+
+
+def profile_read() -> dict:
+    """{stage: (total_ms, count)} since the last profile_enable(True)."""
+    h = handle()
+    st = StageTimes()
+    h.check(_lib.elm_profile_read(h.ptr, ctypes.byref(st)), "elm_profile_read")
+    return {name: (float(st.ms[i]), int(st.count[i])) for i, name in enumerate(STAGES)}
 
 
 # ----------------------------------------------------------------------------
