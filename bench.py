@@ -139,7 +139,7 @@ def main():
     def step():
         res = elm.train(X, W, b, T, precision=args.precision, ir_tol=1e-10, H64=H64, Hlp=Hlp,
                         check_convergence=False)
-        _, labels = elm.elm_predict(X, W, b, res.beta, want_Y=True, want_labels=True)
+        elm.elm_predict_hidden(H64, res.beta)  # training-set outputs and labels (step 3)
         return res
 
     for i in range(args.warmup):
@@ -189,7 +189,7 @@ def main():
             ts = time.perf_counter()
             r64 = elm.train(X, W, b, T, precision="fp64", ir_tol=1e-10, ir_max_iter=8, H64=H64,
                             check_convergence=False)
-            elm.elm_predict(X, W, b, r64.beta)
+            elm.elm_predict_hidden(H64, r64.beta)
             torch.cuda.synchronize()
             ft.append(time.perf_counter() - ts)
             log(f"fp64 step {i}: {ft[-1] * 1e3:.1f} ms, rank {r64.rank}, NE residual "

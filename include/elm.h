@@ -147,6 +147,13 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L,
                            const void* H, int64_t ldh, elm_dtype h_dt, elm_layout layout,
                            double tau_rel, elm_factor** out, int64_t* rank);
 
+/* The Gram step alone (eq. 8): M = H^T H (N >= L) or H H^T (N < L), n x n
+ * FP64 with n = min(N, L), written in full (both triangles, exactly
+ * symmetric) to the caller's M (ld ldm >= n).  Same accepted inputs and the
+ * same kernels as elm_rank_factor; asynchronous. */
+elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
+                    elm_dtype h_dt, elm_layout layout, double* M, int64_t ldm);
+
 /* r of a factor (host read, no synchronisation needed). */
 elm_status elm_factor_rank(const elm_factor* f, int64_t* rank);
 
@@ -198,6 +205,16 @@ elm_status elm_predict(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m
                        const void* b, elm_dtype dt,
                        const double* beta, int64_t ldbeta,
                        void* Y, int64_t ldy, int32_t* labels);
+
+/* Step 3 of the three-step ELM as stated in Section 2.1: multiply the
+ * hidden-layer matrix by beta.  H: FP64 sample-major N x L (ld ldh >= L),
+ * e.g. the training H from elm_hidden; beta: L x m FP64.  Y (optional): N x m
+ * FP64, ld ldy >= m.  labels (optional): N int32 arg-max per row (lowest index
+ * on ties).  At least one of Y and labels must be non-NULL.  1 <= m <= 64. */
+elm_status elm_predict_hidden(elm_handle* h, int64_t N, int64_t L, int64_t m,
+                              const double* H, int64_t ldh,
+                              const double* beta, int64_t ldbeta,
+                              double* Y, int64_t ldy, int32_t* labels);
 
 /* ------------------------------------------------------------------------ */
 /* Stage timers (not part of the method; for measurement).                   */

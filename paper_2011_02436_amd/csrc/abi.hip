@@ -142,8 +142,11 @@ void free_factor_buffers(elm_factor* f) {
     if (f->Rinv) (void)hipFree(f->Rinv);
     if (f->K) (void)hipFree(f->K);
     if (f->Usinv) (void)hipFree(f->Usinv);
+    if (f->RinvT) (void)hipFree(f->RinvT);
+    if (f->KT) (void)hipFree(f->KT);
+    if (f->UsinvT) (void)hipFree(f->UsinvT);
     f->piv = nullptr;
-    f->R = f->Rinv = f->K = f->Usinv = nullptr;
+    f->R = f->Rinv = f->K = f->Usinv = f->RinvT = f->KT = f->UsinvT = nullptr;
 }
 
 }  // namespace
@@ -299,6 +302,38 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, i
     return st;
 }
 
+elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh, elm_dtype h_dt,
+                    elm_layout layout, double* M, int64_t ldm) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(N >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N and L must be >= 1");
+        REQUIRE(H && M, ELM_ERR_INVALID_ARG, "H and M must be non-null");
+        REQUIRE(layout == ELM_SAMPLE_MAJOR || layout == ELM_NODE_MAJOR, ELM_ERR_INVALID_ARG,
+                "unknown layout");
+        REQUIRE(h_dt == ELM_F64 || h_dt == ELM_F32 || h_dt == ELM_BF16 || h_dt == ELM_F16,
+                ELM_ERR_INVALID_ARG, "unknown dtype");
+        REQUIRE(ldh >= (layout == ELM_SAMPLE_MAJOR ? L : N), ELM_ERR_SHAPE,
+                "ldh smaller than the row length");
+        const bool transposed = N < L;
+        const int64_t n = transposed ? N : L;
+        REQUIRE(ldm >= n, ELM_ERR_SHAPE, "ldm < min(N, L)");
+        if (h_dt == ELM_F64)
+            REQUIRE(layout == ELM_SAMPLE_MAJOR, ELM_ERR_UNSUPPORTED, "FP64 H must be sample-major");
+        else
+            REQUIRE(layout == ELM_NODE_MAJOR && !transposed, ELM_ERR_UNSUPPORTED,
+                    "low-precision H must be node-major, with N >= L");
+        elm::use_device(h);
+        if (h_dt == ELM_F64) {
+            if (transposed)
+                elm::launch_gram_f64_rows(h->stream, N, L, (const double*)H, ldh, M, ldm, h->ws);
+            else
+                elm::launch_gram_f64_cols(h->stream, N, L, (const double*)H, ldh, M, ldm, h->ws);
+        } else {
+            elm::launch_gram_lp_nodes(h->stream, h_dt, N, L, H, ldh, M, ldm, h->ws);
+        }
+    });
+}
+
 elm_status elm_factor_rank(const elm_factor* f, int64_t* rank) {
     if (!f || !rank) return ELM_ERR_INVALID_ARG;
     *rank = f->r;
@@ -359,7 +394,10 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
         if (!f->transposed) {
             {
                 elm::StageScope sc(pr, ELM_STAGE_RHS, s);
-                elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);   // H^T T, eq. (8)
+                // H^T T, eq. (8)
+                if (!elm::launch_fused_ht_resid(s, N, L, m, H64, ldh64, T, ldt, nullptr, 0, Z, m, nrm,
+                                                ws, h->num_cu))
+                    elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);
             }
             elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
             elm::apply_pinv(s, f, m, Z, m, H64, ldh64, beta, ldbeta, ws);
@@ -383,13 +421,20 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
         double res = 0;
         int it = 0;
         for (;;) {
-            {
-                elm::StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
-                elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m);  // T - H beta
-            }
-            {
+            // G = H^T (T - H beta): one fused pass when N >= L, else E is needed too
+            bool fused = false;
+            if (!f->transposed) {
                 elm::StageScope sc(pr, ELM_STAGE_RHS, s);
-                elm::launch_ht_times(s, N, L, m, H64, ldh64, E, m, G, m, nrm + 1, ws);    // H^T (T - H beta)
+                fused = elm::launch_fused_ht_resid(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, G, m,
+                                                   nrm + 1, ws, h->num_cu);
+            }
+            if (!fused) {
+                {
+                    elm::StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
+                    elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m);
+                }
+                elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+                elm::launch_ht_times(s, N, L, m, H64, ldh64, E, m, G, m, nrm + 1, ws);
             }
             double g2 = 0;
             ELM_HIP_TRY(hipMemcpyAsync(&g2, nrm + 1, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -434,6 +479,23 @@ elm_status elm_predict(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m
         elm::StageScope sc(&h->prof, ELM_STAGE_PREDICT, h->stream);
         elm::launch_predict(h->stream, dt, N, d, L, m, X, ldx, W, ldw, b, beta, ldbeta, Y, ldy,
                             labels, h->ws);
+    });
+}
+
+elm_status elm_predict_hidden(elm_handle* h, int64_t N, int64_t L, int64_t m, const double* H,
+                              int64_t ldh, const double* beta, int64_t ldbeta, double* Y, int64_t ldy,
+                              int32_t* labels) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(N >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N and L must be >= 1");
+        REQUIRE(m >= 1 && m <= 64, ELM_ERR_INVALID_ARG, "m must be in [1, 64]");
+        REQUIRE(H && beta, ELM_ERR_INVALID_ARG, "H and beta must be non-null");
+        REQUIRE(Y || labels, ELM_ERR_INVALID_ARG, "at least one of Y and labels must be non-null");
+        REQUIRE(ldh >= L && ldbeta >= m, ELM_ERR_SHAPE, "leading dimension too small");
+        if (Y) REQUIRE(ldy >= m, ELM_ERR_SHAPE, "ldy < m");
+        elm::use_device(h);
+        elm::StageScope sc(&h->prof, ELM_STAGE_PREDICT, h->stream);
+        elm::launch_hidden_output(h->stream, N, L, m, H, ldh, beta, ldbeta, Y, ldy, labels);
     });
 }
 

@@ -127,6 +127,9 @@ struct elm_factor {
     double* K = nullptr;      // r x (n - r), ld n - r: K = R11^-1 R12
     double* Usinv = nullptr;  // q x q, ld q: Us^-1 where Us^T Us = I + K K^T (q = r)
                               // or I + K^T K (q = n - r, woodbury)
+    double* RinvT = nullptr;  // transposes, so every product in the solves reads rows
+    double* KT = nullptr;     // (n - r) x r
+    double* UsinvT = nullptr;
     int64_t q = 0;
     bool woodbury = false;
     int device = 0;
@@ -177,6 +180,15 @@ void launch_residual(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
 void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
                      const double* E, int64_t lde, double* G, int64_t ldg, double* nrm2,
                      Workspace& ws);
+//   G = H^T (T - H beta) in one pass over H (beta NULL: G = H^T T); false if the
+//   shape is outside the fused kernel's register/LDS budget (L > 10240 or m > 8)
+bool launch_fused_ht_resid(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
+                           int64_t ldh, const double* T, int64_t ldt, const double* beta, int64_t ldb,
+                           double* G, int64_t ldg, double* nrm2, Workspace& ws, int num_cu);
+//   Y = H beta and/or arg-max labels
+void launch_hidden_output(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
+                          int64_t ldh, const double* beta, int64_t ldb, double* Y, int64_t ldy,
+                          int32_t* labels);
 //   beta += delta, elementwise over L x m
 void launch_axpy_mat(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx,
                      double* Y, int64_t ldy);

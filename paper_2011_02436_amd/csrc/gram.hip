@@ -20,6 +20,7 @@
 //   gram_reduce_kernel  sums the split-K partial tiles in FP64 and mirrors.
 #include "elm_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace elm {
@@ -253,6 +254,164 @@ void run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, dou
     ELM_LAUNCH_CHECK();
 }
 
+
+// ---------------------------------------------------------------------------
+// 16-bit node-major Gram, 256 x 256 tiles (the high-throughput path).
+//
+// Each block owns one work item (split-K chunk, tile bi <= bj) from a table
+// built on the host.  4 waves in a 2 x 2 grid each accumulate a 128 x 128
+// sub-tile as 4 x 4 blocks of the 32x32x16 MFMA (256 FP32 accumulators per
+// lane).  K is consumed in chunks of 64 samples through two LDS stages: the
+// next chunk's global loads are in flight while the current one feeds the
+// MFMAs.  In LDS each tile row holds 8 chunks of 16 B; chunk c of row i sits
+// at position c ^ (i & 7) so the 32 rows an MFMA operand read touches spread
+// over all banks.  Diagonal tiles read B from A's copy of the same rows
+// (both copies are loaded; only the read side is shared).
+// ---------------------------------------------------------------------------
+constexpr int GT = 256;   // tile
+constexpr int GBK = 64;   // samples per LDS stage
+constexpr int G_CHUNKS = GT * GBK * 2 / 16;  // 16-byte chunks per operand per stage (2048)
+
+template <typename HT>
+__global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, int64_t kc_len,
+                                                         const HT* __restrict__ A, int64_t ld,
+                                                         float* __restrict__ part,
+                                                         const int4* __restrict__ work) {
+    __shared__ uint4 smem[2 * 2 * G_CHUNKS];  // 2 stages x (A, B) x 32 KB = 128 KB
+    typedef typename Mfma32<HT>::vec_t vec_t;
+    const int4 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    const int64_t r0 = (int64_t)wk.y * GT, c0 = (int64_t)wk.z * GT;
+    const bool diag = wk.y == wk.z;
+    const int64_t kbeg = (int64_t)wk.x * kc_len;
+    const int64_t kend = min(K, kbeg + kc_len);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const bool vec_ok = ((ld & 7) == 0) && ((((uintptr_t)A) & 15) == 0);
+
+    // two register sets of staged loads: the chunk two stages ahead is in
+    // flight while the current one feeds the MFMAs (one wave per SIMD, so
+    // the staging registers are what hides global-memory latency)
+    uint4 ra0[8], rb0[8], ra1[8], rb1[8];
+    auto load_chunk = [&](int64_t grow, int64_t gk) -> uint4 {
+        if (grow < n && vec_ok && gk + 8 <= kend) return *(const uint4*)(A + grow * ld + gk);
+        {
+            const uint16_t* A16 = (const uint16_t*)A;
+            auto el = [&](int e) -> uint32_t {
+                return (grow < n && gk + e < kend) ? (uint32_t)A16[grow * ld + gk + e] : 0u;
+            };
+            return make_uint4(el(0) | (el(1) << 16), el(2) | (el(3) << 16), el(4) | (el(5) << 16),
+                              el(6) | (el(7) << 16));
+        }
+    };
+#define GRAM_GLOAD(K0, RA, RB)                                                    \
+    do {                                                                          \
+        const int64_t k0_ = (K0);                                                 \
+        if (k0_ < kend) {                                                         \
+            _Pragma("unroll") for (int it = 0; it < 8; ++it) {                    \
+                const int q = tid + 256 * it;                                     \
+                const int row = q >> 3;                                           \
+                const int c = (q & 7) ^ (row & 7);                                \
+                RA[it] = load_chunk(r0 + row, k0_ + c * 8);                       \
+                RB[it] = load_chunk(c0 + row, k0_ + c * 8);            \
+            }                                                                     \
+        }                                                                         \
+    } while (0)
+#define GRAM_SWRITE(STAGE, RA, RB)                                                \
+    do {                                                                          \
+        uint4* sA_ = smem + (STAGE) * 2 * G_CHUNKS;                               \
+        uint4* sB_ = sA_ + G_CHUNKS;                                              \
+        _Pragma("unroll") for (int it = 0; it < 8; ++it) {                        \
+            const int q = tid + 256 * it;                                         \
+            sA_[q] = RA[it];                                                      \
+            sB_[q] = RB[it];                                           \
+        }                                                                         \
+    } while (0)
+
+    f16v acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = f16v{};
+
+#define GRAM_COMPUTE(STAGE)                                                                \
+    do {                                                                                   \
+        const uint4* sA = smem + (STAGE) * 2 * G_CHUNKS;                                   \
+        const uint4* sB = diag ? sA : sA + G_CHUNKS;                                       \
+        _Pragma("unroll") for (int kk = 0; kk < 4; ++kk) {                                 \
+            const int c = kk * 2 + (lane >> 5);                                            \
+            vec_t a[4], b[4];                                                              \
+            _Pragma("unroll") for (int x = 0; x < 4; ++x) {                                \
+                const int ra_row = wm * 128 + x * 32 + (lane & 31);                        \
+                const int rb_row = wn * 128 + x * 32 + (lane & 31);                        \
+                a[x] = *(const vec_t*)&sA[ra_row * 8 + (c ^ (ra_row & 7))];                \
+                b[x] = *(const vec_t*)&sB[rb_row * 8 + (c ^ (rb_row & 7))];                \
+            }                                                                              \
+            _Pragma("unroll") for (int x = 0; x < 4; ++x)                                  \
+                _Pragma("unroll") for (int y = 0; y < 4; ++y)                              \
+                    acc[x][y] = Mfma32<HT>::op(a[x], b[y], acc[x][y]);                     \
+        }                                                                                  \
+    } while (0)
+
+    // prologue: stage 0 to LDS, stage 1 in set 1, stage 2 in set 0
+    GRAM_GLOAD(kbeg, ra0, rb0);
+    GRAM_SWRITE(0, ra0, rb0);
+    GRAM_GLOAD(kbeg + GBK, ra1, rb1);
+    GRAM_GLOAD(kbeg + 2 * GBK, ra0, rb0);
+    __syncthreads();
+    // iteration i computes LDS stage i % 2, then stores the set holding chunk
+    // i + 1 and refills it with chunk i + 3; unrolled by two so each set is
+    // named statically; an odd last stage is handled after the loop
+    const int64_t nst = (kend - kbeg + GBK - 1) / GBK;
+    int64_t st = 0;
+    for (; st + 2 <= nst; st += 2) {
+        GRAM_COMPUTE(0);
+        GRAM_SWRITE(1, ra1, rb1);
+        GRAM_GLOAD(kbeg + (st + 3) * GBK, ra1, rb1);
+        __syncthreads();
+        GRAM_COMPUTE(1);
+        if (st + 2 < nst) {
+            GRAM_SWRITE(0, ra0, rb0);
+            GRAM_GLOAD(kbeg + (st + 4) * GBK, ra0, rb0);
+        }
+        __syncthreads();
+    }
+    if (st < nst) GRAM_COMPUTE(0);
+#undef GRAM_GLOAD
+#undef GRAM_SWRITE
+#undef GRAM_COMPUTE
+
+    float* out = part + (int64_t)wk.w * (GT * GT);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = wm * 128 + x * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int col = wn * 128 + y * 32 + (lane & 31);
+                out[row * GT + col] = acc[x][y][v];
+            }
+}
+
+// M[i][j] = M[j][i] = sum over splits (in order, FP64) of the 256-tile partials;
+// partial slot of (split s, tile t) is s * ntile + t.
+__global__ __launch_bounds__(NT) void gram_reduce256_kernel(int64_t n, const float* __restrict__ part,
+                                                            int64_t ntile, int nsplit,
+                                                            double* __restrict__ M, int64_t ldm) {
+    int bi, bj;
+    tile_coords(blockIdx.x, bi, bj);
+    const int64_t r0 = (int64_t)bi * GT, c0 = (int64_t)bj * GT;
+    const int64_t e = (int64_t)blockIdx.y * NT + threadIdx.x;  // element within the tile
+    const int row = (int)(e / GT), col = (int)(e % GT);
+    const int64_t gi = r0 + row, gj = c0 + col;
+    if (gi >= n || gj >= n || gi > gj) return;
+    double s = 0.0;
+    for (int c = 0; c < nsplit; ++c) s += (double)part[((int64_t)c * ntile + blockIdx.x) * (GT * GT) + e];
+    M[gi * ldm + gj] = s;
+    M[gj * ldm + gi] = s;
+}
+
 __global__ __launch_bounds__(NT) void diag_max_kernel(int64_t n, const double* __restrict__ M,
                                                       int64_t ldm, double* __restrict__ out) {
     __shared__ double red[NT];
@@ -292,30 +451,82 @@ void launch_gram_f64_rows(hipStream_t s, int64_t N, int64_t L, const double* H, 
     run_gram16<double, true>(s, N, L, H, ldh, M, ldm, ws);
 }
 
+// Work table for the 256-tile Gram: items (split, bi, bj, slot) ordered by
+// split, then by 4 x 8 patches of tiles, then dealt to XCDs in chunks of 32
+// consecutive items (block b runs on XCD b % 8 as its (b / 8)-th block), so
+// the blocks an XCD runs together cover one patch and share its panels in
+// that XCD's L2.  b -> item = ((b/8)/32 * 8 + b%8) * 32 + (b/8)%32 is a
+// bijection on [0, nb) for nb a multiple of 256.  Unused slots hold split = -1.
+static std::vector<int4> gram_work_table(int64_t nt, int nsplit, int64_t ntile) {
+    std::vector<int4> items;
+    const int PI = 4, PJ = 8;
+    for (int s = 0; s < nsplit; ++s)
+        for (int64_t pj = 0; pj < nt; pj += PJ)
+            for (int64_t pi = 0; pi <= pj + PJ - 1 && pi < nt; pi += PI)
+                for (int64_t bj = pj; bj < std::min<int64_t>(pj + PJ, nt); ++bj)
+                    for (int64_t bi = pi; bi < std::min<int64_t>(pi + PI, nt); ++bi) {
+                        if (bi > bj) continue;
+                        const int64_t t = bj * (bj + 1) / 2 + bi;
+                        items.push_back(int4{s, (int)bi, (int)bj, (int)(s * ntile + t)});
+                    }
+    const int64_t nb = cdiv((int64_t)items.size(), 256) * 256;
+    std::vector<int4> tab(nb, int4{-1, 0, 0, 0});
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t xcd = b % 8, j = b / 8;
+        const int64_t c = (j / 32) * 8 + xcd;
+        const int64_t item = c * 32 + j % 32;
+        if (item < (int64_t)items.size()) tab[b] = items[item];
+    }
+    return tab;
+}
+
+// splits of K: enough work items to fill 256 CUs in whole rounds
+static int pick_splits(int64_t ntile, int64_t K) {
+    int best = 1;
+    double best_eff = 0.0;
+    for (int s = 1; s <= 16; ++s) {
+        if (s > 1 && K / s < 2048) break;
+        const double items = (double)ntile * s;
+        const double eff = items / (std::ceil(items / 256.0) * 256.0);
+        if (eff > best_eff + 0.02) {
+            best_eff = eff;
+            best = s;
+        }
+    }
+    return best;
+}
+
 void launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
                           int64_t ldn, double* M, int64_t ldm, Workspace& ws) {
     if (dt == ELM_F32) {
         run_gram16<float, true>(s, L, N, (const float*)Hn, ldn, M, ldm, ws);
         return;
     }
-    const int64_t nt = cdiv(L, TILE);
+    const int64_t nt = cdiv(L, GT);
     const int64_t ntile = nt * (nt + 1) / 2;
-    int64_t kc_len;
-    int nchunk;
-    plan_chunks(ntile, N, 32, kc_len, nchunk);
-    float* part = (float*)ws.get("gram_part", (size_t)ntile * nchunk * TILE * TILE * sizeof(float));
-    dim3 grid((unsigned)ntile, (unsigned)nchunk);
+    const int nsplit = pick_splits(ntile, N);
+    const int64_t kc_len = cdiv(cdiv(N, nsplit), GBK) * GBK;
+    const int nsplit_eff = (int)cdiv(N, kc_len);
+    std::vector<int4> tab = gram_work_table(nt, nsplit_eff, ntile);
+    const std::string key = "gram_tab_" + std::to_string(L) + "_" + std::to_string(nsplit_eff);
+    int4* dtab = (int4*)ws.get(key, tab.size() * sizeof(int4));
+    ELM_HIP_TRY(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    ELM_HIP_TRY(hipStreamSynchronize(s));  // tab is a host temporary
+    float* part = (float*)ws.get("gram_part", (size_t)ntile * nsplit_eff * GT * GT * sizeof(float));
     {
         StageScope sc(ws.prof, ELM_STAGE_GRAM, s);
         if (dt == ELM_BF16)
-            gram_lp_kernel<__bf16><<<grid, NT, 0, s>>>(L, N, kc_len, (const __bf16*)Hn, ldn, part, ntile);
+            gram_lp256_kernel<__bf16><<<(unsigned)tab.size(), 256, 0, s>>>(L, N, kc_len, (const __bf16*)Hn,
+                                                                         ldn, part, dtab);
         else
-            gram_lp_kernel<_Float16><<<grid, NT, 0, s>>>(L, N, kc_len, (const _Float16*)Hn, ldn, part,
-                                                         ntile);
+            gram_lp256_kernel<_Float16><<<(unsigned)tab.size(), 256, 0, s>>>(L, N, kc_len,
+                                                                           (const _Float16*)Hn, ldn, part,
+                                                                           dtab);
         ELM_LAUNCH_CHECK();
     }
     StageScope sc(ws.prof, ELM_STAGE_GRAM_REDUCE, s);
-    gram_reduce_kernel<float><<<(unsigned)ntile, NT, 0, s>>>(L, part, ntile, nchunk, M, ldm);
+    gram_reduce256_kernel<<<dim3((unsigned)ntile, GT * GT / NT), NT, 0, s>>>(L, part, ntile, nsplit_eff,
+                                                                            M, ldm);
     ELM_LAUNCH_CHECK();
 }
 

@@ -39,23 +39,14 @@ __device__ inline bool better(double v1, int o1, double v2, int o2) {
     return v1 > v2 || (v1 == v2 && o1 < o2);
 }
 
-// all threads of the block end with the block-wide best (v, o, p)
-__device__ void block_argmax(double& v, int& o, int& p) {
+// all lanes of the wave end with the wave-wide best (v, o, p)
+__device__ inline void wave_argmax(double& v, int& o, int& p) {
     for (int off = 32; off > 0; off >>= 1) {
         double v2 = __shfl_xor(v, off);
         int o2 = __shfl_xor(o, off);
         int p2 = __shfl_xor(p, off);
         if (better(v2, o2, v, o)) { v = v2; o = o2; p = p2; }
     }
-    __shared__ double sv[PT / 64];
-    __shared__ int so[PT / 64], sp[PT / 64];
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { sv[w] = v; so[w] = o; sp[w] = p; }
-    __syncthreads();
-    v = sv[0]; o = so[0]; p = sp[0];
-    for (int q = 1; q < PT / 64; ++q)
-        if (better(sv[q], so[q], v, o)) { v = sv[q]; o = so[q]; p = sp[q]; }
-    __syncthreads();
 }
 
 struct Parts {
@@ -76,6 +67,9 @@ __global__ void fill_kernel(double* p, int64_t count, double v) {
         p[i] = v;
 }
 
+// partials are per wave: slot blockIdx.x * WPB + wave
+constexpr int WPB = PT / 64;
+
 __global__ __launch_bounds__(PT) void panel_start_kernel(int64_t n_rem, const double* __restrict__ S,
                                                          int64_t lds, double* __restrict__ d,
                                                          int* __restrict__ chosen, const int* rem0,
@@ -92,8 +86,11 @@ __global__ __launch_bounds__(PT) void panel_start_kernel(int64_t n_rem, const do
         if (!isfinite(x)) state[ST_BAD] = 1;
         v = x; o = rem[a]; p = (int)a;
     }
-    block_argmax(v, o, p);
-    if (threadIdx.x == 0) { out.v[blockIdx.x] = v; out.o[blockIdx.x] = o; out.p[blockIdx.x] = p; }
+    wave_argmax(v, o, p);
+    if ((threadIdx.x & 63) == 0) {
+        const int slot = blockIdx.x * WPB + (threadIdx.x >> 6);
+        out.v[slot] = v; out.o[slot] = o; out.p[slot] = p;
+    }
 }
 
 __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_rem,
@@ -105,12 +102,16 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
                                                   int* __restrict__ piv) {
     if (state[ST_DONE]) return;
     const int* rem = state[ST_CUR] ? rem1 : rem0;
-    // global pivot from the previous launch's per-block partials
+    const int lane = threadIdx.x & 63;
+    // global pivot: every wave reduces all of the previous launch's per-wave
+    // partials itself, so no block barrier is needed
     double bv = -INFINITY;
     int bo = INT_MAX, bp = -1;
-    for (int i = threadIdx.x; i < nparts; i += PT)
+    for (int i = lane; i < nparts; i += 64)
         if (better(in.v[i], in.o[i], bv, bo)) { bv = in.v[i]; bo = in.o[i]; bp = in.p[i]; }
-    block_argmax(bv, bo, bp);
+    wave_argmax(bv, bo, bp);
+    bp = __builtin_amdgcn_readfirstlane(bp);
+    bo = __builtin_amdgcn_readfirstlane(bo);
     if (!(bv > tau)) {  // largest remaining Schur diagonal at or below tau: rank = k
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             state[ST_RANK] = (int)k;
@@ -120,10 +121,6 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
         return;
     }
     const double rpp = sqrt(bv);
-    __shared__ double colp[NB];
-    for (int q = threadIdx.x; q < t; q += PT) colp[q] = P[(int64_t)q * ldp + bp];
-    __syncthreads();
-
     const int64_t a = (int64_t)blockIdx.x * PT + threadIdx.x;
     double v = -INFINITY;
     int o = INT_MAX, p = -1;
@@ -134,8 +131,22 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
         } else if (chosen[a]) {
             P[(int64_t)t * ldp + a] = 0.0;
         } else {
+            // S[p][a] - sum_{q < t} P[q][p] P[q][a]; P[q][p] is the same for the whole wave
             double s = S[(int64_t)bp * lds + a];
-            for (int q = 0; q < t; ++q) s -= colp[q] * P[(int64_t)q * ldp + a];
+            const double* __restrict__ pa = P + a;
+            const double* __restrict__ pp = P + bp;
+            int q = 0;
+            for (; q + 8 <= t; q += 8) {
+                double x[8], y[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    x[u] = pp[(int64_t)(q + u) * ldp];
+                    y[u] = pa[(int64_t)(q + u) * ldp];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s -= x[u] * y[u];
+            }
+            for (; q < t; ++q) s -= pp[(int64_t)q * ldp] * pa[(int64_t)q * ldp];
             const double val = s / rpp;
             P[(int64_t)t * ldp + a] = val;
             const double da = d[a] - val * val;
@@ -143,8 +154,11 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
             v = da; o = rem[a]; p = (int)a;
         }
     }
-    block_argmax(v, o, p);
-    if (threadIdx.x == 0) { out.v[blockIdx.x] = v; out.o[blockIdx.x] = o; out.p[blockIdx.x] = p; }
+    wave_argmax(v, o, p);
+    if (lane == 0) {
+        const int slot = blockIdx.x * WPB + (threadIdx.x >> 6);
+        out.v[slot] = v; out.o[slot] = o; out.p[slot] = p;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) piv[k] = bo;
 }
 
@@ -304,7 +318,7 @@ __global__ void gather_kernel(int64_t r, int64_t n, const double* __restrict__ R
 
 int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double tau,
                          int32_t* piv, double** R_out, Workspace& ws) {
-    const int64_t nparts_max = cdiv(n, PT);
+    const int64_t nparts_max = cdiv(n, PT) * WPB;
     int* state = (int*)ws.get("pc_state", ST_N * sizeof(int));
     int* rem0 = (int*)ws.get("pc_rem0", n * sizeof(int));
     int* rem1 = (int*)ws.get("pc_rem1", n * sizeof(int));
@@ -334,18 +348,19 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
     int64_t ps = 0, n_rem = n;
     while (ps < n) {
         const int nbp = (int)(n_rem < NB ? n_rem : NB);
-        const int nparts = (int)cdiv(n_rem, PT);
-        panel_start_kernel<<<nparts, PT, 0, s>>>(n_rem, Scur, lds, d, chosen, rem0, rem1,
+        const int nblk = (int)cdiv(n_rem, PT);
+        const int nparts = nblk * WPB;
+        panel_start_kernel<<<nblk, PT, 0, s>>>(n_rem, Scur, lds, d, chosen, rem0, rem1,
                                                  part[ps & 1], state);
         ELM_LAUNCH_CHECK();
         for (int t = 0; t < nbp; ++t) {
             const int64_t k = ps + t;
-            step_kernel<<<nparts, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
+            step_kernel<<<nblk, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
                                               part[k & 1], nparts, part[(k + 1) & 1], state, tau,
                                               piv);
             ELM_LAUNCH_CHECK();
         }
-        scatter_kernel<<<dim3((unsigned)nparts, (unsigned)nbp), PT, 0, s>>>(
+        scatter_kernel<<<dim3((unsigned)nblk, (unsigned)nbp), PT, 0, s>>>(
             ps, nbp, n_rem, P, n, rem0, rem1, Rorig, n, state);
         ELM_LAUNCH_CHECK();
         const int64_t n_new = n_rem - nbp;

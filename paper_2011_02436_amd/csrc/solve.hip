@@ -109,6 +109,90 @@ __global__ void zero_mat_kernel(int64_t rows, int64_t cols, double* __restrict__
     if (c < cols && i < rows) A[i * lda + c] = 0.0;
 }
 
+// C[i][c] = alpha * sum_k A[i][k] B[k][c] + beta * C[i][c] for thin B (m <= MM
+// columns): one wave per output row, lanes striding over k (coalesced reads
+// of A's row and of B's rows), fixed-order wave reduction.  tri restricts k
+// to the nonzero part of a triangular A (1: k >= i, 2: k <= i).
+template <int MM>
+__global__ __launch_bounds__(256) void rowprod_kernel(int64_t M, int64_t K, int m, double alpha,
+                                                      const double* __restrict__ A, int64_t lda,
+                                                      int tri, const double* __restrict__ B,
+                                                      int64_t ldb, double beta, double* C,
+                                                      int64_t ldc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= M) return;
+    int64_t kb = 0, ke = K;
+    if (tri == 1) kb = i;
+    if (tri == 2) ke = min(K, i + 1);
+    double acc[MM];
+#pragma unroll
+    for (int c = 0; c < MM; ++c) acc[c] = 0.0;
+    const double* __restrict__ arow = A + i * lda;
+    for (int64_t k = kb + lane; k < ke; k += 64) {
+        const double a = arow[k];
+        const double* __restrict__ brow = B + k * ldb;
+#pragma unroll
+        for (int c = 0; c < MM; ++c)
+            if (c < m) acc[c] += a * brow[c];
+    }
+#pragma unroll
+    for (int c = 0; c < MM; ++c) {
+        double v = acc[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        acc[c] = v;
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < MM; ++c)
+            if (c < m) {
+                double v = alpha * acc[c];
+                if (beta != 0.0) v += beta * C[i * ldc + c];
+                C[i * ldc + c] = v;
+            }
+}
+
+// B = A^T for an R x C matrix A (ld lda) into B (C x R, ld ldb)
+__global__ void transpose_kernel(int64_t R, int64_t Cn, const double* __restrict__ A, int64_t lda,
+                                 double* __restrict__ B, int64_t ldb) {
+    __shared__ double t[32][33];
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        const int64_t r = r0 + k, c = c0 + threadIdx.x;
+        if (r < R && c < Cn) t[k][threadIdx.x] = A[r * lda + c];
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        const int64_t c = c0 + k, r = r0 + threadIdx.x;
+        if (r < R && c < Cn) B[c * ldb + r] = t[threadIdx.x][k];
+    }
+}
+
+void rowprod(hipStream_t s, int64_t M, int64_t K, int64_t m, double alpha, const double* A, int64_t lda,
+             int tri, const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
+    if (M <= 0) return;
+    const unsigned grid = (unsigned)cdiv(M, 4);
+    const int mi = (int)m;
+    if (m <= 4)
+        rowprod_kernel<4><<<grid, 256, 0, s>>>(M, K, mi, alpha, A, lda, tri, B, ldb, beta, C, ldc);
+    else if (m <= 8)
+        rowprod_kernel<8><<<grid, 256, 0, s>>>(M, K, mi, alpha, A, lda, tri, B, ldb, beta, C, ldc);
+    else if (m <= 16)
+        rowprod_kernel<16><<<grid, 256, 0, s>>>(M, K, mi, alpha, A, lda, tri, B, ldb, beta, C, ldc);
+    else
+        rowprod_kernel<64><<<grid, 256, 0, s>>>(M, K, mi, alpha, A, lda, tri, B, ldb, beta, C, ldc);
+    ELM_LAUNCH_CHECK();
+}
+
+double* transposed_copy(hipStream_t s, int64_t R, int64_t Cn, const double* A, int64_t lda) {
+    double* B = nullptr;
+    ELM_HIP_TRY(hipMalloc(&B, (size_t)R * Cn * sizeof(double)));
+    transpose_kernel<<<dim3((unsigned)cdiv(Cn, 32), (unsigned)cdiv(R, 32)), dim3(32, 8), 0, s>>>(R, Cn, A,
+                                                                                                lda, B, R);
+    ELM_LAUNCH_CHECK();
+    return B;
+}
+
 void gather_rows(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds,
                  const int32_t* idx, double* dst, int64_t ldd) {
     if (rows <= 0 || cols <= 0) return;
@@ -159,8 +243,8 @@ void trtri_upper(hipStream_t s, int64_t r, const double* U, int64_t ldu, double*
 void apply_s_inv(hipStream_t s, const elm_factor* f, int64_t m, double* Y, Workspace& ws) {
     const int64_t q = f->q;
     double* t = (double*)ws.get("ap_sinv", (size_t)q * m * sizeof(double));
-    gemm_f64(s, q, m, q, 1.0, f->Usinv, 1, q, Y, m, 1, 0.0, t, m);       // t = Usinv^T Y
-    gemm_f64(s, q, m, q, 1.0, f->Usinv, q, 1, t, m, 1, 0.0, Y, m);       // Y = Usinv t
+    rowprod(s, q, q, m, 1.0, f->UsinvT, q, 2, Y, m, 0.0, t, m);     // t = Usinv^T Y
+    rowprod(s, q, q, m, 1.0, f->Usinv, q, 1, t, m, 0.0, Y, m);      // Y = Usinv t
 }
 
 // u (r x m) <- (G G^T)^-1 u = (I + K K^T)^-1 u
@@ -170,9 +254,9 @@ void apply_g_gram_inv(hipStream_t s, const elm_factor* f, int64_t m, double* u, 
     if (f->woodbury) {
         // (I + K K^T)^-1 = I - K (I + K^T K)^-1 K^T
         double* w = (double*)ws.get("ap_w", (size_t)c * m * sizeof(double));
-        gemm_f64(s, c, m, r, 1.0, f->K, 1, c, u, m, 1, 0.0, w, m);        // w = K^T u
-        apply_s_inv(s, f, m, w, ws);                                      // w = S'^-1 w
-        gemm_f64(s, r, m, c, -1.0, f->K, c, 1, w, m, 1, 1.0, u, m);       // u -= K w
+        rowprod(s, c, r, m, 1.0, f->KT, r, 0, u, m, 0.0, w, m);      // w = K^T u
+        apply_s_inv(s, f, m, w, ws);                                 // w = S'^-1 w
+        rowprod(s, r, c, m, -1.0, f->K, c, 0, w, m, 1.0, u, m);      // u -= K w
     } else {
         apply_s_inv(s, f, m, u, ws);
     }
@@ -182,8 +266,8 @@ void apply_g_gram_inv(hipStream_t s, const elm_factor* f, int64_t m, double* u, 
 void apply_f_gram_inv(hipStream_t s, const elm_factor* f, int64_t m, double* y, Workspace& ws) {
     const int64_t r = f->r;
     double* t = (double*)ws.get("ap_finv", (size_t)r * m * sizeof(double));
-    gemm_f64(s, r, m, r, 1.0, f->Rinv, 1, r, y, m, 1, 0.0, t, m);        // t = Rinv^T y
-    gemm_f64(s, r, m, r, 1.0, f->Rinv, r, 1, t, m, 1, 0.0, y, m);        // y = Rinv t
+    rowprod(s, r, r, m, 1.0, f->RinvT, r, 2, y, m, 0.0, t, m);      // t = Rinv^T y
+    rowprod(s, r, r, m, 1.0, f->Rinv, r, 1, t, m, 0.0, y, m);       // y = Rinv t
 }
 
 }  // namespace
@@ -193,9 +277,11 @@ void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws) {
     if (r == 0) return;
     ELM_HIP_TRY(hipMalloc(&f->Rinv, (size_t)r * r * sizeof(double)));
     trtri_upper(s, r, f->R, n, f->Rinv, r, ws);
+    f->RinvT = transposed_copy(s, r, r, f->Rinv, r);
     if (c > 0) {
         ELM_HIP_TRY(hipMalloc(&f->K, (size_t)r * c * sizeof(double)));
         gemm_f64(s, r, c, r, 1.0, f->Rinv, r, 1, f->R + r, n, 1, 0.0, f->K, c);   // K = R11^-1 R12
+        f->KT = transposed_copy(s, r, c, f->K, c);
     }
     const int64_t q = r < c ? r : c;
     f->q = q;
@@ -214,6 +300,7 @@ void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws) {
     ELM_LAUNCH_CHECK();
     ELM_HIP_TRY(hipMalloc(&f->Usinv, (size_t)q * q * sizeof(double)));
     trtri_upper(s, q, S, q, f->Usinv, q, ws);
+    f->UsinvT = transposed_copy(s, q, q, f->Usinv, q);
     int hflag = 0;
     ELM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));
@@ -239,7 +326,7 @@ void apply_pinv(hipStream_t s, const elm_factor* f, int64_t m, const double* rhs
         scatter_rows(s, r, m, u, m, f->piv, out, ldo);
         if (c > 0) {
             double* bd = (double*)ws.get("ap_bd", (size_t)c * m * sizeof(double));
-            gemm_f64(s, c, m, r, 1.0, f->K, 1, c, u, m, 1, 0.0, bd, m);
+            rowprod(s, c, r, m, 1.0, f->KT, r, 0, u, m, 0.0, bd, m);    // K^T u
             scatter_rows(s, c, m, bd, m, f->piv + r, out, ldo);
         }
         return;
@@ -249,7 +336,7 @@ void apply_pinv(hipStream_t s, const elm_factor* f, int64_t m, const double* rhs
     if (c > 0) {
         double* t2 = (double*)ws.get("ap_t2", (size_t)c * m * sizeof(double));
         gather_rows(s, c, m, rhs, ldr, f->piv + r, t2, m);
-        gemm_f64(s, r, m, c, 1.0, f->K, c, 1, t2, m, 1, 1.0, u, m);
+        rowprod(s, r, c, m, 1.0, f->K, c, 0, t2, m, 1.0, u, m);        // u += K rhs[piv[r:]]
     }
     apply_g_gram_inv(s, f, m, u, ws);                     // (G' G'^T)^-1
     apply_f_gram_inv(s, f, m, u, ws);                     // (F'^T F')^-1

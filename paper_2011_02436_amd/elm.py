@@ -67,6 +67,7 @@ def _load():
         "elm_hidden": ([vp, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, i32], i32),
         "elm_rank_factor": ([vp, i64, i64, vp, i64, i32, i32, dbl, ctypes.POINTER(vp),
                              ctypes.POINTER(i64)], i32),
+        "elm_gram": ([vp, i64, i64, vp, i64, i32, i32, vp, i64], i32),
         "elm_factor_rank": ([vp, ctypes.POINTER(i64)], i32),
         "elm_factor_pivots": ([vp, vp, ctypes.POINTER(i32)], i32),
         "elm_factor_destroy": ([vp], i32),
@@ -74,6 +75,7 @@ def _load():
                             ctypes.POINTER(SolveInfo)], i32),
         "elm_predict": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, vp],
                         i32),
+        "elm_predict_hidden": ([vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp], i32),
         "elm_profile_enable": ([vp, i32], i32),
         "elm_profile_read": ([vp, ctypes.POINTER(StageTimes)], i32),
     }
@@ -86,9 +88,9 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", "elm_last_error",
-            "elm_hidden", "elm_rank_factor", "elm_factor_rank", "elm_factor_pivots",
-            "elm_factor_destroy", "elm_pinv_solve", "elm_predict", "elm_profile_enable",
-            "elm_profile_read"]
+            "elm_hidden", "elm_gram", "elm_rank_factor", "elm_factor_rank", "elm_factor_pivots",
+            "elm_factor_destroy", "elm_pinv_solve", "elm_predict", "elm_predict_hidden",
+            "elm_profile_enable", "elm_profile_read"]
 
 
 def _status_string(st: int) -> str:
@@ -185,6 +187,24 @@ def elm_hidden(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor,
         lp, ldlp, lpdt = ctypes.c_void_p(), 0, ELM_BF16
     h.check(_lib.elm_hidden(h.ptr, N, d, L, xp, ldx, wp, ldw, bp, _DT[X.dtype], hp, ldh, lp, ldlp,
                             lpdt), "elm_hidden")
+
+
+def elm_gram(H: torch.Tensor, layout: str = "sample") -> torch.Tensor:
+    """The FP64 Gram (H^T H, or H H^T when N < L) of a sample-major FP64 H or a
+    node-major low-precision copy."""
+    h = handle()
+    if layout == "sample":
+        N, L = H.shape
+        lay = ELM_SAMPLE_MAJOR
+    else:
+        L, N = H.shape
+        lay = ELM_NODE_MAJOR
+    n = min(N, L)
+    M = torch.empty((n, n), dtype=torch.float64, device=H.device)
+    hp, ldh = _mat(H, "H")
+    mp, ldm = _mat(M, "M")
+    h.check(_lib.elm_gram(h.ptr, N, L, hp, ldh, _DT[H.dtype], lay, mp, ldm), "elm_gram")
+    return M
 
 
 class Factor:
@@ -295,6 +315,26 @@ def profile_read() -> dict:
     st = StageTimes()
     h.check(_lib.elm_profile_read(h.ptr, ctypes.byref(st)), "elm_profile_read")
     return {name: (float(st.ms[i]), int(st.count[i])) for i, name in enumerate(STAGES)}
+
+
+def elm_predict_hidden(H: torch.Tensor, beta: torch.Tensor, want_Y: bool = True,
+                       want_labels: bool = True):
+    """Y = H beta and arg-max labels from a stored FP64 sample-major H."""
+    h = handle()
+    N, L = H.shape
+    m = beta.shape[1]
+    if H.dtype != torch.float64 or beta.dtype != torch.float64:
+        raise ValueError("H and beta must be float64")
+    if beta.shape[0] != L:
+        raise ValueError("beta must have L rows")
+    hp, ldh = _mat(H, "H")
+    bp, ldb = _mat(beta, "beta")
+    Y = torch.empty((N, m), dtype=torch.float64, device=H.device) if want_Y else None
+    labels = torch.empty(N, dtype=torch.int32, device=H.device) if want_labels else None
+    yp, ldy = (ctypes.c_void_p(), 0) if Y is None else _mat(Y, "Y")
+    lp = ctypes.c_void_p() if labels is None else ctypes.c_void_p(labels.data_ptr())
+    h.check(_lib.elm_predict_hidden(h.ptr, N, L, m, hp, ldh, bp, ldb, yp, ldy, lp), "elm_predict_hidden")
+    return Y, labels
 
 
 # ----------------------------------------------------------------------------

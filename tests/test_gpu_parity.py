@@ -220,3 +220,45 @@ def test_dedup_closed_form_mixture_shape(elm):
     print(f"mixture N=8000 L=600: rank {res.rank} (structural {p.structural_rank}), err {err:.2e}")
     assert res.rank == p.structural_rank == 540
     assert err <= 1e-10
+
+
+# ----------------------------------------------------------------------------
+# Gram kernels on their own (multi-tile, split-K, ragged edges)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("N,L", [(2000, 200), (20011, 600), (5000, 257), (70000, 530), (900, 1200)])
+def test_gram_fp64_matches_numpy(elm, N, L):
+    rng = np.random.default_rng(N + L)
+    Hn = rng.uniform(0, 1, (N, L))
+    H = to_dev(Hn)
+    M = elm.elm_gram(H, "sample").cpu().numpy()
+    ref = Hn.T @ Hn if N >= L else Hn @ Hn.T
+    assert np.array_equal(M, M.T)
+    assert np.max(np.abs(M - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("lp", ["bf16", "fp16", "fp32"])
+@pytest.mark.parametrize("N,L", [(2000, 200), (20011, 600), (70000, 530), (6001, 777)])
+def test_gram_lowprec_matches_fp64_of_rounded_input(elm, lp, N, L):
+    rng = np.random.default_rng(N * 3 + L)
+    H64 = rng.uniform(0, 1, (N, L))
+    H64[:, 5] = H64[:, 3]                      # a duplicated column
+    dt = {"bf16": torch.bfloat16, "fp16": torch.float16, "fp32": torch.float32}[lp]
+    Hn = to_dev(H64.T.copy()).to(dt)           # node-major copy
+    Hr = Hn.double().cpu().numpy()             # the values the kernel sees
+    M = elm.elm_gram(Hn, "node").cpu().numpy()
+    ref = Hr @ Hr.T
+    assert np.array_equal(M, M.T)
+    # FP32 accumulation within each split-K chunk, FP64 across chunks
+    assert np.max(np.abs(M - ref)) <= 2e-6 * np.max(np.abs(ref))
+    # bitwise-equal input columns give bitwise-equal Gram rows
+    assert np.array_equal(M[5], M[3])
+
+
+def test_predict_hidden_matches_numpy(elm):
+    rng = np.random.default_rng(2)
+    H = rng.uniform(0, 1, (1000, 130))
+    beta = rng.standard_normal((130, 7))
+    Y, lab = elm.elm_predict_hidden(to_dev(H), to_dev(beta))
+    ref = H @ beta
+    assert np.max(np.abs(Y.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert np.array_equal(lab.cpu().numpy(), np.argmax(ref, axis=1))
