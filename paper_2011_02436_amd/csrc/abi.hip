@@ -394,10 +394,7 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
         if (!f->transposed) {
             {
                 elm::StageScope sc(pr, ELM_STAGE_RHS, s);
-                // H^T T, eq. (8)
-                if (!elm::launch_fused_ht_resid(s, N, L, m, H64, ldh64, T, ldt, nullptr, 0, Z, m, nrm,
-                                                ws, h->num_cu))
-                    elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);
+                elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);   // H^T T, eq. (8)
             }
             elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
             elm::apply_pinv(s, f, m, Z, m, H64, ldh64, beta, ldbeta, ws);
@@ -421,18 +418,12 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
         double res = 0;
         int it = 0;
         for (;;) {
-            // G = H^T (T - H beta): one fused pass when N >= L, else E is needed too
-            bool fused = false;
-            if (!f->transposed) {
-                elm::StageScope sc(pr, ELM_STAGE_RHS, s);
-                fused = elm::launch_fused_ht_resid(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, G, m,
-                                                   nrm + 1, ws, h->num_cu);
+            // G = H^T (T - H beta): two streaming passes over H
+            {
+                elm::StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
+                elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m);
             }
-            if (!fused) {
-                {
-                    elm::StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
-                    elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m);
-                }
+            {
                 elm::StageScope sc(pr, ELM_STAGE_RHS, s);
                 elm::launch_ht_times(s, N, L, m, H64, ldh64, E, m, G, m, nrm + 1, ws);
             }

@@ -261,72 +261,41 @@ void run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, dou
 // Each block owns one work item (split-K chunk, tile bi <= bj) from a table
 // built on the host.  4 waves in a 2 x 2 grid each accumulate a 128 x 128
 // sub-tile as 4 x 4 blocks of the 32x32x16 MFMA (256 FP32 accumulators per
-// lane).  K is consumed in chunks of 64 samples through two LDS stages: the
-// next chunk's global loads are in flight while the current one feeds the
-// MFMAs.  In LDS each tile row holds 8 chunks of 16 B; chunk c of row i sits
-// at position c ^ (i & 7) so the 32 rows an MFMA operand read touches spread
-// over all banks.  Diagonal tiles read B from A's copy of the same rows
-// (both copies are loaded; only the read side is shared).
+// lane, in AGPRs).  K is consumed in stages of 32 samples through 4 LDS
+// buffers filled by direct global->LDS loads (global_load_lds_dwordx4) issued
+// three stages ahead: no staging registers, and the loads of later stages
+// stay in flight across the per-stage barrier (an explicit vmcnt wait plus a
+// bare s_barrier; a full __syncthreads would drain them).  Every stage issues
+// the same number of loads (past the last full stage they re-read it into a
+// buffer nobody reads again), so the wait count is static.
+// In LDS a tile row is 4 chunks of 16 B; chunk c of row r sits at position
+// c ^ ((r >> 1) & 3), spreading the rows an MFMA operand read touches over
+// the banks.  Ragged tiles, the K tail and unaligned input take a plain path.
 // ---------------------------------------------------------------------------
-constexpr int GT = 256;   // tile
-constexpr int GBK = 64;   // samples per LDS stage
-constexpr int G_CHUNKS = GT * GBK * 2 / 16;  // 16-byte chunks per operand per stage (2048)
+constexpr int GT = 256;    // tile
+constexpr int GBK = 32;    // samples per stage
+constexpr int GNS = 4;     // LDS stages
+constexpr int G_OPB = GT * GBK * 2;            // bytes per operand per stage (16 KB)
+constexpr int G_STB = 2 * G_OPB;               // bytes per stage (32 KB)
+#define G_VMCNT(N) (((N) & 15) | (((N) >> 4) << 14) | (7 << 4) | (15 << 8))
+
+typedef __attribute__((address_space(3))) void lds_void;
 
 template <typename HT>
 __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, int64_t kc_len,
                                                          const HT* __restrict__ A, int64_t ld,
                                                          float* __restrict__ part,
                                                          const int4* __restrict__ work) {
-    __shared__ uint4 smem[2 * 2 * G_CHUNKS];  // 2 stages x (A, B) x 32 KB = 128 KB
+    __shared__ __attribute__((aligned(1024))) unsigned char smem[GNS * G_STB];  // 128 KB
     typedef typename Mfma32<HT>::vec_t vec_t;
     const int4 wk = work[blockIdx.x];
     if (wk.x < 0) return;
     const int64_t r0 = (int64_t)wk.y * GT, c0 = (int64_t)wk.z * GT;
-    const bool diag = wk.y == wk.z;
     const int64_t kbeg = (int64_t)wk.x * kc_len;
     const int64_t kend = min(K, kbeg + kc_len);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const bool vec_ok = ((ld & 7) == 0) && ((((uintptr_t)A) & 15) == 0);
-
-    // two register sets of staged loads: the chunk two stages ahead is in
-    // flight while the current one feeds the MFMAs (one wave per SIMD, so
-    // the staging registers are what hides global-memory latency)
-    uint4 ra0[8], rb0[8], ra1[8], rb1[8];
-    auto load_chunk = [&](int64_t grow, int64_t gk) -> uint4 {
-        if (grow < n && vec_ok && gk + 8 <= kend) return *(const uint4*)(A + grow * ld + gk);
-        {
-            const uint16_t* A16 = (const uint16_t*)A;
-            auto el = [&](int e) -> uint32_t {
-                return (grow < n && gk + e < kend) ? (uint32_t)A16[grow * ld + gk + e] : 0u;
-            };
-            return make_uint4(el(0) | (el(1) << 16), el(2) | (el(3) << 16), el(4) | (el(5) << 16),
-                              el(6) | (el(7) << 16));
-        }
-    };
-#define GRAM_GLOAD(K0, RA, RB)                                                    \
-    do {                                                                          \
-        const int64_t k0_ = (K0);                                                 \
-        if (k0_ < kend) {                                                         \
-            _Pragma("unroll") for (int it = 0; it < 8; ++it) {                    \
-                const int q = tid + 256 * it;                                     \
-                const int row = q >> 3;                                           \
-                const int c = (q & 7) ^ (row & 7);                                \
-                RA[it] = load_chunk(r0 + row, k0_ + c * 8);                       \
-                RB[it] = load_chunk(c0 + row, k0_ + c * 8);            \
-            }                                                                     \
-        }                                                                         \
-    } while (0)
-#define GRAM_SWRITE(STAGE, RA, RB)                                                \
-    do {                                                                          \
-        uint4* sA_ = smem + (STAGE) * 2 * G_CHUNKS;                               \
-        uint4* sB_ = sA_ + G_CHUNKS;                                              \
-        _Pragma("unroll") for (int it = 0; it < 8; ++it) {                        \
-            const int q = tid + 256 * it;                                         \
-            sA_[q] = RA[it];                                                      \
-            sB_[q] = RB[it];                                           \
-        }                                                                         \
-    } while (0)
 
     f16v acc[4][4];
 #pragma unroll
@@ -334,51 +303,100 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = f16v{};
 
-#define GRAM_COMPUTE(STAGE)                                                                \
+    // one stage from LDS buffer ST: read both k16 steps' fragments, then MFMAs
+#define GRAM_COMPUTE(ST)                                                                   \
     do {                                                                                   \
-        const uint4* sA = smem + (STAGE) * 2 * G_CHUNKS;                                   \
-        const uint4* sB = diag ? sA : sA + G_CHUNKS;                                       \
-        _Pragma("unroll") for (int kk = 0; kk < 4; ++kk) {                                 \
-            const int c = kk * 2 + (lane >> 5);                                            \
-            vec_t a[4], b[4];                                                              \
-            _Pragma("unroll") for (int x = 0; x < 4; ++x) {                                \
-                const int ra_row = wm * 128 + x * 32 + (lane & 31);                        \
-                const int rb_row = wn * 128 + x * 32 + (lane & 31);                        \
-                a[x] = *(const vec_t*)&sA[ra_row * 8 + (c ^ (ra_row & 7))];                \
-                b[x] = *(const vec_t*)&sB[rb_row * 8 + (c ^ (rb_row & 7))];                \
-            }                                                                              \
-            _Pragma("unroll") for (int x = 0; x < 4; ++x)                                  \
-                _Pragma("unroll") for (int y = 0; y < 4; ++y)                              \
-                    acc[x][y] = Mfma32<HT>::op(a[x], b[y], acc[x][y]);                     \
+        const unsigned char* sA = smem + (ST) * G_STB;                                     \
+        const unsigned char* sB = sA + G_OPB;                                              \
+        vec_t a0[4], b0[4], a1[4], b1[4];                                                  \
+        _Pragma("unroll") for (int x = 0; x < 4; ++x) {                                    \
+            const int ra = wm * 128 + x * 32 + (lane & 31);                                \
+            const int rb = wn * 128 + x * 32 + (lane & 31);                                \
+            const int c = lane >> 5;                                                       \
+            a0[x] = *(const vec_t*)(sA + ra * 64 + ((c ^ ((ra >> 1) & 3)) << 4));          \
+            b0[x] = *(const vec_t*)(sB + rb * 64 + ((c ^ ((rb >> 1) & 3)) << 4));          \
+            a1[x] = *(const vec_t*)(sA + ra * 64 + (((c + 2) ^ ((ra >> 1) & 3)) << 4));    \
+            b1[x] = *(const vec_t*)(sB + rb * 64 + (((c + 2) ^ ((rb >> 1) & 3)) << 4));    \
         }                                                                                  \
+        _Pragma("unroll") for (int x = 0; x < 4; ++x)                                      \
+            _Pragma("unroll") for (int y = 0; y < 4; ++y)                                  \
+                acc[x][y] = Mfma32<HT>::op(a0[x], b0[y], acc[x][y]);                       \
+        _Pragma("unroll") for (int x = 0; x < 4; ++x)                                      \
+            _Pragma("unroll") for (int y = 0; y < 4; ++y)                                  \
+                acc[x][y] = Mfma32<HT>::op(a1[x], b1[y], acc[x][y]);                       \
     } while (0)
 
-    // prologue: stage 0 to LDS, stage 1 in set 1, stage 2 in set 0
-    GRAM_GLOAD(kbeg, ra0, rb0);
-    GRAM_SWRITE(0, ra0, rb0);
-    GRAM_GLOAD(kbeg + GBK, ra1, rb1);
-    GRAM_GLOAD(kbeg + 2 * GBK, ra0, rb0);
-    __syncthreads();
-    // iteration i computes LDS stage i % 2, then stores the set holding chunk
-    // i + 1 and refills it with chunk i + 3; unrolled by two so each set is
-    // named statically; an odd last stage is handled after the loop
-    const int64_t nst = (kend - kbeg + GBK - 1) / GBK;
-    int64_t st = 0;
-    for (; st + 2 <= nst; st += 2) {
-        GRAM_COMPUTE(0);
-        GRAM_SWRITE(1, ra1, rb1);
-        GRAM_GLOAD(kbeg + (st + 3) * GBK, ra1, rb1);
-        __syncthreads();
-        GRAM_COMPUTE(1);
-        if (st + 2 < nst) {
-            GRAM_SWRITE(0, ra0, rb0);
-            GRAM_GLOAD(kbeg + (st + 4) * GBK, ra0, rb0);
+    const bool interior = vec_ok && r0 + GT <= n && c0 + GT <= n;  // block-uniform
+    const int64_t nfull = interior ? (kend - kbeg) / GBK : 0;
+    if (nfull > 0) {
+        // DMA lane mapping: instruction i of wave w fills LDS bytes
+        // [(4 i + w) * 1024, +1024) of an operand buffer = rows (4 i + w) * 16
+        // .. +16, lane l -> row (4 i + w) * 16 + l / 4, position l % 4, which
+        // holds global chunk (l % 4) ^ ((row >> 1) & 3).
+        const HT* asrc[4];
+        const HT* bsrc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = (4 * i + wave) * 16 + (lane >> 2);
+            const int c = (lane & 3) ^ ((row >> 1) & 3);
+            asrc[i] = A + (r0 + row) * ld + c * 8;
+            bsrc[i] = A + (c0 + row) * ld + c * 8;
+        }
+        const int64_t klast = kbeg + (nfull - 1) * GBK;
+#define GRAM_DMA(STG, K0)                                                                    \
+    do {                                                                                     \
+        const int64_t k_ = min((int64_t)(K0), klast);                                        \
+        unsigned char* dA = smem + ((STG) % GNS) * G_STB + wave * 1024;                      \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                      \
+            __builtin_amdgcn_global_load_lds((const void*)(asrc[i] + k_),                    \
+                                             (lds_void*)(dA + i * 4096), 16, 0, 0);          \
+            __builtin_amdgcn_global_load_lds((const void*)(bsrc[i] + k_),                    \
+                                             (lds_void*)(dA + G_OPB + i * 4096), 16, 0, 0);  \
+        }                                                                                    \
+    } while (0)
+        GRAM_DMA(0, kbeg);
+        GRAM_DMA(1, kbeg + GBK);
+        GRAM_DMA(2, kbeg + 2 * GBK);
+        for (int64_t st = 0; st < nfull; ++st) {
+            // stage st landed (two later stages may still be in flight), and
+            // every wave is done with buffer (st - 1) % GNS before it is refilled
+            __builtin_amdgcn_s_waitcnt(G_VMCNT(16));
+            __builtin_amdgcn_s_barrier();
+            GRAM_DMA(st + 3, kbeg + (st + 3) * GBK);
+            GRAM_COMPUTE((int)(st % GNS));
+        }
+        __builtin_amdgcn_s_waitcnt(G_VMCNT(0));
+        __builtin_amdgcn_s_barrier();
+#undef GRAM_DMA
+    }
+    // what the DMA path did not cover: the K tail of an interior item, or a
+    // whole ragged/unaligned item, one stage at a time through registers
+    for (int64_t k0 = kbeg + nfull * GBK; k0 < kend; k0 += GBK) {
+        const uint16_t* A16 = (const uint16_t*)A;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = tid + 256 * i;        // 16-byte slot in the operand buffer
+            const int row = q >> 2;
+            const int c = (q & 3) ^ ((row >> 1) & 3);
+            uint32_t wa[4], wb[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t k = k0 + c * 8 + 2 * e;
+                const int64_t ga = r0 + row, gb = c0 + row;
+                const uint32_t alo = (ga < n && k < kend) ? A16[ga * ld + k] : 0u;
+                const uint32_t ahi = (ga < n && k + 1 < kend) ? A16[ga * ld + k + 1] : 0u;
+                const uint32_t blo = (gb < n && k < kend) ? A16[gb * ld + k] : 0u;
+                const uint32_t bhi = (gb < n && k + 1 < kend) ? A16[gb * ld + k + 1] : 0u;
+                wa[e] = alo | (ahi << 16);
+                wb[e] = blo | (bhi << 16);
+            }
+            *(uint4*)(smem + q * 16) = make_uint4(wa[0], wa[1], wa[2], wa[3]);
+            *(uint4*)(smem + G_OPB + q * 16) = make_uint4(wb[0], wb[1], wb[2], wb[3]);
         }
         __syncthreads();
+        GRAM_COMPUTE(0);
+        __syncthreads();
     }
-    if (st < nst) GRAM_COMPUTE(0);
-#undef GRAM_GLOAD
-#undef GRAM_SWRITE
 #undef GRAM_COMPUTE
 
     float* out = part + (int64_t)wk.w * (GT * GT);

@@ -100,15 +100,31 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
                                                   const int* rem0, const int* rem1, Parts in,
                                                   int nparts, Parts out, int* state, double tau,
                                                   int* __restrict__ piv) {
-    if (state[ST_DONE]) return;
-    const int* rem = state[ST_CUR] ? rem1 : rem0;
+    // The kernel is a chain of dependent memory round trips, so loads that do
+    // not depend on each other are issued together: (flags, all partials),
+    // then (S row entry, d, chosen, rem, the panel column).
     const int lane = threadIdx.x & 63;
-    // global pivot: every wave reduces all of the previous launch's per-wave
-    // partials itself, so no block barrier is needed
+    const int done = state[ST_DONE];
+    const int cur = state[ST_CUR];
+    // every wave reduces all of the previous launch's per-wave partials itself
+    double pv[4];
+    int po[4], pq[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int i = lane + 64 * j;
+        const bool ok = i < nparts;
+        pv[j] = ok ? in.v[i] : -INFINITY;
+        po[j] = ok ? in.o[i] : INT_MAX;
+        pq[j] = ok ? in.p[i] : -1;
+    }
     double bv = -INFINITY;
     int bo = INT_MAX, bp = -1;
-    for (int i = lane; i < nparts; i += 64)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (better(pv[j], po[j], bv, bo)) { bv = pv[j]; bo = po[j]; bp = pq[j]; }
+    for (int i = lane + 256; i < nparts; i += 64)
         if (better(in.v[i], in.o[i], bv, bo)) { bv = in.v[i]; bo = in.o[i]; bp = in.p[i]; }
+    if (done) return;
     wave_argmax(bv, bo, bp);
     bp = __builtin_amdgcn_readfirstlane(bp);
     bo = __builtin_amdgcn_readfirstlane(bo);
@@ -122,36 +138,41 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
     }
     const double rpp = sqrt(bv);
     const int64_t a = (int64_t)blockIdx.x * PT + threadIdx.x;
+    const int64_t ac = a < n_rem ? a : n_rem - 1;  // in-bounds twin for the batched loads
+    double s = S[(int64_t)bp * lds + ac];
+    const double d_a = d[ac];
+    const int ch = chosen[ac];
+    const int ra = cur ? rem1[ac] : rem0[ac];
+    // S[p][a] - sum_{q < t} P[q][p] P[q][a]; P[q][p] is the same for the whole
+    // wave.  Chunks of 16 keep 32 loads in flight.
+    const double* __restrict__ pa = P + ac;
+    const double* __restrict__ pp = P + bp;
+    int q = 0;
+    for (; q + 16 <= t; q += 16) {
+        double x[16], y[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            x[u] = pp[(int64_t)(q + u) * ldp];
+            y[u] = pa[(int64_t)(q + u) * ldp];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s -= x[u] * y[u];
+    }
+    for (; q < t; ++q) s -= pp[(int64_t)q * ldp] * pa[(int64_t)q * ldp];
     double v = -INFINITY;
     int o = INT_MAX, p = -1;
     if (a < n_rem) {
         if (a == bp) {
             P[(int64_t)t * ldp + a] = rpp;
             chosen[a] = 1;
-        } else if (chosen[a]) {
+        } else if (ch) {
             P[(int64_t)t * ldp + a] = 0.0;
         } else {
-            // S[p][a] - sum_{q < t} P[q][p] P[q][a]; P[q][p] is the same for the whole wave
-            double s = S[(int64_t)bp * lds + a];
-            const double* __restrict__ pa = P + a;
-            const double* __restrict__ pp = P + bp;
-            int q = 0;
-            for (; q + 8 <= t; q += 8) {
-                double x[8], y[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    x[u] = pp[(int64_t)(q + u) * ldp];
-                    y[u] = pa[(int64_t)(q + u) * ldp];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) s -= x[u] * y[u];
-            }
-            for (; q < t; ++q) s -= pp[(int64_t)q * ldp] * pa[(int64_t)q * ldp];
             const double val = s / rpp;
             P[(int64_t)t * ldp + a] = val;
-            const double da = d[a] - val * val;
+            const double da = d_a - val * val;
             d[a] = da;
-            v = da; o = rem[a]; p = (int)a;
+            v = da; o = ra; p = (int)a;
         }
     }
     wave_argmax(v, o, p);

@@ -289,6 +289,125 @@ __global__ __launch_bounds__(FT) void fused_ht_resid_kernel(int64_t N, int64_t L
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Streaming passes built for HBM bandwidth.
+//
+// rows_dot_kernel: out[row][o] = sign * (H beta)[row][o] + (T ? T[row][o] : 0)
+//   for RB rows per block; thread t walks columns t, t + 256, ... keeping
+//   RB x MM partial sums, so each beta row it loads (through the cache) serves
+//   RB rows of H; one block reduction at the end.  With labels, also the
+//   arg-max of each row (lowest index on ties).
+// cols_dot_kernel: part[chunk][col][o] = sum over the chunk's rows of
+//   H[row][col] E[row][o]; thread per column, the chunk's E rows in LDS.
+// ---------------------------------------------------------------------------
+constexpr int SB = 256;   // threads per block
+constexpr int RBR = 8;    // rows per block, rows_dot_kernel
+constexpr int CR_ROWS = 1024;  // rows per chunk, cols_dot_kernel
+
+template <int MM>
+__global__ __launch_bounds__(SB) void rows_dot_kernel(int64_t N, int64_t L, int m,
+                                                      const double* __restrict__ H, int64_t ldh,
+                                                      const double* __restrict__ beta, int64_t ldb,
+                                                      const double* __restrict__ T, int64_t ldt,
+                                                      double sign, double* __restrict__ out,
+                                                      int64_t ldo, int32_t* __restrict__ labels) {
+    __shared__ double red[SB / 64][RBR * MM];
+    __shared__ double fin[RBR * MM];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * RBR;
+    double acc[RBR][MM];
+#pragma unroll
+    for (int r = 0; r < RBR; ++r)
+#pragma unroll
+        for (int c = 0; c < MM; ++c) acc[r][c] = 0.0;
+    const double* __restrict__ hrow[RBR];
+#pragma unroll
+    for (int r = 0; r < RBR; ++r) hrow[r] = H + min(r0 + r, N - 1) * ldh;
+    for (int64_t col = tid; col < L; col += SB) {
+        double bv[MM];
+#pragma unroll
+        for (int c = 0; c < MM; ++c) bv[c] = c < m ? beta[col * ldb + c] : 0.0;
+#pragma unroll
+        for (int r = 0; r < RBR; ++r) {
+            const double h = hrow[r][col];
+#pragma unroll
+            for (int c = 0; c < MM; ++c) acc[r][c] += h * bv[c];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RBR; ++r)
+#pragma unroll
+        for (int c = 0; c < MM; ++c) {
+            double v = acc[r][c];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) red[wave][r * MM + c] = v;
+        }
+    __syncthreads();
+    if (tid < RBR * MM) {
+        double v = 0.0;
+        for (int w = 0; w < SB / 64; ++w) v += red[w][tid];
+        const int r = tid / MM, c = tid % MM;
+        const int64_t row = r0 + r;
+        double o = sign * v;
+        if (T && row < N && c < m) o += T[row * ldt + c];
+        fin[tid] = o;
+        if (out && row < N && c < m) out[row * ldo + c] = o;
+    }
+    if (labels) {
+        __syncthreads();
+        if (tid < RBR && r0 + tid < N) {
+            int best = 0;
+            double bvv = fin[tid * MM];
+            for (int c = 1; c < m; ++c)
+                if (fin[tid * MM + c] > bvv) { bvv = fin[tid * MM + c]; best = c; }
+            labels[r0 + tid] = best;
+        }
+    }
+}
+
+template <int MM>
+__global__ __launch_bounds__(SB) void cols_dot_kernel(int64_t N, int64_t L, int m,
+                                                      const double* __restrict__ H, int64_t ldh,
+                                                      const double* __restrict__ E, int64_t lde,
+                                                      double* __restrict__ part) {
+    __shared__ double Es[CR_ROWS * MM];
+    const int tid = threadIdx.x;
+    const int64_t col = (int64_t)blockIdx.x * SB + tid;
+    const int64_t rbeg = (int64_t)blockIdx.y * CR_ROWS;
+    const int nrows = (int)min<int64_t>(CR_ROWS, N - rbeg);
+    for (int e = tid; e < CR_ROWS * MM; e += SB) {
+        const int r = e / MM, c = e % MM;
+        Es[e] = (r < nrows && c < m) ? E[(rbeg + r) * lde + c] : 0.0;
+    }
+    __syncthreads();
+    double acc[MM];
+#pragma unroll
+    for (int c = 0; c < MM; ++c) acc[c] = 0.0;
+    if (col < L) {
+        const double* __restrict__ hp = H + rbeg * ldh + col;
+        int r = 0;
+        for (; r + 8 <= nrows; r += 8) {
+            double h[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) h[u] = hp[(int64_t)(r + u) * ldh];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < MM; ++c) acc[c] += h[u] * Es[(r + u) * MM + c];
+        }
+        for (; r < nrows; ++r) {
+            const double hv = hp[(int64_t)r * ldh];
+#pragma unroll
+            for (int c = 0; c < MM; ++c) acc[c] += hv * Es[r * MM + c];
+        }
+        double* o = part + (int64_t)blockIdx.y * L * m + col * m;
+#pragma unroll
+        for (int c = 0; c < MM; ++c)
+            if (c < m) o[c] = acc[c];
+    }
+}
+
 // G[i][o] = sum over chunks of the partials; per-block sum of squares
 __global__ __launch_bounds__(NT) void ht_reduce_kernel(int64_t L, int m, int nchunk,
                                                        const double* __restrict__ part,
@@ -338,55 +457,74 @@ __global__ void axpy_mat_kernel(int64_t rows, int64_t cols, const double* __rest
 
 }  // namespace
 
+static void launch_rows_dot(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
+                            int64_t ldh, const double* beta, int64_t ldb, const double* T, int64_t ldt,
+                            double sign, double* out, int64_t ldo, int32_t* labels) {
+    const unsigned grid = (unsigned)cdiv(N, RBR);
+    const int mi = (int)m;
+    if (m <= 2)
+        rows_dot_kernel<2><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels);
+    else if (m <= 4)
+        rows_dot_kernel<4><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels);
+    else if (m <= 8)
+        rows_dot_kernel<8><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels);
+    else if (m <= 16)
+        rows_dot_kernel<16><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels);
+    else
+        throw Error{ELM_ERR_UNSUPPORTED, "m > 16 on the streaming row pass"};
+    ELM_LAUNCH_CHECK();
+}
+
 void launch_residual(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
                      const double* T, int64_t ldt, const double* beta, int64_t ldb, double* E,
                      int64_t lde) {
+    if (m <= 16) {
+        launch_rows_dot(s, N, L, m, H, ldh, beta, ldb, T, ldt, -1.0, E, lde, nullptr);
+        return;
+    }
     const unsigned grid = (unsigned)cdiv(N, RT);
-    const int mi = (int)m;
-    if (m <= 4)
-        residual_kernel<1><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, T, ldt, beta, ldb, E, lde);
-    else if (m <= 8)
-        residual_kernel<2><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, T, ldt, beta, ldb, E, lde);
-    else if (m <= 16)
-        residual_kernel<4><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, T, ldt, beta, ldb, E, lde);
-    else
-        residual_kernel<16><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, T, ldt, beta, ldb, E, lde);
+    residual_kernel<16><<<grid, NT, 0, s>>>(N, L, (int)m, H, ldh, T, ldt, beta, ldb, E, lde);
     ELM_LAUNCH_CHECK();
 }
 
 void launch_hidden_output(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
                           int64_t ldh, const double* beta, int64_t ldb, double* Y, int64_t ldy,
                           int32_t* labels) {
+    if (m <= 16) {
+        launch_rows_dot(s, N, L, m, H, ldh, beta, ldb, nullptr, 0, 1.0, Y, ldy, labels);
+        return;
+    }
     const unsigned grid = (unsigned)cdiv(N, RT);
-    const int mi = (int)m;
-    if (m <= 4)
-        hidden_output_kernel<1><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, beta, ldb, Y, ldy, labels);
-    else if (m <= 8)
-        hidden_output_kernel<2><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, beta, ldb, Y, ldy, labels);
-    else if (m <= 16)
-        hidden_output_kernel<4><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, beta, ldb, Y, ldy, labels);
-    else
-        hidden_output_kernel<16><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, beta, ldb, Y, ldy, labels);
+    hidden_output_kernel<16><<<grid, NT, 0, s>>>(N, L, (int)m, H, ldh, beta, ldb, Y, ldy, labels);
     ELM_LAUNCH_CHECK();
 }
 
 void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
                      const double* E, int64_t lde, double* G, int64_t ldg, double* nrm2,
                      Workspace& ws) {
-    const int nchunk = (int)cdiv(N, HT_ROWS);
-    double* part = (double*)ws.get("ht_part", (size_t)nchunk * L * m * sizeof(double));
     const unsigned nred = (unsigned)cdiv(L * m, NT);
     double* sq = (double*)ws.get("ht_sq", (size_t)nred * sizeof(double));
-    dim3 grid((unsigned)cdiv(L, CT), (unsigned)nchunk);
     const int mi = (int)m;
-    if (m <= 4)
-        ht_kernel<1><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
-    else if (m <= 8)
-        ht_kernel<2><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
-    else if (m <= 16)
-        ht_kernel<4><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
-    else
+    int nchunk;
+    double* part;
+    if (m <= 16) {
+        nchunk = (int)cdiv(N, CR_ROWS);
+        part = (double*)ws.get("ht_part", (size_t)nchunk * L * m * sizeof(double));
+        dim3 grid((unsigned)cdiv(L, SB), (unsigned)nchunk);
+        if (m <= 2)
+            cols_dot_kernel<2><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
+        else if (m <= 4)
+            cols_dot_kernel<4><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
+        else if (m <= 8)
+            cols_dot_kernel<8><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
+        else
+            cols_dot_kernel<16><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
+    } else {
+        nchunk = (int)cdiv(N, HT_ROWS);
+        part = (double*)ws.get("ht_part", (size_t)nchunk * L * m * sizeof(double));
+        dim3 grid((unsigned)cdiv(L, CT), (unsigned)nchunk);
         ht_kernel<16><<<grid, NT, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
+    }
     ELM_LAUNCH_CHECK();
     ht_reduce_kernel<<<nred, NT, 0, s>>>(L, mi, nchunk, part, G, ldg, sq);
     ELM_LAUNCH_CHECK();
