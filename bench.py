@@ -111,8 +111,8 @@ def traffic_from_profiles(kernel_src):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the N-sharded design is described in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the path has no multi-GPU execution "
+              "(it would shard over samples with one Gram all-reduce). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -230,7 +230,7 @@ def main():
         "refine_iterations": info_lp["iterations"],
         "gram_tflops": round(gram_tflops, 2) if gram_tflops else None,
         "roofline": {
-            "kernel": "gram_lp_kernel" if args.precision != "fp32" else "gram16_kernel<float>",
+            "kernel": "gram_lp256_kernel" if args.precision != "fp32" else "gram16_kernel<float>",
             "bound": "mfma",
             "achieved": round(gram_tflops, 2) if gram_tflops else None,
             "peak": PEAK_BF16_TFLOPS if args.precision != "fp32" else 157.3,
