@@ -228,6 +228,11 @@ def main():
         "rank": rank_lp,
         "ne_residual": info_lp["ne_residual"],
         "refine_iterations": info_lp["iterations"],
+        "ne_history": info_lp["ne_history"],
+        "gram_dtype_used": info_lp["gram_dtype"],
+        "precision_escalations": info_lp["escalations"],
+        "rank_decision": {k: info_lp["factor"][k] for k in
+                          ("max_diag", "last_pivot", "first_rejected", "tau", "noise_floor", "reliable")},
         "gram_tflops": round(gram_tflops, 2) if gram_tflops else None,
         "roofline": {
             "kernel": "gram_lp256_kernel" if args.precision != "fp32" else "gram16_kernel<float>",

@@ -162,6 +162,33 @@ elm_status elm_factor_rank(const elm_factor* f, int64_t* rank);
  * Synchronises the handle's stream. */
 elm_status elm_factor_pivots(elm_handle* h, const elm_factor* f, int32_t* piv_host);
 
+/* Diagnostics of the rank decision (host struct, filled by
+ * elm_factor_get_info; no synchronisation).  Accepted pivots of the greedy
+ * pivoted Cholesky are non-increasing, so the last one is the smallest.
+ * noise_floor estimates the rounding noise of the Schur diagonals of the Gram
+ * actually factored: a column that is an exact combination of others keeps,
+ * after rounding H to unit roundoff u, a Schur diagonal near u^2/3 times the
+ * largest diagonal, and FP32 accumulation over kc products adds about
+ * sqrt(kc) 2^-24 per Gram entry.  `reliable` is 1 when the decision clears
+ * that noise: last_pivot >= 2 noise_floor (r > 0) and first_rejected >=
+ * -2 noise_floor (r < n).  A 0 means that the rank found on a low-precision
+ * Gram may differ from the FP64 one: the caller should factor a
+ * higher-precision Gram (elm_train does so by itself). */
+typedef struct {
+    int64_t rank;          /* r */
+    int64_t n;             /* order of the Gram, min(N, L) */
+    int32_t transposed;    /* 1: Gram H H^T (N < L) */
+    int32_t gram_dtype;    /* elm_dtype of the operand the Gram was formed from */
+    double max_diag;       /* largest Gram diagonal (the first pivot) */
+    double last_pivot;     /* smallest accepted pivot; +inf if r = 0 */
+    double first_rejected; /* largest remaining Schur diagonal at the stop; -inf if r = n */
+    double tau;            /* absolute stopping threshold */
+    double noise_floor;    /* absolute noise scale of the Schur diagonals */
+    int32_t reliable;      /* see above */
+} elm_factor_info;
+
+elm_status elm_factor_get_info(const elm_factor* f, elm_factor_info* out);
+
 /* Free a factor.  NULL is accepted. */
 elm_status elm_factor_destroy(elm_factor* f);
 
@@ -179,8 +206,9 @@ elm_status elm_factor_destroy(elm_factor* f);
  * beta_0 = H^+ T through the factor; then, while the relative normal-equation
  * residual ||H^T (T - H beta)||_F / ||H^T T||_F exceeds ir_tol and fewer
  * than ir_max_iter corrections were made, beta += H^+ (T - H beta) with H^+
- * applied through the (possibly low-precision-derived) factor.  ir_max_iter
- * = 0 gives beta_0 and skips the residual.  ir_tol must be in [0, 1).
+ * applied through the (possibly low-precision-derived) factor; the loop also
+ * stops when a correction did not lower the residual.  ir_max_iter = 0 gives
+ * beta_0 and skips the residual.  ir_tol must be in [0, 1).
  * info (host, may be NULL) receives rank, iterations and residuals.
  * Synchronises once per refinement iteration.
  * Errors: NO_CONVERGENCE if ir_max_iter > 0 and the final residual is above
@@ -190,6 +218,75 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m,
                           const double* H64, int64_t ldh64,
                           double ir_tol, int32_t ir_max_iter,
                           double* beta, int64_t ldbeta, elm_solve_info* info);
+
+/* ------------------------------------------------------------------------ */
+/* The whole training (steps 2-9) with the precision policy.                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    elm_solve_info solve;    /* of the solve that produced beta */
+    elm_factor_info factor;  /* of the factor that produced beta */
+    int32_t gram_dtype;      /* elm_dtype of the Gram that produced beta */
+    int32_t escalations;     /* precision steps taken after a failed guard (0-2) */
+    int32_t guard;           /* last failed guard: 0 none, 1 rank decision within the
+                                Gram's noise (elm_factor_info.reliable = 0), 2 the
+                                refinement did not reach ir_tol */
+} elm_train_info;
+
+/* beta = H^+ T for H = sigma(X W + b) (Section 2.1; algorithm steps 2-9):
+ * elm_hidden -> elm_rank_factor -> elm_pinv_solve in one call.
+ *
+ * X (N x d), W (d x L), b (L), T (N x m): FP64, leading dimensions >= row
+ * lengths.  H64: caller buffer N x L FP64 (ld ldh64 >= L), receives H.
+ * gram_dt selects the form: ELM_F64 factors the FP64 Gram of H64 (plain form);
+ * ELM_F32 / ELM_BF16 / ELM_F16 factor the Gram of a node-major copy of H
+ * rounded to that type (precision form), written to Hlp (L x N, ld ldlp >= N,
+ * of type gram_dt) or, when Hlp is NULL, to library workspace.  When N < L the
+ * FP64 form is used whatever gram_dt says (the low-precision Gram needs N >= L).
+ * Precision policy: if the rank decision on a low-precision Gram is within its
+ * rounding noise (elm_factor_info.reliable = 0) or the refinement does not
+ * reach ir_tol, the Gram is formed again one step up (16-bit -> FP32 -> FP64)
+ * and the factor and solve are redone; info reports the steps taken.
+ * tau_rel, ir_tol, ir_max_iter as for elm_rank_factor / elm_pinv_solve.
+ * factor_out (may be NULL) receives the final factor (caller frees it).
+ * Errors: as the three calls; NO_CONVERGENCE only when the FP64 form does not
+ * reach ir_tol (beta then holds the last iterate). */
+elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m,
+                     const double* X, int64_t ldx, const double* W, int64_t ldw,
+                     const double* b, const double* T, int64_t ldt,
+                     elm_dtype gram_dt, double* H64, int64_t ldh64,
+                     void* Hlp, int64_t ldlp,
+                     double tau_rel, double ir_tol, int32_t ir_max_iter,
+                     double* beta, int64_t ldbeta, elm_train_info* info,
+                     elm_factor** factor_out);
+
+/* One independent training of a batch (all pointers device pointers, FP64,
+ * with the shapes and leading dimensions of elm_train). */
+typedef struct {
+    int64_t N, d, L, m;
+    const double* X; int64_t ldx;
+    const double* W; int64_t ldw;
+    const double* b;
+    const double* T; int64_t ldt;
+    double* H64; int64_t ldh64;   /* caller buffer N x L, receives H */
+    double* beta; int64_t ldbeta; /* caller buffer L x m, receives beta */
+} elm_problem;
+
+/* elm_train on each of `count` independent problems (e.g. a sweep over
+ * hidden-layer sizes or seeds), with one precision form and tolerances for
+ * all.  The trainings run concurrently on worker streams owned by the handle
+ * (created on first use), assigned longest-first by the Gram's cost; they
+ * start after the work already queued on the handle's stream, and that stream
+ * continues only after all of them.  The call returns when every training has
+ * finished.  infos and statuses (host arrays of `count`, may be NULL) receive
+ * each training's report and status; the return value is ELM_OK or the status
+ * of the first failed problem (by index), whose message elm_last_error gives.
+ * Errors: INVALID_ARG / SHAPE for a malformed problem (nothing runs); those of
+ * elm_train per problem. */
+elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* probs,
+                             elm_dtype gram_dt, double tau_rel, double ir_tol,
+                             int32_t ir_max_iter, elm_train_info* infos,
+                             elm_status* statuses);
 
 /* ------------------------------------------------------------------------ */
 /* Step 3 of the three-step ELM: prediction Y = H beta, label = argmax.      */

@@ -3,6 +3,9 @@
 // All device work is in the kernels of the other translation units.
 #include "elm_internal.h"
 
+#include <algorithm>
+#include <thread>
+
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -184,8 +187,11 @@ elm_status elm_destroy(elm_handle* h) {
     if (!h) return ELM_OK;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
+    for (elm_handle* w : h->workers) elm_destroy(w);
+    h->workers.clear();
     h->prof.release();
     h->ws.release();
+    if (h->owns_stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return ELM_OK;
 }
@@ -267,14 +273,16 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, i
         f->transposed = transposed;
         f->device = h->device;
         double* M = (double*)h->ws.get("gram_M", (size_t)n * n * sizeof(double));
+        int64_t kc = 0;  // products accumulated in FP32 per partial (low-precision Grams)
         if (h_dt == ELM_F64) {
             if (transposed)
                 elm::launch_gram_f64_rows(h->stream, N, L, (const double*)H, ldh, M, n, h->ws);
             else
                 elm::launch_gram_f64_cols(h->stream, N, L, (const double*)H, ldh, M, n, h->ws);
         } else {
-            elm::launch_gram_lp_nodes(h->stream, h_dt, N, L, H, ldh, M, n, h->ws);
+            kc = elm::launch_gram_lp_nodes(h->stream, h_dt, N, L, H, ldh, M, n, h->ws);
         }
+        f->gram_dtype = h_dt;
         // tau from the largest diagonal entry (read back once)
         double* dmax = (double*)h->ws.get("gram_dmax", sizeof(double));
         elm::launch_diag_max(h->stream, n, M, n, dmax);
@@ -284,10 +292,17 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, i
         if (!std::isfinite(hdmax)) throw Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
         f->tau = (tau_rel > 0 ? tau_rel : (double)n * std::ldexp(1.0, -53)) * hdmax;
         ELM_HIP_TRY(hipMalloc(&f->piv, (size_t)n * sizeof(int32_t)));
+        double pst[3];
         {
             elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
-            f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, h->ws);
+            f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, pst, h->ws);
         }
+        f->last_pivot = pst[0];
+        f->first_rejected = pst[1];
+        f->max_diag = hdmax;
+        f->noise_floor = elm::schur_noise_floor(h_dt, n, N > L ? N : L, kc) * hdmax;
+        f->reliable = (f->r == 0 || f->last_pivot >= 2.0 * f->noise_floor) &&
+                      (f->r == n || f->first_rejected >= -2.0 * f->noise_floor);
         {
             elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
             elm::build_factor_tail(h->stream, f, h->ws);
@@ -337,6 +352,21 @@ elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t 
 elm_status elm_factor_rank(const elm_factor* f, int64_t* rank) {
     if (!f || !rank) return ELM_ERR_INVALID_ARG;
     *rank = f->r;
+    return ELM_OK;
+}
+
+elm_status elm_factor_get_info(const elm_factor* f, elm_factor_info* out) {
+    if (!f || !out) return ELM_ERR_INVALID_ARG;
+    out->rank = f->r;
+    out->n = f->n;
+    out->transposed = f->transposed ? 1 : 0;
+    out->gram_dtype = (int32_t)f->gram_dtype;
+    out->max_diag = f->max_diag;
+    out->last_pivot = f->last_pivot;
+    out->first_rejected = f->first_rejected;
+    out->tau = f->tau;
+    out->noise_floor = f->noise_floor;
+    out->reliable = f->reliable ? 1 : 0;
     return ELM_OK;
 }
 
@@ -415,7 +445,7 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
         double* E = (double*)ws.get("ps_E", (size_t)N * m * sizeof(double));
         double* G = (double*)ws.get("ps_G", (size_t)L * m * sizeof(double));
         double* D = (double*)ws.get("ps_D", (size_t)L * m * sizeof(double));
-        double res = 0;
+        double res = 0, prev = 0;
         int it = 0;
         for (;;) {
             // G = H^T (T - H beta): two streaming passes over H
@@ -433,6 +463,8 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
             res = z2 > 0 ? std::sqrt(g2 / z2) : std::sqrt(g2);
             if (info && it < 32) info->ne_history[it] = res;
             if (!(res > ir_tol) || it >= ir_max_iter) break;
+            if (it >= 1 && !(res < prev)) break;  // the last correction made no progress
+            prev = res;
             {
                 elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
                 if (!f->transposed)
@@ -453,6 +485,201 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
     if (result != ELM_OK) h->last_error = "refinement stopped above ir_tol";
     return result;
 }
+
+}  // extern "C"
+
+namespace elm {
+namespace {
+
+// Precision ladder of the precision form: after a failed guard the Gram is
+// formed again one step up (16-bit -> FP32 -> FP64).
+elm_dtype next_gram_dtype(elm_dtype dt) { return dt == ELM_F32 ? ELM_F64 : ELM_F32; }
+
+void check_status(elm_handle* h, elm_status st) {
+    if (st != ELM_OK) throw Error{st, h->last_error};
+}
+
+}  // namespace
+}  // namespace elm
+
+extern "C" {
+
+elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, const double* X,
+                     int64_t ldx, const double* W, int64_t ldw, const double* b, const double* T,
+                     int64_t ldt, elm_dtype gram_dt, double* H64, int64_t ldh64, void* Hlp,
+                     int64_t ldlp, double tau_rel, double ir_tol, int32_t ir_max_iter, double* beta,
+                     int64_t ldbeta, elm_train_info* info, elm_factor** factor_out) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    elm_factor* f = nullptr;
+    elm_status st = elm::guarded(h, [&] {
+        REQUIRE(N >= 1 && d >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N, d and L must be >= 1");
+        REQUIRE(m >= 1 && m <= 64, ELM_ERR_INVALID_ARG, "m must be in [1, 64]");
+        REQUIRE(X && W && b && T && H64 && beta, ELM_ERR_INVALID_ARG,
+                "X, W, b, T, H64 and beta must be non-null");
+        REQUIRE(gram_dt == ELM_F64 || gram_dt == ELM_F32 || gram_dt == ELM_BF16 || gram_dt == ELM_F16,
+                ELM_ERR_INVALID_ARG, "unknown gram dtype");
+        REQUIRE(ldx >= d && ldw >= L && ldt >= m && ldh64 >= L && ldbeta >= m, ELM_ERR_SHAPE,
+                "a leading dimension is smaller than its row length");
+        REQUIRE(!Hlp || ldlp >= N, ELM_ERR_SHAPE, "ldlp < N");
+        REQUIRE(ir_tol >= 0.0 && ir_tol < 1.0, ELM_ERR_INVALID_ARG, "ir_tol must be in [0, 1)");
+        REQUIRE(ir_max_iter >= 0 && ir_max_iter <= 31, ELM_ERR_INVALID_ARG,
+                "ir_max_iter must be in [0, 31]");
+        if (factor_out) *factor_out = nullptr;
+        elm::use_device(h);
+        elm_train_info ti;
+        std::memset(&ti, 0, sizeof(ti));
+        // the low-precision Gram is formed from a node-major copy, N >= L only
+        elm_dtype gdt = N < L ? ELM_F64 : gram_dt;
+        const bool own_lp = gdt != ELM_F64 && !Hlp;
+        void* lp = Hlp;
+        int64_t ldl = ldlp;
+        if (own_lp) {
+            lp = h->ws.get("train_lp", (size_t)L * N * elm::dtype_size(gdt));
+            ldl = N;
+        }
+        elm::check_status(h, elm_hidden(h, N, d, L, X, ldx, W, ldw, b, ELM_F64, H64, ldh64,
+                                        gdt == ELM_F64 ? nullptr : lp, ldl, gdt));
+        for (;;) {
+            int64_t r = 0;
+            if (gdt == ELM_F64)
+                elm::check_status(h, elm_rank_factor(h, N, L, H64, ldh64, ELM_F64, ELM_SAMPLE_MAJOR,
+                                                     tau_rel, &f, &r));
+            else
+                elm::check_status(h, elm_rank_factor(h, N, L, lp, ldl, gdt, ELM_NODE_MAJOR, tau_rel,
+                                                     &f, &r));
+            elm::check_status(h, elm_factor_get_info(f, &ti.factor));
+            ti.gram_dtype = gdt;
+            const bool can_escalate = gdt != ELM_F64;
+            if (can_escalate && !f->reliable) {
+                ti.guard = 1;
+            } else {
+                const elm_status ss = elm_pinv_solve(h, f, m, T, ldt, H64, ldh64, ir_tol, ir_max_iter,
+                                                     beta, ldbeta, &ti.solve);
+                if (ss == ELM_OK) break;
+                if (ss != ELM_ERR_NO_CONVERGENCE || !can_escalate) {
+                    if (info) *info = ti;
+                    elm::check_status(h, ss);
+                }
+                ti.guard = 2;
+            }
+            // a guard failed: factor a higher-precision Gram of the same H
+            elm::free_factor_buffers(f);
+            delete f;
+            f = nullptr;
+            ++ti.escalations;
+            gdt = elm::next_gram_dtype(gdt);
+            if (gdt == ELM_F32) {
+                void* lp32 = h->ws.get("train_lp32", (size_t)L * N * sizeof(float));
+                elm::check_status(h, elm_hidden(h, N, d, L, X, ldx, W, ldw, b, ELM_F64, nullptr, 0,
+                                                lp32, N, ELM_F32));
+                lp = lp32;
+                ldl = N;
+            }
+        }
+        if (info) *info = ti;
+        if (factor_out) {
+            *factor_out = f;
+            f = nullptr;
+        }
+    });
+    if (f) {
+        elm::free_factor_buffers(f);
+        delete f;
+    }
+    return st;
+}
+
+elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* probs,
+                             elm_dtype gram_dt, double tau_rel, double ir_tol, int32_t ir_max_iter,
+                             elm_train_info* infos, elm_status* statuses) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    std::vector<elm_status> st_all;
+    std::vector<std::string> msg_all;
+    elm_status st = elm::guarded(h, [&] {
+        REQUIRE(count >= 0, ELM_ERR_INVALID_ARG, "count must be >= 0");
+        REQUIRE(count == 0 || probs, ELM_ERR_INVALID_ARG, "probs must be non-null");
+        REQUIRE(gram_dt == ELM_F64 || gram_dt == ELM_F32 || gram_dt == ELM_BF16 || gram_dt == ELM_F16,
+                ELM_ERR_INVALID_ARG, "unknown gram dtype");
+        for (int32_t e = 0; e < count; ++e) {
+            const elm_problem& p = probs[e];
+            const std::string at = "problem " + std::to_string(e) + ": ";
+            REQUIRE(p.N >= 1 && p.d >= 1 && p.L >= 1 && p.m >= 1 && p.m <= 64, ELM_ERR_INVALID_ARG,
+                    at + "N, d, L must be >= 1 and m in [1, 64]");
+            REQUIRE(p.X && p.W && p.b && p.T && p.H64 && p.beta, ELM_ERR_INVALID_ARG,
+                    at + "a pointer is null");
+            REQUIRE(p.ldx >= p.d && p.ldw >= p.L && p.ldt >= p.m && p.ldh64 >= p.L && p.ldbeta >= p.m,
+                    ELM_ERR_SHAPE, at + "a leading dimension is smaller than its row length");
+        }
+        if (count == 0) return;
+        elm::use_device(h);
+        const int nw = count < elm::BATCH_WORKERS ? count : elm::BATCH_WORKERS;
+        while ((int)h->workers.size() < nw) {
+            hipStream_t ws_stream = nullptr;
+            ELM_HIP_TRY(hipStreamCreateWithFlags(&ws_stream, hipStreamNonBlocking));
+            elm_handle* w = nullptr;
+            if (elm_create(&w, ws_stream) != ELM_OK) {
+                (void)hipStreamDestroy(ws_stream);
+                throw elm::Error{ELM_ERR_HIP, "cannot create a worker handle"};
+            }
+            w->owns_stream = true;
+            h->workers.push_back(w);
+        }
+        // the workers start after the work already queued on the caller's stream
+        hipEvent_t ev = nullptr;
+        ELM_HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        ELM_HIP_TRY(hipEventRecord(ev, h->stream));
+        for (int w = 0; w < nw; ++w) ELM_HIP_TRY(hipStreamWaitEvent(h->workers[w]->stream, ev, 0));
+        // longest-processing-time assignment by the Gram's cost N n min(N, L)
+        std::vector<int32_t> order(count);
+        for (int32_t e = 0; e < count; ++e) order[e] = e;
+        auto cost = [&](int32_t e) {
+            const double n = (double)std::min(probs[e].N, probs[e].L);
+            return (double)std::max(probs[e].N, probs[e].L) * n * n + 2.0e5 * n;
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+        std::vector<std::vector<int32_t>> lists(nw);
+        std::vector<double> load(nw, 0.0);
+        for (int32_t e : order) {
+            const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            lists[w].push_back(e);
+            load[w] += cost(e);
+        }
+        st_all.assign(count, ELM_OK);
+        msg_all.assign(count, std::string());
+        std::vector<elm_train_info> info_all(count);
+        std::vector<std::thread> threads;
+        for (int w = 0; w < nw; ++w) {
+            threads.emplace_back([&, w] {
+                elm_handle* wh = h->workers[w];
+                for (int32_t e : lists[w]) {
+                    const elm_problem& p = probs[e];
+                    std::memset(&info_all[e], 0, sizeof(elm_train_info));
+                    st_all[e] = elm_train(wh, p.N, p.d, p.L, p.m, p.X, p.ldx, p.W, p.ldw, p.b, p.T, p.ldt,
+                                          gram_dt, p.H64, p.ldh64, nullptr, 0, tau_rel, ir_tol,
+                                          ir_max_iter, p.beta, p.ldbeta, &info_all[e], nullptr);
+                    if (st_all[e] != ELM_OK) msg_all[e] = wh->last_error;
+                }
+            });
+        }
+        for (auto& t : threads) t.join();
+        // the caller's stream continues after the workers
+        for (int w = 0; w < nw; ++w) {
+            ELM_HIP_TRY(hipEventRecord(ev, h->workers[w]->stream));
+            ELM_HIP_TRY(hipStreamWaitEvent(h->stream, ev, 0));
+        }
+        ELM_HIP_TRY(hipEventDestroy(ev));
+        if (infos) std::memcpy(infos, info_all.data(), (size_t)count * sizeof(elm_train_info));
+        if (statuses) std::memcpy(statuses, st_all.data(), (size_t)count * sizeof(elm_status));
+        for (int32_t e = 0; e < count; ++e)
+            if (st_all[e] != ELM_OK)
+                throw elm::Error{st_all[e], "problem " + std::to_string(e) + ": " + msg_all[e]};
+    });
+    return st;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 elm_status elm_predict(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, const void* X,
                        int64_t ldx, const void* W, int64_t ldw, const void* b, elm_dtype dt,

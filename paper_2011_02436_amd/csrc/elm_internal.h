@@ -5,6 +5,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -105,6 +106,12 @@ struct Workspace {
 
 }  // namespace elm
 
+namespace elm {
+// Independent trainings run concurrently on this many streams (the HIP
+// runtime's default number of hardware queues per process).
+constexpr int BATCH_WORKERS = 4;
+}  // namespace elm
+
 struct elm_handle {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -112,6 +119,10 @@ struct elm_handle {
     elm::Workspace ws;
     elm::Profiler prof;
     std::string last_error;
+    // batched training: worker handles, each on a stream of its own (created
+    // on first use, kept for reuse of their workspaces)
+    std::vector<elm_handle*> workers;
+    bool owns_stream = false;
 };
 
 struct elm_factor {
@@ -120,6 +131,11 @@ struct elm_factor {
     int64_t r = 0;            // rank
     bool transposed = false;  // the Gram is H H^T (N < L)
     double tau = 0;           // absolute stopping threshold of the pivoted Cholesky
+    // rank-decision diagnostics (host copies)
+    elm_dtype gram_dtype = ELM_F64;  // element type the Gram was formed from
+    double max_diag = 0, last_pivot = 0, first_rejected = 0;
+    double noise_floor = 0;   // absolute rounding-noise scale of the Schur diagonals
+    bool reliable = true;
     // device buffers owned by the factor (hipMalloc'd)
     int32_t* piv = nullptr;   // n: original index at each pivoted position
     double* R = nullptr;      // r x n, pivot order, ld n: [R11 R12]
@@ -153,18 +169,40 @@ void launch_gram_f64_cols(hipStream_t s, int64_t N, int64_t L, const double* H, 
 //   row Gram     M = H H^T  of sample-major FP64 H (N x L, N < L)
 void launch_gram_f64_rows(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
                           double* M, int64_t ldm, Workspace& ws);
-//   column Gram of a node-major low-precision copy (L x N): M = Hn Hn^T
-void launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
-                          int64_t ldn, double* M, int64_t ldm, Workspace& ws);
+//   column Gram of a node-major low-precision copy (L x N): M = Hn Hn^T.
+//   Returns the longest run of products accumulated in FP32 before the FP64
+//   sum of the partial Grams.
+int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
+                             int64_t ldn, double* M, int64_t ldm, Workspace& ws);
 //   *out = max_i M[i][i]  (NaN if any diagonal entry is NaN)
 void launch_diag_max(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
 
 // pchol.hip: greedy pivoted Cholesky of M (n x n FP64, full symmetric, ld = ldm).
 // Writes piv (n), allocates *R_out = R (r x n in pivot order, ld n, hipMalloc'd,
-// NULL when r = 0) and returns r (synchronises the stream once).
+// NULL when r = 0) and returns r (synchronises the stream once).  stats_out
+// (host, 3 doubles): last accepted pivot (+inf if r = 0), largest Schur
+// diagonal at the stop (-inf if r = n), largest Gram diagonal.
 int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double tau,
-                         int32_t* piv, double** R_out, Workspace& ws);
+                         int32_t* piv, double** R_out, double* stats_out, Workspace& ws);
 void launch_fill(hipStream_t s, double* p, int64_t count, double v);
+
+// Relative rounding-noise scale of the Schur diagonals of a Gram formed from
+// H rounded to `dt` with `kc` products per FP32 partial sum (kc = 0: FP64
+// accumulation), for a Gram of order n over K samples.  A column that is an
+// exact combination of others in FP64 but not after rounding keeps a residual
+// of about u/sqrt(3) of its norm (u the unit roundoff of dt), i.e. a Schur
+// diagonal of u^2/3 of the largest diagonal; FP32 accumulation adds about
+// sqrt(kc) 2^-24 per Gram entry.
+inline double schur_noise_floor(elm_dtype dt, int64_t n, int64_t K, int64_t kc) {
+    const double u = dt == ELM_BF16 ? std::ldexp(1.0, -8)
+                   : dt == ELM_F16  ? std::ldexp(1.0, -11)
+                   : dt == ELM_F32  ? std::ldexp(1.0, -24)
+                                    : std::ldexp(1.0, -53);
+    const double acc = kc > 0 ? std::sqrt((double)kc) * std::ldexp(1.0, -24)
+                              : std::sqrt((double)K) * std::ldexp(1.0, -53);
+    const double fp64 = (double)n * std::ldexp(1.0, -53);
+    return u * u / 3.0 + acc + fp64;
+}
 
 // solve.hip: dense FP64 helpers for the factor and the pseudoinverse apply
 void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws);

@@ -1,66 +1,116 @@
-// General FP64 matrix product on the 16x16x4 FP64 MFMA, for the small dense
-// steps after the rank reveal: K = R11^-1 R12, the Gram I + K K^T of G, the
-// block triangular inverse and the applications of (F^T F)^-1 and
-// (G G^T)^-1.  Operands are strided views, so transposes cost nothing:
+// General FP64 matrix product on the 16x16x4 FP64 MFMA, for the dense steps
+// after the rank reveal: the block triangular inverse of R11, K = R11^-1 R12
+// and the Gram I + K K^T of G.  Operands are strided views, so transposes
+// cost nothing:
 //   C[i][j] = alpha * sum_k A(i, k) B(k, j) + beta * C[i][j],
 //   A(i, k) = A[i * a_rs + k * a_cs],  B(k, j) = B[k * b_rs + j * b_cs].
+// A triangular operand can be declared so that tiles skip its zero half:
+//   tri_a: A is upper triangular (A(i, k) = 0 for k < i);
+//   tri_b: B is upper triangular (B(k, j) = 0 for k > j).
+// The skipped products are exact zeros, so the result is the same.
+// A batch of equally shaped products (blockIdx.z) shares one launch.
 #include "elm_internal.h"
 
 namespace elm {
 namespace {
 
-constexpr int T = 64;   // output tile
 constexpr int BK = 16;
 constexpr int NT = 256;
 
-__global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
-                                                  const double* __restrict__ A, int64_t a_rs,
-                                                  int64_t a_cs, const double* __restrict__ B,
-                                                  int64_t b_rs, int64_t b_cs, double beta,
-                                                  double* __restrict__ C, int64_t ldc) {
-    __shared__ double As[BK][T + 1];
-    __shared__ double Bs[BK][T + 1];
-    const int64_t i0 = (int64_t)blockIdx.x * T, j0 = (int64_t)blockIdx.y * T;
+// TS x TS output tile, 4 waves in 2 x 2, each (TS/2) x (TS/2) as blocks of
+// 16 x 16; k-major LDS tiles, double-buffered through registers.
+template <int TS>
+__global__ __launch_bounds__(NT, 2) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                     const double* __restrict__ A, int64_t a_rs,
+                                                     int64_t a_cs, int64_t a_bs,
+                                                     const double* __restrict__ B, int64_t b_rs,
+                                                     int64_t b_cs, int64_t b_bs, double beta,
+                                                     double* __restrict__ C, int64_t ldc,
+                                                     int64_t c_bs, int tri_a, int tri_b) {
+    constexpr int P = TS + 16;          // LDS pitch (see the hidden-layer kernel)
+    constexpr int EPT = TS * BK / NT;   // elements per thread per operand tile
+    constexpr int WB = TS / 32;         // 16 x 16 blocks per wave and dimension
+    __shared__ double As[2][BK][P];
+    __shared__ double Bs[2][BK][P];
+    const int64_t i0 = (int64_t)blockIdx.x * TS, j0 = (int64_t)blockIdx.y * TS;
+    A += (int64_t)blockIdx.z * a_bs;
+    B += (int64_t)blockIdx.z * b_bs;
+    C += (int64_t)blockIdx.z * c_bs;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const bool a_icontig = (a_rs == 1);
+    const bool a_kcontig = (a_cs == 1);
     const bool b_jcontig = (b_cs == 1);
 
-    d4v acc[2][2];
-    for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y) acc[x][y] = d4v{};
+    // k range of this tile: triangular operands have zero blocks
+    int64_t k_lo = 0, k_hi = K;
+    if (tri_a) k_lo = (i0 / BK) * BK;
+    if (tri_b) k_hi = (j0 + TS < K) ? j0 + TS : K;
 
-    for (int64_t k0 = 0; k0 < K; k0 += BK) {
+    // thread -> EPT consecutive elements along the operand's contiguous
+    // dimension: (row, k + e) for a k-contiguous A, (row + e, k) otherwise
+    const int ta = tid * EPT;
+    const int a_i = a_kcontig ? ta / BK : ta % TS, a_k = a_kcontig ? ta % BK : ta / TS;
+    const int b_j = b_jcontig ? ta % TS : ta / BK, b_k = b_jcontig ? ta / TS : ta % BK;
+    const int a_di = a_kcontig ? 0 : 1, a_dk = a_kcontig ? 1 : 0;
+    const int b_dj = b_jcontig ? 1 : 0, b_dk = b_jcontig ? 0 : 1;
+    double av[EPT], bv[EPT];
+    auto load = [&](int64_t k0) {
 #pragma unroll
-        for (int it = 0; it < (BK * T) / NT; ++it) {
-            const int e = tid + it * NT;
-            int i, k;
-            if (a_icontig) { k = e / T; i = e % T; } else { i = e / BK; k = e % BK; }
-            const int64_t gi = i0 + i, gk = k0 + k;
-            As[k][i] = (gi < M && gk < K) ? A[gi * a_rs + gk * a_cs] : 0.0;
-            int j, kb;
-            if (b_jcontig) { kb = e / T; j = e % T; } else { j = e / BK; kb = e % BK; }
-            const int64_t gj = j0 + j, gkb = k0 + kb;
-            Bs[kb][j] = (gj < N && gkb < K) ? B[gkb * b_rs + gj * b_cs] : 0.0;
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t gi = i0 + a_i + e * a_di, gk = k0 + a_k + e * a_dk;
+            av[e] = (gi < M && gk < k_hi) ? A[gi * a_rs + gk * a_cs] : 0.0;
+            const int64_t gj = j0 + b_j + e * b_dj, gkb = k0 + b_k + e * b_dk;
+            bv[e] = (gj < N && gkb < k_hi) ? B[gkb * b_rs + gj * b_cs] : 0.0;
         }
-        __syncthreads();
+    };
+    auto store = [&](int buf) {
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            const int k = kk + (lane >> 4);
-            const double a0 = As[k][wm * 32 + (lane & 15)], a1 = As[k][wm * 32 + 16 + (lane & 15)];
-            const double b0 = Bs[k][wn * 32 + (lane & 15)], b1 = Bs[k][wn * 32 + 16 + (lane & 15)];
-            acc[0][0] = Mfma16<double>::op(a0, b0, acc[0][0]);
-            acc[0][1] = Mfma16<double>::op(a0, b1, acc[0][1]);
-            acc[1][0] = Mfma16<double>::op(a1, b0, acc[1][0]);
-            acc[1][1] = Mfma16<double>::op(a1, b1, acc[1][1]);
+        for (int e = 0; e < EPT; ++e) {
+            As[buf][a_k + e * a_dk][a_i + e * a_di] = av[e];
+            Bs[buf][b_k + e * b_dk][b_j + e * b_dj] = bv[e];
         }
+    };
+
+    d4v acc[WB][WB];
+#pragma unroll
+    for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y) acc[x][y] = d4v{};
+
+    if (k_lo < k_hi) {
+        load(k_lo);
+        store(0);
         __syncthreads();
+        int buf = 0;
+        for (int64_t k0 = k_lo; k0 < k_hi; k0 += BK) {
+            const bool more = k0 + BK < k_hi;
+            if (more) load(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                const int k = kk + (lane >> 4);
+                double a[WB], b[WB];
+#pragma unroll
+                for (int x = 0; x < WB; ++x) a[x] = As[buf][k][wm * (TS / 2) + x * 16 + (lane & 15)];
+#pragma unroll
+                for (int y = 0; y < WB; ++y) b[y] = Bs[buf][k][wn * (TS / 2) + y * 16 + (lane & 15)];
+#pragma unroll
+                for (int x = 0; x < WB; ++x)
+#pragma unroll
+                    for (int y = 0; y < WB; ++y) acc[x][y] = Mfma16<double>::op(a[x], b[y], acc[x][y]);
+            }
+            if (more) store(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
     }
-    for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y)
+#pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t gi = i0 + wm * 32 + x * 16 + Mfma16<double>::row(lane, v);
-                const int64_t gj = j0 + wn * 32 + y * 16 + (lane & 15);
+                const int64_t gi = i0 + wm * (TS / 2) + x * 16 + Mfma16<double>::row(lane, v);
+                const int64_t gj = j0 + wn * (TS / 2) + y * 16 + (lane & 15);
                 if (gi >= M || gj >= N) continue;
                 double c = alpha * acc[x][y][v];
                 if (beta != 0.0) c += beta * C[gi * ldc + gj];
@@ -70,13 +120,28 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t 
 
 }  // namespace
 
+void gemm_f64_batched(hipStream_t s, int64_t batch, int64_t M, int64_t N, int64_t K, double alpha,
+                      const double* A, int64_t a_rs, int64_t a_cs, int64_t a_bs, const double* B,
+                      int64_t b_rs, int64_t b_cs, int64_t b_bs, double beta, double* C, int64_t ldc,
+                      int64_t c_bs, bool tri_a, bool tri_b) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    if (M >= 128 && N >= 128) {
+        dim3 grid((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128), (unsigned)batch);
+        gemm_kernel<128><<<grid, NT, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs, b_bs,
+                                             beta, C, ldc, c_bs, tri_a, tri_b);
+    } else {
+        dim3 grid((unsigned)cdiv(M, 64), (unsigned)cdiv(N, 64), (unsigned)batch);
+        gemm_kernel<64><<<grid, NT, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs, b_bs,
+                                            beta, C, ldc, c_bs, tri_a, tri_b);
+    }
+    ELM_LAUNCH_CHECK();
+}
+
 void gemm_f64(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
               int64_t a_rs, int64_t a_cs, const double* B, int64_t b_rs, int64_t b_cs, double beta,
               double* C, int64_t ldc) {
-    if (M <= 0 || N <= 0) return;
-    dim3 grid((unsigned)cdiv(M, T), (unsigned)cdiv(N, T));
-    gemm_kernel<<<grid, NT, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, B, b_rs, b_cs, beta, C, ldc);
-    ELM_LAUNCH_CHECK();
+    gemm_f64_batched(s, 1, M, N, K, alpha, A, a_rs, a_cs, 0, B, b_rs, b_cs, 0, beta, C, ldc, 0, false,
+                     false);
 }
 
 }  // namespace elm

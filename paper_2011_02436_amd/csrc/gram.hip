@@ -234,9 +234,10 @@ void plan_chunks(int64_t ntile, int64_t K, int64_t quantum, int64_t& kc_len, int
     nchunk = (int)cdiv(K, kc_len);
 }
 
+// Returns the longest run of products accumulated in T before the FP64 sum.
 template <typename T, bool KCONTIG>
-void run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, double* M,
-                int64_t ldm, Workspace& ws) {
+int64_t run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, double* M,
+                   int64_t ldm, Workspace& ws) {
     const int64_t nt = cdiv(n, TILE);
     const int64_t ntile = nt * (nt + 1) / 2;
     int64_t kc_len;
@@ -252,6 +253,7 @@ void run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, dou
     StageScope sc(ws.prof, ELM_STAGE_GRAM_REDUCE, s);
     gram_reduce_kernel<T><<<(unsigned)ntile, NT, 0, s>>>(n, part, ntile, nchunk, M, ldm);
     ELM_LAUNCH_CHECK();
+    return kc_len;
 }
 
 
@@ -514,12 +516,9 @@ static int pick_splits(int64_t ntile, int64_t K) {
     return best;
 }
 
-void launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
-                          int64_t ldn, double* M, int64_t ldm, Workspace& ws) {
-    if (dt == ELM_F32) {
-        run_gram16<float, true>(s, L, N, (const float*)Hn, ldn, M, ldm, ws);
-        return;
-    }
+int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
+                             int64_t ldn, double* M, int64_t ldm, Workspace& ws) {
+    if (dt == ELM_F32) return run_gram16<float, true>(s, L, N, (const float*)Hn, ldn, M, ldm, ws);
     const int64_t nt = cdiv(L, GT);
     const int64_t ntile = nt * (nt + 1) / 2;
     const int nsplit = pick_splits(ntile, N);
@@ -546,6 +545,7 @@ void launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, con
     gram_reduce256_kernel<<<dim3((unsigned)ntile, GT * GT / NT), NT, 0, s>>>(L, part, ntile, nsplit_eff,
                                                                             M, ldm);
     ELM_LAUNCH_CHECK();
+    return kc_len;
 }
 
 }  // namespace elm

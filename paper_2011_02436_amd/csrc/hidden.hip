@@ -13,10 +13,13 @@
 namespace elm {
 namespace {
 
-constexpr int BM = 64;   // samples per tile
-constexpr int BN = 64;   // hidden nodes per tile
-constexpr int BK = 16;   // reduction chunk over input features
-constexpr int NT = 256;  // 4 waves, each a 32 x 32 sub-tile of 2 x 2 MFMA blocks
+constexpr int HT = 128;  // tile: 128 samples x 128 hidden nodes
+constexpr int HK = 16;   // reduction chunk over input features
+constexpr int NT = 256;  // 4 waves in 2 x 2, each a 64 x 64 sub-tile of 4 x 4 MFMA blocks
+constexpr int XCDS = 8;  // blocks are dealt round-robin to the 8 XCDs
+// LDS row pitch of the k-major operand tiles: 16 elements of padding put the
+// 4 k rows one MFMA operand read touches on disjoint halves of the banks
+constexpr int HP = HT + 16;
 
 __device__ inline double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 __device__ inline float sigmoid(float z) { return 1.0f / (1.0f + expf(-z)); }
@@ -41,83 +44,163 @@ __device__ inline uint16_t bf16_rne_bits(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// low-precision bits of one value (round to nearest even through round-to-odd)
 template <typename T>
-__device__ inline void store_lp(void* Hlp, elm_dtype lp, int64_t idx, T v) {
-    if (lp == ELM_BF16) {
-        ((uint16_t*)Hlp)[idx] = bf16_rne_bits(narrow_odd(v));
-    } else if (lp == ELM_F16) {
-        ((__half*)Hlp)[idx] = __float2half_rn(narrow_odd(v));
-    } else {  // ELM_F32
-        ((float*)Hlp)[idx] = (float)v;
-    }
+__device__ inline uint16_t lp16_bits(elm_dtype lp, T v) {
+    if (lp == ELM_BF16) return bf16_rne_bits(narrow_odd(v));
+    return __half_as_ushort(__float2half_rn(narrow_odd(v)));
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void hidden_kernel(int64_t N, int64_t d, int64_t L,
-                                                    const T* __restrict__ X, int64_t ldx,
-                                                    const T* __restrict__ W, int64_t ldw,
-                                                    const T* __restrict__ bias,
-                                                    T* __restrict__ H, int64_t ldh,
-                                                    void* __restrict__ Hlp, int64_t ldlp,
-                                                    elm_dtype lp_dt) {
-    __shared__ T Xs[BK][BM + 1];  // k-major so each MFMA A read is 16 consecutive samples
-    __shared__ T Ws[BK][BN + 1];
+struct HiddenSmem {
+    static constexpr int LOOP = 2 * 2 * HK * HP * (int)sizeof(T);  // [buf][X|W][k][i]
+    static constexpr int STAGE16 = HT * (HT + 8) * 2;                   // node-major 16-bit tile
+    static constexpr int STAGE32 = HT * (HT + 4) * 4;                   // node-major FP32 tile
+    static constexpr int BYTES = LOOP > STAGE32 ? LOOP : STAGE32;
+};
 
+// Tile (row_t, col_t) of block b: XCD x = b % 8 owns the column tiles
+// x, x + 8, ..., so its L2 keeps its strips of W (d x 128 each) for the whole
+// launch while the X row tiles stream past; within an XCD the column tiles of
+// one row tile are consecutive, so each X tile is read once per XCD.
+__device__ inline bool hidden_tile(int64_t nrow_t, int64_t ncol_t, int64_t& row_t, int64_t& col_t) {
+    const int64_t b = blockIdx.x;
+    const int x = (int)(b % XCDS);
+    const int64_t j = b / XCDS;
+    const int64_t ncx = (ncol_t - x + XCDS - 1) / XCDS;
+    if (ncx <= 0) return false;
+    row_t = j / ncx;
+    col_t = x + XCDS * (j % ncx);
+    return row_t < nrow_t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT, 2) void hidden_kernel(int64_t N, int64_t d, int64_t L,
+                                                       int64_t nrow_t, int64_t ncol_t,
+                                                       const T* __restrict__ X, int64_t ldx,
+                                                       const T* __restrict__ W, int64_t ldw,
+                                                       const T* __restrict__ bias,
+                                                       T* __restrict__ H, int64_t ldh,
+                                                       void* __restrict__ Hlp, int64_t ldlp,
+                                                       elm_dtype lp_dt) {
+    __shared__ __align__(16) unsigned char smem[HiddenSmem<T>::BYTES];
+    typedef T Tile[HK][HP];
+    Tile* Xs = (Tile*)smem;  // Xs[buf]: k-major, so an MFMA A read is 16 consecutive samples
+    Tile* Ws = Xs + 2;       // Ws[buf]
+
+    int64_t row_t, col_t;
+    if (!hidden_tile(nrow_t, ncol_t, row_t, col_t)) return;
+    const int64_t n0 = row_t * HT, j0 = col_t * HT;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int64_t n0 = (int64_t)blockIdx.x * BM;
-    const int64_t j0 = (int64_t)blockIdx.y * BN;
 
-    typename Mfma16<T>::acc_t acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 2; ++c) acc[a][c] = typename Mfma16<T>::acc_t{};
-
-    for (int64_t k0 = 0; k0 < d; k0 += BK) {
-        // X tile: BM x BK, k fastest across threads (contiguous in X)
-        for (int e = tid; e < BM * BK; e += NT) {
-            int i = e / BK, k = e % BK;
-            int64_t gi = n0 + i, gk = k0 + k;
-            Xs[k][i] = (gi < N && gk < d) ? X[gi * ldx + gk] : T(0);
-        }
-        // W tile: BK x BN, j fastest (contiguous in W)
-        for (int e = tid; e < BK * BN; e += NT) {
-            int k = e / BN, j = e % BN;
-            int64_t gk = k0 + k, gj = j0 + j;
-            Ws[k][j] = (gk < d && gj < L) ? W[gk * ldw + gj] : T(0);
-        }
-        __syncthreads();
+    // global -> register staging: 8 X values (one sample, 8 consecutive
+    // features) and 8 W values (one feature, 8 consecutive nodes) per thread
+    const int xr = tid >> 1, xk = (tid & 1) * 8;
+    const int wk = tid >> 4, wj = (tid & 15) * 8;
+    const int64_t gxr = n0 + xr;
+    T xv[8], wv[8];
+    auto load_chunk = [&](int64_t k0) {
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            const int k = kk + (lane >> 4);
-            T a0 = Xs[k][wm * 32 + (lane & 15)];
-            T a1 = Xs[k][wm * 32 + 16 + (lane & 15)];
-            T b0 = Ws[k][wn * 32 + (lane & 15)];
-            T b1 = Ws[k][wn * 32 + 16 + (lane & 15)];
-            acc[0][0] = Mfma16<T>::op(a0, b0, acc[0][0]);
-            acc[0][1] = Mfma16<T>::op(a0, b1, acc[0][1]);
-            acc[1][0] = Mfma16<T>::op(a1, b0, acc[1][0]);
-            acc[1][1] = Mfma16<T>::op(a1, b1, acc[1][1]);
+        for (int e = 0; e < 8; ++e) {
+            const int64_t k = k0 + xk + e;
+            xv[e] = (gxr < N && k < d) ? X[gxr * ldx + k] : T(0);
         }
+        const int64_t kw = k0 + wk;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t j = j0 + wj + e;
+            wv[e] = (kw < d && j < L) ? W[kw * ldw + j] : T(0);
+        }
+    };
+    auto store_chunk = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Xs[buf][xk + e][xr] = xv[e];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Ws[buf][wk][wj + e] = wv[e];
+    };
+
+    typename Mfma16<T>::acc_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = typename Mfma16<T>::acc_t{};
+
+    const int64_t nchunk = (d + HK - 1) / HK;
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+    for (int64_t c = 0; c < nchunk; ++c) {
+        const int buf = (int)(c & 1);
+        const bool more = c + 1 < nchunk;
+        if (more) load_chunk((c + 1) * HK);  // in flight during the MFMAs below
+#pragma unroll
+        for (int kk = 0; kk < HK; kk += 4) {
+            const int k = kk + (lane >> 4);
+            T a[4], bb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = Xs[buf][k][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bb[j] = Ws[buf][k][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = Mfma16<T>::op(a[i], bb[j], acc[i][j]);
+        }
+        if (more) store_chunk(buf ^ 1);
         __syncthreads();
     }
 
-    // epilogue: element (i, j) of each 16 x 16 block, see Mfma16<T>::row
+    // epilogue: bias, sigmoid, the sample-major store, and the low-precision
+    // values staged node-major in LDS (the loop buffers are free now)
+    const bool lp16 = Hlp && lp_dt != ELM_F32;
+    const bool lp32 = Hlp && lp_dt == ELM_F32;
+    uint16_t* st16 = (uint16_t*)smem;  // [node][HT + 8]
+    float* st32 = (float*)smem;        // [node][HT + 4]
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        const int64_t gj = j0 + wn * 32 + bj * 16 + (lane & 15);
-        if (gj >= L) continue;
-        const T bj_val = bias[gj];
+    for (int j = 0; j < 4; ++j) {
+        const int lj = wn * 64 + j * 16 + (lane & 15);
+        const int64_t gj = j0 + lj;
+        const T bj_val = gj < L ? bias[gj] : T(0);
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi) {
+        for (int i = 0; i < 4; ++i) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t gi = n0 + wm * 32 + bi * 16 + Mfma16<T>::row(lane, v);
-                if (gi >= N) continue;
-                const T h = sigmoid(acc[bi][bj][v] + bj_val);
-                if (H) H[gi * ldh + gj] = h;
-                if (Hlp) store_lp<T>(Hlp, lp_dt, gj * ldlp + gi, h);
+                const int li = wm * 64 + i * 16 + Mfma16<T>::row(lane, v);
+                const int64_t gi = n0 + li;
+                const T h = sigmoid(acc[i][j][v] + bj_val);
+                if (H && gi < N && gj < L) H[gi * ldh + gj] = h;
+                if (lp16) st16[lj * (HT + 8) + li] = lp16_bits<T>(lp_dt, h);
+                if (lp32) st32[lj * (HT + 4) + li] = (float)h;
+            }
+        }
+    }
+    if (!Hlp) return;
+    __syncthreads();
+    // node-major copy: each node's 128 samples are 256 B (16-bit) or 512 B
+    // (FP32), written in 16-byte pieces where the tile is whole and aligned
+    const int esz = lp16 ? 2 : 4;
+    const int per = 16 / esz;  // elements per 16-byte piece
+    const bool vec = n0 + HT <= N && (((uintptr_t)Hlp | (uintptr_t)(ldlp * esz)) & 15) == 0;
+    const int pieces = HT / per;  // per node
+    for (int e = tid; e < HT * pieces; e += NT) {
+        const int lj = e / pieces, q = e % pieces;
+        const int64_t gj = j0 + lj;
+        if (gj >= L) continue;
+        const int64_t gi = n0 + q * per;
+        if (vec) {
+            const uint4 val = lp16 ? *(const uint4*)&st16[lj * (HT + 8) + q * per]
+                                   : *(const uint4*)&st32[lj * (HT + 4) + q * per];
+            *(uint4*)((char*)Hlp + (gj * ldlp + gi) * esz) = val;
+        } else {
+            for (int u = 0; u < per; ++u) {
+                if (gi + u >= N) break;
+                if (lp16)
+                    ((uint16_t*)Hlp)[gj * ldlp + gi + u] = st16[lj * (HT + 8) + q * per + u];
+                else
+                    ((float*)Hlp)[gj * ldlp + gi + u] = st32[lj * (HT + 4) + q * per + u];
             }
         }
     }
@@ -128,15 +211,17 @@ __global__ __launch_bounds__(NT) void hidden_kernel(int64_t N, int64_t d, int64_
 void launch_hidden(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L, const void* X,
                    int64_t ldx, const void* W, int64_t ldw, const void* b, void* H, int64_t ldh,
                    void* Hlp, int64_t ldlp, elm_dtype lp_dt) {
-    dim3 grid((unsigned)cdiv(N, BM), (unsigned)cdiv(L, BN));
+    const int64_t nrow_t = cdiv(N, HT), ncol_t = cdiv(L, HT);
+    const int64_t per_xcd = nrow_t * cdiv(ncol_t, XCDS);  // work items of the busiest XCD
+    const unsigned grid = (unsigned)(XCDS * per_xcd);
     if (dt == ELM_F64) {
-        hidden_kernel<double><<<grid, NT, 0, s>>>(N, d, L, (const double*)X, ldx, (const double*)W,
-                                                  ldw, (const double*)b, (double*)H, ldh, Hlp,
-                                                  ldlp, lp_dt);
+        hidden_kernel<double><<<grid, NT, 0, s>>>(N, d, L, nrow_t, ncol_t, (const double*)X, ldx,
+                                                  (const double*)W, ldw, (const double*)b,
+                                                  (double*)H, ldh, Hlp, ldlp, lp_dt);
     } else {
-        hidden_kernel<float><<<grid, NT, 0, s>>>(N, d, L, (const float*)X, ldx, (const float*)W,
-                                                 ldw, (const float*)b, (float*)H, ldh, Hlp, ldlp,
-                                                 lp_dt);
+        hidden_kernel<float><<<grid, NT, 0, s>>>(N, d, L, nrow_t, ncol_t, (const float*)X, ldx,
+                                                 (const float*)W, ldw, (const float*)b, (float*)H,
+                                                 ldh, Hlp, ldlp, lp_dt);
     }
     ELM_LAUNCH_CHECK();
 }

@@ -32,33 +32,67 @@ namespace {
 
 constexpr int PT = 256;     // threads per block, step kernels
 constexpr int NB = 128;     // panel width
-constexpr int TT = 64;      // trailing-update tile
+static_assert(NB <= 16 * 8, "a step covers at most 8 groups of 16 panel rows");
+constexpr int TT = 128;     // trailing-update tile
 enum { ST_DONE = 0, ST_RANK = 1, ST_BAD = 2, ST_CUR = 3, ST_NREM = 4, ST_N = 5 };
 
 __device__ inline bool better(double v1, int o1, double v2, int o2) {
     return v1 > v2 || (v1 == v2 && o1 < o2);
 }
 
-// all lanes of the wave end with the wave-wide best (v, o, p)
-__device__ inline void wave_argmax(double& v, int& o, int& p) {
+// One argmax candidate: Schur diagonal v, original index o, position p.
+struct __align__(16) Part {
+    double v;
+    int o;
+    int p;
+};
+
+__device__ inline Part part_none() { return Part{-INFINITY, INT_MAX, -1}; }
+
+__device__ inline void part_take(Part& b, const Part& x) {
+    if (better(x.v, x.o, b.v, b.o)) b = x;
+}
+
+// all lanes of the wave end with the wave-wide best
+__device__ inline void wave_argmax(Part& b) {
     for (int off = 32; off > 0; off >>= 1) {
-        double v2 = __shfl_xor(v, off);
-        int o2 = __shfl_xor(o, off);
-        int p2 = __shfl_xor(p, off);
-        if (better(v2, o2, v, o)) { v = v2; o = o2; p = p2; }
+        Part x;
+        x.v = __shfl_xor(b.v, off);
+        x.o = __shfl_xor(b.o, off);
+        x.p = __shfl_xor(b.p, off);
+        part_take(b, x);
     }
 }
 
-struct Parts {
-    double* v;
-    int* o;
-    int* p;
-};
+// block-wide best, written to out[blockIdx.x] by thread 0.  `better` is a
+// strict total order on (v, o) with distinct original indices, so the result
+// does not depend on the combination order.
+__device__ inline void block_argmax_store(Part b, Part* __restrict__ out) {
+    __shared__ Part wbest[PT / 64];
+    wave_argmax(b);
+    if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Part r = wbest[0];
+#pragma unroll
+        for (int w = 1; w < PT / 64; ++w) part_take(r, wbest[w]);
+        out[blockIdx.x] = r;
+    }
+}
 
-__global__ void init_kernel(int64_t n, int* rem0, int* state) {
+// pivot statistics: last accepted pivot, largest Schur diagonal at the stop
+// (-inf when every position is accepted), largest Gram diagonal
+enum { PS_LAST = 0, PS_REJECT = 1, PS_MAX = 2, PS_N = 3 };
+
+__global__ void init_kernel(int64_t n, int* rem0, int* state, double* pstats) {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a < n) rem0[a] = (int)a;
     if (a < ST_N) state[a] = 0;
+    if (a == 0) {
+        pstats[PS_LAST] = INFINITY;
+        pstats[PS_REJECT] = -INFINITY;
+        pstats[PS_MAX] = 0.0;
+    }
 }
 
 __global__ void fill_kernel(double* p, int64_t count, double v) {
@@ -67,120 +101,124 @@ __global__ void fill_kernel(double* p, int64_t count, double v) {
         p[i] = v;
 }
 
-// partials are per wave: slot blockIdx.x * WPB + wave
-constexpr int WPB = PT / 64;
-
 __global__ __launch_bounds__(PT) void panel_start_kernel(int64_t n_rem, const double* __restrict__ S,
                                                          int64_t lds, double* __restrict__ d,
                                                          int* __restrict__ chosen, const int* rem0,
-                                                         const int* rem1, Parts out, int* state) {
+                                                         const int* rem1, Part* __restrict__ out,
+                                                         int* state) {
     if (state[ST_DONE]) return;
     const int* rem = state[ST_CUR] ? rem1 : rem0;
     const int64_t a = (int64_t)blockIdx.x * PT + threadIdx.x;
-    double v = -INFINITY;
-    int o = INT_MAX, p = -1;
+    Part b = part_none();
     if (a < n_rem) {
         const double x = S[a * lds + a];
         d[a] = x;
         chosen[a] = 0;
         if (!isfinite(x)) state[ST_BAD] = 1;
-        v = x; o = rem[a]; p = (int)a;
+        b = Part{x, rem[a], (int)a};
     }
-    wave_argmax(v, o, p);
-    if ((threadIdx.x & 63) == 0) {
-        const int slot = blockIdx.x * WPB + (threadIdx.x >> 6);
-        out.v[slot] = v; out.o[slot] = o; out.p[slot] = p;
-    }
+    block_argmax_store(b, out);
 }
 
+// One pivot.  G lanes share each remaining position a; lane group g holds
+// panel rows [16 g, 16 g + 16) of the dot product
+//   P[t][a] = (S[p][a] - sum_{q<t} P[q][p] P[q][a]) / sqrt(d[p]),
+// so every lane issues at most 16 + 16 loads and the kernel is two dependent
+// memory round trips: (flags, argmax partials, d, chosen, rem, P[.][a]) and,
+// once the pivot p is known, (S[p][a], P[.][p]).  The partial sums are
+// combined by an xor butterfly, so every lane holds the same bits and the
+// order of operations is the same for every position: identical columns of
+// the Gram stay bitwise identical.
+template <int G>
 __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_rem,
                                                   const double* __restrict__ S, int64_t lds,
                                                   double* __restrict__ P, int64_t ldp,
                                                   double* __restrict__ d, int* __restrict__ chosen,
-                                                  const int* rem0, const int* rem1, Parts in,
-                                                  int nparts, Parts out, int* state, double tau,
-                                                  int* __restrict__ piv) {
-    // The kernel is a chain of dependent memory round trips, so loads that do
-    // not depend on each other are issued together: (flags, all partials),
-    // then (S row entry, d, chosen, rem, the panel column).
+                                                  const int* rem0, const int* rem1,
+                                                  const Part* __restrict__ in, int nparts,
+                                                  Part* __restrict__ out, int* state, double tau,
+                                                  int* __restrict__ piv, double* __restrict__ pstats) {
+    constexpr int CPW = 64 / G;  // positions per wave
+    constexpr int CPB = CPW * (PT / 64);
     const int lane = threadIdx.x & 63;
+    const int g = lane / CPW;
+    const int64_t a = (int64_t)blockIdx.x * CPB + (threadIdx.x >> 6) * CPW + lane % CPW;
+    const int64_t ac = a < n_rem ? a : n_rem - 1;  // in-bounds twin for the batched loads
+    const int q0 = 16 * g;
+
+    // round trip 1: nothing here depends on the pivot
     const int done = state[ST_DONE];
     const int cur = state[ST_CUR];
-    // every wave reduces all of the previous launch's per-wave partials itself
-    double pv[4];
-    int po[4], pq[4];
+    Part pin[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
         const int i = lane + 64 * j;
-        const bool ok = i < nparts;
-        pv[j] = ok ? in.v[i] : -INFINITY;
-        po[j] = ok ? in.o[i] : INT_MAX;
-        pq[j] = ok ? in.p[i] : -1;
+        pin[j] = i < nparts ? in[i] : part_none();
     }
-    double bv = -INFINITY;
-    int bo = INT_MAX, bp = -1;
+    double y[16];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if (better(pv[j], po[j], bv, bo)) { bv = pv[j]; bo = po[j]; bp = pq[j]; }
-    for (int i = lane + 256; i < nparts; i += 64)
-        if (better(in.v[i], in.o[i], bv, bo)) { bv = in.v[i]; bo = in.o[i]; bp = in.p[i]; }
+    for (int u = 0; u < 16; ++u) y[u] = (q0 + u < t) ? P[(int64_t)(q0 + u) * ldp + ac] : 0.0;
+    const double d_a = d[ac];
+    const int ch = chosen[ac];
+    const int ra = cur ? rem1[ac] : rem0[ac];
+
+    Part best = part_none();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) part_take(best, pin[j]);
+    for (int i = lane + 512; i < nparts; i += 64) part_take(best, in[i]);
     if (done) return;
-    wave_argmax(bv, bo, bp);
-    bp = __builtin_amdgcn_readfirstlane(bp);
-    bo = __builtin_amdgcn_readfirstlane(bo);
+    wave_argmax(best);
+    const int bp = __builtin_amdgcn_readfirstlane(best.p);
+    const int bo = __builtin_amdgcn_readfirstlane(best.o);
+    const double bv = best.v;
     if (!(bv > tau)) {  // largest remaining Schur diagonal at or below tau: rank = k
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             state[ST_RANK] = (int)k;
             state[ST_NREM] = (int)n_rem;
             state[ST_DONE] = 1;
+            pstats[PS_REJECT] = bv;
+            if (k == 0) pstats[PS_MAX] = bv;
         }
         return;
     }
+
+    // round trip 2: the pivot's Schur row entry and panel column
+    const double s0 = S[(int64_t)bp * lds + ac];
+    double x[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) x[u] = (q0 + u < t) ? P[(int64_t)(q0 + u) * ldp + bp] : 0.0;
+    double part = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) part += x[u] * y[u];
+#pragma unroll
+    for (int off = CPW; off < 64; off <<= 1) part += __shfl_xor(part, off);
+
     const double rpp = sqrt(bv);
-    const int64_t a = (int64_t)blockIdx.x * PT + threadIdx.x;
-    const int64_t ac = a < n_rem ? a : n_rem - 1;  // in-bounds twin for the batched loads
-    double s = S[(int64_t)bp * lds + ac];
-    const double d_a = d[ac];
-    const int ch = chosen[ac];
-    const int ra = cur ? rem1[ac] : rem0[ac];
-    // S[p][a] - sum_{q < t} P[q][p] P[q][a]; P[q][p] is the same for the whole
-    // wave.  Chunks of 16 keep 32 loads in flight.
-    const double* __restrict__ pa = P + ac;
-    const double* __restrict__ pp = P + bp;
-    int q = 0;
-    for (; q + 16 <= t; q += 16) {
-        double x[16], y[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            x[u] = pp[(int64_t)(q + u) * ldp];
-            y[u] = pa[(int64_t)(q + u) * ldp];
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) s -= x[u] * y[u];
-    }
-    for (; q < t; ++q) s -= pp[(int64_t)q * ldp] * pa[(int64_t)q * ldp];
-    double v = -INFINITY;
-    int o = INT_MAX, p = -1;
+    Part cand = part_none();
     if (a < n_rem) {
         if (a == bp) {
-            P[(int64_t)t * ldp + a] = rpp;
-            chosen[a] = 1;
+            if (g == 0) {
+                P[(int64_t)t * ldp + a] = rpp;
+                chosen[a] = 1;
+            }
         } else if (ch) {
-            P[(int64_t)t * ldp + a] = 0.0;
+            if (g == 0) P[(int64_t)t * ldp + a] = 0.0;
         } else {
-            const double val = s / rpp;
-            P[(int64_t)t * ldp + a] = val;
+            const double val = (s0 - part) / rpp;
             const double da = d_a - val * val;
-            d[a] = da;
-            v = da; o = ra; p = (int)a;
+            if (g == 0) {
+                P[(int64_t)t * ldp + a] = val;
+                d[a] = da;
+                cand = Part{da, ra, (int)a};
+            }
         }
     }
-    wave_argmax(v, o, p);
-    if (lane == 0) {
-        const int slot = blockIdx.x * WPB + (threadIdx.x >> 6);
-        out.v[slot] = v; out.o[slot] = o; out.p[slot] = p;
+    block_argmax_store(cand, out);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        piv[k] = bo;
+        pstats[PS_LAST] = bv;  // accepted pivots are non-increasing
+        if (k == 0) pstats[PS_MAX] = bv;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) piv[k] = bo;
 }
 
 // panel rows -> R, columns by original index
@@ -263,16 +301,23 @@ __global__ __launch_bounds__(1024) void finalize_kernel(int64_t n,
     block_compact(state[ST_NREM], chosen, rem, piv + r, nullptr);
 }
 
-// S'[a][b] = S[q(a)][q(b)] - sum_t P[t][q(a)] P[t][q(b)], upper tiles, mirrored
-__global__ __launch_bounds__(256) void trailing_kernel(int64_t n_new, const double* __restrict__ S,
-                                                       int64_t lds, double* __restrict__ Sn,
-                                                       int64_t ldsn, const double* __restrict__ P,
-                                                       int64_t ldp, int nbp,
-                                                       const int* __restrict__ map, const int* state) {
+// S'[a][b] = S[q(a)][q(b)] - sum_t P[t][q(a)] P[t][q(b)], upper TT x TT
+// tiles, mirrored.  4 waves in 2 x 2, each (TT/2)^2 as 16 x 16 FP64 MFMA
+// blocks; the panel rows are gathered through the compaction map into
+// k-major LDS tiles, double-buffered through registers.
+__global__ __launch_bounds__(256, 2) void trailing_kernel(int64_t n_new, const double* __restrict__ S,
+                                                          int64_t lds, double* __restrict__ Sn,
+                                                          int64_t ldsn, const double* __restrict__ P,
+                                                          int64_t ldp, int nbp,
+                                                          const int* __restrict__ map,
+                                                          const int* state) {
     if (state[ST_DONE]) return;
     constexpr int BK = 16;
-    __shared__ double As[BK][TT + 1];
-    __shared__ double Bs[BK][TT + 1];
+    constexpr int PP = TT + 16;           // LDS pitch: 4 k rows of an operand read on disjoint banks
+    constexpr int EPT = TT * BK / 256;    // panel entries per thread per operand tile
+    constexpr int WB = TT / 32;
+    __shared__ double As[2][BK][PP];
+    __shared__ double Bs[2][BK][PP];
     __shared__ int qa[TT], qb[TT];
 
     // tile index -> (bi <= bj)
@@ -291,35 +336,64 @@ __global__ __launch_bounds__(256) void trailing_kernel(int64_t n_new, const doub
     }
     __syncthreads();
 
-    d4v acc[2][2];
-    for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y) acc[x][y] = d4v{};
-
-    for (int k0 = 0; k0 < nbp; k0 += BK) {
-        for (int e = tid; e < BK * TT; e += 256) {
-            const int k = e / TT, i = e % TT;
-            const bool kin = (k0 + k) < nbp;
-            As[k][i] = (kin && r0 + i < n_new) ? P[(int64_t)(k0 + k) * ldp + qa[i]] : 0.0;
-            Bs[k][i] = (kin && c0 + i < n_new) ? P[(int64_t)(k0 + k) * ldp + qb[i]] : 0.0;
+    // thread -> panel row k, positions i .. i + EPT - 1 of the tile
+    const int lk = (tid * EPT) / TT, li0 = (tid * EPT) % TT;
+    double av[EPT], bv[EPT];
+    auto load = [&](int k0) {
+        const bool kin = k0 + lk < nbp;
+        const double* prow = P + (int64_t)(k0 + lk) * ldp;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            av[e] = (kin && r0 + li0 + e < n_new) ? prow[qa[li0 + e]] : 0.0;
+            bv[e] = (kin && c0 + li0 + e < n_new) ? prow[qb[li0 + e]] : 0.0;
         }
-        __syncthreads();
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            As[buf][lk][li0 + e] = av[e];
+            Bs[buf][lk][li0 + e] = bv[e];
+        }
+    };
+
+    d4v acc[WB][WB];
+#pragma unroll
+    for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y) acc[x][y] = d4v{};
+
+    load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < nbp; k0 += BK) {
+        const bool more = k0 + BK < nbp;
+        if (more) load(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int k = kk + (lane >> 4);
-            const double a0 = As[k][wm * 32 + (lane & 15)], a1 = As[k][wm * 32 + 16 + (lane & 15)];
-            const double b0 = Bs[k][wn * 32 + (lane & 15)], b1 = Bs[k][wn * 32 + 16 + (lane & 15)];
-            acc[0][0] = Mfma16<double>::op(a0, b0, acc[0][0]);
-            acc[0][1] = Mfma16<double>::op(a0, b1, acc[0][1]);
-            acc[1][0] = Mfma16<double>::op(a1, b0, acc[1][0]);
-            acc[1][1] = Mfma16<double>::op(a1, b1, acc[1][1]);
+            double a[WB], b[WB];
+#pragma unroll
+            for (int x = 0; x < WB; ++x) a[x] = As[buf][k][wm * (TT / 2) + x * 16 + (lane & 15)];
+#pragma unroll
+            for (int y = 0; y < WB; ++y) b[y] = Bs[buf][k][wn * (TT / 2) + y * 16 + (lane & 15)];
+#pragma unroll
+            for (int x = 0; x < WB; ++x)
+#pragma unroll
+                for (int y = 0; y < WB; ++y) acc[x][y] = Mfma16<double>::op(a[x], b[y], acc[x][y]);
         }
+        if (more) store(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
     }
-    for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y)
+#pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int li = wm * 32 + x * 16 + Mfma16<double>::row(lane, v);
-                const int lj = wn * 32 + y * 16 + (lane & 15);
+                const int li = wm * (TT / 2) + x * 16 + Mfma16<double>::row(lane, v);
+                const int lj = wn * (TT / 2) + y * 16 + (lane & 15);
                 const int64_t gi = r0 + li, gj = c0 + lj;
                 if (gi >= n_new || gj >= n_new || gi > gj) continue;
                 const double val = S[(int64_t)qa[li] * lds + qb[lj]] - acc[x][y][v];
@@ -338,27 +412,26 @@ __global__ void gather_kernel(int64_t r, int64_t n, const double* __restrict__ R
 }  // namespace
 
 int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double tau,
-                         int32_t* piv, double** R_out, Workspace& ws) {
-    const int64_t nparts_max = cdiv(n, PT) * WPB;
+                         int32_t* piv, double** R_out, double* stats_out, Workspace& ws) {
+    const int64_t nparts_max = cdiv(n, PT / 8);  // most blocks of any step launch
     int* state = (int*)ws.get("pc_state", ST_N * sizeof(int));
+    double* pstats = (double*)ws.get("pc_stats", PS_N * sizeof(double));
     int* rem0 = (int*)ws.get("pc_rem0", n * sizeof(int));
     int* rem1 = (int*)ws.get("pc_rem1", n * sizeof(int));
     int* map = (int*)ws.get("pc_map", n * sizeof(int));
     int* chosen = (int*)ws.get("pc_chosen", n * sizeof(int));
     double* d = (double*)ws.get("pc_d", n * sizeof(double));
     double* P = (double*)ws.get("pc_P", (size_t)NB * n * sizeof(double));
-    double* pv = (double*)ws.get("pc_pv", 2 * nparts_max * sizeof(double));
-    int* po = (int*)ws.get("pc_po", 2 * nparts_max * sizeof(int));
-    int* pp = (int*)ws.get("pc_pp", 2 * nparts_max * sizeof(int));
+    Part* parts = (Part*)ws.get("pc_parts", 2 * nparts_max * sizeof(Part));
     double* Rorig = (double*)ws.get("pc_Rorig", (size_t)n * n * sizeof(double));
     double* Sbuf[2] = {nullptr, nullptr};
     if (n > NB) {
         Sbuf[0] = (double*)ws.get("pc_S0", (size_t)n * n * sizeof(double));
         Sbuf[1] = (double*)ws.get("pc_S1", (size_t)n * n * sizeof(double));
     }
-    Parts part[2] = {{pv, po, pp}, {pv + nparts_max, po + nparts_max, pp + nparts_max}};
+    Part* part[2] = {parts, parts + nparts_max};
 
-    init_kernel<<<(unsigned)cdiv(n > ST_N ? n : ST_N, 256), 256, 0, s>>>(n, rem0, state);
+    init_kernel<<<(unsigned)cdiv(n > ST_N ? n : ST_N, 256), 256, 0, s>>>(n, rem0, state, pstats);
     ELM_LAUNCH_CHECK();
     fill_kernel<<<1024, 256, 0, s>>>(Rorig, n * n, 0.0);
     ELM_LAUNCH_CHECK();
@@ -370,16 +443,38 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
     while (ps < n) {
         const int nbp = (int)(n_rem < NB ? n_rem : NB);
         const int nblk = (int)cdiv(n_rem, PT);
-        const int nparts = nblk * WPB;
         panel_start_kernel<<<nblk, PT, 0, s>>>(n_rem, Scur, lds, d, chosen, rem0, rem1,
                                                  part[ps & 1], state);
         ELM_LAUNCH_CHECK();
+        int nparts = nblk;
         for (int t = 0; t < nbp; ++t) {
             const int64_t k = ps + t;
-            step_kernel<<<nblk, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
-                                              part[k & 1], nparts, part[(k + 1) & 1], state, tau,
-                                              piv);
+            Part* pin = part[k & 1];
+            Part* pout = part[(k + 1) & 1];
+            // lanes per position: enough 16-row groups to cover the t panel rows
+            int g = 1;
+            while (16 * g < t) g *= 2;
+            const int nb = (int)cdiv(n_rem, PT / g);
+            switch (g) {
+            case 1:
+                step_kernel<1><<<nb, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
+                                                 pin, nparts, pout, state, tau, piv, pstats);
+                break;
+            case 2:
+                step_kernel<2><<<nb, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
+                                                 pin, nparts, pout, state, tau, piv, pstats);
+                break;
+            case 4:
+                step_kernel<4><<<nb, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
+                                                 pin, nparts, pout, state, tau, piv, pstats);
+                break;
+            default:
+                step_kernel<8><<<nb, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
+                                                 pin, nparts, pout, state, tau, piv, pstats);
+                break;
+            }
             ELM_LAUNCH_CHECK();
+            nparts = nb;
         }
         scatter_kernel<<<dim3((unsigned)nblk, (unsigned)nbp), PT, 0, s>>>(
             ps, nbp, n_rem, P, n, rem0, rem1, Rorig, n, state);
@@ -405,6 +500,7 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
 
     int hstate[ST_N];
     ELM_HIP_TRY(hipMemcpyAsync(hstate, state, sizeof(hstate), hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipMemcpyAsync(stats_out, pstats, PS_N * sizeof(double), hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));
     if (hstate[ST_BAD]) throw Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
     const int64_t r = hstate[ST_RANK];

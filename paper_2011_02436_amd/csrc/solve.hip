@@ -20,6 +20,10 @@ namespace elm {
 void gemm_f64(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
               int64_t a_rs, int64_t a_cs, const double* B, int64_t b_rs, int64_t b_cs, double beta,
               double* C, int64_t ldc);
+void gemm_f64_batched(hipStream_t s, int64_t batch, int64_t M, int64_t N, int64_t K, double alpha,
+                      const double* A, int64_t a_rs, int64_t a_cs, int64_t a_bs, const double* B,
+                      int64_t b_rs, int64_t b_cs, int64_t b_bs, double beta, double* C, int64_t ldc,
+                      int64_t c_bs, bool tri_a, bool tri_b);
 
 namespace {
 
@@ -222,19 +226,37 @@ void trtri_upper(hipStream_t s, int64_t r, const double* U, int64_t ldu, double*
     zero_mat(s, r, r, X, ldx);
     trtri_leaf_kernel<<<(unsigned)cdiv(r, LB), LB, 0, s>>>(r, U, ldu, X, ldx);
     ELM_LAUNCH_CHECK();
-    int64_t szmax = 0;
-    for (int64_t sz = LB; sz < r; sz *= 2) szmax = sz;
-    double* T1 = szmax ? (double*)ws.get("trtri_T1", (size_t)szmax * szmax * sizeof(double)) : nullptr;
+    // level sz joins pairs of inverted diagonal blocks a = [a0, a0 + sz),
+    // c = [a0 + sz, a0 + 2 sz):  X[a, c] = -X[a, a] U[a, c] X[c, c].
+    // The full-size pairs of a level share one launch per product; a ragged
+    // last pair gets its own.
+    size_t t1_max = 0;
     for (int64_t sz = LB; sz < r; sz *= 2) {
-        for (int64_t a0 = 0; a0 < r; a0 += 2 * sz) {
-            const int64_t c0 = a0 + sz;
-            if (c0 >= r) continue;
-            const int64_t na = sz, nc = (r - c0) < sz ? (r - c0) : sz;
-            // T1 = U[a, c] * X[c, c];  X[a, c] = -X[a, a] * T1
-            gemm_f64(s, na, nc, nc, 1.0, U + a0 * ldu + c0, ldu, 1, X + c0 * ldx + c0, ldx, 1, 0.0,
-                     T1, nc);
-            gemm_f64(s, na, nc, na, -1.0, X + a0 * ldx + a0, ldx, 1, T1, nc, 1, 0.0,
-                     X + a0 * ldx + c0, ldx);
+        const int64_t full = r / (2 * sz);
+        size_t need = (size_t)full * sz * sz;
+        if (full * 2 * sz + sz < r) need += (size_t)sz * sz;
+        if (need > t1_max) t1_max = need;
+    }
+    double* T1 = t1_max ? (double*)ws.get("trtri_T1", t1_max * sizeof(double)) : nullptr;
+    for (int64_t sz = LB; sz < r; sz *= 2) {
+        const int64_t full = r / (2 * sz);  // pairs with both halves of size sz
+        const int64_t pstride_u = 2 * sz * (ldu + 1), pstride_x = 2 * sz * (ldx + 1);
+        if (full > 0) {
+            // T1_p = U[a, c] X[c, c]   (X[c, c] upper triangular)
+            gemm_f64_batched(s, full, sz, sz, sz, 1.0, U + sz, ldu, 1, pstride_u, X + sz * ldx + sz, ldx,
+                             1, pstride_x, 0.0, T1, sz, sz * sz, false, true);
+            // X[a, c] = -X[a, a] T1_p   (X[a, a] upper triangular)
+            gemm_f64_batched(s, full, sz, sz, sz, -1.0, X, ldx, 1, pstride_x, T1, sz, 1, sz * sz, 0.0,
+                             X + sz, ldx, pstride_x, true, false);
+        }
+        const int64_t a0 = full * 2 * sz, c0 = a0 + sz;
+        if (c0 < r) {
+            const int64_t nc = r - c0;
+            double* T1r = T1 + (size_t)full * sz * sz;
+            gemm_f64_batched(s, 1, sz, nc, nc, 1.0, U + a0 * ldu + c0, ldu, 1, 0, X + c0 * ldx + c0, ldx,
+                             1, 0, 0.0, T1r, nc, 0, false, true);
+            gemm_f64_batched(s, 1, sz, nc, sz, -1.0, X + a0 * ldx + a0, ldx, 1, 0, T1r, nc, 1, 0, 0.0,
+                             X + a0 * ldx + c0, ldx, 0, true, false);
         }
     }
 }
@@ -280,7 +302,9 @@ void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws) {
     f->RinvT = transposed_copy(s, r, r, f->Rinv, r);
     if (c > 0) {
         ELM_HIP_TRY(hipMalloc(&f->K, (size_t)r * c * sizeof(double)));
-        gemm_f64(s, r, c, r, 1.0, f->Rinv, r, 1, f->R + r, n, 1, 0.0, f->K, c);   // K = R11^-1 R12
+        // K = R11^-1 R12 (R11^-1 upper triangular)
+        gemm_f64_batched(s, 1, r, c, r, 1.0, f->Rinv, r, 1, 0, f->R + r, n, 1, 0, 0.0, f->K, c, 0, true,
+                         false);
         f->KT = transposed_copy(s, r, c, f->K, c);
     }
     const int64_t q = r < c ? r : c;

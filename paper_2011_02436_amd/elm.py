@@ -26,6 +26,7 @@ ELM_SAMPLE_MAJOR, ELM_NODE_MAJOR = 0, 1
 _DT = {torch.float64: ELM_F64, torch.float32: ELM_F32, torch.bfloat16: ELM_BF16,
        torch.float16: ELM_F16}
 _LP = {"bf16": torch.bfloat16, "fp16": torch.float16, "fp32": torch.float32}
+_DT_NAME = {ELM_F64: "fp64", ELM_F32: "fp32", ELM_BF16: "bf16", ELM_F16: "fp16"}
 
 
 class ElmError(RuntimeError):
@@ -44,6 +45,33 @@ class SolveInfo(ctypes.Structure):
         return {"rank": int(self.rank), "transposed": bool(self.transposed),
                 "iterations": int(self.iterations), "ne_residual": float(self.ne_residual),
                 "ne_history": [float(self.ne_history[i]) for i in range(min(n, 32))]}
+
+
+class FactorInfo(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int64), ("n", ctypes.c_int64), ("transposed", ctypes.c_int32),
+                ("gram_dtype", ctypes.c_int32), ("max_diag", ctypes.c_double),
+                ("last_pivot", ctypes.c_double), ("first_rejected", ctypes.c_double),
+                ("tau", ctypes.c_double), ("noise_floor", ctypes.c_double), ("reliable", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"rank": int(self.rank), "n": int(self.n), "transposed": bool(self.transposed),
+                "gram_dtype": _DT_NAME.get(int(self.gram_dtype), "?"), "max_diag": float(self.max_diag),
+                "last_pivot": float(self.last_pivot), "first_rejected": float(self.first_rejected),
+                "tau": float(self.tau), "noise_floor": float(self.noise_floor),
+                "reliable": bool(self.reliable)}
+
+
+class TrainInfo(ctypes.Structure):
+    _fields_ = [("solve", SolveInfo), ("factor", FactorInfo), ("gram_dtype", ctypes.c_int32),
+                ("escalations", ctypes.c_int32), ("guard", ctypes.c_int32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("d", ctypes.c_int64), ("L", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("W", ctypes.c_void_p), ("ldw", ctypes.c_int64),
+                ("b", ctypes.c_void_p), ("T", ctypes.c_void_p), ("ldt", ctypes.c_int64),
+                ("H64", ctypes.c_void_p), ("ldh64", ctypes.c_int64),
+                ("beta", ctypes.c_void_p), ("ldbeta", ctypes.c_int64)]
 
 
 STAGES = ["hidden", "gram", "gram_reduce", "rank", "factor", "solve", "rhs", "residual", "predict"]
@@ -71,6 +99,11 @@ def _load():
         "elm_factor_rank": ([vp, ctypes.POINTER(i64)], i32),
         "elm_factor_pivots": ([vp, vp, ctypes.POINTER(i32)], i32),
         "elm_factor_destroy": ([vp], i32),
+        "elm_factor_get_info": ([vp, ctypes.POINTER(FactorInfo)], i32),
+        "elm_train_batched": ([vp, i32, ctypes.POINTER(Problem), i32, dbl, dbl, i32,
+                               ctypes.POINTER(TrainInfo), ctypes.POINTER(i32)], i32),
+        "elm_train": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, vp, i64, i32, vp, i64, vp, i64,
+                       dbl, dbl, i32, vp, i64, ctypes.POINTER(TrainInfo), ctypes.POINTER(vp)], i32),
         "elm_pinv_solve": ([vp, vp, i64, vp, i64, vp, i64, dbl, i32, vp, i64,
                             ctypes.POINTER(SolveInfo)], i32),
         "elm_predict": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, vp],
@@ -89,7 +122,8 @@ def _load():
 _lib = _load()
 EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", "elm_last_error",
             "elm_hidden", "elm_gram", "elm_rank_factor", "elm_factor_rank", "elm_factor_pivots",
-            "elm_factor_destroy", "elm_pinv_solve", "elm_predict", "elm_predict_hidden",
+            "elm_factor_destroy", "elm_factor_get_info", "elm_train", "elm_train_batched",
+            "elm_pinv_solve", "elm_predict", "elm_predict_hidden",
             "elm_profile_enable", "elm_profile_read"]
 
 
@@ -217,6 +251,14 @@ class Factor:
     @property
     def n(self) -> int:
         return min(self.N, self.L)
+
+    def info(self) -> dict:
+        """Rank-decision diagnostics: pivots, noise floor, reliability."""
+        out = FactorInfo()
+        st = _lib.elm_factor_get_info(self.ptr, ctypes.byref(out))
+        if st != 0:
+            raise ElmError(st, "elm_factor_get_info", "")
+        return out.as_dict()
 
     def pivots(self):
         import numpy as np
@@ -352,28 +394,104 @@ def train(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, T: torch.Tensor, pr
           ir_tol: float = 1e-10, ir_max_iter: Optional[int] = None, tau_rel: float = 0.0,
           H64: Optional[torch.Tensor] = None, Hlp: Optional[torch.Tensor] = None,
           check_convergence: bool = True) -> TrainResult:
-    """H = g(XW + b) -> rank factor -> beta = H^+ T (+ FP64 refinement).
+    """H = g(XW + b) -> rank factor -> beta = H^+ T (+ FP64 refinement), one
+    elm_train call.
 
     precision: 'fp64' (FP64 Gram), or 'fp32' / 'bf16' / 'fp16' (Gram of a
     node-major low-precision copy; the rank decision and the refinement
-    residual stay in FP64).  X, W, b must be float64; H64/Hlp may be passed
-    preallocated to keep allocation out of timed regions."""
+    residual stay in FP64, and a failed guard moves the Gram one precision
+    up).  X, W, b, T must be float64; H64 (N x L float64) and Hlp (L x N of
+    the precision's dtype) may be passed preallocated to keep allocation out
+    of timed regions.  info holds the solve report plus 'factor' (rank
+    diagnostics), 'gram_dtype', 'escalations' and 'guard'."""
+    if precision not in ("fp64", "fp32", "bf16", "fp16"):
+        raise ValueError("precision must be one of fp64, fp32, bf16, fp16")
+    h = handle()
     N, d = X.shape
     L = W.shape[1]
+    m = T.shape[1]
+    for name, t in (("X", X), ("W", W), ("b", b), ("T", T)):
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name} must be float64")
     if H64 is None:
         H64 = torch.empty((N, L), dtype=torch.float64, device=X.device)
-    if precision == "fp64":
-        elm_hidden(X, W, b, H=H64)
-        factor = elm_rank_factor(H64, "sample", tau_rel)
-        its = 2 if ir_max_iter is None else ir_max_iter
+    gdt = {"fp64": ELM_F64, "fp32": ELM_F32, "bf16": ELM_BF16, "fp16": ELM_F16}[precision]
+    lp_ptr, ldlp = None, 0
+    if precision != "fp64" and Hlp is not None:
+        if Hlp.dtype != _LP[precision] or tuple(Hlp.shape) != (L, N):
+            raise ValueError("Hlp must be L x N of the precision's dtype")
+        lp_ptr, ldlp = _mat(Hlp, "Hlp")
+    its = (2 if precision == "fp64" else 30) if ir_max_iter is None else ir_max_iter
+    xp, ldx = _mat(X, "X")
+    wp, ldw = _mat(W, "W")
+    tp, ldt = _mat(T, "T")
+    hp, ldh = _mat(H64, "H64")
+    beta = torch.empty((L, m), dtype=torch.float64, device=X.device)
+    bp, ldb = _mat(beta, "beta")
+    ti = TrainInfo()
+    fptr = ctypes.c_void_p()
+    st = _lib.elm_train(h.ptr, N, d, L, m, xp, ldx, wp, ldw, _vec(b, "b"), tp, ldt, gdt, hp, ldh,
+                        lp_ptr, ldlp, tau_rel, ir_tol, its, bp, ldb, ctypes.byref(ti), ctypes.byref(fptr))
+    if st == ELM_ERR_NO_CONVERGENCE and not check_convergence:
+        pass
     else:
-        dt = _LP[precision]
-        if N < L:
-            raise ValueError("low-precision Gram requires N >= L; use precision='fp64'")
-        if Hlp is None:
-            Hlp = torch.empty((L, N), dtype=dt, device=X.device)
-        elm_hidden(X, W, b, H=H64, Hlp=Hlp)
-        factor = elm_rank_factor(Hlp, "node", tau_rel)
-        its = 30 if ir_max_iter is None else ir_max_iter
-    beta, info = elm_pinv_solve(factor, T, H64, ir_tol, its, check_convergence=check_convergence)
-    return TrainResult(beta, factor.rank, info, factor)
+        h.check(st, "elm_train")
+    info = ti.solve.as_dict()
+    info["factor"] = ti.factor.as_dict()
+    info["gram_dtype"] = _DT_NAME.get(int(ti.gram_dtype), "?")
+    info["escalations"] = int(ti.escalations)
+    info["guard"] = int(ti.guard)
+    factor = Factor(fptr, N, L, int(ti.factor.rank)) if fptr.value else None
+    return TrainResult(beta, int(ti.factor.rank), info, factor)
+
+
+def _train_info_dict(ti: TrainInfo) -> dict:
+    info = ti.solve.as_dict()
+    info["factor"] = ti.factor.as_dict()
+    info["gram_dtype"] = _DT_NAME.get(int(ti.gram_dtype), "?")
+    info["escalations"] = int(ti.escalations)
+    info["guard"] = int(ti.guard)
+    return info
+
+
+def train_batched(problems, precision: str = "fp64", ir_tol: float = 1e-10,
+                  ir_max_iter: Optional[int] = None, tau_rel: float = 0.0, H64s=None,
+                  betas=None, check: bool = True):
+    """elm_train_batched over a list of (X, W, b, T) float64 device tensors.
+
+    H64s / betas: optional lists of preallocated N x L / L x m float64
+    buffers.  Returns (betas, infos, statuses); with check=True a failed
+    problem raises ElmError."""
+    if precision not in ("fp64", "fp32", "bf16", "fp16"):
+        raise ValueError("precision must be one of fp64, fp32, bf16, fp16")
+    h = handle()
+    count = len(problems)
+    arr = (Problem * max(count, 1))()
+    keep = []
+    out_betas = []
+    for e, (X, W, b, T) in enumerate(problems):
+        for name, t in (("X", X), ("W", W), ("b", b), ("T", T)):
+            if t.dtype != torch.float64:
+                raise TypeError(f"problem {e}: {name} must be float64")
+        N, d = X.shape
+        L = W.shape[1]
+        m = T.shape[1]
+        H64 = H64s[e] if H64s is not None else torch.empty((N, L), dtype=torch.float64, device=X.device)
+        beta = betas[e] if betas is not None else torch.empty((L, m), dtype=torch.float64, device=X.device)
+        keep.append(H64)
+        out_betas.append(beta)
+        xp, ldx = _mat(X, "X")
+        wp, ldw = _mat(W, "W")
+        tp, ldt = _mat(T, "T")
+        hp, ldh = _mat(H64, "H64")
+        bp, ldb = _mat(beta, "beta")
+        arr[e] = Problem(N, d, L, m, xp.value, ldx, wp.value, ldw, _vec(b, "b").value, tp.value, ldt,
+                         hp.value, ldh, bp.value, ldb)
+    gdt = {"fp64": ELM_F64, "fp32": ELM_F32, "bf16": ELM_BF16, "fp16": ELM_F16}[precision]
+    its = (2 if precision == "fp64" else 30) if ir_max_iter is None else ir_max_iter
+    infos = (TrainInfo * max(count, 1))()
+    stats = (ctypes.c_int32 * max(count, 1))()
+    st = _lib.elm_train_batched(h.ptr, count, arr, gdt, tau_rel, ir_tol, its, infos, stats)
+    if check:
+        h.check(st, "elm_train_batched")
+    return out_betas, [_train_info_dict(infos[e]) for e in range(count)], [int(stats[e]) for e in range(count)]

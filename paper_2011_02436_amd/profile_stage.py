@@ -4,7 +4,7 @@ profiling a single kernel under rocprofv3 (kernel trace or counters).
     python -m paper_2011_02436_amd.profile_stage --stage gram [--N 500000 --L 10000]
 
 Stages: hidden (FP64 H + BF16 copy), gram (BF16 Gram), gram64 (FP64 Gram),
-rank (pivoted Cholesky + factor), refine (one fused refinement pass),
+rank (pivoted Cholesky + factor), refine (factor and one refinement pass),
 predict (Y = H beta), copy (a plain device copy of the FP64 H, the
 reference for scaling memory counters).  Each stage runs --reps times after
 one untimed call.
