@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=4000, help="oracle sample: rows at full L")
     ap.add_argument("--cpu-nodes", type=int, default=3000, help="oracle sample: nodes for the factor")
+    ap.add_argument("--batch-steps", type=int, default=2,
+                    help="timed batches of the 256-ELM hidden-size sweep (0 = skip)")
     return ap.parse_args()
 
 
@@ -88,10 +90,52 @@ def cpu_baseline(prob, rows, nodes):
     }
 
 
+def bench_batch(args, elm, torch, wl, dev):
+    """The hidden-size sweep: 256 independent ELMs (N, L log-uniform in
+    [1000, 50000] x [64, 2048], d=32, m=5, 10% duplicated nodes) trained by one
+    elm_train_batched call, BF16 form and FP64 form, to NE residual 1e-10."""
+    t0 = time.perf_counter()
+    probs = wl.batch_sweep()
+    dev_probs = [tuple(torch.from_numpy(a).to(dev) for a in (p.X, p.W, p.b, p.T)) for p in probs]
+    H64s = [torch.empty((p.N, p.L), dtype=torch.float64, device=dev) for p in probs]
+    betas = [torch.empty((p.L, p.m), dtype=torch.float64, device=dev) for p in probs]
+    torch.cuda.synchronize()
+    log(f"batch: {len(probs)} ELMs generated and uploaded in {time.perf_counter() - t0:.1f} s")
+    out = {"workload": "batch_sweep: 256 ELMs, N log-U[1000,50000], L log-U[64,2048], d=32, m=5, 10% duplicated nodes",
+           "count": len(probs), "sum_N_L2": float(sum(p.N * p.L * p.L for p in probs))}
+    for precision in ("bf16", "fp64"):
+        _, infos, stats = elm.train_batched(dev_probs, precision=precision, ir_tol=1e-10, H64s=H64s,
+                                            betas=betas, check=False)
+        torch.cuda.synchronize()
+        ts = []
+        for i in range(args.batch_steps):
+            t1 = time.perf_counter()
+            _, infos, stats = elm.train_batched(dev_probs, precision=precision, ir_tol=1e-10, H64s=H64s,
+                                                betas=betas, check=False)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+            log(f"batch {precision} {i}: {ts[-1] * 1e3:.1f} ms")
+        ms = sum(ts) / len(ts) * 1e3
+        used = {}
+        for inf in infos:
+            used[inf["gram_dtype"]] = used.get(inf["gram_dtype"], 0) + 1
+        out[precision] = {
+            "ms_per_batch": round(ms, 2), "trainings_per_s": round(len(probs) * 1e3 / ms, 2),
+            "failed": int(sum(1 for st in stats if st != 0)),
+            "max_ne_residual": max(inf["ne_residual"] for inf in infos),
+            "gram_dtype_used": used,
+            "escalations": int(sum(inf["escalations"] for inf in infos)),
+            "max_refine_iterations": max(inf["iterations"] for inf in infos),
+        }
+    del H64s, betas, dev_probs
+    torch.cuda.empty_cache()
+    return out
+
+
 def traffic_from_profiles(kernel_src):
     """HBM traffic per launch of the Gram kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "gram_bf16_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "gram_lp256_bf16_N500000_L10000_traffic.txt")
     if not os.path.exists(path):
         return None
     src_hash = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
@@ -202,6 +246,8 @@ def main():
                 "speedup_of_mixed": round(fp64_ms / ms_per_step, 3),
                 "beta_rel_diff_mixed_vs_fp64": diff}
 
+    batch = bench_batch(args, elm, torch, wl, dev) if args.batch_steps > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
@@ -248,6 +294,7 @@ def main():
         },
         "stage_ms_per_step": stage_ms_per_step,
         "fp64_form": fp64,
+        "batch_sweep": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -43,6 +43,7 @@ void Workspace::release() {
     for (auto& kv : bufs)
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     bufs.clear();
+    tables.clear();
 }
 
 hipEvent_t Profiler::take() {
@@ -393,6 +394,99 @@ elm_status elm_factor_destroy(elm_factor* f) {
     return ELM_OK;
 }
 
+}  // extern "C"
+
+namespace elm {
+namespace {
+
+// beta = H^+ T with refinement (see elm_pinv_solve).  With z_ready the
+// caller has already put Z = H^T T and ||Z||_F^2 in the workspace buffers
+// "ps_Z" / "ps_nrm" (the hidden-layer kernel can produce them on the fly).
+elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const double* T, int64_t ldt,
+                           const double* H64, int64_t ldh64, double ir_tol, int32_t ir_max_iter,
+                           double* beta, int64_t ldbeta, elm_solve_info* info, bool z_ready) {
+    elm_status result = ELM_OK;
+    const int64_t N = f->N, L = f->L;
+    elm::use_device(h);
+    hipStream_t s = h->stream;
+    elm::Workspace& ws = h->ws;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->rank = f->r;
+        info->transposed = f->transposed ? 1 : 0;
+        info->ne_residual = -1.0;
+    }
+    double* Z = (double*)ws.get("ps_Z", (size_t)L * m * sizeof(double));
+    double* nrm = (double*)ws.get("ps_nrm", 2 * sizeof(double));
+    // beta_0 = H^+ T
+    elm::Profiler* pr = &h->prof;
+    if (!f->transposed) {
+        if (!z_ready) {
+            elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+            elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);   // H^T T, eq. (8)
+        }
+        elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
+        elm::apply_pinv(s, f, m, Z, m, H64, ldh64, beta, ldbeta, ws);
+    } else {
+        elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
+        elm::apply_pinv(s, f, m, T, ldt, H64, ldh64, beta, ldbeta, ws);
+    }
+    if (ir_max_iter == 0) {
+        ELM_HIP_TRY(hipStreamSynchronize(s));
+        return result;
+    }
+    if (f->transposed && !z_ready) {
+        elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+        elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);
+    }
+    double z2 = 0;
+    ELM_HIP_TRY(hipMemcpyAsync(&z2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    double* E = (double*)ws.get("ps_E", (size_t)N * m * sizeof(double));
+    double* G = (double*)ws.get("ps_G", (size_t)L * m * sizeof(double));
+    double* D = (double*)ws.get("ps_D", (size_t)L * m * sizeof(double));
+    double res = 0, prev = 0;
+    int it = 0;
+    for (;;) {
+        // G = H^T (T - H beta): two streaming passes over H
+        {
+            elm::StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
+            elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m);
+        }
+        {
+            elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+            elm::launch_ht_times(s, N, L, m, H64, ldh64, E, m, G, m, nrm + 1, ws);
+        }
+        double g2 = 0;
+        ELM_HIP_TRY(hipMemcpyAsync(&g2, nrm + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        ELM_HIP_TRY(hipStreamSynchronize(s));
+        res = z2 > 0 ? std::sqrt(g2 / z2) : std::sqrt(g2);
+        if (info && it < 32) info->ne_history[it] = res;
+        if (!(res > ir_tol) || it >= ir_max_iter) break;
+        if (it >= 1 && !(res < prev)) break;  // the last correction made no progress
+        prev = res;
+        {
+            elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
+            if (!f->transposed)
+                elm::apply_pinv(s, f, m, G, m, H64, ldh64, D, m, ws);
+            else
+                elm::apply_pinv(s, f, m, E, m, H64, ldh64, D, m, ws);
+        }
+        elm::launch_axpy_mat(s, L, m, D, m, beta, ldbeta);
+        ++it;
+    }
+    if (info) {
+        info->iterations = it;
+        info->ne_residual = res;
+    }
+    if (res > ir_tol) result = ELM_ERR_NO_CONVERGENCE;
+    return result;
+}
+
+}  // namespace
+}  // namespace elm
+
+extern "C" {
+
 elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const double* T, int64_t ldt,
                           const double* H64, int64_t ldh64, double ir_tol, int32_t ir_max_iter,
                           double* beta, int64_t ldbeta, elm_solve_info* info) {
@@ -407,79 +501,8 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
         REQUIRE(ir_tol >= 0.0 && ir_tol < 1.0, ELM_ERR_INVALID_ARG, "ir_tol must be in [0, 1)");
         REQUIRE(ir_max_iter >= 0 && ir_max_iter <= 31, ELM_ERR_INVALID_ARG,
                 "ir_max_iter must be in [0, 31]");
-        const int64_t N = f->N, L = f->L;
-        elm::use_device(h);
-        hipStream_t s = h->stream;
-        elm::Workspace& ws = h->ws;
-        if (info) {
-            std::memset(info, 0, sizeof(*info));
-            info->rank = f->r;
-            info->transposed = f->transposed ? 1 : 0;
-            info->ne_residual = -1.0;
-        }
-        double* Z = (double*)ws.get("ps_Z", (size_t)L * m * sizeof(double));
-        double* nrm = (double*)ws.get("ps_nrm", 2 * sizeof(double));
-        // beta_0 = H^+ T
-        elm::Profiler* pr = &h->prof;
-        if (!f->transposed) {
-            {
-                elm::StageScope sc(pr, ELM_STAGE_RHS, s);
-                elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);   // H^T T, eq. (8)
-            }
-            elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
-            elm::apply_pinv(s, f, m, Z, m, H64, ldh64, beta, ldbeta, ws);
-        } else {
-            elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
-            elm::apply_pinv(s, f, m, T, ldt, H64, ldh64, beta, ldbeta, ws);
-        }
-        if (ir_max_iter == 0) {
-            ELM_HIP_TRY(hipStreamSynchronize(s));
-            return;
-        }
-        if (f->transposed) {
-            elm::StageScope sc(pr, ELM_STAGE_RHS, s);
-            elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);
-        }
-        double z2 = 0;
-        ELM_HIP_TRY(hipMemcpyAsync(&z2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-        double* E = (double*)ws.get("ps_E", (size_t)N * m * sizeof(double));
-        double* G = (double*)ws.get("ps_G", (size_t)L * m * sizeof(double));
-        double* D = (double*)ws.get("ps_D", (size_t)L * m * sizeof(double));
-        double res = 0, prev = 0;
-        int it = 0;
-        for (;;) {
-            // G = H^T (T - H beta): two streaming passes over H
-            {
-                elm::StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
-                elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m);
-            }
-            {
-                elm::StageScope sc(pr, ELM_STAGE_RHS, s);
-                elm::launch_ht_times(s, N, L, m, H64, ldh64, E, m, G, m, nrm + 1, ws);
-            }
-            double g2 = 0;
-            ELM_HIP_TRY(hipMemcpyAsync(&g2, nrm + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-            ELM_HIP_TRY(hipStreamSynchronize(s));
-            res = z2 > 0 ? std::sqrt(g2 / z2) : std::sqrt(g2);
-            if (info && it < 32) info->ne_history[it] = res;
-            if (!(res > ir_tol) || it >= ir_max_iter) break;
-            if (it >= 1 && !(res < prev)) break;  // the last correction made no progress
-            prev = res;
-            {
-                elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
-                if (!f->transposed)
-                    elm::apply_pinv(s, f, m, G, m, H64, ldh64, D, m, ws);
-                else
-                    elm::apply_pinv(s, f, m, E, m, H64, ldh64, D, m, ws);
-            }
-            elm::launch_axpy_mat(s, L, m, D, m, beta, ldbeta);
-            ++it;
-        }
-        if (info) {
-            info->iterations = it;
-            info->ne_residual = res;
-        }
-        if (res > ir_tol) result = ELM_ERR_NO_CONVERGENCE;
+        result = elm::pinv_solve_impl(h, f, m, T, ldt, H64, ldh64, ir_tol, ir_max_iter, beta, ldbeta,
+                                      info, false);
     });
     if (st != ELM_OK) return st;
     if (result != ELM_OK) h->last_error = "refinement stopped above ir_tol";
@@ -537,8 +560,23 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, 
             lp = h->ws.get("train_lp", (size_t)L * N * elm::dtype_size(gdt));
             ldl = N;
         }
-        elm::check_status(h, elm_hidden(h, N, d, L, X, ldx, W, ldw, b, ELM_F64, H64, ldh64,
-                                        gdt == ELM_F64 ? nullptr : lp, ldl, gdt));
+        // the hidden layer also forms the per-row-tile partials of Z = H^T T
+        const bool fuse_z = m <= elm::HIDDEN_Z_MAX_M;
+        double* Zp = nullptr;
+        if (fuse_z)
+            Zp = (double*)h->ws.get("train_zpart",
+                                    (size_t)elm::hidden_row_tiles(N) * L * m * sizeof(double));
+        {
+            elm::StageScope sc(&h->prof, ELM_STAGE_HIDDEN, h->stream);
+            elm::launch_hidden(h->stream, ELM_F64, N, d, L, X, ldx, W, ldw, b, H64, ldh64,
+                               gdt == ELM_F64 ? nullptr : lp, ldl, gdt, T, ldt, m, Zp);
+        }
+        if (fuse_z) {
+            elm::StageScope sc(&h->prof, ELM_STAGE_RHS, h->stream);
+            double* Z = (double*)h->ws.get("ps_Z", (size_t)L * m * sizeof(double));
+            double* nrm = (double*)h->ws.get("ps_nrm", 2 * sizeof(double));
+            elm::launch_partial_sum(h->stream, L, m, elm::hidden_row_tiles(N), Zp, Z, m, nrm, h->ws);
+        }
         for (;;) {
             int64_t r = 0;
             if (gdt == ELM_F64)
@@ -553,8 +591,8 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, 
             if (can_escalate && !f->reliable) {
                 ti.guard = 1;
             } else {
-                const elm_status ss = elm_pinv_solve(h, f, m, T, ldt, H64, ldh64, ir_tol, ir_max_iter,
-                                                     beta, ldbeta, &ti.solve);
+                const elm_status ss = elm::pinv_solve_impl(h, f, m, T, ldt, H64, ldh64, ir_tol,
+                                                           ir_max_iter, beta, ldbeta, &ti.solve, fuse_z);
                 if (ss == ELM_OK) break;
                 if (ss != ELM_ERR_NO_CONVERGENCE || !can_escalate) {
                     if (info) *info = ti;

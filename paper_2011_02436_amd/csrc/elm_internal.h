@@ -99,9 +99,15 @@ struct StageScope {
 
 struct Workspace {
     std::vector<std::pair<std::string, Buffer>> bufs;
+    std::vector<std::string> tables;  // buffers holding an uploaded constant table
     Profiler* prof = nullptr;
     void* get(const std::string& name, size_t bytes);
     void release();
+    bool has_table(const std::string& name) const {
+        for (const auto& t : tables)
+            if (t == name) return true;
+        return false;
+    }
 };
 
 }  // namespace elm
@@ -158,9 +164,15 @@ namespace elm {
 // ---------------------------------------------------------------------------
 
 // hidden.hip: H = sigmoid(X W + b), sample-major H and/or node-major low-precision copy
-void launch_hidden(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L,
-                   const void* X, int64_t ldx, const void* W, int64_t ldw, const void* b,
-                   void* H, int64_t ldh, void* Hlp, int64_t ldlp, elm_dtype lp_dt);
+// Hidden layer; with Zpart (FP64 inputs, T non-null, 1 <= m <= HIDDEN_Z_MAX_M)
+// it also writes the per-row-tile partials of Z = H^T T: Zpart[t][j][c] for
+// row tile t of hidden_row_tiles(N) (sum them in order for Z).
+constexpr int HIDDEN_Z_MAX_M = 8;
+void launch_hidden(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L, const void* X,
+                   int64_t ldx, const void* W, int64_t ldw, const void* b, void* H, int64_t ldh,
+                   void* Hlp, int64_t ldlp, elm_dtype lp_dt, const double* T = nullptr,
+                   int64_t ldt = 0, int64_t m = 0, double* Zpart = nullptr);
+int64_t hidden_row_tiles(int64_t N);
 
 // gram.hip: M (n x n FP64, full symmetric, ld = ldm)
 //   column Gram  M = H^T H  of sample-major FP64 H (N x L)
@@ -215,6 +227,10 @@ void launch_residual(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
                      const double* T, int64_t ldt, const double* beta, int64_t ldb, double* E,
                      int64_t lde);
 //   G = H^T E  (L x m), deterministic two-stage reduction; also writes ||G||_F^2 to *nrm2
+// G = sum over chunks (in order) of part[chunk] (each L x m, row-major), and
+// *nrm2 = ||G||_F^2
+void launch_partial_sum(hipStream_t s, int64_t L, int64_t m, int64_t nchunk, const double* part,
+                        double* G, int64_t ldg, double* nrm2, Workspace& ws);
 void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
                      const double* E, int64_t lde, double* G, int64_t ldg, double* nrm2,
                      Workspace& ws);

@@ -20,6 +20,8 @@
 //   gram_reduce_kernel  sums the split-K partial tiles in FP64 and mirrors.
 #include "elm_internal.h"
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <cmath>
 
@@ -263,32 +265,35 @@ int64_t run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, 
 // Each block owns one work item (split-K chunk, tile bi <= bj) from a table
 // built on the host.  4 waves in a 2 x 2 grid each accumulate a 128 x 128
 // sub-tile as 4 x 4 blocks of the 32x32x16 MFMA (256 FP32 accumulators per
-// lane, in AGPRs).  K is consumed in stages of 32 samples through 4 LDS
-// buffers filled by direct global->LDS loads (global_load_lds_dwordx4) issued
-// three stages ahead: no staging registers, and the loads of later stages
+// lane, in AGPRs).  K is consumed in stages of 32 samples through GNS (4 or 5)
+// LDS buffers filled by direct global->LDS loads (global_load_lds_dwordx4)
+// issued GNS - 1 stages ahead: no staging registers, and the loads of later stages
 // stay in flight across the per-stage barrier (an explicit vmcnt wait plus a
 // bare s_barrier; a full __syncthreads would drain them).  Every stage issues
 // the same number of loads (past the last full stage they re-read it into a
 // buffer nobody reads again), so the wait count is static.
 // In LDS a tile row is 4 chunks of 16 B; chunk c of row r sits at position
-// c ^ ((r >> 1) & 3), spreading the rows an MFMA operand read touches over
-// the banks.  Ragged tiles, the K tail and unaligned input take a plain path.
+// c ^ ((r >> 2) & 3): a 64-byte row covers 16 of the 64 banks, r % 4 picks
+// which 16, and the swizzle spreads rows r, r + 4, r + 8, r + 12 over the
+// four 16-byte slots, so the 16 consecutive rows that one quarter-wave of an
+// operand read (ds_read_b128) touches hit 16 distinct 4-bank groups.  Ragged
+// tiles, the K tail and unaligned input take a plain path.
 // ---------------------------------------------------------------------------
 constexpr int GT = 256;    // tile
 constexpr int GBK = 32;    // samples per stage
-constexpr int GNS = 4;     // LDS stages
 constexpr int G_OPB = GT * GBK * 2;            // bytes per operand per stage (16 KB)
 constexpr int G_STB = 2 * G_OPB;               // bytes per stage (32 KB)
 #define G_VMCNT(N) (((N) & 15) | (((N) >> 4) << 14) | (7 << 4) | (15 << 8))
+#define G_LGKMCNT(N) (15 | (3 << 14) | (7 << 4) | ((N) << 8))
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <typename HT>
+template <typename HT, int GNS>  // GNS: LDS stages, GNS - 2 of them in flight
 __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, int64_t kc_len,
                                                          const HT* __restrict__ A, int64_t ld,
                                                          float* __restrict__ part,
                                                          const int4* __restrict__ work) {
-    __shared__ __attribute__((aligned(1024))) unsigned char smem[GNS * G_STB];  // 128 KB
+    __shared__ __attribute__((aligned(1024))) unsigned char smem[GNS * G_STB];
     typedef typename Mfma32<HT>::vec_t vec_t;
     const int4 wk = work[blockIdx.x];
     if (wk.x < 0) return;
@@ -315,10 +320,10 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
             const int ra = wm * 128 + x * 32 + (lane & 31);                                \
             const int rb = wn * 128 + x * 32 + (lane & 31);                                \
             const int c = lane >> 5;                                                       \
-            a0[x] = *(const vec_t*)(sA + ra * 64 + ((c ^ ((ra >> 1) & 3)) << 4));          \
-            b0[x] = *(const vec_t*)(sB + rb * 64 + ((c ^ ((rb >> 1) & 3)) << 4));          \
-            a1[x] = *(const vec_t*)(sA + ra * 64 + (((c + 2) ^ ((ra >> 1) & 3)) << 4));    \
-            b1[x] = *(const vec_t*)(sB + rb * 64 + (((c + 2) ^ ((rb >> 1) & 3)) << 4));    \
+            a0[x] = *(const vec_t*)(sA + ra * 64 + ((c ^ ((ra >> 2) & 3)) << 4));          \
+            b0[x] = *(const vec_t*)(sB + rb * 64 + ((c ^ ((rb >> 2) & 3)) << 4));          \
+            a1[x] = *(const vec_t*)(sA + ra * 64 + (((c + 2) ^ ((ra >> 2) & 3)) << 4));    \
+            b1[x] = *(const vec_t*)(sB + rb * 64 + (((c + 2) ^ ((rb >> 2) & 3)) << 4));    \
         }                                                                                  \
         _Pragma("unroll") for (int x = 0; x < 4; ++x)                                      \
             _Pragma("unroll") for (int y = 0; y < 4; ++y)                                  \
@@ -327,6 +332,25 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
             _Pragma("unroll") for (int y = 0; y < 4; ++y)                                  \
                 acc[x][y] = Mfma32<HT>::op(a1[x], b1[y], acc[x][y]);                       \
     } while (0)
+    // fragments of one k16 half (H = 0: samples 0-15 of the stage, 1: 16-31)
+#define GRAM_READ(FA, FB, ST, H)                                                           \
+    do {                                                                                   \
+        const unsigned char* sA = smem + (ST) * G_STB;                                     \
+        const unsigned char* sB = sA + G_OPB;                                              \
+        _Pragma("unroll") for (int x = 0; x < 4; ++x) {                                    \
+            const int ra = wm * 128 + x * 32 + (lane & 31);                                \
+            const int rb = wn * 128 + x * 32 + (lane & 31);                                \
+            const int c = (lane >> 5) + 2 * (H);                                           \
+            FA[x] = *(const vec_t*)(sA + ra * 64 + ((c ^ ((ra >> 2) & 3)) << 4));          \
+            FB[x] = *(const vec_t*)(sB + rb * 64 + ((c ^ ((rb >> 2) & 3)) << 4));          \
+        }                                                                                  \
+    } while (0)
+#define GRAM_MMA(FA, FB)                                                                   \
+    do {                                                                                   \
+        _Pragma("unroll") for (int x = 0; x < 4; ++x)                                      \
+            _Pragma("unroll") for (int y = 0; y < 4; ++y)                                  \
+                acc[x][y] = Mfma32<HT>::op(FA[x], FB[y], acc[x][y]);                       \
+    } while (0)
 
     const bool interior = vec_ok && r0 + GT <= n && c0 + GT <= n;  // block-uniform
     const int64_t nfull = interior ? (kend - kbeg) / GBK : 0;
@@ -334,13 +358,13 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
         // DMA lane mapping: instruction i of wave w fills LDS bytes
         // [(4 i + w) * 1024, +1024) of an operand buffer = rows (4 i + w) * 16
         // .. +16, lane l -> row (4 i + w) * 16 + l / 4, position l % 4, which
-        // holds global chunk (l % 4) ^ ((row >> 1) & 3).
+        // holds global chunk (l % 4) ^ ((row >> 2) & 3).
         const HT* asrc[4];
         const HT* bsrc[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = (4 * i + wave) * 16 + (lane >> 2);
-            const int c = (lane & 3) ^ ((row >> 1) & 3);
+            const int c = (lane & 3) ^ ((row >> 2) & 3);
             asrc[i] = A + (r0 + row) * ld + c * 8;
             bsrc[i] = A + (c0 + row) * ld + c * 8;
         }
@@ -356,16 +380,41 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
                                              (lds_void*)(dA + G_OPB + i * 4096), 16, 0, 0);  \
         }                                                                                    \
     } while (0)
-        GRAM_DMA(0, kbeg);
-        GRAM_DMA(1, kbeg + GBK);
-        GRAM_DMA(2, kbeg + 2 * GBK);
+        // Fragment reads are software-pipelined against the MFMAs: the second
+        // half of stage st is read while the first half multiplies, and the
+        // first half of stage st + 1 while the second half multiplies.  The
+        // barrier between the halves publishes stage st + 1 (every wave has
+        // waited for its own loads of it) and retires buffer (st - 1) % GNS,
+        // which the loads issued right after it refill.
+        vec_t f0a[4], f0b[4], f1a[4], f1b[4];
+#pragma unroll
+        for (int p = 0; p < GNS - 1; ++p) GRAM_DMA(p, kbeg + p * GBK);
+        __builtin_amdgcn_s_waitcnt(G_VMCNT(8 * (GNS - 2)));  // stage 0 landed
+        __builtin_amdgcn_s_barrier();
+        GRAM_READ(f0a, f0b, 0, 0);
+        // (The reads of the first half of stage st + 1 are issued in the last
+        // iteration too, from a buffer whose contents are then unused: the
+        // count of LDS operations per iteration stays static, so the
+        // compiler's wait counts stay exact across the back edge.  The
+        // scheduling barriers keep the MFMAs on their side of the s_barrier.)
         for (int64_t st = 0; st < nfull; ++st) {
-            // stage st landed (two later stages may still be in flight), and
-            // every wave is done with buffer (st - 1) % GNS before it is refilled
-            __builtin_amdgcn_s_waitcnt(G_VMCNT(16));
+            const int cur = (int)(st % GNS);
+            // the first half's fragments were read during the previous MFMAs
+            __builtin_amdgcn_s_waitcnt(G_LGKMCNT(0));
+            GRAM_READ(f1a, f1b, cur, 1);
+            __builtin_amdgcn_sched_barrier(0);
+            GRAM_MMA(f0a, f0b);
+            __builtin_amdgcn_sched_barrier(0);
+            // the second half's fragments were read during those MFMAs
+            __builtin_amdgcn_s_waitcnt(G_LGKMCNT(0));
+            __builtin_amdgcn_s_waitcnt(G_VMCNT(8 * (GNS - 3)));  // stage st + 1 landed
             __builtin_amdgcn_s_barrier();
-            GRAM_DMA(st + 3, kbeg + (st + 3) * GBK);
-            GRAM_COMPUTE((int)(st % GNS));
+            __builtin_amdgcn_sched_barrier(0);
+            GRAM_DMA(st + GNS - 1, kbeg + (st + GNS - 1) * GBK);
+            GRAM_READ(f0a, f0b, (int)((st + 1) % GNS), 0);
+            __builtin_amdgcn_sched_barrier(0);
+            GRAM_MMA(f1a, f1b);
+            __builtin_amdgcn_sched_barrier(0);
         }
         __builtin_amdgcn_s_waitcnt(G_VMCNT(0));
         __builtin_amdgcn_s_barrier();
@@ -379,7 +428,7 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
         for (int i = 0; i < 4; ++i) {
             const int q = tid + 256 * i;        // 16-byte slot in the operand buffer
             const int row = q >> 2;
-            const int c = (q & 3) ^ ((row >> 1) & 3);
+            const int c = (q & 3) ^ ((row >> 2) & 3);
             uint32_t wa[4], wb[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -400,6 +449,8 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
         __syncthreads();
     }
 #undef GRAM_COMPUTE
+#undef GRAM_READ
+#undef GRAM_MMA
 
     float* out = part + (int64_t)wk.w * (GT * GT);
 #pragma unroll
@@ -516,6 +567,15 @@ static int pick_splits(int64_t ntile, int64_t K) {
     return best;
 }
 
+// LDS stages of the 16-bit Gram pipeline (4 or 5; ELM_GRAM_STAGES overrides the default)
+static int gram_stages() {
+    static const int ns = [] {
+        const char* e = std::getenv("ELM_GRAM_STAGES");
+        return (e && std::atoi(e) == 5) ? 5 : 4;
+    }();
+    return ns;
+}
+
 int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
                              int64_t ldn, double* M, int64_t ldm, Workspace& ws) {
     if (dt == ELM_F32) return run_gram16<float, true>(s, L, N, (const float*)Hn, ldn, M, ldm, ws);
@@ -524,21 +584,37 @@ int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, 
     const int nsplit = pick_splits(ntile, N);
     const int64_t kc_len = cdiv(cdiv(N, nsplit), GBK) * GBK;
     const int nsplit_eff = (int)cdiv(N, kc_len);
-    std::vector<int4> tab = gram_work_table(nt, nsplit_eff, ntile);
+    // the work table depends only on (L, splits): built and uploaded once per workspace
     const std::string key = "gram_tab_" + std::to_string(L) + "_" + std::to_string(nsplit_eff);
-    int4* dtab = (int4*)ws.get(key, tab.size() * sizeof(int4));
-    ELM_HIP_TRY(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int4), hipMemcpyHostToDevice, s));
-    ELM_HIP_TRY(hipStreamSynchronize(s));  // tab is a host temporary
+    const size_t nwork = (size_t)ntile * nsplit_eff;
+    const size_t nblocks = cdiv((int64_t)nwork, 256) * 256;
+    int4* dtab = (int4*)ws.get(key, nblocks * sizeof(int4));
+    if (!ws.has_table(key)) {
+        std::vector<int4> tab = gram_work_table(nt, nsplit_eff, ntile);
+        if (tab.size() != nblocks) throw Error{ELM_ERR_HIP, "Gram work table size mismatch"};
+        ELM_HIP_TRY(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+        ELM_HIP_TRY(hipStreamSynchronize(s));  // tab is a host temporary
+        ws.tables.push_back(key);
+    }
     float* part = (float*)ws.get("gram_part", (size_t)ntile * nsplit_eff * GT * GT * sizeof(float));
     {
         StageScope sc(ws.prof, ELM_STAGE_GRAM, s);
-        if (dt == ELM_BF16)
-            gram_lp256_kernel<__bf16><<<(unsigned)tab.size(), 256, 0, s>>>(L, N, kc_len, (const __bf16*)Hn,
-                                                                         ldn, part, dtab);
-        else
-            gram_lp256_kernel<_Float16><<<(unsigned)tab.size(), 256, 0, s>>>(L, N, kc_len,
-                                                                           (const _Float16*)Hn, ldn, part,
-                                                                           dtab);
+        const int ns = gram_stages();
+        if (dt == ELM_BF16) {
+            if (ns == 5)
+                gram_lp256_kernel<__bf16, 5><<<(unsigned)nblocks, 256, 0, s>>>(L, N, kc_len, (const __bf16*)Hn,
+                                                                             ldn, part, dtab);
+            else
+                gram_lp256_kernel<__bf16, 4><<<(unsigned)nblocks, 256, 0, s>>>(L, N, kc_len, (const __bf16*)Hn,
+                                                                             ldn, part, dtab);
+        } else {
+            if (ns == 5)
+                gram_lp256_kernel<_Float16, 5><<<(unsigned)nblocks, 256, 0, s>>>(
+                    L, N, kc_len, (const _Float16*)Hn, ldn, part, dtab);
+            else
+                gram_lp256_kernel<_Float16, 4><<<(unsigned)nblocks, 256, 0, s>>>(
+                    L, N, kc_len, (const _Float16*)Hn, ldn, part, dtab);
+        }
         ELM_LAUNCH_CHECK();
     }
     StageScope sc(ws.prof, ELM_STAGE_GRAM_REDUCE, s);

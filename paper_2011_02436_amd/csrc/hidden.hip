@@ -10,6 +10,8 @@
 // MFMA operands want each hidden node's samples contiguous.
 #include "elm_internal.h"
 
+#include <type_traits>
+
 namespace elm {
 namespace {
 
@@ -74,6 +76,80 @@ __device__ inline bool hidden_tile(int64_t nrow_t, int64_t ncol_t, int64_t& row_
     return row_t < nrow_t;
 }
 
+// node-major copy of a tile staged in LDS: each node's 128 samples are 256 B
+// (16-bit) or 512 B (FP32), written in 16-byte pieces where the tile is whole
+// and aligned
+__device__ inline void store_node_major(void* __restrict__ Hlp, int64_t ldlp, bool lp16,
+                                        const uint16_t* st16, const float* st32, int64_t N,
+                                        int64_t L, int64_t n0, int64_t j0, int tid) {
+    __syncthreads();
+    const int esz = lp16 ? 2 : 4;
+    const int per = 16 / esz;  // elements per 16-byte piece
+    const bool vec = n0 + HT <= N && (((uintptr_t)Hlp | (uintptr_t)(ldlp * esz)) & 15) == 0;
+    const int pieces = HT / per;  // per node
+    for (int e = tid; e < HT * pieces; e += NT) {
+        const int lj = e / pieces, q = e % pieces;
+        const int64_t gj = j0 + lj;
+        if (gj >= L) continue;
+        const int64_t gi = n0 + q * per;
+        if (vec) {
+            const uint4 val = lp16 ? *(const uint4*)&st16[lj * (HT + 8) + q * per]
+                                   : *(const uint4*)&st32[lj * (HT + 4) + q * per];
+            *(uint4*)((char*)Hlp + (gj * ldlp + gi) * esz) = val;
+        } else {
+            for (int u = 0; u < per; ++u) {
+                if (gi + u >= N) break;
+                if (lp16)
+                    ((uint16_t*)Hlp)[gj * ldlp + gi + u] = st16[lj * (HT + 8) + q * per + u];
+                else
+                    ((float*)Hlp)[gj * ldlp + gi + u] = st32[lj * (HT + 4) + q * per + u];
+            }
+        }
+    }
+}
+
+// Partial Z = H^T T of one tile: Zp[j][c] = sum over the tile's rows i of
+// H[i][j] T[i][c] (j local to the tile's columns, written at global column
+// j0 + j), in a fixed order: each lane's 16 rows, then the four row groups of
+// a wave by an xor butterfly, then the two waves' halves through LDS.
+template <typename A>
+__device__ inline void tile_ht_times_t(const A (&acc)[4][4], const double* __restrict__ Tg,
+                                       int64_t ldt, int m, double* __restrict__ Zp, int64_t N,
+                                       int64_t L, int64_t n0, int64_t j0, unsigned char* smem) {
+    constexpr int MZ = HIDDEN_Z_MAX_M;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    double* zs = (double*)smem;  // [2][HT][MZ]
+    __syncthreads();             // the LDS staging is free
+    for (int c = 0; c < m; ++c) {
+        double tv[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gi = n0 + wm * 64 + i * 16 + Mfma16<double>::row(lane, v);
+                tv[i][v] = gi < N ? Tg[gi * ldt + c] : 0.0;
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double z = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) z += acc[i][j][v] * tv[i][v];
+            z += __shfl_xor(z, 16);
+            z += __shfl_xor(z, 32);
+            if (lane < 16) zs[(wm * HT + wn * 64 + j * 16 + lane) * MZ + c] = z;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < HT * m; e += NT) {
+        const int col = e / m, c = e % m;
+        const int64_t gj = j0 + col;
+        if (gj < L) Zp[gj * m + c] = zs[col * MZ + c] + zs[(HT + col) * MZ + c];
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT, 2) void hidden_kernel(int64_t N, int64_t d, int64_t L,
                                                        int64_t nrow_t, int64_t ncol_t,
@@ -82,7 +158,8 @@ __global__ __launch_bounds__(NT, 2) void hidden_kernel(int64_t N, int64_t d, int
                                                        const T* __restrict__ bias,
                                                        T* __restrict__ H, int64_t ldh,
                                                        void* __restrict__ Hlp, int64_t ldlp,
-                                                       elm_dtype lp_dt) {
+                                                       elm_dtype lp_dt, const double* __restrict__ Tg,
+                                                       int64_t ldt, int m, double* __restrict__ Zp) {
     __shared__ __align__(16) unsigned char smem[HiddenSmem<T>::BYTES];
     typedef T Tile[HK][HP];
     Tile* Xs = (Tile*)smem;  // Xs[buf]: k-major, so an MFMA A read is 16 consecutive samples
@@ -174,56 +251,39 @@ __global__ __launch_bounds__(NT, 2) void hidden_kernel(int64_t N, int64_t d, int
                 if (H && gi < N && gj < L) H[gi * ldh + gj] = h;
                 if (lp16) st16[lj * (HT + 8) + li] = lp16_bits<T>(lp_dt, h);
                 if (lp32) st32[lj * (HT + 4) + li] = (float)h;
+                acc[i][j][v] = h;
             }
         }
     }
-    if (!Hlp) return;
-    __syncthreads();
-    // node-major copy: each node's 128 samples are 256 B (16-bit) or 512 B
-    // (FP32), written in 16-byte pieces where the tile is whole and aligned
-    const int esz = lp16 ? 2 : 4;
-    const int per = 16 / esz;  // elements per 16-byte piece
-    const bool vec = n0 + HT <= N && (((uintptr_t)Hlp | (uintptr_t)(ldlp * esz)) & 15) == 0;
-    const int pieces = HT / per;  // per node
-    for (int e = tid; e < HT * pieces; e += NT) {
-        const int lj = e / pieces, q = e % pieces;
-        const int64_t gj = j0 + lj;
-        if (gj >= L) continue;
-        const int64_t gi = n0 + q * per;
-        if (vec) {
-            const uint4 val = lp16 ? *(const uint4*)&st16[lj * (HT + 8) + q * per]
-                                   : *(const uint4*)&st32[lj * (HT + 4) + q * per];
-            *(uint4*)((char*)Hlp + (gj * ldlp + gi) * esz) = val;
-        } else {
-            for (int u = 0; u < per; ++u) {
-                if (gi + u >= N) break;
-                if (lp16)
-                    ((uint16_t*)Hlp)[gj * ldlp + gi + u] = st16[lj * (HT + 8) + q * per + u];
-                else
-                    ((float*)Hlp)[gj * ldlp + gi + u] = st32[lj * (HT + 4) + q * per + u];
-            }
-        }
-    }
+    if (Hlp) store_node_major(Hlp, ldlp, lp16, st16, st32, N, L, n0, j0, tid);
+    if constexpr (std::is_same<T, double>::value)
+        if (Zp) tile_ht_times_t(acc, Tg, ldt, m, Zp + row_t * L * m, N, L, n0, j0, smem);
 }
 
 }  // namespace
 
 void launch_hidden(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L, const void* X,
                    int64_t ldx, const void* W, int64_t ldw, const void* b, void* H, int64_t ldh,
-                   void* Hlp, int64_t ldlp, elm_dtype lp_dt) {
+                   void* Hlp, int64_t ldlp, elm_dtype lp_dt, const double* T, int64_t ldt, int64_t m,
+                   double* Zpart) {
     const int64_t nrow_t = cdiv(N, HT), ncol_t = cdiv(L, HT);
     const int64_t per_xcd = nrow_t * cdiv(ncol_t, XCDS);  // work items of the busiest XCD
     const unsigned grid = (unsigned)(XCDS * per_xcd);
+    if (Zpart && (dt != ELM_F64 || m < 1 || m > HIDDEN_Z_MAX_M || !T))
+        throw Error{ELM_ERR_INVALID_ARG, "fused H^T T needs FP64 inputs, T, and 1 <= m <= 8"};
     if (dt == ELM_F64) {
         hidden_kernel<double><<<grid, NT, 0, s>>>(N, d, L, nrow_t, ncol_t, (const double*)X, ldx,
                                                   (const double*)W, ldw, (const double*)b,
-                                                  (double*)H, ldh, Hlp, ldlp, lp_dt);
+                                                  (double*)H, ldh, Hlp, ldlp, lp_dt, T, ldt, (int)m,
+                                                  Zpart);
     } else {
         hidden_kernel<float><<<grid, NT, 0, s>>>(N, d, L, nrow_t, ncol_t, (const float*)X, ldx,
                                                  (const float*)W, ldw, (const float*)b, (float*)H,
-                                                 ldh, Hlp, ldlp, lp_dt);
+                                                 ldh, Hlp, ldlp, lp_dt, nullptr, 0, 0, nullptr);
     }
     ELM_LAUNCH_CHECK();
 }
+
+int64_t hidden_row_tiles(int64_t N) { return cdiv(N, HT); }
 
 }  // namespace elm

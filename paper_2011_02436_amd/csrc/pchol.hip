@@ -31,8 +31,8 @@ namespace elm {
 namespace {
 
 constexpr int PT = 256;     // threads per block, step kernels
-constexpr int NB = 128;     // panel width
-static_assert(NB <= 16 * 8, "a step covers at most 8 groups of 16 panel rows");
+constexpr int NB = 256;     // panel width
+static_assert(NB <= 8 * 32, "a step covers at most 8 groups of 32 panel rows");
 constexpr int TT = 128;     // trailing-update tile
 enum { ST_DONE = 0, ST_RANK = 1, ST_BAD = 2, ST_CUR = 3, ST_NREM = 4, ST_N = 5 };
 
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(PT) void panel_start_kernel(int64_t n_rem, const do
 // combined by an xor butterfly, so every lane holds the same bits and the
 // order of operations is the same for every position: identical columns of
 // the Gram stay bitwise identical.
-template <int G>
+template <int G, int R>
 __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_rem,
                                                   const double* __restrict__ S, int64_t lds,
                                                   double* __restrict__ P, int64_t ldp,
@@ -140,32 +140,33 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
                                                   int* __restrict__ piv, double* __restrict__ pstats) {
     constexpr int CPW = 64 / G;  // positions per wave
     constexpr int CPB = CPW * (PT / 64);
+    constexpr int PIN = 8;  // argmax partials per lane loaded in the first batch
     const int lane = threadIdx.x & 63;
     const int g = lane / CPW;
     const int64_t a = (int64_t)blockIdx.x * CPB + (threadIdx.x >> 6) * CPW + lane % CPW;
     const int64_t ac = a < n_rem ? a : n_rem - 1;  // in-bounds twin for the batched loads
-    const int q0 = 16 * g;
+    const int q0 = R * g;
 
     // round trip 1: nothing here depends on the pivot
     const int done = state[ST_DONE];
     const int cur = state[ST_CUR];
-    Part pin[8];
+    Part pin[PIN];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < PIN; ++j) {
         const int i = lane + 64 * j;
         pin[j] = i < nparts ? in[i] : part_none();
     }
-    double y[16];
+    double y[R];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) y[u] = (q0 + u < t) ? P[(int64_t)(q0 + u) * ldp + ac] : 0.0;
+    for (int u = 0; u < R; ++u) y[u] = (q0 + u < t) ? P[(int64_t)(q0 + u) * ldp + ac] : 0.0;
     const double d_a = d[ac];
     const int ch = chosen[ac];
     const int ra = cur ? rem1[ac] : rem0[ac];
 
     Part best = part_none();
 #pragma unroll
-    for (int j = 0; j < 8; ++j) part_take(best, pin[j]);
-    for (int i = lane + 512; i < nparts; i += 64) part_take(best, in[i]);
+    for (int j = 0; j < PIN; ++j) part_take(best, pin[j]);
+    for (int i = lane + 64 * PIN; i < nparts; i += 64) part_take(best, in[i]);
     if (done) return;
     wave_argmax(best);
     const int bp = __builtin_amdgcn_readfirstlane(best.p);
@@ -184,12 +185,12 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
 
     // round trip 2: the pivot's Schur row entry and panel column
     const double s0 = S[(int64_t)bp * lds + ac];
-    double x[16];
+    double x[R];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) x[u] = (q0 + u < t) ? P[(int64_t)(q0 + u) * ldp + bp] : 0.0;
+    for (int u = 0; u < R; ++u) x[u] = (q0 + u < t) ? P[(int64_t)(q0 + u) * ldp + bp] : 0.0;
     double part = 0.0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) part += x[u] * y[u];
+    for (int u = 0; u < R; ++u) part += x[u] * y[u];
 #pragma unroll
     for (int off = CPW; off < 64; off <<= 1) part += __shfl_xor(part, off);
 
@@ -316,8 +317,11 @@ __global__ __launch_bounds__(256, 2) void trailing_kernel(int64_t n_new, const d
     constexpr int PP = TT + 16;           // LDS pitch: 4 k rows of an operand read on disjoint banks
     constexpr int EPT = TT * BK / 256;    // panel entries per thread per operand tile
     constexpr int WB = TT / 32;
-    __shared__ double As[2][BK][PP];
-    __shared__ double Bs[2][BK][PP];
+    // operand tiles As[buf][k][i], Bs[buf][k][j]; reused for the mirror staging
+    __shared__ double smem_tr[2 * 2 * BK * PP];
+    typedef double OpTile[BK][PP];
+    OpTile* As = (OpTile*)smem_tr;
+    OpTile* Bs = As + 2;
     __shared__ int qa[TT], qb[TT];
 
     // tile index -> (bi <= bj)
@@ -386,6 +390,10 @@ __global__ __launch_bounds__(256, 2) void trailing_kernel(int64_t n_new, const d
         __syncthreads();
         buf ^= 1;
     }
+    // upper tile in place; its mirror goes through LDS (half a tile at a
+    // time, in the free operand buffers) so that both are written as rows
+    double (*Tm)[TT + 1] = (double (*)[TT + 1])smem_tr;  // [TT / 2][TT + 1]
+    static_assert(sizeof(smem_tr) >= sizeof(double) * (TT / 2) * (TT + 1), "mirror staging");
 #pragma unroll
     for (int x = 0; x < WB; ++x)
 #pragma unroll
@@ -395,11 +403,32 @@ __global__ __launch_bounds__(256, 2) void trailing_kernel(int64_t n_new, const d
                 const int li = wm * (TT / 2) + x * 16 + Mfma16<double>::row(lane, v);
                 const int lj = wn * (TT / 2) + y * 16 + (lane & 15);
                 const int64_t gi = r0 + li, gj = c0 + lj;
-                if (gi >= n_new || gj >= n_new || gi > gj) continue;
-                const double val = S[(int64_t)qa[li] * lds + qb[lj]] - acc[x][y][v];
-                Sn[gi * ldsn + gj] = val;
-                Sn[gj * ldsn + gi] = val;
+                const bool ok = gi < n_new && gj < n_new && gi <= gj;
+                const double val = ok ? S[(int64_t)qa[li] * lds + qb[lj]] - acc[x][y][v] : 0.0;
+                if (ok) Sn[gi * ldsn + gj] = val;
+                acc[x][y][v] = val;
             }
+    for (int h = 0; h < 2; ++h) {
+        __syncthreads();  // the operand buffers (then the previous half) are free
+        if (wn == h) {
+#pragma unroll
+            for (int x = 0; x < WB; ++x)
+#pragma unroll
+                for (int y = 0; y < WB; ++y)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int li = wm * (TT / 2) + x * 16 + Mfma16<double>::row(lane, v);
+                        const int lj = y * 16 + (lane & 15);  // within the half
+                        Tm[lj][li] = acc[x][y][v];
+                    }
+        }
+        __syncthreads();
+        for (int e = tid; e < (TT / 2) * TT; e += 256) {
+            const int lr = e / TT, lc = e % TT;
+            const int64_t gj = c0 + h * (TT / 2) + lr, gi = r0 + lc;  // mirror element (gj, gi)
+            if (gj < n_new && gi < gj) Sn[gj * ldsn + gi] = Tm[lr][lc];
+        }
+    }
 }
 
 __global__ void gather_kernel(int64_t r, int64_t n, const double* __restrict__ Rorig, int64_t ldro,
@@ -451,28 +480,20 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
             const int64_t k = ps + t;
             Part* pin = part[k & 1];
             Part* pout = part[(k + 1) & 1];
-            // lanes per position: enough 16-row groups to cover the t panel rows
+            // lanes per position: enough 16-row groups to cover the t panel rows,
+            // at most 8 (then 32 rows per lane)
             int g = 1;
-            while (16 * g < t) g *= 2;
+            while (g < 8 && 16 * g < t) g *= 2;
             const int nb = (int)cdiv(n_rem, PT / g);
-            switch (g) {
-            case 1:
-                step_kernel<1><<<nb, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
-                                                 pin, nparts, pout, state, tau, piv, pstats);
-                break;
-            case 2:
-                step_kernel<2><<<nb, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
-                                                 pin, nparts, pout, state, tau, piv, pstats);
-                break;
-            case 4:
-                step_kernel<4><<<nb, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
-                                                 pin, nparts, pout, state, tau, piv, pstats);
-                break;
-            default:
-                step_kernel<8><<<nb, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1,
-                                                 pin, nparts, pout, state, tau, piv, pstats);
-                break;
-            }
+#define ELM_STEP(G, R)                                                                            \
+    step_kernel<G, R><<<nb, PT, 0, s>>>(k, t, n_rem, Scur, lds, P, n, d, chosen, rem0, rem1, pin, \
+                                        nparts, pout, state, tau, piv, pstats)
+            if (g == 1) ELM_STEP(1, 16);
+            else if (g == 2) ELM_STEP(2, 16);
+            else if (g == 4) ELM_STEP(4, 16);
+            else if (t <= 128) ELM_STEP(8, 16);
+            else ELM_STEP(8, 32);
+#undef ELM_STEP
             ELM_LAUNCH_CHECK();
             nparts = nb;
         }

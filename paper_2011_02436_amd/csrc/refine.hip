@@ -499,6 +499,40 @@ void launch_hidden_output(hipStream_t s, int64_t N, int64_t L, int64_t m, const 
     ELM_LAUNCH_CHECK();
 }
 
+// out[g][e] = sum of part[c][e] over the chunks c of group g (GS consecutive
+// chunks), in order
+__global__ __launch_bounds__(NT) void group_sum_kernel(int64_t len, int64_t nchunk, int gs,
+                                                       const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= len) return;
+    const int64_t c0 = (int64_t)blockIdx.y * gs;
+    const int64_t c1 = c0 + gs < nchunk ? c0 + gs : nchunk;
+    double acc = 0.0;
+    for (int64_t c = c0; c < c1; ++c) acc += part[c * len + e];
+    out[(int64_t)blockIdx.y * len + e] = acc;
+}
+
+void launch_partial_sum(hipStream_t s, int64_t L, int64_t m, int64_t nchunk, const double* part,
+                        double* G, int64_t ldg, double* nrm2, Workspace& ws) {
+    constexpr int GS = 64;
+    if (nchunk > 2 * GS) {  // two levels, so that no thread sums thousands of chunks
+        const int64_t ng = cdiv(nchunk, GS);
+        double* part2 = (double*)ws.get("psum_part2", (size_t)ng * L * m * sizeof(double));
+        group_sum_kernel<<<dim3((unsigned)cdiv(L * m, NT), (unsigned)ng), NT, 0, s>>>(L * m, nchunk, GS,
+                                                                                    part, part2);
+        ELM_LAUNCH_CHECK();
+        part = part2;
+        nchunk = ng;
+    }
+    const unsigned nred = (unsigned)cdiv(L * m, NT);
+    double* sq = (double*)ws.get("ht_sq", (size_t)nred * sizeof(double));
+    ht_reduce_kernel<<<nred, NT, 0, s>>>(L, (int)m, (int)nchunk, part, G, ldg, sq);
+    ELM_LAUNCH_CHECK();
+    sum_kernel<<<1, NT, 0, s>>>(nred, sq, nrm2);
+    ELM_LAUNCH_CHECK();
+}
+
 void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
                      const double* E, int64_t lde, double* G, int64_t ldg, double* nrm2,
                      Workspace& ws) {

@@ -130,3 +130,18 @@ def test_train_rejects_bad_arguments(elm):
         elm.train(X, W, b, T, precision="bf16", Hlp=bad)
     with pytest.raises(elm.ElmError):
         elm.train(X, W, b, T, ir_tol=2.0)
+
+
+@pytest.mark.parametrize("m", [1, 8, 12])
+def test_train_target_widths(elm, m):
+    # m <= 8 forms H^T T inside the hidden-layer kernel; wider targets take
+    # the separate streaming pass
+    p = wl.random_problem(seed=30 + m, N=3001, d=24, L=257, m=m, n_dup=17)
+    X, W, b, T = _dev(p)
+    ref, _ = O.solve(O.hidden(p.X, p.W, p.b), p.T)
+    for precision, tol in (("fp64", 1e-10), ("bf16", 1e-6)):
+        res = elm.train(X, W, b, T, precision=precision, ir_tol=1e-12)
+        err = O.rel_err(res.beta.cpu().numpy(), ref)
+        print(f"m={m} {precision}: rank {res.rank} err {err:.2e} its {res.info['iterations']}")
+        assert res.rank == p.structural_rank
+        assert err <= tol
