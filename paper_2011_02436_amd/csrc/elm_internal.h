@@ -226,19 +226,14 @@ void apply_pinv(hipStream_t s, const elm_factor* f, int64_t m, const double* rhs
 void launch_residual(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
                      const double* T, int64_t ldt, const double* beta, int64_t ldb, double* E,
                      int64_t lde);
-//   G = H^T E  (L x m), deterministic two-stage reduction; also writes ||G||_F^2 to *nrm2
-// G = sum over chunks (in order) of part[chunk] (each L x m, row-major), and
-// *nrm2 = ||G||_F^2
+//   G = sum over chunks (in order) of part[chunk] (each L x m, row-major), and
+//   *nrm2 = ||G||_F^2
 void launch_partial_sum(hipStream_t s, int64_t L, int64_t m, int64_t nchunk, const double* part,
                         double* G, int64_t ldg, double* nrm2, Workspace& ws);
+//   G = H^T E  (L x m), deterministic two-stage reduction; also writes ||G||_F^2 to *nrm2
 void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
                      const double* E, int64_t lde, double* G, int64_t ldg, double* nrm2,
                      Workspace& ws);
-//   G = H^T (T - H beta) in one pass over H (beta NULL: G = H^T T); false if the
-//   shape is outside the fused kernel's register/LDS budget (L > 10240 or m > 8)
-bool launch_fused_ht_resid(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
-                           int64_t ldh, const double* T, int64_t ldt, const double* beta, int64_t ldb,
-                           double* G, int64_t ldg, double* nrm2, Workspace& ws, int num_cu);
 //   Y = H beta and/or arg-max labels
 void launch_hidden_output(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
                           int64_t ldh, const double* beta, int64_t ldb, double* Y, int64_t ldy,

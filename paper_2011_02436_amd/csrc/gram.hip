@@ -125,84 +125,9 @@ template <> struct Mfma32<_Float16> {
     }
 };
 
-// 16-bit node-major Gram.  32x32x16 MFMA: lane l holds A[l % 32][8 (l / 32) + e],
-// e = 0..7, and B likewise by column; result row of register v is
-// 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32 (measured on gfx950).
-template <typename HT>
-__global__ __launch_bounds__(NT) void gram_lp_kernel(int64_t n, int64_t K, int64_t kc_len,
-                                                     const HT* __restrict__ A, int64_t ld,
-                                                     float* __restrict__ part, int64_t ntile) {
-    constexpr int BK = 32;
-    constexpr int LDK = BK + 8;  // row pitch in elements (80 B)
-    typedef typename Mfma32<HT>::vec_t vec_t;
-    __shared__ __attribute__((aligned(16))) HT As[TILE * LDK];
-    __shared__ __attribute__((aligned(16))) HT Bs[TILE * LDK];
-
-    int bi, bj;
-    tile_coords(blockIdx.x, bi, bj);
-    const int64_t r0 = (int64_t)bi * TILE, c0 = (int64_t)bj * TILE;
-    const int64_t kbeg = (int64_t)blockIdx.y * kc_len;
-    const int64_t kend = min(K, kbeg + kc_len);
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const bool vec_ok = ((ld & 7) == 0) && ((((uintptr_t)A) & 15) == 0);
-
-    f16v acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f16v{};
-
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-        // 128 rows x 32 k per operand = 512 vectors of 8 elements
-#pragma unroll
-        for (int it = 0; it < 2; ++it) {
-            const int vix = tid + it * NT;
-            const int row = vix >> 2, seg = vix & 3;
-            const int64_t gk = k0 + seg * 8;
-#pragma unroll
-            for (int opnd = 0; opnd < 2; ++opnd) {
-                const int64_t grow = (opnd == 0 ? r0 : c0) + row;
-                HT* dst = (opnd == 0 ? As : Bs) + row * LDK + seg * 8;
-                if (grow < n && vec_ok && gk + 8 <= kend) {
-                    *(uint4*)dst = *(const uint4*)(A + grow * ld + gk);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                        dst[e] = (grow < n && gk + e < kend) ? A[grow * ld + gk + e] : HT(0);
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 16) {
-            vec_t a[2], b[2];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                a[q] = *(const vec_t*)(As + (wm * 64 + q * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5));
-                b[q] = *(const vec_t*)(Bs + (wn * 64 + q * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5));
-            }
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y) acc[x][y] = Mfma32<HT>::op(a[x], b[y], acc[x][y]);
-        }
-        __syncthreads();
-    }
-
-    float* out = part + ((int64_t)blockIdx.y * ntile + blockIdx.x) * (TILE * TILE);
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int row = wm * 64 + x * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int col = wn * 64 + y * 32 + (lane & 31);
-                out[row * TILE + col] = acc[x][y][v];
-            }
-}
+// 32x32x16 MFMA operand/result layout (measured on gfx950): lane l holds
+// A[l % 32][8 (l / 32) + e], e = 0..7, and B likewise by column; result row of
+// register v is 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
 
 // M[i][j] = M[j][i] = sum over chunks (in chunk order, FP64) of the partial tiles
 template <typename PT>
@@ -277,7 +202,8 @@ int64_t run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, 
 // which 16, and the swizzle spreads rows r, r + 4, r + 8, r + 12 over the
 // four 16-byte slots, so the 16 consecutive rows that one quarter-wave of an
 // operand read (ds_read_b128) touches hit 16 distinct 4-bank groups.  Ragged
-// tiles, the K tail and unaligned input take a plain path.
+// tiles load clamped rows on the same path; the K tail and unaligned input
+// take a plain path.
 // ---------------------------------------------------------------------------
 constexpr int GT = 256;    // tile
 constexpr int GBK = 32;    // samples per stage
@@ -352,7 +278,9 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
                 acc[x][y] = Mfma32<HT>::op(FA[x], FB[y], acc[x][y]);                       \
     } while (0)
 
-    const bool interior = vec_ok && r0 + GT <= n && c0 + GT <= n;  // block-uniform
+    // Ragged tiles take the same path: rows past n read row n - 1 (their
+    // results land in partial-tile rows the reduction never reads).
+    const bool interior = vec_ok;  // block-uniform
     const int64_t nfull = interior ? (kend - kbeg) / GBK : 0;
     if (nfull > 0) {
         // DMA lane mapping: instruction i of wave w fills LDS bytes
@@ -365,8 +293,8 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
         for (int i = 0; i < 4; ++i) {
             const int row = (4 * i + wave) * 16 + (lane >> 2);
             const int c = (lane & 3) ^ ((row >> 2) & 3);
-            asrc[i] = A + (r0 + row) * ld + c * 8;
-            bsrc[i] = A + (c0 + row) * ld + c * 8;
+            asrc[i] = A + min(r0 + row, n - 1) * ld + c * 8;
+            bsrc[i] = A + min(c0 + row, n - 1) * ld + c * 8;
         }
         const int64_t klast = kbeg + (nfull - 1) * GBK;
 #define GRAM_DMA(STG, K0)                                                                    \

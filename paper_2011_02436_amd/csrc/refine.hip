@@ -167,130 +167,6 @@ __global__ __launch_bounds__(NT) void ht_kernel(int64_t N, int64_t L, int m,
 
 
 // ---------------------------------------------------------------------------
-// Fused pass: G = H^T (T - H beta) with one read of H.
-// A block of 1024 threads owns a contiguous range of rows; thread t owns
-// columns t, t + 1024, ... (CPT of them) and keeps their G partials (CPT x MM
-// FP64) in registers across all of the block's rows.  Per pair of rows it
-// loads its H values once, forms partial dot products with beta (read through
-// the cache each time: the register file holds the partials), reduces them
-// over the block (fixed order) into e = T - H beta for the pair, and adds
-// H[row][col] * e[row][:] to its partials.  Blocks write their partials; a
-// fixed-order reduction over blocks finishes G and ||G||_F^2.
-// With beta = NULL the pass computes H^T T.
-// ---------------------------------------------------------------------------
-constexpr int FT = 1024;
-
-// CR columns' partials in registers, CL more in thread-private LDS slots
-// (layout [j][c][thread], conflict-free); FR rows per step.
-template <int CR, int CL, int MM, int FR>
-__global__ __launch_bounds__(FT) void fused_ht_resid_kernel(int64_t N, int64_t L, int m,
-                                                          const double* __restrict__ H, int64_t ldh,
-                                                          const double* __restrict__ T, int64_t ldt,
-                                                          const double* __restrict__ beta, int64_t ldb,
-                                                          int64_t rows_per_block,
-                                                          double* __restrict__ part) {
-    constexpr int CPT = CR + CL;
-    __shared__ double red[FT / 64][FR * MM];
-    __shared__ double e_s[FR * MM];
-    __shared__ double gl[(CL > 0 ? CL : 1) * MM * FT];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t rbeg = (int64_t)blockIdx.x * rows_per_block;
-    const int64_t rend = min(N, rbeg + rows_per_block);
-
-    double g[CR > 0 ? CR : 1][MM];
-#pragma unroll
-    for (int j = 0; j < CR; ++j)
-#pragma unroll
-        for (int c = 0; c < MM; ++c) g[j][c] = 0.0;
-#pragma unroll
-    for (int j = 0; j < CL; ++j)
-#pragma unroll
-        for (int c = 0; c < MM; ++c) gl[(j * MM + c) * FT + tid] = 0.0;
-
-    // columns tid + j * FT; the last one may run past L
-    const int nvalid = (int)min<int64_t>(CPT, L > tid ? (L - 1 - tid) / FT + 1 : 0);
-    const double* __restrict__ bcol = beta ? beta + (int64_t)tid * ldb : nullptr;
-    for (int64_t r0 = rbeg; r0 < rend; r0 += FR) {
-        double h[FR][CPT];
-#pragma unroll
-        for (int r = 0; r < FR; ++r) {
-            const double* __restrict__ hrow = H + (r0 + r) * ldh + tid;
-            const bool rok = r0 + r < rend;
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) h[r][j] = (rok && j < nvalid) ? hrow[j * FT] : 0.0;
-        }
-        if (beta) {
-            // beta rows of my columns come through the cache each step
-            double s[FR][MM];
-#pragma unroll
-            for (int r = 0; r < FR; ++r)
-#pragma unroll
-                for (int c = 0; c < MM; ++c) s[r][c] = 0.0;
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                if (j < nvalid) {
-#pragma unroll
-                    for (int c = 0; c < MM; ++c) {
-                        const double bv = c < m ? bcol[(int64_t)j * FT * ldb + c] : 0.0;
-#pragma unroll
-                        for (int r = 0; r < FR; ++r) s[r][c] += h[r][j] * bv;
-                    }
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < FR; ++r)
-#pragma unroll
-                for (int c = 0; c < MM; ++c) {
-                    double v = s[r][c];
-                    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-                    s[r][c] = v;
-                }
-            if (lane == 0)
-#pragma unroll
-                for (int r = 0; r < FR; ++r)
-#pragma unroll
-                    for (int c = 0; c < MM; ++c) red[wave][r * MM + c] = s[r][c];
-            __syncthreads();
-            if (tid < FR * MM) {
-                const int r = tid / MM, c = tid % MM;
-                double a = 0.0;
-                for (int w = 0; w < FT / 64; ++w) a += red[w][tid];
-                const int64_t row = r0 + r;
-                e_s[tid] = (row < rend && c < m) ? T[row * ldt + c] - a : 0.0;
-            }
-        } else {
-            if (tid < FR * MM) {
-                const int r = tid / MM, c = tid % MM;
-                const int64_t row = r0 + r;
-                e_s[tid] = (row < rend && c < m) ? T[row * ldt + c] : 0.0;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < FR; ++r)
-#pragma unroll
-            for (int c = 0; c < MM; ++c) {
-                const double ev = e_s[r * MM + c];
-#pragma unroll
-                for (int j = 0; j < CR; ++j) g[j][c] += h[r][j] * ev;
-#pragma unroll
-                for (int j = 0; j < CL; ++j) gl[(j * MM + c) * FT + tid] += h[r][CR + j] * ev;
-            }
-        __syncthreads();
-    }
-    double* out = part + (int64_t)blockIdx.x * L * m;
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int64_t col = tid + (int64_t)j * FT;
-        if (col < L)
-#pragma unroll
-            for (int c = 0; c < MM; ++c)
-                if (c < m) out[col * m + c] = j < CR ? g[j < CR ? j : 0][c] : gl[((j - CR) * MM + c) * FT + tid];
-    }
-}
-
-
-// ---------------------------------------------------------------------------
 // Streaming passes built for HBM bandwidth.
 //
 // rows_dot_kernel: out[row][o] = sign * (H beta)[row][o] + (T ? T[row][o] : 0)
@@ -568,47 +444,6 @@ void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
 
 // G = H^T (T - H beta) in one pass over H (beta = NULL: G = H^T T).
 // Returns false when L or m is beyond what the register-resident partials hold.
-bool launch_fused_ht_resid(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
-                           int64_t ldh, const double* T, int64_t ldt, const double* beta, int64_t ldb,
-                           double* G, int64_t ldg, double* nrm2, Workspace& ws, int num_cu) {
-    const int64_t cpt = cdiv(L, FT);
-    if (cpt > 10 || m > 8) return false;
-    int nblk = num_cu;  // one 1024-thread block fills a CU's register file
-    int64_t rows = cdiv(N, nblk);
-    rows = cdiv(rows, 2) * 2;
-    nblk = (int)cdiv(N, rows);
-    double* part = (double*)ws.get("fr_part", (size_t)nblk * L * m * sizeof(double));
-    const unsigned nred = (unsigned)cdiv(L * m, NT);
-    double* sq = (double*)ws.get("ht_sq", (size_t)nred * sizeof(double));
-    const int mi = (int)m;
-#define FUSED_CASE(CR, CL, MMV, FRV)                                                               \
-    fused_ht_resid_kernel<CR, CL, MMV, FRV><<<nblk, FT, 0, s>>>(N, L, mi, H, ldh, T, ldt, beta, ldb, \
-                                                              rows, part)
-    if (m <= 4) {
-        switch (cpt) {
-            case 1: FUSED_CASE(1, 0, 4, 2); break;
-            case 2: FUSED_CASE(2, 0, 4, 2); break;
-            case 3: case 4: FUSED_CASE(4, 0, 4, 2); break;
-            case 5: case 6: FUSED_CASE(6, 0, 4, 1); break;
-            case 7: case 8: FUSED_CASE(8, 0, 4, 1); break;
-            default: FUSED_CASE(6, 4, 4, 1); break;
-        }
-    } else {
-        switch (cpt) {
-            case 1: FUSED_CASE(1, 0, 8, 2); break;
-            case 2: FUSED_CASE(2, 0, 8, 1); break;
-            case 3: case 4: FUSED_CASE(2, 2, 8, 1); break;
-            default: return false;
-        }
-    }
-#undef FUSED_CASE
-    ELM_LAUNCH_CHECK();
-    ht_reduce_kernel<<<nred, NT, 0, s>>>(L, mi, nblk, part, G, ldg, sq);
-    ELM_LAUNCH_CHECK();
-    sum_kernel<<<1, NT, 0, s>>>(nred, sq, nrm2);
-    ELM_LAUNCH_CHECK();
-    return true;
-}
 
 void launch_axpy_mat(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx,
                      double* Y, int64_t ldy) {
