@@ -7,7 +7,8 @@ L=10000, m=4 (synthetic, seeded).
 One step = the whole path on resident inputs: hidden layer (FP64 with a
 node-major BF16 copy), BF16 Gram, FP64 pivoted Cholesky and factor, beta with
 refinement to a relative normal-equation residual of 1e-10, and the
-training-set prediction (arg-max / outputs).
+training-set outputs H beta with their arg-max labels (taken from the last
+refinement pass, which evaluates H beta for the final beta).
 
 Prints ONE JSON line.  Extra keys: the FP64 form's time and the speedup at
 equal residual, per-stage times, the Gram kernel's roofline, and the FP64
@@ -181,10 +182,10 @@ def main():
     torch.cuda.synchronize()
 
     def step():
-        res = elm.train(X, W, b, T, precision=args.precision, ir_tol=1e-10, H64=H64, Hlp=Hlp,
-                        check_convergence=False)
-        elm.elm_predict_hidden(H64, res.beta)  # training-set outputs and labels (step 3)
-        return res
+        # training-set outputs and labels (step 3) come with the training, from
+        # its last refinement pass
+        return elm.train(X, W, b, T, precision=args.precision, ir_tol=1e-10, H64=H64, Hlp=Hlp,
+                         check_convergence=False, outputs=True)
 
     for i in range(args.warmup):
         res = step()
@@ -232,8 +233,7 @@ def main():
         for i in range(args.fp64_steps):
             ts = time.perf_counter()
             r64 = elm.train(X, W, b, T, precision="fp64", ir_tol=1e-10, ir_max_iter=8, H64=H64,
-                            check_convergence=False)
-            elm.elm_predict_hidden(H64, r64.beta)
+                            check_convergence=False, outputs=True)
             torch.cuda.synchronize()
             ft.append(time.perf_counter() - ts)
             log(f"fp64 step {i}: {ft[-1] * 1e3:.1f} ms, rank {r64.rank}, NE residual "
@@ -269,7 +269,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"smooth_regression N={N} d={prob.d} L={L} m={m}, {args.precision} Gram "
                                f"+ FP64 pivoted Cholesky + FP64 refinement to NE residual 1e-10, "
-                               f"plus training-set predict",
+                               f"plus training-set outputs and labels",
                    "N": N, "d": prob.d, "L": L, "m": m, "precision": args.precision},
         "rank": rank_lp,
         "ne_residual": info_lp["ne_residual"],

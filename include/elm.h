@@ -133,8 +133,10 @@ elm_status elm_hidden(elm_handle* h, int64_t N, int64_t d, int64_t L,
  * factored in FP64 by a greedy diagonally pivoted Cholesky: at each step the
  * pivot is the remaining index with the largest Schur-complement diagonal
  * (lowest original index on exact ties); the factorisation stops when that
- * diagonal is <= tau, tau = tau_rel * max_j M_jj, or n * 2^-53 * max_j M_jj
- * when tau_rel <= 0 (tau_rel must be < 1).  Then K = R11^-1 R12 and the
+ * diagonal is <= tau, tau = tau_rel * max_j M_jj, or, when tau_rel <= 0,
+ * 16 (n + K) 2^-53 max_j M_jj with K the number of products summed into each
+ * Gram entry (N for H^T H, L for H H^T), which keeps the Gram's own rounding
+ * from passing for a pivot (tau_rel must be < 1).  Then K = R11^-1 R12 and the
  * Cholesky factor of I + K K^T (or of I + K^T K when n - r < r, used through
  * the Woodbury identity) are formed, all in FP64.
  *
@@ -248,6 +250,11 @@ typedef struct {
  * reach ir_tol, the Gram is formed again one step up (16-bit -> FP32 -> FP64)
  * and the factor and solve are redone; info reports the steps taken.
  * tau_rel, ir_tol, ir_max_iter as for elm_rank_factor / elm_pinv_solve.
+ * Y (N x m FP64, ld ldy >= m) and labels (N int32), each optional: the
+ * training-set outputs H beta and their row arg-max (lowest index on ties) for
+ * the returned beta (step 3 of the three-step ELM; Table 2's training
+ * accuracy), taken from the last refinement pass, which evaluates H beta for
+ * that beta anyway (a separate pass when ir_max_iter = 0).  Need m <= 16.
  * factor_out (may be NULL) receives the final factor (caller frees it).
  * Errors: as the three calls; NO_CONVERGENCE only when the FP64 form does not
  * reach ir_tol (beta then holds the last iterate). */
@@ -257,8 +264,9 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m,
                      elm_dtype gram_dt, double* H64, int64_t ldh64,
                      void* Hlp, int64_t ldlp,
                      double tau_rel, double ir_tol, int32_t ir_max_iter,
-                     double* beta, int64_t ldbeta, elm_train_info* info,
-                     elm_factor** factor_out);
+                     double* beta, int64_t ldbeta,
+                     double* Y, int64_t ldy, int32_t* labels,
+                     elm_train_info* info, elm_factor** factor_out);
 
 /* One independent training of a batch (all pointers device pointers, FP64,
  * with the shapes and leading dimensions of elm_train). */

@@ -21,9 +21,13 @@ Learning Machine for large Datasets" (arXiv 2011.02436):
 Readings (the paper leaves these open; each is listed in the design notes):
 
 * The permutation P and rank r come from a greedy diagonally pivoted Cholesky
-  of the Gram H^T H (largest remaining Schur diagonal first, lowest original
-  column index on exact ties), stopped when the largest remaining diagonal is
-  <= tau = L * 2^-53 * max_j M_jj (the LAPACK xPSTRF default).
+  of the Gram H^T H (H H^T when N < L; largest remaining Schur diagonal
+  first, lowest original index on exact ties), stopped when the largest
+  remaining diagonal is <= tau = 16 (n + K) 2^-53 max_j M_jj, n the order of
+  the Gram and K the number of products summed into each entry.  (The LAPACK
+  xPSTRF default n 2^-53 max M_jj sits below the Gram's own rounding when
+  K > n: on H H^T with N < L and fewer distinct nodes than samples it accepted
+  noise pivots on 11 of 40 random draws; see default_tau.)
 * With H P = [H1 H2] and r = rank(H), H2 = H1 K for K = R11^-1 R12, so
   H = F G with F = H1 (full column rank) and G = [I K] P^T (full row rank),
   and H^+ = G^T (G G^T)^-1 (F^T F)^-1 F^T with F^T F = R11^T R11 and
@@ -38,7 +42,8 @@ Parity pins (tests/test_oracle.py): the SVD pseudoinverse (definition of the
 Moore-Penrose inverse), the four Penrose conditions, the structural rank of
 duplicated nodes, the closed form for duplicated columns, closed forms for
 W = 0, matrices with prescribed singular values, LAPACK dpstrf rank and pivot
-order, and scipy's logistic function.
+order at a given threshold, the rank of a generically rank-deficient H H^T
+against its SVD, and scipy's logistic function.
 """
 from __future__ import annotations
 
@@ -98,19 +103,29 @@ def gram_streamed(X, W, b, T, chunk_rows: int = 16384):
 # Permutation P and rank r (Section 3, eq. (6); algorithm steps 3-4):
 # greedy diagonally pivoted Cholesky  P^T M P ~= R^T R,  R = [R11 R12], r x L.
 # ----------------------------------------------------------------------------
-def default_tau(M: np.ndarray) -> float:
-    L = M.shape[0]
-    return L * EPS53 * (float(np.max(np.diag(M))) if L else 0.0)
+def default_tau(M: np.ndarray, K: Optional[int] = None) -> float:
+    """Stopping threshold of the rank step (the paper leaves it open):
+    tau = 16 (n + K) 2^-53 max_j M_jj, n the order of M and K the number of
+    products summed into each entry (samples for H^T H, nodes for H H^T; n
+    when not given).  Every entry of a Gram of the positive sigmoid matrix
+    carries up to K u of its size in rounding, so a direction that is
+    dependent in exact arithmetic keeps a Schur diagonal of about K u max M_jj
+    (measured: 1.1 K u on H H^T with N < L); LAPACK's default n u sits below
+    that when K > n and then accepts noise pivots."""
+    n = M.shape[0]
+    if K is None:
+        K = n
+    return 16.0 * (n + K) * EPS53 * (float(np.max(np.diag(M))) if n else 0.0)
 
 
-def pivoted_cholesky(M: np.ndarray, tau: Optional[float] = None):
+def pivoted_cholesky(M: np.ndarray, tau: Optional[float] = None, K: Optional[int] = None):
     """Rank-revealing Cholesky with complete (diagonal) pivoting.
 
     Returns (R, piv, r): R is r x L upper trapezoidal in pivoted order, piv
     the original column index at each pivoted position, r the rank.  At step k
     the pivot is the remaining column with the largest Schur-complement
     diagonal (lowest original index on an exact tie); the factorisation stops
-    when that diagonal is <= tau.
+    when that diagonal is <= tau (default_tau(M, K) when tau is None).
     """
     M = np.asarray(M, dtype=np.float64)
     L = M.shape[0]
@@ -119,7 +134,7 @@ def pivoted_cholesky(M: np.ndarray, tau: Optional[float] = None):
     d = np.diag(A).copy()
     R = np.zeros((L, L))
     if tau is None:
-        tau = default_tau(M)
+        tau = default_tau(M, K)
     r = L
     for k in range(L):
         rest = d[k:]
@@ -177,7 +192,7 @@ def rank_factor(H: np.ndarray, tau: Optional[float] = None, M: Optional[np.ndarr
     transposed = N < L
     if M is None:
         M = H @ H.T if transposed else H.T @ H
-    R, piv, r = pivoted_cholesky(M, tau)
+    R, piv, r = pivoted_cholesky(M, tau, K=L if transposed else N)
     return Factor(R, piv, r, transposed)
 
 

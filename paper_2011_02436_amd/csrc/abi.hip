@@ -141,6 +141,11 @@ size_t dtype_size(elm_dtype dt) {
 
 void free_factor_buffers(elm_factor* f) {
     if (!f) return;
+    if (f->pool) {  // workspace buffers stay with the workspace
+        f->piv = nullptr;
+        f->R = f->Rinv = f->K = f->Usinv = f->RinvT = f->KT = f->UsinvT = nullptr;
+        return;
+    }
     if (f->piv) (void)hipFree(f->piv);
     if (f->R) (void)hipFree(f->R);
     if (f->Rinv) (void)hipFree(f->Rinv);
@@ -242,9 +247,11 @@ elm_status elm_hidden(elm_handle* h, int64_t N, int64_t d, int64_t L, const void
     });
 }
 
-elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
-                           elm_dtype h_dt, elm_layout layout, double tau_rel, elm_factor** out,
-                           int64_t* rank) {
+}  // extern "C"
+
+static elm_status rank_factor_impl(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
+                                   elm_dtype h_dt, elm_layout layout, double tau_rel,
+                                   elm_factor** out, int64_t* rank, elm::Workspace* pool) {
     if (!h) return ELM_ERR_INVALID_ARG;
     elm_factor* f = nullptr;
     elm_status st = elm::guarded(h, [&] {
@@ -273,6 +280,7 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, i
         f->n = n;
         f->transposed = transposed;
         f->device = h->device;
+        f->pool = pool;
         double* M = (double*)h->ws.get("gram_M", (size_t)n * n * sizeof(double));
         int64_t kc = 0;  // products accumulated in FP32 per partial (low-precision Grams)
         if (h_dt == ELM_F64) {
@@ -291,12 +299,16 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, i
         ELM_HIP_TRY(hipMemcpyAsync(&hdmax, dmax, sizeof(double), hipMemcpyDeviceToHost, h->stream));
         ELM_HIP_TRY(hipStreamSynchronize(h->stream));
         if (!std::isfinite(hdmax)) throw Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
-        f->tau = (tau_rel > 0 ? tau_rel : (double)n * std::ldexp(1.0, -53)) * hdmax;
-        ELM_HIP_TRY(hipMalloc(&f->piv, (size_t)n * sizeof(int32_t)));
+        // default threshold: 16 (n + K) 2^-53 max diag, K = products summed per
+        // Gram entry, so that the Gram's own rounding (up to K u of an entry)
+        // never passes for a pivot
+        const int64_t K = transposed ? L : N;
+        f->tau = (tau_rel > 0 ? tau_rel : 16.0 * (double)(n + K) * std::ldexp(1.0, -53)) * hdmax;
+        f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
         double pst[3];
         {
             elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
-            f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, pst, h->ws);
+            f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, pst, h->ws, f);
         }
         f->last_pivot = pst[0];
         f->first_rejected = pst[1];
@@ -316,6 +328,14 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, i
         delete f;
     }
     return st;
+}
+
+extern "C" {
+
+elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
+                           elm_dtype h_dt, elm_layout layout, double tau_rel, elm_factor** out,
+                           int64_t* rank) {
+    return rank_factor_impl(h, N, L, H, ldh, h_dt, layout, tau_rel, out, rank, nullptr);
 }
 
 elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh, elm_dtype h_dt,
@@ -402,9 +422,12 @@ namespace {
 // beta = H^+ T with refinement (see elm_pinv_solve).  With z_ready the
 // caller has already put Z = H^T T and ||Z||_F^2 in the workspace buffers
 // "ps_Z" / "ps_nrm" (the hidden-layer kernel can produce them on the fly).
+// Y / labels (optional): H beta and its row arg-max for the returned beta,
+// taken from the last residual pass (a separate pass when there is none).
 elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const double* T, int64_t ldt,
                            const double* H64, int64_t ldh64, double ir_tol, int32_t ir_max_iter,
-                           double* beta, int64_t ldbeta, elm_solve_info* info, bool z_ready) {
+                           double* beta, int64_t ldbeta, elm_solve_info* info, bool z_ready,
+                           double* Y = nullptr, int64_t ldy = 0, int32_t* labels = nullptr) {
     elm_status result = ELM_OK;
     const int64_t N = f->N, L = f->L;
     elm::use_device(h);
@@ -432,6 +455,10 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
         elm::apply_pinv(s, f, m, T, ldt, H64, ldh64, beta, ldbeta, ws);
     }
     if (ir_max_iter == 0) {
+        if (Y || labels) {
+            elm::StageScope sc(pr, ELM_STAGE_PREDICT, s);
+            elm::launch_hidden_output(s, N, L, m, H64, ldh64, beta, ldbeta, Y, ldy, labels);
+        }
         ELM_HIP_TRY(hipStreamSynchronize(s));
         return result;
     }
@@ -450,7 +477,7 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
         // G = H^T (T - H beta): two streaming passes over H
         {
             elm::StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
-            elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m);
+            elm::launch_residual(s, N, L, m, H64, ldh64, T, ldt, beta, ldbeta, E, m, Y, ldy, labels);
         }
         {
             elm::StageScope sc(pr, ELM_STAGE_RHS, s);
@@ -531,7 +558,8 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, 
                      int64_t ldx, const double* W, int64_t ldw, const double* b, const double* T,
                      int64_t ldt, elm_dtype gram_dt, double* H64, int64_t ldh64, void* Hlp,
                      int64_t ldlp, double tau_rel, double ir_tol, int32_t ir_max_iter, double* beta,
-                     int64_t ldbeta, elm_train_info* info, elm_factor** factor_out) {
+                     int64_t ldbeta, double* Y, int64_t ldy, int32_t* labels, elm_train_info* info,
+                     elm_factor** factor_out) {
     if (!h) return ELM_ERR_INVALID_ARG;
     elm_factor* f = nullptr;
     elm_status st = elm::guarded(h, [&] {
@@ -544,6 +572,8 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, 
         REQUIRE(ldx >= d && ldw >= L && ldt >= m && ldh64 >= L && ldbeta >= m, ELM_ERR_SHAPE,
                 "a leading dimension is smaller than its row length");
         REQUIRE(!Hlp || ldlp >= N, ELM_ERR_SHAPE, "ldlp < N");
+        REQUIRE(!Y || ldy >= m, ELM_ERR_SHAPE, "ldy < m");
+        REQUIRE(!(Y || labels) || m <= 16, ELM_ERR_UNSUPPORTED, "training outputs need m <= 16");
         REQUIRE(ir_tol >= 0.0 && ir_tol < 1.0, ELM_ERR_INVALID_ARG, "ir_tol must be in [0, 1)");
         REQUIRE(ir_max_iter >= 0 && ir_max_iter <= 31, ELM_ERR_INVALID_ARG,
                 "ir_max_iter must be in [0, 31]");
@@ -579,12 +609,14 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, 
         }
         for (;;) {
             int64_t r = 0;
+            // a factor that is not handed back lives in the handle's workspace
+            elm::Workspace* pool = factor_out ? nullptr : &h->ws;
             if (gdt == ELM_F64)
-                elm::check_status(h, elm_rank_factor(h, N, L, H64, ldh64, ELM_F64, ELM_SAMPLE_MAJOR,
-                                                     tau_rel, &f, &r));
+                elm::check_status(h, rank_factor_impl(h, N, L, H64, ldh64, ELM_F64, ELM_SAMPLE_MAJOR,
+                                                      tau_rel, &f, &r, pool));
             else
-                elm::check_status(h, elm_rank_factor(h, N, L, lp, ldl, gdt, ELM_NODE_MAJOR, tau_rel,
-                                                     &f, &r));
+                elm::check_status(h, rank_factor_impl(h, N, L, lp, ldl, gdt, ELM_NODE_MAJOR, tau_rel,
+                                                      &f, &r, pool));
             elm::check_status(h, elm_factor_get_info(f, &ti.factor));
             ti.gram_dtype = gdt;
             const bool can_escalate = gdt != ELM_F64;
@@ -592,7 +624,8 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, 
                 ti.guard = 1;
             } else {
                 const elm_status ss = elm::pinv_solve_impl(h, f, m, T, ldt, H64, ldh64, ir_tol,
-                                                           ir_max_iter, beta, ldbeta, &ti.solve, fuse_z);
+                                                           ir_max_iter, beta, ldbeta, &ti.solve, fuse_z,
+                                                           Y, ldy, labels);
                 if (ss == ELM_OK) break;
                 if (ss != ELM_ERR_NO_CONVERGENCE || !can_escalate) {
                     if (info) *info = ti;
@@ -694,7 +727,8 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                     std::memset(&info_all[e], 0, sizeof(elm_train_info));
                     st_all[e] = elm_train(wh, p.N, p.d, p.L, p.m, p.X, p.ldx, p.W, p.ldw, p.b, p.T, p.ldt,
                                           gram_dt, p.H64, p.ldh64, nullptr, 0, tau_rel, ir_tol,
-                                          ir_max_iter, p.beta, p.ldbeta, &info_all[e], nullptr);
+                                          ir_max_iter, p.beta, p.ldbeta, nullptr, 0, nullptr,
+                                          &info_all[e], nullptr);
                     if (st_all[e] != ELM_OK) msg_all[e] = wh->last_error;
                 }
             });

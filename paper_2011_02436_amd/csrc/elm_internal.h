@@ -142,7 +142,9 @@ struct elm_factor {
     double max_diag = 0, last_pivot = 0, first_rejected = 0;
     double noise_floor = 0;   // absolute rounding-noise scale of the Schur diagonals
     bool reliable = true;
-    // device buffers owned by the factor (hipMalloc'd)
+    // device buffers: hipMalloc'd and owned by the factor, or, when pool is
+    // set, named buffers of that workspace (a factor used only inside a call)
+    elm::Workspace* pool = nullptr;
     int32_t* piv = nullptr;   // n: original index at each pivoted position
     double* R = nullptr;      // r x n, pivot order, ld n: [R11 R12]
     double* Rinv = nullptr;   // r x r, ld r: R11^-1 (upper triangular)
@@ -156,6 +158,20 @@ struct elm_factor {
     bool woodbury = false;
     int device = 0;
 };
+
+namespace elm {
+// A device buffer of a factor: from the factor's pool when it has one, else
+// hipMalloc'd (freed by free_factor_buffers).
+inline void* factor_alloc(elm_factor* f, const char* name, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (f->pool) return f->pool->get(std::string("factor_") + name, bytes);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess)
+        throw Error{ELM_ERR_ALLOC, std::string("factor buffer '") + name + "': hipMalloc of " +
+                                       std::to_string(bytes) + " bytes failed"};
+    return p;
+}
+}  // namespace elm
 
 namespace elm {
 
@@ -190,12 +206,13 @@ int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, 
 void launch_diag_max(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
 
 // pchol.hip: greedy pivoted Cholesky of M (n x n FP64, full symmetric, ld = ldm).
-// Writes piv (n), allocates *R_out = R (r x n in pivot order, ld n, hipMalloc'd,
+// Writes piv (n), allocates *R_out = R (r x n in pivot order, ld n, by factor_alloc,
 // NULL when r = 0) and returns r (synchronises the stream once).  stats_out
 // (host, 3 doubles): last accepted pivot (+inf if r = 0), largest Schur
 // diagonal at the stop (-inf if r = n), largest Gram diagonal.
 int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double tau,
-                         int32_t* piv, double** R_out, double* stats_out, Workspace& ws);
+                         int32_t* piv, double** R_out, double* stats_out, Workspace& ws,
+                         elm_factor* f);
 void launch_fill(hipStream_t s, double* p, int64_t count, double v);
 
 // Relative rounding-noise scale of the Schur diagonals of a Gram formed from
@@ -223,9 +240,10 @@ void apply_pinv(hipStream_t s, const elm_factor* f, int64_t m, const double* rhs
 
 // refine.hip: streaming FP64 passes over sample-major H
 //   E = T - H beta  (N x m)
+//   (optionally also Y = H beta and the arg-max of each row of H beta)
 void launch_residual(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
                      const double* T, int64_t ldt, const double* beta, int64_t ldb, double* E,
-                     int64_t lde);
+                     int64_t lde, double* Y = nullptr, int64_t ldy = 0, int32_t* labels = nullptr);
 //   G = sum over chunks (in order) of part[chunk] (each L x m, row-major), and
 //   *nrm2 = ||G||_F^2
 void launch_partial_sum(hipStream_t s, int64_t L, int64_t m, int64_t nchunk, const double* part,

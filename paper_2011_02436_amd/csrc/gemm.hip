@@ -54,13 +54,31 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(int64_t M, int64_t N, int64
     const int a_di = a_kcontig ? 0 : 1, a_dk = a_kcontig ? 1 : 0;
     const int b_dj = b_jcontig ? 1 : 0, b_dk = b_jcontig ? 0 : 1;
     double av[EPT], bv[EPT];
-    auto load = [&](int64_t k0) {
+    // Rows past M and columns past N read clamped (in-range) addresses; their
+    // results are never stored.  Only k needs masking, and only in a chunk
+    // that crosses k_hi (a block-uniform branch): per-lane guarded loads would
+    // compile to branches whose joins wait for each load.
+    int64_t arow[EPT], bcol[EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int64_t gi = i0 + a_i + e * a_di, gk = k0 + a_k + e * a_dk;
-            av[e] = (gi < M && gk < k_hi) ? A[gi * a_rs + gk * a_cs] : 0.0;
-            const int64_t gj = j0 + b_j + e * b_dj, gkb = k0 + b_k + e * b_dk;
-            bv[e] = (gj < N && gkb < k_hi) ? B[gkb * b_rs + gj * b_cs] : 0.0;
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t gi = i0 + a_i + e * a_di, gj = j0 + b_j + e * b_dj;
+        arow[e] = gi < M ? gi : M - 1;
+        bcol[e] = gj < N ? gj : N - 1;
+    }
+    auto load = [&](int64_t k0) {
+        if (k0 + BK <= k_hi) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                av[e] = A[arow[e] * a_rs + (k0 + a_k + e * a_dk) * a_cs];
+                bv[e] = B[(k0 + b_k + e * b_dk) * b_rs + bcol[e] * b_cs];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int64_t gk = k0 + a_k + e * a_dk, gkb = k0 + b_k + e * b_dk;
+                av[e] = gk < k_hi ? A[arow[e] * a_rs + gk * a_cs] : 0.0;
+                bv[e] = gkb < k_hi ? B[gkb * b_rs + bcol[e] * b_cs] : 0.0;
+            }
         }
     };
     auto store = [&](int buf) {

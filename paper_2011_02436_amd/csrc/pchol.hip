@@ -343,13 +343,26 @@ __global__ __launch_bounds__(256, 2) void trailing_kernel(int64_t n_new, const d
     // thread -> panel row k, positions i .. i + EPT - 1 of the tile
     const int lk = (tid * EPT) / TT, li0 = (tid * EPT) % TT;
     double av[EPT], bv[EPT];
+    // qa/qb hold valid positions for every slot (slots past n_new read
+    // position 0; their results are never stored), so only the panel row
+    // needs masking, and only in a chunk that runs past nbp (block-uniform):
+    // per-lane guarded loads would compile to branches that wait on each load
     auto load = [&](int k0) {
-        const bool kin = k0 + lk < nbp;
-        const double* prow = P + (int64_t)(k0 + lk) * ldp;
+        if (k0 + BK <= nbp) {
+            const double* prow = P + (int64_t)(k0 + lk) * ldp;
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            av[e] = (kin && r0 + li0 + e < n_new) ? prow[qa[li0 + e]] : 0.0;
-            bv[e] = (kin && c0 + li0 + e < n_new) ? prow[qb[li0 + e]] : 0.0;
+            for (int e = 0; e < EPT; ++e) {
+                av[e] = prow[qa[li0 + e]];
+                bv[e] = prow[qb[li0 + e]];
+            }
+        } else {
+            const bool kin = k0 + lk < nbp;
+            const double* prow = P + (int64_t)(kin ? k0 + lk : 0) * ldp;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                av[e] = kin ? prow[qa[li0 + e]] : 0.0;
+                bv[e] = kin ? prow[qb[li0 + e]] : 0.0;
+            }
         }
     };
     auto store = [&](int buf) {
@@ -441,7 +454,8 @@ __global__ void gather_kernel(int64_t r, int64_t n, const double* __restrict__ R
 }  // namespace
 
 int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double tau,
-                         int32_t* piv, double** R_out, double* stats_out, Workspace& ws) {
+                         int32_t* piv, double** R_out, double* stats_out, Workspace& ws,
+                         elm_factor* f) {
     const int64_t nparts_max = cdiv(n, PT / 8);  // most blocks of any step launch
     int* state = (int*)ws.get("pc_state", ST_N * sizeof(int));
     double* pstats = (double*)ws.get("pc_stats", PS_N * sizeof(double));
@@ -527,7 +541,7 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
     const int64_t r = hstate[ST_RANK];
     double* R = nullptr;
     if (r > 0) {
-        ELM_HIP_TRY(hipMalloc(&R, (size_t)r * n * sizeof(double)));
+        R = (double*)factor_alloc(f, "R", (size_t)r * n * sizeof(double));
         gather_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)r), 256, 0, s>>>(r, n, Rorig, n, piv,
                                                                                 R, n);
         ELM_LAUNCH_CHECK();

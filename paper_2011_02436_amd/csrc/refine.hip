@@ -187,7 +187,8 @@ __global__ __launch_bounds__(SB) void rows_dot_kernel(int64_t N, int64_t L, int 
                                                       const double* __restrict__ beta, int64_t ldb,
                                                       const double* __restrict__ T, int64_t ldt,
                                                       double sign, double* __restrict__ out,
-                                                      int64_t ldo, int32_t* __restrict__ labels) {
+                                                      int64_t ldo, int32_t* __restrict__ labels,
+                                                      double* __restrict__ y, int64_t ldy) {
     __shared__ double red[SB / 64][RBR * MM];
     __shared__ double fin[RBR * MM];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -227,8 +228,9 @@ __global__ __launch_bounds__(SB) void rows_dot_kernel(int64_t N, int64_t L, int 
         const int64_t row = r0 + r;
         double o = sign * v;
         if (T && row < N && c < m) o += T[row * ldt + c];
-        fin[tid] = o;
+        fin[tid] = v;
         if (out && row < N && c < m) out[row * ldo + c] = o;
+        if (y && row < N && c < m) y[row * ldy + c] = v;
     }
     if (labels) {
         __syncthreads();
@@ -335,17 +337,18 @@ __global__ void axpy_mat_kernel(int64_t rows, int64_t cols, const double* __rest
 
 static void launch_rows_dot(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
                             int64_t ldh, const double* beta, int64_t ldb, const double* T, int64_t ldt,
-                            double sign, double* out, int64_t ldo, int32_t* labels) {
+                            double sign, double* out, int64_t ldo, int32_t* labels,
+                            double* y = nullptr, int64_t ldy = 0) {
     const unsigned grid = (unsigned)cdiv(N, RBR);
     const int mi = (int)m;
     if (m <= 2)
-        rows_dot_kernel<2><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels);
+        rows_dot_kernel<2><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy);
     else if (m <= 4)
-        rows_dot_kernel<4><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels);
+        rows_dot_kernel<4><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy);
     else if (m <= 8)
-        rows_dot_kernel<8><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels);
+        rows_dot_kernel<8><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy);
     else if (m <= 16)
-        rows_dot_kernel<16><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels);
+        rows_dot_kernel<16><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy);
     else
         throw Error{ELM_ERR_UNSUPPORTED, "m > 16 on the streaming row pass"};
     ELM_LAUNCH_CHECK();
@@ -353,11 +356,12 @@ static void launch_rows_dot(hipStream_t s, int64_t N, int64_t L, int64_t m, cons
 
 void launch_residual(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H, int64_t ldh,
                      const double* T, int64_t ldt, const double* beta, int64_t ldb, double* E,
-                     int64_t lde) {
+                     int64_t lde, double* Y, int64_t ldy, int32_t* labels) {
     if (m <= 16) {
-        launch_rows_dot(s, N, L, m, H, ldh, beta, ldb, T, ldt, -1.0, E, lde, nullptr);
+        launch_rows_dot(s, N, L, m, H, ldh, beta, ldb, T, ldt, -1.0, E, lde, labels, Y, ldy);
         return;
     }
+    if (Y || labels) throw Error{ELM_ERR_UNSUPPORTED, "training outputs from the residual pass need m <= 16"};
     const unsigned grid = (unsigned)cdiv(N, RT);
     residual_kernel<16><<<grid, NT, 0, s>>>(N, L, (int)m, H, ldh, T, ldt, beta, ldb, E, lde);
     ELM_LAUNCH_CHECK();

@@ -188,9 +188,9 @@ void rowprod(hipStream_t s, int64_t M, int64_t K, int64_t m, double alpha, const
     ELM_LAUNCH_CHECK();
 }
 
-double* transposed_copy(hipStream_t s, int64_t R, int64_t Cn, const double* A, int64_t lda) {
-    double* B = nullptr;
-    ELM_HIP_TRY(hipMalloc(&B, (size_t)R * Cn * sizeof(double)));
+// B (Cn x R, ld R) = A^T; returns B
+double* transposed_copy(hipStream_t s, int64_t R, int64_t Cn, const double* A, int64_t lda,
+                        double* B) {
     transpose_kernel<<<dim3((unsigned)cdiv(Cn, 32), (unsigned)cdiv(R, 32)), dim3(32, 8), 0, s>>>(R, Cn, A,
                                                                                                 lda, B, R);
     ELM_LAUNCH_CHECK();
@@ -297,15 +297,17 @@ void apply_f_gram_inv(hipStream_t s, const elm_factor* f, int64_t m, double* y, 
 void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws) {
     const int64_t r = f->r, n = f->n, c = n - r;
     if (r == 0) return;
-    ELM_HIP_TRY(hipMalloc(&f->Rinv, (size_t)r * r * sizeof(double)));
+    f->Rinv = (double*)factor_alloc(f, "Rinv", (size_t)r * r * sizeof(double));
     trtri_upper(s, r, f->R, n, f->Rinv, r, ws);
-    f->RinvT = transposed_copy(s, r, r, f->Rinv, r);
+    f->RinvT = transposed_copy(s, r, r, f->Rinv, r,
+                               (double*)factor_alloc(f, "RinvT", (size_t)r * r * sizeof(double)));
     if (c > 0) {
-        ELM_HIP_TRY(hipMalloc(&f->K, (size_t)r * c * sizeof(double)));
+        f->K = (double*)factor_alloc(f, "K", (size_t)r * c * sizeof(double));
         // K = R11^-1 R12 (R11^-1 upper triangular)
         gemm_f64_batched(s, 1, r, c, r, 1.0, f->Rinv, r, 1, 0, f->R + r, n, 1, 0, 0.0, f->K, c, 0, true,
                          false);
-        f->KT = transposed_copy(s, r, c, f->K, c);
+        f->KT = transposed_copy(s, r, c, f->K, c,
+                                (double*)factor_alloc(f, "KT", (size_t)r * c * sizeof(double)));
     }
     const int64_t q = r < c ? r : c;
     f->q = q;
@@ -322,9 +324,10 @@ void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws) {
     ELM_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
     chol_small_kernel<<<1, 1024, 0, s>>>(q, S, q, flag);
     ELM_LAUNCH_CHECK();
-    ELM_HIP_TRY(hipMalloc(&f->Usinv, (size_t)q * q * sizeof(double)));
+    f->Usinv = (double*)factor_alloc(f, "Usinv", (size_t)q * q * sizeof(double));
     trtri_upper(s, q, S, q, f->Usinv, q, ws);
-    f->UsinvT = transposed_copy(s, q, q, f->Usinv, q);
+    f->UsinvT = transposed_copy(s, q, q, f->Usinv, q,
+                                (double*)factor_alloc(f, "UsinvT", (size_t)q * q * sizeof(double)));
     int hflag = 0;
     ELM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));

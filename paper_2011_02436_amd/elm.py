@@ -103,7 +103,8 @@ def _load():
         "elm_train_batched": ([vp, i32, ctypes.POINTER(Problem), i32, dbl, dbl, i32,
                                ctypes.POINTER(TrainInfo), ctypes.POINTER(i32)], i32),
         "elm_train": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, vp, i64, i32, vp, i64, vp, i64,
-                       dbl, dbl, i32, vp, i64, ctypes.POINTER(TrainInfo), ctypes.POINTER(vp)], i32),
+                       dbl, dbl, i32, vp, i64, vp, i64, vp, ctypes.POINTER(TrainInfo),
+                       ctypes.POINTER(vp)], i32),
         "elm_pinv_solve": ([vp, vp, i64, vp, i64, vp, i64, dbl, i32, vp, i64,
                             ctypes.POINTER(SolveInfo)], i32),
         "elm_predict": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, vp],
@@ -388,14 +389,17 @@ class TrainResult:
     rank: int
     info: dict
     factor: Factor = field(repr=False, default=None)
+    Y: Optional[torch.Tensor] = field(repr=False, default=None)       # H beta (training set)
+    labels: Optional[torch.Tensor] = field(repr=False, default=None)  # row arg-max of H beta
 
 
 def train(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, T: torch.Tensor, precision: str = "fp64",
           ir_tol: float = 1e-10, ir_max_iter: Optional[int] = None, tau_rel: float = 0.0,
           H64: Optional[torch.Tensor] = None, Hlp: Optional[torch.Tensor] = None,
-          check_convergence: bool = True) -> TrainResult:
+          check_convergence: bool = True, outputs: bool = False) -> TrainResult:
     """H = g(XW + b) -> rank factor -> beta = H^+ T (+ FP64 refinement), one
-    elm_train call.
+    elm_train call.  outputs=True also returns the training-set outputs
+    Y = H beta and their arg-max labels, taken from the last refinement pass.
 
     precision: 'fp64' (FP64 Gram), or 'fp32' / 'bf16' / 'fp16' (Gram of a
     node-major low-precision copy; the rank decision and the refinement
@@ -428,10 +432,18 @@ def train(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, T: torch.Tensor, pr
     hp, ldh = _mat(H64, "H64")
     beta = torch.empty((L, m), dtype=torch.float64, device=X.device)
     bp, ldb = _mat(beta, "beta")
+    Y = labels = None
+    yp, ldy, lp_lab = None, 0, None
+    if outputs:
+        Y = torch.empty((N, m), dtype=torch.float64, device=X.device)
+        labels = torch.empty((N,), dtype=torch.int32, device=X.device)
+        yp, ldy = _mat(Y, "Y")
+        lp_lab = _vec(labels, "labels")
     ti = TrainInfo()
     fptr = ctypes.c_void_p()
     st = _lib.elm_train(h.ptr, N, d, L, m, xp, ldx, wp, ldw, _vec(b, "b"), tp, ldt, gdt, hp, ldh,
-                        lp_ptr, ldlp, tau_rel, ir_tol, its, bp, ldb, ctypes.byref(ti), ctypes.byref(fptr))
+                        lp_ptr, ldlp, tau_rel, ir_tol, its, bp, ldb, yp, ldy, lp_lab, ctypes.byref(ti),
+                        ctypes.byref(fptr))
     if st == ELM_ERR_NO_CONVERGENCE and not check_convergence:
         pass
     else:
@@ -442,7 +454,7 @@ def train(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, T: torch.Tensor, pr
     info["escalations"] = int(ti.escalations)
     info["guard"] = int(ti.guard)
     factor = Factor(fptr, N, L, int(ti.factor.rank)) if fptr.value else None
-    return TrainResult(beta, int(ti.factor.rank), info, factor)
+    return TrainResult(beta, int(ti.factor.rank), info, factor, Y, labels)
 
 
 def _train_info_dict(ti: TrainInfo) -> dict:

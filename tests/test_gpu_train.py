@@ -45,7 +45,7 @@ def test_factor_info_fp64_matches_oracle(elm):
     assert info["gram_dtype"] == "fp64" and info["reliable"]
     assert abs(info["max_diag"] - mx) <= 1e-13 * mx
     assert abs(info["last_pivot"] - R[r - 1, r - 1] ** 2) <= 1e-9 * mx
-    assert abs(info["tau"] - O.default_tau(M)) <= 1e-13 * O.default_tau(M)
+    assert abs(info["tau"] - O.default_tau(M, K=p.N)) <= 1e-13 * O.default_tau(M, K=p.N)
     # duplicated columns leave Schur diagonals at rounding level
     assert info["first_rejected"] <= info["tau"]
     assert abs(info["first_rejected"]) <= 1e3 * info["n"] * 2.0 ** -53 * mx
@@ -145,3 +145,45 @@ def test_train_target_widths(elm, m):
         print(f"m={m} {precision}: rank {res.rank} err {err:.2e} its {res.info['iterations']}")
         assert res.rank == p.structural_rank
         assert err <= tol
+
+
+@pytest.mark.parametrize("precision,its", [("fp64", None), ("bf16", None), ("fp64", 0)])
+def test_train_outputs_are_h_beta(elm, precision, its):
+    # Y and labels come from the last refinement pass (a separate pass when
+    # there is no refinement); they must be H beta for the returned beta
+    p = wl.random_problem(seed=41, N=2500, d=16, L=300, m=5, n_dup=30)
+    X, W, b, T = _dev(p)
+    res = elm.train(X, W, b, T, precision=precision, ir_tol=1e-12, ir_max_iter=its, outputs=True)
+    H = O.hidden(p.X, p.W, p.b)
+    want = H @ res.beta.cpu().numpy()
+    got = res.Y.cpu().numpy()
+    assert O.rel_err(got, want) <= 1e-13
+    lab = res.labels.cpu().numpy()
+    # arg-max with the lowest index on ties; rows whose top two outputs are
+    # within rounding of each other may take either
+    top2 = np.sort(want, axis=1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0]) > 1e-12 * np.abs(want).max()
+    assert np.array_equal(lab[clear], np.argmax(want, axis=1)[clear])
+    assert np.all((lab >= 0) & (lab < p.m))
+    acc = float(np.mean(lab == p.labels))
+    ref_acc = O.training_accuracy(p.X, p.W, p.b, res.beta.cpu().numpy(), p.labels)
+    assert abs(acc - ref_acc) <= 2.0 / p.N
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_train_generically_rank_deficient_n_below_l(elm, precision):
+    # N < L with fewer distinct nodes than samples: H H^T is singular without
+    # duplicated rows, so its rejected pivots are rounding noise of the Gram;
+    # the default threshold must reject them (the oracle pins the same case
+    # against the SVD)
+    p = wl.random_problem(seed=138, N=399, d=32, L=443, m=3, n_dup=58)
+    X, W, b, T = _dev(p)
+    H = O.hidden(p.X, p.W, p.b)
+    ref, F = O.solve(H, p.T)
+    res = elm.train(X, W, b, T, precision=precision, ir_tol=1e-12)
+    err = O.rel_err(res.beta.cpu().numpy(), ref)
+    print(f"{precision}: rank {res.rank} (oracle {F.r}) err {err:.2e} ne {res.info['ne_residual']:.1e}")
+    assert res.rank == F.r == 385
+    assert res.info["transposed"] and res.info["gram_dtype"] == "fp64"
+    assert res.info["ne_residual"] <= 1e-12
+    assert err <= 1e-8

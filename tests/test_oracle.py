@@ -70,6 +70,29 @@ def test_pivoted_cholesky_matches_lapack_dpstrf(L, k):
     assert np.max(np.abs(R.T @ R - Mp)) <= 1e-12 * np.max(np.abs(M))
 
 
+def test_rank_threshold_on_generically_rank_deficient_h_ht():
+    # N < L with fewer distinct nodes (385) than samples (399): H H^T is
+    # rank-deficient without any duplicated rows, so its rejected Schur
+    # diagonals are rounding noise of the Gram (about K u max diag, K = L
+    # products per entry) rather than exact zeros.  The threshold must sit
+    # above that noise: the rank equals the SVD's and the structural rank,
+    # and the solution satisfies the normal equations.
+    p = wl.random_problem(seed=138, N=399, d=32, L=443, m=3, n_dup=58)
+    H = O.hidden(p.X, p.W, p.b)
+    M = H @ H.T
+    s = np.linalg.svd(H, compute_uv=False)
+    F = O.rank_factor(H)
+    assert F.transposed
+    assert F.r == p.structural_rank == 385 == int(np.sum(s > 1e-10 * s[0]))
+    beta, _ = O.solve(H, p.T)
+    assert O.ne_residual(H, p.T, beta) <= 1e-10
+    assert O.rel_err(beta, np.linalg.pinv(H, rcond=1e-10) @ p.T) <= 1e-8
+    # LAPACK's default n u max diag lies below the noise here and keeps a
+    # noise pivot (why the threshold scales with K as well)
+    _, _, r_lapack = O.pivoted_cholesky(M, tau=H.shape[0] * 2.0 ** -53 * M.diagonal().max())
+    assert r_lapack > 385
+
+
 def test_pivot_tie_break_lowest_original_index():
     # all diagonals equal and orthogonal columns: every step is a tie
     M = np.diag([3.0, 3.0, 3.0, 3.0])
