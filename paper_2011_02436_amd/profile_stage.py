@@ -6,7 +6,8 @@ profiling a single kernel under rocprofv3 (kernel trace or counters).
 Stages: hidden (FP64 H + BF16 copy), gram (BF16 Gram), gram64 (FP64 Gram),
 rank (pivoted Cholesky + factor), refine (factor and one refinement pass),
 predict (Y = H beta), copy (a plain device copy of the FP64 H, the
-reference for scaling memory counters).  Each stage runs --reps times after
+reference for scaling memory counters), batch (the 256-ELM hidden-size sweep
+through elm_train_batched, BF16 form).  Each stage runs --reps times after
 one untimed call.
 """
 import argparse
@@ -22,7 +23,7 @@ if ROOT not in sys.path:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stage", required=True,
-                    choices=["hidden", "gram", "gram64", "rank", "refine", "predict", "copy"])
+                    choices=["hidden", "gram", "gram64", "rank", "refine", "predict", "copy", "batch"])
     ap.add_argument("--N", type=int, default=500000)
     ap.add_argument("--L", type=int, default=10000)
     ap.add_argument("--reps", type=int, default=1)
@@ -34,6 +35,16 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.stage == "batch":
+        probs = wl.batch_sweep()
+        dp = [tuple(torch.from_numpy(a).to(dev) for a in (q.X, q.W, q.b, q.T)) for q in probs]
+        H64s = [torch.empty((q.N, q.L), dtype=torch.float64, device=dev) for q in probs]
+        for i in range(args.reps + 1):
+            t0 = time.perf_counter()
+            elm.train_batched(dp, precision="bf16", ir_tol=1e-10, H64s=H64s, check=False)
+            torch.cuda.synchronize()
+            print(f"[profile_stage] batch rep {i}: {(time.perf_counter() - t0) * 1e3:.2f} ms", flush=True)
+        return
     p = wl.smooth_regression(N=args.N, L=args.L)
     X, W, b, T = (torch.from_numpy(a).to(dev) for a in (p.X, p.W, p.b, p.T))
     H64 = torch.empty((p.N, p.L), dtype=torch.float64, device=dev)
