@@ -345,7 +345,9 @@ typedef struct {
 } elm_stage_times;
 
 /* enable != 0 starts recording HIP events around every stage on the handle's
- * stream and clears the accumulated times; enable == 0 stops recording. */
+ * stream and clears the accumulated times; enable == 0 stops recording.
+ * elm_train_batched adds its workers' stage times (concurrent streams, so
+ * the sums can exceed the wall time). */
 elm_status elm_profile_enable(elm_handle* h, int enable);
 
 /* Accumulated stage times since the last elm_profile_enable(h, 1)

@@ -7,6 +7,7 @@
 #include <thread>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -683,7 +684,12 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
         }
         if (count == 0) return;
         elm::use_device(h);
-        const int nw = count < elm::BATCH_WORKERS ? count : elm::BATCH_WORKERS;
+        int nwmax = elm::BATCH_WORKERS;
+        if (const char* e = std::getenv("ELM_BATCH_WORKERS")) {  // tuning override, 1..16
+            const int v = std::atoi(e);
+            if (v >= 1 && v <= 16) nwmax = v;
+        }
+        const int nw = count < nwmax ? count : nwmax;
         while ((int)h->workers.size() < nw) {
             hipStream_t ws_stream = nullptr;
             ELM_HIP_TRY(hipStreamCreateWithFlags(&ws_stream, hipStreamNonBlocking));
@@ -718,6 +724,8 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
         st_all.assign(count, ELM_OK);
         msg_all.assign(count, std::string());
         std::vector<elm_train_info> info_all(count);
+        // stage timers of the workers follow the handle's (summed into it below)
+        for (int w = 0; w < nw; ++w) h->workers[w]->prof.on = h->prof.on;
         std::vector<std::thread> threads;
         for (int w = 0; w < nw; ++w) {
             threads.emplace_back([&, w] {
@@ -734,6 +742,18 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             });
         }
         for (auto& t : threads) t.join();
+        if (h->prof.on) {
+            for (int w = 0; w < nw; ++w) {
+                elm::Profiler& wp = h->workers[w]->prof;
+                wp.resolve();
+                for (int i = 0; i < ELM_STAGE_COUNT; ++i) {
+                    h->prof.ms[i] += wp.ms[i];
+                    h->prof.cnt[i] += wp.cnt[i];
+                    wp.ms[i] = 0;
+                    wp.cnt[i] = 0;
+                }
+            }
+        }
         // the caller's stream continues after the workers
         for (int w = 0; w < nw; ++w) {
             ELM_HIP_TRY(hipEventRecord(ev, h->workers[w]->stream));

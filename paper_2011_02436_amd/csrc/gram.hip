@@ -481,6 +481,13 @@ static std::vector<int4> gram_work_table(int64_t nt, int nsplit, int64_t ntile) 
 
 // splits of K: enough work items to fill 256 CUs in whole rounds
 static int pick_splits(int64_t ntile, int64_t K) {
+    if (ntile < 64) {
+        // few tiles (small L): split K until about 256 blocks run, keeping
+        // chunks of at least 512 samples; the partial tiles stay small
+        int64_t s = (256 + ntile - 1) / ntile;
+        const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(64, K / 512));
+        return (int)std::min(s, smax);
+    }
     int best = 1;
     double best_eff = 0.0;
     for (int s = 1; s <= 16; ++s) {

@@ -444,6 +444,159 @@ __global__ __launch_bounds__(256, 2) void trailing_kernel(int64_t n_new, const d
     }
 }
 
+// ---------------------------------------------------------------------------
+// Small Grams (n <= SMALL_N): the whole factorisation in one workgroup, so a
+// pivot costs two block barriers instead of a kernel launch.  Same algorithm
+// and pivot rule: S (a copy of M, positions = original indices, both
+// triangles) takes a rank-SNB update after every SNB pivots; within a panel
+// the pivot row is S[p][a] - sum_{t' < t} P[t'][p] P[t'][a] from the panel
+// rows kept in LDS.  Writes R rows in original column order (Rorig), piv
+// (accepted pivots), state[ST_RANK] and the pivot statistics.
+// ---------------------------------------------------------------------------
+constexpr int SMALL_N = 512;
+constexpr int SNB = 16;
+constexpr int SPT = 1024;
+
+__global__ __launch_bounds__(SPT) void pchol_small_kernel(int n, const double* __restrict__ M,
+                                                          int64_t ldm, double* __restrict__ S,
+                                                          double tau, int32_t* __restrict__ piv,
+                                                          double* __restrict__ Rorig, int64_t ldr,
+                                                          int* state, double* pstats) {
+    // No global store happens between the barriers of a pivot step (a
+    // barrier waits for the block's outstanding stores): R rows, pivots and
+    // statistics are written out per panel or at the end.
+    __shared__ double P[SNB][SMALL_N];
+    __shared__ double d[SMALL_N];
+    __shared__ int chosen[SMALL_N];
+    __shared__ int pivl[SMALL_N];
+    __shared__ double wv[SPT / 64];
+    __shared__ int wi[SPT / 64];
+    __shared__ double s_v, st_last, st_reject, st_max;
+    __shared__ int s_p, s_stop;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    bool bad = false;
+    for (int a = tid; a < n; a += SPT) {
+        d[a] = M[(int64_t)a * ldm + a];
+        chosen[a] = 0;
+        if (!isfinite(d[a])) bad = true;
+    }
+    if (bad) state[ST_BAD] = 1;
+    if (tid == 0) {
+        st_last = INFINITY;
+        st_reject = -INFINITY;
+        st_max = 0.0;
+        s_stop = 0;
+    }
+    __syncthreads();
+    int k = 0;
+    while (k < n) {
+        const int k0 = k;
+        const int nb = n - k < SNB ? n - k : SNB;
+        // the first panel reads M itself; later panels the updated copy
+        const double* Sc = k0 == 0 ? M : S;
+        const int64_t lsc = k0 == 0 ? ldm : n;
+        int t = 0;
+        for (; t < nb; ++t) {
+            // largest remaining Schur diagonal, lowest index on ties
+            double bv = -INFINITY;
+            int bi = INT_MAX;
+            for (int a = tid; a < n; a += SPT)
+                if (!chosen[a] && better(d[a], a, bv, bi)) { bv = d[a]; bi = a; }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double v2 = __shfl_xor(bv, off);
+                const int i2 = __shfl_xor(bi, off);
+                if (better(v2, i2, bv, bi)) { bv = v2; bi = i2; }
+            }
+            if (lane == 0) { wv[wave] = bv; wi[wave] = bi; }
+            __syncthreads();
+            if (tid == 0) {
+                for (int w = 1; w < SPT / 64; ++w)
+                    if (better(wv[w], wi[w], bv, bi)) { bv = wv[w]; bi = wi[w]; }
+                if (k == 0) st_max = bv;
+                if (!(bv > tau)) {
+                    s_stop = 1;
+                    st_reject = bv;
+                } else {
+                    chosen[bi] = 1;
+                    pivl[k] = bi;
+                    st_last = bv;
+                }
+                s_v = bv;
+                s_p = bi;
+            }
+            __syncthreads();
+            if (s_stop) break;
+            const int p = s_p;
+            const double rpp = sqrt(s_v);
+            for (int a = tid; a < n; a += SPT) {
+                double val;
+                if (a == p) {
+                    val = rpp;
+                } else if (chosen[a]) {
+                    val = 0.0;
+                } else {
+                    double acc = Sc[(int64_t)p * lsc + a];
+                    for (int q = 0; q < t; ++q) acc -= P[q][p] * P[q][a];
+                    val = acc / rpp;
+                    d[a] -= val * val;
+                }
+                P[t][a] = val;
+            }
+            ++k;
+            __syncthreads();
+        }
+        // this panel's rows of R (original column order)
+        for (int64_t e = tid; e < (int64_t)t * n; e += SPT) {
+            const int q = (int)(e / n), a = (int)(e % n);
+            Rorig[(int64_t)(k0 + q) * ldr + a] = P[q][a];
+        }
+        if (s_stop || k >= n) break;
+        // S[a][b] -= sum_t P[t][a] P[t][b], in 4 x 4 blocks per thread (two
+        // LDS reads per four products).  Entries of chosen positions are
+        // updated too and never read again.
+        const int n4 = (n + 3) >> 2;
+        for (int blk = tid; blk < n4 * n4; blk += SPT) {
+            const int a0 = (blk / n4) * 4, b0 = (blk % n4) * 4;
+            double acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = (a0 + i < n && b0 + j < n) ? Sc[(int64_t)(a0 + i) * lsc + b0 + j] : 0.0;
+            for (int q = 0; q < t; ++q) {
+                double pa[4], pb[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    pa[i] = P[q][a0 + i];
+                    pb[i] = P[q][b0 + i];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] -= pa[i] * pb[j];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (a0 + i < n && b0 + j < n) S[(int64_t)(a0 + i) * n + b0 + j] = acc[i][j];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    for (int q = tid; q < k; q += SPT) piv[q] = pivl[q];
+    if (tid == 0) {
+        state[ST_RANK] = k;
+        pstats[PS_LAST] = st_last;
+        pstats[PS_REJECT] = st_reject;
+        pstats[PS_MAX] = st_max;
+        // the rejected positions follow the accepted pivots, in index order
+        int j = k;
+        for (int a = 0; a < n; ++a)
+            if (!chosen[a]) piv[j++] = a;
+    }
+}
+
 __global__ void gather_kernel(int64_t r, int64_t n, const double* __restrict__ Rorig, int64_t ldro,
                               const int* __restrict__ piv, double* __restrict__ R, int64_t ldr) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -452,6 +605,27 @@ __global__ void gather_kernel(int64_t r, int64_t n, const double* __restrict__ R
 }
 
 }  // namespace
+
+// read back the rank and statistics, then R's columns into pivot order
+static int64_t finish_pivoted_cholesky(hipStream_t s, int64_t n, const int32_t* piv,
+                                       const double* Rorig, const int* state, const double* pstats,
+                                       double** R_out, double* stats_out, elm_factor* f) {
+    int hstate[ST_N];
+    ELM_HIP_TRY(hipMemcpyAsync(hstate, state, sizeof(hstate), hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipMemcpyAsync(stats_out, pstats, PS_N * sizeof(double), hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipStreamSynchronize(s));
+    if (hstate[ST_BAD]) throw Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
+    const int64_t r = hstate[ST_RANK];
+    double* R = nullptr;
+    if (r > 0) {
+        R = (double*)factor_alloc(f, "R", (size_t)r * n * sizeof(double));
+        gather_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)r), 256, 0, s>>>(r, n, Rorig, n, piv,
+                                                                                R, n);
+        ELM_LAUNCH_CHECK();
+    }
+    *R_out = R;
+    return r;
+}
 
 int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double tau,
                          int32_t* piv, double** R_out, double* stats_out, Workspace& ws,
@@ -478,6 +652,12 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
     ELM_LAUNCH_CHECK();
     fill_kernel<<<1024, 256, 0, s>>>(Rorig, n * n, 0.0);
     ELM_LAUNCH_CHECK();
+    if (n <= SMALL_N) {
+        double* Sw = (double*)ws.get("pc_S0", (size_t)n * n * sizeof(double));
+        pchol_small_kernel<<<1, SPT, 0, s>>>((int)n, M, ldm, Sw, tau, piv, Rorig, n, state, pstats);
+        ELM_LAUNCH_CHECK();
+        return finish_pivoted_cholesky(s, n, piv, Rorig, state, pstats, R_out, stats_out, f);
+    }
 
     const double* Scur = M;
     int64_t lds = ldm;
@@ -486,8 +666,8 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
     while (ps < n) {
         const int nbp = (int)(n_rem < NB ? n_rem : NB);
         const int nblk = (int)cdiv(n_rem, PT);
-        panel_start_kernel<<<nblk, PT, 0, s>>>(n_rem, Scur, lds, d, chosen, rem0, rem1,
-                                                 part[ps & 1], state);
+        panel_start_kernel<<<nblk, PT, 0, s>>>(n_rem, Scur, lds, d, chosen, rem0, rem1, part[ps & 1],
+                                                 state);
         ELM_LAUNCH_CHECK();
         int nparts = nblk;
         for (int t = 0; t < nbp; ++t) {
@@ -532,22 +712,7 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
     }
     finalize_kernel<<<1, 1024, 0, s>>>(n, chosen, rem0, rem1, piv, state);
     ELM_LAUNCH_CHECK();
-
-    int hstate[ST_N];
-    ELM_HIP_TRY(hipMemcpyAsync(hstate, state, sizeof(hstate), hipMemcpyDeviceToHost, s));
-    ELM_HIP_TRY(hipMemcpyAsync(stats_out, pstats, PS_N * sizeof(double), hipMemcpyDeviceToHost, s));
-    ELM_HIP_TRY(hipStreamSynchronize(s));
-    if (hstate[ST_BAD]) throw Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
-    const int64_t r = hstate[ST_RANK];
-    double* R = nullptr;
-    if (r > 0) {
-        R = (double*)factor_alloc(f, "R", (size_t)r * n * sizeof(double));
-        gather_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)r), 256, 0, s>>>(r, n, Rorig, n, piv,
-                                                                                R, n);
-        ELM_LAUNCH_CHECK();
-    }
-    *R_out = R;
-    return r;
+    return finish_pivoted_cholesky(s, n, piv, Rorig, state, pstats, R_out, stats_out, f);
 }
 
 void launch_fill(hipStream_t s, double* p, int64_t count, double v) {
