@@ -282,15 +282,24 @@ typedef struct {
 
 /* elm_train on each of `count` independent problems (e.g. a sweep over
  * hidden-layer sizes or seeds), with one precision form and tolerances for
- * all.  The trainings run concurrently on worker streams owned by the handle
- * (created on first use), assigned longest-first by the Gram's cost; they
- * start after the work already queued on the handle's stream, and that stream
- * continues only after all of them.  The call returns when every training has
- * finished.  infos and statuses (host arrays of `count`, may be NULL) receive
- * each training's report and status; the return value is ELM_OK or the status
- * of the first failed problem (by index), whose message elm_last_error gives.
- * Errors: INVALID_ARG / SHAPE for a malformed problem (nothing runs); those of
- * elm_train per problem. */
+ * all, and the same results as elm_train gives each problem alone.  The work
+ * runs in three phases: (1) the hidden layer, Z = H^T T and the Gram of every
+ * problem, on worker streams owned by the handle (created on first use),
+ * longest first by the Gram's cost; (2) the pivoted Cholesky rank decisions
+ * of all problems together on the handle's stream, one launch per pivot step
+ * for the whole group (problems of order <= 512 take one workgroup each);
+ * (3) the factor's dense tail, beta and refinement, on the worker streams.  A
+ * problem whose low-precision guard fails is trained again alone from the
+ * next precision (as elm_train does).  Problems are grouped so that the
+ * Grams and factorisation scratch of a group (about 32 n^2 bytes per problem,
+ * n = min(N, L)) stay within 16 GiB.  The work starts after what is already
+ * queued on the handle's stream, and that stream continues only after all of
+ * it; the call returns when every training has finished.  infos and statuses
+ * (host arrays of `count`, may be NULL) receive each training's report and
+ * status; the return value is ELM_OK or the status of the first failed
+ * problem (by index), whose message elm_last_error gives.
+ * Errors: INVALID_ARG / SHAPE for a malformed problem or argument (nothing
+ * runs); those of elm_train per problem. */
 elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* probs,
                              elm_dtype gram_dt, double tau_rel, double ir_tol,
                              int32_t ir_max_iter, elm_train_info* infos,

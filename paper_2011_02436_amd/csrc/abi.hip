@@ -506,7 +506,15 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
         info->iterations = it;
         info->ne_residual = res;
     }
-    if (res > ir_tol) result = ELM_ERR_NO_CONVERGENCE;
+    if (res > ir_tol) {
+        result = ELM_ERR_NO_CONVERGENCE;
+        char msg[160];
+        std::snprintf(msg, sizeof(msg),
+                      "refinement stopped after %d iterations at relative normal-equation "
+                      "residual %.3e > ir_tol %.3e",
+                      it, res, ir_tol);
+        h->last_error = msg;
+    }
     return result;
 }
 
@@ -672,6 +680,10 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
         REQUIRE(count == 0 || probs, ELM_ERR_INVALID_ARG, "probs must be non-null");
         REQUIRE(gram_dt == ELM_F64 || gram_dt == ELM_F32 || gram_dt == ELM_BF16 || gram_dt == ELM_F16,
                 ELM_ERR_INVALID_ARG, "unknown gram dtype");
+        REQUIRE(tau_rel < 1.0 && !std::isnan(tau_rel), ELM_ERR_INVALID_ARG, "tau_rel must be < 1");
+        REQUIRE(ir_tol >= 0.0 && ir_tol < 1.0, ELM_ERR_INVALID_ARG, "ir_tol must be in [0, 1)");
+        REQUIRE(ir_max_iter >= 0 && ir_max_iter <= 31, ELM_ERR_INVALID_ARG,
+                "ir_max_iter must be in [0, 31]");
         for (int32_t e = 0; e < count; ++e) {
             const elm_problem& p = probs[e];
             const std::string at = "problem " + std::to_string(e) + ": ";
@@ -706,42 +718,277 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
         ELM_HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         ELM_HIP_TRY(hipEventRecord(ev, h->stream));
         for (int w = 0; w < nw; ++w) ELM_HIP_TRY(hipStreamWaitEvent(h->workers[w]->stream, ev, 0));
-        // longest-processing-time assignment by the Gram's cost N n min(N, L)
-        std::vector<int32_t> order(count);
-        for (int32_t e = 0; e < count; ++e) order[e] = e;
+        // workers take problems longest-first by the Gram's cost N n min(N, L)
         auto cost = [&](int32_t e) {
             const double n = (double)std::min(probs[e].N, probs[e].L);
             return (double)std::max(probs[e].N, probs[e].L) * n * n + 2.0e5 * n;
         };
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
-        std::vector<std::vector<int32_t>> lists(nw);
-        std::vector<double> load(nw, 0.0);
-        for (int32_t e : order) {
-            const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            lists[w].push_back(e);
-            load[w] += cost(e);
-        }
         st_all.assign(count, ELM_OK);
         msg_all.assign(count, std::string());
         std::vector<elm_train_info> info_all(count);
+        for (auto& ti : info_all) std::memset(&ti, 0, sizeof(ti));
         // stage timers of the workers follow the handle's (summed into it below)
         for (int w = 0; w < nw; ++w) h->workers[w]->prof.on = h->prof.on;
-        std::vector<std::thread> threads;
-        for (int w = 0; w < nw; ++w) {
-            threads.emplace_back([&, w] {
-                elm_handle* wh = h->workers[w];
-                for (int32_t e : lists[w]) {
-                    const elm_problem& p = probs[e];
-                    std::memset(&info_all[e], 0, sizeof(elm_train_info));
-                    st_all[e] = elm_train(wh, p.N, p.d, p.L, p.m, p.X, p.ldx, p.W, p.ldw, p.b, p.T, p.ldt,
-                                          gram_dt, p.H64, p.ldh64, nullptr, 0, tau_rel, ir_tol,
-                                          ir_max_iter, p.beta, p.ldbeta, nullptr, 0, nullptr,
-                                          &info_all[e], nullptr);
-                    if (st_all[e] != ELM_OK) msg_all[e] = wh->last_error;
+
+        // Per problem: the Gram's order and precision, and where the first
+        // phase leaves the Gram, Z = H^T T, ||Z||^2 and the largest diagonal.
+        struct Item {
+            elm_dtype gdt;
+            int64_t n, kc;
+            bool transposed, fuse_z, ok;
+            double *M, *Z, *nrm;
+        };
+        std::vector<Item> items(count);
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        // Problems run in groups whose Grams and factorisation scratch
+        // (about 4 n^2 doubles each) fit in BATCH_GROUP_BYTES.
+        std::vector<std::vector<int32_t>> groups(1);
+        size_t gbytes = 0;
+        for (int32_t e = 0; e < count; ++e) {
+            const elm_problem& p = probs[e];
+            Item& it = items[e];
+            it.transposed = p.N < p.L;
+            it.n = it.transposed ? p.N : p.L;
+            it.gdt = it.transposed ? ELM_F64 : gram_dt;
+            it.fuse_z = p.m <= elm::HIDDEN_Z_MAX_M;
+            it.kc = 0;
+            it.ok = true;
+            const size_t need = 4 * al((size_t)it.n * it.n * sizeof(double)) +
+                                (size_t)256 * it.n * sizeof(double);
+            if (!groups.back().empty() && gbytes + need > elm::BATCH_GROUP_BYTES) {
+                groups.emplace_back();
+                gbytes = 0;
+            }
+            groups.back().push_back(e);
+            gbytes += need;
+        }
+        hipEvent_t ev2 = nullptr;
+        ELM_HIP_TRY(hipEventCreateWithFlags(&ev2, hipEventDisableTiming));
+        struct EvGuard {
+            hipEvent_t e;
+            ~EvGuard() { (void)hipEventDestroy(e); }
+        } ev2_guard{ev2};
+        // runs body(worker handle, problem) for every problem of the group on
+        // the workers (longest first), recording failures per problem
+        auto run_workers = [&](const std::vector<int32_t>& grp, auto&& body) {
+            std::vector<std::vector<int32_t>> lists(nw);
+            std::vector<double> load(nw, 0.0);
+            std::vector<int32_t> ord(grp);
+            std::stable_sort(ord.begin(), ord.end(),
+                             [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+            for (int32_t e : ord) {
+                if (!items[e].ok) continue;
+                const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                lists[w].push_back(e);
+                load[w] += cost(e);
+            }
+            std::vector<std::thread> threads;
+            for (int w = 0; w < nw; ++w) {
+                threads.emplace_back([&, w] {
+                    elm_handle* wh = h->workers[w];
+                    for (int32_t e : lists[w]) {
+                        try {
+                            body(wh, e);
+                        } catch (const elm::Error& err) {
+                            st_all[e] = err.st;
+                            msg_all[e] = err.msg;
+                            items[e].ok = false;
+                        } catch (const std::bad_alloc&) {
+                            st_all[e] = ELM_ERR_ALLOC;
+                            msg_all[e] = "host allocation failed";
+                            items[e].ok = false;
+                        } catch (const std::exception& x) {
+                            st_all[e] = ELM_ERR_HIP;
+                            msg_all[e] = x.what();
+                            items[e].ok = false;
+                        }
+                    }
+                });
+            }
+            for (auto& t : threads) t.join();
+        };
+        // stream order: each worker waits for `from`, or `from` for every worker
+        auto workers_wait = [&](hipStream_t from) {
+            ELM_HIP_TRY(hipEventRecord(ev2, from));
+            for (int w = 0; w < nw; ++w) ELM_HIP_TRY(hipStreamWaitEvent(h->workers[w]->stream, ev2, 0));
+        };
+        auto wait_workers = [&](hipStream_t into) {
+            for (int w = 0; w < nw; ++w) {
+                ELM_HIP_TRY(hipEventRecord(ev2, h->workers[w]->stream));
+                ELM_HIP_TRY(hipStreamWaitEvent(into, ev2, 0));
+            }
+        };
+
+        for (const std::vector<int32_t>& grp : groups) {
+            // phase 1 (workers): H, Z = H^T T and the Gram of every problem
+            size_t mb = 0, zb = 0;
+            for (int32_t e : grp) {
+                mb += al((size_t)items[e].n * items[e].n * sizeof(double));
+                zb += al((size_t)probs[e].L * probs[e].m * sizeof(double));
+            }
+            char* Marena = (char*)h->ws.get("bt_M", mb);
+            char* Zarena = (char*)h->ws.get("bt_Z", zb);
+            double* nrms = (double*)h->ws.get("bt_nrm", grp.size() * 2 * sizeof(double));
+            double* dmaxs = (double*)h->ws.get("bt_dmax", grp.size() * sizeof(double));
+            {
+                size_t mo = 0, zo = 0;
+                for (size_t i = 0; i < grp.size(); ++i) {
+                    Item& it = items[grp[i]];
+                    it.M = (double*)(Marena + mo);
+                    it.Z = (double*)(Zarena + zo);
+                    it.nrm = nrms + 2 * i;
+                    mo += al((size_t)it.n * it.n * sizeof(double));
+                    zo += al((size_t)probs[grp[i]].L * probs[grp[i]].m * sizeof(double));
                 }
+            }
+            std::vector<int32_t> slot(count, -1);
+            for (size_t i = 0; i < grp.size(); ++i) slot[grp[i]] = (int32_t)i;
+            run_workers(grp, [&](elm_handle* wh, int32_t e) {
+                const elm_problem& p = probs[e];
+                Item& it = items[e];
+                hipStream_t ws = wh->stream;
+                void* lp = nullptr;
+                if (it.gdt != ELM_F64)
+                    lp = wh->ws.get("train_lp", (size_t)p.L * p.N * elm::dtype_size(it.gdt));
+                double* Zp = nullptr;
+                if (it.fuse_z)
+                    Zp = (double*)wh->ws.get("train_zpart", (size_t)elm::hidden_row_tiles(p.N) * p.L *
+                                                                p.m * sizeof(double));
+                {
+                    elm::StageScope sc(&wh->prof, ELM_STAGE_HIDDEN, ws);
+                    elm::launch_hidden(ws, ELM_F64, p.N, p.d, p.L, p.X, p.ldx, p.W, p.ldw, p.b, p.H64,
+                                       p.ldh64, lp, p.N, it.gdt, p.T, p.ldt, p.m, Zp);
+                }
+                if (it.fuse_z) {
+                    elm::StageScope sc(&wh->prof, ELM_STAGE_RHS, ws);
+                    elm::launch_partial_sum(ws, p.L, p.m, elm::hidden_row_tiles(p.N), Zp, it.Z, p.m,
+                                            it.nrm, wh->ws);
+                }
+                if (it.gdt == ELM_F64) {
+                    if (it.transposed)
+                        elm::launch_gram_f64_rows(ws, p.N, p.L, p.H64, p.ldh64, it.M, it.n, wh->ws);
+                    else
+                        elm::launch_gram_f64_cols(ws, p.N, p.L, p.H64, p.ldh64, it.M, it.n, wh->ws);
+                } else {
+                    it.kc = elm::launch_gram_lp_nodes(ws, it.gdt, p.N, p.L, lp, p.N, it.M, it.n, wh->ws);
+                }
+                elm::launch_diag_max(ws, it.n, it.M, it.n, dmaxs + slot[e]);
+            });
+            wait_workers(h->stream);
+
+            // phase 2 (handle's stream): all rank decisions in shared launches
+            std::vector<double> hdmax(grp.size());
+            ELM_HIP_TRY(hipMemcpyAsync(hdmax.data(), dmaxs, grp.size() * sizeof(double),
+                                       hipMemcpyDeviceToHost, h->stream));
+            ELM_HIP_TRY(hipStreamSynchronize(h->stream));
+            std::vector<elm::PcholProblem> pc;
+            std::vector<int32_t> pc_of(count, -1);
+            for (size_t i = 0; i < grp.size(); ++i) {
+                const int32_t e = grp[i];
+                Item& it = items[e];
+                if (!it.ok) continue;
+                if (!std::isfinite(hdmax[i])) {
+                    st_all[e] = ELM_ERR_NOT_PSD;
+                    msg_all[e] = "Gram has a non-finite diagonal entry";
+                    it.ok = false;
+                    continue;
+                }
+                // the threshold of elm_rank_factor
+                const int64_t K = it.transposed ? probs[e].L : probs[e].N;
+                elm::PcholProblem q;
+                q.n = it.n;
+                q.M = it.M;
+                q.ldm = it.n;
+                q.tau = (tau_rel > 0 ? tau_rel : 16.0 * (double)(it.n + K) * std::ldexp(1.0, -53)) *
+                        hdmax[i];
+                pc_of[e] = (int32_t)pc.size();
+                pc.push_back(q);
+            }
+            {
+                elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
+                elm::pivoted_cholesky_grouped(h->stream, pc, h->ws);
+            }
+            workers_wait(h->stream);
+
+            // phase 3 (workers): factor tail, beta and refinement
+            run_workers(grp, [&](elm_handle* wh, int32_t e) {
+                const elm_problem& p = probs[e];
+                Item& it = items[e];
+                const elm::PcholProblem& q = pc[pc_of[e]];
+                hipStream_t ws = wh->stream;
+                elm_train_info& ti = info_all[e];
+                if (q.bad) throw elm::Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
+                elm_factor* f = new elm_factor();
+                struct FactorGuard {
+                    elm_factor* f;
+                    ~FactorGuard() {
+                        elm::free_factor_buffers(f);
+                        delete f;
+                    }
+                } fg{f};
+                f->N = p.N;
+                f->L = p.L;
+                f->n = it.n;
+                f->transposed = it.transposed;
+                f->device = h->device;
+                f->pool = &wh->ws;
+                f->gram_dtype = it.gdt;
+                f->tau = q.tau;
+                f->r = q.rank;
+                f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)it.n * sizeof(int32_t));
+                ELM_HIP_TRY(hipMemcpyAsync(f->piv, q.piv, (size_t)it.n * sizeof(int32_t),
+                                           hipMemcpyDeviceToDevice, ws));
+                if (f->r > 0) {
+                    f->R = (double*)elm::factor_alloc(f, "R", (size_t)f->r * it.n * sizeof(double));
+                    elm::launch_gather_rows(ws, f->r, it.n, q.Rorig, it.n, q.piv, f->R, it.n);
+                }
+                const double hd = hdmax[slot[e]];
+                f->last_pivot = q.stats[0];
+                f->first_rejected = q.stats[1];
+                f->max_diag = hd;
+                f->noise_floor =
+                    elm::schur_noise_floor(it.gdt, it.n, p.N > p.L ? p.N : p.L, it.kc) * hd;
+                f->reliable = (f->r == 0 || f->last_pivot >= 2.0 * f->noise_floor) &&
+                              (f->r == it.n || f->first_rejected >= -2.0 * f->noise_floor);
+                elm::check_status(wh, elm_factor_get_info(f, &ti.factor));
+                ti.gram_dtype = it.gdt;
+                const bool can_escalate = it.gdt != ELM_F64;
+                int guard = 0;
+                if (can_escalate && !f->reliable) {
+                    guard = 1;
+                } else {
+                    {
+                        elm::StageScope sc(&wh->prof, ELM_STAGE_FACTOR, ws);
+                        elm::build_factor_tail(ws, f, wh->ws);
+                    }
+                    if (it.fuse_z) {
+                        double* Z = (double*)wh->ws.get("ps_Z", (size_t)p.L * p.m * sizeof(double));
+                        double* nrm = (double*)wh->ws.get("ps_nrm", 2 * sizeof(double));
+                        ELM_HIP_TRY(hipMemcpyAsync(Z, it.Z, (size_t)p.L * p.m * sizeof(double),
+                                                   hipMemcpyDeviceToDevice, ws));
+                        ELM_HIP_TRY(hipMemcpyAsync(nrm, it.nrm, sizeof(double), hipMemcpyDeviceToDevice,
+                                                   ws));
+                    }
+                    const elm_status ss =
+                        elm::pinv_solve_impl(wh, f, p.m, p.T, p.ldt, p.H64, p.ldh64, ir_tol, ir_max_iter,
+                                             p.beta, p.ldbeta, &ti.solve, it.fuse_z);
+                    if (ss == ELM_OK) return;
+                    if (ss != ELM_ERR_NO_CONVERGENCE || !can_escalate) elm::check_status(wh, ss);
+                    guard = 2;
+                }
+                // a guard failed: train this problem again from a higher-precision Gram
+                elm_train_info t2;
+                std::memset(&t2, 0, sizeof(t2));
+                const elm_status s2 =
+                    elm_train(wh, p.N, p.d, p.L, p.m, p.X, p.ldx, p.W, p.ldw, p.b, p.T, p.ldt,
+                              elm::next_gram_dtype(it.gdt), p.H64, p.ldh64, nullptr, 0, tau_rel, ir_tol,
+                              ir_max_iter, p.beta, p.ldbeta, nullptr, 0, nullptr, &t2, nullptr);
+                t2.escalations += 1;
+                if (!t2.guard) t2.guard = guard;
+                ti = t2;
+                elm::check_status(wh, s2);
             });
         }
-        for (auto& t : threads) t.join();
         if (h->prof.on) {
             for (int w = 0; w < nw; ++w) {
                 elm::Profiler& wp = h->workers[w]->prof;

@@ -116,6 +116,9 @@ namespace elm {
 // Independent trainings run concurrently on this many streams (the HIP
 // runtime's default number of hardware queues per process).
 constexpr int BATCH_WORKERS = 4;
+// device memory for the Grams and factorisation scratch of one group of a
+// batched training (larger batches run group after group)
+constexpr size_t BATCH_GROUP_BYTES = (size_t)16 << 30;
 }  // namespace elm
 
 struct elm_handle {
@@ -215,6 +218,31 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
                          elm_factor* f);
 void launch_fill(hipStream_t s, double* p, int64_t count, double v);
 
+// One factorisation of a group run by pivoted_cholesky_grouped.  In: n, the
+// Gram M (n x n FP64, full symmetric, ld ldm) and the threshold tau.  Out:
+// rank, stats (as stats_out above), bad (a non-finite Gram diagonal), piv
+// (device, n entries: accepted pivots, then the rejected positions) and
+// Rorig (device, n x n, ld n: row k of R with its columns by original
+// index); both stay valid until the workspace's next grouped call.
+struct PcholProblem {
+    int64_t n = 0;
+    const double* M = nullptr;
+    int64_t ldm = 0;
+    double tau = 0.0;
+    int64_t rank = 0;
+    double stats[3] = {0, 0, 0};
+    bool bad = false;
+    const int32_t* piv = nullptr;
+    const double* Rorig = nullptr;
+};
+// Factorises every problem of the group with the same pivot rule and the
+// same arithmetic as pivoted_cholesky, in shared launches (one per pivot
+// step for all problems together); synchronises the stream once.
+void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, Workspace& ws);
+// R (r x n, ld ldr) = the first r rows of Rorig with columns in pivot order
+void launch_gather_rows(hipStream_t s, int64_t r, int64_t n, const double* Rorig, int64_t ldro,
+                        const int32_t* piv, double* R, int64_t ldr);
+
 // Relative rounding-noise scale of the Schur diagonals of a Gram formed from
 // H rounded to `dt` with `kc` products per FP32 partial sum (kc = 0: FP64
 // accumulation), for a Gram of order n over K samples.  A column that is an
@@ -266,6 +294,6 @@ void launch_predict(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L
                     const double* beta, int64_t ldbeta, void* Y, int64_t ldy, int32_t* labels,
                     Workspace& ws);
 
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace elm

@@ -24,7 +24,9 @@
 // waiting for the rank.
 #include "elm_internal.h"
 
+#include <algorithm>
 #include <climits>
+#include <cstring>
 #include <cmath>
 
 namespace elm {
@@ -64,10 +66,10 @@ __device__ inline void wave_argmax(Part& b) {
     }
 }
 
-// block-wide best, written to out[blockIdx.x] by thread 0.  `better` is a
+// block-wide best, written to out[bx] by thread 0.  `better` is a
 // strict total order on (v, o) with distinct original indices, so the result
 // does not depend on the combination order.
-__device__ inline void block_argmax_store(Part b, Part* __restrict__ out) {
+__device__ inline void block_argmax_store(Part b, Part* __restrict__ out, int bx) {
     __shared__ Part wbest[PT / 64];
     wave_argmax(b);
     if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = b;
@@ -76,7 +78,7 @@ __device__ inline void block_argmax_store(Part b, Part* __restrict__ out) {
         Part r = wbest[0];
 #pragma unroll
         for (int w = 1; w < PT / 64; ++w) part_take(r, wbest[w]);
-        out[blockIdx.x] = r;
+        out[bx] = r;
     }
 }
 
@@ -84,8 +86,7 @@ __device__ inline void block_argmax_store(Part b, Part* __restrict__ out) {
 // (-inf when every position is accepted), largest Gram diagonal
 enum { PS_LAST = 0, PS_REJECT = 1, PS_MAX = 2, PS_N = 3 };
 
-__global__ void init_kernel(int64_t n, int* rem0, int* state, double* pstats) {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void init_body(int64_t a, int64_t n, int* rem0, int* state, double* pstats) {
     if (a < n) rem0[a] = (int)a;
     if (a < ST_N) state[a] = 0;
     if (a == 0) {
@@ -101,14 +102,13 @@ __global__ void fill_kernel(double* p, int64_t count, double v) {
         p[i] = v;
 }
 
-__global__ __launch_bounds__(PT) void panel_start_kernel(int64_t n_rem, const double* __restrict__ S,
-                                                         int64_t lds, double* __restrict__ d,
-                                                         int* __restrict__ chosen, const int* rem0,
-                                                         const int* rem1, Part* __restrict__ out,
-                                                         int* state) {
+__device__ inline void panel_start_body(int bx, int64_t n_rem, const double* __restrict__ S,
+                                        int64_t lds, double* __restrict__ d,
+                                        int* __restrict__ chosen, const int* rem0, const int* rem1,
+                                        Part* __restrict__ out, int* state) {
     if (state[ST_DONE]) return;
     const int* rem = state[ST_CUR] ? rem1 : rem0;
-    const int64_t a = (int64_t)blockIdx.x * PT + threadIdx.x;
+    const int64_t a = (int64_t)bx * PT + threadIdx.x;
     Part b = part_none();
     if (a < n_rem) {
         const double x = S[a * lds + a];
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(PT) void panel_start_kernel(int64_t n_rem, const do
         if (!isfinite(x)) state[ST_BAD] = 1;
         b = Part{x, rem[a], (int)a};
     }
-    block_argmax_store(b, out);
+    block_argmax_store(b, out, bx);
 }
 
 // One pivot.  G lanes share each remaining position a; lane group g holds
@@ -130,20 +130,18 @@ __global__ __launch_bounds__(PT) void panel_start_kernel(int64_t n_rem, const do
 // order of operations is the same for every position: identical columns of
 // the Gram stay bitwise identical.
 template <int G, int R>
-__global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_rem,
-                                                  const double* __restrict__ S, int64_t lds,
-                                                  double* __restrict__ P, int64_t ldp,
-                                                  double* __restrict__ d, int* __restrict__ chosen,
-                                                  const int* rem0, const int* rem1,
-                                                  const Part* __restrict__ in, int nparts,
-                                                  Part* __restrict__ out, int* state, double tau,
-                                                  int* __restrict__ piv, double* __restrict__ pstats) {
+__device__ inline void step_body(int bx, int64_t k, int t, int64_t n_rem,
+                                 const double* __restrict__ S, int64_t lds, double* __restrict__ P,
+                                 int64_t ldp, double* __restrict__ d, int* __restrict__ chosen,
+                                 const int* rem0, const int* rem1, const Part* __restrict__ in,
+                                 int nparts, Part* __restrict__ out, int* state, double tau,
+                                 int* __restrict__ piv, double* __restrict__ pstats) {
     constexpr int CPW = 64 / G;  // positions per wave
     constexpr int CPB = CPW * (PT / 64);
     constexpr int PIN = 8;  // argmax partials per lane loaded in the first batch
     const int lane = threadIdx.x & 63;
     const int g = lane / CPW;
-    const int64_t a = (int64_t)blockIdx.x * CPB + (threadIdx.x >> 6) * CPW + lane % CPW;
+    const int64_t a = (int64_t)bx * CPB + (threadIdx.x >> 6) * CPW + lane % CPW;
     const int64_t ac = a < n_rem ? a : n_rem - 1;  // in-bounds twin for the batched loads
     const int q0 = R * g;
 
@@ -173,7 +171,7 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
     const int bo = __builtin_amdgcn_readfirstlane(best.o);
     const double bv = best.v;
     if (!(bv > tau)) {  // largest remaining Schur diagonal at or below tau: rank = k
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (bx == 0 && threadIdx.x == 0) {
             state[ST_RANK] = (int)k;
             state[ST_NREM] = (int)n_rem;
             state[ST_DONE] = 1;
@@ -214,8 +212,8 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
             }
         }
     }
-    block_argmax_store(cand, out);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    block_argmax_store(cand, out, bx);
+    if (bx == 0 && threadIdx.x == 0) {
         piv[k] = bo;
         pstats[PS_LAST] = bv;  // accepted pivots are non-increasing
         if (k == 0) pstats[PS_MAX] = bv;
@@ -223,9 +221,10 @@ __global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_re
 }
 
 // panel rows -> R, columns by original index
-__global__ void scatter_kernel(int64_t ps, int nbp, int64_t n_rem, const double* __restrict__ P,
-                               int64_t ldp, const int* rem0, const int* rem1, double* __restrict__ Rorig,
-                               int64_t ldr, const int* state) {
+__device__ inline void scatter_body(int bx, int64_t t, int64_t ps, int nbp, int64_t n_rem,
+                                    const double* __restrict__ P, int64_t ldp, const int* rem0,
+                                    const int* rem1, double* __restrict__ Rorig, int64_t ldr,
+                                    const int* state) {
     const int* rem = state[ST_CUR] ? rem1 : rem0;
     int64_t t_act = nbp;
     if (state[ST_DONE]) {
@@ -233,9 +232,8 @@ __global__ void scatter_kernel(int64_t ps, int nbp, int64_t n_rem, const double*
         if (t_act < 0) t_act = 0;
         if (t_act > nbp) t_act = nbp;
     }
-    const int64_t t = blockIdx.y;
     if (t >= t_act) return;
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t a = (int64_t)bx * blockDim.x + threadIdx.x;
     if (a < n_rem) Rorig[(ps + t) * ldr + rem[a]] = P[t * ldp + a];
 }
 
@@ -275,9 +273,8 @@ __device__ int64_t block_compact(int64_t n, const int* __restrict__ flag, const 
     return base;
 }
 
-__global__ __launch_bounds__(1024) void compact_kernel(int64_t n_rem, const int* __restrict__ chosen,
-                                                       int* rem0, int* rem1, int* __restrict__ map,
-                                                       int* state) {
+__device__ inline void compact_body(int64_t n_rem, const int* __restrict__ chosen, int* rem0,
+                                    int* rem1, int* __restrict__ map, int* state) {
     if (state[ST_DONE]) return;
     const int cur = state[ST_CUR];
     const int* in = cur ? rem1 : rem0;
@@ -288,10 +285,8 @@ __global__ __launch_bounds__(1024) void compact_kernel(int64_t n_rem, const int*
 }
 
 // tail of the pivot order: the rejected indices, in their current order
-__global__ __launch_bounds__(1024) void finalize_kernel(int64_t n,
-                                                        const int* __restrict__ chosen,
-                                                        const int* rem0, const int* rem1,
-                                                        int* __restrict__ piv, int* state) {
+__device__ inline void finalize_body(int64_t n, const int* __restrict__ chosen, const int* rem0,
+                                     const int* rem1, int* __restrict__ piv, int* state) {
     if (!state[ST_DONE]) {
         if (threadIdx.x == 0) state[ST_RANK] = (int)n;
         return;
@@ -306,12 +301,10 @@ __global__ __launch_bounds__(1024) void finalize_kernel(int64_t n,
 // tiles, mirrored.  4 waves in 2 x 2, each (TT/2)^2 as 16 x 16 FP64 MFMA
 // blocks; the panel rows are gathered through the compaction map into
 // k-major LDS tiles, double-buffered through registers.
-__global__ __launch_bounds__(256, 2) void trailing_kernel(int64_t n_new, const double* __restrict__ S,
-                                                          int64_t lds, double* __restrict__ Sn,
-                                                          int64_t ldsn, const double* __restrict__ P,
-                                                          int64_t ldp, int nbp,
-                                                          const int* __restrict__ map,
-                                                          const int* state) {
+__device__ inline void trailing_body(int bx, int64_t n_new, const double* __restrict__ S,
+                                     int64_t lds, double* __restrict__ Sn, int64_t ldsn,
+                                     const double* __restrict__ P, int64_t ldp, int nbp,
+                                     const int* __restrict__ map, const int* state) {
     if (state[ST_DONE]) return;
     constexpr int BK = 16;
     constexpr int PP = TT + 16;           // LDS pitch: 4 k rows of an operand read on disjoint banks
@@ -325,7 +318,7 @@ __global__ __launch_bounds__(256, 2) void trailing_kernel(int64_t n_new, const d
     __shared__ int qa[TT], qb[TT];
 
     // tile index -> (bi <= bj)
-    const int64_t tix = blockIdx.x;
+    const int64_t tix = bx;
     int64_t c = (int64_t)((sqrt(8.0 * (double)tix + 1.0) - 1.0) * 0.5);
     while (c * (c + 1) / 2 > tix) --c;
     while ((c + 1) * (c + 2) / 2 <= tix) ++c;
@@ -457,11 +450,10 @@ constexpr int SMALL_N = 512;
 constexpr int SNB = 16;
 constexpr int SPT = 1024;
 
-__global__ __launch_bounds__(SPT) void pchol_small_kernel(int n, const double* __restrict__ M,
-                                                          int64_t ldm, double* __restrict__ S,
-                                                          double tau, int32_t* __restrict__ piv,
-                                                          double* __restrict__ Rorig, int64_t ldr,
-                                                          int* state, double* pstats) {
+__device__ inline void pchol_small_body(int n, const double* __restrict__ M, int64_t ldm,
+                                        double* __restrict__ S, double tau, int32_t* __restrict__ piv,
+                                        double* __restrict__ Rorig, int64_t ldr, int* state,
+                                        double* pstats) {
     // No global store happens between the barriers of a pivot step (a
     // barrier waits for the block's outstanding stores): R rows, pivots and
     // statistics are written out per panel or at the end.
@@ -597,6 +589,171 @@ __global__ __launch_bounds__(SPT) void pchol_small_kernel(int n, const double* _
     }
 }
 
+// ---------------------------------------------------------------------------
+// One factorisation per launch
+// ---------------------------------------------------------------------------
+__global__ void init_kernel(int64_t n, int* rem0, int* state, double* pstats) {
+    init_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, rem0, state, pstats);
+}
+
+__global__ __launch_bounds__(PT) void panel_start_kernel(int64_t n_rem, const double* __restrict__ S,
+                                                         int64_t lds, double* __restrict__ d,
+                                                         int* __restrict__ chosen, const int* rem0,
+                                                         const int* rem1, Part* __restrict__ out,
+                                                         int* state) {
+    panel_start_body(blockIdx.x, n_rem, S, lds, d, chosen, rem0, rem1, out, state);
+}
+
+template <int G, int R>
+__global__ __launch_bounds__(PT) void step_kernel(int64_t k, int t, int64_t n_rem,
+                                                  const double* __restrict__ S, int64_t lds,
+                                                  double* __restrict__ P, int64_t ldp,
+                                                  double* __restrict__ d, int* __restrict__ chosen,
+                                                  const int* rem0, const int* rem1,
+                                                  const Part* __restrict__ in, int nparts,
+                                                  Part* __restrict__ out, int* state, double tau,
+                                                  int* __restrict__ piv, double* __restrict__ pstats) {
+    step_body<G, R>(blockIdx.x, k, t, n_rem, S, lds, P, ldp, d, chosen, rem0, rem1, in, nparts, out,
+                    state, tau, piv, pstats);
+}
+
+__global__ __launch_bounds__(PT) void scatter_kernel(int64_t ps, int nbp, int64_t n_rem,
+                                                     const double* __restrict__ P, int64_t ldp,
+                                                     const int* rem0, const int* rem1,
+                                                     double* __restrict__ Rorig, int64_t ldr,
+                                                     const int* state) {
+    scatter_body(blockIdx.x, blockIdx.y, ps, nbp, n_rem, P, ldp, rem0, rem1, Rorig, ldr, state);
+}
+
+__global__ __launch_bounds__(1024) void compact_kernel(int64_t n_rem, const int* __restrict__ chosen,
+                                                       int* rem0, int* rem1, int* __restrict__ map,
+                                                       int* state) {
+    compact_body(n_rem, chosen, rem0, rem1, map, state);
+}
+
+__global__ __launch_bounds__(1024) void finalize_kernel(int64_t n, const int* __restrict__ chosen,
+                                                        const int* rem0, const int* rem1,
+                                                        int* __restrict__ piv, int* state) {
+    finalize_body(n, chosen, rem0, rem1, piv, state);
+}
+
+__global__ __launch_bounds__(256, 2) void trailing_kernel(int64_t n_new, const double* __restrict__ S,
+                                                          int64_t lds, double* __restrict__ Sn,
+                                                          int64_t ldsn, const double* __restrict__ P,
+                                                          int64_t ldp, int nbp,
+                                                          const int* __restrict__ map,
+                                                          const int* state) {
+    trailing_body(blockIdx.x, n_new, S, lds, Sn, ldsn, P, ldp, nbp, map, state);
+}
+
+__global__ __launch_bounds__(SPT) void pchol_small_kernel(int n, const double* __restrict__ M,
+                                                          int64_t ldm, double* __restrict__ S,
+                                                          double tau, int32_t* __restrict__ piv,
+                                                          double* __restrict__ Rorig, int64_t ldr,
+                                                          int* state, double* pstats) {
+    pchol_small_body(n, M, ldm, S, tau, piv, Rorig, ldr, state, pstats);
+}
+
+// ---------------------------------------------------------------------------
+// A group of independent factorisations per launch (blockIdx.y, or z for the
+// two-dimensional scatter grid, selects the problem).  All problems follow
+// the same panel schedule: panel j starts at position ps = j NB of every
+// problem, a problem with n <= ps has finished, and one with fewer than NB
+// remaining positions runs a shorter panel.  Each problem's arithmetic is
+// the one-problem path's, in the same order.
+// ---------------------------------------------------------------------------
+struct GProb {
+    const double* M;
+    int64_t ldm, n;
+    double* S[2];  // trailing matrices of alternate panels (ld n)
+    double* P;     // panel rows, NB x n
+    double* d;
+    int *chosen, *rem0, *rem1, *map;
+    Part* part[2];
+    double* Rorig;  // n x n
+    int* state;
+    double* pstats;
+    int32_t* piv;
+    double tau;
+};
+
+// the trailing matrix that panel j reads
+__device__ inline const double* panel_source(const GProb& q, int j, int64_t& lds) {
+    lds = j == 0 ? q.ldm : q.n;
+    return j == 0 ? q.M : q.S[(j - 1) & 1];
+}
+
+__global__ void init_grouped(const GProb* __restrict__ g) {
+    const GProb& q = g[blockIdx.y];
+    // one-workgroup problems keep no index list
+    init_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, q.rem0 ? q.n : 0, q.rem0, q.state,
+              q.pstats);
+}
+
+__global__ __launch_bounds__(PT) void panel_start_grouped(const GProb* __restrict__ g, int j) {
+    const GProb& q = g[blockIdx.y];
+    const int64_t n_rem = q.n - (int64_t)j * NB;
+    if (n_rem <= 0 || (int64_t)blockIdx.x >= cdiv(n_rem, PT)) return;
+    int64_t lds;
+    const double* S = panel_source(q, j, lds);
+    panel_start_body(blockIdx.x, n_rem, S, lds, q.d, q.chosen, q.rem0, q.rem1, q.part[0], q.state);
+}
+
+// prev_cpb: positions per block of the launch that wrote this step's argmax
+// partials (uniform over the group: it depends on t only)
+template <int G, int R>
+__global__ __launch_bounds__(PT) void step_grouped(const GProb* __restrict__ g, int j, int t,
+                                                   int prev_cpb) {
+    const GProb& q = g[blockIdx.y];
+    const int64_t ps = (int64_t)j * NB, n_rem = q.n - ps;
+    if (n_rem <= 0 || t >= (n_rem < NB ? n_rem : NB)) return;
+    if ((int64_t)blockIdx.x >= cdiv(n_rem, PT / G)) return;
+    const int64_t k = ps + t;
+    int64_t lds;
+    const double* S = panel_source(q, j, lds);
+    step_body<G, R>(blockIdx.x, k, t, n_rem, S, lds, q.P, q.n, q.d, q.chosen, q.rem0, q.rem1,
+                    q.part[k & 1], (int)cdiv(n_rem, prev_cpb), q.part[(k + 1) & 1], q.state, q.tau,
+                    q.piv, q.pstats);
+}
+
+__global__ __launch_bounds__(PT) void scatter_grouped(const GProb* __restrict__ g, int j) {
+    const GProb& q = g[blockIdx.z];
+    const int64_t ps = (int64_t)j * NB, n_rem = q.n - ps;
+    if (n_rem <= 0) return;
+    const int nbp = (int)(n_rem < NB ? n_rem : NB);
+    if ((int64_t)blockIdx.y >= nbp) return;
+    scatter_body(blockIdx.x, blockIdx.y, ps, nbp, n_rem, q.P, q.n, q.rem0, q.rem1, q.Rorig, q.n,
+                 q.state);
+}
+
+__global__ __launch_bounds__(1024) void compact_grouped(const GProb* __restrict__ g, int j) {
+    const GProb& q = g[blockIdx.y];
+    const int64_t n_rem = q.n - (int64_t)j * NB;
+    if (n_rem <= NB) return;  // no trailing matrix after this panel
+    compact_body(n_rem, q.chosen, q.rem0, q.rem1, q.map, q.state);
+}
+
+__global__ __launch_bounds__(256, 2) void trailing_grouped(const GProb* __restrict__ g, int j) {
+    const GProb& q = g[blockIdx.y];
+    const int64_t n_new = q.n - (int64_t)j * NB - NB;
+    if (n_new <= 0) return;
+    const int64_t nt = cdiv(n_new, TT);
+    if ((int64_t)blockIdx.x >= nt * (nt + 1) / 2) return;
+    int64_t lds;
+    const double* S = panel_source(q, j, lds);
+    trailing_body(blockIdx.x, n_new, S, lds, q.S[j & 1], q.n, q.P, q.n, NB, q.map, q.state);
+}
+
+__global__ __launch_bounds__(1024) void finalize_grouped(const GProb* __restrict__ g) {
+    const GProb& q = g[blockIdx.y];
+    finalize_body(q.n, q.chosen, q.rem0, q.rem1, q.piv, q.state);
+}
+
+__global__ __launch_bounds__(SPT) void small_grouped(const GProb* __restrict__ g) {
+    const GProb& q = g[blockIdx.x];
+    pchol_small_body((int)q.n, q.M, q.ldm, q.S[0], q.tau, q.piv, q.Rorig, q.n, q.state, q.pstats);
+}
+
 __global__ void gather_kernel(int64_t r, int64_t n, const double* __restrict__ Rorig, int64_t ldro,
                               const int* __restrict__ piv, double* __restrict__ R, int64_t ldr) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -713,6 +870,146 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
     finalize_kernel<<<1, 1024, 0, s>>>(n, chosen, rem0, rem1, piv, state);
     ELM_LAUNCH_CHECK();
     return finish_pivoted_cholesky(s, n, piv, Rorig, state, pstats, R_out, stats_out, f);
+}
+
+void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, Workspace& ws) {
+    const int count = (int)probs.size();
+    if (count == 0) return;
+    if (count > 65535) throw Error{ELM_ERR_UNSUPPORTED, "at most 65535 factorisations per group"};
+    // large problems first (multi-block panels), then the one-workgroup ones
+    std::vector<int> order(count);
+    for (int e = 0; e < count; ++e) order[e] = e;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].n > probs[b].n; });
+    int nlarge = 0;
+    while (nlarge < count && probs[order[nlarge]].n > SMALL_N) ++nlarge;
+    const int nsmall = count - nlarge;
+
+    // one arena for the per-problem scratch, one for R (cleared in one fill)
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t scratch = 0, rbytes = 0;
+    std::vector<size_t> off(count), roff(count);
+    for (int i = 0; i < count; ++i) {
+        const int64_t n = probs[order[i]].n;
+        if (n < 1) throw Error{ELM_ERR_INVALID_ARG, "a grouped factorisation has n < 1"};
+        const size_t nn = (size_t)n * n * sizeof(double);
+        off[i] = scratch;
+        scratch += al(nn) + al(n * sizeof(int32_t));  // S0, piv
+        if (n > SMALL_N)
+            scratch += al(nn) + al((size_t)NB * n * sizeof(double)) + al(n * sizeof(double)) +
+                       4 * al(n * sizeof(int)) + 2 * al(cdiv(n, PT / 8) * sizeof(Part));
+        roff[i] = rbytes;
+        rbytes += al(nn);
+    }
+    char* arena = (char*)ws.get("gp_arena", scratch);
+    char* rarena = (char*)ws.get("gp_rorig", rbytes);
+    int* states = (int*)ws.get("gp_state", (size_t)count * ST_N * sizeof(int));
+    double* stats = (double*)ws.get("gp_stats", (size_t)count * PS_N * sizeof(double));
+    GProb* dg = (GProb*)ws.get("gp_desc", (size_t)count * sizeof(GProb));
+    std::vector<GProb> hg(count);
+    int64_t nmax_large = 0, nmax = 0;
+    for (int i = 0; i < count; ++i) {
+        const PcholProblem& pr = probs[order[i]];
+        const int64_t n = pr.n;
+        const size_t nn = (size_t)n * n * sizeof(double);
+        char* c = arena + off[i];
+        auto take = [&](size_t b) {
+            char* r = c;
+            c += al(b);
+            return r;
+        };
+        GProb& q = hg[i];
+        std::memset(&q, 0, sizeof(q));
+        q.M = pr.M;
+        q.ldm = pr.ldm;
+        q.n = n;
+        q.tau = pr.tau;
+        q.S[0] = (double*)take(nn);
+        q.piv = (int32_t*)take(n * sizeof(int32_t));
+        if (n > SMALL_N) {
+            q.S[1] = (double*)take(nn);
+            q.P = (double*)take((size_t)NB * n * sizeof(double));
+            q.d = (double*)take(n * sizeof(double));
+            q.chosen = (int*)take(n * sizeof(int));
+            q.rem0 = (int*)take(n * sizeof(int));
+            q.rem1 = (int*)take(n * sizeof(int));
+            q.map = (int*)take(n * sizeof(int));
+            q.part[0] = (Part*)take(cdiv(n, PT / 8) * sizeof(Part));
+            q.part[1] = (Part*)take(cdiv(n, PT / 8) * sizeof(Part));
+            nmax_large = std::max(nmax_large, n);
+        }
+        q.Rorig = (double*)(rarena + roff[i]);
+        q.state = states + (size_t)i * ST_N;
+        q.pstats = stats + (size_t)i * PS_N;
+        nmax = std::max(nmax, n);
+    }
+    ELM_HIP_TRY(hipMemcpyAsync(dg, hg.data(), (size_t)count * sizeof(GProb), hipMemcpyHostToDevice, s));
+    init_grouped<<<dim3((unsigned)cdiv(std::max<int64_t>(nmax, ST_N), 256), (unsigned)count), 256, 0,
+                   s>>>(dg);
+    ELM_LAUNCH_CHECK();
+    launch_fill(s, (double*)rarena, (int64_t)(rbytes / sizeof(double)), 0.0);
+    if (nsmall > 0) {
+        small_grouped<<<(unsigned)nsmall, SPT, 0, s>>>(dg + nlarge);
+        ELM_LAUNCH_CHECK();
+    }
+    if (nlarge > 0) {
+        const unsigned ny = (unsigned)nlarge;
+        for (int j = 0; (int64_t)j * NB < nmax_large; ++j) {
+            const int64_t n_rem = nmax_large - (int64_t)j * NB;  // largest of the group
+            const int nbp = (int)(n_rem < NB ? n_rem : NB);
+            panel_start_grouped<<<dim3((unsigned)cdiv(n_rem, PT), ny), PT, 0, s>>>(dg, j);
+            ELM_LAUNCH_CHECK();
+            int prev_cpb = PT;
+            for (int t = 0; t < nbp; ++t) {
+                int g = 1;
+                while (g < 8 && 16 * g < t) g *= 2;
+                const dim3 grid((unsigned)cdiv(n_rem, PT / g), ny);
+#define ELM_GSTEP(G, R) step_grouped<G, R><<<grid, PT, 0, s>>>(dg, j, t, prev_cpb)
+                if (g == 1) ELM_GSTEP(1, 16);
+                else if (g == 2) ELM_GSTEP(2, 16);
+                else if (g == 4) ELM_GSTEP(4, 16);
+                else if (t <= 128) ELM_GSTEP(8, 16);
+                else ELM_GSTEP(8, 32);
+#undef ELM_GSTEP
+                ELM_LAUNCH_CHECK();
+                prev_cpb = PT / g;
+            }
+            scatter_grouped<<<dim3((unsigned)cdiv(n_rem, PT), (unsigned)nbp, ny), PT, 0, s>>>(dg, j);
+            ELM_LAUNCH_CHECK();
+            const int64_t n_new = n_rem - nbp;
+            if (n_new > 0) {
+                compact_grouped<<<dim3(1, ny), 1024, 0, s>>>(dg, j);
+                ELM_LAUNCH_CHECK();
+                const int64_t nt = cdiv(n_new, TT);
+                trailing_grouped<<<dim3((unsigned)(nt * (nt + 1) / 2), ny), 256, 0, s>>>(dg, j);
+                ELM_LAUNCH_CHECK();
+            }
+        }
+        finalize_grouped<<<dim3(1, ny), 1024, 0, s>>>(dg);
+        ELM_LAUNCH_CHECK();
+    }
+    std::vector<int> hstate((size_t)count * ST_N);
+    std::vector<double> hstats((size_t)count * PS_N);
+    ELM_HIP_TRY(hipMemcpyAsync(hstate.data(), states, hstate.size() * sizeof(int),
+                               hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipMemcpyAsync(hstats.data(), stats, hstats.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < count; ++i) {
+        PcholProblem& pr = probs[order[i]];
+        pr.rank = hstate[(size_t)i * ST_N + ST_RANK];
+        pr.bad = hstate[(size_t)i * ST_N + ST_BAD] != 0;
+        for (int u = 0; u < PS_N; ++u) pr.stats[u] = hstats[(size_t)i * PS_N + u];
+        pr.piv = hg[i].piv;
+        pr.Rorig = hg[i].Rorig;
+    }
+}
+
+void launch_gather_rows(hipStream_t s, int64_t r, int64_t n, const double* Rorig, int64_t ldro,
+                        const int32_t* piv, double* R, int64_t ldr) {
+    if (r <= 0 || n <= 0) return;
+    gather_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)r), 256, 0, s>>>(r, n, Rorig, ldro, piv, R,
+                                                                            ldr);
+    ELM_LAUNCH_CHECK();
 }
 
 void launch_fill(hipStream_t s, double* p, int64_t count, double v) {

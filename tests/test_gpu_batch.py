@@ -35,6 +35,22 @@ def batch():
     return probs, refs
 
 
+@pytest.fixture(scope="module")
+def mixed():
+    """Orders on both sides of the one-workgroup limit (512) in one group:
+    several panels (1100), a ragged last panel (530), the N < L route with
+    n = N = 700, and a small problem."""
+    shapes = [(3000, 1100, 110), (700, 1200, 120), (2500, 530, 53), (1500, 300, 30)]
+    probs = [wl.random_problem(40 + i, N, 16, L, 3, n_dup=k) for i, (N, L, k) in enumerate(shapes)]
+    refs = []
+    for p in probs:
+        H = O.hidden(p.X, p.W, p.b)
+        beta, F = O.solve(H, p.T)
+        s = np.linalg.svd(H[:, F.piv[:F.r]] if p.N >= p.L else H[F.piv[:F.r], :], compute_uv=False)
+        refs.append((beta, F.r, (s[0] / s[-1]) ** 2))
+    return probs, refs
+
+
 def _dev(p):
     return to_dev(p.X), to_dev(p.W), to_dev(p.b), to_dev(p.T)
 
@@ -80,3 +96,53 @@ def test_batched_rejects_malformed_problem_before_running(elm, batch):
         elm.train_batched(dev)
     empty_betas, empty_infos, empty_stats = elm.train_batched([])
     assert empty_betas == [] and empty_infos == [] and empty_stats == []
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_batched_mixed_orders_match_oracle(elm, mixed, precision):
+    probs, refs = mixed
+    dev = [_dev(p) for p in probs]
+    betas, infos, stats = elm.train_batched(dev, precision=precision, ir_tol=1e-12)
+    assert stats == [0] * len(probs)
+    for e, (p, (ref, r, k2)) in enumerate(zip(probs, refs)):
+        err = O.rel_err(betas[e].cpu().numpy(), ref)
+        info = infos[e]
+        tol = max(1e-10, 50 * k2 * EPS) if precision == "fp64" else 1e-6
+        print(f"[{e}] N={p.N} L={p.L} rank {info['rank']} (oracle {r}) {info['gram_dtype']} "
+              f"its {info['iterations']} ne {info['ne_residual']:.1e} err {err:.2e} tol {tol:.1e}")
+        assert info["rank"] == r == p.structural_rank
+        assert info["transposed"] == (p.N < p.L)
+        assert info["ne_residual"] <= 1e-12
+        assert err <= tol
+
+
+def test_batched_mixed_orders_equal_single_trainings(elm, mixed):
+    probs, _ = mixed
+    dev = [_dev(p) for p in probs]
+    betas, infos, _ = elm.train_batched(dev, precision="fp64", ir_tol=1e-12)
+    for e, (X, W, b, T) in enumerate(dev):
+        one = elm.train(X, W, b, T, precision="fp64", ir_tol=1e-12)
+        assert torch.equal(one.beta, betas[e])
+        assert one.rank == infos[e]["rank"]
+        assert one.info["factor"] == infos[e]["factor"]
+
+
+def test_batched_escalation_matches_single_training(elm, batch):
+    # a problem whose BF16 rank decision lies within the Gram's noise (the
+    # single-training escalation case) among ordinary ones: it is trained
+    # again from a higher-precision Gram, the others are not
+    probs, _ = batch
+    hard = wl.random_problem(seed=11, N=4000, d=2, L=120, m=2)
+    dev = [_dev(probs[0]), _dev(hard), _dev(probs[1])]
+    betas, infos, stats = elm.train_batched(dev, precision="bf16", ir_tol=1e-10, ir_max_iter=8,
+                                            check=False)
+    X, W, b, T = dev[1]
+    one = elm.train(X, W, b, T, precision="bf16", ir_tol=1e-10, ir_max_iter=8, check_convergence=False)
+    print(f"batched escalation: {infos[1]['gram_dtype']} after {infos[1]['escalations']} "
+          f"(guard {infos[1]['guard']}); single {one.info['gram_dtype']} after {one.info['escalations']}")
+    assert infos[1]["escalations"] == one.info["escalations"] == 2
+    assert infos[1]["guard"] == one.info["guard"] == 1
+    assert infos[1]["gram_dtype"] == "fp64" and infos[1]["rank"] == one.rank
+    assert torch.equal(betas[1], one.beta)
+    assert infos[0]["escalations"] == 0 and infos[2]["escalations"] == 0
+    assert stats[0] == 0 and stats[2] == 0
