@@ -175,7 +175,18 @@ elm_status elm_factor_pivots(elm_handle* h, const elm_factor* f, int32_t* piv_ho
  * that noise: last_pivot >= 2 noise_floor (r > 0) and first_rejected >=
  * -2 noise_floor (r < n).  A 0 means that the rank found on a low-precision
  * Gram may differ from the FP64 one: the caller should factor a
- * higher-precision Gram (elm_train does so by itself). */
+ * higher-precision Gram (elm_train does so by itself).
+ *
+ * Certified full rank (Grams of order >= the handle's
+ * ELM_OPT_FULL_RANK_MIN_ORDER): the greedy pivots never increase and the
+ * last one equals 1 / (M^-1)_jj for the last remaining index j, so all of
+ * them are at least lambda = 1 / max_j (M^-1)_jj.  The library first factors
+ * M without pivoting (blocked, MFMA updates) and computes lambda from the
+ * rows of the inverse factor; when lambda >= max(64 tau, 2 noise_floor) the
+ * greedy rule provably keeps every position (r = n), the identity order is
+ * used, certified_full_rank is 1 and last_pivot reports lambda (a lower bound
+ * on the greedy rule's smallest pivot).  Otherwise the greedy factorisation
+ * runs as usual. */
 typedef struct {
     int64_t rank;          /* r */
     int64_t n;             /* order of the Gram, min(N, L) */
@@ -187,6 +198,7 @@ typedef struct {
     double tau;            /* absolute stopping threshold */
     double noise_floor;    /* absolute noise scale of the Schur diagonals */
     int32_t reliable;      /* see above */
+    int32_t certified_full_rank; /* 1: rank n certified without the greedy steps */
 } elm_factor_info;
 
 elm_status elm_factor_get_info(const elm_factor* f, elm_factor_info* out);
@@ -352,6 +364,18 @@ typedef struct {
                                       handle's stream around each stage */
     int64_t count[ELM_STAGE_COUNT]; /* number of timed intervals per stage */
 } elm_stage_times;
+
+/* Tuning options of a handle (they change speed, never results beyond
+ * rounding).
+ *   ELM_OPT_FULL_RANK_MIN_ORDER  Grams of at least this order try the
+ *       certified full-rank path before the greedy steps (see
+ *       elm_factor_info); <= 0 disables it.  Default 4097.
+ *   ELM_OPT_BATCH_WORKERS  worker streams of elm_train_batched, 1..16.
+ *       Default 8.
+ * Errors: INVALID_ARG for an unknown option or a value out of range. */
+typedef enum { ELM_OPT_FULL_RANK_MIN_ORDER = 1, ELM_OPT_BATCH_WORKERS = 2 } elm_option;
+elm_status elm_set_option(elm_handle* h, elm_option opt, int64_t value);
+elm_status elm_get_option(const elm_handle* h, elm_option opt, int64_t* value);
 
 /* enable != 0 starts recording HIP events around every stage on the handle's
  * stream and clears the accumulated times; enable == 0 stops recording.

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libelm.so")
 OBJ_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["abi.hip", "hidden.hip", "gram.hip", "pchol.hip", "gemm.hip", "solve.hip",
+SOURCES = ["abi.hip", "hidden.hip", "gram.hip", "pchol.hip", "chol.hip", "gemm.hip", "solve.hip",
            "refine.hip", "predict.hip"]
 
 HIPCC_FLAGS = [

@@ -305,21 +305,57 @@ static elm_status rank_factor_impl(elm_handle* h, int64_t N, int64_t L, const vo
         // never passes for a pivot
         const int64_t K = transposed ? L : N;
         f->tau = (tau_rel > 0 ? tau_rel : 16.0 * (double)(n + K) * std::ldexp(1.0, -53)) * hdmax;
-        f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
-        double pst[3];
-        {
-            elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
-            f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, pst, h->ws, f);
-        }
-        f->last_pivot = pst[0];
-        f->first_rejected = pst[1];
         f->max_diag = hdmax;
         f->noise_floor = elm::schur_noise_floor(h_dt, n, N > L ? N : L, kc) * hdmax;
-        f->reliable = (f->r == 0 || f->last_pivot >= 2.0 * f->noise_floor) &&
-                      (f->r == n || f->first_rejected >= -2.0 * f->noise_floor);
-        {
-            elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
-            elm::build_factor_tail(h->stream, f, h->ws);
+        bool done = false;
+        if (h->full_rank_min_order > 0 && n >= h->full_rank_min_order) {
+            // certified full rank: every greedy pivot is at least
+            // 1 / max_j (M^-1)_jj, read off the rows of the inverse factor
+            const double need = std::max(64.0 * f->tau, 2.0 * f->noise_floor);
+            bool ok;
+            {
+                elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
+                ok = elm::unpivoted_cholesky(h->stream, n, M, n, need, &f->R, f, h->ws);
+            }
+            if (ok) {
+                f->r = n;
+                f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
+                elm::launch_iota(h->stream, n, f->piv);
+                {
+                    elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
+                    elm::build_factor_tail(h->stream, f, h->ws);
+                }
+                const double lam = elm::inv_max_row_sumsq(h->stream, n, f->Rinv, n, h->ws);
+                if (lam >= need) {
+                    f->last_pivot = lam;
+                    f->first_rejected = -INFINITY;
+                    f->reliable = true;
+                    f->certified_full_rank = true;
+                    done = true;
+                }
+            }
+            if (!done) {  // not certified: the greedy rule decides
+                elm::free_factor_buffers(f);
+                f->r = 0;
+                f->q = 0;
+                f->woodbury = false;
+            }
+        }
+        if (!done) {
+            f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
+            double pst[3];
+            {
+                elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
+                f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, pst, h->ws, f);
+            }
+            f->last_pivot = pst[0];
+            f->first_rejected = pst[1];
+            f->reliable = (f->r == 0 || f->last_pivot >= 2.0 * f->noise_floor) &&
+                          (f->r == n || f->first_rejected >= -2.0 * f->noise_floor);
+            {
+                elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
+                elm::build_factor_tail(h->stream, f, h->ws);
+            }
         }
         if (rank) *rank = f->r;
         *out = f;
@@ -389,6 +425,7 @@ elm_status elm_factor_get_info(const elm_factor* f, elm_factor_info* out) {
     out->tau = f->tau;
     out->noise_floor = f->noise_floor;
     out->reliable = f->reliable ? 1 : 0;
+    out->certified_full_rank = f->certified_full_rank ? 1 : 0;
     return ELM_OK;
 }
 
@@ -696,12 +733,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
         }
         if (count == 0) return;
         elm::use_device(h);
-        int nwmax = elm::BATCH_WORKERS;
-        if (const char* e = std::getenv("ELM_BATCH_WORKERS")) {  // tuning override, 1..16
-            const int v = std::atoi(e);
-            if (v >= 1 && v <= 16) nwmax = v;
-        }
-        const int nw = count < nwmax ? count : nwmax;
+        const int nw = count < h->batch_workers ? count : h->batch_workers;
         while ((int)h->workers.size() < nw) {
             hipStream_t ws_stream = nullptr;
             ELM_HIP_TRY(hipStreamCreateWithFlags(&ws_stream, hipStreamNonBlocking));
@@ -713,6 +745,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             w->owns_stream = true;
             h->workers.push_back(w);
         }
+        for (int w = 0; w < nw; ++w) h->workers[w]->full_rank_min_order = h->full_rank_min_order;
         // the workers start after the work already queued on the caller's stream
         hipEvent_t ev = nullptr;
         ELM_HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -1054,6 +1087,37 @@ elm_status elm_predict_hidden(elm_handle* h, int64_t N, int64_t L, int64_t m, co
         elm::StageScope sc(&h->prof, ELM_STAGE_PREDICT, h->stream);
         elm::launch_hidden_output(h->stream, N, L, m, H, ldh, beta, ldbeta, Y, ldy, labels);
     });
+}
+
+elm_status elm_set_option(elm_handle* h, elm_option opt, int64_t value) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    switch (opt) {
+        case ELM_OPT_FULL_RANK_MIN_ORDER:
+            h->full_rank_min_order = value;
+            return ELM_OK;
+        case ELM_OPT_BATCH_WORKERS:
+            if (value < 1 || value > 16) {
+                h->last_error = "batch workers must be in [1, 16]";
+                return ELM_ERR_INVALID_ARG;
+            }
+            h->batch_workers = (int)value;
+            return ELM_OK;
+    }
+    h->last_error = "unknown option";
+    return ELM_ERR_INVALID_ARG;
+}
+
+elm_status elm_get_option(const elm_handle* h, elm_option opt, int64_t* value) {
+    if (!h || !value) return ELM_ERR_INVALID_ARG;
+    switch (opt) {
+        case ELM_OPT_FULL_RANK_MIN_ORDER:
+            *value = h->full_rank_min_order;
+            return ELM_OK;
+        case ELM_OPT_BATCH_WORKERS:
+            *value = h->batch_workers;
+            return ELM_OK;
+    }
+    return ELM_ERR_INVALID_ARG;
 }
 
 elm_status elm_profile_enable(elm_handle* h, int enable) {

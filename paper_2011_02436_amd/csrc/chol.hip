@@ -1,0 +1,239 @@
+// Certified full-rank path of the rank step (Section 3, eq. 6; algorithm
+// step 4), for Grams of large order.
+//
+// The greedy pivoted Cholesky accepts every position of an n x n Gram M
+// exactly when its smallest pivot exceeds tau.  Its pivots never increase
+// (each step only lowers the remaining Schur diagonals), and its last pivot
+// is the Schur complement of the last remaining index j with respect to all
+// the others, 1 / (M^-1)_jj.  So every greedy pivot is at least
+//   lambda = 1 / max_j (M^-1)_jj = 1 / max_j || row j of U^-1 ||^2
+// for any Cholesky factor M = U^T U, pivoted or not.  When lambda clears the
+// threshold with a margin, the greedy rule keeps all n positions and the rank
+// is n without running the n sequential pivot steps: an unpivoted blocked
+// Cholesky (MFMA products) and the row norms of U^-1 (which the solves need
+// anyway) decide it.  Otherwise the caller runs the greedy factorisation.
+//
+// Organisation, per diagonal block of CB positions:
+//   potrf_block   one workgroup: the block's Cholesky factor in LDS, written
+//                 to U, then its inverse, written to W
+//   copy          the block rows right of the diagonal block into T
+//   product       U12 = W^T T                           (FP64 MFMA GEMM)
+//   update        S -= U12^T U12, upper tiles only       (FP64 MFMA GEMM)
+// A block that meets a pivot <= thr sets a device flag, and every later
+// kernel returns at once.
+#include "elm_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace elm {
+namespace {
+
+constexpr int CB = 128;    // diagonal block
+constexpr int CPT = 1024;  // threads of the block kernel
+
+__global__ void clear_flag_kernel(int* flag) {
+    if (threadIdx.x == 0) *flag = 0;
+}
+
+// U = upper triangle of M (diagonal included), zero below
+__global__ void copy_upper_kernel(int64_t n, const double* __restrict__ M, int64_t ldm,
+                                  double* __restrict__ U, int64_t ldu) {
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y)
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+             c += (int64_t)gridDim.x * blockDim.x)
+            U[i * ldu + c] = c >= i ? M[i * ldm + c] : 0.0;
+}
+
+// zero below the diagonal of U
+__global__ void zero_lower_kernel(int64_t n, double* __restrict__ U, int64_t ldu) {
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y)
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < i;
+             c += (int64_t)gridDim.x * blockDim.x)
+            U[i * ldu + c] = 0.0;
+}
+
+__global__ __launch_bounds__(CPT) void potrf_block_kernel(double* __restrict__ U, int64_t ldu,
+                                                          int64_t k0, int nb, double thr,
+                                                          double* __restrict__ W, int* flag) {
+    __shared__ double A[CB][CB + 1];
+    if (*flag) return;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < nb * nb; e += CPT) {
+        const int i = e / nb, c = e % nb;
+        A[i][c] = c >= i ? U[(k0 + i) * ldu + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    // right-looking: row j scaled by its pivot's root, trailing block updated
+    for (int j = 0; j < nb; ++j) {
+        const double d = A[j][j];
+        if (!(d > thr)) {  // the same value for every thread: the block leaves together
+            if (tid == 0) *flag = 1;
+            return;
+        }
+        const double rj = sqrt(d);
+        __syncthreads();  // every thread has read the pivot
+        if (tid < nb - j) {
+            const int c = j + tid;
+            A[j][c] = c == j ? rj : A[j][c] / rj;
+        }
+        __syncthreads();
+        const int m = nb - 1 - j;
+        for (int e = tid; e < m * m; e += CPT) {
+            const int ii = e / m, cc = e % m;
+            if (cc >= ii) A[j + 1 + ii][j + 1 + cc] -= A[j][j + 1 + ii] * A[j][j + 1 + cc];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += CPT) {
+        const int i = e / nb, c = e % nb;
+        U[(k0 + i) * ldu + k0 + c] = c >= i ? A[i][c] : 0.0;
+    }
+    // in-place inverse, column by column: with columns < j already inverted,
+    //   W[i][j] = -(sum_{i <= k < j} W[i][k] U[k][j]) / U[j][j],  W[j][j] = 1 / U[j][j]
+    // (8 lanes per row i share its dot product)
+    static_assert(CPT >= 8 * CB, "eight lanes per row");
+    const int ri = tid >> 3, sub = tid & 7;
+    for (int j = 0; j < nb; ++j) {
+        double v = 0.0;
+        if (ri < j)
+            for (int k = ri + sub; k < j; k += 8) v += A[ri][k] * A[k][j];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        const double inv = 1.0 / A[j][j];
+        __syncthreads();
+        if (ri < j && sub == 0) A[ri][j] = -v * inv;
+        if (tid == 0) A[j][j] = inv;
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += CPT) {
+        const int i = e / nb, c = e % nb;
+        W[i * CB + c] = c >= i ? A[i][c] : 0.0;
+    }
+}
+
+// T (nb x nc, ld nc) = U[k0 .. k0 + nb)[c0 .. c0 + nc)
+__global__ void copy_rows_kernel(int nb, int64_t nc, const double* __restrict__ U, int64_t ldu,
+                                 int64_t k0, int64_t c0, double* __restrict__ T, const int* flag) {
+    if (*flag) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (c < nc && i < nb) T[i * nc + c] = U[(k0 + i) * ldu + c0 + c];
+}
+
+// out[j] = sum_{k >= j} X[j][k]^2, one block per row
+__global__ __launch_bounds__(256) void row_sumsq_kernel(int64_t n, const double* __restrict__ X,
+                                                        int64_t ldx, double* __restrict__ out) {
+    __shared__ double part[4];
+    for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
+        double s = 0.0;
+        for (int64_t k = j + threadIdx.x; k < n; k += 256) {
+            const double x = X[j * ldx + k];
+            s += x * x;
+        }
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) out[j] = (part[0] + part[1]) + (part[2] + part[3]);
+        __syncthreads();
+    }
+}
+
+// *out = max of v[0 .. n) (NaN if any entry is NaN)
+__global__ __launch_bounds__(1024) void max_kernel(int64_t n, const double* __restrict__ v,
+                                                   double* __restrict__ out) {
+    __shared__ double wm[16];
+    double m = -INFINITY;
+    bool nan = false;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const double x = v[i];
+        if (x != x) nan = true;
+        m = x > m ? x : m;
+    }
+    if (nan) m = NAN;
+    for (int off = 32; off > 0; off >>= 1) {
+        const double y = __shfl_xor(m, off);
+        m = (m != m || y != y) ? NAN : (y > m ? y : m);
+    }
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = wm[0];
+        for (int w = 1; w < 16; ++w) r = (r != r || wm[w] != wm[w]) ? NAN : (wm[w] > r ? wm[w] : r);
+        *out = r;
+    }
+}
+
+__global__ void iota_kernel(int64_t n, int32_t* piv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) piv[i] = (int32_t)i;
+}
+
+}  // namespace
+
+bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double thr,
+                        double** R_out, elm_factor* f, Workspace& ws) {
+    *R_out = nullptr;
+    double* U = (double*)factor_alloc(f, "R", (size_t)n * n * sizeof(double));
+    double* W = (double*)ws.get("fr_W", (size_t)CB * CB * sizeof(double));
+    double* T = (double*)ws.get("fr_T", (size_t)CB * n * sizeof(double));
+    int* flag = (int*)ws.get("fr_flag", sizeof(int));
+    clear_flag_kernel<<<1, 64, 0, s>>>(flag);
+    ELM_LAUNCH_CHECK();
+    copy_upper_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)std::min<int64_t>(n, 65535)), 256, 0,
+                        s>>>(n, M, ldm, U, n);
+    ELM_LAUNCH_CHECK();
+    for (int64_t k0 = 0; k0 < n; k0 += CB) {
+        const int nb = (int)std::min<int64_t>(CB, n - k0);
+        potrf_block_kernel<<<1, CPT, 0, s>>>(U, n, k0, nb, thr, W, flag);
+        ELM_LAUNCH_CHECK();
+        const int64_t c0 = k0 + nb, nc = n - c0;
+        if (nc <= 0) break;
+        copy_rows_kernel<<<dim3((unsigned)cdiv(nc, 256), (unsigned)nb), 256, 0, s>>>(nb, nc, U, n, k0,
+                                                                                   c0, T, flag);
+        ELM_LAUNCH_CHECK();
+        // U12 = W^T T: A(i, k) = W[k][i]
+        gemm_f64_batched(s, 1, nb, nc, nb, 1.0, W, 1, CB, 0, T, nc, 1, 0, 0.0, U + k0 * n + c0, n, 0,
+                         false, false, false, flag);
+        // S -= U12^T U12 on the upper tiles: A(i, k) = U12[k][i], B(k, j) = U12[k][j]
+        const double* U12 = U + k0 * n + c0;
+        gemm_f64_batched(s, 1, nc, nc, nb, -1.0, U12, 1, n, 0, U12, n, 1, 0, 1.0, U + c0 * n + c0, n,
+                         0, false, false, true, flag);
+    }
+    int hflag = 0;
+    ELM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipStreamSynchronize(s));
+    if (hflag) {
+        if (!f->pool) (void)hipFree(U);
+        return false;
+    }
+    // the updates above left values below the diagonal of the trailing blocks
+    // that straddle it; U must be zero there
+    zero_lower_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)std::min<int64_t>(n, 65535)), 256, 0,
+                        s>>>(n, U, n);
+    ELM_LAUNCH_CHECK();
+    *R_out = U;
+    return true;
+}
+
+double inv_max_row_sumsq(hipStream_t s, int64_t n, const double* X, int64_t ldx, Workspace& ws) {
+    double* rows = (double*)ws.get("fr_rows", (size_t)n * sizeof(double));
+    double* mx = (double*)ws.get("fr_max", sizeof(double));
+    row_sumsq_kernel<<<(unsigned)std::min<int64_t>(n, 8192), 256, 0, s>>>(n, X, ldx, rows);
+    ELM_LAUNCH_CHECK();
+    max_kernel<<<1, 1024, 0, s>>>(n, rows, mx);
+    ELM_LAUNCH_CHECK();
+    double h = 0.0;
+    ELM_HIP_TRY(hipMemcpyAsync(&h, mx, sizeof(double), hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipStreamSynchronize(s));
+    return h > 0.0 ? 1.0 / h : 0.0;
+}
+
+void launch_iota(hipStream_t s, int64_t n, int32_t* piv) {
+    if (n <= 0) return;
+    iota_kernel<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(n, piv);
+    ELM_LAUNCH_CHECK();
+}
+
+}  // namespace elm

@@ -113,9 +113,12 @@ struct Workspace {
 }  // namespace elm
 
 namespace elm {
-// Independent trainings run concurrently on this many streams (the HIP
-// runtime's default number of hardware queues per process).
-constexpr int BATCH_WORKERS = 4;
+// Independent trainings of a batch run concurrently on this many streams by
+// default (more than the runtime's four hardware queues per process: the
+// streams also hide each other's host synchronisations).
+constexpr int BATCH_WORKERS = 8;
+// Grams of at least this order try the certified full-rank path first
+constexpr int64_t FULL_RANK_MIN_ORDER = 4097;
 // device memory for the Grams and factorisation scratch of one group of a
 // batched training (larger batches run group after group)
 constexpr size_t BATCH_GROUP_BYTES = (size_t)16 << 30;
@@ -132,6 +135,9 @@ struct elm_handle {
     // on first use, kept for reuse of their workspaces)
     std::vector<elm_handle*> workers;
     bool owns_stream = false;
+    // tuning options (elm_set_option)
+    int64_t full_rank_min_order = elm::FULL_RANK_MIN_ORDER;
+    int batch_workers = elm::BATCH_WORKERS;
 };
 
 struct elm_factor {
@@ -145,6 +151,7 @@ struct elm_factor {
     double max_diag = 0, last_pivot = 0, first_rejected = 0;
     double noise_floor = 0;   // absolute rounding-noise scale of the Schur diagonals
     bool reliable = true;
+    bool certified_full_rank = false;  // rank n by the certificate, identity order
     // device buffers: hipMalloc'd and owned by the factor, or, when pool is
     // set, named buffers of that workspace (a factor used only inside a call)
     elm::Workspace* pool = nullptr;
@@ -260,6 +267,32 @@ inline double schur_noise_floor(elm_dtype dt, int64_t n, int64_t K, int64_t kc) 
     const double fp64 = (double)n * std::ldexp(1.0, -53);
     return u * u / 3.0 + acc + fp64;
 }
+
+// gemm.hip: C = alpha A B + beta C on FP64 MFMA, strided operands
+//   A(i, k) = A[i a_rs + k a_cs], B(k, j) = B[k b_rs + j b_cs]; a batch of
+//   equally shaped products at strides a_bs, b_bs, c_bs.  tri_a / tri_b: A /
+//   B upper triangular (their zero blocks are skipped); upper_c: only the
+//   upper triangle of C is needed; skip: device flag, nothing runs when set.
+void gemm_f64(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+              int64_t a_rs, int64_t a_cs, const double* B, int64_t b_rs, int64_t b_cs, double beta,
+              double* C, int64_t ldc);
+void gemm_f64_batched(hipStream_t s, int64_t batch, int64_t M, int64_t N, int64_t K, double alpha,
+                      const double* A, int64_t a_rs, int64_t a_cs, int64_t a_bs, const double* B,
+                      int64_t b_rs, int64_t b_cs, int64_t b_bs, double beta, double* C, int64_t ldc,
+                      int64_t c_bs, bool tri_a, bool tri_b, bool upper_c = false,
+                      const int* skip = nullptr);
+
+// chol.hip: certified full-rank path of the rank step.  Factorises M = U^T U
+// without pivoting (blocked, U in *R_out by factor_alloc, n x n, ld n, zero
+// below the diagonal) and returns false without a result as soon as a pivot
+// is <= thr.  Synchronises the stream once.
+bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double thr,
+                        double** R_out, elm_factor* f, Workspace& ws);
+// 1 / max_j sum_k X[j][k]^2 over the rows of an upper triangular n x n X (ld
+// ldx); synchronises the stream once.
+double inv_max_row_sumsq(hipStream_t s, int64_t n, const double* X, int64_t ldx, Workspace& ws);
+// piv[i] = i
+void launch_iota(hipStream_t s, int64_t n, int32_t* piv);
 
 // solve.hip: dense FP64 helpers for the factor and the pseudoinverse apply
 void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws);

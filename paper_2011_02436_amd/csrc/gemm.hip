@@ -9,6 +9,9 @@
 //   tri_b: B is upper triangular (B(k, j) = 0 for k > j).
 // The skipped products are exact zeros, so the result is the same.
 // A batch of equally shaped products (blockIdx.z) shares one launch.
+// upper_c: only tiles that reach the upper triangle of C (i <= j) are
+// computed (a symmetric update); skip (device flag, may be NULL): the launch
+// does nothing when it is set.
 #include "elm_internal.h"
 
 namespace elm {
@@ -26,13 +29,16 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(int64_t M, int64_t N, int64
                                                      const double* __restrict__ B, int64_t b_rs,
                                                      int64_t b_cs, int64_t b_bs, double beta,
                                                      double* __restrict__ C, int64_t ldc,
-                                                     int64_t c_bs, int tri_a, int tri_b) {
+                                                     int64_t c_bs, int tri_a, int tri_b, int upper_c,
+                                                     const int* __restrict__ skip) {
     constexpr int P = TS + 16;          // LDS pitch (see the hidden-layer kernel)
     constexpr int EPT = TS * BK / NT;   // elements per thread per operand tile
     constexpr int WB = TS / 32;         // 16 x 16 blocks per wave and dimension
     __shared__ double As[2][BK][P];
     __shared__ double Bs[2][BK][P];
     const int64_t i0 = (int64_t)blockIdx.x * TS, j0 = (int64_t)blockIdx.y * TS;
+    if (upper_c && i0 >= j0 + TS) return;  // strictly below the diagonal
+    if (skip && *skip) return;
     A += (int64_t)blockIdx.z * a_bs;
     B += (int64_t)blockIdx.z * b_bs;
     C += (int64_t)blockIdx.z * c_bs;
@@ -141,16 +147,16 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(int64_t M, int64_t N, int64
 void gemm_f64_batched(hipStream_t s, int64_t batch, int64_t M, int64_t N, int64_t K, double alpha,
                       const double* A, int64_t a_rs, int64_t a_cs, int64_t a_bs, const double* B,
                       int64_t b_rs, int64_t b_cs, int64_t b_bs, double beta, double* C, int64_t ldc,
-                      int64_t c_bs, bool tri_a, bool tri_b) {
+                      int64_t c_bs, bool tri_a, bool tri_b, bool upper_c, const int* skip) {
     if (M <= 0 || N <= 0 || batch <= 0) return;
     if (M >= 128 && N >= 128) {
         dim3 grid((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128), (unsigned)batch);
         gemm_kernel<128><<<grid, NT, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs, b_bs,
-                                             beta, C, ldc, c_bs, tri_a, tri_b);
+                                             beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);
     } else {
         dim3 grid((unsigned)cdiv(M, 64), (unsigned)cdiv(N, 64), (unsigned)batch);
         gemm_kernel<64><<<grid, NT, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs, b_bs,
-                                            beta, C, ldc, c_bs, tri_a, tri_b);
+                                            beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);
     }
     ELM_LAUNCH_CHECK();
 }

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <cstring>
 #include <cmath>
 
@@ -33,8 +34,9 @@ namespace elm {
 namespace {
 
 constexpr int PT = 256;     // threads per block, step kernels
-constexpr int NB = 256;     // panel width
+constexpr int NB = 256;     // widest panel
 static_assert(NB <= 8 * 32, "a step covers at most 8 groups of 32 panel rows");
+constexpr int64_t MID_MAX = 4096;  // orders up to this use narrower panels
 constexpr int TT = 128;     // trailing-update tile
 enum { ST_DONE = 0, ST_RANK = 1, ST_BAD = 2, ST_CUR = 3, ST_NREM = 4, ST_N = 5 };
 
@@ -657,8 +659,8 @@ __global__ __launch_bounds__(SPT) void pchol_small_kernel(int n, const double* _
 // ---------------------------------------------------------------------------
 // A group of independent factorisations per launch (blockIdx.y, or z for the
 // two-dimensional scatter grid, selects the problem).  All problems follow
-// the same panel schedule: panel j starts at position ps = j NB of every
-// problem, a problem with n <= ps has finished, and one with fewer than NB
+// the same panel schedule: panel j starts at position ps = j nb of every
+// problem, a problem with n <= ps has finished, and one with fewer than nb
 // remaining positions runs a shorter panel.  Each problem's arithmetic is
 // the one-problem path's, in the same order.
 // ---------------------------------------------------------------------------
@@ -666,7 +668,7 @@ struct GProb {
     const double* M;
     int64_t ldm, n;
     double* S[2];  // trailing matrices of alternate panels (ld n)
-    double* P;     // panel rows, NB x n
+    double* P;     // panel rows, nb x n
     double* d;
     int *chosen, *rem0, *rem1, *map;
     Part* part[2];
@@ -690,9 +692,9 @@ __global__ void init_grouped(const GProb* __restrict__ g) {
               q.pstats);
 }
 
-__global__ __launch_bounds__(PT) void panel_start_grouped(const GProb* __restrict__ g, int j) {
+__global__ __launch_bounds__(PT) void panel_start_grouped(const GProb* __restrict__ g, int j, int nb) {
     const GProb& q = g[blockIdx.y];
-    const int64_t n_rem = q.n - (int64_t)j * NB;
+    const int64_t n_rem = q.n - (int64_t)j * nb;
     if (n_rem <= 0 || (int64_t)blockIdx.x >= cdiv(n_rem, PT)) return;
     int64_t lds;
     const double* S = panel_source(q, j, lds);
@@ -702,11 +704,11 @@ __global__ __launch_bounds__(PT) void panel_start_grouped(const GProb* __restric
 // prev_cpb: positions per block of the launch that wrote this step's argmax
 // partials (uniform over the group: it depends on t only)
 template <int G, int R>
-__global__ __launch_bounds__(PT) void step_grouped(const GProb* __restrict__ g, int j, int t,
+__global__ __launch_bounds__(PT) void step_grouped(const GProb* __restrict__ g, int j, int nb, int t,
                                                    int prev_cpb) {
     const GProb& q = g[blockIdx.y];
-    const int64_t ps = (int64_t)j * NB, n_rem = q.n - ps;
-    if (n_rem <= 0 || t >= (n_rem < NB ? n_rem : NB)) return;
+    const int64_t ps = (int64_t)j * nb, n_rem = q.n - ps;
+    if (n_rem <= 0 || t >= (n_rem < nb ? n_rem : nb)) return;
     if ((int64_t)blockIdx.x >= cdiv(n_rem, PT / G)) return;
     const int64_t k = ps + t;
     int64_t lds;
@@ -716,32 +718,32 @@ __global__ __launch_bounds__(PT) void step_grouped(const GProb* __restrict__ g, 
                     q.piv, q.pstats);
 }
 
-__global__ __launch_bounds__(PT) void scatter_grouped(const GProb* __restrict__ g, int j) {
+__global__ __launch_bounds__(PT) void scatter_grouped(const GProb* __restrict__ g, int j, int nb) {
     const GProb& q = g[blockIdx.z];
-    const int64_t ps = (int64_t)j * NB, n_rem = q.n - ps;
+    const int64_t ps = (int64_t)j * nb, n_rem = q.n - ps;
     if (n_rem <= 0) return;
-    const int nbp = (int)(n_rem < NB ? n_rem : NB);
+    const int nbp = (int)(n_rem < nb ? n_rem : nb);
     if ((int64_t)blockIdx.y >= nbp) return;
     scatter_body(blockIdx.x, blockIdx.y, ps, nbp, n_rem, q.P, q.n, q.rem0, q.rem1, q.Rorig, q.n,
                  q.state);
 }
 
-__global__ __launch_bounds__(1024) void compact_grouped(const GProb* __restrict__ g, int j) {
+__global__ __launch_bounds__(1024) void compact_grouped(const GProb* __restrict__ g, int j, int nb) {
     const GProb& q = g[blockIdx.y];
-    const int64_t n_rem = q.n - (int64_t)j * NB;
-    if (n_rem <= NB) return;  // no trailing matrix after this panel
+    const int64_t n_rem = q.n - (int64_t)j * nb;
+    if (n_rem <= nb) return;  // no trailing matrix after this panel
     compact_body(n_rem, q.chosen, q.rem0, q.rem1, q.map, q.state);
 }
 
-__global__ __launch_bounds__(256, 2) void trailing_grouped(const GProb* __restrict__ g, int j) {
+__global__ __launch_bounds__(256, 2) void trailing_grouped(const GProb* __restrict__ g, int j, int nb) {
     const GProb& q = g[blockIdx.y];
-    const int64_t n_new = q.n - (int64_t)j * NB - NB;
+    const int64_t n_new = q.n - (int64_t)j * nb - nb;
     if (n_new <= 0) return;
     const int64_t nt = cdiv(n_new, TT);
     if ((int64_t)blockIdx.x >= nt * (nt + 1) / 2) return;
     int64_t lds;
     const double* S = panel_source(q, j, lds);
-    trailing_body(blockIdx.x, n_new, S, lds, q.S[j & 1], q.n, q.P, q.n, NB, q.map, q.state);
+    trailing_body(blockIdx.x, n_new, S, lds, q.S[j & 1], q.n, q.P, q.n, nb, q.map, q.state);
 }
 
 __global__ __launch_bounds__(1024) void finalize_grouped(const GProb* __restrict__ g) {
@@ -784,9 +786,26 @@ static int64_t finish_pivoted_cholesky(hipStream_t s, int64_t n, const int32_t* 
     return r;
 }
 
+// Panel width.  Every pivot step re-reads its panel's rows (t of them at step
+// t), every panel ends with a pass over the trailing matrix: orders up to
+// MID_MAX take narrow panels (the re-read rows of many factorisations sharing
+// the launches stay in the caches), larger ones NB.  ELM_MID_PANEL (32, 64,
+// 128 or 256) overrides the narrow width for tuning.
+static int panel_width(int64_t n) {
+    static const int mid = [] {
+        if (const char* e = std::getenv("ELM_MID_PANEL")) {
+            const int v = std::atoi(e);
+            if (v == 32 || v == 64 || v == 128 || v == 256) return v;
+        }
+        return 64;
+    }();
+    return n <= MID_MAX ? mid : NB;
+}
+
 int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double tau,
                          int32_t* piv, double** R_out, double* stats_out, Workspace& ws,
                          elm_factor* f) {
+    const int pw = panel_width(n);
     const int64_t nparts_max = cdiv(n, PT / 8);  // most blocks of any step launch
     int* state = (int*)ws.get("pc_state", ST_N * sizeof(int));
     double* pstats = (double*)ws.get("pc_stats", PS_N * sizeof(double));
@@ -795,11 +814,11 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
     int* map = (int*)ws.get("pc_map", n * sizeof(int));
     int* chosen = (int*)ws.get("pc_chosen", n * sizeof(int));
     double* d = (double*)ws.get("pc_d", n * sizeof(double));
-    double* P = (double*)ws.get("pc_P", (size_t)NB * n * sizeof(double));
+    double* P = (double*)ws.get("pc_P", (size_t)pw * n * sizeof(double));
     Part* parts = (Part*)ws.get("pc_parts", 2 * nparts_max * sizeof(Part));
     double* Rorig = (double*)ws.get("pc_Rorig", (size_t)n * n * sizeof(double));
     double* Sbuf[2] = {nullptr, nullptr};
-    if (n > NB) {
+    if (n > pw) {
         Sbuf[0] = (double*)ws.get("pc_S0", (size_t)n * n * sizeof(double));
         Sbuf[1] = (double*)ws.get("pc_S1", (size_t)n * n * sizeof(double));
     }
@@ -821,7 +840,7 @@ int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
     int which = 0;
     int64_t ps = 0, n_rem = n;
     while (ps < n) {
-        const int nbp = (int)(n_rem < NB ? n_rem : NB);
+        const int nbp = (int)(n_rem < pw ? n_rem : pw);
         const int nblk = (int)cdiv(n_rem, PT);
         panel_start_kernel<<<nblk, PT, 0, s>>>(n_rem, Scur, lds, d, chosen, rem0, rem1, part[ps & 1],
                                                  state);
@@ -880,7 +899,9 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
     std::vector<int> order(count);
     for (int e = 0; e < count; ++e) order[e] = e;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].n > probs[b].n; });
-    int nlarge = 0;
+    int nbig = 0, nlarge = 0;
+    while (nbig < count && probs[order[nbig]].n > MID_MAX) ++nbig;
+    nlarge = nbig;
     while (nlarge < count && probs[order[nlarge]].n > SMALL_N) ++nlarge;
     const int nsmall = count - nlarge;
 
@@ -895,7 +916,7 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
         off[i] = scratch;
         scratch += al(nn) + al(n * sizeof(int32_t));  // S0, piv
         if (n > SMALL_N)
-            scratch += al(nn) + al((size_t)NB * n * sizeof(double)) + al(n * sizeof(double)) +
+            scratch += al(nn) + al((size_t)panel_width(n) * n * sizeof(double)) + al(n * sizeof(double)) +
                        4 * al(n * sizeof(int)) + 2 * al(cdiv(n, PT / 8) * sizeof(Part));
         roff[i] = rbytes;
         rbytes += al(nn);
@@ -906,7 +927,7 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
     double* stats = (double*)ws.get("gp_stats", (size_t)count * PS_N * sizeof(double));
     GProb* dg = (GProb*)ws.get("gp_desc", (size_t)count * sizeof(GProb));
     std::vector<GProb> hg(count);
-    int64_t nmax_large = 0, nmax = 0;
+    int64_t nmax = 0;
     for (int i = 0; i < count; ++i) {
         const PcholProblem& pr = probs[order[i]];
         const int64_t n = pr.n;
@@ -927,7 +948,7 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
         q.piv = (int32_t*)take(n * sizeof(int32_t));
         if (n > SMALL_N) {
             q.S[1] = (double*)take(nn);
-            q.P = (double*)take((size_t)NB * n * sizeof(double));
+            q.P = (double*)take((size_t)panel_width(n) * n * sizeof(double));
             q.d = (double*)take(n * sizeof(double));
             q.chosen = (int*)take(n * sizeof(int));
             q.rem0 = (int*)take(n * sizeof(int));
@@ -935,7 +956,6 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
             q.map = (int*)take(n * sizeof(int));
             q.part[0] = (Part*)take(cdiv(n, PT / 8) * sizeof(Part));
             q.part[1] = (Part*)take(cdiv(n, PT / 8) * sizeof(Part));
-            nmax_large = std::max(nmax_large, n);
         }
         q.Rorig = (double*)(rarena + roff[i]);
         q.state = states + (size_t)i * ST_N;
@@ -951,19 +971,22 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
         small_grouped<<<(unsigned)nsmall, SPT, 0, s>>>(dg + nlarge);
         ELM_LAUNCH_CHECK();
     }
-    if (nlarge > 0) {
-        const unsigned ny = (unsigned)nlarge;
-        for (int j = 0; (int64_t)j * NB < nmax_large; ++j) {
-            const int64_t n_rem = nmax_large - (int64_t)j * NB;  // largest of the group
-            const int nbp = (int)(n_rem < NB ? n_rem : NB);
-            panel_start_grouped<<<dim3((unsigned)cdiv(n_rem, PT), ny), PT, 0, s>>>(dg, j);
+    // one chain of launches per panel width: orders above MID_MAX, then the
+    // mid-size ones
+    auto chain = [&](const GProb* dgs, int np, int64_t nmax_c, int nb) {
+        if (np <= 0) return;
+        const unsigned ny = (unsigned)np;
+        for (int j = 0; (int64_t)j * nb < nmax_c; ++j) {
+            const int64_t n_rem = nmax_c - (int64_t)j * nb;  // largest of the chain
+            const int nbp = (int)(n_rem < nb ? n_rem : nb);
+            panel_start_grouped<<<dim3((unsigned)cdiv(n_rem, PT), ny), PT, 0, s>>>(dgs, j, nb);
             ELM_LAUNCH_CHECK();
             int prev_cpb = PT;
             for (int t = 0; t < nbp; ++t) {
                 int g = 1;
                 while (g < 8 && 16 * g < t) g *= 2;
                 const dim3 grid((unsigned)cdiv(n_rem, PT / g), ny);
-#define ELM_GSTEP(G, R) step_grouped<G, R><<<grid, PT, 0, s>>>(dg, j, t, prev_cpb)
+#define ELM_GSTEP(G, R) step_grouped<G, R><<<grid, PT, 0, s>>>(dgs, j, nb, t, prev_cpb)
                 if (g == 1) ELM_GSTEP(1, 16);
                 else if (g == 2) ELM_GSTEP(2, 16);
                 else if (g == 4) ELM_GSTEP(4, 16);
@@ -973,20 +996,24 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
                 ELM_LAUNCH_CHECK();
                 prev_cpb = PT / g;
             }
-            scatter_grouped<<<dim3((unsigned)cdiv(n_rem, PT), (unsigned)nbp, ny), PT, 0, s>>>(dg, j);
+            scatter_grouped<<<dim3((unsigned)cdiv(n_rem, PT), (unsigned)nbp, ny), PT, 0, s>>>(dgs, j,
+                                                                                           nb);
             ELM_LAUNCH_CHECK();
             const int64_t n_new = n_rem - nbp;
             if (n_new > 0) {
-                compact_grouped<<<dim3(1, ny), 1024, 0, s>>>(dg, j);
+                compact_grouped<<<dim3(1, ny), 1024, 0, s>>>(dgs, j, nb);
                 ELM_LAUNCH_CHECK();
                 const int64_t nt = cdiv(n_new, TT);
-                trailing_grouped<<<dim3((unsigned)(nt * (nt + 1) / 2), ny), 256, 0, s>>>(dg, j);
+                trailing_grouped<<<dim3((unsigned)(nt * (nt + 1) / 2), ny), 256, 0, s>>>(dgs, j, nb);
                 ELM_LAUNCH_CHECK();
             }
         }
-        finalize_grouped<<<dim3(1, ny), 1024, 0, s>>>(dg);
+        finalize_grouped<<<dim3(1, ny), 1024, 0, s>>>(dgs);
         ELM_LAUNCH_CHECK();
-    }
+    };
+    if (nbig > 0) chain(dg, nbig, probs[order[0]].n, panel_width(probs[order[0]].n));
+    if (nlarge > nbig)
+        chain(dg + nbig, nlarge - nbig, probs[order[nbig]].n, panel_width(probs[order[nbig]].n));
     std::vector<int> hstate((size_t)count * ST_N);
     std::vector<double> hstats((size_t)count * PS_N);
     ELM_HIP_TRY(hipMemcpyAsync(hstate.data(), states, hstate.size() * sizeof(int),

@@ -17,14 +17,6 @@
 
 namespace elm {
 
-void gemm_f64(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
-              int64_t a_rs, int64_t a_cs, const double* B, int64_t b_rs, int64_t b_cs, double beta,
-              double* C, int64_t ldc);
-void gemm_f64_batched(hipStream_t s, int64_t batch, int64_t M, int64_t N, int64_t K, double alpha,
-                      const double* A, int64_t a_rs, int64_t a_cs, int64_t a_bs, const double* B,
-                      int64_t b_rs, int64_t b_cs, int64_t b_bs, double beta, double* C, int64_t ldc,
-                      int64_t c_bs, bool tri_a, bool tri_b);
-
 namespace {
 
 constexpr int LB = 64;  // leaf block of the triangular inverse

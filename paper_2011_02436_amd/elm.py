@@ -51,14 +51,15 @@ class FactorInfo(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int64), ("n", ctypes.c_int64), ("transposed", ctypes.c_int32),
                 ("gram_dtype", ctypes.c_int32), ("max_diag", ctypes.c_double),
                 ("last_pivot", ctypes.c_double), ("first_rejected", ctypes.c_double),
-                ("tau", ctypes.c_double), ("noise_floor", ctypes.c_double), ("reliable", ctypes.c_int32)]
+                ("tau", ctypes.c_double), ("noise_floor", ctypes.c_double), ("reliable", ctypes.c_int32),
+                ("certified_full_rank", ctypes.c_int32)]
 
     def as_dict(self):
         return {"rank": int(self.rank), "n": int(self.n), "transposed": bool(self.transposed),
                 "gram_dtype": _DT_NAME.get(int(self.gram_dtype), "?"), "max_diag": float(self.max_diag),
                 "last_pivot": float(self.last_pivot), "first_rejected": float(self.first_rejected),
                 "tau": float(self.tau), "noise_floor": float(self.noise_floor),
-                "reliable": bool(self.reliable)}
+                "reliable": bool(self.reliable), "certified_full_rank": bool(self.certified_full_rank)}
 
 
 class TrainInfo(ctypes.Structure):
@@ -110,6 +111,8 @@ def _load():
         "elm_predict": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, vp],
                         i32),
         "elm_predict_hidden": ([vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp], i32),
+        "elm_set_option": ([vp, i32, i64], i32),
+        "elm_get_option": ([vp, i32, ctypes.POINTER(i64)], i32),
         "elm_profile_enable": ([vp, i32], i32),
         "elm_profile_read": ([vp, ctypes.POINTER(StageTimes)], i32),
     }
@@ -125,7 +128,7 @@ EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", 
             "elm_hidden", "elm_gram", "elm_rank_factor", "elm_factor_rank", "elm_factor_pivots",
             "elm_factor_destroy", "elm_factor_get_info", "elm_train", "elm_train_batched",
             "elm_pinv_solve", "elm_predict", "elm_predict_hidden",
-            "elm_profile_enable", "elm_profile_read"]
+            "elm_set_option", "elm_get_option", "elm_profile_enable", "elm_profile_read"]
 
 
 def _status_string(st: int) -> str:
@@ -344,6 +347,30 @@ def elm_predict(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, beta: torch.T
     h.check(_lib.elm_predict(h.ptr, N, d, L, m, xp, ldx, wp, ldw, bp, _DT[X.dtype], betap, ldbeta, yp, ldy,
                              lp), "elm_predict")
     return Y, labels
+
+
+OPTIONS = {"full_rank_min_order": 1, "batch_workers": 2}
+
+
+def set_option(name: str, value: int) -> int:
+    """Set a tuning option of the current device's handle (elm_set_option);
+    returns the previous value."""
+    if name not in OPTIONS:
+        raise ValueError(f"unknown option {name!r}; known: {sorted(OPTIONS)}")
+    h = handle()
+    old = ctypes.c_int64()
+    h.check(_lib.elm_get_option(h.ptr, OPTIONS[name], ctypes.byref(old)), "elm_get_option")
+    h.check(_lib.elm_set_option(h.ptr, OPTIONS[name], int(value)), "elm_set_option")
+    return int(old.value)
+
+
+def get_option(name: str) -> int:
+    if name not in OPTIONS:
+        raise ValueError(f"unknown option {name!r}; known: {sorted(OPTIONS)}")
+    h = handle()
+    v = ctypes.c_int64()
+    h.check(_lib.elm_get_option(h.ptr, OPTIONS[name], ctypes.byref(v)), "elm_get_option")
+    return int(v.value)
 
 
 def profile_enable(on: bool = True) -> None:

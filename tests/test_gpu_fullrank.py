@@ -1,0 +1,105 @@
+"""GPU: the certified full-rank path of the rank step (unpivoted blocked
+Cholesky, certificate lambda = 1 / max_j (M^-1)_jj), against the FP64 CPU
+oracle's greedy pivoted Cholesky.  The order threshold is lowered so that
+small problems take the path; ragged last blocks (300 = 2 x 128 + 44, 1000 =
+7 x 128 + 104), the N < L route, a rank-deficient Gram (the unpivoted
+factorisation stops and the greedy rule runs) and a threshold the
+certificate cannot clear (the greedy rule runs, full rank) are covered."""
+import numpy as np
+import pytest
+
+import elm_workloads as wl
+import oracle as O
+
+from gpu_helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def elm():
+    from paper_2011_02436_amd import elm as mod
+    return mod
+
+
+@pytest.fixture
+def low_threshold(elm):
+    old = elm.set_option("full_rank_min_order", 1)
+    yield
+    elm.set_option("full_rank_min_order", old)
+
+
+def _dev(p):
+    return to_dev(p.X), to_dev(p.W), to_dev(p.b), to_dev(p.T)
+
+
+def _reference(p):
+    H = O.hidden(p.X, p.W, p.b)
+    M = H.T @ H if p.N >= p.L else H @ H.T
+    K = p.N if p.N >= p.L else p.L
+    R, piv, r = O.pivoted_cholesky(M, K=K)
+    beta, F = O.solve(H, p.T)
+    assert F.r == r
+    lam = 1.0 / np.linalg.inv(M).diagonal().max() if r == M.shape[0] else 0.0
+    s = np.linalg.svd(H[:, F.piv[:r]] if p.N >= p.L else H[F.piv[:r], :], compute_uv=False)
+    return beta, r, R[r - 1, r - 1] ** 2, lam, (s[0] / s[-1]) ** 2
+
+
+FULL = [(6000, 64, 300, 50), (8000, 128, 1000, 52), (4000, 16, 300, 53), (500, 64, 1200, 55)]
+
+
+@pytest.mark.parametrize("shape", FULL, ids=[f"N{s[0]}_L{s[2]}" for s in FULL])
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_certified_full_rank_matches_oracle(elm, low_threshold, shape, precision):
+    N, d, L, seed = shape
+    p = wl.random_problem(seed, N, d, L, 3)
+    beta_ref, r, last_greedy, lam, k2 = _reference(p)
+    res = elm.train(*_dev(p), precision=precision, ir_tol=1e-12 if precision == "fp64" else 1e-10)
+    fi = res.info["factor"]
+    print(f"N={N} L={L} {precision}: certified {fi['certified_full_rank']} rank {res.rank} (oracle {r}); "
+          f"lambda {fi['last_pivot']:.6e} (oracle 1/max(M^-1)_jj {lam:.6e}, last greedy pivot "
+          f"{last_greedy:.6e}); tau {fi['tau']:.3e}")
+    assert fi["certified_full_rank"] and fi["reliable"]
+    assert res.rank == r == min(N, L)
+    assert fi["first_rejected"] == -np.inf
+    # the certificate is the exact leave-one-out bound, below the greedy rule's last pivot
+    if precision == "fp64":
+        assert abs(fi["last_pivot"] - lam) <= 1e-8 * lam
+    else:  # the BF16 Gram's own bound: within the Gram's rounding of the FP64 one
+        assert abs(fi["last_pivot"] - lam) <= 0.05 * lam
+    assert fi["last_pivot"] <= last_greedy * (1 + 1e-8) or precision != "fp64"
+    assert fi["last_pivot"] >= 64 * fi["tau"]
+    err = O.rel_err(res.beta.cpu().numpy(), beta_ref)
+    tol = max(1e-10, 50 * k2 * EPS) if precision == "fp64" else 1e-6
+    assert err <= tol, (err, tol)
+
+
+def test_rank_deficient_gram_falls_back_to_greedy(elm, low_threshold):
+    p = wl.random_problem(54, 3000, 64, 700, 3, n_dup=70)
+    beta_ref, r, _, _, k2 = _reference(p)
+    res = elm.train(*_dev(p), precision="fp64", ir_tol=1e-12)
+    fi = res.info["factor"]
+    assert not fi["certified_full_rank"]
+    assert res.rank == r == p.structural_rank == 630
+    assert O.rel_err(res.beta.cpu().numpy(), beta_ref) <= max(1e-10, 50 * k2 * EPS)
+
+
+def test_threshold_above_certificate_falls_back_to_greedy(elm, low_threshold):
+    # tau_rel = 1e-3: 64 tau is above lambda (~2e-2 of the largest diagonal),
+    # so nothing is certified; the greedy rule still keeps every position
+    p = wl.random_problem(50, 6000, 64, 300, 3)
+    res = elm.train(*_dev(p), precision="fp64", ir_tol=1e-12, tau_rel=1e-3)
+    fi = res.info["factor"]
+    H = O.hidden(p.X, p.W, p.b)
+    _, _, r = O.pivoted_cholesky(H.T @ H, tau=fi["tau"])
+    assert not fi["certified_full_rank"]
+    assert res.rank == r == 300
+
+
+def test_default_threshold_keeps_small_grams_on_the_greedy_path(elm):
+    assert elm.get_option("full_rank_min_order") == 4097
+    p = wl.random_problem(50, 6000, 64, 300, 3)
+    res = elm.train(*_dev(p), precision="fp64", ir_tol=1e-12)
+    assert not res.info["factor"]["certified_full_rank"]

@@ -327,3 +327,23 @@ def test_planted_wrong_tau_changes_rank():
     M = H.T @ H
     _, _, r = O.pivoted_cholesky(M, tau=1e-2 * np.max(np.diag(M)))
     assert r != p.structural_rank
+
+
+def test_greedy_pivots_bounded_by_inverse_diagonal():
+    """The certified full-rank path rests on two facts about the greedy
+    diagonally pivoted Cholesky (Section 3's rank step): its pivots never
+    increase, and its last pivot is the Schur complement of the last index
+    with respect to all others, 1 / (M^-1)_jj; so every pivot is at least
+    1 / max_j (M^-1)_jj."""
+    for seed, (N, d, L) in enumerate([(400, 8, 60), (900, 32, 120), (300, 4, 40)]):
+        p = wl.random_problem(700 + seed, N, d, L, 2)
+        H = O.hidden(p.X, p.W, p.b)
+        M = H.T @ H
+        R, piv, r = O.pivoted_cholesky(M, tau=0.0)
+        assert r == L
+        pivots = np.diag(R) ** 2
+        assert np.all(np.diff(pivots) <= 1e-12 * pivots[0])
+        Minv = np.linalg.inv(M)
+        assert abs(pivots[-1] * Minv[piv[-1], piv[-1]] - 1.0) <= 1e-6
+        lam = 1.0 / Minv.diagonal().max()
+        assert pivots.min() >= lam * (1 - 1e-6)
