@@ -14,11 +14,14 @@
 // anyway) decide it.  Otherwise the caller runs the greedy factorisation.
 //
 // Organisation, per diagonal block of CB positions:
-//   potrf_block   one workgroup: the block's Cholesky factor in LDS, written
-//                 to U, then its inverse, written to W
+//   strip         the block rows take the updates of the earlier block rows
+//                 of their group of GB rows            (FP64 MFMA GEMM)
+//   potrf_block   one workgroup: the block's Cholesky factor (held in
+//                 registers), written to U, then its inverse, written to W
 //   copy          the block rows right of the diagonal block into T
 //   product       U12 = W^T T                           (FP64 MFMA GEMM)
-//   update        S -= U12^T U12, upper tiles only       (FP64 MFMA GEMM)
+// and per group: S -= U_g^T U_g on the trailing matrix's upper tiles, with
+// U_g the group's GB rows (FP64 MFMA GEMM, GB deep).
 // A block that meets a pivot <= thr sets a device flag, and every later
 // kernel returns at once.
 #include "elm_internal.h"
@@ -30,6 +33,7 @@ namespace elm {
 namespace {
 
 constexpr int CB = 128;    // diagonal block
+constexpr int GB = 4 * CB; // block rows per trailing update
 constexpr int CPT = 1024;  // threads of the block kernel
 
 __global__ void clear_flag_kernel(int* flag) {
@@ -53,64 +57,128 @@ __global__ void zero_lower_kernel(int64_t n, double* __restrict__ U, int64_t ldu
             U[i * ldu + c] = 0.0;
 }
 
+// The CB x CB block lives in registers: thread (ty, tx) of a 32 x 32 grid
+// holds the 4 x 4 elements (ty + 32 a, tx + 32 b), so the 32 owners of a row
+// are one half of a wave.  Step j: the owners of row j take its pivot from
+// the diagonal owner by a lane shuffle, scale the row and publish it in LDS
+// (with the stop decision); after one block barrier every thread applies
+// the row to its elements.  Row and pivot buffers alternate between steps,
+// so one barrier per step suffices.
 __global__ __launch_bounds__(CPT) void potrf_block_kernel(double* __restrict__ U, int64_t ldu,
                                                           int64_t k0, int nb, double thr,
                                                           double* __restrict__ W, int* flag) {
-    __shared__ double A[CB][CB + 1];
+    static_assert(CB == 128 && CPT == 1024, "4 x 4 elements per thread of a 32 x 32 grid");
+    __shared__ double rowb[2][CB];
+    __shared__ int stop[2];
+    __shared__ double Us[CB][CB + 1];  // the factor, for the inverse's columns
     if (*flag) return;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += CPT) {
-        const int i = e / nb, c = e % nb;
-        A[i][c] = c >= i ? U[(k0 + i) * ldu + k0 + c] : 0.0;
-    }
-    __syncthreads();
-    // right-looking: row j scaled by its pivot's root, trailing block updated
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int lane = threadIdx.x & 63, half = lane & 32;  // this row's lanes: half .. half + 31
+    double u[4][4], w[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ty + 32 * a, c = tx + 32 * b;
+            u[a][b] = (i < nb && c < nb && c >= i) ? U[(k0 + i) * ldu + k0 + c] : 0.0;
+        }
+    // right-looking Cholesky: row j scaled by the root of its pivot, then
+    // u[i][c] -= U[j][i] U[j][c] for j < i <= c
     for (int j = 0; j < nb; ++j) {
-        const double d = A[j][j];
-        if (!(d > thr)) {  // the same value for every thread: the block leaves together
-            if (tid == 0) *flag = 1;
+        const int jl = j & 31, jh = j >> 5, pb = j & 1;
+        if (ty == jl) {
+            double v[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                v[b] = 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    if (a == jh) v[b] = u[a][b];
+            }
+            // the pivot: element (j, j) sits in lane half + jl, slot b = jh
+            double dv = 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b == jh) dv = v[b];
+            const double d = __shfl(dv, half + jl);
+            const bool ok = d > thr;
+            const double rj = sqrt(ok ? d : 1.0), inv = 1.0 / rj;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = tx + 32 * b;
+                const double x = c > j ? v[b] * inv : (c == j ? rj : 0.0);
+                rowb[pb][c] = x;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    if (a == jh) u[a][b] = x;
+            }
+            if (tx == 0) stop[pb] = ok ? 0 : 1;
+        }
+        __syncthreads();
+        if (stop[pb]) {  // the same value for every thread: the block leaves together
+            if (threadIdx.x == 0) *flag = 1;
             return;
         }
-        const double rj = sqrt(d);
-        __syncthreads();  // every thread has read the pivot
-        if (tid < nb - j) {
-            const int c = j + tid;
-            A[j][c] = c == j ? rj : A[j][c] / rj;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int i = ty + 32 * a;
+            const double ri = rowb[pb][i];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = tx + 32 * b;
+                if (i > j && c >= i) u[a][b] -= ri * rowb[pb][c];
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ty + 32 * a, c = tx + 32 * b;
+            const double x = c >= i ? u[a][b] : 0.0;
+            Us[i][c] = x;
+            if (i < nb && c < nb) U[(k0 + i) * ldu + k0 + c] = x;
+        }
+    // W = U^-1 from the bottom row up: W[k][:] /= U[k][k], then
+    // W[i][:] -= U[i][k] W[k][:] for i < k  (W starts as the identity).
+    // The owners of row k scale it and publish it; one barrier per step.
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) w[a][b] = (ty + 32 * a == tx + 32 * b) ? 1.0 : 0.0;
+    __syncthreads();  // Us complete
+    for (int k = nb - 1; k >= 0; --k) {
+        const int kl = k & 31, kh = k >> 5, pb = k & 1;
+        if (ty == kl) {
+            const double rk = 1.0 / Us[k][k];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                if (a == kh) {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const double x = w[a][b] * rk;
+                        w[a][b] = x;
+                        rowb[pb][tx + 32 * b] = x;
+                    }
+                }
         }
         __syncthreads();
-        const int m = nb - 1 - j;
-        for (int e = tid; e < m * m; e += CPT) {
-            const int ii = e / m, cc = e % m;
-            if (cc >= ii) A[j + 1 + ii][j + 1 + cc] -= A[j][j + 1 + ii] * A[j][j + 1 + cc];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int i = ty + 32 * a;
+            const double uik = Us[i][k];
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (i < k) w[a][b] -= uik * rowb[pb][tx + 32 * b];
         }
-        __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += CPT) {
-        const int i = e / nb, c = e % nb;
-        U[(k0 + i) * ldu + k0 + c] = c >= i ? A[i][c] : 0.0;
-    }
-    // in-place inverse, column by column: with columns < j already inverted,
-    //   W[i][j] = -(sum_{i <= k < j} W[i][k] U[k][j]) / U[j][j],  W[j][j] = 1 / U[j][j]
-    // (8 lanes per row i share its dot product)
-    static_assert(CPT >= 8 * CB, "eight lanes per row");
-    const int ri = tid >> 3, sub = tid & 7;
-    for (int j = 0; j < nb; ++j) {
-        double v = 0.0;
-        if (ri < j)
-            for (int k = ri + sub; k < j; k += 8) v += A[ri][k] * A[k][j];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        const double inv = 1.0 / A[j][j];
-        __syncthreads();
-        if (ri < j && sub == 0) A[ri][j] = -v * inv;
-        if (tid == 0) A[j][j] = inv;
-        __syncthreads();
-    }
-    for (int e = tid; e < nb * nb; e += CPT) {
-        const int i = e / nb, c = e % nb;
-        W[i * CB + c] = c >= i ? A[i][c] : 0.0;
-    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ty + 32 * a, c = tx + 32 * b;
+            W[i * CB + c] = (i < nb && c < nb && c >= i) ? w[a][b] : 0.0;
+        }
 }
 
 // T (nb x nc, ld nc) = U[k0 .. k0 + nb)[c0 .. c0 + nc)
@@ -184,22 +252,36 @@ bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, 
     copy_upper_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)std::min<int64_t>(n, 65535)), 256, 0,
                         s>>>(n, M, ldm, U, n);
     ELM_LAUNCH_CHECK();
-    for (int64_t k0 = 0; k0 < n; k0 += CB) {
-        const int nb = (int)std::min<int64_t>(CB, n - k0);
-        potrf_block_kernel<<<1, CPT, 0, s>>>(U, n, k0, nb, thr, W, flag);
-        ELM_LAUNCH_CHECK();
-        const int64_t c0 = k0 + nb, nc = n - c0;
-        if (nc <= 0) break;
-        copy_rows_kernel<<<dim3((unsigned)cdiv(nc, 256), (unsigned)nb), 256, 0, s>>>(nb, nc, U, n, k0,
-                                                                                   c0, T, flag);
-        ELM_LAUNCH_CHECK();
-        // U12 = W^T T: A(i, k) = W[k][i]
-        gemm_f64_batched(s, 1, nb, nc, nb, 1.0, W, 1, CB, 0, T, nc, 1, 0, 0.0, U + k0 * n + c0, n, 0,
-                         false, false, false, flag);
-        // S -= U12^T U12 on the upper tiles: A(i, k) = U12[k][i], B(k, j) = U12[k][j]
-        const double* U12 = U + k0 * n + c0;
-        gemm_f64_batched(s, 1, nc, nc, nb, -1.0, U12, 1, n, 0, U12, n, 1, 0, 1.0, U + c0 * n + c0, n,
-                         0, false, false, true, flag);
+    // Groups of GB block rows: inside a group each block row first takes the
+    // updates of the group's earlier rows (left-looking, one product), so the
+    // trailing matrix is updated once per group with a GB-row-deep product.
+    for (int64_t g0 = 0; g0 < n; g0 += GB) {
+        const int64_t g1 = std::min<int64_t>(g0 + GB, n);
+        for (int64_t k0 = g0; k0 < g1; k0 += CB) {
+            const int nb = (int)std::min<int64_t>(CB, n - k0);
+            if (k0 > g0) {
+                // rows k0 .. k0 + nb, columns k0 .. n  -=  U[g0 .. k0)[k0 ..]^T U[g0 .. k0)[k0 ..]
+                const double* Ug = U + g0 * n + k0;
+                gemm_f64_batched(s, 1, nb, n - k0, k0 - g0, -1.0, Ug, 1, n, 0, Ug, n, 1, 0, 1.0,
+                                 U + k0 * n + k0, n, 0, false, false, true, flag);
+            }
+            potrf_block_kernel<<<1, CPT, 0, s>>>(U, n, k0, nb, thr, W, flag);
+            ELM_LAUNCH_CHECK();
+            const int64_t c0 = k0 + nb, nc = n - c0;
+            if (nc <= 0) break;
+            copy_rows_kernel<<<dim3((unsigned)cdiv(nc, 256), (unsigned)nb), 256, 0, s>>>(nb, nc, U, n,
+                                                                                       k0, c0, T, flag);
+            ELM_LAUNCH_CHECK();
+            // U12 = W^T T: A(i, k) = W[k][i]
+            gemm_f64_batched(s, 1, nb, nc, nb, 1.0, W, 1, CB, 0, T, nc, 1, 0, 0.0, U + k0 * n + c0, n,
+                             0, false, false, false, flag);
+        }
+        if (g1 < n) {
+            // S -= U[g0 .. g1)[g1 ..]^T U[g0 .. g1)[g1 ..] on the upper tiles
+            const double* Ug = U + g0 * n + g1;
+            gemm_f64_batched(s, 1, n - g1, n - g1, g1 - g0, -1.0, Ug, 1, n, 0, Ug, n, 1, 0, 1.0,
+                             U + g1 * n + g1, n, 0, false, false, true, flag);
+        }
     }
     int hflag = 0;
     ELM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
