@@ -1,0 +1,150 @@
+"""GPU: the training path at the workloads' full sizes, in the configuration
+the benchmark times, checked through properties that hold at any size (the
+FP64 CPU oracle cannot form these Grams in test time):
+
+* rank: the structural rank of the planted node duplication;
+* beta solves the least-squares problem: the relative normal-equation
+  residual ||H^T (T - H beta)|| / ||H^T T||, recomputed here with plain torch
+  FP64 products (not the library's kernels), is <= 1e-10 at the benchmark's
+  own stopping tolerance (and the library's own report agrees);
+* beta is the minimum-norm solution: the null space of H is spanned by the
+  differences of duplicated columns, so beta is orthogonal to it exactly when
+  it is equal across each group of duplicates;
+* sampled entries of H and of the training-set outputs H beta against FP64
+  NumPy evaluations of their definitions, and the BF16 copy against the
+  round-to-nearest-even of H.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import elm_workloads as wl
+
+from gpu_helpers import bf16_rne, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def elm():
+    from paper_2011_02436_amd import elm as mod
+    return mod
+
+
+def _ne_residual_torch(H64, T, beta, chunk=65536):
+    """||H^T (T - H beta)||_F / ||H^T T||_F with torch FP64 products, row chunks."""
+    g = torch.zeros((H64.shape[1], T.shape[1]), dtype=torch.float64, device=H64.device)
+    z = torch.zeros_like(g)
+    for s in range(0, H64.shape[0], chunk):
+        Hc = H64[s:s + chunk]
+        Tc = T[s:s + chunk]
+        e = Tc - Hc @ beta
+        g += Hc.T @ e
+        z += Hc.T @ Tc
+    return float(torch.linalg.norm(g) / torch.linalg.norm(z))
+
+
+def _sampled_h(p, H64, rng, count=64):
+    """Sampled H entries, their FP64 NumPy values and a bound on the
+    difference: the two d-term dot products may round in different orders
+    (|dz| <= (d + 1) u sum |x_k w_k| + |b| ... ), which moves sigma(z) by
+    (1 - sigma) |dz| relative, plus a few roundings in exp and the division."""
+    u = 2.0 ** -53
+    rows = rng.integers(0, p.N, size=count)
+    cols = rng.integers(0, p.L, size=count)
+    prods = p.X[rows] * p.W[:, cols].T
+    z = prods.sum(axis=1) + p.b[cols]
+    ref = 1.0 / (1.0 + np.exp(-z))
+    dz = 2 * (p.d + 1) * u * (np.abs(prods).sum(axis=1) + np.abs(p.b[cols]))
+    bound = ref * ((1.0 - ref) * dz + 8 * u)
+    got = H64[torch.from_numpy(rows).to(H64.device), torch.from_numpy(cols).to(H64.device)].cpu().numpy()
+    return rows, cols, got, ref, bound
+
+
+def _group_spread(beta, groups):
+    """Largest deviation of beta within a group of duplicated columns."""
+    worst = 0.0
+    order = np.argsort(groups, kind="stable")
+    g_sorted = groups[order]
+    starts = np.flatnonzero(np.r_[True, g_sorted[1:] != g_sorted[:-1]])
+    ends = np.r_[starts[1:], len(order)]
+    for s, e in zip(starts, ends):
+        if e - s > 1:
+            blk = beta[order[s:e]]
+            worst = max(worst, float(np.abs(blk - blk.mean(axis=0)).max()))
+    return worst
+
+
+def test_full_size_precision_form(elm):
+    """N=500000, d=128, L=10000, m=4; BF16 Gram, FP64 rank decision and
+    refinement to 1e-10, training-set outputs: the benchmark's step."""
+    p = wl.smooth_regression()
+    X, W, b, T = to_dev(p.X), to_dev(p.W), to_dev(p.b), to_dev(p.T)
+    H64 = torch.empty((p.N, p.L), dtype=torch.float64, device=X.device)
+    Hlp = torch.empty((p.L, p.N), dtype=torch.bfloat16, device=X.device)
+    res = elm.train(X, W, b, T, precision="bf16", ir_tol=1e-10, H64=H64, Hlp=Hlp, outputs=True)
+    torch.cuda.synchronize()
+    fi = res.info["factor"]
+    ne = _ne_residual_torch(H64, T, res.beta)
+    print(f"C4: rank {res.rank}, gram {res.info['gram_dtype']}, certified {fi['certified_full_rank']}, "
+          f"library NE {res.info['ne_residual']:.3e}, torch NE {ne:.3e}, its {res.info['iterations']}")
+    assert res.rank == p.structural_rank == 10000
+    assert res.info["gram_dtype"] == "bf16" and res.info["escalations"] == 0
+    assert fi["reliable"]
+    assert res.info["ne_residual"] <= 1e-10
+    assert ne <= 1e-10
+    # two FP64 evaluations of a residual this small differ in their rounding
+    assert abs(ne - res.info["ne_residual"]) <= 0.5 * res.info["ne_residual"] + 1e-12
+    rng = np.random.default_rng(123)
+    rows, cols, got, ref, bound = _sampled_h(p, H64, rng)
+    assert np.all(np.abs(got - ref) <= bound)
+    lp = Hlp[torch.from_numpy(cols).to(X.device), torch.from_numpy(rows).to(X.device)].double().cpu().numpy()
+    assert np.array_equal(lp, bf16_rne(got))
+    beta = res.beta.cpu().numpy()
+    ridx = rng.integers(0, p.N, size=16)
+    for i in ridx:
+        h = H64[int(i)].cpu().numpy()
+        want = np.array([math.fsum(h * beta[:, k]) for k in range(p.m)])
+        assert np.max(np.abs(res.Y[int(i)].cpu().numpy() - want)) <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_rank_deficient_mixture(elm, precision):
+    """N=100000, d=54, L=5000 with 500 duplicated nodes (rank 4500), 7 classes."""
+    p = wl.mixture_rankdef()
+    X, W, b, T = to_dev(p.X), to_dev(p.W), to_dev(p.b), to_dev(p.T)
+    H64 = torch.empty((p.N, p.L), dtype=torch.float64, device=X.device)
+    res = elm.train(X, W, b, T, precision=precision, ir_tol=1e-10, H64=H64)
+    torch.cuda.synchronize()
+    ne = _ne_residual_torch(H64, T, res.beta)
+    beta = res.beta.cpu().numpy()
+    spread = _group_spread(beta, p.groups) / np.abs(beta).max()
+    print(f"C3 {precision}: rank {res.rank} (structural {p.structural_rank}), gram {res.info['gram_dtype']}, "
+          f"NE {ne:.3e}, duplicate spread {spread:.2e}, its {res.info['iterations']}")
+    assert res.rank == p.structural_rank == 4500
+    assert not res.info["factor"]["certified_full_rank"]
+    assert ne <= 1e-10
+    assert spread <= 1e-9
+    rng = np.random.default_rng(7)
+    _, _, got, ref, bound = _sampled_h(p, H64, rng)
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+def test_full_size_digits_fp32_form(elm):
+    """N=60000, d=784 (80% zeros), L=2000, 10 classes; FP32 Gram + refinement."""
+    p = wl.digits_like()
+    X, W, b, T = to_dev(p.X), to_dev(p.W), to_dev(p.b), to_dev(p.T)
+    H64 = torch.empty((p.N, p.L), dtype=torch.float64, device=X.device)
+    res = elm.train(X, W, b, T, precision="fp32", ir_tol=1e-10, H64=H64, outputs=True)
+    torch.cuda.synchronize()
+    ne = _ne_residual_torch(H64, T, res.beta)
+    acc = float((res.labels.cpu().numpy() == p.labels).mean())
+    print(f"C2 fp32: rank {res.rank}, NE {ne:.3e}, its {res.info['iterations']}, training accuracy {acc:.4f}")
+    assert res.rank == p.structural_rank == 2000
+    assert res.info["gram_dtype"] == "fp32"
+    assert ne <= 1e-10
+    # labels are the arg-max of the returned outputs (lowest index on ties)
+    Y = res.Y.cpu().numpy()
+    assert np.array_equal(res.labels.cpu().numpy(), np.argmax(Y, axis=1))
