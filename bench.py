@@ -94,7 +94,8 @@ def cpu_baseline(prob, rows, nodes):
 def bench_batch(args, elm, torch, wl, dev):
     """The hidden-size sweep: 256 independent ELMs (N, L log-uniform in
     [1000, 50000] x [64, 2048], d=32, m=5, 10% duplicated nodes) trained by one
-    elm_train_batched call, BF16 form and FP64 form, to NE residual 1e-10."""
+    elm_train_batched call, BF16 and FP32 forms (with refinement) and the FP64
+    form, to NE residual 1e-10."""
     t0 = time.perf_counter()
     probs = wl.batch_sweep()
     dev_probs = [tuple(torch.from_numpy(a).to(dev) for a in (p.X, p.W, p.b, p.T)) for p in probs]
@@ -104,7 +105,7 @@ def bench_batch(args, elm, torch, wl, dev):
     log(f"batch: {len(probs)} ELMs generated and uploaded in {time.perf_counter() - t0:.1f} s")
     out = {"workload": "batch_sweep: 256 ELMs, N log-U[1000,50000], L log-U[64,2048], d=32, m=5, 10% duplicated nodes",
            "count": len(probs), "sum_N_L2": float(sum(p.N * p.L * p.L for p in probs))}
-    for precision in ("bf16", "fp64"):
+    for precision in ("bf16", "fp32", "fp64"):
         _, infos, stats = elm.train_batched(dev_probs, precision=precision, ir_tol=1e-10, H64s=H64s,
                                             betas=betas, check=False)
         torch.cuda.synchronize()

@@ -353,8 +353,10 @@ static elm_status rank_factor_impl(elm_handle* h, int64_t N, int64_t L, const vo
             f->reliable = (f->r == 0 || f->last_pivot >= 2.0 * f->noise_floor) &&
                           (f->r == n || f->first_rejected >= -2.0 * f->noise_floor);
             {
+                // a pooled factor is solved with at once (inside elm_train), so
+                // its last check can wait for the solve's first synchronisation
                 elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
-                elm::build_factor_tail(h->stream, f, h->ws);
+                elm::build_factor_tail(h->stream, f, h->ws, /*wait=*/pool == nullptr);
             }
         }
         if (rank) *rank = f->r;
@@ -492,12 +494,21 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
         elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
         elm::apply_pinv(s, f, m, T, ldt, H64, ldh64, beta, ldbeta, ws);
     }
+    // a factor built without waiting: its Gram-of-G flag is read at the
+    // first synchronisation below
+    int pd_bad = 0;
+    if (f->pd_flag)
+        ELM_HIP_TRY(hipMemcpyAsync(&pd_bad, f->pd_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    auto check_pd = [&] {
+        if (pd_bad) throw elm::Error{ELM_ERR_NOT_PSD, "Gram of G is not positive definite"};
+    };
     if (ir_max_iter == 0) {
         if (Y || labels) {
             elm::StageScope sc(pr, ELM_STAGE_PREDICT, s);
             elm::launch_hidden_output(s, N, L, m, H64, ldh64, beta, ldbeta, Y, ldy, labels);
         }
         ELM_HIP_TRY(hipStreamSynchronize(s));
+        check_pd();
         return result;
     }
     if (f->transposed && !z_ready) {
@@ -524,6 +535,7 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
         double g2 = 0;
         ELM_HIP_TRY(hipMemcpyAsync(&g2, nrm + 1, sizeof(double), hipMemcpyDeviceToHost, s));
         ELM_HIP_TRY(hipStreamSynchronize(s));
+        check_pd();
         res = z2 > 0 ? std::sqrt(g2 / z2) : std::sqrt(g2);
         if (info && it < 32) info->ne_history[it] = res;
         if (!(res > ir_tol) || it >= ir_max_iter) break;
@@ -992,7 +1004,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 } else {
                     {
                         elm::StageScope sc(&wh->prof, ELM_STAGE_FACTOR, ws);
-                        elm::build_factor_tail(ws, f, wh->ws);
+                        elm::build_factor_tail(ws, f, wh->ws, /*wait=*/false);
                     }
                     if (it.fuse_z) {
                         double* Z = (double*)wh->ws.get("ps_Z", (size_t)p.L * p.m * sizeof(double));

@@ -166,6 +166,8 @@ struct elm_factor {
     double* UsinvT = nullptr;
     int64_t q = 0;
     bool woodbury = false;
+    // set while the Cholesky of the Gram of G has not been checked yet
+    const int* pd_flag = nullptr;
     int device = 0;
 };
 
@@ -295,7 +297,9 @@ double inv_max_row_sumsq(hipStream_t s, int64_t n, const double* X, int64_t ldx,
 void launch_iota(hipStream_t s, int64_t n, int32_t* piv);
 
 // solve.hip: dense FP64 helpers for the factor and the pseudoinverse apply
-void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws);
+// wait = false: no synchronisation; the positive-definiteness flag of the
+// Gram of G is left in f->pd_flag (a workspace word) for the solve to read.
+void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws, bool wait = true);
 void apply_pinv(hipStream_t s, const elm_factor* f, int64_t m, const double* rhs, int64_t ldr,
                 const double* H64, int64_t ldh64, double* out, int64_t ldo, Workspace& ws);
 

@@ -286,7 +286,7 @@ void apply_f_gram_inv(hipStream_t s, const elm_factor* f, int64_t m, double* y, 
 
 }  // namespace
 
-void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws) {
+void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws, bool wait) {
     const int64_t r = f->r, n = f->n, c = n - r;
     if (r == 0) return;
     f->Rinv = (double*)factor_alloc(f, "Rinv", (size_t)r * r * sizeof(double));
@@ -320,6 +320,10 @@ void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws) {
     trtri_upper(s, q, S, q, f->Usinv, q, ws);
     f->UsinvT = transposed_copy(s, q, q, f->Usinv, q,
                                 (double*)factor_alloc(f, "UsinvT", (size_t)q * q * sizeof(double)));
+    if (!wait) {  // the first solve reads the flag with its own synchronisation
+        f->pd_flag = flag;
+        return;
+    }
     int hflag = 0;
     ELM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));
