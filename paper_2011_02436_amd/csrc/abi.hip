@@ -41,6 +41,8 @@ void* Workspace::get(const std::string& name, size_t bytes) {
 }
 
 void Workspace::release() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
     for (auto& kv : bufs)
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     bufs.clear();
@@ -919,13 +921,16 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 }
                 elm::launch_diag_max(ws, it.n, it.M, it.n, dmaxs + slot[e]);
             });
-            wait_workers(h->stream);
+            // phase 2 runs on the first worker's stream (a created stream, so
+            // its fixed launch sequences can be replayed as HIP graphs)
+            hipStream_t ps = h->workers[0]->stream;
+            wait_workers(ps);
 
-            // phase 2 (handle's stream): all rank decisions in shared launches
+            // phase 2: all rank decisions in shared launches
             std::vector<double> hdmax(grp.size());
             ELM_HIP_TRY(hipMemcpyAsync(hdmax.data(), dmaxs, grp.size() * sizeof(double),
-                                       hipMemcpyDeviceToHost, h->stream));
-            ELM_HIP_TRY(hipStreamSynchronize(h->stream));
+                                       hipMemcpyDeviceToHost, ps));
+            ELM_HIP_TRY(hipStreamSynchronize(ps));
             std::vector<elm::PcholProblem> pc;
             std::vector<int32_t> pc_of(count, -1);
             for (size_t i = 0; i < grp.size(); ++i) {
@@ -950,10 +955,10 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 pc.push_back(q);
             }
             {
-                elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
-                elm::pivoted_cholesky_grouped(h->stream, pc, h->ws);
+                elm::StageScope sc(&h->prof, ELM_STAGE_RANK, ps);
+                elm::pivoted_cholesky_grouped(ps, pc, h->ws);
             }
-            workers_wait(h->stream);
+            workers_wait(ps);
 
             // phase 3 (workers): factor tail, beta and refinement
             run_workers(grp, [&](elm_handle* wh, int32_t e) {

@@ -66,7 +66,8 @@ __global__ void zero_lower_kernel(int64_t n, double* __restrict__ U, int64_t ldu
 // so one barrier per step suffices.
 __global__ __launch_bounds__(CPT) void potrf_block_kernel(double* __restrict__ U, int64_t ldu,
                                                           int64_t k0, int nb, double thr,
-                                                          double* __restrict__ W, int* flag) {
+                                                          double* __restrict__ W, int64_t ldw,
+                                                          int* flag) {
     static_assert(CB == 128 && CPT == 1024, "4 x 4 elements per thread of a 32 x 32 grid");
     __shared__ double rowb[2][CB];
     __shared__ int stop[2];
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(CPT) void potrf_block_kernel(double* __restrict__ U
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int i = ty + 32 * a, c = tx + 32 * b;
-            W[i * CB + c] = (i < nb && c < nb && c >= i) ? w[a][b] : 0.0;
+            if (i < nb && c < nb) W[i * ldw + c] = c >= i ? w[a][b] : 0.0;
         }
 }
 
@@ -240,18 +241,10 @@ __global__ void iota_kernel(int64_t n, int32_t* piv) {
 
 }  // namespace
 
-bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double thr,
-                        double** R_out, elm_factor* f, Workspace& ws) {
-    *R_out = nullptr;
-    double* U = (double*)factor_alloc(f, "R", (size_t)n * n * sizeof(double));
+void cholesky_blocked(hipStream_t s, int64_t n, double* U, int64_t ldu, double thr, int* flag,
+                      Workspace& ws) {
     double* W = (double*)ws.get("fr_W", (size_t)CB * CB * sizeof(double));
     double* T = (double*)ws.get("fr_T", (size_t)CB * n * sizeof(double));
-    int* flag = (int*)ws.get("fr_flag", sizeof(int));
-    clear_flag_kernel<<<1, 64, 0, s>>>(flag);
-    ELM_LAUNCH_CHECK();
-    copy_upper_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)std::min<int64_t>(n, 65535)), 256, 0,
-                        s>>>(n, M, ldm, U, n);
-    ELM_LAUNCH_CHECK();
     // Groups of GB block rows: inside a group each block row first takes the
     // updates of the group's earlier rows (left-looking, one product), so the
     // trailing matrix is updated once per group with a GB-row-deep product.
@@ -261,28 +254,54 @@ bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, 
             const int nb = (int)std::min<int64_t>(CB, n - k0);
             if (k0 > g0) {
                 // rows k0 .. k0 + nb, columns k0 .. n  -=  U[g0 .. k0)[k0 ..]^T U[g0 .. k0)[k0 ..]
-                const double* Ug = U + g0 * n + k0;
-                gemm_f64_batched(s, 1, nb, n - k0, k0 - g0, -1.0, Ug, 1, n, 0, Ug, n, 1, 0, 1.0,
-                                 U + k0 * n + k0, n, 0, false, false, true, flag);
+                const double* Ug = U + g0 * ldu + k0;
+                gemm_f64_batched(s, 1, nb, n - k0, k0 - g0, -1.0, Ug, 1, ldu, 0, Ug, ldu, 1, 0, 1.0,
+                                 U + k0 * ldu + k0, ldu, 0, false, false, true, flag);
             }
-            potrf_block_kernel<<<1, CPT, 0, s>>>(U, n, k0, nb, thr, W, flag);
+            potrf_block_kernel<<<1, CPT, 0, s>>>(U, ldu, k0, nb, thr, W, CB, flag);
             ELM_LAUNCH_CHECK();
             const int64_t c0 = k0 + nb, nc = n - c0;
             if (nc <= 0) break;
-            copy_rows_kernel<<<dim3((unsigned)cdiv(nc, 256), (unsigned)nb), 256, 0, s>>>(nb, nc, U, n,
+            copy_rows_kernel<<<dim3((unsigned)cdiv(nc, 256), (unsigned)nb), 256, 0, s>>>(nb, nc, U, ldu,
                                                                                        k0, c0, T, flag);
             ELM_LAUNCH_CHECK();
             // U12 = W^T T: A(i, k) = W[k][i]
-            gemm_f64_batched(s, 1, nb, nc, nb, 1.0, W, 1, CB, 0, T, nc, 1, 0, 0.0, U + k0 * n + c0, n,
-                             0, false, false, false, flag);
+            gemm_f64_batched(s, 1, nb, nc, nb, 1.0, W, 1, CB, 0, T, nc, 1, 0, 0.0, U + k0 * ldu + c0,
+                             ldu, 0, false, false, false, flag);
         }
         if (g1 < n) {
             // S -= U[g0 .. g1)[g1 ..]^T U[g0 .. g1)[g1 ..] on the upper tiles
-            const double* Ug = U + g0 * n + g1;
-            gemm_f64_batched(s, 1, n - g1, n - g1, g1 - g0, -1.0, Ug, 1, n, 0, Ug, n, 1, 0, 1.0,
-                             U + g1 * n + g1, n, 0, false, false, true, flag);
+            const double* Ug = U + g0 * ldu + g1;
+            gemm_f64_batched(s, 1, n - g1, n - g1, g1 - g0, -1.0, Ug, 1, ldu, 0, Ug, ldu, 1, 0, 1.0,
+                             U + g1 * ldu + g1, ldu, 0, false, false, true, flag);
         }
     }
+    // the updates left values below the diagonal of the blocks that straddle
+    // it; U must be zero there
+    zero_lower_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)std::min<int64_t>(n, 65535)), 256, 0,
+                        s>>>(n, U, ldu);
+    ELM_LAUNCH_CHECK();
+}
+
+void cholesky_inverse_small(hipStream_t s, int64_t q, double* A, int64_t lda, double* Ainv,
+                            int64_t ldi, int* flag) {
+    if (q <= 0) return;
+    if (q > CB) throw Error{ELM_ERR_INVALID_ARG, "cholesky_inverse_small: order above 128"};
+    potrf_block_kernel<<<1, CPT, 0, s>>>(A, lda, 0, (int)q, 0.0, Ainv, ldi, flag);
+    ELM_LAUNCH_CHECK();
+}
+
+bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double thr,
+                        double** R_out, elm_factor* f, Workspace& ws) {
+    *R_out = nullptr;
+    double* U = (double*)factor_alloc(f, "R", (size_t)n * n * sizeof(double));
+    int* flag = (int*)ws.get("fr_flag", sizeof(int));
+    clear_flag_kernel<<<1, 64, 0, s>>>(flag);
+    ELM_LAUNCH_CHECK();
+    copy_upper_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)std::min<int64_t>(n, 65535)), 256, 0,
+                        s>>>(n, M, ldm, U, n);
+    ELM_LAUNCH_CHECK();
+    cholesky_blocked(s, n, U, n, thr, flag, ws);
     int hflag = 0;
     ELM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));
@@ -290,11 +309,6 @@ bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, 
         if (!f->pool) (void)hipFree(U);
         return false;
     }
-    // the updates above left values below the diagonal of the trailing blocks
-    // that straddle it; U must be zero there
-    zero_lower_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)std::min<int64_t>(n, 65535)), 256, 0,
-                        s>>>(n, U, n);
-    ELM_LAUNCH_CHECK();
     *R_out = U;
     return true;
 }

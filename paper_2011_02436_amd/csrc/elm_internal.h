@@ -100,9 +100,24 @@ struct StageScope {
 struct Workspace {
     std::vector<std::pair<std::string, Buffer>> bufs;
     std::vector<std::string> tables;  // buffers holding an uploaded constant table
+    // instantiated HIP graphs of fixed launch sequences, by a key naming
+    // everything their kernel arguments depend on (the most recent 16)
+    std::vector<std::pair<std::string, hipGraphExec_t>> graphs;
     Profiler* prof = nullptr;
     void* get(const std::string& name, size_t bytes);
     void release();
+    hipGraphExec_t find_graph(const std::string& key) const {
+        for (const auto& g : graphs)
+            if (g.first == key) return g.second;
+        return nullptr;
+    }
+    void put_graph(const std::string& key, hipGraphExec_t g) {
+        if (graphs.size() >= 16) {
+            (void)hipGraphExecDestroy(graphs.front().second);
+            graphs.erase(graphs.begin());
+        }
+        graphs.push_back({key, g});
+    }
     bool has_table(const std::string& name) const {
         for (const auto& t : tables)
             if (t == name) return true;
@@ -290,6 +305,15 @@ void gemm_f64_batched(hipStream_t s, int64_t batch, int64_t M, int64_t N, int64_
 // is <= thr.  Synchronises the stream once.
 bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double thr,
                         double** R_out, elm_factor* f, Workspace& ws);
+// In-place blocked Cholesky A = U^T U of the upper triangle of A (n x n, ld
+// lda; zero below the diagonal afterwards); flag (device) is set, and the
+// remaining work skipped, at a pivot <= thr.  No synchronisation.
+void cholesky_blocked(hipStream_t s, int64_t n, double* A, int64_t lda, double thr, int* flag,
+                      Workspace& ws);
+// q <= 128: A = U^T U in place (upper, zero below) and Ainv = U^-1 (q x q, ld
+// ldi), one workgroup; flag set at a pivot <= 0.  No synchronisation.
+void cholesky_inverse_small(hipStream_t s, int64_t q, double* A, int64_t lda, double* Ainv,
+                            int64_t ldi, int* flag);
 // 1 / max_j sum_k X[j][k]^2 over the rows of an upper triangular n x n X (ld
 // ldx); synchronises the stream once.
 double inv_max_row_sumsq(hipStream_t s, int64_t n, const double* X, int64_t ldx, Workspace& ws);

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <cmath>
@@ -1011,9 +1012,44 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
         finalize_grouped<<<dim3(1, ny), 1024, 0, s>>>(dgs);
         ELM_LAUNCH_CHECK();
     };
-    if (nbig > 0) chain(dg, nbig, probs[order[0]].n, panel_width(probs[order[0]].n));
+    // A chain's launches depend only on (descriptor address, problem count,
+    // largest order, panel width): they are captured once into a HIP graph and
+    // replayed, which takes the host's per-launch cost off the pivot steps.
+    // Streams that cannot be captured (the legacy default stream, or one that
+    // is capturing already) launch directly.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool can_graph = s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess &&
+                           cap == hipStreamCaptureStatusNone;
+    auto run_chain = [&](const GProb* dgs, int np, int64_t nmax_c, int nb) {
+        if (!can_graph) {
+            chain(dgs, np, nmax_c, nb);
+            return;
+        }
+        char key[128];
+        std::snprintf(key, sizeof(key), "pchol_chain:%p:%d:%lld:%d", (const void*)dgs, np,
+                      (long long)nmax_c, nb);
+        hipGraphExec_t exec = ws.find_graph(key);
+        if (!exec) {
+            ELM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipGraph_t graph = nullptr;
+            try {
+                chain(dgs, np, nmax_c, nb);
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &graph);
+                if (graph) (void)hipGraphDestroy(graph);
+                throw;
+            }
+            ELM_HIP_TRY(hipStreamEndCapture(s, &graph));
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) throw Error{ELM_ERR_HIP, "graph instantiation of the pivot steps failed"};
+            ws.put_graph(key, exec);
+        }
+        ELM_HIP_TRY(hipGraphLaunch(exec, s));
+    };
+    if (nbig > 0) run_chain(dg, nbig, probs[order[0]].n, panel_width(probs[order[0]].n));
     if (nlarge > nbig)
-        chain(dg + nbig, nlarge - nbig, probs[order[nbig]].n, panel_width(probs[order[nbig]].n));
+        run_chain(dg + nbig, nlarge - nbig, probs[order[nbig]].n, panel_width(probs[order[nbig]].n));
     std::vector<int> hstate((size_t)count * ST_N);
     std::vector<double> hstats((size_t)count * PS_N);
     ELM_HIP_TRY(hipMemcpyAsync(hstate.data(), states, hstate.size() * sizeof(int),

@@ -48,34 +48,6 @@ __global__ __launch_bounds__(LB) void trtri_leaf_kernel(int64_t r, const double*
         if (j < nb) X[(b0 + i) * ldx + b0 + j] = Xs[i][j];
 }
 
-// in-place upper Cholesky A = U^T U of a small SPD matrix, one block;
-// the strict lower triangle is zeroed.  flag[0] = 1 if a pivot is not positive.
-__global__ __launch_bounds__(1024) void chol_small_kernel(int64_t q, double* __restrict__ A,
-                                                          int64_t lda, int* flag) {
-    __shared__ double piv;
-    for (int64_t k = 0; k < q; ++k) {
-        if (threadIdx.x == 0) {
-            const double a = A[k * lda + k];
-            if (!(a > 0.0)) flag[0] = 1;
-            piv = sqrt(a > 0.0 ? a : 1.0);
-            A[k * lda + k] = piv;
-        }
-        __syncthreads();
-        for (int64_t j = k + 1 + threadIdx.x; j < q; j += blockDim.x) A[k * lda + j] /= piv;
-        __syncthreads();
-        const int64_t w = q - k - 1;
-        for (int64_t e = threadIdx.x; e < w * w; e += blockDim.x) {
-            const int64_t i = k + 1 + e / w, j = k + 1 + e % w;
-            if (j >= i) A[i * lda + j] -= A[k * lda + i] * A[k * lda + j];
-        }
-        __syncthreads();
-    }
-    for (int64_t e = threadIdx.x; e < q * q; e += blockDim.x) {
-        const int64_t i = e / q, j = e % q;
-        if (j < i) A[i * lda + j] = 0.0;
-    }
-}
-
 __global__ void add_identity_kernel(int64_t q, double* A, int64_t lda) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < q) A[i * lda + i] += 1.0;
@@ -314,10 +286,13 @@ void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws, bool wait) {
     ELM_LAUNCH_CHECK();
     int* flag = (int*)ws.get("ft_flag", sizeof(int));
     ELM_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
-    chol_small_kernel<<<1, 1024, 0, s>>>(q, S, q, flag);
-    ELM_LAUNCH_CHECK();
     f->Usinv = (double*)factor_alloc(f, "Usinv", (size_t)q * q * sizeof(double));
-    trtri_upper(s, q, S, q, f->Usinv, q, ws);
+    if (q <= 128) {  // factor and inverse in one workgroup
+        cholesky_inverse_small(s, q, S, q, f->Usinv, q, flag);
+    } else {
+        cholesky_blocked(s, q, S, q, 0.0, flag, ws);
+        trtri_upper(s, q, S, q, f->Usinv, q, ws);
+    }
     f->UsinvT = transposed_copy(s, q, q, f->Usinv, q,
                                 (double*)factor_alloc(f, "UsinvT", (size_t)q * q * sizeof(double)));
     if (!wait) {  // the first solve reads the flag with its own synchronisation

@@ -146,3 +146,21 @@ def test_batched_escalation_matches_single_training(elm, batch):
     assert torch.equal(betas[1], one.beta)
     assert infos[0]["escalations"] == 0 and infos[2]["escalations"] == 0
     assert stats[0] == 0 and stats[2] == 0
+
+
+def test_batched_replays_are_identical(elm, mixed):
+    # the shared pivot-step launches of a batch are captured once as a HIP
+    # graph and replayed by later calls with the same shape: every replay,
+    # with other work and synchronisations between them, gives the first
+    # call's results, which equal the single trainings'
+    probs, refs = mixed
+    dev = [_dev(p) for p in probs]
+    first, infos0, _ = elm.train_batched(dev, precision="fp64", ir_tol=1e-12)
+    for rep in range(3):
+        X, W, b, T = dev[0]
+        elm.train(X, W, b, T, precision="bf16", ir_tol=1e-10)  # unrelated eager work
+        torch.cuda.synchronize()
+        again, infos, _ = elm.train_batched(dev, precision="fp64", ir_tol=1e-12)
+        for e in range(len(probs)):
+            assert torch.equal(again[e], first[e]), (rep, e)
+            assert infos[e]["rank"] == infos0[e]["rank"] == refs[e][1]
