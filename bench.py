@@ -41,8 +41,8 @@ def parse():
     ap.add_argument("--L", type=int, default=10000)
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed FP64-form trainings (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=4000, help="oracle sample: rows at full L")
-    ap.add_argument("--cpu-nodes", type=int, default=3000, help="oracle sample: nodes for the factor")
+    ap.add_argument("--cpu-rows", type=int, default=40000, help="oracle sample: rows at full L")
+    ap.add_argument("--cpu-nodes", type=int, default=4000, help="oracle sample: nodes for the factor")
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed batches of the 256-ELM hidden-size sweep (0 = skip)")
     return ap.parse_args()
