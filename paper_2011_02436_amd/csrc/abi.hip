@@ -198,8 +198,12 @@ elm_status elm_destroy(elm_handle* h) {
     (void)hipStreamSynchronize(h->stream);
     for (elm_handle* w : h->workers) elm_destroy(w);
     h->workers.clear();
+    if (h->side) (void)hipStreamSynchronize(h->side);
     h->prof.release();
     h->ws.release();
+    for (auto& e : h->side_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (h->side) (void)hipStreamDestroy(h->side);
     if (h->owns_stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return ELM_OK;
@@ -314,10 +318,15 @@ static elm_status rank_factor_impl(elm_handle* h, int64_t N, int64_t L, const vo
             // certified full rank: every greedy pivot is at least
             // 1 / max_j (M^-1)_jj, read off the rows of the inverse factor
             const double need = std::max(64.0 * f->tau, 2.0 * f->noise_floor);
+            if (!h->side) {  // the look-ahead stream (default priority, non-blocking)
+                ELM_HIP_TRY(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+                for (auto& e : h->side_ev) ELM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            }
             bool ok;
             {
                 elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
-                ok = elm::unpivoted_cholesky(h->stream, n, M, n, need, &f->R, f, h->ws);
+                ok = elm::unpivoted_cholesky(h->stream, n, M, n, need, &f->R, f, h->ws, h->side,
+                                             h->side_ev[0], h->side_ev[1]);
             }
             if (ok) {
                 f->r = n;

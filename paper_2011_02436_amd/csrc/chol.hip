@@ -242,7 +242,9 @@ __global__ void iota_kernel(int64_t n, int32_t* piv) {
 }  // namespace
 
 void cholesky_blocked(hipStream_t s, int64_t n, double* U, int64_t ldu, double thr, int* flag,
-                      Workspace& ws) {
+                      Workspace& ws, hipStream_t side, hipEvent_t ev_main, hipEvent_t ev_side) {
+    const bool look = side && ev_main && ev_side;
+    bool side_pending = false;
     double* W = (double*)ws.get("fr_W", (size_t)CB * CB * sizeof(double));
     double* T = (double*)ws.get("fr_T", (size_t)CB * n * sizeof(double));
     // Groups of GB block rows: inside a group each block row first takes the
@@ -269,13 +271,33 @@ void cholesky_blocked(hipStream_t s, int64_t n, double* U, int64_t ldu, double t
             gemm_f64_batched(s, 1, nb, nc, nb, 1.0, W, 1, CB, 0, T, nc, 1, 0, 0.0, U + k0 * ldu + c0,
                              ldu, 0, false, false, false, flag);
         }
-        if (g1 < n) {
+        if (g1 >= n) continue;
+        if (!look) {
             // S -= U[g0 .. g1)[g1 ..]^T U[g0 .. g1)[g1 ..] on the upper tiles
             const double* Ug = U + g0 * ldu + g1;
             gemm_f64_batched(s, 1, n - g1, n - g1, g1 - g0, -1.0, Ug, 1, ldu, 0, Ug, ldu, 1, 0, 1.0,
                              U + g1 * ldu + g1, ldu, 0, false, false, true, flag);
+            continue;
+        }
+        // Look-ahead: the next group's rows [g1, g2) now (after the previous
+        // group's remote update, which also wrote them), the rows beyond g2
+        // on the side stream, overlapping the next group's diagonal blocks.
+        const int64_t g2 = std::min<int64_t>(g1 + GB, n);
+        if (side_pending) ELM_HIP_TRY(hipStreamWaitEvent(s, ev_side, 0));
+        const double* Ug = U + g0 * ldu + g1;
+        gemm_f64_batched(s, 1, g2 - g1, n - g1, g1 - g0, -1.0, Ug, 1, ldu, 0, Ug, ldu, 1, 0, 1.0,
+                         U + g1 * ldu + g1, ldu, 0, false, false, true, flag);
+        if (g2 < n) {
+            ELM_HIP_TRY(hipEventRecord(ev_main, s));
+            ELM_HIP_TRY(hipStreamWaitEvent(side, ev_main, 0));
+            const double* Ub = U + g0 * ldu + g2;
+            gemm_f64_batched(side, 1, n - g2, n - g2, g1 - g0, -1.0, Ub, 1, ldu, 0, Ub, ldu, 1, 0, 1.0,
+                             U + g2 * ldu + g2, ldu, 0, false, false, true, flag);
+            ELM_HIP_TRY(hipEventRecord(ev_side, side));
+            side_pending = true;
         }
     }
+    if (side_pending) ELM_HIP_TRY(hipStreamWaitEvent(s, ev_side, 0));
     // the updates left values below the diagonal of the blocks that straddle
     // it; U must be zero there
     zero_lower_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)std::min<int64_t>(n, 65535)), 256, 0,
@@ -292,7 +314,8 @@ void cholesky_inverse_small(hipStream_t s, int64_t q, double* A, int64_t lda, do
 }
 
 bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double thr,
-                        double** R_out, elm_factor* f, Workspace& ws) {
+                        double** R_out, elm_factor* f, Workspace& ws, hipStream_t side,
+                        hipEvent_t ev_main, hipEvent_t ev_side) {
     *R_out = nullptr;
     double* U = (double*)factor_alloc(f, "R", (size_t)n * n * sizeof(double));
     int* flag = (int*)ws.get("fr_flag", sizeof(int));
@@ -301,7 +324,7 @@ bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, 
     copy_upper_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)std::min<int64_t>(n, 65535)), 256, 0,
                         s>>>(n, M, ldm, U, n);
     ELM_LAUNCH_CHECK();
-    cholesky_blocked(s, n, U, n, thr, flag, ws);
+    cholesky_blocked(s, n, U, n, thr, flag, ws, side, ev_main, ev_side);
     int hflag = 0;
     ELM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));

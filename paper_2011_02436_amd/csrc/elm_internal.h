@@ -150,6 +150,10 @@ struct elm_handle {
     // on first use, kept for reuse of their workspaces)
     std::vector<elm_handle*> workers;
     bool owns_stream = false;
+    // second stream and its two ordering events, for work that overlaps the
+    // handle's stream inside one call (created on first use)
+    hipStream_t side = nullptr;
+    hipEvent_t side_ev[2] = {nullptr, nullptr};
     // tuning options (elm_set_option)
     int64_t full_rank_min_order = elm::FULL_RANK_MIN_ORDER;
     int batch_workers = elm::BATCH_WORKERS;
@@ -304,12 +308,17 @@ void gemm_f64_batched(hipStream_t s, int64_t batch, int64_t M, int64_t N, int64_
 // below the diagonal) and returns false without a result as soon as a pivot
 // is <= thr.  Synchronises the stream once.
 bool unpivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double thr,
-                        double** R_out, elm_factor* f, Workspace& ws);
+                        double** R_out, elm_factor* f, Workspace& ws, hipStream_t side = nullptr,
+                        hipEvent_t ev_main = nullptr, hipEvent_t ev_side = nullptr);
 // In-place blocked Cholesky A = U^T U of the upper triangle of A (n x n, ld
 // lda; zero below the diagonal afterwards); flag (device) is set, and the
 // remaining work skipped, at a pivot <= thr.  No synchronisation.
+// side (optional, with events ev_main and ev_side): a second stream on which
+// the part of each trailing update beyond the next group of block rows runs
+// while that group is factored on s.
 void cholesky_blocked(hipStream_t s, int64_t n, double* A, int64_t lda, double thr, int* flag,
-                      Workspace& ws);
+                      Workspace& ws, hipStream_t side = nullptr, hipEvent_t ev_main = nullptr,
+                      hipEvent_t ev_side = nullptr);
 // q <= 128: A = U^T U in place (upper, zero below) and Ainv = U^-1 (q x q, ld
 // ldi), one workgroup; flag set at a pivot <= 0.  No synchronisation.
 void cholesky_inverse_small(hipStream_t s, int64_t q, double* A, int64_t lda, double* Ainv,

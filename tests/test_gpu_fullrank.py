@@ -1,10 +1,11 @@
 """GPU: the certified full-rank path of the rank step (unpivoted blocked
 Cholesky, certificate lambda = 1 / max_j (M^-1)_jj), against the FP64 CPU
 oracle's greedy pivoted Cholesky.  The order threshold is lowered so that
-small problems take the path; ragged last blocks (300 = 2 x 128 + 44, 1000 =
-7 x 128 + 104), the N < L route, a rank-deficient Gram (the unpivoted
-factorisation stops and the greedy rule runs) and a threshold the
-certificate cannot clear (the greedy rule runs, full rank) are covered."""
+small problems take the path.  Covered: ragged last blocks (300 = 2 x 128 +
+44, 1000 = 7 x 128 + 104), look-ahead updates on a second stream (1300), the
+N < L route, a rank-deficient Gram (the unpivoted factorisation stops and the
+greedy rule runs) and a threshold the certificate cannot clear (the greedy
+rule runs, full rank)."""
 import numpy as np
 import pytest
 
@@ -47,7 +48,10 @@ def _reference(p):
     return beta, r, R[r - 1, r - 1] ** 2, lam, (s[0] / s[-1]) ** 2
 
 
-FULL = [(6000, 64, 300, 50), (8000, 128, 1000, 52), (4000, 16, 300, 53), (500, 64, 1200, 55)]
+# 1300 = three groups of 512 block rows: the second stream's look-ahead
+# update (rows beyond the next group) runs once
+FULL = [(6000, 64, 300, 50), (8000, 128, 1000, 52), (4000, 16, 300, 53), (500, 64, 1200, 55),
+        (9000, 128, 1300, 56)]
 
 
 @pytest.mark.parametrize("shape", FULL, ids=[f"N{s[0]}_L{s[2]}" for s in FULL])
