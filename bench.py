@@ -134,9 +134,10 @@ def bench_batch(args, elm, torch, wl, dev):
     return out
 
 
-def traffic_from_profiles(kernel_src):
+def traffic_from_profiles(kernel_src, k_splits=None):
     """HBM traffic per launch of the Gram kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary, if it was taken on the current kernel source and with the
+    K-split count this run uses."""
     path = os.path.join(ROOT, "profiles", "gram_lp256_bf16_N500000_L10000_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -148,6 +149,8 @@ def traffic_from_profiles(kernel_src):
             vals[k.strip()] = v.strip()
     if vals.get("source_sha256_16") != src_hash:
         return None
+    if k_splits is not None and (vals.get("gram_k_splits", "").split() or [""])[0] != str(k_splits):
+        return None  # the counters were taken on another tile schedule
     try:
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -194,6 +197,14 @@ def main():
         log(f"warmup {i}: rank {res.rank}, NE residual {res.info['ne_residual']:.2e}, "
             f"iterations {res.info['iterations']}")
 
+    # tile schedule of the BF16 Gram for this shape, picked by the library's
+    # autotuner on the warm-up's node-major copy (untimed, once per shape)
+    tuned = None
+    if args.precision in ("bf16", "fp16") and N >= L:
+        splits, tms = elm.autotune_gram(Hlp)
+        tuned = {"gram_k_splits": splits, "gram_ms": round(tms, 3)}
+        log(f"autotune: Gram with {splits} K splits, {tms:.2f} ms")
+
     elm.profile_enable(True)
     torch.cuda.synchronize()
     times = []
@@ -219,7 +230,8 @@ def main():
     gram_avg_ms = gram_ms / max(gram_n, 1)
     gram_flops = float(N) * L * (L + 1)
     gram_tflops = gram_flops / (gram_avg_ms * 1e-3) / 1e12 if gram_n else None
-    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_2011_02436_amd", "csrc", "gram.hip"))
+    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_2011_02436_amd", "csrc", "gram.hip"),
+                                    tuned["gram_k_splits"] if tuned else None)
     stage_ms_per_step = {k: round(v[0] / args.steps, 3) for k, v in stages.items()}
 
     # FP64 form at equal residual
@@ -279,7 +291,8 @@ def main():
         "gram_dtype_used": info_lp["gram_dtype"],
         "precision_escalations": info_lp["escalations"],
         "rank_decision": {k: info_lp["factor"][k] for k in
-                          ("max_diag", "last_pivot", "first_rejected", "tau", "noise_floor", "reliable")},
+                          ("max_diag", "last_pivot", "first_rejected", "tau", "noise_floor", "reliable",
+                           "certified_full_rank")},
         "gram_tflops": round(gram_tflops, 2) if gram_tflops else None,
         "roofline": {
             "kernel": "gram_lp256_kernel" if args.precision != "fp32" else "gram16_kernel<float>",
@@ -293,6 +306,7 @@ def main():
             "avg_launch_ms": round(gram_avg_ms, 3),
             "algorithmic_flops_per_launch": gram_flops,
         },
+        "gram_schedule": dict(tuned, chosen_by="elm_autotune_gram") if tuned else None,
         "stage_ms_per_step": stage_ms_per_step,
         "fp64_form": fp64,
         "batch_sweep": batch,

@@ -156,6 +156,24 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L,
 elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
                     elm_dtype h_dt, elm_layout layout, double* M, int64_t ldm);
 
+/* Autotuner of the 16-bit Gram's tile schedule.  The Gram of a node-major
+ * BF16/FP16 copy Hn (L x N, ld ldn >= N, N >= L; as for elm_gram) is split
+ * along the samples into work items of one 256 x 256 output tile each, and
+ * the number of splits trades the length of a work item (blocks that share
+ * operand panels stay in step, the last round is shorter) against one more
+ * FP32 partial tile per split.  This call times the Gram (and its partial
+ * sums) of the caller's data with the default rule's split count and with
+ * 1/2, 3/4, 3/2 and 2 times it (1 .. 48 splits, at least 2048 samples each),
+ * and keeps the fastest (the default's count unless another is at least 2%
+ * faster) for this (L, N, dtype) in the handle: later Grams of
+ * that shape on this handle (elm_gram, elm_rank_factor, elm_train) use it.
+ * splits_out and ms_out (host, may be NULL) receive the choice and its time
+ * in milliseconds.  Synchronises the handle's stream; uses a scratch Gram of
+ * L x L FP64 in the handle's workspace.
+ * Errors: INVALID_ARG; SHAPE; UNSUPPORTED (FP32/FP64 copies, N < L). */
+elm_status elm_autotune_gram(elm_handle* h, int64_t N, int64_t L, const void* Hn, int64_t ldn,
+                             elm_dtype dt, int32_t* splits_out, double* ms_out);
+
 /* r of a factor (host read, no synchronisation needed). */
 elm_status elm_factor_rank(const elm_factor* f, int64_t* rank);
 

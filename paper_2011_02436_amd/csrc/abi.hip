@@ -420,6 +420,64 @@ elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t 
     });
 }
 
+elm_status elm_autotune_gram(elm_handle* h, int64_t N, int64_t L, const void* Hn, int64_t ldn,
+                             elm_dtype dt, int32_t* splits_out, double* ms_out) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(N >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N and L must be >= 1");
+        REQUIRE(Hn, ELM_ERR_INVALID_ARG, "Hn must be non-null");
+        REQUIRE(dt == ELM_BF16 || dt == ELM_F16, ELM_ERR_UNSUPPORTED,
+                "the autotuner covers the BF16/FP16 Gram");
+        REQUIRE(N >= L, ELM_ERR_UNSUPPORTED, "the 16-bit Gram needs N >= L");
+        REQUIRE(ldn >= N, ELM_ERR_SHAPE, "ldn < N");
+        elm::use_device(h);
+        const int base = elm::gram_default_splits(N, L);
+        std::vector<int> cand;
+        for (double f : {1.0, 0.5, 0.75, 1.5, 2.0}) {
+            int c = (int)std::lround(base * f);
+            c = std::max(1, std::min(48, c));
+            while (c > 1 && N / c < 2048) --c;
+            if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+        }
+        double* M = (double*)h->ws.get("tune_M", (size_t)L * L * sizeof(double));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ELM_HIP_TRY(hipEventCreate(&e0));
+        ELM_HIP_TRY(hipEventCreate(&e1));
+        struct Ev {
+            hipEvent_t a, b;
+            ~Ev() {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } ev{e0, e1};
+        // the default rule's count stays unless another is at least 2% faster
+        int best = cand[0];
+        double best_ms = 1e300, base_ms = 0.0;
+        for (int c : cand) {
+            // one untimed run (tables, partial buffer), then the mean of two
+            elm::launch_gram_lp_nodes(h->stream, dt, N, L, Hn, ldn, M, L, h->ws, c);
+            ELM_HIP_TRY(hipEventRecord(e0, h->stream));
+            for (int r = 0; r < 2; ++r)
+                elm::launch_gram_lp_nodes(h->stream, dt, N, L, Hn, ldn, M, L, h->ws, c);
+            ELM_HIP_TRY(hipEventRecord(e1, h->stream));
+            ELM_HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            ELM_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            const double t = ms / 2.0;
+            if (c == cand[0]) {
+                base_ms = t;
+                best_ms = t;
+            } else if (t < best_ms && t < 0.98 * base_ms) {
+                best_ms = t;
+                best = c;
+            }
+        }
+        h->ws.put_splits(L, N, (int)dt, best);
+        if (splits_out) *splits_out = best;
+        if (ms_out) *ms_out = best_ms;
+    });
+}
+
 elm_status elm_factor_rank(const elm_factor* f, int64_t* rank) {
     if (!f || !rank) return ELM_ERR_INVALID_ARG;
     *rank = f->r;

@@ -103,9 +103,28 @@ struct Workspace {
     // instantiated HIP graphs of fixed launch sequences, by a key naming
     // everything their kernel arguments depend on (the most recent 16)
     std::vector<std::pair<std::string, hipGraphExec_t>> graphs;
+    // K-split counts of the 16-bit Gram chosen by the autotuner, by (L, N, dtype)
+    struct TunedSplits {
+        int64_t L, N;
+        int dt, splits;
+    };
+    std::vector<TunedSplits> tuned_splits;
     Profiler* prof = nullptr;
     void* get(const std::string& name, size_t bytes);
     void release();
+    int find_splits(int64_t L, int64_t N, int dt) const {
+        for (const auto& t : tuned_splits)
+            if (t.L == L && t.N == N && t.dt == dt) return t.splits;
+        return 0;
+    }
+    void put_splits(int64_t L, int64_t N, int dt, int splits) {
+        for (auto& t : tuned_splits)
+            if (t.L == L && t.N == N && t.dt == dt) {
+                t.splits = splits;
+                return;
+            }
+        tuned_splits.push_back({L, N, dt, splits});
+    }
     hipGraphExec_t find_graph(const std::string& key) const {
         for (const auto& g : graphs)
             if (g.first == key) return g.second;
@@ -231,8 +250,14 @@ void launch_gram_f64_rows(hipStream_t s, int64_t N, int64_t L, const double* H, 
 //   column Gram of a node-major low-precision copy (L x N): M = Hn Hn^T.
 //   Returns the longest run of products accumulated in FP32 before the FP64
 //   sum of the partial Grams.
+//   force_splits > 0 fixes the number of K splits (the autotuner's candidates);
+//   otherwise an ELM_GRAM_SPLITS override, the autotuner's choice for this
+//   shape, or the default rule decides.
 int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
-                             int64_t ldn, double* M, int64_t ldm, Workspace& ws);
+                             int64_t ldn, double* M, int64_t ldm, Workspace& ws,
+                             int force_splits = 0);
+//   the default rule's K splits for a 16-bit Gram of L nodes over N samples
+int gram_default_splits(int64_t N, int64_t L);
 //   *out = max_i M[i][i]  (NaN if any diagonal entry is NaN)
 void launch_diag_max(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
 

@@ -529,12 +529,20 @@ static int gram_splits_override() {
     return v;
 }
 
+int gram_default_splits(int64_t N, int64_t L) {
+    const int64_t nt = cdiv(L, GT);
+    return pick_splits(nt * (nt + 1) / 2, N);
+}
+
 int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
-                             int64_t ldn, double* M, int64_t ldm, Workspace& ws) {
+                             int64_t ldn, double* M, int64_t ldm, Workspace& ws, int force_splits) {
     if (dt == ELM_F32) return run_gram16<float, true>(s, L, N, (const float*)Hn, ldn, M, ldm, ws);
     const int64_t nt = cdiv(L, GT);
     const int64_t ntile = nt * (nt + 1) / 2;
-    const int nsplit = gram_splits_override() ? gram_splits_override() : pick_splits(ntile, N);
+    int nsplit = force_splits;
+    if (nsplit <= 0) nsplit = gram_splits_override();
+    if (nsplit <= 0) nsplit = ws.find_splits(L, N, (int)dt);
+    if (nsplit <= 0) nsplit = pick_splits(ntile, N);
     const int64_t kc_len = cdiv(cdiv(N, nsplit), GBK) * GBK;
     const int nsplit_eff = (int)cdiv(N, kc_len);
     // the work table depends only on (L, splits): built and uploaded once per workspace

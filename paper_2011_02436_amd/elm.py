@@ -111,6 +111,8 @@ def _load():
         "elm_predict": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, vp],
                         i32),
         "elm_predict_hidden": ([vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp], i32),
+        "elm_autotune_gram": ([vp, i64, i64, vp, i64, i32, ctypes.POINTER(i32),
+                               ctypes.POINTER(dbl)], i32),
         "elm_set_option": ([vp, i32, i64], i32),
         "elm_get_option": ([vp, i32, ctypes.POINTER(i64)], i32),
         "elm_profile_enable": ([vp, i32], i32),
@@ -128,7 +130,8 @@ EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", 
             "elm_hidden", "elm_gram", "elm_rank_factor", "elm_factor_rank", "elm_factor_pivots",
             "elm_factor_destroy", "elm_factor_get_info", "elm_train", "elm_train_batched",
             "elm_pinv_solve", "elm_predict", "elm_predict_hidden",
-            "elm_set_option", "elm_get_option", "elm_profile_enable", "elm_profile_read"]
+            "elm_autotune_gram", "elm_set_option", "elm_get_option", "elm_profile_enable",
+            "elm_profile_read"]
 
 
 def _status_string(st: int) -> str:
@@ -347,6 +350,22 @@ def elm_predict(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, beta: torch.T
     h.check(_lib.elm_predict(h.ptr, N, d, L, m, xp, ldx, wp, ldw, bp, _DT[X.dtype], betap, ldbeta, yp, ldy,
                              lp), "elm_predict")
     return Y, labels
+
+
+def autotune_gram(Hn: torch.Tensor) -> Tuple[int, float]:
+    """elm_autotune_gram on a node-major BF16/FP16 copy Hn (L x N): times the
+    Gram with several K-split counts and keeps the fastest for this shape in
+    the handle.  Returns (splits, milliseconds)."""
+    if Hn.dtype not in (torch.bfloat16, torch.float16) or Hn.dim() != 2 or Hn.stride(1) != 1:
+        raise ValueError("Hn must be a row-major 2-D bfloat16/float16 tensor (L x N)")
+    h = handle()
+    L, N = Hn.shape
+    sp = ctypes.c_int32()
+    ms = ctypes.c_double()
+    h.check(_lib.elm_autotune_gram(h.ptr, N, L, ctypes.c_void_p(Hn.data_ptr()), Hn.stride(0),
+                                   _DT[Hn.dtype], ctypes.byref(sp), ctypes.byref(ms)),
+            "elm_autotune_gram")
+    return int(sp.value), float(ms.value)
 
 
 OPTIONS = {"full_rank_min_order": 1, "batch_workers": 2}

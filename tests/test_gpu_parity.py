@@ -262,3 +262,28 @@ def test_predict_hidden_matches_numpy(elm):
     ref = H @ beta
     assert np.max(np.abs(Y.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
     assert np.array_equal(lab.cpu().numpy(), np.argmax(ref, axis=1))
+
+
+def test_autotuned_gram_splits(elm):
+    # the autotuner picks among the default rule's split count and its 1/2,
+    # 3/4, 3/2 and 2 multiples; the tuned Gram is still the Gram (FP32 partial
+    # sums, FP64 across them) of the rounded input, symmetric, with bitwise
+    # equal rows for equal columns
+    N, L = 300000, 2304  # 45 x 46 / 2 = 1035 tiles of 256: the many-tiles rule
+    rng = np.random.default_rng(77)
+    H64 = rng.uniform(0, 1, (N, L))
+    H64[:, 7] = H64[:, 2]
+    Hn = to_dev(H64.T.copy()).to(torch.bfloat16)
+    splits, ms = elm.autotune_gram(Hn)
+    assert 1 <= splits <= 48 and ms > 0
+    Hr = Hn.double().cpu().numpy()
+    M = elm.elm_gram(Hn, "node").cpu().numpy()
+    ref = Hr @ Hr.T
+    assert np.array_equal(M, M.T)
+    # FP32 sums over the kc = N / splits samples of a work item (rounding
+    # errors grow like sqrt(kc) 2^-24 of the sum), FP64 across items
+    kc = -(-N // splits)
+    assert np.max(np.abs(M - ref)) <= 4 * np.sqrt(kc) * 2.0 ** -24 * np.max(np.abs(ref))
+    assert np.array_equal(M[7], M[2])
+    # repeat calls with the tuned schedule are bitwise identical
+    assert np.array_equal(elm.elm_gram(Hn, "node").cpu().numpy(), M)
