@@ -316,8 +316,10 @@ typedef struct {
  * runs in three phases: (1) the hidden layer, Z = H^T T and the Gram of every
  * problem, on worker streams owned by the handle (created on first use),
  * longest first by the Gram's cost; (2) the pivoted Cholesky rank decisions
- * of all problems together on the handle's stream, one launch per pivot step
- * for the whole group (problems of order <= 512 take one workgroup each);
+ * of all problems together, one launch per pivot step for the whole group
+ * (problems of order <= 512 take one workgroup each), on the first worker's
+ * stream, where the chain of pivot steps is captured once as a HIP graph and
+ * replayed by later calls with the same group shape;
  * (3) the factor's dense tail, beta and refinement, on the worker streams.  A
  * problem whose low-precision guard fails is trained again alone from the
  * next precision (as elm_train does).  Problems are grouped so that the
