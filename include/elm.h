@@ -312,7 +312,9 @@ typedef struct {
 
 /* elm_train on each of `count` independent problems (e.g. a sweep over
  * hidden-layer sizes or seeds), with one precision form and tolerances for
- * all, and the same results as elm_train gives each problem alone.  The work
+ * all, and the same results as elm_train gives each problem alone (problems of
+ * order >= ELM_OPT_FULL_RANK_MIN_ORDER take the greedy rank rule here, not
+ * the certified full-rank path, so their beta agrees to rounding).  The work
  * runs in three phases: (1) the hidden layer, Z = H^T T and the Gram of every
  * problem, on worker streams owned by the handle (created on first use),
  * longest first by the Gram's cost; (2) the pivoted Cholesky rank decisions
