@@ -17,7 +17,10 @@ namespace {
 
 constexpr int HT = 128;  // tile: 128 samples x 128 hidden nodes
 constexpr int HK = 16;   // reduction chunk over input features
-constexpr int NT = 256;  // 4 waves in 2 x 2, each a 64 x 64 sub-tile of 4 x 4 MFMA blocks
+constexpr int NT = 512;  // 8 waves in 2 x 4, each a 64 x 32 sub-tile of 4 x 2 MFMA blocks
+constexpr int WGN = 4;   // waves across the tile's columns
+constexpr int JB = HT / WGN / 16;  // 16-column MFMA blocks per wave
+constexpr int HE = HK * HT / NT;   // staged X (and W) values per thread and chunk
 constexpr int XCDS = 8;  // blocks are dealt round-robin to the 8 XCDs
 // LDS row pitch of the k-major operand tiles: 16 elements of padding put the
 // 4 k rows one MFMA operand read touches on disjoint halves of the banks
@@ -58,7 +61,9 @@ struct HiddenSmem {
     static constexpr int LOOP = 2 * 2 * HK * HP * (int)sizeof(T);  // [buf][X|W][k][i]
     static constexpr int STAGE16 = HT * (HT + 8) * 2;                   // node-major 16-bit tile
     static constexpr int STAGE32 = HT * (HT + 4) * 4;                   // node-major FP32 tile
-    static constexpr int BYTES = LOOP > STAGE32 ? LOOP : STAGE32;
+    static constexpr int ZT = 3 * HT * HIDDEN_Z_MAX_M * 8;                 // HᵀT partials + T rows
+    static constexpr int B = LOOP > STAGE32 ? LOOP : STAGE32;
+    static constexpr int BYTES = B > ZT ? B : ZT;
 };
 
 // Tile (row_t, col_t) of block b: XCD x = b % 8 owns the column tiles
@@ -113,25 +118,30 @@ __device__ inline void store_node_major(void* __restrict__ Hlp, int64_t ldlp, bo
 // j0 + j), in a fixed order: each lane's 16 rows, then the four row groups of
 // a wave by an xor butterfly, then the two waves' halves through LDS.
 template <typename A>
-__device__ inline void tile_ht_times_t(const A (&acc)[4][4], const double* __restrict__ Tg,
+__device__ inline void tile_ht_times_t(const A (&acc)[4][JB], const double* __restrict__ Tg,
                                        int64_t ldt, int m, double* __restrict__ Zp, int64_t N,
                                        int64_t L, int64_t n0, int64_t j0, unsigned char* smem) {
     constexpr int MZ = HIDDEN_Z_MAX_M;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    double* zs = (double*)smem;  // [2][HT][MZ]
-    __syncthreads();             // the LDS staging is free
+    const int wm = wave / WGN, wn = wave % WGN;
+    double* zs = (double*)smem;         // [2][HT][MZ]
+    double* ts = zs + 2 * HT * MZ;      // the tile's rows of T, [HT][MZ]
+    __syncthreads();                    // the LDS staging is free
+    for (int e = tid; e < HT * m; e += NT) {  // coalesced: T rows are m contiguous values
+        const int r = e / m, c = e % m;
+        const int64_t gi = n0 + r;
+        ts[r * MZ + c] = gi < N ? Tg[gi * ldt + c] : 0.0;
+    }
+    __syncthreads();
     for (int c = 0; c < m; ++c) {
         double tv[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t gi = n0 + wm * 64 + i * 16 + Mfma16<double>::row(lane, v);
-                tv[i][v] = gi < N ? Tg[gi * ldt + c] : 0.0;
-            }
+            for (int v = 0; v < 4; ++v)
+                tv[i][v] = ts[(wm * 64 + i * 16 + Mfma16<double>::row(lane, v)) * MZ + c];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < JB; ++j) {
             double z = 0.0;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -139,7 +149,7 @@ __device__ inline void tile_ht_times_t(const A (&acc)[4][4], const double* __res
                 for (int v = 0; v < 4; ++v) z += acc[i][j][v] * tv[i][v];
             z += __shfl_xor(z, 16);
             z += __shfl_xor(z, 32);
-            if (lane < 16) zs[(wm * HT + wn * 64 + j * 16 + lane) * MZ + c] = z;
+            if (lane < 16) zs[(wm * HT + wn * (HT / WGN) + j * 16 + lane) * MZ + c] = z;
         }
     }
     __syncthreads();
@@ -151,7 +161,7 @@ __device__ inline void tile_ht_times_t(const A (&acc)[4][4], const double* __res
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT, 2) void hidden_kernel(int64_t N, int64_t d, int64_t L,
+__global__ __launch_bounds__(NT, 4) void hidden_kernel(int64_t N, int64_t d, int64_t L,
                                                        int64_t nrow_t, int64_t ncol_t,
                                                        const T* __restrict__ X, int64_t ldx,
                                                        const T* __restrict__ W, int64_t ldw,
@@ -171,39 +181,40 @@ __global__ __launch_bounds__(NT, 2) void hidden_kernel(int64_t N, int64_t d, int
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WGN, wn = wave % WGN;
 
-    // global -> register staging: 8 X values (one sample, 8 consecutive
-    // features) and 8 W values (one feature, 8 consecutive nodes) per thread
-    const int xr = tid >> 1, xk = (tid & 1) * 8;
-    const int wk = tid >> 4, wj = (tid & 15) * 8;
+    // global -> register staging: HE X values (one sample, HE consecutive
+    // features) and HE W values (one feature, HE consecutive nodes) per thread
+    static_assert(HE * NT == HK * HT && HT % HE == 0 && HK % HE == 0, "staging split");
+    const int xr = tid / (HK / HE), xk = (tid % (HK / HE)) * HE;
+    const int wk = tid / (HT / HE), wj = (tid % (HT / HE)) * HE;
     const int64_t gxr = n0 + xr;
-    T xv[8], wv[8];
+    T xv[HE], wv[HE];
     auto load_chunk = [&](int64_t k0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < HE; ++e) {
             const int64_t k = k0 + xk + e;
             xv[e] = (gxr < N && k < d) ? X[gxr * ldx + k] : T(0);
         }
         const int64_t kw = k0 + wk;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < HE; ++e) {
             const int64_t j = j0 + wj + e;
             wv[e] = (kw < d && j < L) ? W[kw * ldw + j] : T(0);
         }
     };
     auto store_chunk = [&](int buf) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Xs[buf][xk + e][xr] = xv[e];
+        for (int e = 0; e < HE; ++e) Xs[buf][xk + e][xr] = xv[e];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Ws[buf][wk][wj + e] = wv[e];
+        for (int e = 0; e < HE; ++e) Ws[buf][wk][wj + e] = wv[e];
     };
 
-    typename Mfma16<T>::acc_t acc[4][4];
+    typename Mfma16<T>::acc_t acc[4][JB];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = typename Mfma16<T>::acc_t{};
+        for (int j = 0; j < JB; ++j) acc[i][j] = typename Mfma16<T>::acc_t{};
 
     const int64_t nchunk = (d + HK - 1) / HK;
     load_chunk(0);
@@ -216,15 +227,15 @@ __global__ __launch_bounds__(NT, 2) void hidden_kernel(int64_t N, int64_t d, int
 #pragma unroll
         for (int kk = 0; kk < HK; kk += 4) {
             const int k = kk + (lane >> 4);
-            T a[4], bb[4];
+            T a[4], bb[JB];
 #pragma unroll
             for (int i = 0; i < 4; ++i) a[i] = Xs[buf][k][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bb[j] = Ws[buf][k][wn * 64 + j * 16 + (lane & 15)];
+            for (int j = 0; j < JB; ++j) bb[j] = Ws[buf][k][wn * (HT / WGN) + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = Mfma16<T>::op(a[i], bb[j], acc[i][j]);
+                for (int j = 0; j < JB; ++j) acc[i][j] = Mfma16<T>::op(a[i], bb[j], acc[i][j]);
         }
         if (more) store_chunk(buf ^ 1);
         __syncthreads();
@@ -237,8 +248,8 @@ __global__ __launch_bounds__(NT, 2) void hidden_kernel(int64_t N, int64_t d, int
     uint16_t* st16 = (uint16_t*)smem;  // [node][HT + 8]
     float* st32 = (float*)smem;        // [node][HT + 4]
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int lj = wn * 64 + j * 16 + (lane & 15);
+    for (int j = 0; j < JB; ++j) {
+        const int lj = wn * (HT / WGN) + j * 16 + (lane & 15);
         const int64_t gj = j0 + lj;
         const T bj_val = gj < L ? bias[gj] : T(0);
 #pragma unroll
