@@ -18,12 +18,13 @@ namespace elm {
 namespace {
 
 constexpr int BK = 16;
-constexpr int NT = 256;
 
-// TS x TS output tile, 4 waves in 2 x 2, each (TS/2) x (TS/2) as blocks of
-// 16 x 16; k-major LDS tiles, double-buffered through registers.
-template <int TS>
-__global__ __launch_bounds__(NT, 2) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+// TS x TS output tile, NTH / 64 waves in 2 x (NTH / 128), each (TS / 2) x
+// (TS / (NTH / 128)) as blocks of 16 x 16; k-major LDS tiles, double-buffered
+// through registers.  The 128-wide tile runs 8 waves (four per SIMD with two
+// blocks per CU), so each wave holds 4 x 2 accumulator blocks.
+template <int TS, int NTH>
+__global__ __launch_bounds__(NTH, NTH / 128) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                      const double* __restrict__ A, int64_t a_rs,
                                                      int64_t a_cs, int64_t a_bs,
                                                      const double* __restrict__ B, int64_t b_rs,
@@ -31,9 +32,12 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(int64_t M, int64_t N, int64
                                                      double* __restrict__ C, int64_t ldc,
                                                      int64_t c_bs, int tri_a, int tri_b, int upper_c,
                                                      const int* __restrict__ skip) {
-    constexpr int P = TS + 16;          // LDS pitch (see the hidden-layer kernel)
-    constexpr int EPT = TS * BK / NT;   // elements per thread per operand tile
-    constexpr int WB = TS / 32;         // 16 x 16 blocks per wave and dimension
+    constexpr int P = TS + 16;           // LDS pitch (see the hidden-layer kernel)
+    constexpr int EPT = TS * BK / NTH;   // elements per thread per operand tile
+    constexpr int WGN = NTH / 128;       // waves across the tile's columns
+    constexpr int WBI = TS / 32;         // 16 x 16 blocks per wave: rows
+    constexpr int WBJ = TS / WGN / 16;   //                          columns
+    static_assert(EPT >= 1 && WBJ >= 1, "tile and block size");
     __shared__ double As[2][BK][P];
     __shared__ double Bs[2][BK][P];
     const int64_t i0 = (int64_t)blockIdx.x * TS, j0 = (int64_t)blockIdx.y * TS;
@@ -43,7 +47,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(int64_t M, int64_t N, int64
     B += (int64_t)blockIdx.z * b_bs;
     C += (int64_t)blockIdx.z * c_bs;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WGN, wn = wave % WGN;
     const bool a_kcontig = (a_cs == 1);
     const bool b_jcontig = (b_cs == 1);
 
@@ -95,11 +99,11 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(int64_t M, int64_t N, int64
         }
     };
 
-    d4v acc[WB][WB];
+    d4v acc[WBI][WBJ];
 #pragma unroll
-    for (int x = 0; x < WB; ++x)
+    for (int x = 0; x < WBI; ++x)
 #pragma unroll
-        for (int y = 0; y < WB; ++y) acc[x][y] = d4v{};
+        for (int y = 0; y < WBJ; ++y) acc[x][y] = d4v{};
 
     if (k_lo < k_hi) {
         load(k_lo);
@@ -112,15 +116,16 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(int64_t M, int64_t N, int64
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
                 const int k = kk + (lane >> 4);
-                double a[WB], b[WB];
+                double a[WBI], b[WBJ];
 #pragma unroll
-                for (int x = 0; x < WB; ++x) a[x] = As[buf][k][wm * (TS / 2) + x * 16 + (lane & 15)];
+                for (int x = 0; x < WBI; ++x) a[x] = As[buf][k][wm * (TS / 2) + x * 16 + (lane & 15)];
 #pragma unroll
-                for (int y = 0; y < WB; ++y) b[y] = Bs[buf][k][wn * (TS / 2) + y * 16 + (lane & 15)];
+                for (int y = 0; y < WBJ; ++y)
+                    b[y] = Bs[buf][k][wn * (TS / WGN) + y * 16 + (lane & 15)];
 #pragma unroll
-                for (int x = 0; x < WB; ++x)
+                for (int x = 0; x < WBI; ++x)
 #pragma unroll
-                    for (int y = 0; y < WB; ++y) acc[x][y] = Mfma16<double>::op(a[x], b[y], acc[x][y]);
+                    for (int y = 0; y < WBJ; ++y) acc[x][y] = Mfma16<double>::op(a[x], b[y], acc[x][y]);
             }
             if (more) store(buf ^ 1);
             __syncthreads();
@@ -128,13 +133,13 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(int64_t M, int64_t N, int64
         }
     }
 #pragma unroll
-    for (int x = 0; x < WB; ++x)
+    for (int x = 0; x < WBI; ++x)
 #pragma unroll
-        for (int y = 0; y < WB; ++y)
+        for (int y = 0; y < WBJ; ++y)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t gi = i0 + wm * (TS / 2) + x * 16 + Mfma16<double>::row(lane, v);
-                const int64_t gj = j0 + wn * (TS / 2) + y * 16 + (lane & 15);
+                const int64_t gj = j0 + wn * (TS / WGN) + y * 16 + (lane & 15);
                 if (gi >= M || gj >= N) continue;
                 double c = alpha * acc[x][y][v];
                 if (beta != 0.0) c += beta * C[gi * ldc + gj];
@@ -151,12 +156,12 @@ void gemm_f64_batched(hipStream_t s, int64_t batch, int64_t M, int64_t N, int64_
     if (M <= 0 || N <= 0 || batch <= 0) return;
     if (M >= 128 && N >= 128) {
         dim3 grid((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128), (unsigned)batch);
-        gemm_kernel<128><<<grid, NT, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs, b_bs,
-                                             beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);
+        gemm_kernel<128, 512><<<grid, 512, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs,
+                                                   b_bs, beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);
     } else {
         dim3 grid((unsigned)cdiv(M, 64), (unsigned)cdiv(N, 64), (unsigned)batch);
-        gemm_kernel<64><<<grid, NT, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs, b_bs,
-                                            beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);
+        gemm_kernel<64, 256><<<grid, 256, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs,
+                                                  b_bs, beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);
     }
     ELM_LAUNCH_CHECK();
 }
