@@ -134,6 +134,36 @@ def bench_batch(args, elm, torch, wl, dev):
     return out
 
 
+# The paper's own RBP-ELM training times on GINA (N=3468, d=971), Table 1:
+# MATLAB R2016a on an Intel i5-7200U at 2.5 GHz.  Context only: the dataset is
+# not available, so the same shapes are trained on synthetic inputs here.
+PAPER_TABLE1_S = {500: 1.1875, 1500: 6.8906, 2000: 13.1875}
+PAPER_HW = "MATLAB R2016a, Intel i5-7200U 2.50 GHz (Table 1)"
+
+
+def bench_paper_shapes(elm, torch, wl, dev, reps=5):
+    """Median FP64-form training time on GINA-shaped synthetic problems next
+    to the paper's Table 1 times for those shapes."""
+    rows = []
+    for L, paper_s in PAPER_TABLE1_S.items():
+        p = wl.gina_shape(L)
+        X, W, b, T = (torch.from_numpy(a).to(dev) for a in (p.X, p.W, p.b, p.T))
+        elm.train(X, W, b, T, precision="fp64", ir_tol=1e-10)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            res = elm.train(X, W, b, T, precision="fp64", ir_tol=1e-10)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ms = sorted(ts)[len(ts) // 2] * 1e3
+        rows.append({"N": p.N, "d": p.d, "L": L, "rank": res.rank, "ms": round(ms, 3),
+                     "paper_s": paper_s, "ratio": round(paper_s * 1e3 / ms, 1)})
+        log(f"paper shape L={L}: {ms:.2f} ms (paper {paper_s} s)")
+    return {"workload": "GINA shape (N=3468, d=971), synthetic inputs, FP64 form", "paper_hw": PAPER_HW,
+            "rows": rows}
+
+
 def traffic_from_profiles(kernel_src, k_splits=None):
     """HBM traffic per launch of the Gram kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source and with the
@@ -260,6 +290,7 @@ def main():
                 "beta_rel_diff_mixed_vs_fp64": diff}
 
     batch = bench_batch(args, elm, torch, wl, dev) if args.batch_steps > 0 else None
+    paper = bench_paper_shapes(elm, torch, wl, dev) if args.batch_steps > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -310,6 +341,7 @@ def main():
         "stage_ms_per_step": stage_ms_per_step,
         "fp64_form": fp64,
         "batch_sweep": batch,
+        "paper_context": paper,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests need a visible device; skipping here keeps `-m "not gpu"` and
-    # plain runs on CPU-only hosts green, while on the GPU machine they run.
+    # plain runs on CPU-only hosts green, while on a host with the GPU they run.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
