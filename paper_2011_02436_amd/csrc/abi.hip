@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <new>
 
 namespace elm {
@@ -144,7 +145,7 @@ size_t dtype_size(elm_dtype dt) {
 
 void free_factor_buffers(elm_factor* f) {
     if (!f) return;
-    if (f->pool) {  // workspace buffers stay with the workspace
+    if (f->pool || f->arena) {  // workspace and arena buffers stay where they are
         f->piv = nullptr;
         f->R = f->Rinv = f->K = f->Usinv = f->RinvT = f->KT = f->UsinvT = nullptr;
         return;
@@ -636,6 +637,277 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
     return result;
 }
 
+// One problem of a batch refined by refine_grouped.
+struct GroupedSolve {
+    const elm_factor* f = nullptr;  // non-transposed, rank >= 1, checks done
+    int64_t m = 0;                  // 1..16
+    const double* H64 = nullptr;
+    int64_t ldh64 = 0;
+    const double* T = nullptr;
+    int64_t ldt = 0;
+    double* beta = nullptr;
+    int64_t ldbeta = 0;
+    const double* Z = nullptr;  // H^T T (L x m, ld m)
+    double z2 = 0.0;            // ||Z||_F^2 (host)
+    elm_solve_info* info = nullptr;
+    elm_status status = ELM_OK;  // out: OK or NO_CONVERGENCE (message in msg)
+    std::string msg;
+};
+
+// beta = H^+ T with refinement for every problem of gs: the steps, kernels,
+// arithmetic and stopping rules of pinv_solve_impl for each problem, with each
+// step one launch for all problems still iterating and one host read-back of
+// every residual norm per iteration.
+void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs, double ir_tol,
+                    int32_t ir_max_iter) {
+    const int P = (int)gs.size();
+    if (P == 0) return;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    int maxm = 1;
+    for (const GroupedSolve& g : gs) {
+        if (g.f->transposed || g.f->r < 1 || g.m < 1 || g.m > 16)
+            throw Error{ELM_ERR_UNSUPPORTED, "grouped refinement: unsupported problem"};
+        maxm = std::max<int>(maxm, (int)g.m);
+    }
+    // per-problem buffers from one arena: g2 of every problem first, then
+    // E, part, G, sq, D, u, t, w, t2, bd of each
+    auto carve = [&](char* base, std::vector<RefineDesc>* rd, std::vector<double*>* scratch) {
+        size_t off = al((size_t)P * sizeof(double));
+        for (int j = 0; j < P; ++j) {
+            const GroupedSolve& g = gs[j];
+            const elm_factor* f = g.f;
+            const int64_t N = f->N, L = f->L, m = g.m, r = f->r, c = f->n - f->r;
+            const size_t sz[10] = {(size_t)(N * m), refine_part_doubles(N, L, m), (size_t)(L * m),
+                                   refine_sq_doubles(L, m), (size_t)(L * m), (size_t)(r * m),
+                                   (size_t)(r * m), (size_t)(c * m), (size_t)(f->q * m),
+                                   (size_t)(c * m)};
+            double* ptr[10];
+            for (int k = 0; k < 10; ++k) {
+                ptr[k] = base ? (double*)(base + off) : nullptr;
+                off += al(std::max<size_t>(sz[k], 1) * sizeof(double));
+            }
+            if (rd) {
+                RefineDesc& q = (*rd)[j];
+                q.N = N;
+                q.L = L;
+                q.m = (int)m;
+                q.H = g.H64;
+                q.ldh = g.ldh64;
+                q.T = g.T;
+                q.ldt = g.ldt;
+                q.beta = g.beta;
+                q.ldbeta = g.ldbeta;
+                q.E = ptr[0];
+                q.part = ptr[1];
+                q.G = ptr[2];
+                q.sq = ptr[3];
+                q.g2 = (double*)base + j;
+                q.D = ptr[4];
+                for (int k = 0; k < 5; ++k) (*scratch)[(size_t)j * 5 + k] = ptr[5 + k];
+            }
+        }
+        return off;
+    };
+    char* arena = (char*)h->ws.get("bt_refine", carve(nullptr, nullptr, nullptr));
+    std::vector<RefineDesc> rd(P);
+    std::vector<double*> scr((size_t)P * 5);
+    carve(arena, &rd, &scr);
+    const double* g2dev = (const double*)arena;
+    // the apply's descriptors: row copies (0 gather Z, 1 gather G, 2 scatter u
+    // into beta, 3 into D, 4 scatter K^T u into beta, 5 into D) and its seven
+    // products
+    std::vector<CopyRowsDesc> cp((size_t)6 * P);
+    std::vector<RowprodDesc> rp((size_t)7 * P);
+    for (int j = 0; j < P; ++j) {
+        const GroupedSolve& g = gs[j];
+        const elm_factor* f = g.f;
+        const int64_t r = f->r, c = f->n - f->r, q = f->q, m = g.m;
+        double *u = scr[(size_t)j * 5], *t = scr[(size_t)j * 5 + 1], *w = scr[(size_t)j * 5 + 2],
+               *t2 = scr[(size_t)j * 5 + 3], *bd = scr[(size_t)j * 5 + 4];
+        auto copy = [&](int k, int64_t rows, const double* src, int64_t lds, const int32_t* idx,
+                        double* dst, int64_t ldd) {
+            CopyRowsDesc& x = cp[(size_t)k * P + j];
+            x.rows = rows;
+            x.cols = m;
+            x.src = src;
+            x.lds = lds;
+            x.idx = idx;
+            x.dst = dst;
+            x.ldd = ldd;
+        };
+        copy(0, r, g.Z, m, f->piv, u, m);                         // F^T (.) = rows piv[:r]
+        copy(1, r, rd[j].G, m, f->piv, u, m);
+        copy(2, r, u, m, f->piv, g.beta, g.ldbeta);               // out[piv[:r]] = u
+        copy(3, r, u, m, f->piv, rd[j].D, m);
+        copy(4, c, bd, m, f->piv + r, g.beta, g.ldbeta);         // out[piv[r:]] = K^T u
+        copy(5, c, bd, m, f->piv + r, rd[j].D, m);
+        auto prod = [&](int k, int64_t M, int64_t K, double alpha, const double* A, int64_t lda,
+                        int tri, const double* B, double beta, double* C) {
+            RowprodDesc& x = rp[(size_t)k * P + j];
+            x.M = M;
+            x.K = K;
+            x.m = (int)m;
+            x.tri = tri;
+            x.alpha = alpha;
+            x.beta = beta;
+            x.A = A;
+            x.lda = lda;
+            x.B = B;
+            x.ldb = m;
+            x.C = C;
+            x.ldc = m;
+        };
+        // (F^T F)^-1 = Rinv Rinv^T
+        prod(0, r, r, 1.0, f->RinvT, r, 2, u, 0.0, t);
+        prod(1, r, r, 1.0, f->Rinv, r, 1, t, 0.0, u);
+        // (G G^T)^-1: Woodbury through K^T K, or S^-1 directly
+        double* x = f->woodbury ? w : u;
+        if (q > 0) {
+            if (f->woodbury) prod(2, c, r, 1.0, f->KT, r, 0, u, 0.0, w);
+            prod(3, q, q, 1.0, f->UsinvT, q, 2, x, 0.0, t2);
+            prod(4, q, q, 1.0, f->Usinv, q, 1, t2, 0.0, x);
+            if (f->woodbury) prod(5, r, c, -1.0, f->K, c, 0, w, 1.0, u);
+        }
+        if (c > 0) prod(6, c, r, 1.0, f->KT, r, 0, u, 0.0, bd);
+    }
+    const size_t o_cp = al((size_t)P * sizeof(RefineDesc));
+    const size_t o_rp = o_cp + al(cp.size() * sizeof(CopyRowsDesc));
+    const size_t dbytes = o_rp + rp.size() * sizeof(RowprodDesc);
+    std::vector<char> blob(dbytes);
+    std::memcpy(blob.data(), rd.data(), (size_t)P * sizeof(RefineDesc));
+    std::memcpy(blob.data() + o_cp, cp.data(), cp.size() * sizeof(CopyRowsDesc));
+    std::memcpy(blob.data() + o_rp, rp.data(), rp.size() * sizeof(RowprodDesc));
+    char* ddesc = (char*)h->ws.get("bt_refine_desc", dbytes);
+    ELM_HIP_TRY(hipMemcpyAsync(ddesc, blob.data(), dbytes, hipMemcpyHostToDevice, s));
+    const RefineDesc* drd = (const RefineDesc*)ddesc;
+    const CopyRowsDesc* dcp = (const CopyRowsDesc*)(ddesc + o_cp);
+    const RowprodDesc* drp = (const RowprodDesc*)(ddesc + o_rp);
+
+    // block counts of every launch kind, and the schedules of the problems
+    // still iterating
+    enum { K_ROWS, K_COLS, K_HTR, K_SUM, K_AXPY, K_GAT, K_SCU, K_SCB, K_P0, NK = K_P0 + 7 };
+    std::vector<int64_t> nblk((size_t)NK * P, 0);
+    for (int j = 0; j < P; ++j) {
+        nblk[(size_t)K_ROWS * P + j] = refine_group_blocks(RefinePass::ROWS_DOT, rd[j], maxm);
+        nblk[(size_t)K_COLS * P + j] = refine_group_blocks(RefinePass::COLS_DOT, rd[j], maxm);
+        nblk[(size_t)K_HTR * P + j] = refine_group_blocks(RefinePass::HT_REDUCE, rd[j], maxm);
+        nblk[(size_t)K_SUM * P + j] = refine_group_blocks(RefinePass::SUM, rd[j], maxm);
+        nblk[(size_t)K_AXPY * P + j] = refine_group_blocks(RefinePass::AXPY, rd[j], maxm);
+        nblk[(size_t)K_GAT * P + j] = copy_rows_group_blocks(cp[j]);
+        nblk[(size_t)K_SCU * P + j] = copy_rows_group_blocks(cp[(size_t)2 * P + j]);
+        nblk[(size_t)K_SCB * P + j] = copy_rows_group_blocks(cp[(size_t)4 * P + j]);
+        for (int k = 0; k < 7; ++k)
+            nblk[(size_t)(K_P0 + k) * P + j] = rowprod_group_blocks(rp[(size_t)k * P + j]);
+    }
+    const size_t per = (size_t)2 * P + 1;
+    std::vector<int32_t> hs((size_t)NK * per);
+    int32_t* ds = (int32_t*)h->ws.get("bt_refine_sched", hs.size() * sizeof(int32_t));
+    GroupSched sched[NK];
+    std::vector<char> active(P, 1);
+    auto upload_sched = [&] {
+        for (int k = 0; k < NK; ++k) {
+            int32_t* st = hs.data() + (size_t)k * per;
+            int32_t* pr = st + P + 1;
+            int cnt = 0;
+            int64_t tot = 0;
+            for (int j = 0; j < P; ++j) {
+                const int64_t nb = nblk[(size_t)k * P + j];
+                if (!active[j] || nb == 0) continue;
+                st[cnt] = (int32_t)tot;
+                pr[cnt] = j;
+                ++cnt;
+                tot += nb;
+                if (tot >= INT32_MAX) throw Error{ELM_ERR_UNSUPPORTED, "grouped launch too large"};
+            }
+            st[cnt] = (int32_t)tot;
+            sched[k].start = ds + (size_t)k * per;
+            sched[k].prob = ds + (size_t)k * per + P + 1;
+            sched[k].count = cnt;
+            sched[k].blocks = tot;
+        }
+        ELM_HIP_TRY(hipMemcpyAsync(ds, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    };
+    // out = H^+ (.) through each factor: from Z into beta (first) or from G into D
+    auto apply = [&](bool first) {
+        launch_copy_rows_grouped(s, false, dcp + (first ? 0 : 1) * P, sched[K_GAT]);
+        for (int k = 0; k < 6; ++k) launch_rowprod_grouped(s, drp + (size_t)k * P, sched[K_P0 + k], maxm);
+        launch_copy_rows_grouped(s, true, dcp + (size_t)(first ? 2 : 3) * P, sched[K_SCU]);
+        launch_rowprod_grouped(s, drp + (size_t)6 * P, sched[K_P0 + 6], maxm);
+        launch_copy_rows_grouped(s, true, dcp + (size_t)(first ? 4 : 5) * P, sched[K_SCB]);
+    };
+    Profiler* pr = &h->prof;
+    for (GroupedSolve& g : gs) {
+        g.status = ELM_OK;
+        if (g.info) {
+            std::memset(g.info, 0, sizeof(*g.info));
+            g.info->rank = g.f->r;
+            g.info->ne_residual = -1.0;
+        }
+    }
+    upload_sched();
+    {
+        StageScope sc(pr, ELM_STAGE_SOLVE, s);
+        apply(true);  // beta_0 = H^+ T
+    }
+    if (ir_max_iter == 0) {
+        ELM_HIP_TRY(hipStreamSynchronize(s));
+        return;
+    }
+    std::vector<double> g2(P), res(P, 0.0), prev(P, 0.0);
+    int it = 0;
+    for (;;) {
+        {
+            StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
+            launch_refine_grouped(s, RefinePass::ROWS_DOT, drd, sched[K_ROWS], maxm);
+        }
+        {
+            StageScope sc(pr, ELM_STAGE_RHS, s);
+            launch_refine_grouped(s, RefinePass::COLS_DOT, drd, sched[K_COLS], maxm);
+            launch_refine_grouped(s, RefinePass::HT_REDUCE, drd, sched[K_HTR], maxm);
+            launch_refine_grouped(s, RefinePass::SUM, drd, sched[K_SUM], maxm);
+        }
+        ELM_HIP_TRY(hipMemcpyAsync(g2.data(), g2dev, (size_t)P * sizeof(double), hipMemcpyDeviceToHost, s));
+        ELM_HIP_TRY(hipStreamSynchronize(s));
+        bool any = false;
+        for (int j = 0; j < P; ++j) {
+            if (!active[j]) continue;
+            GroupedSolve& g = gs[j];
+            const double rj = g.z2 > 0 ? std::sqrt(g2[j] / g.z2) : std::sqrt(g2[j]);
+            res[j] = rj;
+            if (g.info && it < 32) g.info->ne_history[it] = rj;
+            // the last correction made no progress, or the loop is done
+            const bool stop = !(rj > ir_tol) || it >= ir_max_iter || (it >= 1 && !(rj < prev[j]));
+            if (!stop) {
+                prev[j] = rj;
+                any = true;
+                continue;
+            }
+            active[j] = 0;
+            if (g.info) {
+                g.info->iterations = it;
+                g.info->ne_residual = rj;
+            }
+            if (rj > ir_tol) {
+                g.status = ELM_ERR_NO_CONVERGENCE;
+                char msg[160];
+                std::snprintf(msg, sizeof(msg),
+                              "refinement stopped after %d iterations at relative normal-equation "
+                              "residual %.3e > ir_tol %.3e",
+                              it, rj, ir_tol);
+                g.msg = msg;
+            }
+        }
+        if (!any) break;
+        upload_sched();
+        {
+            StageScope sc(pr, ELM_STAGE_SOLVE, s);
+            apply(false);
+        }
+        launch_refine_grouped(s, RefinePass::AXPY, drd, sched[K_AXPY], maxm);
+        ++it;
+    }
+}
+
 }  // namespace
 }  // namespace elm
 
@@ -994,8 +1266,10 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             wait_workers(ps);
 
             // phase 2: all rank decisions in shared launches
-            std::vector<double> hdmax(grp.size());
+            std::vector<double> hdmax(grp.size()), hnrm(grp.size() * 2);
             ELM_HIP_TRY(hipMemcpyAsync(hdmax.data(), dmaxs, grp.size() * sizeof(double),
+                                       hipMemcpyDeviceToHost, ps));
+            ELM_HIP_TRY(hipMemcpyAsync(hnrm.data(), nrms, grp.size() * 2 * sizeof(double),
                                        hipMemcpyDeviceToHost, ps));
             ELM_HIP_TRY(hipStreamSynchronize(ps));
             std::vector<elm::PcholProblem> pc;
@@ -1027,7 +1301,60 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             }
             workers_wait(ps);
 
-            // phase 3 (workers): factor tail, beta and refinement
+            // Rank decisions: the rule of elm_rank_factor's diagnostics
+            auto reliable_of = [&](int32_t e) {
+                const Item& it = items[e];
+                const elm::PcholProblem& q = pc[pc_of[e]];
+                const double hd = hdmax[slot[e]];
+                const double nf = elm::schur_noise_floor(it.gdt, it.n, std::max(probs[e].N, probs[e].L),
+                                                         it.kc) * hd;
+                return (q.rank == 0 || q.stats[0] >= 2.0 * nf) &&
+                       (q.rank == it.n || q.stats[1] >= -2.0 * nf);
+            };
+            // Problems whose solve and refinement run grouped (phase 3b):
+            // non-transposed, H^T T from the hidden layer, rank >= 1, a rank
+            // decision that stands.  Their factors live in one arena.
+            auto factor_bytes = [&](int64_t r, int64_t n) {
+                const int64_t c = n - r, q = std::min(r, c);
+                size_t b = al((size_t)r * n * sizeof(double)) + 2 * al((size_t)r * r * sizeof(double));
+                if (c > 0) b += 2 * al((size_t)r * c * sizeof(double));
+                if (q > 0) b += 2 * al((size_t)q * q * sizeof(double));
+                return b;
+            };
+            std::vector<size_t> foff(count, 0), fsize(count, 0);
+            std::vector<char> grouped(count, 0);
+            size_t fbytes = 0;
+            for (int32_t e : grp) {
+                const Item& it = items[e];
+                if (!it.ok || pc_of[e] < 0) continue;
+                const elm::PcholProblem& q = pc[pc_of[e]];
+                if (q.bad || it.transposed || !it.fuse_z || q.rank == 0) continue;
+                if (it.gdt != ELM_F64 && !reliable_of(e)) continue;  // escalates at once
+                grouped[e] = 1;
+                foff[e] = fbytes;
+                fsize[e] = factor_bytes(q.rank, it.n);
+                fbytes += fsize[e];
+            }
+            char* farena = fbytes ? (char*)h->ws.get("bt_factors", fbytes) : nullptr;
+            std::vector<std::unique_ptr<elm_factor>> gfac(count);
+
+            // a guard failed: train problem e again from a higher-precision Gram
+            auto escalate = [&](elm_handle* wh, int32_t e, int guard) {
+                const elm_problem& p = probs[e];
+                elm_train_info t2;
+                std::memset(&t2, 0, sizeof(t2));
+                const elm_status s2 =
+                    elm_train(wh, p.N, p.d, p.L, p.m, p.X, p.ldx, p.W, p.ldw, p.b, p.T, p.ldt,
+                              elm::next_gram_dtype(items[e].gdt), p.H64, p.ldh64, nullptr, 0, tau_rel,
+                              ir_tol, ir_max_iter, p.beta, p.ldbeta, nullptr, 0, nullptr, &t2, nullptr);
+                t2.escalations += 1;
+                if (!t2.guard) t2.guard = guard;
+                info_all[e] = t2;
+                elm::check_status(wh, s2);
+            };
+
+            // phase 3a (workers): factor tails; beta and refinement of the
+            // problems that do not run grouped
             run_workers(grp, [&](elm_handle* wh, int32_t e) {
                 const elm_problem& p = probs[e];
                 Item& it = items[e];
@@ -1035,26 +1362,31 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 hipStream_t ws = wh->stream;
                 elm_train_info& ti = info_all[e];
                 if (q.bad) throw elm::Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
-                elm_factor* f = new elm_factor();
-                struct FactorGuard {
+                std::unique_ptr<elm_factor> fp(new elm_factor());
+                elm_factor* f = fp.get();
+                struct BufGuard {
                     elm_factor* f;
-                    ~FactorGuard() {
-                        elm::free_factor_buffers(f);
-                        delete f;
-                    }
-                } fg{f};
+                    ~BufGuard() { elm::free_factor_buffers(f); }
+                } bg{f};
                 f->N = p.N;
                 f->L = p.L;
                 f->n = it.n;
                 f->transposed = it.transposed;
                 f->device = h->device;
-                f->pool = &wh->ws;
                 f->gram_dtype = it.gdt;
                 f->tau = q.tau;
                 f->r = q.rank;
-                f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)it.n * sizeof(int32_t));
-                ELM_HIP_TRY(hipMemcpyAsync(f->piv, q.piv, (size_t)it.n * sizeof(int32_t),
-                                           hipMemcpyDeviceToDevice, ws));
+                if (grouped[e]) {
+                    // the grouped factorisation's pivots stay valid until the next group
+                    f->arena = farena + foff[e];
+                    f->arena_left = fsize[e];
+                    f->piv = const_cast<int32_t*>(q.piv);
+                } else {
+                    f->pool = &wh->ws;
+                    f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)it.n * sizeof(int32_t));
+                    ELM_HIP_TRY(hipMemcpyAsync(f->piv, q.piv, (size_t)it.n * sizeof(int32_t),
+                                               hipMemcpyDeviceToDevice, ws));
+                }
                 if (f->r > 0) {
                     f->R = (double*)elm::factor_alloc(f, "R", (size_t)f->r * it.n * sizeof(double));
                     elm::launch_gather_rows(ws, f->r, it.n, q.Rorig, it.n, q.piv, f->R, it.n);
@@ -1065,46 +1397,90 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 f->max_diag = hd;
                 f->noise_floor =
                     elm::schur_noise_floor(it.gdt, it.n, p.N > p.L ? p.N : p.L, it.kc) * hd;
-                f->reliable = (f->r == 0 || f->last_pivot >= 2.0 * f->noise_floor) &&
-                              (f->r == it.n || f->first_rejected >= -2.0 * f->noise_floor);
+                f->reliable = reliable_of(e);
                 elm::check_status(wh, elm_factor_get_info(f, &ti.factor));
                 ti.gram_dtype = it.gdt;
                 const bool can_escalate = it.gdt != ELM_F64;
-                int guard = 0;
                 if (can_escalate && !f->reliable) {
-                    guard = 1;
-                } else {
-                    {
-                        elm::StageScope sc(&wh->prof, ELM_STAGE_FACTOR, ws);
-                        elm::build_factor_tail(ws, f, wh->ws, /*wait=*/false);
-                    }
-                    if (it.fuse_z) {
-                        double* Z = (double*)wh->ws.get("ps_Z", (size_t)p.L * p.m * sizeof(double));
-                        double* nrm = (double*)wh->ws.get("ps_nrm", 2 * sizeof(double));
-                        ELM_HIP_TRY(hipMemcpyAsync(Z, it.Z, (size_t)p.L * p.m * sizeof(double),
-                                                   hipMemcpyDeviceToDevice, ws));
-                        ELM_HIP_TRY(hipMemcpyAsync(nrm, it.nrm, sizeof(double), hipMemcpyDeviceToDevice,
-                                                   ws));
-                    }
-                    const elm_status ss =
-                        elm::pinv_solve_impl(wh, f, p.m, p.T, p.ldt, p.H64, p.ldh64, ir_tol, ir_max_iter,
-                                             p.beta, p.ldbeta, &ti.solve, it.fuse_z);
-                    if (ss == ELM_OK) return;
-                    if (ss != ELM_ERR_NO_CONVERGENCE || !can_escalate) elm::check_status(wh, ss);
-                    guard = 2;
+                    escalate(wh, e, 1);
+                    return;
                 }
-                // a guard failed: train this problem again from a higher-precision Gram
-                elm_train_info t2;
-                std::memset(&t2, 0, sizeof(t2));
-                const elm_status s2 =
-                    elm_train(wh, p.N, p.d, p.L, p.m, p.X, p.ldx, p.W, p.ldw, p.b, p.T, p.ldt,
-                              elm::next_gram_dtype(it.gdt), p.H64, p.ldh64, nullptr, 0, tau_rel, ir_tol,
-                              ir_max_iter, p.beta, p.ldbeta, nullptr, 0, nullptr, &t2, nullptr);
-                t2.escalations += 1;
-                if (!t2.guard) t2.guard = guard;
-                ti = t2;
-                elm::check_status(wh, s2);
+                if (grouped[e]) {
+                    elm::StageScope sc(&wh->prof, ELM_STAGE_FACTOR, ws);
+                    elm::build_factor_tail(ws, f, wh->ws, /*wait=*/true);
+                    bg.f = nullptr;
+                    gfac[e] = std::move(fp);
+                    return;
+                }
+                {
+                    elm::StageScope sc(&wh->prof, ELM_STAGE_FACTOR, ws);
+                    elm::build_factor_tail(ws, f, wh->ws, /*wait=*/false);
+                }
+                if (it.fuse_z) {
+                    double* Z = (double*)wh->ws.get("ps_Z", (size_t)p.L * p.m * sizeof(double));
+                    double* nrm = (double*)wh->ws.get("ps_nrm", 2 * sizeof(double));
+                    ELM_HIP_TRY(hipMemcpyAsync(Z, it.Z, (size_t)p.L * p.m * sizeof(double),
+                                               hipMemcpyDeviceToDevice, ws));
+                    ELM_HIP_TRY(hipMemcpyAsync(nrm, it.nrm, sizeof(double), hipMemcpyDeviceToDevice, ws));
+                }
+                const elm_status ss =
+                    elm::pinv_solve_impl(wh, f, p.m, p.T, p.ldt, p.H64, p.ldh64, ir_tol, ir_max_iter,
+                                         p.beta, p.ldbeta, &ti.solve, it.fuse_z);
+                if (ss == ELM_OK) return;
+                if (ss != ELM_ERR_NO_CONVERGENCE || !can_escalate) elm::check_status(wh, ss);
+                escalate(wh, e, 2);
             });
+
+            // phase 3b (one stream): beta and refinement of the grouped problems
+            wait_workers(ps);
+            std::vector<elm::GroupedSolve> gs;
+            std::vector<int32_t> gs_of;
+            for (int32_t e : grp) {
+                if (!gfac[e] || !items[e].ok) continue;
+                const elm_problem& p = probs[e];
+                elm::GroupedSolve g;
+                g.f = gfac[e].get();
+                g.m = p.m;
+                g.H64 = p.H64;
+                g.ldh64 = p.ldh64;
+                g.T = p.T;
+                g.ldt = p.ldt;
+                g.beta = p.beta;
+                g.ldbeta = p.ldbeta;
+                g.Z = items[e].Z;
+                g.z2 = hnrm[2 * (size_t)slot[e]];
+                g.info = &info_all[e].solve;
+                gs.push_back(g);
+                gs_of.push_back(e);
+            }
+            std::vector<int32_t> esc;
+            try {
+                elm::refine_grouped(h, ps, gs, ir_tol, ir_max_iter);
+                for (size_t j = 0; j < gs.size(); ++j) {
+                    const int32_t e = gs_of[j];
+                    if (gs[j].status == ELM_OK) continue;
+                    if (items[e].gdt != ELM_F64) {
+                        esc.push_back(e);
+                    } else {
+                        st_all[e] = gs[j].status;
+                        msg_all[e] = gs[j].msg;
+                        items[e].ok = false;
+                    }
+                }
+            } catch (const elm::Error& err) {
+                for (int32_t e : gs_of) {
+                    st_all[e] = err.st;
+                    msg_all[e] = err.msg;
+                    items[e].ok = false;
+                }
+            }
+            for (auto& f : gfac)
+                if (f) elm::free_factor_buffers(f.get());
+            // phase 3c (workers): problems whose grouped refinement missed ir_tol
+            if (!esc.empty()) {
+                workers_wait(ps);
+                run_workers(esc, [&](elm_handle* wh, int32_t e) { escalate(wh, e, 2); });
+            }
         }
         if (h->prof.on) {
             for (int w = 0; w < nw; ++w) {

@@ -193,6 +193,10 @@ struct elm_factor {
     // device buffers: hipMalloc'd and owned by the factor, or, when pool is
     // set, named buffers of that workspace (a factor used only inside a call)
     elm::Workspace* pool = nullptr;
+    // or, when arena is set, carved from a caller's device arena (256-byte
+    // aligned pieces, arena_left bytes still free; nothing is freed with the factor)
+    char* arena = nullptr;
+    size_t arena_left = 0;
     int32_t* piv = nullptr;   // n: original index at each pivoted position
     double* R = nullptr;      // r x n, pivot order, ld n: [R11 R12]
     double* Rinv = nullptr;   // r x r, ld r: R11^-1 (upper triangular)
@@ -214,6 +218,15 @@ namespace elm {
 // hipMalloc'd (freed by free_factor_buffers).
 inline void* factor_alloc(elm_factor* f, const char* name, size_t bytes) {
     if (bytes == 0) bytes = 256;
+    if (f->arena) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (bytes > f->arena_left)
+            throw Error{ELM_ERR_ALLOC, std::string("factor buffer '") + name + "' exceeds its arena"};
+        void* p = f->arena;
+        f->arena += bytes;
+        f->arena_left -= bytes;
+        return p;
+    }
     if (f->pool) return f->pool->get(std::string("factor_") + name, bytes);
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess)
@@ -382,6 +395,91 @@ void launch_hidden_output(hipStream_t s, int64_t N, int64_t L, int64_t m, const 
 //   beta += delta, elementwise over L x m
 void launch_axpy_mat(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx,
                      double* Y, int64_t ldy);
+
+// ---------------------------------------------------------------------------
+// Grouped launches over the problems of a batch.  Blocks [start[j],
+// start[j + 1]) of a launch serve problem prob[j] (j < count); start (count +
+// 1 entries) and prob are device arrays and blocks = start[count] < 2^31.
+// Each block runs the single-problem kernel's body with its problem's
+// arguments and its block index within that problem, so a grouped launch
+// computes what the single-problem launches would, bit for bit.
+// ---------------------------------------------------------------------------
+struct GroupSched {
+    const int32_t* start = nullptr;
+    const int32_t* prob = nullptr;
+    int count = 0;
+    int64_t blocks = 0;
+};
+// the problem of this block (a descriptor index) and its block index within it
+__device__ inline int group_problem(const GroupSched& g, int64_t& local) {
+    const int32_t b = (int32_t)blockIdx.x;
+    int lo = 0, hi = g.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    local = b - g.start[lo];
+    return g.prob[lo];
+}
+
+// refine.hip, grouped: one problem's refinement buffers (m <= 16)
+struct RefineDesc {
+    int64_t N = 0, L = 0;
+    int m = 0;
+    const double* H = nullptr;  // N x L sample-major FP64
+    int64_t ldh = 0;
+    const double* T = nullptr;  // N x m
+    int64_t ldt = 0;
+    double* beta = nullptr;     // L x m
+    int64_t ldbeta = 0;
+    double* E = nullptr;        // N x m, ld m: T - H beta
+    double* part = nullptr;     // refine_part_doubles(N, L, m): column partials of H^T E
+    double* G = nullptr;        // L x m, ld m: H^T E
+    double* sq = nullptr;       // refine_sq_doubles(L, m)
+    double* g2 = nullptr;       // ||G||_F^2
+    double* D = nullptr;        // L x m, ld m: the correction added to beta
+};
+enum class RefinePass {
+    ROWS_DOT,   // E = T - H beta
+    COLS_DOT,   // part = column-chunk partials of H^T E
+    HT_REDUCE,  // G = sum of the partials, per-block sums of squares
+    SUM,        // g2 = ||G||_F^2
+    AXPY        // beta += D
+};
+// blocks of problem q in a launch whose largest m is maxm
+int64_t refine_group_blocks(RefinePass pass, const RefineDesc& q, int maxm);
+size_t refine_part_doubles(int64_t N, int64_t L, int64_t m);
+size_t refine_sq_doubles(int64_t L, int64_t m);
+// maxm: the largest m of the scheduled problems
+void launch_refine_grouped(hipStream_t s, RefinePass pass, const RefineDesc* d, const GroupSched& g,
+                           int maxm);
+
+// solve.hip, grouped: C = alpha A B + beta C with thin B (the apply's products)
+struct RowprodDesc {
+    int64_t M = 0, K = 0;
+    int m = 0, tri = 0;  // tri 1: A upper triangular (k >= i), 2: lower (k <= i)
+    double alpha = 1.0, beta = 0.0;
+    const double* A = nullptr;
+    int64_t lda = 0;
+    const double* B = nullptr;
+    int64_t ldb = 0;
+    double* C = nullptr;
+    int64_t ldc = 0;
+};
+//   row copies through an index: gather dst[i] = src[idx[i]], scatter dst[idx[i]] = src[i]
+struct CopyRowsDesc {
+    int64_t rows = 0, cols = 0;
+    const double* src = nullptr;
+    int64_t lds = 0;
+    const int32_t* idx = nullptr;
+    double* dst = nullptr;
+    int64_t ldd = 0;
+};
+int64_t rowprod_group_blocks(const RowprodDesc& q);
+int64_t copy_rows_group_blocks(const CopyRowsDesc& q);
+void launch_rowprod_grouped(hipStream_t s, const RowprodDesc* d, const GroupSched& g, int maxm);
+void launch_copy_rows_grouped(hipStream_t s, bool scatter, const CopyRowsDesc* d, const GroupSched& g);
 
 // predict.hip
 void launch_predict(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L, int64_t m,

@@ -89,7 +89,7 @@ __device__ inline void block_argmax_store(Part b, Part* __restrict__ out, int bx
 // (-inf when every position is accepted), largest Gram diagonal
 enum { PS_LAST = 0, PS_REJECT = 1, PS_MAX = 2, PS_N = 3 };
 
-__device__ inline void init_body(int64_t a, int64_t n, int* rem0, int* state, double* pstats) {
+__device__ __forceinline__ void init_body(int64_t a, int64_t n, int* rem0, int* state, double* pstats) {
     if (a < n) rem0[a] = (int)a;
     if (a < ST_N) state[a] = 0;
     if (a == 0) {
@@ -105,7 +105,7 @@ __global__ void fill_kernel(double* p, int64_t count, double v) {
         p[i] = v;
 }
 
-__device__ inline void panel_start_body(int bx, int64_t n_rem, const double* __restrict__ S,
+__device__ __forceinline__ void panel_start_body(int bx, int64_t n_rem, const double* __restrict__ S,
                                         int64_t lds, double* __restrict__ d,
                                         int* __restrict__ chosen, const int* rem0, const int* rem1,
                                         Part* __restrict__ out, int* state) {
@@ -133,7 +133,7 @@ __device__ inline void panel_start_body(int bx, int64_t n_rem, const double* __r
 // order of operations is the same for every position: identical columns of
 // the Gram stay bitwise identical.
 template <int G, int R>
-__device__ inline void step_body(int bx, int64_t k, int t, int64_t n_rem,
+__device__ __forceinline__ void step_body(int bx, int64_t k, int t, int64_t n_rem,
                                  const double* __restrict__ S, int64_t lds, double* __restrict__ P,
                                  int64_t ldp, double* __restrict__ d, int* __restrict__ chosen,
                                  const int* rem0, const int* rem1, const Part* __restrict__ in,
@@ -224,7 +224,7 @@ __device__ inline void step_body(int bx, int64_t k, int t, int64_t n_rem,
 }
 
 // panel rows -> R, columns by original index
-__device__ inline void scatter_body(int bx, int64_t t, int64_t ps, int nbp, int64_t n_rem,
+__device__ __forceinline__ void scatter_body(int bx, int64_t t, int64_t ps, int nbp, int64_t n_rem,
                                     const double* __restrict__ P, int64_t ldp, const int* rem0,
                                     const int* rem1, double* __restrict__ Rorig, int64_t ldr,
                                     const int* state) {
@@ -276,7 +276,7 @@ __device__ int64_t block_compact(int64_t n, const int* __restrict__ flag, const 
     return base;
 }
 
-__device__ inline void compact_body(int64_t n_rem, const int* __restrict__ chosen, int* rem0,
+__device__ __forceinline__ void compact_body(int64_t n_rem, const int* __restrict__ chosen, int* rem0,
                                     int* rem1, int* __restrict__ map, int* state) {
     if (state[ST_DONE]) return;
     const int cur = state[ST_CUR];
@@ -288,7 +288,7 @@ __device__ inline void compact_body(int64_t n_rem, const int* __restrict__ chose
 }
 
 // tail of the pivot order: the rejected indices, in their current order
-__device__ inline void finalize_body(int64_t n, const int* __restrict__ chosen, const int* rem0,
+__device__ __forceinline__ void finalize_body(int64_t n, const int* __restrict__ chosen, const int* rem0,
                                      const int* rem1, int* __restrict__ piv, int* state) {
     if (!state[ST_DONE]) {
         if (threadIdx.x == 0) state[ST_RANK] = (int)n;
@@ -304,7 +304,7 @@ __device__ inline void finalize_body(int64_t n, const int* __restrict__ chosen, 
 // tiles, mirrored.  4 waves in 2 x 2, each (TT/2)^2 as 16 x 16 FP64 MFMA
 // blocks; the panel rows are gathered through the compaction map into
 // k-major LDS tiles, double-buffered through registers.
-__device__ inline void trailing_body(int bx, int64_t n_new, const double* __restrict__ S,
+__device__ __forceinline__ void trailing_body(int bx, int64_t n_new, const double* __restrict__ S,
                                      int64_t lds, double* __restrict__ Sn, int64_t ldsn,
                                      const double* __restrict__ P, int64_t ldp, int nbp,
                                      const int* __restrict__ map, const int* state) {
@@ -453,7 +453,7 @@ constexpr int SMALL_N = 512;
 constexpr int SNB = 16;
 constexpr int SPT = 1024;
 
-__device__ inline void pchol_small_body(int n, const double* __restrict__ M, int64_t ldm,
+__device__ __forceinline__ void pchol_small_body(int n, const double* __restrict__ M, int64_t ldm,
                                         double* __restrict__ S, double tau, int32_t* __restrict__ piv,
                                         double* __restrict__ Rorig, int64_t ldr, int* state,
                                         double* pstats) {

@@ -169,90 +169,101 @@ __global__ __launch_bounds__(NT) void ht_kernel(int64_t N, int64_t L, int m,
 // ---------------------------------------------------------------------------
 // Streaming passes built for HBM bandwidth.
 //
-// rows_dot_kernel: out[row][o] = sign * (H beta)[row][o] + (T ? T[row][o] : 0)
-//   for RB rows per block; thread t walks columns t, t + 256, ... keeping
-//   RB x MM partial sums, so each beta row it loads (through the cache) serves
-//   RB rows of H; one block reduction at the end.  With labels, also the
-//   arg-max of each row (lowest index on ties).
+// rows_dot_kernel: out[row][o] = sign * (H beta)[row][o] + (T ? T[row][o] : 0).
+//   Each wave owns RW rows (RW MM <= 32 FP64 partial sums per lane);
+//   lane l walks columns l, l + 64, ..., and a 64-lane butterfly gives every
+//   lane the row sums.  The order of every sum is fixed by the column stride
+//   64 alone (not by the rows per wave or the launch), no LDS, no barrier.
+//   With labels, also the arg-max of each row (lowest index on ties).
 // cols_dot_kernel: part[chunk][col][o] = sum over the chunk's rows of
 //   H[row][col] E[row][o]; thread per column, the chunk's E rows in LDS.
 // ---------------------------------------------------------------------------
 constexpr int SB = 256;   // threads per block
-constexpr int RBR = 8;    // rows per block, rows_dot_kernel
 constexpr int CR_ROWS = 1024;  // rows per chunk, cols_dot_kernel
+template <int MM>
+struct RowsDot {
+    static constexpr int RW = MM <= 4 ? 8 : 32 / MM;  // rows per wave
+    static constexpr int RB = RW * SB / 64;  // rows per block
+};
 
 template <int MM>
-__global__ __launch_bounds__(SB) void rows_dot_kernel(int64_t N, int64_t L, int m,
-                                                      const double* __restrict__ H, int64_t ldh,
-                                                      const double* __restrict__ beta, int64_t ldb,
-                                                      const double* __restrict__ T, int64_t ldt,
-                                                      double sign, double* __restrict__ out,
-                                                      int64_t ldo, int32_t* __restrict__ labels,
-                                                      double* __restrict__ y, int64_t ldy) {
-    __shared__ double red[SB / 64][RBR * MM];
-    __shared__ double fin[RBR * MM];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * RBR;
-    double acc[RBR][MM];
+__device__ __forceinline__ void rows_dot_body(int64_t bx, int64_t N, int64_t L, int m,
+                                     const double* __restrict__ H, int64_t ldh,
+                                     const double* __restrict__ beta, int64_t ldb,
+                                     const double* __restrict__ T, int64_t ldt, double sign,
+                                     double* __restrict__ out, int64_t ldo,
+                                     int32_t* __restrict__ labels, double* __restrict__ y,
+                                     int64_t ldy) {
+    constexpr int RW = RowsDot<MM>::RW;
+    const int lane = threadIdx.x & 63;
+    // the wave index is uniform: row addresses stay in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t r0 = bx * RowsDot<MM>::RB + (int64_t)wave * RW;
+    if (r0 >= N) return;
+    double acc[RW][MM];
 #pragma unroll
-    for (int r = 0; r < RBR; ++r)
+    for (int r = 0; r < RW; ++r)
 #pragma unroll
         for (int c = 0; c < MM; ++c) acc[r][c] = 0.0;
-    const double* __restrict__ hrow[RBR];
+    const double* __restrict__ hrow[RW];
 #pragma unroll
-    for (int r = 0; r < RBR; ++r) hrow[r] = H + min(r0 + r, N - 1) * ldh;
-    for (int64_t col = tid; col < L; col += SB) {
+    for (int r = 0; r < RW; ++r) hrow[r] = H + min(r0 + r, N - 1) * ldh;
+#pragma unroll 2
+    for (int64_t col = lane; col < L; col += 64) {
         double bv[MM];
 #pragma unroll
         for (int c = 0; c < MM; ++c) bv[c] = c < m ? beta[col * ldb + c] : 0.0;
 #pragma unroll
-        for (int r = 0; r < RBR; ++r) {
+        for (int r = 0; r < RW; ++r) {
             const double h = hrow[r][col];
 #pragma unroll
             for (int c = 0; c < MM; ++c) acc[r][c] += h * bv[c];
         }
     }
 #pragma unroll
-    for (int r = 0; r < RBR; ++r)
+    for (int r = 0; r < RW; ++r)
 #pragma unroll
         for (int c = 0; c < MM; ++c) {
             double v = acc[r][c];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-            if (lane == 0) red[wave][r * MM + c] = v;
+            acc[r][c] = v;
         }
-    __syncthreads();
-    if (tid < RBR * MM) {
-        double v = 0.0;
-        for (int w = 0; w < SB / 64; ++w) v += red[w][tid];
-        const int r = tid / MM, c = tid % MM;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
         const int64_t row = r0 + r;
-        double o = sign * v;
-        if (T && row < N && c < m) o += T[row * ldt + c];
-        fin[tid] = v;
-        if (out && row < N && c < m) out[row * ldo + c] = o;
-        if (y && row < N && c < m) y[row * ldy + c] = v;
-    }
-    if (labels) {
-        __syncthreads();
-        if (tid < RBR && r0 + tid < N) {
+        if (row >= N) break;
+        // lane c < m writes column c of the row
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < MM; ++c)
+            if (lane == c) v = acc[r][c];
+        if (lane < m) {
+            if (out) out[row * ldo + lane] = sign * v + (T ? T[row * ldt + lane] : 0.0);
+            if (y) y[row * ldy + lane] = v;
+        }
+        if (labels && lane == 0) {
             int best = 0;
-            double bvv = fin[tid * MM];
-            for (int c = 1; c < m; ++c)
-                if (fin[tid * MM + c] > bvv) { bvv = fin[tid * MM + c]; best = c; }
-            labels[r0 + tid] = best;
+            double bvv = acc[r][0];
+#pragma unroll
+            for (int c = 1; c < MM; ++c)
+                if (c < m && acc[r][c] > bvv) {
+                    bvv = acc[r][c];
+                    best = c;
+                }
+            labels[row] = best;
         }
     }
 }
 
 template <int MM>
-__global__ __launch_bounds__(SB) void cols_dot_kernel(int64_t N, int64_t L, int m,
-                                                      const double* __restrict__ H, int64_t ldh,
-                                                      const double* __restrict__ E, int64_t lde,
-                                                      double* __restrict__ part) {
+__device__ __forceinline__ void cols_dot_body(int64_t bx, int64_t by, int64_t N, int64_t L, int m,
+                                     const double* __restrict__ H, int64_t ldh,
+                                     const double* __restrict__ E, int64_t lde,
+                                     double* __restrict__ part) {
     __shared__ double Es[CR_ROWS * MM];
     const int tid = threadIdx.x;
-    const int64_t col = (int64_t)blockIdx.x * SB + tid;
-    const int64_t rbeg = (int64_t)blockIdx.y * CR_ROWS;
+    const int64_t col = bx * SB + tid;
+    const int64_t rbeg = by * CR_ROWS;
     const int nrows = (int)min<int64_t>(CR_ROWS, N - rbeg);
     for (int e = tid; e < CR_ROWS * MM; e += SB) {
         const int r = e / MM, c = e % MM;
@@ -279,7 +290,7 @@ __global__ __launch_bounds__(SB) void cols_dot_kernel(int64_t N, int64_t L, int 
 #pragma unroll
             for (int c = 0; c < MM; ++c) acc[c] += hv * Es[r * MM + c];
         }
-        double* o = part + (int64_t)blockIdx.y * L * m + col * m;
+        double* o = part + by * L * m + col * m;
 #pragma unroll
         for (int c = 0; c < MM; ++c)
             if (c < m) o[c] = acc[c];
@@ -287,11 +298,10 @@ __global__ __launch_bounds__(SB) void cols_dot_kernel(int64_t N, int64_t L, int 
 }
 
 // G[i][o] = sum over chunks of the partials; per-block sum of squares
-__global__ __launch_bounds__(NT) void ht_reduce_kernel(int64_t L, int m, int nchunk,
-                                                       const double* __restrict__ part,
-                                                       double* __restrict__ G, int64_t ldg,
-                                                       double* __restrict__ sq_part) {
-    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+__device__ __forceinline__ void ht_reduce_body(int64_t bx, int64_t L, int m, int nchunk,
+                                      const double* __restrict__ part, double* __restrict__ G,
+                                      int64_t ldg, double* __restrict__ sq_part) {
+    const int64_t e = bx * NT + threadIdx.x;
     double sq = 0.0;
     if (e < L * m) {
         double s = 0.0;
@@ -307,11 +317,10 @@ __global__ __launch_bounds__(NT) void ht_reduce_kernel(int64_t L, int m, int nch
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) sq_part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) sq_part[bx] = red[0];
 }
 
-__global__ __launch_bounds__(NT) void sum_kernel(int64_t n, const double* __restrict__ x,
-                                                 double* __restrict__ out) {
+__device__ __forceinline__ void sum_body(int64_t n, const double* __restrict__ x, double* __restrict__ out) {
     __shared__ double red[NT];
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += NT) s += x[i];
@@ -324,33 +333,163 @@ __global__ __launch_bounds__(NT) void sum_kernel(int64_t n, const double* __rest
     if (threadIdx.x == 0) out[0] = red[0];
 }
 
-__global__ void axpy_mat_kernel(int64_t rows, int64_t cols, const double* __restrict__ X,
-                                int64_t ldx, double* __restrict__ Y, int64_t ldy) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void axpy_mat_body(int64_t bx, int64_t rows, int64_t cols,
+                                     const double* __restrict__ X, int64_t ldx,
+                                     double* __restrict__ Y, int64_t ldy) {
+    const int64_t e = bx * blockDim.x + threadIdx.x;
     if (e < rows * cols) {
         const int64_t i = e / cols, j = e % cols;
         Y[i * ldy + j] += X[i * ldx + j];
     }
 }
 
+template <int MM>
+__global__ __launch_bounds__(SB, 2) void rows_dot_kernel(int64_t N, int64_t L, int m,
+                                                      const double* __restrict__ H, int64_t ldh,
+                                                      const double* __restrict__ beta, int64_t ldb,
+                                                      const double* __restrict__ T, int64_t ldt,
+                                                      double sign, double* __restrict__ out,
+                                                      int64_t ldo, int32_t* __restrict__ labels,
+                                                      double* __restrict__ y, int64_t ldy) {
+    rows_dot_body<MM>(blockIdx.x, N, L, m, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y,
+                      ldy);
+}
+
+template <int MM>
+__global__ __launch_bounds__(SB) void cols_dot_kernel(int64_t N, int64_t L, int m,
+                                                      const double* __restrict__ H, int64_t ldh,
+                                                      const double* __restrict__ E, int64_t lde,
+                                                      double* __restrict__ part) {
+    cols_dot_body<MM>(blockIdx.x, blockIdx.y, N, L, m, H, ldh, E, lde, part);
+}
+
+__global__ __launch_bounds__(NT) void ht_reduce_kernel(int64_t L, int m, int nchunk,
+                                                       const double* __restrict__ part,
+                                                       double* __restrict__ G, int64_t ldg,
+                                                       double* __restrict__ sq_part) {
+    ht_reduce_body(blockIdx.x, L, m, nchunk, part, G, ldg, sq_part);
+}
+
+__global__ __launch_bounds__(NT) void sum_kernel(int64_t n, const double* __restrict__ x,
+                                                 double* __restrict__ out) {
+    sum_body(n, x, out);
+}
+
+__global__ void axpy_mat_kernel(int64_t rows, int64_t cols, const double* __restrict__ X,
+                                int64_t ldx, double* __restrict__ Y, int64_t ldy) {
+    axpy_mat_body(blockIdx.x, rows, cols, X, ldx, Y, ldy);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped refinement passes: one launch serves every scheduled problem of a
+// batch.  The launch's blocks are laid out problem after problem (GroupSched);
+// each block runs the single-problem kernel's body with that problem's
+// arguments and its own block index, so the arithmetic is the same.
+// ---------------------------------------------------------------------------
+template <int MM>
+__global__ __launch_bounds__(SB, 2) void rows_dot_grouped(const RefineDesc* __restrict__ d,
+                                                       GroupSched g) {
+    int64_t lb;
+    const RefineDesc& q = d[group_problem(g, lb)];
+    rows_dot_body<MM>(lb, q.N, q.L, q.m, q.H, q.ldh, q.beta, q.ldbeta, q.T, q.ldt, -1.0, q.E, q.m,
+                      nullptr, nullptr, 0);
+}
+
+template <int MM>
+__global__ __launch_bounds__(SB) void cols_dot_grouped(const RefineDesc* __restrict__ d,
+                                                       GroupSched g) {
+    int64_t lb;
+    const RefineDesc& q = d[group_problem(g, lb)];
+    const int64_t nbx = cdiv(q.L, SB);
+    cols_dot_body<MM>(lb % nbx, lb / nbx, q.N, q.L, q.m, q.H, q.ldh, q.E, q.m, q.part);
+}
+
+__global__ __launch_bounds__(NT) void ht_reduce_grouped(const RefineDesc* __restrict__ d,
+                                                        GroupSched g) {
+    int64_t lb;
+    const RefineDesc& q = d[group_problem(g, lb)];
+    ht_reduce_body(lb, q.L, q.m, (int)cdiv(q.N, CR_ROWS), q.part, q.G, q.m, q.sq);
+}
+
+__global__ __launch_bounds__(NT) void sum_grouped(const RefineDesc* __restrict__ d, GroupSched g) {
+    int64_t lb;
+    const RefineDesc& q = d[group_problem(g, lb)];
+    sum_body(cdiv(q.L * q.m, NT), q.sq, q.g2);
+}
+
+__global__ void axpy_grouped(const RefineDesc* __restrict__ d, GroupSched g) {
+    int64_t lb;
+    const RefineDesc& q = d[group_problem(g, lb)];
+    axpy_mat_body(lb, q.L, q.m, q.D, q.m, q.beta, q.ldbeta);
+}
+
 }  // namespace
+
+int64_t refine_group_blocks(RefinePass pass, const RefineDesc& q, int maxm) {
+    switch (pass) {
+        case RefinePass::ROWS_DOT:
+            return cdiv(q.N, maxm <= 2 ? RowsDot<2>::RB
+                             : maxm <= 4 ? RowsDot<4>::RB
+                             : maxm <= 8 ? RowsDot<8>::RB : RowsDot<16>::RB);
+        case RefinePass::COLS_DOT: return cdiv(q.L, SB) * cdiv(q.N, CR_ROWS);
+        case RefinePass::HT_REDUCE: return cdiv(q.L * q.m, NT);
+        case RefinePass::SUM: return 1;
+        case RefinePass::AXPY: return cdiv(q.L * q.m, 256);
+    }
+    return 0;
+}
+
+size_t refine_part_doubles(int64_t N, int64_t L, int64_t m) { return (size_t)cdiv(N, CR_ROWS) * L * m; }
+size_t refine_sq_doubles(int64_t L, int64_t m) { return (size_t)cdiv(L * m, NT); }
+
+void launch_refine_grouped(hipStream_t s, RefinePass pass, const RefineDesc* d, const GroupSched& g,
+                           int maxm) {
+    if (g.count <= 0 || g.blocks <= 0) return;
+    const unsigned grid = (unsigned)g.blocks;
+    switch (pass) {
+        case RefinePass::ROWS_DOT:
+        case RefinePass::COLS_DOT: {
+#define ELM_RG(MM)                                                                   \
+    do {                                                                             \
+        if (pass == RefinePass::ROWS_DOT)                                            \
+            rows_dot_grouped<MM><<<grid, SB, 0, s>>>(d, g);                          \
+        else                                                                         \
+            cols_dot_grouped<MM><<<grid, SB, 0, s>>>(d, g);                          \
+    } while (0)
+            if (maxm <= 2) ELM_RG(2);
+            else if (maxm <= 4) ELM_RG(4);
+            else if (maxm <= 8) ELM_RG(8);
+            else if (maxm <= 16) ELM_RG(16);
+            else throw Error{ELM_ERR_UNSUPPORTED, "grouped refinement needs m <= 16"};
+#undef ELM_RG
+            break;
+        }
+        case RefinePass::HT_REDUCE: ht_reduce_grouped<<<grid, NT, 0, s>>>(d, g); break;
+        case RefinePass::SUM: sum_grouped<<<grid, NT, 0, s>>>(d, g); break;
+        case RefinePass::AXPY: axpy_grouped<<<grid, 256, 0, s>>>(d, g); break;
+    }
+    ELM_LAUNCH_CHECK();
+}
 
 static void launch_rows_dot(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
                             int64_t ldh, const double* beta, int64_t ldb, const double* T, int64_t ldt,
                             double sign, double* out, int64_t ldo, int32_t* labels,
                             double* y = nullptr, int64_t ldy = 0) {
-    const unsigned grid = (unsigned)cdiv(N, RBR);
     const int mi = (int)m;
+#define ELM_RD(MM)                                                                                  \
+    rows_dot_kernel<MM><<<(unsigned)cdiv(N, RowsDot<MM>::RB), SB, 0, s>>>(                          \
+        N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy)
     if (m <= 2)
-        rows_dot_kernel<2><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy);
+        ELM_RD(2);
     else if (m <= 4)
-        rows_dot_kernel<4><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy);
+        ELM_RD(4);
     else if (m <= 8)
-        rows_dot_kernel<8><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy);
+        ELM_RD(8);
     else if (m <= 16)
-        rows_dot_kernel<16><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy);
+        ELM_RD(16);
     else
         throw Error{ELM_ERR_UNSUPPORTED, "m > 16 on the streaming row pass"};
+#undef ELM_RD
     ELM_LAUNCH_CHECK();
 }
 

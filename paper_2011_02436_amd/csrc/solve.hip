@@ -82,13 +82,12 @@ __global__ void zero_mat_kernel(int64_t rows, int64_t cols, double* __restrict__
 // of A's row and of B's rows), fixed-order wave reduction.  tri restricts k
 // to the nonzero part of a triangular A (1: k >= i, 2: k <= i).
 template <int MM>
-__global__ __launch_bounds__(256) void rowprod_kernel(int64_t M, int64_t K, int m, double alpha,
-                                                      const double* __restrict__ A, int64_t lda,
-                                                      int tri, const double* __restrict__ B,
-                                                      int64_t ldb, double beta, double* C,
-                                                      int64_t ldc) {
+__device__ __forceinline__ void rowprod_body(int64_t bx, int64_t M, int64_t K, int m, double alpha,
+                                    const double* __restrict__ A, int64_t lda, int tri,
+                                    const double* __restrict__ B, int64_t ldb, double beta,
+                                    double* C, int64_t ldc) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t i = bx * 4 + (threadIdx.x >> 6);
     if (i >= M) return;
     int64_t kb = 0, ke = K;
     if (tri == 1) kb = i;
@@ -118,6 +117,39 @@ __global__ __launch_bounds__(256) void rowprod_kernel(int64_t M, int64_t K, int 
                 if (beta != 0.0) v += beta * C[i * ldc + c];
                 C[i * ldc + c] = v;
             }
+}
+
+template <int MM>
+__global__ __launch_bounds__(256) void rowprod_kernel(int64_t M, int64_t K, int m, double alpha,
+                                                      const double* __restrict__ A, int64_t lda,
+                                                      int tri, const double* __restrict__ B,
+                                                      int64_t ldb, double beta, double* C,
+                                                      int64_t ldc) {
+    rowprod_body<MM>(blockIdx.x, M, K, m, alpha, A, lda, tri, B, ldb, beta, C, ldc);
+}
+
+template <int MM>
+__global__ __launch_bounds__(256) void rowprod_grouped(const RowprodDesc* __restrict__ d,
+                                                       GroupSched g) {
+    int64_t lb;
+    const RowprodDesc& q = d[group_problem(g, lb)];
+    rowprod_body<MM>(lb, q.M, q.K, q.m, q.alpha, q.A, q.lda, q.tri, q.B, q.ldb, q.beta, q.C, q.ldc);
+}
+
+// row copies of the grouped apply, one element per thread
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void copy_rows_grouped(const CopyRowsDesc* __restrict__ d,
+                                                         GroupSched g) {
+    int64_t lb;
+    const CopyRowsDesc& q = d[group_problem(g, lb)];
+    const int64_t e = lb * 256 + threadIdx.x;
+    if (e >= q.rows * q.cols) return;
+    const int64_t i = e / q.cols, c = e % q.cols;
+    const int64_t j = q.idx[i];
+    if (SCATTER)
+        q.dst[j * q.ldd + c] = q.src[i * q.lds + c];
+    else
+        q.dst[i * q.ldd + c] = q.src[j * q.lds + c];
 }
 
 // B = A^T for an R x C matrix A (ld lda) into B (C x R, ld ldb)
@@ -257,6 +289,35 @@ void apply_f_gram_inv(hipStream_t s, const elm_factor* f, int64_t m, double* y, 
 }
 
 }  // namespace
+
+int64_t rowprod_group_blocks(const RowprodDesc& q) { return q.M > 0 ? cdiv(q.M, 4) : 0; }
+
+int64_t copy_rows_group_blocks(const CopyRowsDesc& q) { return cdiv(q.rows * q.cols, 256); }
+
+void launch_rowprod_grouped(hipStream_t s, const RowprodDesc* d, const GroupSched& g, int maxm) {
+    if (g.count <= 0 || g.blocks <= 0) return;
+    const unsigned grid = (unsigned)g.blocks;
+    // the template follows the single-problem rule; the products do not depend on it
+    if (maxm <= 4)
+        rowprod_grouped<4><<<grid, 256, 0, s>>>(d, g);
+    else if (maxm <= 8)
+        rowprod_grouped<8><<<grid, 256, 0, s>>>(d, g);
+    else if (maxm <= 16)
+        rowprod_grouped<16><<<grid, 256, 0, s>>>(d, g);
+    else
+        rowprod_grouped<64><<<grid, 256, 0, s>>>(d, g);
+    ELM_LAUNCH_CHECK();
+}
+
+void launch_copy_rows_grouped(hipStream_t s, bool scatter, const CopyRowsDesc* d,
+                              const GroupSched& g) {
+    if (g.count <= 0 || g.blocks <= 0) return;
+    if (scatter)
+        copy_rows_grouped<true><<<(unsigned)g.blocks, 256, 0, s>>>(d, g);
+    else
+        copy_rows_grouped<false><<<(unsigned)g.blocks, 256, 0, s>>>(d, g);
+    ELM_LAUNCH_CHECK();
+}
 
 void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws, bool wait) {
     const int64_t r = f->r, n = f->n, c = n - r;

@@ -164,3 +164,45 @@ def test_batched_replays_are_identical(elm, mixed):
         for e in range(len(probs)):
             assert torch.equal(again[e], first[e]), (rep, e)
             assert infos[e]["rank"] == infos0[e]["rank"] == refs[e][1]
+
+
+def _solve_fields(info):
+    return (info["rank"], info["iterations"], info["ne_residual"], info["transposed"])
+
+
+def test_batched_bf16_equals_single_trainings(elm, batch):
+    # BF16 Grams need different numbers of corrections per problem, so the
+    # problems leave the shared refinement loop at different iterations
+    probs, _ = batch
+    dev = [_dev(p) for p in probs[:8]]
+    betas, infos, stats = elm.train_batched(dev, precision="bf16", ir_tol=1e-12)
+    assert stats == [0] * len(dev)
+    its = set()
+    for e, (X, W, b, T) in enumerate(dev):
+        one = elm.train(X, W, b, T, precision="bf16", ir_tol=1e-12)
+        assert torch.equal(one.beta, betas[e]), e
+        assert _solve_fields(one.info) == _solve_fields(infos[e]), e
+        assert one.info["ne_history"] == infos[e]["ne_history"], e
+        if probs[e].N >= probs[e].L:
+            its.add(infos[e]["iterations"])
+    print(f"iterations per problem: {sorted(its)}")
+    assert len(its) > 1
+
+
+@pytest.mark.parametrize("ir_max_iter", [0, 1])
+def test_batched_iteration_cap_equals_single_trainings(elm, batch, ir_max_iter):
+    # ir_tol = 0 is never reached: every problem stops at the cap (or when a
+    # correction makes no progress) with NO_CONVERGENCE, beta the last iterate
+    probs, _ = batch
+    dev = [_dev(p) for p in probs[:6]]
+    betas, infos, stats = elm.train_batched(dev, precision="fp64", ir_tol=0.0, ir_max_iter=ir_max_iter,
+                                            check=False)
+    for e, (X, W, b, T) in enumerate(dev):
+        one = elm.train(X, W, b, T, precision="fp64", ir_tol=0.0, ir_max_iter=ir_max_iter,
+                        check_convergence=False)
+        assert torch.equal(one.beta, betas[e]), e
+        assert _solve_fields(one.info) == _solve_fields(infos[e]), e
+        if ir_max_iter == 0:
+            assert stats[e] == 0 and infos[e]["ne_residual"] == -1.0
+        else:
+            assert stats[e] == elm.ELM_ERR_NO_CONVERGENCE and infos[e]["iterations"] <= 1
