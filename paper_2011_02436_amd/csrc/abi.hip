@@ -1353,9 +1353,9 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 elm::check_status(wh, s2);
             };
 
-            // phase 3a (workers): factor tails; beta and refinement of the
-            // problems that do not run grouped
+            // phase 3a (workers): the problems that do not run grouped
             run_workers(grp, [&](elm_handle* wh, int32_t e) {
+                if (grouped[e]) return;
                 const elm_problem& p = probs[e];
                 Item& it = items[e];
                 const elm::PcholProblem& q = pc[pc_of[e]];
@@ -1376,17 +1376,10 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 f->gram_dtype = it.gdt;
                 f->tau = q.tau;
                 f->r = q.rank;
-                if (grouped[e]) {
-                    // the grouped factorisation's pivots stay valid until the next group
-                    f->arena = farena + foff[e];
-                    f->arena_left = fsize[e];
-                    f->piv = const_cast<int32_t*>(q.piv);
-                } else {
-                    f->pool = &wh->ws;
-                    f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)it.n * sizeof(int32_t));
-                    ELM_HIP_TRY(hipMemcpyAsync(f->piv, q.piv, (size_t)it.n * sizeof(int32_t),
-                                               hipMemcpyDeviceToDevice, ws));
-                }
+                f->pool = &wh->ws;
+                f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)it.n * sizeof(int32_t));
+                ELM_HIP_TRY(hipMemcpyAsync(f->piv, q.piv, (size_t)it.n * sizeof(int32_t),
+                                           hipMemcpyDeviceToDevice, ws));
                 if (f->r > 0) {
                     f->R = (double*)elm::factor_alloc(f, "R", (size_t)f->r * it.n * sizeof(double));
                     elm::launch_gather_rows(ws, f->r, it.n, q.Rorig, it.n, q.piv, f->R, it.n);
@@ -1403,13 +1396,6 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 const bool can_escalate = it.gdt != ELM_F64;
                 if (can_escalate && !f->reliable) {
                     escalate(wh, e, 1);
-                    return;
-                }
-                if (grouped[e]) {
-                    elm::StageScope sc(&wh->prof, ELM_STAGE_FACTOR, ws);
-                    elm::build_factor_tail(ws, f, wh->ws, /*wait=*/true);
-                    bg.f = nullptr;
-                    gfac[e] = std::move(fp);
                     return;
                 }
                 {
@@ -1431,8 +1417,68 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 escalate(wh, e, 2);
             });
 
-            // phase 3b (one stream): beta and refinement of the grouped problems
+            // phase 3b (one stream): factor tails, beta and refinement of the
+            // grouped problems
             wait_workers(ps);
+            {
+                std::vector<elm_factor*> tf;
+                std::vector<const double*> rorig;
+                std::vector<int32_t> tf_of;
+                for (int32_t e : grp) {
+                    if (!grouped[e]) continue;
+                    const elm_problem& p = probs[e];
+                    const Item& it = items[e];
+                    const elm::PcholProblem& q = pc[pc_of[e]];
+                    std::unique_ptr<elm_factor> f(new elm_factor());
+                    f->N = p.N;
+                    f->L = p.L;
+                    f->n = it.n;
+                    f->transposed = false;
+                    f->device = h->device;
+                    f->gram_dtype = it.gdt;
+                    f->tau = q.tau;
+                    f->r = q.rank;
+                    // the grouped factorisation's pivots stay valid until the next group
+                    f->arena = farena + foff[e];
+                    f->arena_left = fsize[e];
+                    f->piv = const_cast<int32_t*>(q.piv);
+                    f->R = (double*)elm::factor_alloc(f.get(), "R", (size_t)f->r * it.n * sizeof(double));
+                    const double hd = hdmax[slot[e]];
+                    f->last_pivot = q.stats[0];
+                    f->first_rejected = q.stats[1];
+                    f->max_diag = hd;
+                    f->noise_floor =
+                        elm::schur_noise_floor(it.gdt, it.n, std::max(p.N, p.L), it.kc) * hd;
+                    f->reliable = reliable_of(e);
+                    elm_train_info& ti = info_all[e];
+                    elm::check_status(h, elm_factor_get_info(f.get(), &ti.factor));
+                    ti.gram_dtype = it.gdt;
+                    tf.push_back(f.get());
+                    rorig.push_back(q.Rorig);
+                    tf_of.push_back(e);
+                    gfac[e] = std::move(f);
+                }
+                try {
+                    std::vector<int> bad;
+                    {
+                        elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, ps);
+                        bad = elm::build_factor_tails_grouped(ps, tf, rorig, h->ws);
+                    }
+                    for (size_t j = 0; j < tf_of.size(); ++j)
+                        if (bad[j]) {
+                            const int32_t e = tf_of[j];
+                            st_all[e] = ELM_ERR_NOT_PSD;
+                            msg_all[e] = "Gram of G is not positive definite";
+                            items[e].ok = false;
+                        }
+                } catch (const elm::Error& err) {
+                    for (int32_t e : tf_of) {
+                        st_all[e] = err.st;
+                        msg_all[e] = err.msg;
+                        items[e].ok = false;
+                    }
+                }
+            }
             std::vector<elm::GroupedSolve> gs;
             std::vector<int32_t> gs_of;
             for (int32_t e : grp) {

@@ -64,10 +64,9 @@ __global__ void zero_lower_kernel(int64_t n, double* __restrict__ U, int64_t ldu
 // (with the stop decision); after one block barrier every thread applies
 // the row to its elements.  Row and pivot buffers alternate between steps,
 // so one barrier per step suffices.
-__global__ __launch_bounds__(CPT) void potrf_block_kernel(double* __restrict__ U, int64_t ldu,
-                                                          int64_t k0, int nb, double thr,
-                                                          double* __restrict__ W, int64_t ldw,
-                                                          int* flag) {
+__device__ __forceinline__ void potrf_block_body(double* __restrict__ U, int64_t ldu, int64_t k0,
+                                                 int nb, double thr, double* __restrict__ W,
+                                                 int64_t ldw, int* flag) {
     static_assert(CB == 128 && CPT == 1024, "4 x 4 elements per thread of a 32 x 32 grid");
     __shared__ double rowb[2][CB];
     __shared__ int stop[2];
@@ -180,6 +179,21 @@ __global__ __launch_bounds__(CPT) void potrf_block_kernel(double* __restrict__ U
             const int i = ty + 32 * a, c = tx + 32 * b;
             if (i < nb && c < nb) W[i * ldw + c] = c >= i ? w[a][b] : 0.0;
         }
+}
+
+__global__ __launch_bounds__(CPT) void potrf_block_kernel(double* __restrict__ U, int64_t ldu,
+                                                          int64_t k0, int nb, double thr,
+                                                          double* __restrict__ W, int64_t ldw,
+                                                          int* flag) {
+    potrf_block_body(U, ldu, k0, nb, thr, W, ldw, flag);
+}
+
+// one block per factor: dst (rows <= CB) factored in place, aux = its inverse
+__global__ __launch_bounds__(CPT) void chol_inv_small_grouped(const MatDesc* __restrict__ d,
+                                                              GroupSched g) {
+    int64_t lb;
+    const MatDesc& q = d[group_problem(g, lb)];
+    potrf_block_body(q.dst, q.ldd, 0, (int)q.rows, 0.0, q.aux, q.lda, q.flag);
 }
 
 // T (nb x nc, ld nc) = U[k0 .. k0 + nb)[c0 .. c0 + nc)
@@ -302,6 +316,12 @@ void cholesky_blocked(hipStream_t s, int64_t n, double* U, int64_t ldu, double t
     // it; U must be zero there
     zero_lower_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)std::min<int64_t>(n, 65535)), 256, 0,
                         s>>>(n, U, ldu);
+    ELM_LAUNCH_CHECK();
+}
+
+void launch_chol_inv_small_grouped(hipStream_t s, const MatDesc* d, const GroupSched& g) {
+    if (g.count <= 0 || g.blocks <= 0) return;
+    chol_inv_small_grouped<<<(unsigned)g.blocks, CPT, 0, s>>>(d, g);
     ELM_LAUNCH_CHECK();
 }
 

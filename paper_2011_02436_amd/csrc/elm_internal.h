@@ -373,6 +373,14 @@ void launch_iota(hipStream_t s, int64_t n, int32_t* piv);
 void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws, bool wait = true);
 void apply_pinv(hipStream_t s, const elm_factor* f, int64_t m, const double* rhs, int64_t ldr,
                 const double* H64, int64_t ldh64, double* out, int64_t ldo, Workspace& ws);
+// build_factor_tail for several factors (rank >= 1, buffers from factor_alloc)
+// at once: every step one launch for all of them, with the same kernels and
+// arithmetic per factor; Grams of G above order 128 take the blocked Cholesky
+// one by one.  Rorig[p] (may be NULL): R of factor p is first gathered from it
+// (n x n, ld n, columns by original index) through f->piv.  Returns per
+// factor 1 when the Gram of G is not positive definite; synchronises once.
+std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm_factor*>& fs,
+                                            const std::vector<const double*>& Rorig, Workspace& ws);
 
 // refine.hip: streaming FP64 passes over sample-major H
 //   E = T - H beta  (N x m)
@@ -422,6 +430,49 @@ __device__ inline int group_problem(const GroupSched& g, int64_t& local) {
     local = b - g.start[lo];
     return g.prob[lo];
 }
+
+// gemm.hip, grouped: one (batched) product of gemm_f64_batched
+struct GemmDesc {
+    int64_t M = 0, N = 0, K = 0, batch = 0;
+    double alpha = 1.0, beta = 0.0;
+    const double* A = nullptr;
+    int64_t a_rs = 0, a_cs = 0, a_bs = 0;
+    const double* B = nullptr;
+    int64_t b_rs = 0, b_cs = 0, b_bs = 0;
+    double* C = nullptr;
+    int64_t ldc = 0, c_bs = 0;
+    int tri_a = 0, tri_b = 0;
+};
+// the tile gemm_f64_batched takes for this shape (128 or 64); the result does
+// not depend on it (every tile sums k in the same order, and the products a
+// triangular operand skips are exact zeros)
+int gemm_tile(const GemmDesc& q);
+int64_t gemm_group_blocks(const GemmDesc& q, int ts);
+void launch_gemm_grouped(hipStream_t s, int ts, const GemmDesc* d, const GroupSched& g);
+
+// solve.hip / chol.hip, grouped: one matrix step of a factor tail
+struct MatDesc {
+    int64_t rows = 0, cols = 0;
+    const double* src = nullptr;
+    int64_t lds = 0;
+    double* dst = nullptr;
+    int64_t ldd = 0;
+    const int32_t* idx = nullptr;
+    double* aux = nullptr;
+    int64_t lda = 0;
+    int* flag = nullptr;
+};
+enum class MatOp {
+    ZERO,          // dst (rows x cols) = 0
+    TRANSPOSE,     // dst (cols x rows) = src^T
+    ADD_IDENTITY,  // dst[i][i] += 1, i < rows
+    GATHER_COLS,   // dst[i][j] = src[i][idx[j]]
+    TRTRI_LEAF,    // the leaf diagonal blocks of dst = src^-1 (src upper triangular, rows x rows)
+    CHOL_INV_SMALL // dst (rows <= 128) = U^T U in place, aux = U^-1 (ld lda), *flag at a pivot <= 0
+};
+int64_t mat_group_blocks(MatOp op, const MatDesc& q);
+void launch_mat_grouped(hipStream_t s, MatOp op, const MatDesc* d, const GroupSched& g);
+void launch_chol_inv_small_grouped(hipStream_t s, const MatDesc* d, const GroupSched& g);
 
 // refine.hip, grouped: one problem's refinement buffers (m <= 16)
 struct RefineDesc {

@@ -24,14 +24,13 @@ constexpr int BK = 16;
 // through registers.  The 128-wide tile runs 8 waves (four per SIMD with two
 // blocks per CU), so each wave holds 4 x 2 accumulator blocks.
 template <int TS, int NTH>
-__global__ __launch_bounds__(NTH, NTH / 128) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
-                                                     const double* __restrict__ A, int64_t a_rs,
-                                                     int64_t a_cs, int64_t a_bs,
-                                                     const double* __restrict__ B, int64_t b_rs,
-                                                     int64_t b_cs, int64_t b_bs, double beta,
-                                                     double* __restrict__ C, int64_t ldc,
-                                                     int64_t c_bs, int tri_a, int tri_b, int upper_c,
-                                                     const int* __restrict__ skip) {
+__device__ __forceinline__ void gemm_body(int64_t bx, int64_t by, int64_t bz, int64_t M, int64_t N,
+                                          int64_t K, double alpha, const double* __restrict__ A,
+                                          int64_t a_rs, int64_t a_cs, int64_t a_bs,
+                                          const double* __restrict__ B, int64_t b_rs, int64_t b_cs,
+                                          int64_t b_bs, double beta, double* __restrict__ C,
+                                          int64_t ldc, int64_t c_bs, int tri_a, int tri_b,
+                                          int upper_c, const int* __restrict__ skip) {
     constexpr int P = TS + 16;           // LDS pitch (see the hidden-layer kernel)
     constexpr int EPT = TS * BK / NTH;   // elements per thread per operand tile
     constexpr int WGN = NTH / 128;       // waves across the tile's columns
@@ -40,12 +39,12 @@ __global__ __launch_bounds__(NTH, NTH / 128) void gemm_kernel(int64_t M, int64_t
     static_assert(EPT >= 1 && WBJ >= 1, "tile and block size");
     __shared__ double As[2][BK][P];
     __shared__ double Bs[2][BK][P];
-    const int64_t i0 = (int64_t)blockIdx.x * TS, j0 = (int64_t)blockIdx.y * TS;
+    const int64_t i0 = bx * TS, j0 = by * TS;
     if (upper_c && i0 >= j0 + TS) return;  // strictly below the diagonal
     if (skip && *skip) return;
-    A += (int64_t)blockIdx.z * a_bs;
-    B += (int64_t)blockIdx.z * b_bs;
-    C += (int64_t)blockIdx.z * c_bs;
+    A += bz * a_bs;
+    B += bz * b_bs;
+    C += bz * c_bs;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     const bool a_kcontig = (a_cs == 1);
@@ -147,14 +146,57 @@ __global__ __launch_bounds__(NTH, NTH / 128) void gemm_kernel(int64_t M, int64_t
             }
 }
 
+template <int TS, int NTH>
+__global__ __launch_bounds__(NTH, NTH / 128) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                     const double* __restrict__ A, int64_t a_rs,
+                                                     int64_t a_cs, int64_t a_bs,
+                                                     const double* __restrict__ B, int64_t b_rs,
+                                                     int64_t b_cs, int64_t b_bs, double beta,
+                                                     double* __restrict__ C, int64_t ldc,
+                                                     int64_t c_bs, int tri_a, int tri_b, int upper_c,
+                                                     const int* __restrict__ skip) {
+    gemm_body<TS, NTH>(blockIdx.x, blockIdx.y, blockIdx.z, M, N, K, alpha, A, a_rs, a_cs, a_bs, B,
+                       b_rs, b_cs, b_bs, beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);
+}
+
+// products of a grouped launch: blocks of a descriptor run over its tiles
+// (rows fastest, then columns, then the batch)
+template <int TS, int NTH>
+__global__ __launch_bounds__(NTH, NTH / 128) void gemm_grouped(const GemmDesc* __restrict__ d,
+                                                               GroupSched g) {
+    int64_t lb;
+    const GemmDesc& q = d[group_problem(g, lb)];
+    const int64_t nx = cdiv(q.M, TS), ny = cdiv(q.N, TS);
+    const int64_t bx = lb % nx, t = lb / nx;
+    gemm_body<TS, NTH>(bx, t % ny, t / ny, q.M, q.N, q.K, q.alpha, q.A, q.a_rs, q.a_cs, q.a_bs, q.B,
+                       q.b_rs, q.b_cs, q.b_bs, q.beta, q.C, q.ldc, q.c_bs, q.tri_a, q.tri_b, 0,
+                       nullptr);
+}
+
 }  // namespace
+
+int gemm_tile(const GemmDesc& q) { return (q.M >= 128 && q.N >= 128) ? 128 : 64; }
+
+int64_t gemm_group_blocks(const GemmDesc& q, int ts) {
+    if (q.M <= 0 || q.N <= 0 || q.batch <= 0) return 0;
+    return cdiv(q.M, ts) * cdiv(q.N, ts) * q.batch;
+}
+
+void launch_gemm_grouped(hipStream_t s, int ts, const GemmDesc* d, const GroupSched& g) {
+    if (g.count <= 0 || g.blocks <= 0) return;
+    if (ts == 128)
+        gemm_grouped<128, 512><<<(unsigned)g.blocks, 512, 0, s>>>(d, g);
+    else
+        gemm_grouped<64, 256><<<(unsigned)g.blocks, 256, 0, s>>>(d, g);
+    ELM_LAUNCH_CHECK();
+}
 
 void gemm_f64_batched(hipStream_t s, int64_t batch, int64_t M, int64_t N, int64_t K, double alpha,
                       const double* A, int64_t a_rs, int64_t a_cs, int64_t a_bs, const double* B,
                       int64_t b_rs, int64_t b_cs, int64_t b_bs, double beta, double* C, int64_t ldc,
                       int64_t c_bs, bool tri_a, bool tri_b, bool upper_c, const int* skip) {
     if (M <= 0 || N <= 0 || batch <= 0) return;
-    if (M >= 128 && N >= 128) {
+    if (M >= 128 && N >= 128) {  // the rule of gemm_tile
         dim3 grid((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128), (unsigned)batch);
         gemm_kernel<128, 512><<<grid, 512, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs,
                                                    b_bs, beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);

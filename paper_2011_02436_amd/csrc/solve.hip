@@ -15,6 +15,10 @@
 //   [A B; 0 C]^-1 = [A^-1, -A^-1 B C^-1; 0, C^-1].
 #include "elm_internal.h"
 
+#include <algorithm>
+#include <cstring>
+#include <functional>
+
 namespace elm {
 
 namespace {
@@ -22,12 +26,11 @@ namespace {
 constexpr int LB = 64;  // leaf block of the triangular inverse
 
 // invert the LB x LB (or smaller, last) diagonal blocks of upper-triangular U
-__global__ __launch_bounds__(LB) void trtri_leaf_kernel(int64_t r, const double* __restrict__ U,
-                                                        int64_t ldu, double* __restrict__ X,
-                                                        int64_t ldx) {
+__device__ __forceinline__ void trtri_leaf_body(int64_t bx, int64_t r, const double* __restrict__ U,
+                                                int64_t ldu, double* __restrict__ X, int64_t ldx) {
     __shared__ double Us[LB][LB + 1];
     __shared__ double Xs[LB][LB + 1];
-    const int64_t b0 = (int64_t)blockIdx.x * LB;
+    const int64_t b0 = bx * LB;
     const int nb = (int)((r - b0) < LB ? (r - b0) : LB);
     const int j = threadIdx.x;
     for (int i = 0; i < nb; ++i)
@@ -46,6 +49,12 @@ __global__ __launch_bounds__(LB) void trtri_leaf_kernel(int64_t r, const double*
     __syncthreads();
     for (int i = 0; i < nb; ++i)
         if (j < nb) X[(b0 + i) * ldx + b0 + j] = Xs[i][j];
+}
+
+__global__ __launch_bounds__(LB) void trtri_leaf_kernel(int64_t r, const double* __restrict__ U,
+                                                        int64_t ldu, double* __restrict__ X,
+                                                        int64_t ldx) {
+    trtri_leaf_body(blockIdx.x, r, U, ldu, X, ldx);
 }
 
 __global__ void add_identity_kernel(int64_t q, double* A, int64_t lda) {
@@ -153,10 +162,11 @@ __global__ __launch_bounds__(256) void copy_rows_grouped(const CopyRowsDesc* __r
 }
 
 // B = A^T for an R x C matrix A (ld lda) into B (C x R, ld ldb)
-__global__ void transpose_kernel(int64_t R, int64_t Cn, const double* __restrict__ A, int64_t lda,
-                                 double* __restrict__ B, int64_t ldb) {
+__device__ __forceinline__ void transpose_body(int64_t bx, int64_t by, int64_t R, int64_t Cn,
+                                               const double* __restrict__ A, int64_t lda,
+                                               double* __restrict__ B, int64_t ldb) {
     __shared__ double t[32][33];
-    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    const int64_t r0 = by * 32, c0 = bx * 32;
     for (int k = threadIdx.y; k < 32; k += 8) {
         const int64_t r = r0 + k, c = c0 + threadIdx.x;
         if (r < R && c < Cn) t[k][threadIdx.x] = A[r * lda + c];
@@ -165,6 +175,34 @@ __global__ void transpose_kernel(int64_t R, int64_t Cn, const double* __restrict
     for (int k = threadIdx.y; k < 32; k += 8) {
         const int64_t c = c0 + k, r = r0 + threadIdx.x;
         if (r < R && c < Cn) B[c * ldb + r] = t[threadIdx.x][k];
+    }
+}
+
+__global__ void transpose_kernel(int64_t R, int64_t Cn, const double* __restrict__ A, int64_t lda,
+                                 double* __restrict__ B, int64_t ldb) {
+    transpose_body(blockIdx.x, blockIdx.y, R, Cn, A, lda, B, ldb);
+}
+
+// the matrix steps of grouped factor tails (MatOp); element-wise steps take
+// one element per thread, in blocks of 256
+template <MatOp OP>
+__global__ __launch_bounds__(256) void mat_grouped(const MatDesc* __restrict__ d, GroupSched g) {
+    int64_t lb;
+    const MatDesc& q = d[group_problem(g, lb)];
+    if constexpr (OP == MatOp::TRANSPOSE) {
+        const int64_t nbx = cdiv(q.cols, 32);
+        transpose_body(lb % nbx, lb / nbx, q.rows, q.cols, q.src, q.lds, q.dst, q.ldd);
+    } else if constexpr (OP == MatOp::TRTRI_LEAF) {
+        trtri_leaf_body(lb, q.rows, q.src, q.lds, q.dst, q.ldd);
+    } else if constexpr (OP == MatOp::ADD_IDENTITY) {
+        const int64_t e = lb * 256 + threadIdx.x;
+        if (e < q.rows) q.dst[e * q.ldd + e] += 1.0;
+    } else {
+        const int64_t e = lb * 256 + threadIdx.x;
+        if (e >= q.rows * q.cols) return;
+        const int64_t i = e / q.cols, j = e % q.cols;
+        if constexpr (OP == MatOp::ZERO) q.dst[i * q.ldd + j] = 0.0;
+        if constexpr (OP == MatOp::GATHER_COLS) q.dst[i * q.ldd + j] = q.src[i * q.lds + q.idx[j]];
     }
 }
 
@@ -290,6 +328,30 @@ void apply_f_gram_inv(hipStream_t s, const elm_factor* f, int64_t m, double* y, 
 
 }  // namespace
 
+int64_t mat_group_blocks(MatOp op, const MatDesc& q) {
+    switch (op) {
+        case MatOp::TRANSPOSE: return cdiv(q.cols, 32) * cdiv(q.rows, 32);
+        case MatOp::TRTRI_LEAF: return cdiv(q.rows, LB);
+        case MatOp::ADD_IDENTITY: return cdiv(q.rows, 256);
+        case MatOp::CHOL_INV_SMALL: return q.rows > 0 ? 1 : 0;
+        default: return cdiv(q.rows * q.cols, 256);
+    }
+}
+
+void launch_mat_grouped(hipStream_t s, MatOp op, const MatDesc* d, const GroupSched& g) {
+    if (g.count <= 0 || g.blocks <= 0) return;
+    const unsigned grid = (unsigned)g.blocks;
+    switch (op) {
+        case MatOp::ZERO: mat_grouped<MatOp::ZERO><<<grid, 256, 0, s>>>(d, g); break;
+        case MatOp::TRANSPOSE: mat_grouped<MatOp::TRANSPOSE><<<grid, dim3(32, 8), 0, s>>>(d, g); break;
+        case MatOp::ADD_IDENTITY: mat_grouped<MatOp::ADD_IDENTITY><<<grid, 256, 0, s>>>(d, g); break;
+        case MatOp::GATHER_COLS: mat_grouped<MatOp::GATHER_COLS><<<grid, 256, 0, s>>>(d, g); break;
+        case MatOp::TRTRI_LEAF: mat_grouped<MatOp::TRTRI_LEAF><<<grid, LB, 0, s>>>(d, g); break;
+        case MatOp::CHOL_INV_SMALL: launch_chol_inv_small_grouped(s, d, g); return;
+    }
+    ELM_LAUNCH_CHECK();
+}
+
 int64_t rowprod_group_blocks(const RowprodDesc& q) { return q.M > 0 ? cdiv(q.M, 4) : 0; }
 
 int64_t copy_rows_group_blocks(const CopyRowsDesc& q) { return cdiv(q.rows * q.cols, 256); }
@@ -364,6 +426,322 @@ void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws, bool wait) {
     ELM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));
     if (hflag) throw Error{ELM_ERR_NOT_PSD, "Gram of G is not positive definite"};
+}
+
+namespace {
+
+// A grouped program: launches recorded with their descriptor arrays and
+// schedules, uploaded in one copy, then issued in order on one stream.
+struct GroupProgram {
+    enum Kind { MAT, GEMM, CALL };
+    struct Launch {
+        Kind kind = MAT;
+        int op = 0;  // MatOp, or the GEMM tile
+        size_t doff = 0, soff = 0;
+        int count = 0;
+        int64_t blocks = 0;
+        std::function<void()> call;
+    };
+    std::vector<char> blob;
+    std::vector<Launch> launches;
+    static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+    template <class D>
+    void add(Kind kind, int op, const std::vector<D>& descs, const std::vector<int64_t>& nblk) {
+        std::vector<int32_t> st, pr;
+        int64_t tot = 0;
+        for (size_t j = 0; j < descs.size(); ++j) {
+            if (nblk[j] <= 0) continue;
+            st.push_back((int32_t)tot);
+            pr.push_back((int32_t)j);
+            tot += nblk[j];
+            if (tot >= INT32_MAX) throw Error{ELM_ERR_UNSUPPORTED, "grouped launch too large"};
+        }
+        if (pr.empty()) return;
+        st.push_back((int32_t)tot);
+        Launch l;
+        l.kind = kind;
+        l.op = op;
+        l.count = (int)pr.size();
+        l.blocks = tot;
+        l.doff = al(blob.size());
+        blob.resize(l.doff + descs.size() * sizeof(D));
+        std::memcpy(blob.data() + l.doff, descs.data(), descs.size() * sizeof(D));
+        l.soff = al(blob.size());
+        blob.resize(l.soff + (st.size() + pr.size()) * sizeof(int32_t));
+        std::memcpy(blob.data() + l.soff, st.data(), st.size() * sizeof(int32_t));
+        std::memcpy(blob.data() + l.soff + st.size() * sizeof(int32_t), pr.data(),
+                    pr.size() * sizeof(int32_t));
+        launches.push_back(std::move(l));
+    }
+    void mat(MatOp op, const std::vector<MatDesc>& d) {
+        std::vector<int64_t> nb(d.size());
+        for (size_t j = 0; j < d.size(); ++j) nb[j] = mat_group_blocks(op, d[j]);
+        add(MAT, (int)op, d, nb);
+    }
+    // products in two launches by the single-product tile rule
+    void gemm(const std::vector<GemmDesc>& d) {
+        for (int ts : {128, 64}) {
+            std::vector<GemmDesc> sel;
+            std::vector<int64_t> nb;
+            for (const GemmDesc& g : d)
+                if (gemm_tile(g) == ts) {
+                    sel.push_back(g);
+                    nb.push_back(gemm_group_blocks(g, ts));
+                }
+            add(GEMM, ts, sel, nb);
+        }
+    }
+    void call(std::function<void()> f) {
+        Launch l;
+        l.kind = CALL;
+        l.call = std::move(f);
+        launches.push_back(std::move(l));
+    }
+    void run(hipStream_t s, Workspace& ws, const char* name) {
+        char* dev = blob.empty() ? nullptr : (char*)ws.get(name, blob.size());
+        if (dev) ELM_HIP_TRY(hipMemcpyAsync(dev, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
+        for (const Launch& l : launches) {
+            if (l.kind == CALL) {
+                l.call();
+                continue;
+            }
+            GroupSched g;
+            g.start = (const int32_t*)(dev + l.soff);
+            g.prob = g.start + l.count + 1;
+            g.count = l.count;
+            g.blocks = l.blocks;
+            if (l.kind == MAT)
+                launch_mat_grouped(s, (MatOp)l.op, (const MatDesc*)(dev + l.doff), g);
+            else
+                launch_gemm_grouped(s, l.op, (const GemmDesc*)(dev + l.doff), g);
+        }
+    }
+};
+
+GemmDesc gemm_desc(int64_t batch, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                   int64_t a_rs, int64_t a_cs, int64_t a_bs, const double* B, int64_t b_rs,
+                   int64_t b_cs, int64_t b_bs, double beta, double* C, int64_t ldc, int64_t c_bs,
+                   bool tri_a, bool tri_b) {
+    GemmDesc g;
+    g.batch = batch;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.alpha = alpha;
+    g.A = A;
+    g.a_rs = a_rs;
+    g.a_cs = a_cs;
+    g.a_bs = a_bs;
+    g.B = B;
+    g.b_rs = b_rs;
+    g.b_cs = b_cs;
+    g.b_bs = b_bs;
+    g.beta = beta;
+    g.C = C;
+    g.ldc = ldc;
+    g.c_bs = c_bs;
+    g.tri_a = tri_a ? 1 : 0;
+    g.tri_b = tri_b ? 1 : 0;
+    return g;
+}
+
+// doubles of trtri_upper's level scratch for order r
+size_t trtri_scratch(int64_t r) {
+    size_t t1_max = 0;
+    for (int64_t sz = LB; sz < r; sz *= 2) {
+        const int64_t full = r / (2 * sz);
+        size_t need = (size_t)full * sz * sz;
+        if (full * 2 * sz + sz < r) need += (size_t)sz * sz;
+        if (need > t1_max) t1_max = need;
+    }
+    return t1_max;
+}
+
+// X = U^-1 for several upper-triangular U: trtri_upper's steps, each level's
+// products of every order in shared launches (a level's ragged pair is
+// independent of its full pairs, so they share the launches too)
+struct TriJob {
+    int64_t r;
+    const double* U;
+    int64_t ldu;
+    double* X;
+    int64_t ldx;
+    double* T1;  // trtri_scratch(r) doubles
+};
+void trtri_grouped(GroupProgram& prog, const std::vector<TriJob>& jobs) {
+    std::vector<MatDesc> z, leaf;
+    int64_t rmax = 0;
+    for (const TriJob& j : jobs) {
+        MatDesc a;
+        a.rows = j.r;
+        a.cols = j.r;
+        a.dst = j.X;
+        a.ldd = j.ldx;
+        z.push_back(a);
+        MatDesc b;
+        b.rows = j.r;
+        b.src = j.U;
+        b.lds = j.ldu;
+        b.dst = j.X;
+        b.ldd = j.ldx;
+        leaf.push_back(b);
+        rmax = std::max(rmax, j.r);
+    }
+    prog.mat(MatOp::ZERO, z);
+    prog.mat(MatOp::TRTRI_LEAF, leaf);
+    for (int64_t sz = LB; sz < rmax; sz *= 2) {
+        std::vector<GemmDesc> pa, pb;
+        for (const TriJob& j : jobs) {
+            const int64_t r = j.r;
+            if (sz >= r) continue;
+            const int64_t full = r / (2 * sz);
+            const int64_t pstride_u = 2 * sz * (j.ldu + 1), pstride_x = 2 * sz * (j.ldx + 1);
+            if (full > 0) {
+                pa.push_back(gemm_desc(full, sz, sz, sz, 1.0, j.U + sz, j.ldu, 1, pstride_u,
+                                       j.X + sz * j.ldx + sz, j.ldx, 1, pstride_x, 0.0, j.T1, sz,
+                                       sz * sz, false, true));
+                pb.push_back(gemm_desc(full, sz, sz, sz, -1.0, j.X, j.ldx, 1, pstride_x, j.T1, sz, 1,
+                                       sz * sz, 0.0, j.X + sz, j.ldx, pstride_x, true, false));
+            }
+            const int64_t a0 = full * 2 * sz, c0 = a0 + sz;
+            if (c0 < r) {
+                const int64_t nc = r - c0;
+                double* T1r = j.T1 + (size_t)full * sz * sz;
+                pa.push_back(gemm_desc(1, sz, nc, nc, 1.0, j.U + a0 * j.ldu + c0, j.ldu, 1, 0,
+                                       j.X + c0 * j.ldx + c0, j.ldx, 1, 0, 0.0, T1r, nc, 0, false, true));
+                pb.push_back(gemm_desc(1, sz, nc, sz, -1.0, j.X + a0 * j.ldx + a0, j.ldx, 1, 0, T1r, nc,
+                                       1, 0, 0.0, j.X + a0 * j.ldx + c0, j.ldx, 0, true, false));
+            }
+        }
+        prog.gemm(pa);
+        prog.gemm(pb);
+    }
+}
+
+MatDesc transpose_desc(int64_t R, int64_t Cn, const double* A, int64_t lda, double* B) {
+    MatDesc d;
+    d.rows = R;
+    d.cols = Cn;
+    d.src = A;
+    d.lds = lda;
+    d.dst = B;
+    d.ldd = R;
+    return d;
+}
+
+}  // namespace
+
+std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm_factor*>& fs,
+                                            const std::vector<const double*>& Rorig, Workspace& ws) {
+    const size_t P = fs.size();
+    std::vector<int> bad(P, 0);
+    if (P == 0) return bad;
+    auto al = GroupProgram::al;
+    // scratch: the level products of both inverses, the Gram of G, and a flag each
+    std::vector<size_t> o_t1(P), o_s(P), o_t1s(P);
+    size_t off = 0;
+    for (size_t p = 0; p < P; ++p) {
+        const elm_factor* f = fs[p];
+        const int64_t r = f->r, c = f->n - r, q = std::min(r, c);
+        if (r < 1) throw Error{ELM_ERR_INVALID_ARG, "grouped factor tail needs rank >= 1"};
+        o_t1[p] = off;
+        off += al(std::max<size_t>(trtri_scratch(r), 1) * sizeof(double));
+        o_s[p] = off;
+        off += al(std::max<size_t>((size_t)(q * q), 1) * sizeof(double));
+        o_t1s[p] = off;
+        off += al(std::max<size_t>(q > 128 ? trtri_scratch(q) : 0, 1) * sizeof(double));
+    }
+    const size_t o_flags = off;
+    off += al(P * sizeof(int));
+    char* sc = (char*)ws.get("tl_scratch", off);
+    int* flags = (int*)(sc + o_flags);
+
+    GroupProgram prog;
+    std::vector<MatDesc> gat, tr_r, tr_k, addi, small, tr_s;
+    std::vector<GemmDesc> kk, ss;
+    std::vector<TriJob> tri_r, tri_s;
+    for (size_t p = 0; p < P; ++p) {
+        elm_factor* f = fs[p];
+        const int64_t r = f->r, n = f->n, c = n - r;
+        if (Rorig[p]) {  // R = the first r rows of Rorig, columns in pivot order
+            MatDesc d;
+            d.rows = r;
+            d.cols = n;
+            d.src = Rorig[p];
+            d.lds = n;
+            d.idx = f->piv;
+            d.dst = f->R;
+            d.ldd = n;
+            gat.push_back(d);
+        }
+        f->Rinv = (double*)factor_alloc(f, "Rinv", (size_t)r * r * sizeof(double));
+        f->RinvT = (double*)factor_alloc(f, "RinvT", (size_t)r * r * sizeof(double));
+        tri_r.push_back(TriJob{r, f->R, n, f->Rinv, r, (double*)(sc + o_t1[p])});
+        tr_r.push_back(transpose_desc(r, r, f->Rinv, r, f->RinvT));
+        if (c > 0) {
+            f->K = (double*)factor_alloc(f, "K", (size_t)r * c * sizeof(double));
+            f->KT = (double*)factor_alloc(f, "KT", (size_t)r * c * sizeof(double));
+            // K = R11^-1 R12 (R11^-1 upper triangular)
+            kk.push_back(gemm_desc(1, r, c, r, 1.0, f->Rinv, r, 1, 0, f->R + r, n, 1, 0, 0.0, f->K, c, 0,
+                                   true, false));
+            tr_k.push_back(transpose_desc(r, c, f->K, c, f->KT));
+        }
+        const int64_t q = r < c ? r : c;
+        f->q = q;
+        f->woodbury = (c < r);
+        if (q == 0) continue;
+        double* S = (double*)(sc + o_s[p]);
+        if (f->woodbury)  // K^T K
+            ss.push_back(gemm_desc(1, c, c, r, 1.0, f->K, 1, c, 0, f->K, c, 1, 0, 0.0, S, c, 0, false, false));
+        else  // K K^T
+            ss.push_back(gemm_desc(1, r, r, c, 1.0, f->K, c, 1, 0, f->K, 1, c, 0, 0.0, S, r, 0, false, false));
+        MatDesc a;
+        a.rows = q;
+        a.dst = S;
+        a.ldd = q;
+        addi.push_back(a);
+        f->Usinv = (double*)factor_alloc(f, "Usinv", (size_t)q * q * sizeof(double));
+        f->UsinvT = (double*)factor_alloc(f, "UsinvT", (size_t)q * q * sizeof(double));
+        if (q <= 128) {  // factor and inverse in one workgroup
+            MatDesc d;
+            d.rows = q;
+            d.dst = S;
+            d.ldd = q;
+            d.aux = f->Usinv;
+            d.lda = q;
+            d.flag = flags + p;
+            small.push_back(d);
+        } else {
+            tri_s.push_back(TriJob{q, S, q, f->Usinv, q, (double*)(sc + o_t1s[p])});
+        }
+        tr_s.push_back(transpose_desc(q, q, f->Usinv, q, f->UsinvT));
+    }
+    prog.mat(MatOp::GATHER_COLS, gat);
+    trtri_grouped(prog, tri_r);
+    prog.mat(MatOp::TRANSPOSE, tr_r);
+    prog.gemm(kk);
+    prog.mat(MatOp::TRANSPOSE, tr_k);
+    prog.gemm(ss);
+    prog.mat(MatOp::ADD_IDENTITY, addi);
+    prog.mat(MatOp::CHOL_INV_SMALL, small);
+    // larger Grams of G: the blocked factorisation one at a time, then the
+    // inverses of all of them together
+    for (size_t p = 0; p < P; ++p) {
+        const int64_t q = fs[p]->q;
+        if (q <= 128) continue;
+        double* S = (double*)(sc + o_s[p]);
+        int* flag = flags + p;
+        prog.call([=, &ws] { cholesky_blocked(s, q, S, q, 0.0, flag, ws); });
+    }
+    trtri_grouped(prog, tri_s);
+    prog.mat(MatOp::TRANSPOSE, tr_s);
+    ELM_HIP_TRY(hipMemsetAsync(flags, 0, P * sizeof(int), s));
+    prog.run(s, ws, "tl_program");
+    std::vector<int> hf(P, 0);
+    ELM_HIP_TRY(hipMemcpyAsync(hf.data(), flags, P * sizeof(int), hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipStreamSynchronize(s));
+    for (size_t p = 0; p < P; ++p) bad[p] = hf[p] ? 1 : 0;
+    return bad;
 }
 
 // out (L x m) = H^+ (.) through the factor.
