@@ -200,11 +200,13 @@ elm_status elm_destroy(elm_handle* h) {
     for (elm_handle* w : h->workers) elm_destroy(w);
     h->workers.clear();
     if (h->side) (void)hipStreamSynchronize(h->side);
+    if (h->batch_stream) (void)hipStreamSynchronize(h->batch_stream);
     h->prof.release();
     h->ws.release();
     for (auto& e : h->side_ev)
         if (e) (void)hipEventDestroy(e);
     if (h->side) (void)hipStreamDestroy(h->side);
+    if (h->batch_stream) (void)hipStreamDestroy(h->batch_stream);
     if (h->owns_stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return ELM_OK;
@@ -1104,6 +1106,11 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
         ELM_HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         ELM_HIP_TRY(hipEventRecord(ev, h->stream));
         for (int w = 0; w < nw; ++w) ELM_HIP_TRY(hipStreamWaitEvent(h->workers[w]->stream, ev, 0));
+        if (!h->batch_stream)  // default priority, non-blocking
+            ELM_HIP_TRY(hipStreamCreateWithFlags(&h->batch_stream, hipStreamNonBlocking));
+        ELM_HIP_TRY(hipStreamWaitEvent(h->batch_stream, ev, 0));
+        // the shared launches of the batch (phases 1 to 3) run on this stream
+        hipStream_t ps = h->batch_stream;
         // workers take problems longest-first by the Gram's cost N n min(N, L)
         auto cost = [&](int32_t e) {
             const double n = (double)std::min(probs[e].N, probs[e].L);
@@ -1139,8 +1146,12 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             it.fuse_z = p.m <= elm::HIDDEN_Z_MAX_M;
             it.kc = 0;
             it.ok = true;
-            const size_t need = 4 * al((size_t)it.n * it.n * sizeof(double)) +
-                                (size_t)256 * it.n * sizeof(double);
+            size_t need = 4 * al((size_t)it.n * it.n * sizeof(double)) +
+                          (size_t)256 * it.n * sizeof(double);
+            if (!it.transposed && it.fuse_z)  // the shared phase-1 buffers
+                need += al((size_t)p.L * p.N * elm::dtype_size(it.gdt)) +
+                        al((size_t)elm::hidden_row_tiles(p.N) * p.L * p.m * sizeof(double)) +
+                        al((size_t)p.L * p.L * sizeof(double));
             if (!groups.back().empty() && gbytes + need > elm::BATCH_GROUP_BYTES) {
                 groups.emplace_back();
                 gbytes = 0;
@@ -1205,8 +1216,109 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             }
         };
 
+        // Phase 1 of problems g1 in shared launches on stream s: the hidden
+        // layers (H, the low-precision copy, the row-tile partials of
+        // Z = H^T T), Z and ||Z||^2, the Grams and their largest diagonal
+        // entries; the kernels, tiles and splits of the single-problem launches.
+        // The programs' host blobs must live until their uploads are done (the
+        // caller keeps them to its next synchronisation).
+        auto run_phase1_grouped = [&](elm_handle* hh, hipStream_t s, const std::vector<int32_t>& g1,
+                                      const std::vector<int32_t>& slot, double* dmaxs,
+                                      std::vector<elm::GroupProgram>& progs) {
+            const size_t P = g1.size();
+            std::vector<elm::HiddenDesc> hd(P);
+            std::vector<elm::PsumDesc> sd(P);
+            std::vector<elm::GramDesc> gd(P);
+            std::vector<size_t> o_lp(P), o_zp(P), o_p2(P), o_sq(P), o_gp(P);
+            std::vector<int64_t> kc(P, 0);
+            size_t off = 0;
+            for (size_t j = 0; j < P; ++j) {
+                const elm_problem& p = probs[g1[j]];
+                const Item& it = items[g1[j]];
+                const int64_t nrt = elm::hidden_row_tiles(p.N);
+                o_lp[j] = off;
+                if (it.gdt != ELM_F64) off += al((size_t)p.L * p.N * elm::dtype_size(it.gdt));
+                o_zp[j] = off;
+                off += al((size_t)nrt * p.L * p.m * sizeof(double));
+                o_p2[j] = off;
+                off += al(std::max<size_t>(elm::psum_part2_doubles(p.L, p.m, nrt), 1) * sizeof(double));
+                o_sq[j] = off;
+                off += al(elm::refine_sq_doubles(p.L, p.m) * sizeof(double));
+                o_gp[j] = off;
+                off += al(elm::gram_group_plan(s, it.gdt, p.N, p.L, gd[j], hh->ws, &kc[j]));
+            }
+            char* arena = (char*)hh->ws.get("bt_phase1", off);
+            for (size_t j = 0; j < P; ++j) {
+                const int32_t e = g1[j];
+                const elm_problem& p = probs[e];
+                Item& it = items[e];
+                void* lp = it.gdt != ELM_F64 ? (void*)(arena + o_lp[j]) : nullptr;
+                double* Zp = (double*)(arena + o_zp[j]);
+                elm::HiddenDesc& h1 = hd[j];
+                h1.N = p.N;
+                h1.d = p.d;
+                h1.L = p.L;
+                h1.X = (const double*)p.X;
+                h1.ldx = p.ldx;
+                h1.W = (const double*)p.W;
+                h1.ldw = p.ldw;
+                h1.b = (const double*)p.b;
+                h1.H = p.H64;
+                h1.ldh = p.ldh64;
+                h1.Hlp = lp;
+                h1.ldlp = p.N;
+                h1.lp_dt = it.gdt;
+                h1.T = p.T;
+                h1.ldt = p.ldt;
+                h1.m = (int)p.m;
+                h1.Zp = Zp;
+                elm::PsumDesc& s1 = sd[j];
+                s1.L = p.L;
+                s1.m = p.m;
+                s1.nchunk = elm::hidden_row_tiles(p.N);
+                s1.part = Zp;
+                s1.part2 = (double*)(arena + o_p2[j]);
+                s1.G = it.Z;
+                s1.sq = (double*)(arena + o_sq[j]);
+                s1.nrm2 = it.nrm;
+                elm::GramDesc& g = gd[j];
+                g.A = it.gdt == ELM_F64 ? (const void*)p.H64 : (const void*)lp;
+                g.ld = it.gdt == ELM_F64 ? p.ldh64 : p.N;
+                g.part = arena + o_gp[j];
+                g.M = it.M;
+                g.ldm = it.n;
+                g.dmax = dmaxs + slot[e];
+                it.kc = it.gdt != ELM_F64 ? kc[j] : 0;
+            }
+            progs.assign(3, elm::GroupProgram());
+            std::vector<int64_t> nb(P);
+            for (size_t j = 0; j < P; ++j) nb[j] = elm::hidden_group_blocks(hd[j]);
+            progs[0].add(hd, nb, [](hipStream_t st, const void* d, const elm::GroupSched& g) {
+                elm::launch_hidden_grouped(st, (const elm::HiddenDesc*)d, g);
+            });
+            for (int stage = 0; stage < 3; ++stage) {
+                for (size_t j = 0; j < P; ++j) nb[j] = elm::partial_sum_group_blocks(stage, sd[j]);
+                progs[1].add(sd, nb, [stage](hipStream_t st, const void* d, const elm::GroupSched& g) {
+                    elm::launch_partial_sum_grouped(st, stage, (const elm::PsumDesc*)d, g);
+                });
+            }
+            const int kind = gd[0].kind;  // one Gram type per batch
+            for (int stage = 0; stage < 3; ++stage) {
+                for (size_t j = 0; j < P; ++j) nb[j] = elm::gram_group_blocks(stage, gd[j]);
+                progs[2].add(gd, nb, [stage, kind](hipStream_t st, const void* d, const elm::GroupSched& g) {
+                    elm::launch_gram_grouped(st, stage, kind, (const elm::GramDesc*)d, g);
+                });
+            }
+            const char* names[3] = {"bt_p1_hidden", "bt_p1_rhs", "bt_p1_gram"};
+            const int stages[3] = {ELM_STAGE_HIDDEN, ELM_STAGE_RHS, ELM_STAGE_GRAM};
+            for (int k = 0; k < 3; ++k) {
+                elm::StageScope sc(&hh->prof, stages[k], s);
+                progs[k].run(s, hh->ws, names[k]);
+            }
+        };
+
         for (const std::vector<int32_t>& grp : groups) {
-            // phase 1 (workers): H, Z = H^T T and the Gram of every problem
+            // phase 1: H, Z = H^T T and the Gram of every problem
             size_t mb = 0, zb = 0;
             for (int32_t e : grp) {
                 mb += al((size_t)items[e].n * items[e].n * sizeof(double));
@@ -1229,9 +1341,30 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             }
             std::vector<int32_t> slot(count, -1);
             for (size_t i = 0; i < grp.size(); ++i) slot[grp[i]] = (int32_t)i;
+            // phase 1, shared launches (batch stream): the problems with
+            // N >= L and H^T T from the hidden layer
+            std::vector<elm::GroupProgram> p1progs;  // until the synchronisation of phase 2
+            {
+                std::vector<int32_t> g1;
+                for (int32_t e : grp)
+                    if (items[e].ok && !items[e].transposed && items[e].fuse_z) g1.push_back(e);
+                if (!g1.empty()) {
+                    try {
+                        run_phase1_grouped(h, ps, g1, slot, dmaxs, p1progs);
+                    } catch (const elm::Error& err) {
+                        for (int32_t e : g1) {
+                            st_all[e] = err.st;
+                            msg_all[e] = err.msg;
+                            items[e].ok = false;
+                        }
+                    }
+                }
+            }
+            // phase 1 (workers): the others
             run_workers(grp, [&](elm_handle* wh, int32_t e) {
                 const elm_problem& p = probs[e];
                 Item& it = items[e];
+                if (!it.transposed && it.fuse_z) return;  // shared launches
                 hipStream_t ws = wh->stream;
                 void* lp = nullptr;
                 if (it.gdt != ELM_F64)
@@ -1260,9 +1393,8 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 }
                 elm::launch_diag_max(ws, it.n, it.M, it.n, dmaxs + slot[e]);
             });
-            // phase 2 runs on the first worker's stream (a created stream, so
-            // its fixed launch sequences can be replayed as HIP graphs)
-            hipStream_t ps = h->workers[0]->stream;
+            // phase 2 runs on the batch stream (a created stream, so its fixed
+            // launch sequences can be replayed as HIP graphs)
             wait_workers(ps);
 
             // phase 2: all rank decisions in shared launches

@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <string>
 #include <vector>
+#include <functional>
+#include <cstring>
 
 #include "../../include/elm.h"
 
@@ -172,6 +174,8 @@ struct elm_handle {
     // second stream and its two ordering events, for work that overlaps the
     // handle's stream inside one call (created on first use)
     hipStream_t side = nullptr;
+    // the stream of a batch's shared launches (created on first use)
+    hipStream_t batch_stream = nullptr;
     hipEvent_t side_ev[2] = {nullptr, nullptr};
     // tuning options (elm_set_option)
     int64_t full_rank_min_order = elm::FULL_RANK_MIN_ORDER;
@@ -431,6 +435,77 @@ __device__ inline int group_problem(const GroupSched& g, int64_t& local) {
     return g.prob[lo];
 }
 
+// A sequence of grouped launches: add() copies one launch's descriptors and
+// schedule (problems with no blocks left out) into a host blob, call() inserts
+// host-issued work; run() uploads the blob in one copy and issues everything
+// in order on one stream (the blob stays valid until the workspace buffer
+// `name` is requested again).
+struct GroupProgram {
+    typedef std::function<void(hipStream_t s, const void* desc, const GroupSched& g)> LaunchFn;
+    struct Launch {
+        size_t doff = 0, soff = 0;
+        int count = 0;
+        int64_t blocks = 0;
+        LaunchFn fn;
+        std::function<void()> call;
+    };
+    std::vector<char> blob;
+    std::vector<Launch> launches;
+    static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+    template <class D>
+    void add(const std::vector<D>& descs, const std::vector<int64_t>& nblk, LaunchFn fn) {
+        std::vector<int32_t> st, pr;
+        int64_t tot = 0;
+        for (size_t j = 0; j < descs.size(); ++j) {
+            if (nblk[j] <= 0) continue;
+            st.push_back((int32_t)tot);
+            pr.push_back((int32_t)j);
+            tot += nblk[j];
+            if (tot >= INT32_MAX) throw Error{ELM_ERR_UNSUPPORTED, "grouped launch too large"};
+        }
+        if (pr.empty()) return;
+        st.push_back((int32_t)tot);
+        Launch l;
+        l.count = (int)pr.size();
+        l.blocks = tot;
+        l.fn = std::move(fn);
+        l.doff = al(blob.size());
+        blob.resize(l.doff + descs.size() * sizeof(D));
+        std::memcpy(blob.data() + l.doff, descs.data(), descs.size() * sizeof(D));
+        l.soff = al(blob.size());
+        blob.resize(l.soff + (st.size() + pr.size()) * sizeof(int32_t));
+        std::memcpy(blob.data() + l.soff, st.data(), st.size() * sizeof(int32_t));
+        std::memcpy(blob.data() + l.soff + st.size() * sizeof(int32_t), pr.data(),
+                    pr.size() * sizeof(int32_t));
+        launches.push_back(std::move(l));
+    }
+    void call(std::function<void()> f) {
+        Launch l;
+        l.call = std::move(f);
+        launches.push_back(std::move(l));
+    }
+    void run(hipStream_t s, Workspace& ws, const char* name) {
+        char* dev = blob.empty() ? nullptr : (char*)ws.get(name, blob.size());
+        if (dev) {
+            const hipError_t e = hipMemcpyAsync(dev, blob.data(), blob.size(), hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) throw Error{ELM_ERR_HIP, std::string("grouped program upload: ") +
+                                                              hipGetErrorString(e)};
+        }
+        for (const Launch& l : launches) {
+            if (l.call) {
+                l.call();
+                continue;
+            }
+            GroupSched g;
+            g.start = (const int32_t*)(dev + l.soff);
+            g.prob = g.start + l.count + 1;
+            g.count = l.count;
+            g.blocks = l.blocks;
+            l.fn(s, dev + l.doff, g);
+        }
+    }
+};
+
 // gemm.hip, grouped: one (batched) product of gemm_f64_batched
 struct GemmDesc {
     int64_t M = 0, N = 0, K = 0, batch = 0;
@@ -473,6 +548,66 @@ enum class MatOp {
 int64_t mat_group_blocks(MatOp op, const MatDesc& q);
 void launch_mat_grouped(hipStream_t s, MatOp op, const MatDesc* d, const GroupSched& g);
 void launch_chol_inv_small_grouped(hipStream_t s, const MatDesc* d, const GroupSched& g);
+
+// hidden.hip, grouped: one problem's hidden layer (FP64 inputs), as launch_hidden
+struct HiddenDesc {
+    int64_t N = 0, d = 0, L = 0;
+    const double* X = nullptr;
+    int64_t ldx = 0;
+    const double* W = nullptr;
+    int64_t ldw = 0;
+    const double* b = nullptr;
+    double* H = nullptr;
+    int64_t ldh = 0;
+    void* Hlp = nullptr;
+    int64_t ldlp = 0;
+    elm_dtype lp_dt = ELM_F64;
+    const double* T = nullptr;
+    int64_t ldt = 0;
+    int m = 0;
+    double* Zp = nullptr;
+};
+int64_t hidden_group_blocks(const HiddenDesc& q);
+void launch_hidden_grouped(hipStream_t s, const HiddenDesc* d, const GroupSched& g);
+
+// gram.hip, grouped: one problem's column Gram M (L x L) as the single launch
+// computes it (16-bit or FP32 node-major H, or FP64 sample-major H)
+enum GramKind { GRAM_BF16 = 0, GRAM_F16 = 1, GRAM_F32 = 2, GRAM_F64 = 3 };
+struct GramDesc {
+    int kind = 0;
+    int64_t n = 0, K = 0, kc_len = 0, ntile = 0, nsplit = 0, nblocks = 0;
+    const void* A = nullptr;  // H: node-major (ld N) or, for FP64, sample-major
+    int64_t ld = 0;
+    void* part = nullptr;     // the partial tiles (gram_group_plan's bytes)
+    const int4* work = nullptr;
+    double* M = nullptr;
+    int64_t ldm = 0;
+    double* dmax = nullptr;   // stage 2: the largest diagonal entry (NaN if any is NaN or Inf)
+};
+// Plans q for the Gram the single-problem launch of this dtype takes: kind,
+// tiles, splits, chunk length and (16-bit) the work table, uploaded once per
+// workspace.  Returns the bytes of its partials; *kc_out: the products per
+// FP32 partial sum (the single launch's return value).
+size_t gram_group_plan(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, GramDesc& q,
+                       Workspace& ws, int64_t* kc_out);
+// stage 0: the partial products, 1: their FP64 sum into M, 2: the diagonal maximum
+int64_t gram_group_blocks(int stage, const GramDesc& q);
+void launch_gram_grouped(hipStream_t s, int stage, int kind, const GramDesc* d, const GroupSched& g);
+
+// refine.hip, grouped: launch_partial_sum of one problem (Z = sum of its
+// row-tile partials and ||Z||_F^2)
+struct PsumDesc {
+    int64_t L = 0, m = 0, nchunk = 0;
+    const double* part = nullptr;  // nchunk x (L x m)
+    double* part2 = nullptr;       // psum_part2_doubles(L, m, nchunk) (when nchunk > 128)
+    double* G = nullptr;           // L x m, ld m
+    double* sq = nullptr;          // refine_sq_doubles(L, m)
+    double* nrm2 = nullptr;
+};
+size_t psum_part2_doubles(int64_t L, int64_t m, int64_t nchunk);
+// group sums (problems with nchunk > 128), the column sums and squares, the total
+void launch_partial_sum_grouped(hipStream_t s, int stage, const PsumDesc* d, const GroupSched& g);
+int64_t partial_sum_group_blocks(int stage, const PsumDesc& q);
 
 // refine.hip, grouped: one problem's refinement buffers (m <= 16)
 struct RefineDesc {

@@ -41,17 +41,17 @@ __device__ inline void tile_coords(int64_t t, int& bi, int& bj) {
 }
 
 template <typename T, bool KCONTIG>
-__global__ __launch_bounds__(NT) void gram16_kernel(int64_t n, int64_t K, int64_t kc_len,
-                                                    const T* __restrict__ A, int64_t ld,
-                                                    T* __restrict__ part, int64_t ntile) {
+__device__ __forceinline__ void gram16_body(int64_t bx, int64_t by, int64_t n, int64_t K,
+                                            int64_t kc_len, const T* __restrict__ A, int64_t ld,
+                                            T* __restrict__ part, int64_t ntile) {
     constexpr int BK = 16;
     __shared__ T As[BK][TILE + 1];
     __shared__ T Bs[BK][TILE + 1];
 
     int bi, bj;
-    tile_coords(blockIdx.x, bi, bj);
+    tile_coords(bx, bi, bj);
     const int64_t r0 = (int64_t)bi * TILE, c0 = (int64_t)bj * TILE;
-    const int64_t kbeg = (int64_t)blockIdx.y * kc_len;
+    const int64_t kbeg = by * kc_len;
     const int64_t kend = min(K, kbeg + kc_len);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(NT) void gram16_kernel(int64_t n, int64_t K, int64_
         __syncthreads();
     }
 
-    T* out = part + ((int64_t)blockIdx.y * ntile + blockIdx.x) * (TILE * TILE);
+    T* out = part + (by * ntile + bx) * (TILE * TILE);
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -109,6 +109,13 @@ __global__ __launch_bounds__(NT) void gram16_kernel(int64_t n, int64_t K, int64_
                 const int col = wn * 64 + y * 16 + (lane & 15);
                 out[row * TILE + col] = acc[x][y][v];
             }
+}
+
+template <typename T, bool KCONTIG>
+__global__ __launch_bounds__(NT) void gram16_kernel(int64_t n, int64_t K, int64_t kc_len,
+                                                    const T* __restrict__ A, int64_t ld,
+                                                    T* __restrict__ part, int64_t ntile) {
+    gram16_body<T, KCONTIG>(blockIdx.x, blockIdx.y, n, K, kc_len, A, ld, part, ntile);
 }
 
 template <typename HT> struct Mfma32;
@@ -131,11 +138,11 @@ template <> struct Mfma32<_Float16> {
 
 // M[i][j] = M[j][i] = sum over chunks (in chunk order, FP64) of the partial tiles
 template <typename PT>
-__global__ __launch_bounds__(NT) void gram_reduce_kernel(int64_t n, const PT* __restrict__ part,
-                                                         int64_t ntile, int nchunk,
-                                                         double* __restrict__ M, int64_t ldm) {
+__device__ __forceinline__ void gram_reduce_body(int64_t bx, int64_t n, const PT* __restrict__ part,
+                                                 int64_t ntile, int nchunk, double* __restrict__ M,
+                                                 int64_t ldm) {
     int bi, bj;
-    tile_coords(blockIdx.x, bi, bj);
+    tile_coords(bx, bi, bj);
     const int64_t r0 = (int64_t)bi * TILE, c0 = (int64_t)bj * TILE;
     for (int e = threadIdx.x; e < TILE * TILE; e += NT) {
         const int row = e / TILE, col = e % TILE;
@@ -143,10 +150,17 @@ __global__ __launch_bounds__(NT) void gram_reduce_kernel(int64_t n, const PT* __
         if (gi >= n || gj >= n || gi > gj) continue;
         double s = 0.0;
         for (int c = 0; c < nchunk; ++c)
-            s += (double)part[((int64_t)c * ntile + blockIdx.x) * (TILE * TILE) + e];
+            s += (double)part[((int64_t)c * ntile + bx) * (TILE * TILE) + e];
         M[gi * ldm + gj] = s;
         M[gj * ldm + gi] = s;
     }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(NT) void gram_reduce_kernel(int64_t n, const PT* __restrict__ part,
+                                                         int64_t ntile, int nchunk,
+                                                         double* __restrict__ M, int64_t ldm) {
+    gram_reduce_body<PT>(blockIdx.x, n, part, ntile, nchunk, M, ldm);
 }
 
 // Split the reduction length K into chunks so the grid has enough blocks.
@@ -215,13 +229,11 @@ constexpr int G_STB = 2 * G_OPB;               // bytes per stage (32 KB)
 typedef __attribute__((address_space(3))) void lds_void;
 
 template <typename HT, int GNS>  // GNS: LDS stages, GNS - 2 of them in flight
-__global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, int64_t kc_len,
-                                                         const HT* __restrict__ A, int64_t ld,
-                                                         float* __restrict__ part,
-                                                         const int4* __restrict__ work) {
+__device__ __forceinline__ void gram_lp256_body(const int4 wk, int64_t n, int64_t K, int64_t kc_len,
+                                                const HT* __restrict__ A, int64_t ld,
+                                                float* __restrict__ part) {
     __shared__ __attribute__((aligned(1024))) unsigned char smem[GNS * G_STB];
     typedef typename Mfma32<HT>::vec_t vec_t;
-    const int4 wk = work[blockIdx.x];
     if (wk.x < 0) return;
     const int64_t r0 = (int64_t)wk.y * GT, c0 = (int64_t)wk.z * GT;
     const int64_t kbeg = (int64_t)wk.x * kc_len;
@@ -393,26 +405,41 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
             }
 }
 
+template <typename HT, int GNS>
+__global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, int64_t kc_len,
+                                                         const HT* __restrict__ A, int64_t ld,
+                                                         float* __restrict__ part,
+                                                         const int4* __restrict__ work) {
+    gram_lp256_body<HT, GNS>(work[blockIdx.x], n, K, kc_len, A, ld, part);
+}
+
 // M[i][j] = M[j][i] = sum over splits (in order, FP64) of the 256-tile partials;
 // partial slot of (split s, tile t) is s * ntile + t.
-__global__ __launch_bounds__(NT) void gram_reduce256_kernel(int64_t n, const float* __restrict__ part,
-                                                            int64_t ntile, int nsplit,
-                                                            double* __restrict__ M, int64_t ldm) {
+__device__ __forceinline__ void gram_reduce256_body(int64_t bx, int64_t by, int64_t n,
+                                                    const float* __restrict__ part, int64_t ntile,
+                                                    int nsplit, double* __restrict__ M,
+                                                    int64_t ldm) {
     int bi, bj;
-    tile_coords(blockIdx.x, bi, bj);
+    tile_coords(bx, bi, bj);
     const int64_t r0 = (int64_t)bi * GT, c0 = (int64_t)bj * GT;
-    const int64_t e = (int64_t)blockIdx.y * NT + threadIdx.x;  // element within the tile
+    const int64_t e = by * NT + threadIdx.x;  // element within the tile
     const int row = (int)(e / GT), col = (int)(e % GT);
     const int64_t gi = r0 + row, gj = c0 + col;
     if (gi >= n || gj >= n || gi > gj) return;
     double s = 0.0;
-    for (int c = 0; c < nsplit; ++c) s += (double)part[((int64_t)c * ntile + blockIdx.x) * (GT * GT) + e];
+    for (int c = 0; c < nsplit; ++c) s += (double)part[((int64_t)c * ntile + bx) * (GT * GT) + e];
     M[gi * ldm + gj] = s;
     M[gj * ldm + gi] = s;
 }
 
-__global__ __launch_bounds__(NT) void diag_max_kernel(int64_t n, const double* __restrict__ M,
-                                                      int64_t ldm, double* __restrict__ out) {
+__global__ __launch_bounds__(NT) void gram_reduce256_kernel(int64_t n, const float* __restrict__ part,
+                                                            int64_t ntile, int nsplit,
+                                                            double* __restrict__ M, int64_t ldm) {
+    gram_reduce256_body(blockIdx.x, blockIdx.y, n, part, ntile, nsplit, M, ldm);
+}
+
+__device__ __forceinline__ void diag_max_body(int64_t n, const double* __restrict__ M, int64_t ldm,
+                                              double* __restrict__ out) {
     __shared__ double red[NT];
     double m = 0.0;
     bool nan = false;
@@ -431,6 +458,47 @@ __global__ __launch_bounds__(NT) void diag_max_kernel(int64_t n, const double* _
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ __launch_bounds__(NT) void diag_max_kernel(int64_t n, const double* __restrict__ M,
+                                                      int64_t ldm, double* __restrict__ out) {
+    diag_max_body(n, M, ldm, out);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped Grams of a batch (GramDesc): the blocks of a problem run over its
+// work items exactly as its single launches would.
+// ---------------------------------------------------------------------------
+template <typename HT, int GNS>
+__global__ __launch_bounds__(256) void gram_lp256_grouped(const GramDesc* __restrict__ d,
+                                                          GroupSched g) {
+    int64_t lb;
+    const GramDesc& q = d[group_problem(g, lb)];
+    gram_lp256_body<HT, GNS>(q.work[lb], q.n, q.K, q.kc_len, (const HT*)q.A, q.ld, (float*)q.part);
+}
+
+template <typename T, bool KCONTIG>
+__global__ __launch_bounds__(NT) void gram16_grouped(const GramDesc* __restrict__ d, GroupSched g) {
+    int64_t lb;
+    const GramDesc& q = d[group_problem(g, lb)];
+    gram16_body<T, KCONTIG>(lb % q.ntile, lb / q.ntile, q.n, q.K, q.kc_len, (const T*)q.A, q.ld,
+                            (T*)q.part, q.ntile);
+}
+
+template <int KIND>  // 0: 256-tile FP32 partials, 1: FP32 128-tile, 2: FP64 128-tile, 3: diagonal max
+__global__ __launch_bounds__(NT) void gram_finish_grouped(const GramDesc* __restrict__ d,
+                                                          GroupSched g) {
+    int64_t lb;
+    const GramDesc& q = d[group_problem(g, lb)];
+    if constexpr (KIND == 0)
+        gram_reduce256_body(lb % q.ntile, lb / q.ntile, q.n, (const float*)q.part, q.ntile, q.nsplit,
+                            q.M, q.ldm);
+    else if constexpr (KIND == 1)
+        gram_reduce_body<float>(lb, q.n, (const float*)q.part, q.ntile, q.nsplit, q.M, q.ldm);
+    else if constexpr (KIND == 2)
+        gram_reduce_body<double>(lb, q.n, (const double*)q.part, q.ntile, q.nsplit, q.M, q.ldm);
+    else
+        diag_max_body(q.n, q.M, q.ldm, q.dmax);
 }
 
 }  // namespace
@@ -534,18 +602,12 @@ int gram_default_splits(int64_t N, int64_t L) {
     return pick_splits(nt * (nt + 1) / 2, N);
 }
 
-int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
-                             int64_t ldn, double* M, int64_t ldm, Workspace& ws, int force_splits) {
-    if (dt == ELM_F32) return run_gram16<float, true>(s, L, N, (const float*)Hn, ldn, M, ldm, ws);
+// the work table of a 16-bit Gram of L nodes in nsplit_eff splits: it depends
+// only on (L, splits), so it is built and uploaded once per workspace
+static const int4* gram_table(hipStream_t s, int64_t L, int nsplit_eff, Workspace& ws,
+                              size_t* nblocks_out) {
     const int64_t nt = cdiv(L, GT);
     const int64_t ntile = nt * (nt + 1) / 2;
-    int nsplit = force_splits;
-    if (nsplit <= 0) nsplit = gram_splits_override();
-    if (nsplit <= 0) nsplit = ws.find_splits(L, N, (int)dt);
-    if (nsplit <= 0) nsplit = pick_splits(ntile, N);
-    const int64_t kc_len = cdiv(cdiv(N, nsplit), GBK) * GBK;
-    const int nsplit_eff = (int)cdiv(N, kc_len);
-    // the work table depends only on (L, splits): built and uploaded once per workspace
     const std::string key = "gram_tab_" + std::to_string(L) + "_" + std::to_string(nsplit_eff);
     const size_t nwork = (size_t)ntile * nsplit_eff;
     const size_t nblocks = cdiv((int64_t)nwork, 256) * 256;
@@ -557,6 +619,96 @@ int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, 
         ELM_HIP_TRY(hipStreamSynchronize(s));  // tab is a host temporary
         ws.tables.push_back(key);
     }
+    *nblocks_out = nblocks;
+    return dtab;
+}
+
+size_t gram_group_plan(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, GramDesc& q,
+                       Workspace& ws, int64_t* kc_out) {
+    if (dt == ELM_BF16 || dt == ELM_F16) {  // launch_gram_lp_nodes' choices
+        const int64_t nt = cdiv(L, GT);
+        const int64_t ntile = nt * (nt + 1) / 2;
+        int nsplit = gram_splits_override();
+        if (nsplit <= 0) nsplit = ws.find_splits(L, N, (int)dt);
+        if (nsplit <= 0) nsplit = pick_splits(ntile, N);
+        const int64_t kc_len = cdiv(cdiv(N, nsplit), GBK) * GBK;
+        const int nsplit_eff = (int)cdiv(N, kc_len);
+        size_t nblocks = 0;
+        q.work = gram_table(s, L, nsplit_eff, ws, &nblocks);
+        q.kind = dt == ELM_BF16 ? GRAM_BF16 : GRAM_F16;
+        q.n = L;
+        q.K = N;
+        q.kc_len = kc_len;
+        q.ntile = ntile;
+        q.nsplit = nsplit_eff;
+        q.nblocks = (int64_t)nblocks;
+        *kc_out = kc_len;
+        return (size_t)ntile * nsplit_eff * GT * GT * sizeof(float);
+    }
+    // run_gram16: FP32 node-major (n = L, K = N) or FP64 sample-major columns
+    const int64_t nt = cdiv(L, TILE);
+    const int64_t ntile = nt * (nt + 1) / 2;
+    int64_t kc_len;
+    int nchunk;
+    plan_chunks(ntile, N, 16, kc_len, nchunk);
+    q.kind = dt == ELM_F32 ? GRAM_F32 : GRAM_F64;
+    q.n = L;
+    q.K = N;
+    q.kc_len = kc_len;
+    q.ntile = ntile;
+    q.nsplit = nchunk;
+    q.nblocks = ntile * nchunk;
+    q.work = nullptr;
+    *kc_out = kc_len;
+    return (size_t)ntile * nchunk * TILE * TILE * (dt == ELM_F32 ? sizeof(float) : sizeof(double));
+}
+
+int64_t gram_group_blocks(int stage, const GramDesc& q) {
+    if (stage == 0) return q.nblocks;
+    if (stage == 1) return q.kind <= GRAM_F16 ? q.ntile * (GT * GT / NT) : q.ntile;
+    return 1;
+}
+
+void launch_gram_grouped(hipStream_t s, int stage, int kind, const GramDesc* d, const GroupSched& g) {
+    if (g.count <= 0 || g.blocks <= 0) return;
+    const unsigned grid = (unsigned)g.blocks;
+    if (stage == 0) {
+        const bool five = gram_stages() == 5;
+        switch (kind) {
+            case GRAM_BF16:
+                if (five) gram_lp256_grouped<__bf16, 5><<<grid, 256, 0, s>>>(d, g);
+                else gram_lp256_grouped<__bf16, 4><<<grid, 256, 0, s>>>(d, g);
+                break;
+            case GRAM_F16:
+                if (five) gram_lp256_grouped<_Float16, 5><<<grid, 256, 0, s>>>(d, g);
+                else gram_lp256_grouped<_Float16, 4><<<grid, 256, 0, s>>>(d, g);
+                break;
+            case GRAM_F32: gram16_grouped<float, true><<<grid, NT, 0, s>>>(d, g); break;
+            default: gram16_grouped<double, false><<<grid, NT, 0, s>>>(d, g); break;
+        }
+    } else if (stage == 1) {
+        if (kind <= GRAM_F16) gram_finish_grouped<0><<<grid, NT, 0, s>>>(d, g);
+        else if (kind == GRAM_F32) gram_finish_grouped<1><<<grid, NT, 0, s>>>(d, g);
+        else gram_finish_grouped<2><<<grid, NT, 0, s>>>(d, g);
+    } else {
+        gram_finish_grouped<3><<<grid, NT, 0, s>>>(d, g);
+    }
+    ELM_LAUNCH_CHECK();
+}
+
+int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
+                             int64_t ldn, double* M, int64_t ldm, Workspace& ws, int force_splits) {
+    if (dt == ELM_F32) return run_gram16<float, true>(s, L, N, (const float*)Hn, ldn, M, ldm, ws);
+    const int64_t nt = cdiv(L, GT);
+    const int64_t ntile = nt * (nt + 1) / 2;
+    int nsplit = force_splits;
+    if (nsplit <= 0) nsplit = gram_splits_override();
+    if (nsplit <= 0) nsplit = ws.find_splits(L, N, (int)dt);
+    if (nsplit <= 0) nsplit = pick_splits(ntile, N);
+    const int64_t kc_len = cdiv(cdiv(N, nsplit), GBK) * GBK;
+    const int nsplit_eff = (int)cdiv(N, kc_len);
+    size_t nblocks = 0;
+    const int4* dtab = gram_table(s, L, nsplit_eff, ws, &nblocks);
     float* part = (float*)ws.get("gram_part", (size_t)ntile * nsplit_eff * GT * GT * sizeof(float));
     {
         StageScope sc(ws.prof, ELM_STAGE_GRAM, s);

@@ -161,22 +161,18 @@ __device__ inline void tile_ht_times_t(const A (&acc)[4][JB], const double* __re
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT, 4) void hidden_kernel(int64_t N, int64_t d, int64_t L,
-                                                       int64_t nrow_t, int64_t ncol_t,
-                                                       const T* __restrict__ X, int64_t ldx,
-                                                       const T* __restrict__ W, int64_t ldw,
-                                                       const T* __restrict__ bias,
-                                                       T* __restrict__ H, int64_t ldh,
-                                                       void* __restrict__ Hlp, int64_t ldlp,
-                                                       elm_dtype lp_dt, const double* __restrict__ Tg,
-                                                       int64_t ldt, int m, double* __restrict__ Zp) {
+__device__ __forceinline__ void hidden_body(int64_t row_t, int64_t col_t, int64_t N, int64_t d,
+                                            int64_t L, const T* __restrict__ X, int64_t ldx,
+                                            const T* __restrict__ W, int64_t ldw,
+                                            const T* __restrict__ bias, T* __restrict__ H,
+                                            int64_t ldh, void* __restrict__ Hlp, int64_t ldlp,
+                                            elm_dtype lp_dt, const double* __restrict__ Tg,
+                                            int64_t ldt, int m, double* __restrict__ Zp) {
     __shared__ __align__(16) unsigned char smem[HiddenSmem<T>::BYTES];
     typedef T Tile[HK][HP];
     Tile* Xs = (Tile*)smem;  // Xs[buf]: k-major, so an MFMA A read is 16 consecutive samples
     Tile* Ws = Xs + 2;       // Ws[buf]
 
-    int64_t row_t, col_t;
-    if (!hidden_tile(nrow_t, ncol_t, row_t, col_t)) return;
     const int64_t n0 = row_t * HT, j0 = col_t * HT;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -271,7 +267,42 @@ __global__ __launch_bounds__(NT, 4) void hidden_kernel(int64_t N, int64_t d, int
         if (Zp) tile_ht_times_t(acc, Tg, ldt, m, Zp + row_t * L * m, N, L, n0, j0, smem);
 }
 
+template <typename T>
+__global__ __launch_bounds__(NT, 4) void hidden_kernel(int64_t N, int64_t d, int64_t L,
+                                                       int64_t nrow_t, int64_t ncol_t,
+                                                       const T* __restrict__ X, int64_t ldx,
+                                                       const T* __restrict__ W, int64_t ldw,
+                                                       const T* __restrict__ bias,
+                                                       T* __restrict__ H, int64_t ldh,
+                                                       void* __restrict__ Hlp, int64_t ldlp,
+                                                       elm_dtype lp_dt, const double* __restrict__ Tg,
+                                                       int64_t ldt, int m, double* __restrict__ Zp) {
+    int64_t row_t, col_t;
+    if (!hidden_tile(nrow_t, ncol_t, row_t, col_t)) return;
+    hidden_body<T>(row_t, col_t, N, d, L, X, ldx, W, ldw, bias, H, ldh, Hlp, ldlp, lp_dt, Tg, ldt, m,
+                   Zp);
+}
+
+// the hidden layers of a batch (FP64 inputs): the blocks of a problem run
+// over its tiles, column tiles of a row tile consecutive
+__global__ __launch_bounds__(NT, 4) void hidden_grouped(const HiddenDesc* __restrict__ dd,
+                                                        GroupSched g) {
+    int64_t lb;
+    const HiddenDesc& q = dd[group_problem(g, lb)];
+    const int64_t ncol_t = cdiv(q.L, HT);
+    hidden_body<double>(lb / ncol_t, lb % ncol_t, q.N, q.d, q.L, q.X, q.ldx, q.W, q.ldw, q.b, q.H,
+                        q.ldh, q.Hlp, q.ldlp, q.lp_dt, q.T, q.ldt, q.m, q.Zp);
+}
+
 }  // namespace
+
+int64_t hidden_group_blocks(const HiddenDesc& q) { return cdiv(q.N, HT) * cdiv(q.L, HT); }
+
+void launch_hidden_grouped(hipStream_t s, const HiddenDesc* d, const GroupSched& g) {
+    if (g.count <= 0 || g.blocks <= 0) return;
+    hidden_grouped<<<(unsigned)g.blocks, NT, 0, s>>>(d, g);
+    ELM_LAUNCH_CHECK();
+}
 
 void launch_hidden(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L, const void* X,
                    int64_t ldx, const void* W, int64_t ldw, const void* b, void* H, int64_t ldh,

@@ -520,21 +520,72 @@ void launch_hidden_output(hipStream_t s, int64_t N, int64_t L, int64_t m, const 
 
 // out[g][e] = sum of part[c][e] over the chunks c of group g (GS consecutive
 // chunks), in order
-__global__ __launch_bounds__(NT) void group_sum_kernel(int64_t len, int64_t nchunk, int gs,
-                                                       const double* __restrict__ part,
-                                                       double* __restrict__ out) {
-    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+__device__ __forceinline__ void group_sum_body(int64_t bx, int64_t by, int64_t len, int64_t nchunk,
+                                               int gs, const double* __restrict__ part,
+                                               double* __restrict__ out) {
+    const int64_t e = bx * NT + threadIdx.x;
     if (e >= len) return;
-    const int64_t c0 = (int64_t)blockIdx.y * gs;
+    const int64_t c0 = by * gs;
     const int64_t c1 = c0 + gs < nchunk ? c0 + gs : nchunk;
     double acc = 0.0;
     for (int64_t c = c0; c < c1; ++c) acc += part[c * len + e];
-    out[(int64_t)blockIdx.y * len + e] = acc;
+    out[by * len + e] = acc;
+}
+
+__global__ __launch_bounds__(NT) void group_sum_kernel(int64_t len, int64_t nchunk, int gs,
+                                                       const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+    group_sum_body(blockIdx.x, blockIdx.y, len, nchunk, gs, part, out);
+}
+
+constexpr int PSUM_GS = 64;  // chunks per group sum (two levels above 2 PSUM_GS chunks)
+
+// launch_partial_sum of a batch: stage 0 the group sums, 1 the column sums
+// and their squares, 2 the total
+template <int STAGE>
+__global__ __launch_bounds__(NT) void partial_sum_grouped(const PsumDesc* __restrict__ d,
+                                                          GroupSched g) {
+    int64_t lb;
+    const PsumDesc& q = d[group_problem(g, lb)];
+    const int64_t len = q.L * q.m;
+    const bool two = q.nchunk > 2 * PSUM_GS;
+    if constexpr (STAGE == 0) {
+        const int64_t nbx = cdiv(len, NT);
+        group_sum_body(lb % nbx, lb / nbx, len, q.nchunk, PSUM_GS, q.part, q.part2);
+    } else if constexpr (STAGE == 1) {
+        ht_reduce_body(lb, q.L, (int)q.m, (int)(two ? cdiv(q.nchunk, PSUM_GS) : q.nchunk),
+                       two ? q.part2 : q.part, q.G, q.m, q.sq);
+    } else {
+        sum_body(cdiv(len, NT), q.sq, q.nrm2);
+    }
+}
+
+size_t psum_part2_doubles(int64_t L, int64_t m, int64_t nchunk) {
+    return nchunk > 2 * PSUM_GS ? (size_t)cdiv(nchunk, PSUM_GS) * L * m : 0;
+}
+
+int64_t partial_sum_group_blocks(int stage, const PsumDesc& q) {
+    const int64_t len = q.L * q.m;
+    if (stage == 0) return q.nchunk > 2 * PSUM_GS ? cdiv(len, NT) * cdiv(q.nchunk, PSUM_GS) : 0;
+    if (stage == 1) return cdiv(len, NT);
+    return 1;
+}
+
+void launch_partial_sum_grouped(hipStream_t s, int stage, const PsumDesc* d, const GroupSched& g) {
+    if (g.count <= 0 || g.blocks <= 0) return;
+    const unsigned grid = (unsigned)g.blocks;
+    if (stage == 0)
+        partial_sum_grouped<0><<<grid, NT, 0, s>>>(d, g);
+    else if (stage == 1)
+        partial_sum_grouped<1><<<grid, NT, 0, s>>>(d, g);
+    else
+        partial_sum_grouped<2><<<grid, NT, 0, s>>>(d, g);
+    ELM_LAUNCH_CHECK();
 }
 
 void launch_partial_sum(hipStream_t s, int64_t L, int64_t m, int64_t nchunk, const double* part,
                         double* G, int64_t ldg, double* nrm2, Workspace& ws) {
-    constexpr int GS = 64;
+    constexpr int GS = PSUM_GS;
     if (nchunk > 2 * GS) {  // two levels, so that no thread sums thousands of chunks
         const int64_t ng = cdiv(nchunk, GS);
         double* part2 = (double*)ws.get("psum_part2", (size_t)ng * L * m * sizeof(double));

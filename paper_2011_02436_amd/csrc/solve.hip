@@ -430,93 +430,29 @@ void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws, bool wait) {
 
 namespace {
 
-// A grouped program: launches recorded with their descriptor arrays and
-// schedules, uploaded in one copy, then issued in order on one stream.
-struct GroupProgram {
-    enum Kind { MAT, GEMM, CALL };
-    struct Launch {
-        Kind kind = MAT;
-        int op = 0;  // MatOp, or the GEMM tile
-        size_t doff = 0, soff = 0;
-        int count = 0;
-        int64_t blocks = 0;
-        std::function<void()> call;
-    };
-    std::vector<char> blob;
-    std::vector<Launch> launches;
-    static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
-    template <class D>
-    void add(Kind kind, int op, const std::vector<D>& descs, const std::vector<int64_t>& nblk) {
-        std::vector<int32_t> st, pr;
-        int64_t tot = 0;
-        for (size_t j = 0; j < descs.size(); ++j) {
-            if (nblk[j] <= 0) continue;
-            st.push_back((int32_t)tot);
-            pr.push_back((int32_t)j);
-            tot += nblk[j];
-            if (tot >= INT32_MAX) throw Error{ELM_ERR_UNSUPPORTED, "grouped launch too large"};
-        }
-        if (pr.empty()) return;
-        st.push_back((int32_t)tot);
-        Launch l;
-        l.kind = kind;
-        l.op = op;
-        l.count = (int)pr.size();
-        l.blocks = tot;
-        l.doff = al(blob.size());
-        blob.resize(l.doff + descs.size() * sizeof(D));
-        std::memcpy(blob.data() + l.doff, descs.data(), descs.size() * sizeof(D));
-        l.soff = al(blob.size());
-        blob.resize(l.soff + (st.size() + pr.size()) * sizeof(int32_t));
-        std::memcpy(blob.data() + l.soff, st.data(), st.size() * sizeof(int32_t));
-        std::memcpy(blob.data() + l.soff + st.size() * sizeof(int32_t), pr.data(),
-                    pr.size() * sizeof(int32_t));
-        launches.push_back(std::move(l));
-    }
-    void mat(MatOp op, const std::vector<MatDesc>& d) {
-        std::vector<int64_t> nb(d.size());
-        for (size_t j = 0; j < d.size(); ++j) nb[j] = mat_group_blocks(op, d[j]);
-        add(MAT, (int)op, d, nb);
-    }
-    // products in two launches by the single-product tile rule
-    void gemm(const std::vector<GemmDesc>& d) {
-        for (int ts : {128, 64}) {
-            std::vector<GemmDesc> sel;
-            std::vector<int64_t> nb;
-            for (const GemmDesc& g : d)
-                if (gemm_tile(g) == ts) {
-                    sel.push_back(g);
-                    nb.push_back(gemm_group_blocks(g, ts));
-                }
-            add(GEMM, ts, sel, nb);
-        }
-    }
-    void call(std::function<void()> f) {
-        Launch l;
-        l.kind = CALL;
-        l.call = std::move(f);
-        launches.push_back(std::move(l));
-    }
-    void run(hipStream_t s, Workspace& ws, const char* name) {
-        char* dev = blob.empty() ? nullptr : (char*)ws.get(name, blob.size());
-        if (dev) ELM_HIP_TRY(hipMemcpyAsync(dev, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
-        for (const Launch& l : launches) {
-            if (l.kind == CALL) {
-                l.call();
-                continue;
+void add_mat(GroupProgram& prog, MatOp op, const std::vector<MatDesc>& d) {
+    std::vector<int64_t> nb(d.size());
+    for (size_t j = 0; j < d.size(); ++j) nb[j] = mat_group_blocks(op, d[j]);
+    prog.add(d, nb, [op](hipStream_t s, const void* dev, const GroupSched& g) {
+        launch_mat_grouped(s, op, (const MatDesc*)dev, g);
+    });
+}
+
+// products in two launches by the single-product tile rule
+void add_gemm(GroupProgram& prog, const std::vector<GemmDesc>& d) {
+    for (int ts : {128, 64}) {
+        std::vector<GemmDesc> sel;
+        std::vector<int64_t> nb;
+        for (const GemmDesc& g : d)
+            if (gemm_tile(g) == ts) {
+                sel.push_back(g);
+                nb.push_back(gemm_group_blocks(g, ts));
             }
-            GroupSched g;
-            g.start = (const int32_t*)(dev + l.soff);
-            g.prob = g.start + l.count + 1;
-            g.count = l.count;
-            g.blocks = l.blocks;
-            if (l.kind == MAT)
-                launch_mat_grouped(s, (MatOp)l.op, (const MatDesc*)(dev + l.doff), g);
-            else
-                launch_gemm_grouped(s, l.op, (const GemmDesc*)(dev + l.doff), g);
-        }
+        prog.add(sel, nb, [ts](hipStream_t s, const void* dev, const GroupSched& g) {
+            launch_gemm_grouped(s, ts, (const GemmDesc*)dev, g);
+        });
     }
-};
+}
 
 GemmDesc gemm_desc(int64_t batch, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                    int64_t a_rs, int64_t a_cs, int64_t a_bs, const double* B, int64_t b_rs,
@@ -587,8 +523,8 @@ void trtri_grouped(GroupProgram& prog, const std::vector<TriJob>& jobs) {
         leaf.push_back(b);
         rmax = std::max(rmax, j.r);
     }
-    prog.mat(MatOp::ZERO, z);
-    prog.mat(MatOp::TRTRI_LEAF, leaf);
+    add_mat(prog, MatOp::ZERO, z);
+    add_mat(prog, MatOp::TRTRI_LEAF, leaf);
     for (int64_t sz = LB; sz < rmax; sz *= 2) {
         std::vector<GemmDesc> pa, pb;
         for (const TriJob& j : jobs) {
@@ -613,8 +549,8 @@ void trtri_grouped(GroupProgram& prog, const std::vector<TriJob>& jobs) {
                                        1, 0, 0.0, j.X + a0 * j.ldx + c0, j.ldx, 0, true, false));
             }
         }
-        prog.gemm(pa);
-        prog.gemm(pb);
+        add_gemm(prog, pa);
+        add_gemm(prog, pb);
     }
 }
 
@@ -716,14 +652,14 @@ std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm
         }
         tr_s.push_back(transpose_desc(q, q, f->Usinv, q, f->UsinvT));
     }
-    prog.mat(MatOp::GATHER_COLS, gat);
+    add_mat(prog, MatOp::GATHER_COLS, gat);
     trtri_grouped(prog, tri_r);
-    prog.mat(MatOp::TRANSPOSE, tr_r);
-    prog.gemm(kk);
-    prog.mat(MatOp::TRANSPOSE, tr_k);
-    prog.gemm(ss);
-    prog.mat(MatOp::ADD_IDENTITY, addi);
-    prog.mat(MatOp::CHOL_INV_SMALL, small);
+    add_mat(prog, MatOp::TRANSPOSE, tr_r);
+    add_gemm(prog, kk);
+    add_mat(prog, MatOp::TRANSPOSE, tr_k);
+    add_gemm(prog, ss);
+    add_mat(prog, MatOp::ADD_IDENTITY, addi);
+    add_mat(prog, MatOp::CHOL_INV_SMALL, small);
     // larger Grams of G: the blocked factorisation one at a time, then the
     // inverses of all of them together
     for (size_t p = 0; p < P; ++p) {
@@ -734,7 +670,7 @@ std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm
         prog.call([=, &ws] { cholesky_blocked(s, q, S, q, 0.0, flag, ws); });
     }
     trtri_grouped(prog, tri_s);
-    prog.mat(MatOp::TRANSPOSE, tr_s);
+    add_mat(prog, MatOp::TRANSPOSE, tr_s);
     ELM_HIP_TRY(hipMemsetAsync(flags, 0, P * sizeof(int), s));
     prog.run(s, ws, "tl_program");
     std::vector<int> hf(P, 0);
