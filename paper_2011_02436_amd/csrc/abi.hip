@@ -988,8 +988,8 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, 
         void* lp = Hlp;
         int64_t ldl = ldlp;
         if (own_lp) {
-            lp = h->ws.get("train_lp", (size_t)L * N * elm::dtype_size(gdt));
-            ldl = N;
+            ldl = elm::lp_ld(N);
+            lp = h->ws.get("train_lp", (size_t)L * ldl * elm::dtype_size(gdt));
         }
         // the hidden layer also forms the per-row-tile partials of Z = H^T T
         const bool fuse_z = m <= elm::HIDDEN_Z_MAX_M;
@@ -1041,11 +1041,11 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, 
             ++ti.escalations;
             gdt = elm::next_gram_dtype(gdt);
             if (gdt == ELM_F32) {
-                void* lp32 = h->ws.get("train_lp32", (size_t)L * N * sizeof(float));
+                ldl = elm::lp_ld(N);
+                void* lp32 = h->ws.get("train_lp32", (size_t)L * ldl * sizeof(float));
                 elm::check_status(h, elm_hidden(h, N, d, L, X, ldx, W, ldw, b, ELM_F64, nullptr, 0,
-                                                lp32, N, ELM_F32));
+                                                lp32, ldl, ELM_F32));
                 lp = lp32;
-                ldl = N;
             }
         }
         if (info) *info = ti;
@@ -1149,7 +1149,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             size_t need = 4 * al((size_t)it.n * it.n * sizeof(double)) +
                           (size_t)256 * it.n * sizeof(double);
             if (!it.transposed && it.fuse_z)  // the shared phase-1 buffers
-                need += al((size_t)p.L * p.N * elm::dtype_size(it.gdt)) +
+                need += al((size_t)p.L * elm::lp_ld(p.N) * elm::dtype_size(it.gdt)) +
                         al((size_t)elm::hidden_row_tiles(p.N) * p.L * p.m * sizeof(double)) +
                         al((size_t)p.L * p.L * sizeof(double));
             if (!groups.back().empty() && gbytes + need > elm::BATCH_GROUP_BYTES) {
@@ -1237,7 +1237,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 const Item& it = items[g1[j]];
                 const int64_t nrt = elm::hidden_row_tiles(p.N);
                 o_lp[j] = off;
-                if (it.gdt != ELM_F64) off += al((size_t)p.L * p.N * elm::dtype_size(it.gdt));
+                if (it.gdt != ELM_F64) off += al((size_t)p.L * elm::lp_ld(p.N) * elm::dtype_size(it.gdt));
                 o_zp[j] = off;
                 off += al((size_t)nrt * p.L * p.m * sizeof(double));
                 o_p2[j] = off;
@@ -1266,7 +1266,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 h1.H = p.H64;
                 h1.ldh = p.ldh64;
                 h1.Hlp = lp;
-                h1.ldlp = p.N;
+                h1.ldlp = elm::lp_ld(p.N);
                 h1.lp_dt = it.gdt;
                 h1.T = p.T;
                 h1.ldt = p.ldt;
@@ -1283,7 +1283,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 s1.nrm2 = it.nrm;
                 elm::GramDesc& g = gd[j];
                 g.A = it.gdt == ELM_F64 ? (const void*)p.H64 : (const void*)lp;
-                g.ld = it.gdt == ELM_F64 ? p.ldh64 : p.N;
+                g.ld = it.gdt == ELM_F64 ? p.ldh64 : elm::lp_ld(p.N);
                 g.part = arena + o_gp[j];
                 g.M = it.M;
                 g.ldm = it.n;
@@ -1368,7 +1368,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 hipStream_t ws = wh->stream;
                 void* lp = nullptr;
                 if (it.gdt != ELM_F64)
-                    lp = wh->ws.get("train_lp", (size_t)p.L * p.N * elm::dtype_size(it.gdt));
+                    lp = wh->ws.get("train_lp", (size_t)p.L * elm::lp_ld(p.N) * elm::dtype_size(it.gdt));
                 double* Zp = nullptr;
                 if (it.fuse_z)
                     Zp = (double*)wh->ws.get("train_zpart", (size_t)elm::hidden_row_tiles(p.N) * p.L *
@@ -1376,7 +1376,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 {
                     elm::StageScope sc(&wh->prof, ELM_STAGE_HIDDEN, ws);
                     elm::launch_hidden(ws, ELM_F64, p.N, p.d, p.L, p.X, p.ldx, p.W, p.ldw, p.b, p.H64,
-                                       p.ldh64, lp, p.N, it.gdt, p.T, p.ldt, p.m, Zp);
+                                       p.ldh64, lp, elm::lp_ld(p.N), it.gdt, p.T, p.ldt, p.m, Zp);
                 }
                 if (it.fuse_z) {
                     elm::StageScope sc(&wh->prof, ELM_STAGE_RHS, ws);
@@ -1389,7 +1389,8 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                     else
                         elm::launch_gram_f64_cols(ws, p.N, p.L, p.H64, p.ldh64, it.M, it.n, wh->ws);
                 } else {
-                    it.kc = elm::launch_gram_lp_nodes(ws, it.gdt, p.N, p.L, lp, p.N, it.M, it.n, wh->ws);
+                    it.kc = elm::launch_gram_lp_nodes(ws, it.gdt, p.N, p.L, lp, elm::lp_ld(p.N), it.M, it.n,
+                                                      wh->ws);
                 }
                 elm::launch_diag_max(ws, it.n, it.M, it.n, dmaxs + slot[e]);
             });

@@ -674,5 +674,8 @@ void launch_predict(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L
                     Workspace& ws);
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+// leading dimension of an internal node-major low-precision copy of H: rows
+// start on 16-byte boundaries, so the 16-bit Gram takes its vector loads
+inline int64_t lp_ld(int64_t N) { return cdiv(N, 8) * 8; }
 
 }  // namespace elm
