@@ -255,7 +255,8 @@ __device__ __forceinline__ void hidden_body(int64_t row_t, int64_t col_t, int64_
                 const int li = wm * 64 + i * 16 + Mfma16<T>::row(lane, v);
                 const int64_t gi = n0 + li;
                 const T h = sigmoid(acc[i][j][v] + bj_val);
-                if (H && gi < N && gj < L) H[gi * ldh + gj] = h;
+                // not read again until the refinement: a streaming store
+                if (H && gi < N && gj < L) __builtin_nontemporal_store(h, &H[gi * ldh + gj]);
                 if (lp16) st16[lj * (HT + 8) + li] = lp16_bits<T>(lp_dt, h);
                 if (lp32) st32[lj * (HT + 4) + li] = (float)h;
                 acc[i][j][v] = h;

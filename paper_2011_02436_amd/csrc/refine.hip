@@ -174,6 +174,8 @@ __global__ __launch_bounds__(NT) void ht_kernel(int64_t N, int64_t L, int m,
 //   lane l walks columns l, l + 64, ..., and a 64-lane butterfly gives every
 //   lane the row sums.  The order of every sum is fixed by the column stride
 //   64 alone (not by the rows per wave or the launch), no LDS, no barrier.
+//   H is read once per pass: its loads are non-temporal, so it does not push
+//   beta (re-read by every wave) and the partials out of the caches.
 //   With labels, also the arg-max of each row (lowest index on ties).
 // cols_dot_kernel: part[chunk][col][o] = sum over the chunk's rows of
 //   H[row][col] E[row][o]; thread per column, the chunk's E rows in LDS.
@@ -215,7 +217,7 @@ __device__ __forceinline__ void rows_dot_body(int64_t bx, int64_t N, int64_t L, 
         for (int c = 0; c < MM; ++c) bv[c] = c < m ? beta[col * ldb + c] : 0.0;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
-            const double h = hrow[r][col];
+            const double h = __builtin_nontemporal_load(&hrow[r][col]);
 #pragma unroll
             for (int c = 0; c < MM; ++c) acc[r][c] += h * bv[c];
         }
@@ -279,14 +281,14 @@ __device__ __forceinline__ void cols_dot_body(int64_t bx, int64_t by, int64_t N,
         for (; r + 8 <= nrows; r += 8) {
             double h[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) h[u] = hp[(int64_t)(r + u) * ldh];
+            for (int u = 0; u < 8; ++u) h[u] = __builtin_nontemporal_load(&hp[(int64_t)(r + u) * ldh]);
 #pragma unroll
             for (int u = 0; u < 8; ++u)
 #pragma unroll
                 for (int c = 0; c < MM; ++c) acc[c] += h[u] * Es[(r + u) * MM + c];
         }
         for (; r < nrows; ++r) {
-            const double hv = hp[(int64_t)r * ldh];
+            const double hv = __builtin_nontemporal_load(&hp[(int64_t)r * ldh]);
 #pragma unroll
             for (int c = 0; c < MM; ++c) acc[c] += hv * Es[r * MM + c];
         }
