@@ -155,8 +155,23 @@ __global__ __launch_bounds__(NTH, NTH / 128) void gemm_kernel(int64_t M, int64_t
                                                      double* __restrict__ C, int64_t ldc,
                                                      int64_t c_bs, int tri_a, int tri_b, int upper_c,
                                                      const int* __restrict__ skip) {
-    gemm_body<TS, NTH>(blockIdx.x, blockIdx.y, blockIdx.z, M, N, K, alpha, A, a_rs, a_cs, a_bs, B,
-                       b_rs, b_cs, b_bs, beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);
+    // A triangular operand makes the tiles' k ranges unequal: blocks are
+    // dispatched in the order of their ids, so the longest tiles take the
+    // first ids (tri_a: the top tile rows first; tri_b: the rightmost tile
+    // columns first) and the short ones fill in behind them.
+    int64_t bx = blockIdx.x, by = blockIdx.y;
+    if (tri_a || tri_b) {
+        const int64_t b = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+        if (tri_a) {
+            bx = b / gridDim.y;
+            by = b % gridDim.y;
+        } else {
+            by = gridDim.y - 1 - b / gridDim.x;
+            bx = b % gridDim.x;
+        }
+    }
+    gemm_body<TS, NTH>(bx, by, blockIdx.z, M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs, b_bs,
+                       beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);
 }
 
 // products of a grouped launch: blocks of a descriptor run over its tiles
