@@ -414,22 +414,39 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
 }
 
 // M[i][j] = M[j][i] = sum over splits (in order, FP64) of the 256-tile partials;
-// partial slot of (split s, tile t) is s * ntile + t.
+// partial slot of (split s, tile t) is s * ntile + t.  A block sums one 32 x 32
+// sub-tile (by: its position in the tile), writes its rows of M, and writes the
+// mirrored rows from an LDS copy, so both stores are coalesced.
+constexpr int RS = 32;                       // sub-tile of the partial sums
+constexpr int RSUBS = (GT / RS) * (GT / RS); // sub-tiles per tile
 __device__ __forceinline__ void gram_reduce256_body(int64_t bx, int64_t by, int64_t n,
                                                     const float* __restrict__ part, int64_t ntile,
                                                     int nsplit, double* __restrict__ M,
                                                     int64_t ldm) {
+    __shared__ double sm[RS][RS + 1];
     int bi, bj;
     tile_coords(bx, bi, bj);
-    const int64_t r0 = (int64_t)bi * GT, c0 = (int64_t)bj * GT;
-    const int64_t e = by * NT + threadIdx.x;  // element within the tile
-    const int row = (int)(e / GT), col = (int)(e % GT);
-    const int64_t gi = r0 + row, gj = c0 + col;
-    if (gi >= n || gj >= n || gi > gj) return;
-    double s = 0.0;
-    for (int c = 0; c < nsplit; ++c) s += (double)part[((int64_t)c * ntile + bx) * (GT * GT) + e];
-    M[gi * ldm + gj] = s;
-    M[gj * ldm + gi] = s;
+    const int sr = (int)(by / (GT / RS)), sc = (int)(by % (GT / RS));
+    const int64_t r0 = (int64_t)bi * GT + sr * RS, c0 = (int64_t)bj * GT + sc * RS;
+    const int tx = threadIdx.x % RS, ty = threadIdx.x / RS;  // 32 x 8 threads
+    for (int k = 0; k < RS; k += NT / RS) {
+        const int row = ty + k;
+        const int64_t gi = r0 + row, gj = c0 + tx;
+        double s = 0.0;
+        const bool on = gi < n && gj < n && gi <= gj;
+        if (on) {
+            const int64_t e = (int64_t)(sr * RS + row) * GT + sc * RS + tx;  // element within the tile
+            for (int c = 0; c < nsplit; ++c) s += (double)part[((int64_t)c * ntile + bx) * (GT * GT) + e];
+            M[gi * ldm + gj] = s;
+        }
+        sm[row][tx] = s;
+    }
+    __syncthreads();
+    for (int k = 0; k < RS; k += NT / RS) {
+        const int col = ty + k;                 // sub-tile column: the mirrored row
+        const int64_t gi = r0 + tx, gj = c0 + col;
+        if (gi < n && gj < n && gi <= gj) M[gj * ldm + gi] = sm[tx][col];
+    }
 }
 
 __global__ __launch_bounds__(NT) void gram_reduce256_kernel(int64_t n, const float* __restrict__ part,
@@ -665,7 +682,7 @@ size_t gram_group_plan(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, GramDe
 
 int64_t gram_group_blocks(int stage, const GramDesc& q) {
     if (stage == 0) return q.nblocks;
-    if (stage == 1) return q.kind <= GRAM_F16 ? q.ntile * (GT * GT / NT) : q.ntile;
+    if (stage == 1) return q.kind <= GRAM_F16 ? q.ntile * RSUBS : q.ntile;
     return 1;
 }
 
@@ -731,7 +748,7 @@ int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, 
         ELM_LAUNCH_CHECK();
     }
     StageScope sc(ws.prof, ELM_STAGE_GRAM_REDUCE, s);
-    gram_reduce256_kernel<<<dim3((unsigned)ntile, GT * GT / NT), NT, 0, s>>>(L, part, ntile, nsplit_eff,
+    gram_reduce256_kernel<<<dim3((unsigned)ntile, RSUBS), NT, 0, s>>>(L, part, ntile, nsplit_eff,
                                                                             M, ldm);
     ELM_LAUNCH_CHECK();
     return kc_len;
