@@ -206,3 +206,48 @@ def test_batched_iteration_cap_equals_single_trainings(elm, batch, ir_max_iter):
             assert stats[e] == 0 and infos[e]["ne_residual"] == -1.0
         else:
             assert stats[e] == elm.ELM_ERR_NO_CONVERGENCE and infos[e]["iterations"] <= 1
+
+
+@pytest.fixture(scope="module")
+def tails():
+    """Shapes the other fixtures miss: Grams of G above order 128 (blocked
+    Cholesky, then the shared inverse) in the Woodbury form (n - r < r) and
+    the direct form (n - r >= r), full rank (no K), m > 8 (trained per problem
+    beside the shared launches) and N < L, in one batch."""
+    specs = [(3000, 700, 200, 3), (2500, 600, 350, 3), (2000, 300, 0, 3), (1500, 200, 20, 12),
+             (400, 900, 90, 3)]
+    probs = [wl.random_problem(60 + i, N, 16, L, m, n_dup=k) for i, (N, L, k, m) in enumerate(specs)]
+    refs = []
+    for p in probs:
+        H = O.hidden(p.X, p.W, p.b)
+        beta, F = O.solve(H, p.T)
+        s = np.linalg.svd(H[:, F.piv[:F.r]] if p.N >= p.L else H[F.piv[:F.r], :], compute_uv=False)
+        refs.append((beta, F.r, (s[0] / s[-1]) ** 2))
+    return probs, refs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_batched_tail_shapes_match_oracle_and_single(elm, tails, precision):
+    probs, refs = tails
+    dev = [_dev(p) for p in probs]
+    betas, infos, stats = elm.train_batched(dev, precision=precision, ir_tol=1e-12)
+    assert stats == [0] * len(probs)
+    for e, (p, (ref, r, k2)) in enumerate(zip(probs, refs)):
+        info = infos[e]
+        err = O.rel_err(betas[e].cpu().numpy(), ref)
+        tol = max(1e-10, 50 * k2 * EPS) if precision == "fp64" else 1e-6
+        n = min(p.N, p.L)
+        print(f"[{e}] N={p.N} L={p.L} m={p.m} rank {info['rank']} (oracle {r}), n - r = {n - r}, "
+              f"{info['gram_dtype']} its {info['iterations']} err {err:.2e} tol {tol:.1e}")
+        assert info["rank"] == r == p.structural_rank
+        assert info["ne_residual"] <= 1e-12
+        assert err <= tol
+        X, W, b, T = dev[e]
+        one = elm.train(X, W, b, T, precision=precision, ir_tol=1e-12)
+        assert torch.equal(one.beta, betas[e]), e
+        assert one.info["iterations"] == info["iterations"]
+    # the shapes reach the branches they are meant for
+    r = [info["rank"] for info in infos]
+    assert 700 - r[0] > 128 and 700 - r[0] < r[0]
+    assert 600 - r[1] > 128 and 600 - r[1] >= r[1]
+    assert r[2] == 300
