@@ -314,19 +314,23 @@ typedef struct {
  * hidden-layer sizes or seeds), with one precision form and tolerances for
  * all, and the same results as elm_train gives each problem alone (problems of
  * order >= ELM_OPT_FULL_RANK_MIN_ORDER take the greedy rank rule here, not
- * the certified full-rank path, so their beta agrees to rounding).  The work
- * runs in three phases: (1) the hidden layer, Z = H^T T and the Gram of every
- * problem, on worker streams owned by the handle (created on first use),
- * longest first by the Gram's cost; (2) the pivoted Cholesky rank decisions
- * of all problems together, one launch per pivot step for the whole group
- * (problems of order <= 512 take one workgroup each), on the first worker's
- * stream, where the chain of pivot steps is captured once as a HIP graph and
- * replayed by later calls with the same group shape;
- * (3) the factor's dense tail, beta and refinement, on the worker streams.  A
+ * the certified full-rank path, so their beta agrees to rounding).  Each step
+ * is one launch for all problems (each block runs the single-problem kernel's
+ * arithmetic for its problem), on a batch stream owned by the handle, in
+ * three phases: (1) the hidden layer, Z = H^T T and the Gram of every problem
+ * with N >= L and m <= 8 (the others on worker streams owned by the handle,
+ * created on first use); (2) the pivoted Cholesky rank decisions, one launch
+ * per pivot step for the whole group (problems of order <= 512 take one
+ * workgroup each), the chain captured once as a HIP graph and replayed by later
+ * calls with the same group shape; (3) the factors' dense tails, then beta and
+ * the refinement of every problem with N >= L, m <= 8 and rank >= 1, with one
+ * host read-back per refinement iteration for all of them (the others on the
+ * worker streams).  A
  * problem whose low-precision guard fails is trained again alone from the
  * next precision (as elm_train does).  Problems are grouped so that the
- * Grams and factorisation scratch of a group (about 32 n^2 bytes per problem,
- * n = min(N, L)) stay within 16 GiB.  The work starts after what is already
+ * Grams, factorisation scratch and phase-1 buffers of a group (about 32 n^2
+ * bytes per problem, n = min(N, L), plus its low-precision copy of H) stay
+ * within 16 GiB.  The work starts after what is already
  * queued on the handle's stream, and that stream continues only after all of
  * it; the call returns when every training has finished.  infos and statuses
  * (host arrays of `count`, may be NULL) receive each training's report and
