@@ -170,7 +170,8 @@ __global__ __launch_bounds__(NT) void ht_kernel(int64_t N, int64_t L, int m,
 // Streaming passes built for HBM bandwidth.
 //
 // rows_dot_kernel: out[row][o] = sign * (H beta)[row][o] + (T ? T[row][o] : 0).
-//   Each wave owns RW rows (RW MM <= 32 FP64 partial sums per lane);
+//   Each wave owns RW rows (16 for m <= 4, else 32 / MM: up to 64 FP64
+//   partial sums per lane);
 //   lane l walks columns l, l + 64, ..., and a 64-lane butterfly gives every
 //   lane the row sums.  The order of every sum is fixed by the column stride
 //   64 alone (not by the rows per wave or the launch), no LDS, no barrier.
@@ -184,7 +185,7 @@ constexpr int SB = 256;   // threads per block
 constexpr int CR_ROWS = 1024;  // rows per chunk, cols_dot_kernel
 template <int MM>
 struct RowsDot {
-    static constexpr int RW = MM <= 4 ? 8 : 32 / MM;  // rows per wave
+    static constexpr int RW = MM <= 4 ? 16 : 32 / MM;  // rows per wave
     static constexpr int RB = RW * SB / 64;  // rows per block
 };
 
