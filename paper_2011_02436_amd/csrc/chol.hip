@@ -63,7 +63,11 @@ __global__ void zero_lower_kernel(int64_t n, double* __restrict__ U, int64_t ldu
 // the diagonal owner by a lane shuffle, scale the row and publish it in LDS
 // (with the stop decision); after one block barrier every thread applies
 // the row to its elements.  Row and pivot buffers alternate between steps,
-// so one barrier per step suffices.
+// so one barrier per step suffices.  A step's work is issue-bound, so the
+// element slices a step cannot change are skipped by block-uniform tests:
+// slices below the diagonal (b < a), slices whose rows are all final, and in
+// the inverse the columns left of the step's row (its entries there are 0).
+// Every remaining element is updated exactly as before.
 __device__ __forceinline__ void potrf_block_body(double* __restrict__ U, int64_t ldu, int64_t k0,
                                                  int nb, double thr, double* __restrict__ W,
                                                  int64_t ldw, int* flag) {
@@ -121,10 +125,11 @@ __device__ __forceinline__ void potrf_block_body(double* __restrict__ U, int64_t
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
+            if (32 * a + 31 <= j) continue;  // every row of slice a is final
             const int i = ty + 32 * a;
             const double ri = rowb[pb][i];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = a; b < 4; ++b) {  // b < a: below the diagonal
                 const int c = tx + 32 * b;
                 if (i > j && c >= i) u[a][b] -= ri * rowb[pb][c];
             }
@@ -165,11 +170,14 @@ __device__ __forceinline__ void potrf_block_body(double* __restrict__ U, int64_t
         __syncthreads();
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
+            if (32 * a >= k) continue;  // no row of slice a is above row k
             const int i = ty + 32 * a;
             const double uik = Us[i][k];
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+            for (int b = a; b < 4; ++b) {
+                if (32 * b + 31 < k) continue;  // W[k][c] = 0 for c < k
                 if (i < k) w[a][b] -= uik * rowb[pb][tx + 32 * b];
+            }
         }
     }
 #pragma unroll
