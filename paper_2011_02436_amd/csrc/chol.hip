@@ -17,7 +17,8 @@
 //   strip         the block rows take the updates of the earlier block rows
 //                 of their group of GB rows            (FP64 MFMA GEMM)
 //   potrf_block   one workgroup: the block's Cholesky factor (held in
-//                 registers), written to U, then its inverse, written to W
+//                 registers), written to U, then its inverse (in LDS), written
+//                 to W
 //   copy          the block rows right of the diagonal block into T
 //   product       U12 = W^T T                           (FP64 MFMA GEMM)
 // and per group: S -= U_g^T U_g on the trailing matrix's upper tiles, with
@@ -65,9 +66,9 @@ __global__ void zero_lower_kernel(int64_t n, double* __restrict__ U, int64_t ldu
 // the row to its elements.  Row and pivot buffers alternate between steps,
 // so one barrier per step suffices.  A step's work is issue-bound, so the
 // element slices a step cannot change are skipped by block-uniform tests:
-// slices below the diagonal (b < a), slices whose rows are all final, and in
-// the inverse the columns left of the step's row (its entries there are 0).
-// Every remaining element is updated exactly as before.
+// slices below the diagonal (b < a) and slices whose rows are all final.
+// The inverse is then formed in LDS by recursive doubling (log2 CB levels of
+// two small products each) rather than by CB more dependent steps.
 __device__ __forceinline__ void potrf_block_body(double* __restrict__ U, int64_t ldu, int64_t k0,
                                                  int nb, double thr, double* __restrict__ W,
                                                  int64_t ldw, int* flag) {
@@ -78,7 +79,7 @@ __device__ __forceinline__ void potrf_block_body(double* __restrict__ U, int64_t
     if (*flag) return;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const int lane = threadIdx.x & 63, half = lane & 32;  // this row's lanes: half .. half + 31
-    double u[4][4], w[4][4];
+    double u[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -144,48 +145,66 @@ __device__ __forceinline__ void potrf_block_body(double* __restrict__ U, int64_t
             Us[i][c] = x;
             if (i < nb && c < nb) U[(k0 + i) * ldu + k0 + c] = x;
         }
-    // W = U^-1 from the bottom row up: W[k][:] /= U[k][k], then
-    // W[i][:] -= U[i][k] W[k][:] for i < k  (W starts as the identity).
-    // The owners of row k scale it and publish it; one barrier per step.
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) w[a][b] = (ty + 32 * a == tx + 32 * b) ? 1.0 : 0.0;
+    // W = U^-1 in place in Us by recursive doubling: first the inverted
+    // diagonal, then for s = 1, 2, ..., CB / 2 each pair of inverted s x s
+    // diagonal blocks A^-1, C^-1 and the block B of U between them give the
+    // inverse's block -A^-1 (B C^-1): two products whose entries are staged in
+    // registers across a barrier before they overwrite B.  Each entry is a sum
+    // over k in increasing order (the triangular factors' zeros bound k).  Rows
+    // past nb carry an identity, so they add exact zeros.
     __syncthreads();  // Us complete
-    for (int k = nb - 1; k >= 0; --k) {
-        const int kl = k & 31, kh = k >> 5, pb = k & 1;
-        if (ty == kl) {
-            const double rk = 1.0 / Us[k][k];
+    if (threadIdx.x < CB) {
+        const int i = threadIdx.x;
+        Us[i][i] = i < nb ? 1.0 / Us[i][i] : 1.0;
+    }
+    __syncthreads();
+    for (int s = 1; s < CB; s *= 2) {
+        const int E = s >= 16 ? s / 16 : 1;  // entries per thread: a 1 x E row piece
+        const int groups = s / E;            // row pieces per row
+        const int t = threadIdx.x;
+        const bool act = t < (CB / (2 * s)) * s * groups;  // pairs x rows x pieces
+        const int pg = s * groups;
+        const int i0 = act ? 2 * s * (t / pg) : 0, i = act ? (t % pg) / groups : 0;
+        const int j0 = act ? (t % groups) * E : 0;   // first column of the piece within C
+        const int ra = i0 + i, cb = i0 + s + j0;     // row in A, first column in C
+        double acc[4];
+        // T = B C^-1: row ra of B times columns cb .. cb + E - 1 of C^-1 (rows k <= column)
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-                if (a == kh) {
+        for (int e = 0; e < 4; ++e) acc[e] = 0.0;
+        if (act)
+            for (int k = 0; k < j0 + E; ++k) {
+                const double bik = Us[ra][i0 + s + k];
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const double x = w[a][b] * rk;
-                        w[a][b] = x;
-                        rowb[pb][tx + 32 * b] = x;
-                    }
-                }
-        }
+                for (int e = 0; e < 4; ++e)
+                    if (e < E) acc[e] += bik * Us[i0 + s + k][cb + e];
+            }
         __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            if (32 * a >= k) continue;  // no row of slice a is above row k
-            const int i = ty + 32 * a;
-            const double uik = Us[i][k];
+        for (int e = 0; e < 4; ++e)
+            if (act && e < E) Us[ra][cb + e] = acc[e];
+        __syncthreads();
+        // -A^-1 T: row i of A^-1 (columns k >= i) times the same columns of T
 #pragma unroll
-            for (int b = a; b < 4; ++b) {
-                if (32 * b + 31 < k) continue;  // W[k][c] = 0 for c < k
-                if (i < k) w[a][b] -= uik * rowb[pb][tx + 32 * b];
+        for (int e = 0; e < 4; ++e) acc[e] = 0.0;
+        if (act)
+            for (int k = i; k < s; ++k) {
+                const double aik = Us[ra][i0 + k];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (e < E) acc[e] += aik * Us[i0 + k][cb + e];
             }
-        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (act && e < E) Us[ra][cb + e] = -acc[e];
+        __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int i = ty + 32 * a, c = tx + 32 * b;
-            if (i < nb && c < nb) W[i * ldw + c] = c >= i ? w[a][b] : 0.0;
+            if (i < nb && c < nb) W[i * ldw + c] = c >= i ? Us[i][c] : 0.0;
         }
 }
 
