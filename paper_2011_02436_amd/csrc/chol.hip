@@ -58,10 +58,58 @@ __global__ void zero_lower_kernel(int64_t n, double* __restrict__ U, int64_t ldu
             U[i * ldu + c] = 0.0;
 }
 
+// lane l's value of x, read by every lane of the wave (l wave-uniform)
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const unsigned long long v = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+// Steps j = 32 JH .. 32 JH + 31 of the block Cholesky below (JH: the slice of
+// the pivot rows, a compile-time index into the thread's registers).
+// Returns true when a pivot is <= thr (every thread alike).
+template <int JH>
+__device__ __forceinline__ bool potrf_slice(double (&u)[4][4], double (*rowb)[CB], int* stop, int nb,
+                                            double thr, int tx, int ty) {
+    for (int jl = 0; jl < 32; ++jl) {
+        const int j = 32 * JH + jl, pb = j & 1;
+        if (j >= nb) return false;
+        if (ty == jl) {
+            // the pivot (j, j): slot (JH, JH) of lane 32 (jl % 2) + jl of this wave
+            const double d = readlane_f64(u[JH][JH], 32 * (jl & 1) + jl);
+            const bool ok = d > thr;
+            const double rj = sqrt(ok ? d : 1.0), inv = 1.0 / rj;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = tx + 32 * b;
+                const double x = c > j ? u[JH][b] * inv : (c == j ? rj : 0.0);
+                rowb[pb][c] = x;
+                u[JH][b] = x;
+            }
+            if (tx == 0) stop[pb] = ok ? 0 : 1;
+        }
+        __syncthreads();
+        if (stop[pb]) return true;  // the same value for every thread
+#pragma unroll
+        for (int a = JH; a < 4; ++a) {  // slices a < JH hold final rows only
+            if (a == JH && jl == 31) continue;  // nor does slice JH after its last step
+            const int i = ty + 32 * a;
+            const double ri = rowb[pb][i];
+#pragma unroll
+            for (int b = a; b < 4; ++b) {  // b < a: below the diagonal
+                const int c = tx + 32 * b;
+                if (i > j && c >= i) u[a][b] -= ri * rowb[pb][c];
+            }
+        }
+    }
+    return false;
+}
+
 // The CB x CB block lives in registers: thread (ty, tx) of a 32 x 32 grid
 // holds the 4 x 4 elements (ty + 32 a, tx + 32 b), so the 32 owners of a row
-// are one half of a wave.  Step j: the owners of row j take its pivot from
-// the diagonal owner by a lane shuffle, scale the row and publish it in LDS
+// are one half of a wave.  Step j: the owners of row j read its pivot from
+// the diagonal owner's lane (readlane), scale the row and publish it in LDS
 // (with the stop decision); after one block barrier every thread applies
 // the row to its elements.  Row and pivot buffers alternate between steps,
 // so one barrier per step suffices.  A step's work is issue-bound, so the
@@ -78,7 +126,6 @@ __device__ __forceinline__ void potrf_block_body(double* __restrict__ U, int64_t
     __shared__ double Us[CB][CB + 1];  // the factor, for the inverse's columns
     if (*flag) return;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int lane = threadIdx.x & 63, half = lane & 32;  // this row's lanes: half .. half + 31
     double u[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -89,52 +136,10 @@ __device__ __forceinline__ void potrf_block_body(double* __restrict__ U, int64_t
         }
     // right-looking Cholesky: row j scaled by the root of its pivot, then
     // u[i][c] -= U[j][i] U[j][c] for j < i <= c
-    for (int j = 0; j < nb; ++j) {
-        const int jl = j & 31, jh = j >> 5, pb = j & 1;
-        if (ty == jl) {
-            double v[4];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                v[b] = 0.0;
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-                    if (a == jh) v[b] = u[a][b];
-            }
-            // the pivot: element (j, j) sits in lane half + jl, slot b = jh
-            double dv = 0.0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (b == jh) dv = v[b];
-            const double d = __shfl(dv, half + jl);
-            const bool ok = d > thr;
-            const double rj = sqrt(ok ? d : 1.0), inv = 1.0 / rj;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int c = tx + 32 * b;
-                const double x = c > j ? v[b] * inv : (c == j ? rj : 0.0);
-                rowb[pb][c] = x;
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-                    if (a == jh) u[a][b] = x;
-            }
-            if (tx == 0) stop[pb] = ok ? 0 : 1;
-        }
-        __syncthreads();
-        if (stop[pb]) {  // the same value for every thread: the block leaves together
-            if (threadIdx.x == 0) *flag = 1;
-            return;
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            if (32 * a + 31 <= j) continue;  // every row of slice a is final
-            const int i = ty + 32 * a;
-            const double ri = rowb[pb][i];
-#pragma unroll
-            for (int b = a; b < 4; ++b) {  // b < a: below the diagonal
-                const int c = tx + 32 * b;
-                if (i > j && c >= i) u[a][b] -= ri * rowb[pb][c];
-            }
-        }
+    if (potrf_slice<0>(u, rowb, stop, nb, thr, tx, ty) || potrf_slice<1>(u, rowb, stop, nb, thr, tx, ty) ||
+        potrf_slice<2>(u, rowb, stop, nb, thr, tx, ty) || potrf_slice<3>(u, rowb, stop, nb, thr, tx, ty)) {
+        if (threadIdx.x == 0) *flag = 1;  // the block leaves together
+        return;
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
