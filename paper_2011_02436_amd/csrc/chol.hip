@@ -79,7 +79,15 @@ __device__ __forceinline__ bool potrf_slice(double (&u)[4][4], double (*rowb)[CB
             // the pivot (j, j): slot (JH, JH) of lane 32 (jl % 2) + jl of this wave
             const double d = readlane_f64(u[JH][JH], 32 * (jl & 1) + jl);
             const bool ok = d > thr;
-            const double rj = sqrt(ok ? d : 1.0), inv = 1.0 / rj;
+            const double dd = ok ? d : 1.0;
+            // 1 / sqrt(dd): the hardware estimate (about 23 bits) and two
+            // Newton-Raphson steps y <- y (3 - dd y^2) / 2, a short dependent
+            // chain on the step's critical path; the root is dd y
+            const double hd = 0.5 * dd;
+            double y = __builtin_amdgcn_rsq(dd);
+            y = y * fma(-hd, y * y, 1.5);
+            y = y * fma(-hd, y * y, 1.5);
+            const double rj = dd * y, inv = y;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int c = tx + 32 * b;
