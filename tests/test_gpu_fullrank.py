@@ -2,7 +2,8 @@
 Cholesky, certificate lambda = 1 / max_j (M^-1)_jj), against the FP64 CPU
 oracle's greedy pivoted Cholesky.  The order threshold is lowered so that
 small problems take the path.  Covered: ragged last blocks (300 = 2 x 128 +
-44, 1000 = 7 x 128 + 104), look-ahead updates on a second stream (1300), the
+44, 1000 = 7 x 128 + 104, single rows at 129 and 1153), one block (128),
+look-ahead updates on a second stream (1300, 1153), the
 N < L route, a rank-deficient Gram (the unpivoted factorisation stops and the
 greedy rule runs) and a threshold the certificate cannot clear (the greedy
 rule runs, full rank)."""
@@ -49,9 +50,11 @@ def _reference(p):
 
 
 # 1300 = three groups of 512 block rows: the second stream's look-ahead
-# update (rows beyond the next group) runs once
+# update (rows beyond the next group) runs once.  Single-row last blocks
+# (129 = 128 + 1, 1153 = 9 x 128 + 1) and exactly one block (128) exercise the
+# diagonal-block kernel's padding (its inverse's identity rows).
 FULL = [(6000, 64, 300, 50), (8000, 128, 1000, 52), (4000, 16, 300, 53), (500, 64, 1200, 55),
-        (9000, 128, 1300, 56)]
+        (9000, 128, 1300, 56), (3000, 32, 129, 57), (9000, 128, 1153, 58), (2000, 32, 128, 59)]
 
 
 @pytest.mark.parametrize("shape", FULL, ids=[f"N{s[0]}_L{s[2]}" for s in FULL])
