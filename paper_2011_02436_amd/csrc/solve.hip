@@ -574,7 +574,7 @@ std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm
     if (P == 0) return bad;
     auto al = GroupProgram::al;
     // scratch: the level products of both inverses, the Gram of G, and a flag each
-    std::vector<size_t> o_t1(P), o_s(P), o_t1s(P);
+    std::vector<size_t> o_t1(P), o_s(P), o_t1s(P), o_w(P);
     size_t off = 0;
     for (size_t p = 0; p < P; ++p) {
         const elm_factor* f = fs[p];
@@ -586,6 +586,10 @@ std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm
         off += al(std::max<size_t>((size_t)(q * q), 1) * sizeof(double));
         o_t1s[p] = off;
         off += al(std::max<size_t>(q > 128 ? trtri_scratch(q) : 0, 1) * sizeof(double));
+        // two-block Grams of G: the first block's inverse and its block row, transposed
+        o_w[p] = off;
+        off += al(std::max<size_t>(q > 128 && q <= 256 ? (size_t)(128 * 128 + (q - 128) * 128) : 0, 1) *
+                  sizeof(double));
     }
     const size_t o_flags = off;
     off += al(P * sizeof(int));
@@ -593,8 +597,8 @@ std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm
     int* flags = (int*)(sc + o_flags);
 
     GroupProgram prog;
-    std::vector<MatDesc> gat, tr_r, tr_k, addi, small, tr_s;
-    std::vector<GemmDesc> kk, ss;
+    std::vector<MatDesc> gat, tr_r, tr_k, addi, small, tr_s, t2, small2, zl2;
+    std::vector<GemmDesc> kk, ss, u12, strip2;
     std::vector<TriJob> tri_r, tri_s;
     for (size_t p = 0; p < P; ++p) {
         elm_factor* f = fs[p];
@@ -649,6 +653,42 @@ std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm
             small.push_back(d);
         } else {
             tri_s.push_back(TriJob{q, S, q, f->Usinv, q, (double*)(sc + o_t1s[p])});
+            if (q <= 256) {
+                // two diagonal blocks: the steps of the blocked factorisation
+                // (first block, U12 = W^T T, the second block row's update,
+                // second block), each shared by every such problem; every
+                // element is computed as in the single-problem factorisation
+                const int64_t q2 = q - 128;
+                double* W = (double*)(sc + o_w[p]);
+                double* Tt = W + 128 * 128;
+                MatDesc d1;
+                d1.rows = 128;
+                d1.dst = S;
+                d1.ldd = q;
+                d1.aux = W;
+                d1.lda = 128;
+                d1.flag = flags + p;
+                small.push_back(d1);
+                t2.push_back(transpose_desc(128, q2, S + 128, q, Tt));
+                u12.push_back(gemm_desc(1, 128, q2, 128, 1.0, W, 1, 128, 0, Tt, 1, 128, 0, 0.0, S + 128, q,
+                                        0, false, false));
+                strip2.push_back(gemm_desc(1, q2, q2, 128, -1.0, S + 128, 1, q, 0, S + 128, q, 1, 0, 1.0,
+                                           S + 128 * q + 128, q, 0, false, false));
+                MatDesc d2;
+                d2.rows = q2;
+                d2.dst = S + 128 * q + 128;
+                d2.ldd = q;
+                d2.aux = W;  // the first block's inverse is no longer needed
+                d2.lda = 128;
+                d2.flag = flags + p;
+                small2.push_back(d2);
+                MatDesc z;  // below the diagonal: zero, as the factorisation leaves it
+                z.rows = q2;
+                z.cols = 128;
+                z.dst = S + 128 * q;
+                z.ldd = q;
+                zl2.push_back(z);
+            }
         }
         tr_s.push_back(transpose_desc(q, q, f->Usinv, q, f->UsinvT));
     }
@@ -660,11 +700,16 @@ std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm
     add_gemm(prog, ss);
     add_mat(prog, MatOp::ADD_IDENTITY, addi);
     add_mat(prog, MatOp::CHOL_INV_SMALL, small);
+    add_mat(prog, MatOp::TRANSPOSE, t2);
+    add_gemm(prog, u12);
+    add_gemm(prog, strip2);
+    add_mat(prog, MatOp::CHOL_INV_SMALL, small2);
+    add_mat(prog, MatOp::ZERO, zl2);
     // larger Grams of G: the blocked factorisation one at a time, then the
     // inverses of all of them together
     for (size_t p = 0; p < P; ++p) {
         const int64_t q = fs[p]->q;
-        if (q <= 128) continue;
+        if (q <= 256) continue;
         double* S = (double*)(sc + o_s[p]);
         int* flag = flags + p;
         prog.call([=, &ws] { cholesky_blocked(s, q, S, q, 0.0, flag, ws); });
