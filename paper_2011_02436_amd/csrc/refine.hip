@@ -172,8 +172,8 @@ __global__ __launch_bounds__(NT) void ht_kernel(int64_t N, int64_t L, int m,
 // rows_dot_kernel: out[row][o] = sign * (H beta)[row][o] + (T ? T[row][o] : 0).
 //   Each wave owns RW rows (16 for m <= 4, else 32 / MM: up to 64 FP64
 //   partial sums per lane);
-//   lane l walks columns l, l + 64, ..., and a 64-lane butterfly gives every
-//   lane the row sums.  The order of every sum is fixed by the column stride
+//   lane l walks columns l, l + 64, ..., and a halving exchange across the
+//   64 lanes forms the row sums (each by a butterfly's pairwise tree).  The order of every sum is fixed by the column stride
 //   64 alone (not by the rows per wave or the launch), no LDS, no barrier.
 //   H is read once per pass: its loads are non-temporal, so it does not push
 //   beta (re-read by every wave) and the partials out of the caches.
@@ -223,35 +223,54 @@ __device__ __forceinline__ void rows_dot_body(int64_t bx, int64_t N, int64_t L, 
             for (int c = 0; c < MM; ++c) acc[r][c] += h * bv[c];
         }
     }
+    // Row sums by a halving exchange over the 64 lanes (offsets 32, 16, ..., 1):
+    // at offset o a lane keeps half of its V partial sums (the upper half when
+    // lane & o) and adds its partner's values of that half, V/2 + V/4 + ...
+    // exchanges instead of 6 V.  Every sum is still formed by the pairwise
+    // tree of a butterfly over that value alone (own + partner at each level),
+    // so the results are those of one.  Value r MM + c ends in lane
+    // (r MM + c) DUP.
+    constexpr int V = RW * MM, DUP = 64 / V;
+    static_assert(V <= 64 && (V & (V - 1)) == 0, "a power-of-two count of sums per lane");
 #pragma unroll
-    for (int r = 0; r < RW; ++r)
+    for (int k = 0; k < 6; ++k) {
+        const int o = 32 >> k, n = V >> k;
+        if (n > 1) {
+            const bool up = (lane & o) != 0;
 #pragma unroll
-        for (int c = 0; c < MM; ++c) {
-            double v = acc[r][c];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-            acc[r][c] = v;
+            for (int i = 0; i < n / 2; ++i) {
+                double& lo = acc[i / MM][i % MM];
+                const double hi = acc[(i + n / 2) / MM][(i + n / 2) % MM];
+                const double send = up ? lo : hi, keep = up ? hi : lo;
+                lo = keep + __shfl_xor(send, o);
+            }
+        } else {
+            acc[0][0] += __shfl_xor(acc[0][0], o);
         }
+    }
+    const double v = acc[0][0];
+    const int idx = lane / DUP, rr = idx / MM, c = idx % MM;
+    const int64_t row = r0 + rr;
+    // one lane per value writes column c of its row
+    if (lane % DUP == 0 && row < N && c < m) {
+        if (out) out[row * ldo + c] = sign * v + (T ? T[row * ldt + c] : 0.0);
+        if (y) y[row * ldy + c] = v;
+    }
+    if (labels) {
+        // the row's values sit in lanes (rr MM + c') DUP; its column-0 lane
+        // takes the arg-max (lowest index on ties)
+        double vals[MM];
+        vals[0] = v;
 #pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const int64_t row = r0 + r;
-        if (row >= N) break;
-        // lane c < m writes column c of the row
-        double v = 0.0;
-#pragma unroll
-        for (int c = 0; c < MM; ++c)
-            if (lane == c) v = acc[r][c];
-        if (lane < m) {
-            if (out) out[row * ldo + lane] = sign * v + (T ? T[row * ldt + lane] : 0.0);
-            if (y) y[row * ldy + lane] = v;
-        }
-        if (labels && lane == 0) {
+        for (int cc = 1; cc < MM; ++cc) vals[cc] = __shfl(v, (lane + cc * DUP) & 63);
+        if (c == 0 && lane % DUP == 0 && row < N) {
             int best = 0;
-            double bvv = acc[r][0];
+            double bvv = vals[0];
 #pragma unroll
-            for (int c = 1; c < MM; ++c)
-                if (c < m && acc[r][c] > bvv) {
-                    bvv = acc[r][c];
-                    best = c;
+            for (int cc = 1; cc < MM; ++cc)
+                if (cc < m && vals[cc] > bvv) {
+                    bvv = vals[cc];
+                    best = cc;
                 }
             labels[row] = best;
         }
