@@ -88,7 +88,7 @@ __global__ void zero_mat_kernel(int64_t rows, int64_t cols, double* __restrict__
 
 // C[i][c] = alpha * sum_k A[i][k] B[k][c] + beta * C[i][c] for thin B (m <= MM
 // columns): one wave per output row, lanes striding over k (coalesced reads
-// of A's row and of B's rows), fixed-order wave reduction.  tri restricts k
+// of A's row and of B's rows), fixed-order lane reduction.  tri restricts k
 // to the nonzero part of a triangular A (1: k >= i, 2: k <= i).
 template <int MM>
 __device__ __forceinline__ void rowprod_body(int64_t bx, int64_t M, int64_t K, int m, double alpha,
@@ -112,20 +112,34 @@ __device__ __forceinline__ void rowprod_body(int64_t bx, int64_t M, int64_t K, i
         for (int c = 0; c < MM; ++c)
             if (c < m) acc[c] += a * brow[c];
     }
+    // the MM sums by a halving exchange across the lanes: at offset o a lane
+    // keeps half of its partial sums (the upper half when lane & o) and adds
+    // its partner's values of that half, so each sum is formed by a
+    // butterfly's pairwise tree with MM/2 + MM/4 + ... shuffles instead of
+    // 6 MM; sum c ends in lane c * (64 / MM)
+    static_assert(MM <= 64 && (MM & (MM - 1)) == 0, "a power-of-two count of sums");
+    constexpr int DUP = 64 / MM;
 #pragma unroll
-    for (int c = 0; c < MM; ++c) {
-        double v = acc[c];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        acc[c] = v;
-    }
-    if (lane == 0)
+    for (int k = 0; k < 6; ++k) {
+        const int o = 32 >> k, n = MM >> k;
+        if (n > 1) {
+            const bool up = (lane & o) != 0;
 #pragma unroll
-        for (int c = 0; c < MM; ++c)
-            if (c < m) {
-                double v = alpha * acc[c];
-                if (beta != 0.0) v += beta * C[i * ldc + c];
-                C[i * ldc + c] = v;
+            for (int c = 0; c < n / 2; ++c) {
+                const double lo = acc[c], hi = acc[c + n / 2];
+                const double send = up ? lo : hi, keep = up ? hi : lo;
+                acc[c] = keep + __shfl_xor(send, o);
             }
+        } else {
+            acc[0] += __shfl_xor(acc[0], o);
+        }
+    }
+    const int c = lane / DUP;
+    if (lane % DUP == 0 && c < m) {
+        double v = alpha * acc[0];
+        if (beta != 0.0) v += beta * C[i * ldc + c];
+        C[i * ldc + c] = v;
+    }
 }
 
 template <int MM>
