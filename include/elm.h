@@ -239,8 +239,10 @@ elm_status elm_factor_destroy(elm_factor* f);
  * residual ||H^T (T - H beta)||_F / ||H^T T||_F exceeds ir_tol and fewer
  * than ir_max_iter corrections were made, beta += H^+ (T - H beta) with H^+
  * applied through the (possibly low-precision-derived) factor; the loop also
- * stops when a correction did not lower the residual.  ir_max_iter = 0 gives
- * beta_0 and skips the residual.  ir_tol must be in [0, 1).
+ * stops when a correction did not lower the residual, and that correction is
+ * taken back (beta is then the best iterate, whose residual is reported, and
+ * `iterations` counts the corrections kept).  ir_max_iter = 0 gives beta_0 and
+ * skips the residual.  ir_tol must be in [0, 1).
  * info (host, may be NULL) receives rank, iterations and residuals.
  * Synchronises once per refinement iteration.
  * Errors: NO_CONVERGENCE if ir_max_iter > 0 and the final residual is above

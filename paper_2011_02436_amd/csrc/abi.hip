@@ -592,6 +592,7 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
     double* E = (double*)ws.get("ps_E", (size_t)N * m * sizeof(double));
     double* G = (double*)ws.get("ps_G", (size_t)L * m * sizeof(double));
     double* D = (double*)ws.get("ps_D", (size_t)L * m * sizeof(double));
+    double* Bprev = (double*)ws.get("ps_Bprev", (size_t)L * m * sizeof(double));
     double res = 0, prev = 0;
     int it = 0;
     for (;;) {
@@ -610,8 +611,21 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
         check_pd();
         res = z2 > 0 ? std::sqrt(g2 / z2) : std::sqrt(g2);
         if (info && it < 32) info->ne_history[it] = res;
+        if (it >= 1 && !(res < prev)) {
+            // the last correction made no progress: take it back, so beta is
+            // the best iterate and the reported residual is its own
+            ELM_HIP_TRY(hipMemcpy2DAsync(beta, (size_t)ldbeta * sizeof(double), Bprev,
+                                         (size_t)m * sizeof(double), (size_t)m * sizeof(double),
+                                         (size_t)L, hipMemcpyDeviceToDevice, s));
+            --it;
+            res = prev;
+            if (Y || labels) {
+                elm::StageScope sc(pr, ELM_STAGE_PREDICT, s);
+                elm::launch_hidden_output(s, N, L, m, H64, ldh64, beta, ldbeta, Y, ldy, labels);
+            }
+            break;
+        }
         if (!(res > ir_tol) || it >= ir_max_iter) break;
-        if (it >= 1 && !(res < prev)) break;  // the last correction made no progress
         prev = res;
         {
             elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
@@ -620,7 +634,7 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
             else
                 elm::apply_pinv(s, f, m, E, m, H64, ldh64, D, m, ws);
         }
-        elm::launch_axpy_mat(s, L, m, D, m, beta, ldbeta);
+        elm::launch_axpy_mat(s, L, m, D, m, beta, ldbeta, Bprev);
         ++it;
     }
     if (info) {
@@ -672,19 +686,19 @@ void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs,
         maxm = std::max<int>(maxm, (int)g.m);
     }
     // per-problem buffers from one arena: g2 of every problem first, then
-    // E, part, G, sq, D, u, t, w, t2, bd of each
+    // E, part, G, sq, D, u, t, w, t2, bd, prev of each
     auto carve = [&](char* base, std::vector<RefineDesc>* rd, std::vector<double*>* scratch) {
         size_t off = al((size_t)P * sizeof(double));
         for (int j = 0; j < P; ++j) {
             const GroupedSolve& g = gs[j];
             const elm_factor* f = g.f;
             const int64_t N = f->N, L = f->L, m = g.m, r = f->r, c = f->n - f->r;
-            const size_t sz[10] = {(size_t)(N * m), refine_part_doubles(N, L, m), (size_t)(L * m),
+            const size_t sz[11] = {(size_t)(N * m), refine_part_doubles(N, L, m), (size_t)(L * m),
                                    refine_sq_doubles(L, m), (size_t)(L * m), (size_t)(r * m),
                                    (size_t)(r * m), (size_t)(c * m), (size_t)(f->q * m),
-                                   (size_t)(c * m)};
-            double* ptr[10];
-            for (int k = 0; k < 10; ++k) {
+                                   (size_t)(c * m), (size_t)(L * m)};
+            double* ptr[11];
+            for (int k = 0; k < 11; ++k) {
                 ptr[k] = base ? (double*)(base + off) : nullptr;
                 off += al(std::max<size_t>(sz[k], 1) * sizeof(double));
             }
@@ -705,6 +719,7 @@ void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs,
                 q.sq = ptr[3];
                 q.g2 = (double*)base + j;
                 q.D = ptr[4];
+                q.prev = ptr[10];
                 for (int k = 0; k < 5; ++k) (*scratch)[(size_t)j * 5 + k] = ptr[5 + k];
             }
         }
@@ -877,25 +892,36 @@ void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs,
             const double rj = g.z2 > 0 ? std::sqrt(g2[j] / g.z2) : std::sqrt(g2[j]);
             res[j] = rj;
             if (g.info && it < 32) g.info->ne_history[it] = rj;
-            // the last correction made no progress, or the loop is done
-            const bool stop = !(rj > ir_tol) || it >= ir_max_iter || (it >= 1 && !(rj < prev[j]));
+            // the last correction made no progress (it is taken back, as in
+            // pinv_solve_impl), or the loop is done
+            const bool noprog = it >= 1 && !(rj < prev[j]);
+            const bool stop = noprog || !(rj > ir_tol) || it >= ir_max_iter;
             if (!stop) {
                 prev[j] = rj;
                 any = true;
                 continue;
             }
             active[j] = 0;
-            if (g.info) {
-                g.info->iterations = it;
-                g.info->ne_residual = rj;
+            int kept = it;
+            double rk = rj;
+            if (noprog) {
+                ELM_HIP_TRY(hipMemcpy2DAsync(g.beta, (size_t)g.ldbeta * sizeof(double), rd[j].prev,
+                                             (size_t)g.m * sizeof(double), (size_t)g.m * sizeof(double),
+                                             (size_t)g.f->L, hipMemcpyDeviceToDevice, s));
+                kept = it - 1;
+                rk = prev[j];
             }
-            if (rj > ir_tol) {
+            if (g.info) {
+                g.info->iterations = kept;
+                g.info->ne_residual = rk;
+            }
+            if (rk > ir_tol) {
                 g.status = ELM_ERR_NO_CONVERGENCE;
                 char msg[160];
                 std::snprintf(msg, sizeof(msg),
                               "refinement stopped after %d iterations at relative normal-equation "
                               "residual %.3e > ir_tol %.3e",
-                              it, rj, ir_tol);
+                              kept, rk, ir_tol);
                 g.msg = msg;
             }
         }

@@ -404,9 +404,9 @@ void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
 void launch_hidden_output(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
                           int64_t ldh, const double* beta, int64_t ldb, double* Y, int64_t ldy,
                           int32_t* labels);
-//   beta += delta, elementwise over L x m
+//   beta += delta, elementwise over L x m; prev (ld cols) receives beta before it
 void launch_axpy_mat(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx,
-                     double* Y, int64_t ldy);
+                     double* Y, int64_t ldy, double* prev);
 
 // ---------------------------------------------------------------------------
 // Grouped launches over the problems of a batch.  Blocks [start[j],
@@ -625,13 +625,14 @@ struct RefineDesc {
     double* sq = nullptr;       // refine_sq_doubles(L, m)
     double* g2 = nullptr;       // ||G||_F^2
     double* D = nullptr;        // L x m, ld m: the correction added to beta
+    double* prev = nullptr;     // L x m, ld m: beta before the last correction
 };
 enum class RefinePass {
     ROWS_DOT,   // E = T - H beta
     COLS_DOT,   // part = column-chunk partials of H^T E
     HT_REDUCE,  // G = sum of the partials, per-block sums of squares
     SUM,        // g2 = ||G||_F^2
-    AXPY        // beta += D
+    AXPY        // prev = beta, beta += D
 };
 // blocks of problem q in a launch whose largest m is maxm
 int64_t refine_group_blocks(RefinePass pass, const RefineDesc& q, int maxm);

@@ -355,13 +355,18 @@ __device__ __forceinline__ void sum_body(int64_t n, const double* __restrict__ x
     if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// Y += X; the previous Y is kept in B (ld cols), so that a correction that
+// did not lower the residual can be taken back exactly.
 __device__ __forceinline__ void axpy_mat_body(int64_t bx, int64_t rows, int64_t cols,
                                      const double* __restrict__ X, int64_t ldx,
-                                     double* __restrict__ Y, int64_t ldy) {
+                                     double* __restrict__ Y, int64_t ldy,
+                                     double* __restrict__ B) {
     const int64_t e = bx * blockDim.x + threadIdx.x;
     if (e < rows * cols) {
         const int64_t i = e / cols, j = e % cols;
-        Y[i * ldy + j] += X[i * ldx + j];
+        const double y = Y[i * ldy + j];
+        B[e] = y;
+        Y[i * ldy + j] = y + X[i * ldx + j];
     }
 }
 
@@ -398,8 +403,9 @@ __global__ __launch_bounds__(NT) void sum_kernel(int64_t n, const double* __rest
 }
 
 __global__ void axpy_mat_kernel(int64_t rows, int64_t cols, const double* __restrict__ X,
-                                int64_t ldx, double* __restrict__ Y, int64_t ldy) {
-    axpy_mat_body(blockIdx.x, rows, cols, X, ldx, Y, ldy);
+                                int64_t ldx, double* __restrict__ Y, int64_t ldy,
+                                double* __restrict__ B) {
+    axpy_mat_body(blockIdx.x, rows, cols, X, ldx, Y, ldy, B);
 }
 
 // ---------------------------------------------------------------------------
@@ -442,7 +448,7 @@ __global__ __launch_bounds__(NT) void sum_grouped(const RefineDesc* __restrict__
 __global__ void axpy_grouped(const RefineDesc* __restrict__ d, GroupSched g) {
     int64_t lb;
     const RefineDesc& q = d[group_problem(g, lb)];
-    axpy_mat_body(lb, q.L, q.m, q.D, q.m, q.beta, q.ldbeta);
+    axpy_mat_body(lb, q.L, q.m, q.D, q.m, q.beta, q.ldbeta, q.prev);
 }
 
 }  // namespace
@@ -662,9 +668,10 @@ void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
 // Returns false when L or m is beyond what the register-resident partials hold.
 
 void launch_axpy_mat(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx,
-                     double* Y, int64_t ldy) {
+                     double* Y, int64_t ldy, double* prev) {
     if (rows <= 0 || cols <= 0) return;
-    axpy_mat_kernel<<<(unsigned)cdiv(rows * cols, 256), 256, 0, s>>>(rows, cols, X, ldx, Y, ldy);
+    axpy_mat_kernel<<<(unsigned)cdiv(rows * cols, 256), 256, 0, s>>>(rows, cols, X, ldx, Y, ldy,
+                                                                      prev);
     ELM_LAUNCH_CHECK();
 }
 

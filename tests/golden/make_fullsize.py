@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Write the full-size expected values used by tests/test_gpu_golden.py.
+
+Calls only the FP64 CPU oracle (`oracle/`) and the seeded input generators
+(`elm_workloads`); nothing here touches the GPU library.  For each workload
+at its full size it stores the oracle's rank r and beta = H^+ T (eq. 5, by
+the rank-based route of Section 3 with two FP64 refinement steps), plus the
+independent checks that pin the oracle at that size:
+
+* digits_like (N=60000, d=784, L=2000, full rank): the textbook least-squares
+  solution by LAPACK's SVD-based solver on H itself (no Gram), eq. (5);
+* mixture_rankdef (N=100000, d=54, L=5000, 500 duplicated nodes, rank 4500):
+  the duplicated-column closed form (an SVD of the distinct columns, accurate
+  to about kappa * eps rather than kappa^2 * eps);
+* smooth_regression (N=500000, d=128, L=10000, full rank): the oracle with the
+  Gram streamed over row chunks (FP64 H would take 40 GB), and kappa from the
+  Gram's eigenvalues;
+* batch_sweep (256 ELMs, seed 5): per ELM the oracle's r and beta, kappa_r and
+  the closed form's beta.
+
+kappa_r (the condition number of H restricted to its rank) is stored beside
+every beta: kappa_r^2 * 2^-53 is the scale of the rounding differences two
+correct FP64 normal-equation solvers may show.
+
+Usage: python tests/golden/make_fullsize.py [name ...]   (default: all)
+Output: tests/golden/fullsize_<name>.npz (float64 / int64 arrays, no pickles).
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import elm_workloads as wl  # noqa: E402
+import oracle as O  # noqa: E402
+from oracle.validators import dedup_closed_form  # noqa: E402
+
+EPS = 2.0 ** -53
+
+
+def log(msg):
+    print(f"[golden] {msg}", flush=True)
+
+
+def kappa_from_singular_values(s: np.ndarray, r: int) -> float:
+    return float(s[0] / s[r - 1]) if r > 0 else 1.0
+
+
+def dedup_with_kappa(H, T, groups):
+    """Closed form for duplicated columns and kappa_r of H.  The nonzero
+    singular values of H = (H_u D^1/2)(D^-1/2 E) are those of H_u D^1/2,
+    since D^-1/2 E has orthonormal rows."""
+    beta = dedup_closed_form(H, T, groups)
+    n_u = int(groups.max()) + 1
+    first = np.full(n_u, -1)
+    for j, g in enumerate(groups):
+        if first[g] < 0:
+            first[g] = j
+    mult = np.bincount(groups, minlength=n_u).astype(np.float64)
+    s = np.linalg.svd(H[:, first] * np.sqrt(mult)[None, :], compute_uv=False)
+    r = int(np.count_nonzero(s > s[0] * max(H.shape[0], n_u) * 2.0 ** -52))
+    return beta, kappa_from_singular_values(s, r), r
+
+
+def out_path(name):
+    return os.path.join(HERE, f"fullsize_{name}.npz")
+
+
+def make_digits():
+    p = wl.digits_like()
+    t0 = time.perf_counter()
+    H = O.hidden(p.X, p.W, p.b)
+    beta, F = O.solve(H, p.T)
+    t1 = time.perf_counter()
+    ref, _, rank_ls, s = np.linalg.lstsq(H, p.T, rcond=None)
+    kappa = kappa_from_singular_values(s, rank_ls)
+    err_ls = O.rel_err(beta, ref)
+    log(f"digits_like: r {F.r} (lstsq rank {rank_ls}), kappa {kappa:.1f}, oracle vs lstsq {err_ls:.2e}, "
+        f"oracle {t1 - t0:.1f} s")
+    assert F.r == rank_ls == p.structural_rank
+    assert err_ls <= 1e-10
+    np.savez(out_path("digits_like"), rank=np.int64(F.r), beta=beta, beta_check=ref,
+             kappa=np.float64(kappa), check_err=np.float64(err_ls))
+
+
+def make_mixture():
+    p = wl.mixture_rankdef()
+    t0 = time.perf_counter()
+    H = O.hidden(p.X, p.W, p.b)
+    beta, F = O.solve(H, p.T)
+    t1 = time.perf_counter()
+    ref, kappa, r_svd = dedup_with_kappa(H, p.T, p.groups)
+    err = O.rel_err(beta, ref)
+    log(f"mixture_rankdef: r {F.r} (SVD of distinct columns {r_svd}), kappa {kappa:.1f}, "
+        f"kappa^2 eps {kappa * kappa * EPS:.1e}, oracle vs closed form {err:.2e}, oracle {t1 - t0:.1f} s")
+    assert F.r == r_svd == p.structural_rank
+    assert err <= max(1e-10, 10 * kappa * kappa * EPS)
+    np.savez(out_path("mixture_rankdef"), rank=np.int64(F.r), beta=beta, beta_check=ref,
+             kappa=np.float64(kappa), check_err=np.float64(err))
+
+
+def make_smooth():
+    p = wl.smooth_regression()
+    t0 = time.perf_counter()
+    M, Z = O.gram_streamed(p.X, p.W, p.b, p.T, chunk_rows=8192)
+    t1 = time.perf_counter()
+    log(f"smooth_regression: streamed Gram {t1 - t0:.0f} s")
+    F = O.rank_factor(O.ShapeOnly(p.N, p.L), M=M)
+    beta = O.apply_pinv(F, None, None, Z=Z)
+    t2 = time.perf_counter()
+    log(f"smooth_regression: rank step and beta {t2 - t1:.0f} s, r {F.r}")
+    for step in range(2):
+        g = O.ne_gradient_streamed(p.X, p.W, p.b, p.T, beta, chunk_rows=8192)
+        ne = float(np.linalg.norm(g) / np.linalg.norm(Z))
+        log(f"smooth_regression: NE residual before refinement step {step + 1}: {ne:.2e}")
+        beta = beta + O.apply_pinv(F, None, None, Z=g)
+    g = O.ne_gradient_streamed(p.X, p.W, p.b, p.T, beta, chunk_rows=8192)
+    ne = float(np.linalg.norm(g) / np.linalg.norm(Z))
+    ev = np.linalg.eigvalsh(M)
+    kappa = float(np.sqrt(ev[-1] / ev[0]))
+    t3 = time.perf_counter()
+    log(f"smooth_regression: final NE residual {ne:.2e}, kappa {kappa:.1f}, total {t3 - t0:.0f} s")
+    assert F.r == p.structural_rank
+    assert ne <= 1e-12
+    np.savez(out_path("smooth_regression"), rank=np.int64(F.r), beta=beta, kappa=np.float64(kappa),
+             ne_residual=np.float64(ne))
+
+
+def make_batch():
+    probs = wl.batch_sweep()
+    Ls = np.array([p.L for p in probs], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(Ls)]).astype(np.int64)
+    m = probs[0].m
+    beta_all = np.zeros((int(off[-1]), m))
+    check_all = np.zeros((int(off[-1]), m))
+    ranks = np.zeros(len(probs), dtype=np.int64)
+    kappas = np.zeros(len(probs))
+    check_err = np.zeros(len(probs))
+    t0 = time.perf_counter()
+    for e, p in enumerate(probs):
+        H = O.hidden(p.X, p.W, p.b)
+        beta, F = O.solve(H, p.T)
+        ref, kappa, r_svd = dedup_with_kappa(H, p.T, p.groups)
+        assert F.r == r_svd == p.structural_rank, (e, F.r, r_svd, p.structural_rank)
+        err = O.rel_err(beta, ref)
+        assert err <= max(1e-10, 10 * kappa * kappa * EPS), (e, err, kappa)
+        beta_all[off[e]:off[e + 1]] = beta
+        check_all[off[e]:off[e + 1]] = ref
+        ranks[e], kappas[e], check_err[e] = F.r, kappa, err
+    log(f"batch_sweep: 256 ELMs in {time.perf_counter() - t0:.0f} s; kappa {kappas.min():.0f}..{kappas.max():.0f}, "
+        f"oracle vs closed form max {check_err.max():.2e}")
+    np.savez(out_path("batch_sweep"), rank=ranks, offsets=off, beta=beta_all, beta_check=check_all,
+             kappa=kappas, check_err=check_err)
+
+
+MAKERS = {"digits_like": make_digits, "mixture_rankdef": make_mixture,
+          "batch_sweep": make_batch, "smooth_regression": make_smooth}
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(MAKERS)
+    for n in names:
+        MAKERS[n]()

@@ -1,6 +1,14 @@
 """GPU: the training path at the workloads' full sizes, in the configuration
-the benchmark times, checked through properties that hold at any size (the
-FP64 CPU oracle cannot form these Grams in test time):
+the benchmark times, against the FP64 oracle's stored results and through
+properties that hold at any size.
+
+The expected ranks and beta come from tests/golden/make_fullsize.py, which
+runs only the FP64 CPU oracle (minutes per workload, too long for test
+time) and stores r, beta and kappa_r for each; rank must be equal and beta
+within 1e-10 (FP64 form) or 1e-6 (low-precision Gram + FP64 refinement)
+relative, each error printed beside its bar and kappa_r^2 2^-53 (the
+scale of rounding differences two correct FP64 normal-equation solvers may
+show).  Besides:
 
 * rank: the structural rank of the planted node duplication;
 * beta solves the least-squares problem: the relative normal-equation
@@ -15,16 +23,40 @@ FP64 CPU oracle cannot form these Grams in test time):
   round-to-nearest-even of H.
 """
 import math
+import os
 
 import numpy as np
 import pytest
 import torch
 
 import elm_workloads as wl
+import oracle as O
 
 from gpu_helpers import bf16_rne, to_dev
 
 pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -53
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    """Stored oracle results of one full-size workload (plain float64/int64
+    arrays; loaded without pickles)."""
+    with np.load(os.path.join(GOLDEN, f"fullsize_{name}.npz")) as z:
+        return {k: z[k] for k in z.files}
+
+
+def check_against_golden(tag, beta, rank, g, tol):
+    err = O.rel_err(beta, g["beta"])
+    k2e = float(g["kappa"]) ** 2 * EPS
+    line = f"{tag}: rank {rank} (oracle {int(g['rank'])}), beta err vs oracle {err:.2e} (bar {tol:.0e}; " \
+           f"kappa_r {float(g['kappa']):.0f}, kappa_r^2 eps {k2e:.1e})"
+    if "beta_check" in g:
+        line += f", vs independent check {O.rel_err(beta, g['beta_check']):.2e}"
+    print(line)
+    assert rank == int(g["rank"])
+    assert err <= tol
 
 
 @pytest.fixture(scope="module")
@@ -91,6 +123,7 @@ def test_full_size_precision_form(elm):
     print(f"C4: rank {res.rank}, gram {res.info['gram_dtype']}, certified {fi['certified_full_rank']}, "
           f"library NE {res.info['ne_residual']:.3e}, torch NE {ne:.3e}, its {res.info['iterations']}")
     assert res.rank == p.structural_rank == 10000
+    check_against_golden("C4 bf16", res.beta.cpu().numpy(), res.rank, golden("smooth_regression"), 1e-6)
     assert res.info["gram_dtype"] == "bf16" and res.info["escalations"] == 0
     assert fi["reliable"]
     assert res.info["ne_residual"] <= 1e-10
@@ -124,6 +157,8 @@ def test_full_size_rank_deficient_mixture(elm, precision):
     print(f"C3 {precision}: rank {res.rank} (structural {p.structural_rank}), gram {res.info['gram_dtype']}, "
           f"NE {ne:.3e}, duplicate spread {spread:.2e}, its {res.info['iterations']}")
     assert res.rank == p.structural_rank == 4500
+    check_against_golden(f"C3 {precision}", beta, res.rank, golden("mixture_rankdef"),
+                         1e-10 if precision == "fp64" else 1e-6)
     assert not res.info["factor"]["certified_full_rank"]
     assert ne <= 1e-10
     assert spread <= 1e-9
@@ -143,8 +178,55 @@ def test_full_size_digits_fp32_form(elm):
     acc = float((res.labels.cpu().numpy() == p.labels).mean())
     print(f"C2 fp32: rank {res.rank}, NE {ne:.3e}, its {res.info['iterations']}, training accuracy {acc:.4f}")
     assert res.rank == p.structural_rank == 2000
+    check_against_golden("C2 fp32", res.beta.cpu().numpy(), res.rank, golden("digits_like"), 1e-6)
     assert res.info["gram_dtype"] == "fp32"
     assert ne <= 1e-10
     # labels are the arg-max of the returned outputs (lowest index on ties)
     Y = res.Y.cpu().numpy()
     assert np.array_equal(res.labels.cpu().numpy(), np.argmax(Y, axis=1))
+
+
+def test_full_size_fp64_form_regression(elm):
+    """N=500000, d=128, L=10000, m=4 in the plain FP64 form (FP64 Gram), the
+    form the benchmark times beside the precision form."""
+    p = wl.smooth_regression()
+    X, W, b, T = to_dev(p.X), to_dev(p.W), to_dev(p.b), to_dev(p.T)
+    H64 = torch.empty((p.N, p.L), dtype=torch.float64, device=X.device)
+    res = elm.train(X, W, b, T, precision="fp64", ir_tol=1e-10, H64=H64)
+    torch.cuda.synchronize()
+    print(f"C4 fp64: NE {res.info['ne_residual']:.2e}, its {res.info['iterations']}")
+    assert res.info["gram_dtype"] == "fp64" and res.info["ne_residual"] <= 1e-10
+    check_against_golden("C4 fp64", res.beta.cpu().numpy(), res.rank, golden("smooth_regression"), 1e-10)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32", "fp64"])
+def test_full_size_batch_sweep(elm, precision):
+    """The 256-ELM hidden-size sweep (N log-U[1000, 50000], L log-U[64, 2048],
+    d=32, m=5, 10% duplicated nodes) in one elm_train_batched call, as the
+    benchmark runs it (refinement to NE residual 1e-10): every ELM's rank and
+    beta against the oracle's."""
+    probs = wl.batch_sweep()
+    g = golden("batch_sweep")
+    dev = [tuple(to_dev(a) for a in (q.X, q.W, q.b, q.T)) for q in probs]
+    betas, infos, stats = elm.train_batched(dev, precision=precision, ir_tol=1e-10, check=False)
+    torch.cuda.synchronize()
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    off = g["offsets"]
+    worst = (0.0, -1)
+    bad = []
+    for e, q in enumerate(probs):
+        ref = g["beta"][off[e]:off[e + 1]]
+        err = O.rel_err(betas[e].cpu().numpy(), ref)
+        if err > worst[0]:
+            worst = (err, e)
+        if infos[e]["rank"] != int(g["rank"][e]) or err > tol or stats[e] != 0:
+            bad.append((e, q.N, q.L, infos[e]["rank"], int(g["rank"][e]), err, float(g["kappa"][e]),
+                        stats[e], infos[e]["gram_dtype"], infos[e]["iterations"]))
+    e = worst[1]
+    print(f"C5 {precision}: worst beta err {worst[0]:.2e} (bar {tol:.0e}) at ELM {e} (N={probs[e].N}, "
+          f"L={probs[e].L}, kappa_r {float(g['kappa'][e]):.0f}, kappa_r^2 eps "
+          f"{float(g['kappa'][e]) ** 2 * EPS:.1e}, oracle vs closed form {float(g['check_err'][e]):.1e}); "
+          f"gram dtypes {sorted(set(i['gram_dtype'] for i in infos))}")
+    for b_ in bad:
+        print("  outside the bar:", b_)
+    assert not bad
