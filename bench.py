@@ -11,8 +11,15 @@ training-set outputs H beta with their arg-max labels (taken from the last
 refinement pass, which evaluates H beta for the final beta).
 
 Prints ONE JSON line.  Extra keys: the FP64 form's time and the speedup at
-equal residual, per-stage times, the Gram kernel's roofline, and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+equal residual, the FP16 form on the same workload, per-stage times, the Gram
+kernel's roofline, trainings/s of the other named workloads (the tiny FP64
+problem, the digits-like FP32 form, the rank-deficient mixture in the FP64 and
+FP32 forms, the 256-ELM hidden-size sweep), and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+`--stage NAME` instead runs one stage of the path alone `--reps` times (after
+one untimed call) and prints its wall times: the command the rocprofv3 kernel
+and counter summaries are taken with.
 """
 import argparse
 import hashlib
@@ -45,6 +52,14 @@ def parse():
     ap.add_argument("--cpu-nodes", type=int, default=4000, help="oracle sample: nodes for the factor")
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed batches of the 256-ELM hidden-size sweep (0 = skip)")
+    ap.add_argument("--fp16-steps", type=int, default=2,
+                    help="timed FP16-form trainings on the same workload (0 = skip)")
+    ap.add_argument("--config-steps", type=int, default=3,
+                    help="timed trainings per form of the other named workloads (0 = skip)")
+    ap.add_argument("--stage", default=None,
+                    choices=["hidden", "gram", "gram64", "rank", "refine", "predict", "copy", "batch"],
+                    help="run one stage alone (for profiling) instead of the benchmark")
+    ap.add_argument("--reps", type=int, default=1, help="timed repetitions of --stage")
     return ap.parse_args()
 
 
@@ -84,6 +99,9 @@ def cpu_baseline(prob, rows, nodes):
     t_full = t_rows * (N / rows) + t_factor * (L / nodes) ** 3
     return {
         "value": 1.0 / t_full, "unit": "trainings/s", "cores": int(cores), "kind": "oracle",
+        "extrapolated": True,
+        "measured_s": {"rows_part": round(t_rows, 3), "factor_part": round(t_factor, 3)},
+        "scale": {"rows_part": N / rows, "factor_part": (L / nodes) ** 3},
         "sample": (f"FP64 oracle on the first {rows} of {N} rows at full L={L} (hidden, Gram, 2 residual "
                    f"passes: {t_rows:.2f} s, scaled x{N / rows:.0f}) plus its rank step and beta "
                    f"assembly at {nodes} nodes ({t_factor:.2f} s, scaled x(L/{nodes})^3); "
@@ -132,6 +150,123 @@ def bench_batch(args, elm, torch, wl, dev):
     del H64s, betas, dev_probs
     torch.cuda.empty_cache()
     return out
+
+
+def _median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def _stage_ms(stages, reps):
+    return {k: round(v[0] / reps, 3) for k, v in stages.items() if v[1]}
+
+
+def bench_configs(args, elm, torch, wl, dev):
+    """Trainings/s of the other named workloads, each form timed over
+    `config_steps` trainings (median) after one untimed training, with the
+    per-stage device times averaged over the timed ones:
+      tiny_fp64        N=2000, d=20, L=200 (rank 160), m=2, FP64 form;
+      digits_like      N=60000, d=784 (80% zeros), L=2000, m=10, FP32 form;
+      mixture_rankdef  N=100000, d=54, L=5000 (rank 4500), m=7, FP64 and FP32
+                       forms (rank-deficient: the greedy pivoted Cholesky,
+                       256-wide panels at this order, is what the rank stage
+                       times here)."""
+    specs = [("tiny_fp64", wl.tiny_fp64, ("fp64",), 20),
+             ("digits_like", wl.digits_like, ("fp32",), args.config_steps),
+             ("mixture_rankdef", wl.mixture_rankdef, ("fp64", "fp32"), args.config_steps)]
+    out = {}
+    for name, gen, forms, reps in specs:
+        p = gen()
+        X, W, b, T = (torch.from_numpy(a).to(dev) for a in (p.X, p.W, p.b, p.T))
+        H64 = torch.empty((p.N, p.L), dtype=torch.float64, device=dev)
+        entry = {"N": p.N, "d": p.d, "L": p.L, "m": p.m}
+        for form in forms:
+            Hlp = None if form == "fp64" else torch.empty((p.L, p.N), dtype=torch.float32, device=dev)
+            res = elm.train(X, W, b, T, precision=form, ir_tol=1e-10, H64=H64, Hlp=Hlp, check_convergence=False)
+            torch.cuda.synchronize()
+            elm.profile_enable(True)
+            ts = []
+            for _ in range(max(reps, 1)):
+                t0 = time.perf_counter()
+                res = elm.train(X, W, b, T, precision=form, ir_tol=1e-10, H64=H64, Hlp=Hlp,
+                                check_convergence=False)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            stages = elm.profile_read()
+            elm.profile_enable(False)
+            ms = _median(ts) * 1e3
+            fi = res.info["factor"]
+            entry[form] = {"ms_per_training": round(ms, 3), "trainings_per_s": round(1e3 / ms, 2),
+                           "rank": res.rank, "certified_full_rank": fi["certified_full_rank"],
+                           "gram_dtype_used": res.info["gram_dtype"], "ne_residual": res.info["ne_residual"],
+                           "refine_iterations": res.info["iterations"],
+                           "stage_ms_per_training": _stage_ms(stages, len(ts))}
+            log(f"{name} {form}: {ms:.2f} ms, rank {res.rank}, NE {res.info['ne_residual']:.1e}, "
+                f"its {res.info['iterations']}")
+            del Hlp
+        out[name] = entry
+        del X, W, b, T, H64
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_stage(args):
+    """One stage of the path on the precision-form workload (or the batch
+    sweep), --reps times after one untimed call, for rocprofv3.  Stages:
+    hidden (FP64 H + BF16 copy), gram (BF16 Gram), gram64 (FP64 Gram), rank
+    (rank step + factor on the BF16 Gram), refine (factor and one refinement
+    pass), predict (Y = H beta), copy (a plain device copy of the FP64 H: the
+    reference that scales memory counters), batch (the 256-ELM sweep through
+    elm_train_batched, BF16 form)."""
+    import torch
+    import elm_workloads as wl
+    from paper_2011_02436_amd import elm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.stage == "batch":
+        probs = wl.batch_sweep()
+        dp = [tuple(torch.from_numpy(a).to(dev) for a in (q.X, q.W, q.b, q.T)) for q in probs]
+        H64s = [torch.empty((q.N, q.L), dtype=torch.float64, device=dev) for q in probs]
+        for i in range(args.reps + 1):
+            t0 = time.perf_counter()
+            elm.train_batched(dp, precision="bf16", ir_tol=1e-10, H64s=H64s, check=False)
+            torch.cuda.synchronize()
+            log(f"stage batch rep {i}: {(time.perf_counter() - t0) * 1e3:.2f} ms")
+        return
+    p = wl.smooth_regression(N=args.N, L=args.L)
+    X, W, b, T = (torch.from_numpy(a).to(dev) for a in (p.X, p.W, p.b, p.T))
+    H64 = torch.empty((p.N, p.L), dtype=torch.float64, device=dev)
+    Hb = torch.empty((p.L, p.N), dtype=torch.bfloat16, device=dev)
+    elm.elm_hidden(X, W, b, H=H64, Hlp=Hb)
+    torch.cuda.synchronize()
+
+    def run():
+        if args.stage == "hidden":
+            elm.elm_hidden(X, W, b, H=H64, Hlp=Hb)
+        elif args.stage == "gram":
+            elm.elm_gram(Hb, "node")
+        elif args.stage == "gram64":
+            elm.elm_gram(H64, "sample")
+        elif args.stage == "rank":
+            elm.elm_rank_factor(Hb, "node")
+        elif args.stage == "refine":
+            f = elm.elm_rank_factor(Hb, "node")
+            elm.elm_pinv_solve(f, T, H64, ir_tol=0.0, ir_max_iter=1, check_convergence=False)
+        elif args.stage == "predict":
+            beta = torch.zeros((p.L, p.m), dtype=torch.float64, device=dev)
+            elm.elm_predict_hidden(H64, beta)
+        elif args.stage == "copy":
+            dst = torch.empty_like(H64)
+            dst.copy_(H64)
+
+    run()
+    torch.cuda.synchronize()
+    for i in range(args.reps):
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        log(f"stage {args.stage} rep {i}: {(time.perf_counter() - t0) * 1e3:.2f} ms")
 
 
 # The paper's own RBP-ELM training times on GINA (N=3468, d=971), Table 1:
@@ -193,6 +328,9 @@ def main():
         print("bench.py measures one GPU only: the path has no multi-GPU execution "
               "(it would shard over samples with one Gram all-reduce). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.stage:
+        run_stage(args)
+        return
 
     import numpy as np
     import torch
@@ -289,7 +427,41 @@ def main():
                 "speedup_of_mixed": round(fp64_ms / ms_per_step, 3),
                 "beta_rel_diff_mixed_vs_fp64": diff}
 
+    # FP16 form on the same workload (FP16 copy of H in the BF16 copy's memory)
+    fp16 = None
+    if args.fp16_steps > 0 and args.precision != "fp16":
+        Hh = torch.empty((L, N), dtype=torch.float16, device=dev)
+        r16 = elm.train(X, W, b, T, precision="fp16", ir_tol=1e-10, H64=H64, Hlp=Hh, check_convergence=False)
+        torch.cuda.synchronize()
+        elm.profile_enable(True)
+        ht = []
+        for i in range(args.fp16_steps):
+            ts = time.perf_counter()
+            r16 = elm.train(X, W, b, T, precision="fp16", ir_tol=1e-10, H64=H64, Hlp=Hh,
+                            check_convergence=False, outputs=True)
+            torch.cuda.synchronize()
+            ht.append(time.perf_counter() - ts)
+            log(f"fp16 step {i}: {ht[-1] * 1e3:.1f} ms, rank {r16.rank}, NE residual "
+                f"{r16.info['ne_residual']:.2e}, its {r16.info['iterations']}")
+        st16 = elm.profile_read()
+        elm.profile_enable(False)
+        fp16_ms = sum(ht) / len(ht) * 1e3
+        g16_ms, g16_n = st16["gram"]
+        fp16 = {"ms_per_step": round(fp16_ms, 2), "trainings_per_s": round(1e3 / fp16_ms, 4),
+                "rank": r16.rank, "gram_dtype_used": r16.info["gram_dtype"],
+                "ne_residual": r16.info["ne_residual"], "refine_iterations": r16.info["iterations"],
+                "ne_history": r16.info["ne_history"],
+                "gram_tflops": round(gram_flops / (g16_ms / g16_n * 1e-3) / 1e12, 2) if g16_n else None,
+                "stage_ms_per_step": _stage_ms(st16, len(ht))}
+        del Hh, r16
+        torch.cuda.empty_cache()
+
     batch = bench_batch(args, elm, torch, wl, dev) if args.batch_steps > 0 else None
+    configs = None
+    if args.config_steps > 0:
+        del H64
+        torch.cuda.empty_cache()
+        configs = bench_configs(args, elm, torch, wl, dev)
     paper = bench_paper_shapes(elm, torch, wl, dev) if args.batch_steps > 0 else None
 
     cpu = None
@@ -298,6 +470,9 @@ def main():
         cpu = cpu_baseline(prob, min(args.cpu_rows, N), min(args.cpu_nodes, L))
         log(f"cpu baseline {time.perf_counter() - t0:.1f} s: {cpu['sample']}")
 
+    certified = bool(info_lp["factor"]["certified_full_rank"])
+    rank_path = ("certified full rank: unpivoted blocked Cholesky whose inverse-factor rows bound every "
+                 "greedy pivot above the threshold" if certified else "greedy diagonally pivoted Cholesky")
     out = {
         "metric": METRIC,
         "value": round(1e3 / ms_per_step, 4),
@@ -312,8 +487,9 @@ def main():
         "dtype": f"{args.precision}+f64",
         "data": "synthetic",
         "config": {"workload": f"smooth_regression N={N} d={prob.d} L={L} m={m}, {args.precision} Gram "
-                               f"+ FP64 pivoted Cholesky + FP64 refinement to NE residual 1e-10, "
-                               f"plus training-set outputs and labels",
+                               f"+ FP64 rank decision ({rank_path}) + FP64 refinement to NE residual "
+                               f"1e-10, plus training-set outputs and labels",
+                   "rank_path": rank_path,
                    "N": N, "d": prob.d, "L": L, "m": m, "precision": args.precision},
         "rank": rank_lp,
         "ne_residual": info_lp["ne_residual"],
@@ -340,7 +516,9 @@ def main():
         "gram_schedule": dict(tuned, chosen_by="elm_autotune_gram") if tuned else None,
         "stage_ms_per_step": stage_ms_per_step,
         "fp64_form": fp64,
+        "fp16_form": fp16,
         "batch_sweep": batch,
+        "other_workloads": configs,
         "paper_context": paper,
         "cpu_baseline": cpu,
     }

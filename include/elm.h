@@ -174,6 +174,35 @@ elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t 
 elm_status elm_autotune_gram(elm_handle* h, int64_t N, int64_t L, const void* Hn, int64_t ldn,
                              elm_dtype dt, int32_t* splits_out, double* ms_out);
 
+/* Grow a factor by new hidden nodes: the incremental form of the rank step
+ * for a hidden-size sweep (adding nodes to a trained network, as the
+ * incremental ELM variants the paper's introduction surveys do), reusing the
+ * smaller layer's factorisation.
+ *
+ * f: a factor of the FP64 column Gram H^T H of an N x L0 hidden matrix H (from
+ * elm_rank_factor on FP64 sample-major H with N >= L0, or an earlier
+ * elm_factor_grow).  H64: the grown FP64 sample-major hidden matrix H' = [H Hn]
+ * (N x L, ld ldh64 >= L, L > L0, N >= L) whose first L0 columns are that H.
+ * Only the new Gram blocks H^T Hn and Hn^T Hn are formed (2 N L0 (L - L0) +
+ * N (L - L0)^2 flops instead of N L^2); f's accepted pivots stay first, the
+ * rows of its R extend over the new columns by a triangular solve, and the
+ * greedy diagonal pivoting continues on the Schur complement of the new
+ * columns (f's rejected positions cannot become pivots: their Schur
+ * diagonals are already below the threshold and only decrease).  The
+ * threshold is elm_rank_factor's for the grown shape (tau_rel as there).
+ * When f's decision would not stand under it (an accepted pivot at or below
+ * the grown threshold, or a rejected one above), H' is factored from scratch
+ * instead.  Either way the rank and beta = H'^+ T (through elm_pinv_solve)
+ * are those of elm_rank_factor on H'; the pivot order may differ.
+ * *out receives a new library-owned factor (f is unchanged); rank (host, may
+ * be NULL) its rank; grown (host, may be NULL) 1 when it was grown, 0 when
+ * factored from scratch.  Synchronises the stream.
+ * Errors: INVALID_ARG; SHAPE (N differs from f's, L <= L0, ldh64);
+ * UNSUPPORTED (f not of an FP64 column Gram, N < L); NOT_PSD; ALLOC; HIP. */
+elm_status elm_factor_grow(elm_handle* h, const elm_factor* f, int64_t N, int64_t L,
+                           const double* H64, int64_t ldh64, double tau_rel,
+                           elm_factor** out, int64_t* rank, int32_t* grown);
+
 /* r of a factor (host read, no synchronisation needed). */
 elm_status elm_factor_rank(const elm_factor* f, int64_t* rank);
 
@@ -238,10 +267,18 @@ elm_status elm_factor_destroy(elm_factor* f);
  * beta_0 = H^+ T through the factor; then, while the relative normal-equation
  * residual ||H^T (T - H beta)||_F / ||H^T T||_F exceeds ir_tol and fewer
  * than ir_max_iter corrections were made, beta += H^+ (T - H beta) with H^+
- * applied through the (possibly low-precision-derived) factor; the loop also
- * stops when a correction did not lower the residual, and that correction is
- * taken back (beta is then the best iterate, whose residual is reported, and
- * `iterations` counts the corrections kept).  ir_max_iter = 0 gives beta_0 and
+ * applied through the (possibly low-precision-derived) factor.  With
+ * ir_max_iter >= 1 at least one correction is made whatever the first
+ * residual: beta_0's residual can sit at its rounding floor while its forward
+ * error is about kappa^2 eps (kappa the condition number of H on its rank),
+ * and the first correction removes that.  The loop also
+ * stops when a correction did not lower the residual.  A correction that
+ * raised it more than fourfold diverged and is taken back (beta is then the
+ * previous iterate); a smaller rise is rounding noise at the residual's
+ * floor, and that correction is kept (near the floor a correction still
+ * removes forward error that the residual does not show).  The reported
+ * residual is always that of the returned beta, and `iterations` counts the
+ * corrections kept.  ir_max_iter = 0 gives beta_0 and
  * skips the residual.  ir_tol must be in [0, 1).
  * info (host, may be NULL) receives rank, iterations and residuals.
  * Synchronises once per refinement iteration.
@@ -252,6 +289,34 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m,
                           const double* H64, int64_t ldh64,
                           double ir_tol, int32_t ir_max_iter,
                           double* beta, int64_t ldbeta, elm_solve_info* info);
+
+/* The paper's own block form of the solve (Section 3, eqs. 13-23; algorithm
+ * steps 5-9) for a hidden matrix of full column rank.  The columns, in the
+ * order piv (device int32 array of L original indices; NULL = identity), are
+ * split as H P = [H1 H2] with H1 the first `split` of them (1 <= split <= L)
+ * and H2 the other L - split, and
+ *   A = H2^T H2 (eq. 20),  B = A^-1 H2^T T (eq. 21),
+ *   D = H1^T C H1 with C = I - H2 A^-1 H2^T (eqs. 22-23),
+ *   beta1 = D^-1 H1^T (T - H2 B),  beta2 = B - A^-1 H2^T H1 beta1 (eq. 19,
+ *   read with the transpose on H1 that the printed eq. 19 omits),
+ *   beta[piv] = [beta1; beta2] (eq. 7's block order),
+ * all in FP64.  Every block product is taken from the Gram M = H^T H and
+ * Z = H^T T, so the N x N matrix C is never formed (D = M11 - M12 A^-1 M21).
+ * H64: FP64 sample-major N x L (ld ldh64 >= L), N >= L; T: N x m FP64 (ld
+ * ldt >= m), 1 <= m <= 64.  M (may be NULL): the FP64 Gram H^T H (L x L, ld
+ * ldm >= L, e.g. from elm_gram on H64); when NULL it is formed here in the
+ * handle's workspace.  beta: L x m FP64 (ld ldbeta >= m).  For a rank-
+ * deficient H the block form has no solution (A or D is singular); use
+ * elm_rank_factor and elm_pinv_solve.  Synchronises the stream once.
+ * Errors: INVALID_ARG; SHAPE (N < L, leading dimensions); NOT_PSD when a
+ * pivot of the Cholesky factorisation of A or D is at or below the rank
+ * step's default threshold 16 (L + N) 2^-53 max_j M_jj (H is then not of full
+ * column rank to working precision) or the Gram has a non-finite diagonal;
+ * ALLOC; HIP. */
+elm_status elm_block_solve(elm_handle* h, int64_t N, int64_t L, int64_t m,
+                           const double* H64, int64_t ldh64, const double* T, int64_t ldt,
+                           const double* M, int64_t ldm, int64_t split, const int32_t* piv,
+                           double* beta, int64_t ldbeta);
 
 /* ------------------------------------------------------------------------ */
 /* The whole training (steps 2-9) with the precision policy.                 */

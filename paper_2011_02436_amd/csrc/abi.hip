@@ -128,6 +128,11 @@ elm_status guarded(elm_handle* h, F&& body) {
 
 void use_device(elm_handle* h) { ELM_HIP_TRY(hipSetDevice(h->device)); }
 
+// a nested entry point's failure, rethrown with its message
+void check_status(elm_handle* h, elm_status st) {
+    if (st != ELM_OK) throw Error{st, h->last_error};
+}
+
 #define REQUIRE(cond, st, msg) \
     do {                       \
         if (!(cond)) throw ::elm::Error{st, msg}; \
@@ -391,6 +396,47 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L, const void* H, i
     return rank_factor_impl(h, N, L, H, ldh, h_dt, layout, tau_rel, out, rank, nullptr);
 }
 
+elm_status elm_factor_grow(elm_handle* h, const elm_factor* f, int64_t N, int64_t L, const double* H64,
+                           int64_t ldh64, double tau_rel, elm_factor** out, int64_t* rank, int32_t* grown) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    elm_factor* g = nullptr;
+    elm_status st = elm::guarded(h, [&] {
+        REQUIRE(out, ELM_ERR_INVALID_ARG, "out must be non-null");
+        *out = nullptr;
+        REQUIRE(f && H64, ELM_ERR_INVALID_ARG, "f and H64 must be non-null");
+        REQUIRE(tau_rel < 1.0 && !std::isnan(tau_rel), ELM_ERR_INVALID_ARG, "tau_rel must be < 1");
+        REQUIRE(!f->transposed && f->gram_dtype == ELM_F64, ELM_ERR_UNSUPPORTED,
+                "growth needs a factor of the FP64 column Gram H^T H");
+        REQUIRE(N == f->N, ELM_ERR_SHAPE, "N differs from the factor's");
+        REQUIRE(L > f->L, ELM_ERR_SHAPE, "L must exceed the factor's number of nodes");
+        REQUIRE(N >= L, ELM_ERR_UNSUPPORTED, "growth keeps the column Gram: N >= L");
+        REQUIRE(ldh64 >= L, ELM_ERR_SHAPE, "ldh64 < L");
+        elm::use_device(h);
+        g = new elm_factor();
+        g->device = h->device;
+        bool ok;
+        {
+            elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
+            ok = elm::grow_factor(h->stream, f, N, L, H64, ldh64, tau_rel, g, h->ws);
+        }
+        if (!ok) {  // the old decision does not stand under the grown threshold
+            delete g;
+            g = nullptr;
+            elm::check_status(h, rank_factor_impl(h, N, L, H64, ldh64, ELM_F64, ELM_SAMPLE_MAJOR, tau_rel,
+                                                  &g, nullptr, nullptr));
+        }
+        if (grown) *grown = ok ? 1 : 0;
+        if (rank) *rank = g->r;
+        *out = g;
+        g = nullptr;
+    });
+    if (g) {
+        elm::free_factor_buffers(g);
+        delete g;
+    }
+    return st;
+}
+
 elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh, elm_dtype h_dt,
                     elm_layout layout, double* M, int64_t ldm) {
     if (!h) return ELM_ERR_INVALID_ARG;
@@ -536,6 +582,15 @@ namespace {
 // "ps_Z" / "ps_nrm" (the hidden-layer kernel can produce them on the fly).
 // Y / labels (optional): H beta and its row arg-max for the returned beta,
 // taken from the last residual pass (a separate pass when there is none).
+// A refinement correction after which the normal-equation residual exceeds
+// this many times the previous one has diverged and is taken back.  Near the
+// rounding floor the residuals of successive iterates differ by small
+// factors at random, and there a correction that does not lower the residual
+// is kept: the first corrections after an FP64 factor of an ill-conditioned
+// Gram remove a forward error of about kappa^2 eps that the residual (already
+// at its floor) does not show.
+constexpr double IR_ROLLBACK_RISE = 4.0;
+
 elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const double* T, int64_t ldt,
                            const double* H64, int64_t ldh64, double ir_tol, int32_t ir_max_iter,
                            double* beta, int64_t ldbeta, elm_solve_info* info, bool z_ready,
@@ -612,20 +667,27 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
         res = z2 > 0 ? std::sqrt(g2 / z2) : std::sqrt(g2);
         if (info && it < 32) info->ne_history[it] = res;
         if (it >= 1 && !(res < prev)) {
-            // the last correction made no progress: take it back, so beta is
-            // the best iterate and the reported residual is its own
-            ELM_HIP_TRY(hipMemcpy2DAsync(beta, (size_t)ldbeta * sizeof(double), Bprev,
-                                         (size_t)m * sizeof(double), (size_t)m * sizeof(double),
-                                         (size_t)L, hipMemcpyDeviceToDevice, s));
-            --it;
-            res = prev;
-            if (Y || labels) {
-                elm::StageScope sc(pr, ELM_STAGE_PREDICT, s);
-                elm::launch_hidden_output(s, N, L, m, H64, ldh64, beta, ldbeta, Y, ldy, labels);
+            // no progress: the loop ends.  A correction that raised the
+            // residual beyond IR_ROLLBACK_RISE times the previous one diverged
+            // and is taken back (beta is then the previous iterate, with its
+            // residual); a smaller rise is rounding noise at the floor, where
+            // the correction still removed the forward error the factor left
+            if (!(res <= IR_ROLLBACK_RISE * prev)) {
+                ELM_HIP_TRY(hipMemcpy2DAsync(beta, (size_t)ldbeta * sizeof(double), Bprev,
+                                             (size_t)m * sizeof(double), (size_t)m * sizeof(double),
+                                             (size_t)L, hipMemcpyDeviceToDevice, s));
+                --it;
+                res = prev;
+                if (Y || labels) {
+                    elm::StageScope sc(pr, ELM_STAGE_PREDICT, s);
+                    elm::launch_hidden_output(s, N, L, m, H64, ldh64, beta, ldbeta, Y, ldy, labels);
+                }
             }
             break;
         }
-        if (!(res > ir_tol) || it >= ir_max_iter) break;
+        // at least one correction: the first solve's residual can be at its
+        // floor while its forward error is about kappa^2 eps
+        if ((it >= 1 && !(res > ir_tol)) || it >= ir_max_iter) break;
         prev = res;
         {
             elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
@@ -892,10 +954,10 @@ void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs,
             const double rj = g.z2 > 0 ? std::sqrt(g2[j] / g.z2) : std::sqrt(g2[j]);
             res[j] = rj;
             if (g.info && it < 32) g.info->ne_history[it] = rj;
-            // the last correction made no progress (it is taken back, as in
-            // pinv_solve_impl), or the loop is done
+            // the last correction made no progress (taken back when it
+            // diverged, as in pinv_solve_impl), or the loop is done
             const bool noprog = it >= 1 && !(rj < prev[j]);
-            const bool stop = noprog || !(rj > ir_tol) || it >= ir_max_iter;
+            const bool stop = noprog || (it >= 1 && !(rj > ir_tol)) || it >= ir_max_iter;
             if (!stop) {
                 prev[j] = rj;
                 any = true;
@@ -904,7 +966,7 @@ void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs,
             active[j] = 0;
             int kept = it;
             double rk = rj;
-            if (noprog) {
+            if (noprog && !(rj <= IR_ROLLBACK_RISE * prev[j])) {
                 ELM_HIP_TRY(hipMemcpy2DAsync(g.beta, (size_t)g.ldbeta * sizeof(double), rd[j].prev,
                                              (size_t)g.m * sizeof(double), (size_t)g.m * sizeof(double),
                                              (size_t)g.f->L, hipMemcpyDeviceToDevice, s));
@@ -963,6 +1025,48 @@ elm_status elm_pinv_solve(elm_handle* h, const elm_factor* f, int64_t m, const d
     return result;
 }
 
+elm_status elm_block_solve(elm_handle* h, int64_t N, int64_t L, int64_t m, const double* H64,
+                           int64_t ldh64, const double* T, int64_t ldt, const double* M, int64_t ldm,
+                           int64_t split, const int32_t* piv, double* beta, int64_t ldbeta) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(N >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N and L must be >= 1");
+        REQUIRE(m >= 1 && m <= 64, ELM_ERR_INVALID_ARG, "m must be in [1, 64]");
+        REQUIRE(H64 && T && beta, ELM_ERR_INVALID_ARG, "H64, T and beta must be non-null");
+        REQUIRE(split >= 1 && split <= L, ELM_ERR_INVALID_ARG, "split must be in [1, L]");
+        REQUIRE(N >= L, ELM_ERR_SHAPE, "the block form needs full column rank, so N >= L");
+        REQUIRE(ldh64 >= L && ldt >= m && ldbeta >= m, ELM_ERR_SHAPE,
+                "a leading dimension is smaller than its row length");
+        REQUIRE(!M || ldm >= L, ELM_ERR_SHAPE, "ldm < L");
+        elm::use_device(h);
+        hipStream_t s = h->stream;
+        // Z = H^T T (the same pass as the solves' right-hand sides)
+        double* Z = (double*)h->ws.get("bs_Z", (size_t)L * m * sizeof(double));
+        double* nrm = (double*)h->ws.get("bs_nrm", sizeof(double));
+        {
+            elm::StageScope sc(&h->prof, ELM_STAGE_RHS, s);
+            elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, h->ws);
+        }
+        if (!M) {
+            double* Mw = (double*)h->ws.get("bs_M", (size_t)L * L * sizeof(double));
+            elm::launch_gram_f64_cols(s, N, L, H64, ldh64, Mw, L, h->ws);
+            M = Mw;
+            ldm = L;
+        }
+        // the rank step's default threshold: a pivot of A or D at or below
+        // 16 (L + N) 2^-53 max_j M_jj is a numerically dependent column
+        double* dmax = (double*)h->ws.get("bs_dmax", sizeof(double));
+        elm::launch_diag_max(s, L, M, ldm, dmax);
+        double hmax = 0.0;
+        ELM_HIP_TRY(hipMemcpyAsync(&hmax, dmax, sizeof(double), hipMemcpyDeviceToHost, s));
+        ELM_HIP_TRY(hipStreamSynchronize(s));
+        REQUIRE(std::isfinite(hmax), ELM_ERR_NOT_PSD, "the Gram has a non-finite diagonal");
+        const double thr = 16.0 * (double)(L + N) * std::ldexp(1.0, -53) * hmax;
+        elm::StageScope sc(&h->prof, ELM_STAGE_SOLVE, s);
+        elm::block_solve(s, L, m, split, M, ldm, Z, m, piv, thr, beta, ldbeta, h->ws);
+    });
+}
+
 }  // extern "C"
 
 namespace elm {
@@ -972,9 +1076,6 @@ namespace {
 // formed again one step up (16-bit -> FP32 -> FP64).
 elm_dtype next_gram_dtype(elm_dtype dt) { return dt == ELM_F32 ? ELM_F64 : ELM_F32; }
 
-void check_status(elm_handle* h, elm_status st) {
-    if (st != ELM_OK) throw Error{st, h->last_error};
-}
 
 }  // namespace
 }  // namespace elm

@@ -366,10 +366,10 @@ void launch_chol_inv_small_grouped(hipStream_t s, const MatDesc* d, const GroupS
 }
 
 void cholesky_inverse_small(hipStream_t s, int64_t q, double* A, int64_t lda, double* Ainv,
-                            int64_t ldi, int* flag) {
+                            int64_t ldi, int* flag, double thr) {
     if (q <= 0) return;
     if (q > CB) throw Error{ELM_ERR_INVALID_ARG, "cholesky_inverse_small: order above 128"};
-    potrf_block_kernel<<<1, CPT, 0, s>>>(A, lda, 0, (int)q, 0.0, Ainv, ldi, flag);
+    potrf_block_kernel<<<1, CPT, 0, s>>>(A, lda, 0, (int)q, thr, Ainv, ldi, flag);
     ELM_LAUNCH_CHECK();
 }
 

@@ -362,9 +362,9 @@ void cholesky_blocked(hipStream_t s, int64_t n, double* A, int64_t lda, double t
                       Workspace& ws, hipStream_t side = nullptr, hipEvent_t ev_main = nullptr,
                       hipEvent_t ev_side = nullptr);
 // q <= 128: A = U^T U in place (upper, zero below) and Ainv = U^-1 (q x q, ld
-// ldi), one workgroup; flag set at a pivot <= 0.  No synchronisation.
+// ldi), one workgroup; flag set at a pivot <= thr.  No synchronisation.
 void cholesky_inverse_small(hipStream_t s, int64_t q, double* A, int64_t lda, double* Ainv,
-                            int64_t ldi, int* flag);
+                            int64_t ldi, int* flag, double thr = 0.0);
 // 1 / max_j sum_k X[j][k]^2 over the rows of an upper triangular n x n X (ld
 // ldx); synchronises the stream once.
 double inv_max_row_sumsq(hipStream_t s, int64_t n, const double* X, int64_t ldx, Workspace& ws);
@@ -372,6 +372,22 @@ double inv_max_row_sumsq(hipStream_t s, int64_t n, const double* X, int64_t ldx,
 void launch_iota(hipStream_t s, int64_t n, int32_t* piv);
 
 // solve.hip: dense FP64 helpers for the factor and the pseudoinverse apply
+//   C (M x m, ld ldc) = alpha A B + beta C for A (M x K, ld lda) and a thin B
+//   (K x m, ld ldb, m <= 64); tri 1: A upper triangular (only k >= i read),
+//   2: A lower triangular (k <= i), 0: dense
+void rowprod(hipStream_t s, int64_t M, int64_t K, int64_t m, double alpha, const double* A, int64_t lda,
+             int tri, const double* B, int64_t ldb, double beta, double* C, int64_t ldc);
+//   B (Cn x R, ld R) = A^T for A (R x Cn, ld lda); returns B
+double* transposed_copy(hipStream_t s, int64_t R, int64_t Cn, const double* A, int64_t lda, double* B);
+//   dst[i][:] = src[idx[i]][:]  /  dst[idx[i]][:] = src[i][:]   (rows x cols)
+void gather_rows(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds,
+                 const int32_t* idx, double* dst, int64_t ldd);
+void scatter_rows(hipStream_t s, int64_t rows, int64_t cols, const double* src, int64_t lds,
+                  const int32_t* idx, double* dst, int64_t ldd);
+void zero_mat(hipStream_t s, int64_t rows, int64_t cols, double* A, int64_t lda);
+//   X = U^-1 for upper-triangular U (r x r); X must not alias U
+void trtri_upper(hipStream_t s, int64_t r, const double* U, int64_t ldu, double* X, int64_t ldx,
+                 Workspace& ws);
 // wait = false: no synchronisation; the positive-definiteness flag of the
 // Gram of G is left in f->pd_flag (a workspace word) for the solve to read.
 void build_factor_tail(hipStream_t s, elm_factor* f, Workspace& ws, bool wait = true);
@@ -385,6 +401,22 @@ void apply_pinv(hipStream_t s, const elm_factor* f, int64_t m, const double* rhs
 // factor 1 when the Gram of G is not positive definite; synchronises once.
 std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm_factor*>& fs,
                                             const std::vector<const double*>& Rorig, Workspace& ws);
+
+// block.hip: the block form of Section 3 (eqs. 19-23) for a full-column-rank
+// H split after `split` columns of the order piv (NULL: identity), from the
+// FP64 Gram M (L x L, ld ldm) and Z = H^T T (L x m, ld ldz); beta (L x m, ld
+// ldb).  Synchronises once; NOT_PSD when a pivot of A or D is <= thr.
+void block_solve(hipStream_t s, int64_t L, int64_t m, int64_t split, const double* M, int64_t ldm,
+                 const double* Z, int64_t ldz, const int32_t* piv, double thr, double* beta, int64_t ldb,
+                 Workspace& ws);
+
+// grow.hip: the factor g of H' = [H Hn] (N x L2 FP64 sample-major, ld ldh, its
+// first f->n columns the H of factor f: FP64 Gram, N >= L2) from f and the new
+// Gram blocks, keeping f's accepted pivots first.  Returns false (g untouched
+// beyond its scalar fields) when f's decision would not stand under the grown
+// threshold.  Synchronises.
+bool grow_factor(hipStream_t s, const elm_factor* f, int64_t N, int64_t L2, const double* H, int64_t ldh,
+                 double tau_rel, elm_factor* g, Workspace& ws);
 
 // refine.hip: streaming FP64 passes over sample-major H
 //   E = T - H beta  (N x m)

@@ -664,9 +664,8 @@ void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
     ELM_LAUNCH_CHECK();
 }
 
-// G = H^T (T - H beta) in one pass over H (beta = NULL: G = H^T T).
-// Returns false when L or m is beyond what the register-resident partials hold.
-
+// Y += X (rows x cols); prev (rows x cols, ld cols) receives the old Y, so a
+// correction that did not lower the residual can be taken back.
 void launch_axpy_mat(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx,
                      double* Y, int64_t ldy, double* prev) {
     if (rows <= 0 || cols <= 0) return;

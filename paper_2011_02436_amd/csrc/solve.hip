@@ -220,6 +220,8 @@ __global__ __launch_bounds__(256) void mat_grouped(const MatDesc* __restrict__ d
     }
 }
 
+}  // namespace
+
 void rowprod(hipStream_t s, int64_t M, int64_t K, int64_t m, double alpha, const double* A, int64_t lda,
              int tri, const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
     if (M <= 0) return;
@@ -308,6 +310,8 @@ void trtri_upper(hipStream_t s, int64_t r, const double* U, int64_t ldu, double*
         }
     }
 }
+
+namespace {
 
 // Y (q x m, ld m) <- S^-1 Y with S^-1 = Usinv Usinv^T (S = Us^T Us)
 void apply_s_inv(hipStream_t s, const elm_factor* f, int64_t m, double* Y, Workspace& ws) {

@@ -98,6 +98,8 @@ def _load():
                              ctypes.POINTER(i64)], i32),
         "elm_gram": ([vp, i64, i64, vp, i64, i32, i32, vp, i64], i32),
         "elm_factor_rank": ([vp, ctypes.POINTER(i64)], i32),
+        "elm_factor_grow": ([vp, vp, i64, i64, vp, i64, dbl, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                             ctypes.POINTER(i32)], i32),
         "elm_factor_pivots": ([vp, vp, ctypes.POINTER(i32)], i32),
         "elm_factor_destroy": ([vp], i32),
         "elm_factor_get_info": ([vp, ctypes.POINTER(FactorInfo)], i32),
@@ -108,6 +110,7 @@ def _load():
                        ctypes.POINTER(vp)], i32),
         "elm_pinv_solve": ([vp, vp, i64, vp, i64, vp, i64, dbl, i32, vp, i64,
                             ctypes.POINTER(SolveInfo)], i32),
+        "elm_block_solve": ([vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, i64, vp, vp, i64], i32),
         "elm_predict": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, vp],
                         i32),
         "elm_predict_hidden": ([vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp], i32),
@@ -127,9 +130,9 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", "elm_last_error",
-            "elm_hidden", "elm_gram", "elm_rank_factor", "elm_factor_rank", "elm_factor_pivots",
+            "elm_hidden", "elm_gram", "elm_rank_factor", "elm_factor_rank", "elm_factor_grow", "elm_factor_pivots",
             "elm_factor_destroy", "elm_factor_get_info", "elm_train", "elm_train_batched",
-            "elm_pinv_solve", "elm_predict", "elm_predict_hidden",
+            "elm_pinv_solve", "elm_block_solve", "elm_predict", "elm_predict_hidden",
             "elm_autotune_gram", "elm_set_option", "elm_get_option", "elm_profile_enable",
             "elm_profile_read"]
 
@@ -230,9 +233,10 @@ def elm_hidden(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor,
                             lpdt), "elm_hidden")
 
 
-def elm_gram(H: torch.Tensor, layout: str = "sample") -> torch.Tensor:
+def elm_gram(H: torch.Tensor, layout: str = "sample", M: Optional[torch.Tensor] = None) -> torch.Tensor:
     """The FP64 Gram (H^T H, or H H^T when N < L) of a sample-major FP64 H or a
-    node-major low-precision copy."""
+    node-major low-precision copy.  M: optional preallocated n x n float64
+    output."""
     h = handle()
     if layout == "sample":
         N, L = H.shape
@@ -241,7 +245,10 @@ def elm_gram(H: torch.Tensor, layout: str = "sample") -> torch.Tensor:
         L, N = H.shape
         lay = ELM_NODE_MAJOR
     n = min(N, L)
-    M = torch.empty((n, n), dtype=torch.float64, device=H.device)
+    if M is None:
+        M = torch.empty((n, n), dtype=torch.float64, device=H.device)
+    elif M.dtype != torch.float64 or M.shape[0] != n or M.shape[1] < n:
+        raise ValueError("M must be float64 with n rows and at least n columns")
     hp, ldh = _mat(H, "H")
     mp, ldm = _mat(M, "M")
     h.check(_lib.elm_gram(h.ptr, N, L, hp, ldh, _DT[H.dtype], lay, mp, ldm), "elm_gram")
@@ -304,6 +311,23 @@ def elm_rank_factor(H: torch.Tensor, layout: str = "sample", tau_rel: float = 0.
     return Factor(f, N, L, int(r.value))
 
 
+def elm_factor_grow(factor: Factor, H64: torch.Tensor, tau_rel: float = 0.0) -> Tuple[Factor, bool]:
+    """The factor of H' = [H Hn] grown from `factor` (of the FP64 column Gram of
+    H, the first columns of H64).  Returns (new factor, grown), grown False
+    when the library factored H' from scratch."""
+    h = handle()
+    N, L = H64.shape
+    if H64.dtype != torch.float64:
+        raise TypeError("H64 must be float64")
+    hp, ldh = _mat(H64, "H64")
+    out = ctypes.c_void_p()
+    r = ctypes.c_int64()
+    grown = ctypes.c_int32()
+    h.check(_lib.elm_factor_grow(h.ptr, factor.ptr, N, L, hp, ldh, tau_rel, ctypes.byref(out),
+                                 ctypes.byref(r), ctypes.byref(grown)), "elm_factor_grow")
+    return Factor(out, N, L, int(r.value)), bool(grown.value)
+
+
 def elm_pinv_solve(factor: Factor, T: torch.Tensor, H64: torch.Tensor, ir_tol: float = 1e-10,
                    ir_max_iter: int = 0, beta: Optional[torch.Tensor] = None,
                    check_convergence: bool = True):
@@ -328,6 +352,30 @@ def elm_pinv_solve(factor: Factor, T: torch.Tensor, H64: torch.Tensor, ir_tol: f
         st = ELM_OK
     h.check(st, "elm_pinv_solve")
     return beta, info.as_dict()
+
+
+def elm_block_solve(H64: torch.Tensor, T: torch.Tensor, split: int, M: Optional[torch.Tensor] = None,
+                    piv: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """beta by the paper's block form (eqs. 19-23) for a full-column-rank
+    sample-major FP64 H split after `split` columns of the order piv (int32
+    device tensor of L indices; None = identity).  M: optional FP64 Gram
+    H^T H (formed by the library when None)."""
+    h = handle()
+    N, L = H64.shape
+    m = T.shape[1]
+    if H64.dtype != torch.float64 or T.dtype != torch.float64:
+        raise TypeError("H64 and T must be float64")
+    hp, ldh = _mat(H64, "H64")
+    tp, ldt = _mat(T, "T")
+    mp, ldm = (None, 0) if M is None else _mat(M, "M")
+    if piv is not None and (piv.dtype != torch.int32 or piv.numel() != L or not piv.is_contiguous()):
+        raise ValueError("piv must be a contiguous int32 tensor of L entries")
+    pp = None if piv is None else ctypes.c_void_p(piv.data_ptr())
+    beta = torch.empty((L, m), dtype=torch.float64, device=H64.device)
+    bp, ldb = _mat(beta, "beta")
+    h.check(_lib.elm_block_solve(h.ptr, N, L, m, hp, ldh, tp, ldt, mp, ldm, split, pp, bp, ldb),
+            "elm_block_solve")
+    return beta
 
 
 def elm_predict(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, beta: torch.Tensor,

@@ -15,7 +15,7 @@ import elm_workloads as wl
 import oracle as O
 from oracle import validators as V
 
-from gpu_helpers import to_dev
+from gpu_helpers import check_fp64_beta, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -119,23 +119,41 @@ def test_train_escalation_matches_oracle_and_closed_form(elm):
     # (about 1e-5 and 2e-6 of the largest diagonal), so both are flagged and
     # the training ends on the FP64 Gram; r and beta must then be the
     # oracle's, and beta the duplicated-column closed form's.
+    # kappa_r is ~3200 here (kappa_r^2 eps 1.2e-9), so with uncorrelated
+    # targets beta's rounding sensitivity would exceed the 1e-10 bar for any
+    # FP64 solver.  The targets are a linear function of H plus 1e-3 noise
+    # instead: the least-squares residual is then small and the sensitivity is
+    # kappa eps + kappa^2 eps ||r|| / (||H|| ||beta||) ~ 5e-13.  The solve from
+    # the FP64 factor alone still carries a forward error of about
+    # kappa_r^2 eps (the Gram's rounding) while its normal-equation residual is
+    # already at its floor, so, as the oracle does, two refinement corrections
+    # are always applied (ir_tol = 0: the loop runs to ir_max_iter and reports
+    # that it did not reach 0).
     p = wl.random_problem(seed=109, N=4000, d=3, L=16, m=2, n_dup=2)
-    X, W, b, T = _dev(p)
     H = O.hidden(p.X, p.W, p.b)
-    ref, F = O.solve(H, p.T)
-    closed = V.dedup_closed_form(H, p.T, p.groups)
+    rng = np.random.default_rng(1109)
+    T_h = H @ rng.standard_normal((p.L, p.m)) + 1e-3 * rng.standard_normal((p.N, p.m))
+    X, W, b, _ = _dev(p)
+    T = to_dev(T_h)
+    ref, F = O.solve(H, T_h)
+    closed = V.dedup_closed_form(H, T_h, p.groups)
     s = np.linalg.svd(H[:, F.piv[:F.r]], compute_uv=False)
-    k2e = (s[0] / s[-1]) ** 2 * 2.0 ** -53
-    res = elm.train(X, W, b, T, precision="bf16", ir_tol=1e-12, ir_max_iter=8, check_convergence=False)
+    kappa = s[0] / s[-1]
+    resid = np.linalg.norm(T_h - H @ closed) / (s[0] * np.linalg.norm(closed))
+    sens = kappa * 2.0 ** -53 + kappa ** 2 * 2.0 ** -53 * resid
+    res = elm.train(X, W, b, T, precision="bf16", ir_tol=0.0, ir_max_iter=2, check_convergence=False)
     fi = res.info["factor"]
     err = O.rel_err(res.beta.cpu().numpy(), ref)
     err_c = O.rel_err(res.beta.cpu().numpy(), closed)
+    print(f"escalation: residuals {res.info['ne_history']}, corrections kept {res.info['iterations']}")
     print(f"escalation: {res.info['gram_dtype']} after {res.info['escalations']} (guard {res.info['guard']}), "
           f"rank {res.rank} (oracle {F.r}), last pivot {fi['last_pivot'] / fi['max_diag']:.2e} of max, "
-          f"err vs oracle {err:.2e}, vs closed form {err_c:.2e} (bar 1e-10; kappa^2 eps {k2e:.1e})")
+          f"err vs oracle {err:.2e}, vs closed form {err_c:.2e} (bar 1e-10; kappa_r {kappa:.0f}, "
+          f"sensitivity {sens:.1e}; oracle vs closed form {O.rel_err(ref, closed):.1e})")
     assert res.info["escalations"] == 2 and res.info["guard"] == 1
     assert res.info["gram_dtype"] == "fp64" and fi["reliable"]
     assert res.rank == F.r == p.structural_rank == 14
+    assert res.info["iterations"] == 2
     assert err <= 1e-10
     assert err_c <= 1e-10
 
@@ -239,15 +257,19 @@ def test_train_generically_rank_deficient_n_below_l(elm, precision):
     # N < L with fewer distinct nodes than samples: H H^T is singular without
     # duplicated rows, so its rejected pivots are rounding noise of the Gram;
     # the default threshold must reject them (the oracle pins the same case
-    # against the SVD)
+    # against the SVD).  kappa_r is ~8300 here (kappa_r^2 eps 7.6e-9): the
+    # oracle itself is 3.3e-10 from the SVD and closed-form solutions, so beta
+    # is held to the conditioning rule (closed form within kappa_r^2 eps).
     p = wl.random_problem(seed=138, N=399, d=32, L=443, m=3, n_dup=58)
     X, W, b, T = _dev(p)
     H = O.hidden(p.X, p.W, p.b)
     ref, F = O.solve(H, p.T)
+    closed = V.dedup_closed_form(H, p.T, p.groups)
+    sv = np.linalg.svd(H, compute_uv=False)
     res = elm.train(X, W, b, T, precision=precision, ir_tol=1e-12)
-    err = O.rel_err(res.beta.cpu().numpy(), ref)
-    print(f"{precision}: rank {res.rank} (oracle {F.r}) err {err:.2e} ne {res.info['ne_residual']:.1e}")
+    print(f"{precision}: rank {res.rank} (oracle {F.r}) ne {res.info['ne_residual']:.1e}, "
+          f"corrections {res.info['iterations']}")
     assert res.rank == F.r == 385
     assert res.info["transposed"] and res.info["gram_dtype"] == "fp64"
     assert res.info["ne_residual"] <= 1e-12
-    assert err <= 1e-10
+    check_fp64_beta(f"N < L {precision}", res.beta.cpu().numpy(), ref, closed, sv[0] / sv[F.r - 1])
