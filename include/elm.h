@@ -156,6 +156,27 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L,
 elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
                     elm_dtype h_dt, elm_layout layout, double* M, int64_t ldm);
 
+/* elm_gram for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, accepted inputs, kernels and result as elm_gram; the
+ * split-K partial tiles go to a static device array of 64 MiB per GPU
+ * (allocated with the library's code on each device it runs on and held
+ * until the process ends) instead of the handle's workspace, and this call
+ * allocates nothing.  The K splits are those of elm_gram's default rule
+ * (autotuned counts are not used), lowered until the partial tiles fit:
+ * 128 x 128 FP64 tiles (128 KiB each), FP32 (64 KiB) or 256 x 256 FP32
+ * partials of the 16-bit Gram (256 KiB), times the number of upper tiles,
+ * times the splits.  With the default rule's count the result is bitwise
+ * that of elm_gram; with fewer splits it differs by rounding only.
+ * Orders whose tiles do not fit even unsplit (about n > 5600 for the 16-bit
+ * and FP32 Grams, n > 3900 for FP64) are rejected with ELM_ERR_SHAPE.
+ * All calls on one GPU share the array (it keeps the last call's partials):
+ * calls that overlap on one GPU, from several streams or host threads, race.
+ * Errors: as elm_gram, plus SHAPE for an order beyond the array and HIP if
+ * the array's device address cannot be looked up. */
+elm_status elm_gram_noalloc(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
+                            elm_dtype h_dt, elm_layout layout, double* M, int64_t ldm);
+
 /* Autotuner of the 16-bit Gram's tile schedule.  The Gram of a node-major
  * BF16/FP16 copy Hn (L x N, ld ldn >= N, N >= L; as for elm_gram) is split
  * along the samples into work items of one 256 x 256 output tile each, and

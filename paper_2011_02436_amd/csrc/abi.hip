@@ -190,6 +190,13 @@ elm_status elm_create(elm_handle** out, void* stream) {
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
             cu > 0)
             h->num_cu = cu;
+        // set-up of elm_gram_noalloc's static scratch on this device (its
+        // address is looked up once per device); a failure here is reported
+        // by that entry point's first call instead
+        try {
+            (void)elm::noalloc_scratch(h->device);
+        } catch (const elm::Error&) {
+        }
     } catch (...) {
         delete h;
         return ELM_ERR_ALLOC;
@@ -466,6 +473,31 @@ elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t 
         } else {
             elm::launch_gram_lp_nodes(h->stream, h_dt, N, L, H, ldh, M, ldm, h->ws);
         }
+    });
+}
+
+elm_status elm_gram_noalloc(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
+                            elm_dtype h_dt, elm_layout layout, double* M, int64_t ldm) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(N >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N and L must be >= 1");
+        REQUIRE(H && M, ELM_ERR_INVALID_ARG, "H and M must be non-null");
+        REQUIRE(layout == ELM_SAMPLE_MAJOR || layout == ELM_NODE_MAJOR, ELM_ERR_INVALID_ARG,
+                "unknown layout");
+        REQUIRE(h_dt == ELM_F64 || h_dt == ELM_F32 || h_dt == ELM_BF16 || h_dt == ELM_F16,
+                ELM_ERR_INVALID_ARG, "unknown dtype");
+        REQUIRE(ldh >= (layout == ELM_SAMPLE_MAJOR ? L : N), ELM_ERR_SHAPE,
+                "ldh smaller than the row length");
+        const bool transposed = N < L;
+        const int64_t n = transposed ? N : L;
+        REQUIRE(ldm >= n, ELM_ERR_SHAPE, "ldm < min(N, L)");
+        if (h_dt == ELM_F64)
+            REQUIRE(layout == ELM_SAMPLE_MAJOR, ELM_ERR_UNSUPPORTED, "FP64 H must be sample-major");
+        else
+            REQUIRE(layout == ELM_NODE_MAJOR && !transposed, ELM_ERR_UNSUPPORTED,
+                    "low-precision H must be node-major, with N >= L");
+        elm::use_device(h);
+        elm::launch_gram_noalloc(h->stream, h->device, h_dt, N, L, H, ldh, M, ldm);
     });
 }
 

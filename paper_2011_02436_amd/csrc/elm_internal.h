@@ -275,6 +275,15 @@ int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, 
                              int force_splits = 0);
 //   the default rule's K splits for a 16-bit Gram of L nodes over N samples
 int gram_default_splits(int64_t N, int64_t L);
+//   the Gram of elm_gram with its partial tiles in a static device array of
+//   GRAM_NOALLOC_SCRATCH_BYTES per GPU instead of the workspace (no device
+//   allocation); K splits lowered until they fit, ELM_ERR_SHAPE if none does
+constexpr size_t GRAM_NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+void launch_gram_noalloc(hipStream_t s, int device, elm_dtype dt, int64_t N, int64_t L, const void* H,
+                         int64_t ldh, double* M, int64_t ldm);
+//   device address of that array on `device` (which must be current), looked
+//   up once per device
+void* noalloc_scratch(int device);
 //   *out = max_i M[i][i]  (NaN if any diagonal entry is NaN)
 void launch_diag_max(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
 

@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 namespace elm {
 namespace {
@@ -413,6 +414,18 @@ __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, i
     gram_lp256_body<HT, GNS>(work[blockIdx.x], n, K, kc_len, A, ld, part);
 }
 
+// The same work items without a table: block b is split b / ntile, upper tile
+// b % ntile, partial slot b (one launch covers every item in item order).
+template <typename HT, int GNS>
+__global__ __launch_bounds__(256) void gram_lp256_direct_kernel(int64_t n, int64_t K, int64_t kc_len,
+                                                                const HT* __restrict__ A, int64_t ld,
+                                                                float* __restrict__ part, int64_t ntile) {
+    const int64_t b = blockIdx.x;
+    int bi, bj;
+    tile_coords(b % ntile, bi, bj);
+    gram_lp256_body<HT, GNS>(int4{(int)(b / ntile), bi, bj, (int)b}, n, K, kc_len, A, ld, part);
+}
+
 // M[i][j] = M[j][i] = sum over splits (in order, FP64) of the 256-tile partials;
 // partial slot of (split s, tile t) is s * ntile + t.  A block sums one 32 x 32
 // sub-tile (by: its position in the tile), writes its rows of M, and writes the
@@ -752,6 +765,122 @@ int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, 
                                                                             M, ldm);
     ELM_LAUNCH_CHECK();
     return kc_len;
+}
+
+// ---------------------------------------------------------------------------
+// The Gram without device allocation (elm_gram_noalloc).  Its split-K partial
+// tiles live in `scratch`, a file-scope device array that every GPU the
+// library runs on holds until the process ends.  In host code the array's
+// name is not a device address: its address on each device is looked up once
+// (hipGetSymbolAddress, with that device current) and only that pointer is
+// passed to kernels.  Every call on a GPU shares the array: calls that
+// overlap on one GPU (several streams, several host threads) race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[GRAM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// chunks of K for the 128-tile FP64/FP32 Gram: plan_chunks' count, lowered
+// until ntile * nchunk partial tiles of `tile_bytes` fit in the scratch
+bool fit_chunks(int64_t ntile, int64_t K, size_t tile_bytes, int64_t& kc_len, int& nchunk) {
+    plan_chunks(ntile, K, 16, kc_len, nchunk);
+    for (int64_t nc = nchunk; nc >= 1; --nc) {
+        kc_len = cdiv(cdiv(K, nc), 16) * 16;
+        nchunk = (int)cdiv(K, kc_len);
+        if ((size_t)ntile * nchunk * tile_bytes <= GRAM_NOALLOC_SCRATCH_BYTES) return true;
+    }
+    return false;
+}
+}  // namespace
+
+void* noalloc_scratch(int device) {
+    if (device < 0 || device >= MAX_DEVICES) throw Error{ELM_ERR_HIP, "device index out of range"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        ELM_HIP_TRY(hipGetDevice(&cur));
+        if (cur != device) throw Error{ELM_ERR_HIP, "scratch lookup needs its device current"};
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            throw Error{ELM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
+
+void launch_gram_noalloc(hipStream_t s, int device, elm_dtype dt, int64_t N, int64_t L, const void* H,
+                         int64_t ldh, double* M, int64_t ldm) {
+    void* scr = noalloc_scratch(device);
+    const bool transposed = N < L;
+    if (dt == ELM_F64 || dt == ELM_F32) {
+        // FP64 sample-major: columns (n = L, K = N) or rows (n = N, K = L);
+        // FP32 node-major: n = L, K = N
+        const int64_t n = transposed ? N : L, K = transposed ? L : N;
+        const int64_t nt = cdiv(n, TILE);
+        const int64_t ntile = nt * (nt + 1) / 2;
+        const size_t tb = (size_t)TILE * TILE * (dt == ELM_F64 ? sizeof(double) : sizeof(float));
+        int64_t kc_len;
+        int nchunk;
+        if (!fit_chunks(ntile, K, tb, kc_len, nchunk))
+            throw Error{ELM_ERR_SHAPE, "Gram order too large for the static scratch of elm_gram_noalloc"};
+        dim3 grid((unsigned)ntile, (unsigned)nchunk);
+        if (dt == ELM_F64) {
+            double* part = (double*)scr;
+            if (transposed)
+                gram16_kernel<double, true><<<grid, NT, 0, s>>>(n, K, kc_len, (const double*)H, ldh, part, ntile);
+            else
+                gram16_kernel<double, false><<<grid, NT, 0, s>>>(n, K, kc_len, (const double*)H, ldh, part,
+                                                                 ntile);
+            ELM_LAUNCH_CHECK();
+            gram_reduce_kernel<double><<<(unsigned)ntile, NT, 0, s>>>(n, part, ntile, nchunk, M, ldm);
+        } else {
+            float* part = (float*)scr;
+            gram16_kernel<float, true><<<grid, NT, 0, s>>>(n, K, kc_len, (const float*)H, ldh, part, ntile);
+            ELM_LAUNCH_CHECK();
+            gram_reduce_kernel<float><<<(unsigned)ntile, NT, 0, s>>>(n, part, ntile, nchunk, M, ldm);
+        }
+        ELM_LAUNCH_CHECK();
+        return;
+    }
+    // 16-bit node-major (n = L, K = N): the default split rule (or the
+    // ELM_GRAM_SPLITS override), lowered until the partial tiles fit
+    const int64_t nt = cdiv(L, GT);
+    const int64_t ntile = nt * (nt + 1) / 2;
+    const size_t tb = (size_t)GT * GT * sizeof(float);
+    int nsplit = gram_splits_override();
+    if (nsplit <= 0) nsplit = pick_splits(ntile, N);
+    int64_t kc_len = 0;
+    int nsplit_eff = 0;
+    for (; nsplit >= 1; --nsplit) {
+        kc_len = cdiv(cdiv(N, nsplit), GBK) * GBK;
+        nsplit_eff = (int)cdiv(N, kc_len);
+        if ((size_t)ntile * nsplit_eff * tb <= GRAM_NOALLOC_SCRATCH_BYTES) break;
+    }
+    if (nsplit < 1)
+        throw Error{ELM_ERR_SHAPE, "Gram order too large for the static scratch of elm_gram_noalloc"};
+    float* part = (float*)scr;
+    const unsigned grid = (unsigned)(ntile * nsplit_eff);
+    const bool five = gram_stages() == 5;
+    if (dt == ELM_BF16) {
+        if (five)
+            gram_lp256_direct_kernel<__bf16, 5><<<grid, 256, 0, s>>>(L, N, kc_len, (const __bf16*)H, ldh, part, ntile);
+        else
+            gram_lp256_direct_kernel<__bf16, 4><<<grid, 256, 0, s>>>(L, N, kc_len, (const __bf16*)H, ldh, part, ntile);
+    } else {
+        if (five)
+            gram_lp256_direct_kernel<_Float16, 5><<<grid, 256, 0, s>>>(L, N, kc_len, (const _Float16*)H, ldh, part,
+                                                                       ntile);
+        else
+            gram_lp256_direct_kernel<_Float16, 4><<<grid, 256, 0, s>>>(L, N, kc_len, (const _Float16*)H, ldh, part,
+                                                                       ntile);
+    }
+    ELM_LAUNCH_CHECK();
+    gram_reduce256_kernel<<<dim3((unsigned)ntile, RSUBS), NT, 0, s>>>(L, part, ntile, nsplit_eff, M, ldm);
+    ELM_LAUNCH_CHECK();
 }
 
 }  // namespace elm

@@ -97,6 +97,7 @@ def _load():
         "elm_rank_factor": ([vp, i64, i64, vp, i64, i32, i32, dbl, ctypes.POINTER(vp),
                              ctypes.POINTER(i64)], i32),
         "elm_gram": ([vp, i64, i64, vp, i64, i32, i32, vp, i64], i32),
+        "elm_gram_noalloc": ([vp, i64, i64, vp, i64, i32, i32, vp, i64], i32),
         "elm_factor_rank": ([vp, ctypes.POINTER(i64)], i32),
         "elm_factor_grow": ([vp, vp, i64, i64, vp, i64, dbl, ctypes.POINTER(vp), ctypes.POINTER(i64),
                              ctypes.POINTER(i32)], i32),
@@ -130,7 +131,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", "elm_last_error",
-            "elm_hidden", "elm_gram", "elm_rank_factor", "elm_factor_rank", "elm_factor_grow", "elm_factor_pivots",
+            "elm_hidden", "elm_gram", "elm_gram_noalloc", "elm_rank_factor", "elm_factor_rank", "elm_factor_grow", "elm_factor_pivots",
             "elm_factor_destroy", "elm_factor_get_info", "elm_train", "elm_train_batched",
             "elm_pinv_solve", "elm_block_solve", "elm_predict", "elm_predict_hidden",
             "elm_autotune_gram", "elm_set_option", "elm_get_option", "elm_profile_enable",
@@ -233,10 +234,12 @@ def elm_hidden(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor,
                             lpdt), "elm_hidden")
 
 
-def elm_gram(H: torch.Tensor, layout: str = "sample", M: Optional[torch.Tensor] = None) -> torch.Tensor:
+def elm_gram(H: torch.Tensor, layout: str = "sample", M: Optional[torch.Tensor] = None,
+             noalloc: bool = False) -> torch.Tensor:
     """The FP64 Gram (H^T H, or H H^T when N < L) of a sample-major FP64 H or a
     node-major low-precision copy.  M: optional preallocated n x n float64
-    output."""
+    output.  noalloc=True calls elm_gram_noalloc (partials in the library's
+    static device array, no device allocation by the library)."""
     h = handle()
     if layout == "sample":
         N, L = H.shape
@@ -251,7 +254,8 @@ def elm_gram(H: torch.Tensor, layout: str = "sample", M: Optional[torch.Tensor] 
         raise ValueError("M must be float64 with n rows and at least n columns")
     hp, ldh = _mat(H, "H")
     mp, ldm = _mat(M, "M")
-    h.check(_lib.elm_gram(h.ptr, N, L, hp, ldh, _DT[H.dtype], lay, mp, ldm), "elm_gram")
+    fn, name = (_lib.elm_gram_noalloc, "elm_gram_noalloc") if noalloc else (_lib.elm_gram, "elm_gram")
+    h.check(fn(h.ptr, N, L, hp, ldh, _DT[H.dtype], lay, mp, ldm), name)
     return M
 
 
