@@ -54,6 +54,8 @@ def parse():
                     help="timed batches of the 256-ELM hidden-size sweep (0 = skip)")
     ap.add_argument("--fp16-steps", type=int, default=2,
                     help="timed FP16-form trainings on the same workload (0 = skip)")
+    ap.add_argument("--streamed-steps", type=int, default=2,
+                    help="timed trainings of the streamed form (H never stored) on the same workload")
     ap.add_argument("--config-steps", type=int, default=3,
                     help="timed trainings per form of the other named workloads (0 = skip)")
     ap.add_argument("--stage", default=None,
@@ -456,10 +458,40 @@ def main():
         del Hh, r16
         torch.cuda.empty_cache()
 
+    # the streamed form on the same workload: H formed 65536 rows at a time for
+    # the Gram and again for every refinement residual, never stored
+    streamed = None
+    if args.streamed_steps > 0:
+        H64 = None          # the stored-H buffers are not needed from here on
+        torch.cuda.empty_cache()
+        rs = elm.train_streamed(X, W, b, T, precision=args.precision, chunk_rows=65536, ir_tol=1e-10,
+                                check_convergence=False)
+        torch.cuda.synchronize()
+        elm.profile_enable(True)
+        sts = []
+        for i in range(args.streamed_steps):
+            ts = time.perf_counter()
+            rs = elm.train_streamed(X, W, b, T, precision=args.precision, chunk_rows=65536, ir_tol=1e-10,
+                                    check_convergence=False)
+            torch.cuda.synchronize()
+            sts.append(time.perf_counter() - ts)
+            log(f"streamed step {i}: {sts[-1] * 1e3:.1f} ms, rank {rs.rank}, NE {rs.info['ne_residual']:.2e}, "
+                f"its {rs.info['iterations']}")
+        stst = elm.profile_read()
+        elm.profile_enable(False)
+        st_ms = sum(sts) / len(sts) * 1e3
+        streamed = {"ms_per_step": round(st_ms, 2), "trainings_per_s": round(1e3 / st_ms, 4),
+                    "chunk_rows": 65536, "rank": rs.rank, "gram_dtype_used": rs.info["gram_dtype"],
+                    "ne_residual": rs.info["ne_residual"], "refine_iterations": rs.info["iterations"],
+                    "beta_rel_diff_vs_stored_h_form": (torch.linalg.norm(rs.beta - beta_lp) /
+                                                       torch.linalg.norm(beta_lp)).item(),
+                    "stage_ms_per_step": _stage_ms(stst, len(sts)),
+                    "h_bytes_not_stored": int(N) * L * (8 + 2)}
+
     batch = bench_batch(args, elm, torch, wl, dev) if args.batch_steps > 0 else None
     configs = None
     if args.config_steps > 0:
-        del H64
+        H64 = None
         torch.cuda.empty_cache()
         configs = bench_configs(args, elm, torch, wl, dev)
     paper = bench_paper_shapes(elm, torch, wl, dev) if args.batch_steps > 0 else None
@@ -517,6 +549,7 @@ def main():
         "stage_ms_per_step": stage_ms_per_step,
         "fp64_form": fp64,
         "fp16_form": fp16,
+        "streamed_form": streamed,
         "batch_sweep": batch,
         "other_workloads": configs,
         "paper_context": paper,

@@ -386,6 +386,29 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m,
                      double* Y, int64_t ldy, int32_t* labels,
                      elm_train_info* info, elm_factor** factor_out);
 
+/* elm_train without storing H: the hidden matrix is formed chunk by chunk
+ * (chunk_rows samples at a time) and consumed at once, so device memory is
+ * O(L^2 + chunk_rows L + L m) instead of the N x L FP64 H plus its copy: the
+ * form for N beyond what HBM holds (the paper's closing remarks name memory
+ * as the limit for large data).  Pass 1 over the samples forms each chunk's
+ * hidden rows (the node-major gram_dt copy only, or FP64 for the FP64 form)
+ * and adds the chunk's Gram to a running FP64 sum, and its H^T T partial to a
+ * per-chunk list summed in chunk order; the rank step, factor and beta_0 are
+ * those of elm_train on that Gram; every refinement residual is one more
+ * pass that forms each chunk's FP64 hidden rows again.  Same precision policy,
+ * stopping rules and report as elm_train (its training-set outputs are not
+ * produced); the Gram's K splits follow the chunks, so beta agrees with
+ * elm_train's to rounding, not bit for bit.  All of X (N x d), W, b, T (N x m)
+ * and beta (L x m) are FP64 device arrays as for elm_train; N >= L;
+ * 1 <= chunk_rows (clamped to N); 1 <= m <= 64.
+ * Errors: as elm_train. */
+elm_status elm_train_streamed(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m,
+                              const double* X, int64_t ldx, const double* W, int64_t ldw,
+                              const double* b, const double* T, int64_t ldt,
+                              elm_dtype gram_dt, int64_t chunk_rows,
+                              double tau_rel, double ir_tol, int32_t ir_max_iter,
+                              double* beta, int64_t ldbeta, elm_train_info* info);
+
 /* One independent training of a batch (all pointers device pointers, FP64,
  * with the shapes and leading dimensions of elm_train). */
 typedef struct {

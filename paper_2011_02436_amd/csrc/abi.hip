@@ -271,6 +271,88 @@ elm_status elm_hidden(elm_handle* h, int64_t N, int64_t d, int64_t L, const void
 
 }  // extern "C"
 
+// The rank step and factor tail of a Gram M (n x n FP64, ld n, in the handle's
+// workspace buffer "gram_M" or any scratch it may overwrite) already formed for
+// factor f (N, L, n, transposed, gram_dtype, device and pool set); kc: products
+// summed in FP32 per Gram partial (0 for an FP64 Gram).
+static void factor_gram(elm_handle* h, elm_factor* f, double* M, int64_t kc, double tau_rel,
+                        elm::Workspace* pool) {
+    const int64_t N = f->N, L = f->L, n = f->n;
+    const bool transposed = f->transposed;
+    const elm_dtype h_dt = f->gram_dtype;
+    // tau from the largest diagonal entry (read back once)
+    double* dmax = (double*)h->ws.get("gram_dmax", sizeof(double));
+    elm::launch_diag_max(h->stream, n, M, n, dmax);
+    double hdmax = 0;
+    ELM_HIP_TRY(hipMemcpyAsync(&hdmax, dmax, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    ELM_HIP_TRY(hipStreamSynchronize(h->stream));
+    if (!std::isfinite(hdmax)) throw Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
+    // default threshold: 16 (n + K) 2^-53 max diag, K = products summed per
+    // Gram entry, so that the Gram's own rounding (up to K u of an entry)
+    // never passes for a pivot
+    const int64_t K = transposed ? L : N;
+    f->tau = (tau_rel > 0 ? tau_rel : 16.0 * (double)(n + K) * std::ldexp(1.0, -53)) * hdmax;
+    f->max_diag = hdmax;
+    f->noise_floor = elm::schur_noise_floor(h_dt, n, N > L ? N : L, kc) * hdmax;
+    bool done = false;
+    if (h->full_rank_min_order > 0 && n >= h->full_rank_min_order) {
+        // certified full rank: every greedy pivot is at least
+        // 1 / max_j (M^-1)_jj, read off the rows of the inverse factor
+        const double need = std::max(64.0 * f->tau, 2.0 * f->noise_floor);
+        if (!h->side) {  // the look-ahead stream (default priority, non-blocking)
+            ELM_HIP_TRY(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+            for (auto& e : h->side_ev) ELM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+        bool ok;
+        {
+            elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
+            ok = elm::unpivoted_cholesky(h->stream, n, M, n, need, &f->R, f, h->ws, h->side,
+                                         h->side_ev[0], h->side_ev[1]);
+        }
+        if (ok) {
+            f->r = n;
+            f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
+            elm::launch_iota(h->stream, n, f->piv);
+            {
+                elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
+                elm::build_factor_tail(h->stream, f, h->ws);
+            }
+            const double lam = elm::inv_max_row_sumsq(h->stream, n, f->Rinv, n, h->ws);
+            if (lam >= need) {
+                f->last_pivot = lam;
+                f->first_rejected = -INFINITY;
+                f->reliable = true;
+                f->certified_full_rank = true;
+                done = true;
+            }
+        }
+        if (!done) {  // not certified: the greedy rule decides
+            elm::free_factor_buffers(f);
+            f->r = 0;
+            f->q = 0;
+            f->woodbury = false;
+        }
+    }
+    if (!done) {
+        f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
+        double pst[3];
+        {
+            elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
+            f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, pst, h->ws, f);
+        }
+        f->last_pivot = pst[0];
+        f->first_rejected = pst[1];
+        f->reliable = (f->r == 0 || f->last_pivot >= 2.0 * f->noise_floor) &&
+                      (f->r == n || f->first_rejected >= -2.0 * f->noise_floor);
+        {
+            // a pooled factor is solved with at once (inside elm_train), so
+            // its last check can wait for the solve's first synchronisation
+            elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
+            elm::build_factor_tail(h->stream, f, h->ws, /*wait=*/pool == nullptr);
+        }
+    }
+}
+
 static elm_status rank_factor_impl(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
                                    elm_dtype h_dt, elm_layout layout, double tau_rel,
                                    elm_factor** out, int64_t* rank, elm::Workspace* pool) {
@@ -314,77 +396,7 @@ static elm_status rank_factor_impl(elm_handle* h, int64_t N, int64_t L, const vo
             kc = elm::launch_gram_lp_nodes(h->stream, h_dt, N, L, H, ldh, M, n, h->ws);
         }
         f->gram_dtype = h_dt;
-        // tau from the largest diagonal entry (read back once)
-        double* dmax = (double*)h->ws.get("gram_dmax", sizeof(double));
-        elm::launch_diag_max(h->stream, n, M, n, dmax);
-        double hdmax = 0;
-        ELM_HIP_TRY(hipMemcpyAsync(&hdmax, dmax, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        ELM_HIP_TRY(hipStreamSynchronize(h->stream));
-        if (!std::isfinite(hdmax)) throw Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
-        // default threshold: 16 (n + K) 2^-53 max diag, K = products summed per
-        // Gram entry, so that the Gram's own rounding (up to K u of an entry)
-        // never passes for a pivot
-        const int64_t K = transposed ? L : N;
-        f->tau = (tau_rel > 0 ? tau_rel : 16.0 * (double)(n + K) * std::ldexp(1.0, -53)) * hdmax;
-        f->max_diag = hdmax;
-        f->noise_floor = elm::schur_noise_floor(h_dt, n, N > L ? N : L, kc) * hdmax;
-        bool done = false;
-        if (h->full_rank_min_order > 0 && n >= h->full_rank_min_order) {
-            // certified full rank: every greedy pivot is at least
-            // 1 / max_j (M^-1)_jj, read off the rows of the inverse factor
-            const double need = std::max(64.0 * f->tau, 2.0 * f->noise_floor);
-            if (!h->side) {  // the look-ahead stream (default priority, non-blocking)
-                ELM_HIP_TRY(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-                for (auto& e : h->side_ev) ELM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-            }
-            bool ok;
-            {
-                elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
-                ok = elm::unpivoted_cholesky(h->stream, n, M, n, need, &f->R, f, h->ws, h->side,
-                                             h->side_ev[0], h->side_ev[1]);
-            }
-            if (ok) {
-                f->r = n;
-                f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
-                elm::launch_iota(h->stream, n, f->piv);
-                {
-                    elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
-                    elm::build_factor_tail(h->stream, f, h->ws);
-                }
-                const double lam = elm::inv_max_row_sumsq(h->stream, n, f->Rinv, n, h->ws);
-                if (lam >= need) {
-                    f->last_pivot = lam;
-                    f->first_rejected = -INFINITY;
-                    f->reliable = true;
-                    f->certified_full_rank = true;
-                    done = true;
-                }
-            }
-            if (!done) {  // not certified: the greedy rule decides
-                elm::free_factor_buffers(f);
-                f->r = 0;
-                f->q = 0;
-                f->woodbury = false;
-            }
-        }
-        if (!done) {
-            f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
-            double pst[3];
-            {
-                elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
-                f->r = elm::pivoted_cholesky(h->stream, n, M, n, f->tau, f->piv, &f->R, pst, h->ws, f);
-            }
-            f->last_pivot = pst[0];
-            f->first_rejected = pst[1];
-            f->reliable = (f->r == 0 || f->last_pivot >= 2.0 * f->noise_floor) &&
-                          (f->r == n || f->first_rejected >= -2.0 * f->noise_floor);
-            {
-                // a pooled factor is solved with at once (inside elm_train), so
-                // its last check can wait for the solve's first synchronisation
-                elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
-                elm::build_factor_tail(h->stream, f, h->ws, /*wait=*/pool == nullptr);
-            }
-        }
+        factor_gram(h, f, M, kc, tau_rel, pool);
         if (rank) *rank = f->r;
         *out = f;
     });
@@ -1211,6 +1223,203 @@ elm_status elm_train(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, 
         if (factor_out) {
             *factor_out = f;
             f = nullptr;
+        }
+    });
+    if (f) {
+        elm::free_factor_buffers(f);
+        delete f;
+    }
+    return st;
+}
+
+elm_status elm_train_streamed(elm_handle* h, int64_t N, int64_t d, int64_t L, int64_t m, const double* X,
+                              int64_t ldx, const double* W, int64_t ldw, const double* b, const double* T,
+                              int64_t ldt, elm_dtype gram_dt, int64_t chunk_rows, double tau_rel, double ir_tol,
+                              int32_t ir_max_iter, double* beta, int64_t ldbeta, elm_train_info* info) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    elm_factor* f = nullptr;
+    elm_status st = elm::guarded(h, [&] {
+        REQUIRE(N >= 1 && d >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N, d and L must be >= 1");
+        REQUIRE(m >= 1 && m <= 64, ELM_ERR_INVALID_ARG, "m must be in [1, 64]");
+        REQUIRE(X && W && b && T && beta, ELM_ERR_INVALID_ARG, "X, W, b, T and beta must be non-null");
+        REQUIRE(gram_dt == ELM_F64 || gram_dt == ELM_F32 || gram_dt == ELM_BF16 || gram_dt == ELM_F16,
+                ELM_ERR_INVALID_ARG, "unknown gram dtype");
+        REQUIRE(chunk_rows >= 1, ELM_ERR_INVALID_ARG, "chunk_rows must be >= 1");
+        REQUIRE(N >= L, ELM_ERR_UNSUPPORTED, "the streamed form sums the column Gram over samples: N >= L");
+        REQUIRE(ldx >= d && ldw >= L && ldt >= m && ldbeta >= m, ELM_ERR_SHAPE,
+                "a leading dimension is smaller than its row length");
+        REQUIRE(tau_rel < 1.0 && !std::isnan(tau_rel), ELM_ERR_INVALID_ARG, "tau_rel must be < 1");
+        REQUIRE(ir_tol >= 0.0 && ir_tol < 1.0, ELM_ERR_INVALID_ARG, "ir_tol must be in [0, 1)");
+        REQUIRE(ir_max_iter >= 0 && ir_max_iter <= 31, ELM_ERR_INVALID_ARG,
+                "ir_max_iter must be in [0, 31]");
+        elm::use_device(h);
+        hipStream_t s = h->stream;
+        elm::Workspace& ws = h->ws;
+        elm::Profiler* pr = &h->prof;
+        const int64_t C = std::min(chunk_rows, N);
+        const int64_t nch = elm::cdiv(N, C);
+        const int64_t ldl = elm::lp_ld(C);
+        const bool fuse_z = m <= elm::HIDDEN_Z_MAX_M;
+        // chunk buffers: the only storage of H
+        double* Hc = (double*)ws.get("st_H64", (size_t)C * L * sizeof(double));
+        double* M = (double*)ws.get("st_M", (size_t)L * L * sizeof(double));
+        double* Mc = (double*)ws.get("st_Mc", (size_t)L * L * sizeof(double));
+        double* Zparts = (double*)ws.get("st_Zparts", (size_t)nch * L * m * sizeof(double));
+        double* Zp = fuse_z ? (double*)ws.get("st_Zp", (size_t)elm::hidden_row_tiles(C) * L * m * sizeof(double))
+                            : nullptr;
+        double* Z = (double*)ws.get("st_Z", (size_t)L * m * sizeof(double));
+        double* nrm = (double*)ws.get("st_nrm", 4 * sizeof(double));
+        double* E = (double*)ws.get("st_E", (size_t)C * m * sizeof(double));
+        double* Gparts = (double*)ws.get("st_Gparts", (size_t)nch * L * m * sizeof(double));
+        double* G = (double*)ws.get("st_G", (size_t)L * m * sizeof(double));
+        double* D = (double*)ws.get("st_D", (size_t)L * m * sizeof(double));
+        double* Bprev = (double*)ws.get("st_Bprev", (size_t)L * m * sizeof(double));
+        auto rows_of = [&](int64_t c) { return std::min(C, N - c * C); };
+        // H of chunk c: FP64 sample-major into Hc (want64) and/or the node-major
+        // low-precision copy; with zc, also that chunk's H^T T partials
+        auto hidden_chunk = [&](int64_t c, bool want64, void* lp, elm_dtype lpdt, bool zc) {
+            const int64_t i0 = c * C, nc = rows_of(c);
+            elm::StageScope sc(pr, ELM_STAGE_HIDDEN, s);
+            elm::launch_hidden(s, ELM_F64, nc, d, L, X + i0 * ldx, ldx, W, ldw, b, want64 ? Hc : nullptr, L,
+                               lp, ldl, lpdt, zc ? T + i0 * ldt : nullptr, ldt, zc ? m : 0, zc ? Zp : nullptr);
+        };
+        elm_train_info ti;
+        std::memset(&ti, 0, sizeof(ti));
+        elm_dtype gdt = gram_dt;
+        for (;;) {
+            // pass 1 over the samples: the Gram (running FP64 sum over chunks, in
+            // chunk order) and H^T T (per-chunk partials summed in order)
+            void* lp = nullptr;
+            if (gdt != ELM_F64)
+                lp = ws.get(gdt == ELM_F32 ? "st_lp32" : "st_lp16", (size_t)L * ldl * elm::dtype_size(gdt));
+            int64_t kc = 0;
+            for (int64_t c = 0; c < nch; ++c) {
+                const int64_t i0 = c * C, nc = rows_of(c);
+                const bool want64 = gdt == ELM_F64 || !fuse_z;
+                hidden_chunk(c, want64, lp, gdt, fuse_z);
+                {
+                    elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+                    if (fuse_z)
+                        elm::launch_partial_sum(s, L, m, elm::hidden_row_tiles(nc), Zp, Zparts + c * L * m, m, nrm,
+                                                ws);
+                    else
+                        elm::launch_ht_times(s, nc, L, m, Hc, L, T + i0 * ldt, ldt, Zparts + c * L * m, m, nrm,
+                                             ws);
+                }
+                double* dst = c == 0 ? M : Mc;
+                if (gdt == ELM_F64)
+                    elm::launch_gram_f64_cols(s, nc, L, Hc, L, dst, L, ws);
+                else
+                    kc = std::max(kc, elm::launch_gram_lp_nodes(s, gdt, nc, L, lp, ldl, dst, L, ws));
+                if (c > 0) elm::launch_add_mat(s, L, L, Mc, L, M, L);
+            }
+            {
+                elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+                elm::launch_partial_sum(s, L, m, nch, Zparts, Z, m, nrm, ws);
+            }
+            // the rank step and factor of the summed Gram
+            f = new elm_factor();
+            f->N = N;
+            f->L = L;
+            f->n = L;
+            f->transposed = false;
+            f->device = h->device;
+            f->pool = &ws;
+            f->gram_dtype = gdt;
+            factor_gram(h, f, M, kc, tau_rel, &ws);
+            (void)elm_factor_get_info(f, &ti.factor);
+            ti.gram_dtype = gdt;
+            const bool can_escalate = gdt != ELM_F64;
+            bool converged = true;
+            if (can_escalate && !f->reliable) {
+                ti.guard = 1;
+                converged = false;
+            } else {
+                // beta_0 and the refinement, each residual a second pass that
+                // forms H again chunk by chunk
+                std::memset(&ti.solve, 0, sizeof(ti.solve));
+                ti.solve.rank = f->r;
+                ti.solve.ne_residual = -1.0;
+                {
+                    elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
+                    elm::apply_pinv(s, f, m, Z, m, nullptr, 0, beta, ldbeta, ws);
+                }
+                double z2 = 0;
+                ELM_HIP_TRY(hipMemcpyAsync(&z2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+                ELM_HIP_TRY(hipStreamSynchronize(s));
+                if (f->pd_flag) {
+                    int bad = 0;
+                    ELM_HIP_TRY(hipMemcpyAsync(&bad, f->pd_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+                    ELM_HIP_TRY(hipStreamSynchronize(s));
+                    if (bad) throw Error{ELM_ERR_NOT_PSD, "Gram of G is not positive definite"};
+                }
+                double res = 0, prev = 0;
+                int it = 0;
+                while (ir_max_iter > 0) {
+                    for (int64_t c = 0; c < nch; ++c) {
+                        const int64_t i0 = c * C, nc = rows_of(c);
+                        hidden_chunk(c, true, nullptr, ELM_F64, false);
+                        {
+                            elm::StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
+                            elm::launch_residual(s, nc, L, m, Hc, L, T + i0 * ldt, ldt, beta, ldbeta, E, m);
+                        }
+                        elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+                        elm::launch_ht_times(s, nc, L, m, Hc, L, E, m, Gparts + c * L * m, m, nrm + 2, ws);
+                    }
+                    {
+                        elm::StageScope sc(pr, ELM_STAGE_RHS, s);
+                        elm::launch_partial_sum(s, L, m, nch, Gparts, G, m, nrm + 1, ws);
+                    }
+                    double g2 = 0;
+                    ELM_HIP_TRY(hipMemcpyAsync(&g2, nrm + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+                    ELM_HIP_TRY(hipStreamSynchronize(s));
+                    res = z2 > 0 ? std::sqrt(g2 / z2) : std::sqrt(g2);
+                    if (it < 32) ti.solve.ne_history[it] = res;
+                    if (it >= 1 && !(res < prev)) {
+                        // as in elm_pinv_solve: a correction that raised the
+                        // residual more than IR_ROLLBACK_RISE times is taken back
+                        if (!(res <= elm::IR_ROLLBACK_RISE * prev)) {
+                            ELM_HIP_TRY(hipMemcpy2DAsync(beta, (size_t)ldbeta * sizeof(double), Bprev,
+                                                         (size_t)m * sizeof(double), (size_t)m * sizeof(double),
+                                                         (size_t)L, hipMemcpyDeviceToDevice, s));
+                            --it;
+                            res = prev;
+                        }
+                        break;
+                    }
+                    if ((it >= 1 && !(res > ir_tol)) || it >= ir_max_iter) break;
+                    prev = res;
+                    {
+                        elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
+                        elm::apply_pinv(s, f, m, G, m, nullptr, 0, D, m, ws);
+                    }
+                    elm::launch_axpy_mat(s, L, m, D, m, beta, ldbeta, Bprev);
+                    ++it;
+                }
+                ti.solve.iterations = it;
+                ti.solve.ne_residual = ir_max_iter > 0 ? res : -1.0;
+                converged = ir_max_iter == 0 || !(res > ir_tol);
+                if (!converged && can_escalate) ti.guard = 2;
+            }
+            if (converged || !can_escalate) {
+                ELM_HIP_TRY(hipStreamSynchronize(s));
+                if (info) *info = ti;
+                if (!converged) {
+                    char msg[160];
+                    std::snprintf(msg, sizeof(msg),
+                                  "refinement stopped after %d iterations at relative normal-equation "
+                                  "residual %.3e > ir_tol %.3e",
+                                  ti.solve.iterations, ti.solve.ne_residual, ir_tol);
+                    throw Error{ELM_ERR_NO_CONVERGENCE, msg};
+                }
+                break;
+            }
+            // a guard failed: the Gram again, one precision up
+            elm::free_factor_buffers(f);
+            delete f;
+            f = nullptr;
+            ++ti.escalations;
+            gdt = elm::next_gram_dtype(gdt);
         }
     });
     if (f) {

@@ -445,6 +445,9 @@ void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
 void launch_hidden_output(hipStream_t s, int64_t N, int64_t L, int64_t m, const double* H,
                           int64_t ldh, const double* beta, int64_t ldb, double* Y, int64_t ldy,
                           int32_t* labels);
+//   Y += X  (rows x cols, both row-major with their leading dimensions)
+void launch_add_mat(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx, double* Y,
+                    int64_t ldy);
 //   beta += delta, elementwise over L x m; prev (ld cols) receives beta before it
 void launch_axpy_mat(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx,
                      double* Y, int64_t ldy, double* prev);

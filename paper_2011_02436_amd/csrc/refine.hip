@@ -6,6 +6,8 @@
 // fixed order (no atomics), so repeated runs are bitwise identical.
 #include "elm_internal.h"
 
+#include <algorithm>
+
 namespace elm {
 namespace {
 
@@ -662,6 +664,25 @@ void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
     ELM_LAUNCH_CHECK();
     sum_kernel<<<1, NT, 0, s>>>(nred, sq, nrm2);
     ELM_LAUNCH_CHECK();
+}
+
+__global__ void add_mat_kernel(int64_t rows, int64_t cols, const double* __restrict__ X, int64_t ldx,
+                               double* __restrict__ Y, int64_t ldy) {
+    const int64_t i = blockIdx.y;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < cols;
+         j += (int64_t)gridDim.x * blockDim.x)
+        Y[i * ldy + j] += X[i * ldx + j];
+}
+
+void launch_add_mat(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx, double* Y,
+                    int64_t ldy) {
+    if (rows <= 0 || cols <= 0) return;
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(cols, 256), 64);
+    for (int64_t r0 = 0; r0 < rows; r0 += 65535) {
+        const int64_t nr = std::min<int64_t>(65535, rows - r0);
+        add_mat_kernel<<<dim3(gx, (unsigned)nr), 256, 0, s>>>(nr, cols, X + r0 * ldx, ldx, Y + r0 * ldy, ldy);
+        ELM_LAUNCH_CHECK();
+    }
 }
 
 // Y += X (rows x cols); prev (rows x cols, ld cols) receives the old Y, so a

@@ -111,6 +111,8 @@ def _load():
                        ctypes.POINTER(vp)], i32),
         "elm_pinv_solve": ([vp, vp, i64, vp, i64, vp, i64, dbl, i32, vp, i64,
                             ctypes.POINTER(SolveInfo)], i32),
+        "elm_train_streamed": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, vp, i64, i32, i64, dbl, dbl,
+                                i32, vp, i64, ctypes.POINTER(TrainInfo)], i32),
         "elm_block_solve": ([vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, i64, vp, vp, i64], i32),
         "elm_predict": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, i32, vp, i64, vp, i64, vp],
                         i32),
@@ -132,7 +134,7 @@ def _load():
 _lib = _load()
 EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", "elm_last_error",
             "elm_hidden", "elm_gram", "elm_gram_noalloc", "elm_rank_factor", "elm_factor_rank", "elm_factor_grow", "elm_factor_pivots",
-            "elm_factor_destroy", "elm_factor_get_info", "elm_train", "elm_train_batched",
+            "elm_factor_destroy", "elm_factor_get_info", "elm_train", "elm_train_streamed", "elm_train_batched",
             "elm_pinv_solve", "elm_block_solve", "elm_predict", "elm_predict_hidden",
             "elm_autotune_gram", "elm_set_option", "elm_get_option", "elm_profile_enable",
             "elm_profile_read"]
@@ -553,6 +555,37 @@ def train(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, T: torch.Tensor, pr
     info["guard"] = int(ti.guard)
     factor = Factor(fptr, N, L, int(ti.factor.rank)) if fptr.value else None
     return TrainResult(beta, int(ti.factor.rank), info, factor, Y, labels)
+
+
+def train_streamed(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, T: torch.Tensor,
+                   precision: str = "fp64", chunk_rows: int = 65536, ir_tol: float = 1e-10,
+                   ir_max_iter: Optional[int] = None, tau_rel: float = 0.0,
+                   check_convergence: bool = True) -> TrainResult:
+    """elm_train_streamed: the training without storing H (formed chunk_rows
+    samples at a time for the Gram and again for each refinement residual)."""
+    if precision not in ("fp64", "fp32", "bf16", "fp16"):
+        raise ValueError("precision must be one of fp64, fp32, bf16, fp16")
+    h = handle()
+    N, d = X.shape
+    L = W.shape[1]
+    m = T.shape[1]
+    for name, t in (("X", X), ("W", W), ("b", b), ("T", T)):
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name} must be float64")
+    gdt = {"fp64": ELM_F64, "fp32": ELM_F32, "bf16": ELM_BF16, "fp16": ELM_F16}[precision]
+    its = (2 if precision == "fp64" else 30) if ir_max_iter is None else ir_max_iter
+    xp, ldx = _mat(X, "X")
+    wp, ldw = _mat(W, "W")
+    tp, ldt = _mat(T, "T")
+    beta = torch.empty((L, m), dtype=torch.float64, device=X.device)
+    bp, ldb = _mat(beta, "beta")
+    ti = TrainInfo()
+    st = _lib.elm_train_streamed(h.ptr, N, d, L, m, xp, ldx, wp, ldw, _vec(b, "b"), tp, ldt, gdt,
+                                 int(chunk_rows), tau_rel, ir_tol, its, bp, ldb, ctypes.byref(ti))
+    if not (st == ELM_ERR_NO_CONVERGENCE and not check_convergence):
+        h.check(st, "elm_train_streamed")
+    info = _train_info_dict(ti)
+    return TrainResult(beta, int(ti.factor.rank), info)
 
 
 def _train_info_dict(ti: TrainInfo) -> dict:
