@@ -148,6 +148,9 @@ def bench_batch(args, elm, torch, wl, dev):
             "gram_dtype_used": used,
             "escalations": int(sum(inf["escalations"] for inf in infos)),
             "max_refine_iterations": max(inf["iterations"] for inf in infos),
+            # how the last timed batch ran: host synchronisations with the batch
+            # stream, HIP graph launches, problems in shared launches / alone
+            "run": elm.batch_report(),
         }
     del H64s, betas, dev_probs
     torch.cuda.empty_cache()

@@ -454,6 +454,25 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                              int32_t ir_max_iter, elm_train_info* infos,
                              elm_status* statuses);
 
+/* How the last elm_train_batched call on a handle ran (host struct, filled by
+ * elm_batch_get_report; no synchronisation). */
+typedef struct {
+    int32_t groups;              /* groups of problems (each within the device budget) */
+    int32_t grouped_problems;    /* problems solved in the shared launches */
+    int32_t worker_problems;     /* problems run alone on the worker streams (N < L, m > 8,
+                                    rank 0, a rank decision within the Gram's noise) */
+    int32_t escalations;         /* problems trained again from a higher-precision Gram */
+    int32_t batch_stream_syncs;  /* host synchronisations with the batch stream: per group one
+                                    read-back of the Grams' largest diagonals (thresholds), one
+                                    of the ranks (they size the factors), one of the factors'
+                                    definiteness flags and one of the refinement's final state;
+                                    plus one per Gram tile table uploaded (first use of a shape) */
+    int32_t graph_captures;      /* HIP graphs captured by the call (pivot steps, refinement) */
+    int32_t graph_launches;      /* HIP graph launches by the call */
+} elm_batch_report;
+
+elm_status elm_batch_get_report(const elm_handle* h, elm_batch_report* out);
+
 /* ------------------------------------------------------------------------ */
 /* Step 3 of the three-step ELM: prediction Y = H beta, label = argmax.      */
 /* ------------------------------------------------------------------------ */

@@ -626,15 +626,6 @@ namespace {
 // "ps_Z" / "ps_nrm" (the hidden-layer kernel can produce them on the fly).
 // Y / labels (optional): H beta and its row arg-max for the returned beta,
 // taken from the last residual pass (a separate pass when there is none).
-// A refinement correction after which the normal-equation residual exceeds
-// this many times the previous one has diverged and is taken back.  Near the
-// rounding floor the residuals of successive iterates differ by small
-// factors at random, and there a correction that does not lower the residual
-// is kept: the first corrections after an FP64 factor of an ill-conditioned
-// Gram remove a forward error of about kappa^2 eps that the residual (already
-// at its floor) does not show.
-constexpr double IR_ROLLBACK_RISE = 4.0;
-
 elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const double* T, int64_t ldt,
                            const double* H64, int64_t ldh64, double ir_tol, int32_t ir_max_iter,
                            double* beta, int64_t ldbeta, elm_solve_info* info, bool z_ready,
@@ -686,14 +677,23 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
         elm::StageScope sc(pr, ELM_STAGE_RHS, s);
         elm::launch_ht_times(s, N, L, m, H64, ldh64, T, ldt, Z, m, nrm, ws);
     }
-    double z2 = 0;
-    ELM_HIP_TRY(hipMemcpyAsync(&z2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
     double* E = (double*)ws.get("ps_E", (size_t)N * m * sizeof(double));
     double* G = (double*)ws.get("ps_G", (size_t)L * m * sizeof(double));
     double* D = (double*)ws.get("ps_D", (size_t)L * m * sizeof(double));
     double* Bprev = (double*)ws.get("ps_Bprev", (size_t)L * m * sizeof(double));
-    double res = 0, prev = 0;
-    int it = 0;
+    // the loop's decisions are taken on the device by the kernel the batched
+    // refinement uses (so a batch and a single training decide alike); the
+    // host reads the state back once per iteration
+    elm::RefineDesc one;
+    one.g2 = nrm + 1;
+    one.z2 = nrm;
+    elm::RefineDesc* done_d = (elm::RefineDesc*)ws.get("ps_desc", sizeof(elm::RefineDesc));
+    elm::IrCtl* ctl = (elm::IrCtl*)ws.get("ps_ctl", sizeof(elm::IrCtl));
+    int32_t* flags = (int32_t*)ws.get("ps_flags", 3 * sizeof(int32_t));
+    ELM_HIP_TRY(hipMemcpyAsync(done_d, &one, sizeof(one), hipMemcpyHostToDevice, s));
+    elm::launch_ir_init(s, 1, ctl, flags, flags + 1);
+    elm::IrCtl hc;
+    int32_t hflags[2] = {0, 0};
     for (;;) {
         // G = H^T (T - H beta): two streaming passes over H
         {
@@ -704,35 +704,22 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
             elm::StageScope sc(pr, ELM_STAGE_RHS, s);
             elm::launch_ht_times(s, N, L, m, H64, ldh64, E, m, G, m, nrm + 1, ws);
         }
-        double g2 = 0;
-        ELM_HIP_TRY(hipMemcpyAsync(&g2, nrm + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        elm::launch_ir_decide(s, 1, ctl, done_d, flags, flags + 1, flags + 2, ir_tol, ir_max_iter);
+        ELM_HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof(hc), hipMemcpyDeviceToHost, s));
+        ELM_HIP_TRY(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
         ELM_HIP_TRY(hipStreamSynchronize(s));
         check_pd();
-        res = z2 > 0 ? std::sqrt(g2 / z2) : std::sqrt(g2);
-        if (info && it < 32) info->ne_history[it] = res;
-        if (it >= 1 && !(res < prev)) {
-            // no progress: the loop ends.  A correction that raised the
-            // residual beyond IR_ROLLBACK_RISE times the previous one diverged
-            // and is taken back (beta is then the previous iterate, with its
-            // residual); a smaller rise is rounding noise at the floor, where
-            // the correction still removed the forward error the factor left
-            if (!(res <= IR_ROLLBACK_RISE * prev)) {
-                ELM_HIP_TRY(hipMemcpy2DAsync(beta, (size_t)ldbeta * sizeof(double), Bprev,
-                                             (size_t)m * sizeof(double), (size_t)m * sizeof(double),
-                                             (size_t)L, hipMemcpyDeviceToDevice, s));
-                --it;
-                res = prev;
-                if (Y || labels) {
-                    elm::StageScope sc(pr, ELM_STAGE_PREDICT, s);
-                    elm::launch_hidden_output(s, N, L, m, H64, ldh64, beta, ldbeta, Y, ldy, labels);
-                }
+        if (hflags[1]) {
+            // a diverging correction is taken back: beta is the previous iterate
+            ELM_HIP_TRY(hipMemcpy2DAsync(beta, (size_t)ldbeta * sizeof(double), Bprev,
+                                         (size_t)m * sizeof(double), (size_t)m * sizeof(double),
+                                         (size_t)L, hipMemcpyDeviceToDevice, s));
+            if (Y || labels) {
+                elm::StageScope sc(pr, ELM_STAGE_PREDICT, s);
+                elm::launch_hidden_output(s, N, L, m, H64, ldh64, beta, ldbeta, Y, ldy, labels);
             }
-            break;
         }
-        // at least one correction: the first solve's residual can be at its
-        // floor while its forward error is about kappa^2 eps
-        if ((it >= 1 && !(res > ir_tol)) || it >= ir_max_iter) break;
-        prev = res;
+        if (!hc.active) break;
         {
             elm::StageScope sc(pr, ELM_STAGE_SOLVE, s);
             if (!f->transposed)
@@ -741,11 +728,13 @@ elm_status pinv_solve_impl(elm_handle* h, const elm_factor* f, int64_t m, const 
                 elm::apply_pinv(s, f, m, E, m, H64, ldh64, D, m, ws);
         }
         elm::launch_axpy_mat(s, L, m, D, m, beta, ldbeta, Bprev);
-        ++it;
     }
+    const double res = hc.res;
+    const int it = hc.it;
     if (info) {
         info->iterations = it;
         info->ne_residual = res;
+        for (int k = 0; k < 32; ++k) info->ne_history[k] = hc.hist[k];
     }
     if (res > ir_tol) {
         result = ELM_ERR_NO_CONVERGENCE;
@@ -770,7 +759,7 @@ struct GroupedSolve {
     double* beta = nullptr;
     int64_t ldbeta = 0;
     const double* Z = nullptr;  // H^T T (L x m, ld m)
-    double z2 = 0.0;            // ||Z||_F^2 (host)
+    const double* z2 = nullptr; // ||Z||_F^2 (device)
     elm_solve_info* info = nullptr;
     elm_status status = ELM_OK;  // out: OK or NO_CONVERGENCE (message in msg)
     std::string msg;
@@ -778,8 +767,12 @@ struct GroupedSolve {
 
 // beta = H^+ T with refinement for every problem of gs: the steps, kernels,
 // arithmetic and stopping rules of pinv_solve_impl for each problem, with each
-// step one launch for all problems still iterating and one host read-back of
-// every residual norm per iteration.
+// step one launch for all problems.  The loop is decided on the device (the
+// kernel pinv_solve_impl uses, for every problem at once); the blocks of a
+// problem that has stopped return at once, so the host issues a fixed
+// sequence -- ir_max_iter + 1 residual evaluations -- which is captured once
+// as a HIP graph and replayed, and reads every problem's state back once at
+// the end.
 void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs, double ir_tol,
                     int32_t ir_max_iter) {
     const int P = (int)gs.size();
@@ -826,6 +819,7 @@ void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs,
                 q.g2 = (double*)base + j;
                 q.D = ptr[4];
                 q.prev = ptr[10];
+                q.z2 = g.z2;
                 for (int k = 0; k < 5; ++k) (*scratch)[(size_t)j * 5 + k] = ptr[5 + k];
             }
         }
@@ -926,18 +920,18 @@ void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs,
     std::vector<int32_t> hs((size_t)NK * per);
     int32_t* ds = (int32_t*)h->ws.get("bt_refine_sched", hs.size() * sizeof(int32_t));
     GroupSched sched[NK];
-    std::vector<char> active(P, 1);
-    auto upload_sched = [&] {
+    // every problem in every launch; the device flags gate them
+    {
         for (int k = 0; k < NK; ++k) {
             int32_t* st = hs.data() + (size_t)k * per;
-            int32_t* pr = st + P + 1;
+            int32_t* pr_ = st + P + 1;
             int cnt = 0;
             int64_t tot = 0;
             for (int j = 0; j < P; ++j) {
                 const int64_t nb = nblk[(size_t)k * P + j];
-                if (!active[j] || nb == 0) continue;
+                if (nb == 0) continue;
                 st[cnt] = (int32_t)tot;
-                pr[cnt] = j;
+                pr_[cnt] = j;
                 ++cnt;
                 tot += nb;
                 if (tot >= INT32_MAX) throw Error{ELM_ERR_UNSUPPORTED, "grouped launch too large"};
@@ -949,14 +943,25 @@ void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs,
             sched[k].blocks = tot;
         }
         ELM_HIP_TRY(hipMemcpyAsync(ds, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    IrCtl* ctl = (IrCtl*)h->ws.get("bt_ir_ctl", (size_t)P * sizeof(IrCtl));
+    int32_t* flags = (int32_t*)h->ws.get("bt_ir_flags", (size_t)(2 * P + 1) * sizeof(int32_t));
+    int32_t* f_active = flags;
+    int32_t* f_rollback = flags + P;
+    int32_t* f_any = flags + 2 * P;
+    auto gated = [&](int k, const int32_t* live) {
+        GroupSched g = sched[k];
+        g.live = live;
+        return g;
     };
     // out = H^+ (.) through each factor: from Z into beta (first) or from G into D
-    auto apply = [&](bool first) {
-        launch_copy_rows_grouped(s, false, dcp + (first ? 0 : 1) * P, sched[K_GAT]);
-        for (int k = 0; k < 6; ++k) launch_rowprod_grouped(s, drp + (size_t)k * P, sched[K_P0 + k], maxm);
-        launch_copy_rows_grouped(s, true, dcp + (size_t)(first ? 2 : 3) * P, sched[K_SCU]);
-        launch_rowprod_grouped(s, drp + (size_t)6 * P, sched[K_P0 + 6], maxm);
-        launch_copy_rows_grouped(s, true, dcp + (size_t)(first ? 4 : 5) * P, sched[K_SCB]);
+    auto apply = [&](bool first, const int32_t* live) {
+        launch_copy_rows_grouped(s, false, dcp + (first ? 0 : 1) * P, gated(K_GAT, live));
+        for (int k = 0; k < 6; ++k)
+            launch_rowprod_grouped(s, drp + (size_t)k * P, gated(K_P0 + k, live), maxm);
+        launch_copy_rows_grouped(s, true, dcp + (size_t)(first ? 2 : 3) * P, gated(K_SCU, live));
+        launch_rowprod_grouped(s, drp + (size_t)6 * P, gated(K_P0 + 6, live), maxm);
+        launch_copy_rows_grouped(s, true, dcp + (size_t)(first ? 4 : 5) * P, gated(K_SCB, live));
     };
     Profiler* pr = &h->prof;
     for (GroupedSolve& g : gs) {
@@ -967,78 +972,124 @@ void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs,
             g.info->ne_residual = -1.0;
         }
     }
-    upload_sched();
-    {
-        StageScope sc(pr, ELM_STAGE_SOLVE, s);
-        apply(true);  // beta_0 = H^+ T
-    }
-    if (ir_max_iter == 0) {
-        ELM_HIP_TRY(hipStreamSynchronize(s));
-        return;
-    }
-    std::vector<double> g2(P), res(P, 0.0), prev(P, 0.0);
-    int it = 0;
+    // The solve as fixed launch sequences: beta_0 and iterations [k0, k1) of
+    // the loop (iteration k: residual k, the decision, a taken-back
+    // correction, and the next correction unless k = ir_max_iter).  With timed
+    // stages when the handle profiles (launched directly then), else each
+    // sequence captured once as a HIP graph and replayed.
+    auto seq = [&](bool timed, bool first, int k0, int k1) {
+        if (first) {
+            StageScope sc(timed ? pr : nullptr, ELM_STAGE_SOLVE, s);
+            apply(true, nullptr);  // beta_0 = H^+ T
+            if (ir_max_iter > 0) launch_ir_init(s, P, ctl, f_active, f_rollback);
+        }
+        for (int k = k0; k < k1; ++k) {
+            {
+                StageScope sc(timed ? pr : nullptr, ELM_STAGE_RESIDUAL, s);
+                launch_refine_grouped(s, RefinePass::ROWS_DOT, drd, gated(K_ROWS, f_active), maxm);
+            }
+            {
+                StageScope sc(timed ? pr : nullptr, ELM_STAGE_RHS, s);
+                launch_refine_grouped(s, RefinePass::COLS_DOT, drd, gated(K_COLS, f_active), maxm);
+                launch_refine_grouped(s, RefinePass::HT_REDUCE, drd, gated(K_HTR, f_active), maxm);
+                launch_refine_grouped(s, RefinePass::SUM, drd, gated(K_SUM, f_active), maxm);
+            }
+            launch_ir_decide(s, P, ctl, drd, f_active, f_rollback, f_any, ir_tol, ir_max_iter);
+            launch_restore_grouped(s, drd, gated(K_AXPY, f_rollback));
+            if (k == ir_max_iter) break;
+            {
+                StageScope sc(timed ? pr : nullptr, ELM_STAGE_SOLVE, s);
+                apply(false, f_active);
+            }
+            launch_refine_grouped(s, RefinePass::AXPY, drd, gated(K_AXPY, f_active), maxm);
+        }
+    };
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool can_graph = !pr->on && s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess &&
+                           cap == hipStreamCaptureStatusNone;
+    // the sequences depend on the descriptor and schedule addresses, the
+    // problem count, every launch's block count, maxm and the loop bounds
+    uint64_t hsh = 1469598103934665603ull;
+    for (int64_t v : nblk) hsh = (hsh ^ (uint64_t)v) * 1099511628211ull;
+    char shape[200];
+    std::snprintf(shape, sizeof(shape), "refine:%p:%p:%p:%p:%d:%d:%d:%a:%llx", (const void*)ddesc,
+                  (const void*)ds, (const void*)ctl, (const void*)flags, P, maxm, (int)ir_max_iter, ir_tol,
+                  (unsigned long long)hsh);
+    auto run_seq = [&](bool first, int k0, int k1) {
+        if (!can_graph) {
+            seq(pr->on, first, k0, k1);
+            return;
+        }
+        char key[260];
+        std::snprintf(key, sizeof(key), "%s:%d:%d:%d", shape, first ? 1 : 0, k0, k1);
+        hipGraphExec_t exec = h->ws.find_graph(key);
+        if (!exec) {
+            ELM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipGraph_t graph = nullptr;
+            try {
+                seq(false, first, k0, k1);
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &graph);
+                if (graph) (void)hipGraphDestroy(graph);
+                throw;
+            }
+            ELM_HIP_TRY(hipStreamEndCapture(s, &graph));
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) throw Error{ELM_ERR_HIP, "graph instantiation of the refinement failed"};
+            h->ws.put_graph(key, exec);
+            ++h->ws.graph_captures;
+        }
+        ELM_HIP_TRY(hipGraphLaunch(exec, s));
+        ++h->ws.graph_launches;
+    };
+    // The first sequence runs as many iterations as the last call of this
+    // shape needed (all of them when unknown, at most ir_max_iter + 1); while
+    // a problem still iterates after it, four more at a time.  Each check is
+    // the read-back of every problem's state, so a repeated batch ends with
+    // one.
+    std::vector<IrCtl> hc(P);
+    int32_t hany = 0;
+    const int kmax = ir_max_iter + 1;
+    int k0 = 0;
+    int k1 = ir_max_iter == 0 ? 0 : std::min(kmax, std::max(1, h->ws.find_iters(shape)));
+    bool first = true;
     for (;;) {
-        {
-            StageScope sc(pr, ELM_STAGE_RESIDUAL, s);
-            launch_refine_grouped(s, RefinePass::ROWS_DOT, drd, sched[K_ROWS], maxm);
+        run_seq(first, k0, k1);
+        first = false;
+        if (ir_max_iter > 0) {
+            ELM_HIP_TRY(hipMemcpyAsync(hc.data(), ctl, (size_t)P * sizeof(IrCtl), hipMemcpyDeviceToHost, s));
+            ELM_HIP_TRY(hipMemcpyAsync(&hany, f_any, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         }
-        {
-            StageScope sc(pr, ELM_STAGE_RHS, s);
-            launch_refine_grouped(s, RefinePass::COLS_DOT, drd, sched[K_COLS], maxm);
-            launch_refine_grouped(s, RefinePass::HT_REDUCE, drd, sched[K_HTR], maxm);
-            launch_refine_grouped(s, RefinePass::SUM, drd, sched[K_SUM], maxm);
-        }
-        ELM_HIP_TRY(hipMemcpyAsync(g2.data(), g2dev, (size_t)P * sizeof(double), hipMemcpyDeviceToHost, s));
         ELM_HIP_TRY(hipStreamSynchronize(s));
-        bool any = false;
-        for (int j = 0; j < P; ++j) {
-            if (!active[j]) continue;
-            GroupedSolve& g = gs[j];
-            const double rj = g.z2 > 0 ? std::sqrt(g2[j] / g.z2) : std::sqrt(g2[j]);
-            res[j] = rj;
-            if (g.info && it < 32) g.info->ne_history[it] = rj;
-            // the last correction made no progress (taken back when it
-            // diverged, as in pinv_solve_impl), or the loop is done
-            const bool noprog = it >= 1 && !(rj < prev[j]);
-            const bool stop = noprog || (it >= 1 && !(rj > ir_tol)) || it >= ir_max_iter;
-            if (!stop) {
-                prev[j] = rj;
-                any = true;
-                continue;
-            }
-            active[j] = 0;
-            int kept = it;
-            double rk = rj;
-            if (noprog && !(rj <= IR_ROLLBACK_RISE * prev[j])) {
-                ELM_HIP_TRY(hipMemcpy2DAsync(g.beta, (size_t)g.ldbeta * sizeof(double), rd[j].prev,
-                                             (size_t)g.m * sizeof(double), (size_t)g.m * sizeof(double),
-                                             (size_t)g.f->L, hipMemcpyDeviceToDevice, s));
-                kept = it - 1;
-                rk = prev[j];
-            }
-            if (g.info) {
-                g.info->iterations = kept;
-                g.info->ne_residual = rk;
-            }
-            if (rk > ir_tol) {
-                g.status = ELM_ERR_NO_CONVERGENCE;
-                char msg[160];
-                std::snprintf(msg, sizeof(msg),
-                              "refinement stopped after %d iterations at relative normal-equation "
-                              "residual %.3e > ir_tol %.3e",
-                              kept, rk, ir_tol);
-                g.msg = msg;
-            }
+        ++h->ws.host_syncs;
+        if (ir_max_iter == 0 || !hany || k1 >= kmax) break;
+        k0 = k1;
+        k1 = std::min(kmax, k1 + 4);
+    }
+    if (ir_max_iter > 0) {
+        int need = 1;
+        for (const IrCtl& c : hc) need = std::max(need, (int)c.evals);
+        h->ws.put_iters(shape, need);
+    }
+    if (ir_max_iter == 0) return;
+    for (int j = 0; j < P; ++j) {
+        GroupedSolve& g = gs[j];
+        const IrCtl& c = hc[j];
+        if (g.info) {
+            g.info->iterations = c.it;
+            g.info->ne_residual = c.res;
+            for (int k = 0; k < 32; ++k) g.info->ne_history[k] = c.hist[k];
         }
-        if (!any) break;
-        upload_sched();
-        {
-            StageScope sc(pr, ELM_STAGE_SOLVE, s);
-            apply(false);
+        if (c.res > ir_tol) {
+            g.status = ELM_ERR_NO_CONVERGENCE;
+            char msg[160];
+            std::snprintf(msg, sizeof(msg),
+                          "refinement stopped after %d iterations at relative normal-equation "
+                          "residual %.3e > ir_tol %.3e",
+                          c.it, c.res, ir_tol);
+            g.msg = msg;
         }
-        launch_refine_grouped(s, RefinePass::AXPY, drd, sched[K_AXPY], maxm);
-        ++it;
     }
 }
 
@@ -1377,8 +1428,8 @@ elm_status elm_train_streamed(elm_handle* h, int64_t N, int64_t d, int64_t L, in
                     if (it < 32) ti.solve.ne_history[it] = res;
                     if (it >= 1 && !(res < prev)) {
                         // as in elm_pinv_solve: a correction that raised the
-                        // residual more than IR_ROLLBACK_RISE times is taken back
-                        if (!(res <= elm::IR_ROLLBACK_RISE * prev)) {
+                        // residual more than IR_RISE times is taken back
+                        if (!(res <= elm::IR_RISE * prev)) {
                             ELM_HIP_TRY(hipMemcpy2DAsync(beta, (size_t)ldbeta * sizeof(double), Bprev,
                                                          (size_t)m * sizeof(double), (size_t)m * sizeof(double),
                                                          (size_t)L, hipMemcpyDeviceToDevice, s));
@@ -1429,6 +1480,12 @@ elm_status elm_train_streamed(elm_handle* h, int64_t N, int64_t d, int64_t L, in
     return st;
 }
 
+elm_status elm_batch_get_report(const elm_handle* h, elm_batch_report* out) {
+    if (!h || !out) return ELM_ERR_INVALID_ARG;
+    *out = h->batch_report;
+    return ELM_OK;
+}
+
 elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* probs,
                              elm_dtype gram_dt, double tau_rel, double ir_tol, int32_t ir_max_iter,
                              elm_train_info* infos, elm_status* statuses) {
@@ -1454,8 +1511,18 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             REQUIRE(p.ldx >= p.d && p.ldw >= p.L && p.ldt >= p.m && p.ldh64 >= p.L && p.ldbeta >= p.m,
                     ELM_ERR_SHAPE, at + "a leading dimension is smaller than its row length");
         }
+        h->batch_report = elm_batch_report{};
         if (count == 0) return;
         elm::use_device(h);
+        struct ReportFill {
+            elm_handle* h;
+            int64_t c0, l0, s0;
+            ~ReportFill() {
+                h->batch_report.graph_captures = (int32_t)(h->ws.graph_captures - c0);
+                h->batch_report.graph_launches = (int32_t)(h->ws.graph_launches - l0);
+                h->batch_report.batch_stream_syncs = (int32_t)(h->ws.host_syncs - s0);
+            }
+        } report_fill{h, h->ws.graph_captures, h->ws.graph_launches, h->ws.host_syncs};
         const int nw = count < h->batch_workers ? count : h->batch_workers;
         while ((int)h->workers.size() < nw) {
             hipStream_t ws_stream = nullptr;
@@ -1685,6 +1752,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             }
         };
 
+        h->batch_report.groups = (int32_t)groups.size();
         for (const std::vector<int32_t>& grp : groups) {
             // phase 1: H, Z = H^T T and the Gram of every problem
             size_t mb = 0, zb = 0;
@@ -1767,12 +1835,11 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             wait_workers(ps);
 
             // phase 2: all rank decisions in shared launches
-            std::vector<double> hdmax(grp.size()), hnrm(grp.size() * 2);
+            std::vector<double> hdmax(grp.size());
             ELM_HIP_TRY(hipMemcpyAsync(hdmax.data(), dmaxs, grp.size() * sizeof(double),
                                        hipMemcpyDeviceToHost, ps));
-            ELM_HIP_TRY(hipMemcpyAsync(hnrm.data(), nrms, grp.size() * 2 * sizeof(double),
-                                       hipMemcpyDeviceToHost, ps));
             ELM_HIP_TRY(hipStreamSynchronize(ps));
+            ++h->ws.host_syncs;
             std::vector<elm::PcholProblem> pc;
             std::vector<int32_t> pc_of(count, -1);
             for (size_t i = 0; i < grp.size(); ++i) {
@@ -1798,7 +1865,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             }
             {
                 elm::StageScope sc(&h->prof, ELM_STAGE_RANK, ps);
-                elm::pivoted_cholesky_grouped(ps, pc, h->ws);
+                elm::pivoted_cholesky_grouped(ps, pc, h->ws);   // reads the ranks back
             }
             workers_wait(ps);
 
@@ -1839,6 +1906,10 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             char* farena = fbytes ? (char*)h->ws.get("bt_factors", fbytes) : nullptr;
             std::vector<std::unique_ptr<elm_factor>> gfac(count);
 
+            for (int32_t e : grp) {
+                if (grouped[e]) ++h->batch_report.grouped_problems;
+                else if (items[e].ok) ++h->batch_report.worker_problems;
+            }
             // a guard failed: train problem e again from a higher-precision Gram
             auto escalate = [&](elm_handle* wh, int32_t e, int guard) {
                 const elm_problem& p = probs[e];
@@ -1963,7 +2034,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                     std::vector<int> bad;
                     {
                         elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, ps);
-                        bad = elm::build_factor_tails_grouped(ps, tf, rorig, h->ws);
+                        bad = elm::build_factor_tails_grouped(ps, tf, rorig, h->ws);   // reads the flags back
                     }
                     for (size_t j = 0; j < tf_of.size(); ++j)
                         if (bad[j]) {
@@ -1995,7 +2066,7 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                 g.beta = p.beta;
                 g.ldbeta = p.ldbeta;
                 g.Z = items[e].Z;
-                g.z2 = hnrm[2 * (size_t)slot[e]];
+                g.z2 = items[e].nrm;   // ||Z||^2 from phase 1, on the device
                 g.info = &info_all[e].solve;
                 gs.push_back(g);
                 gs_of.push_back(e);
@@ -2047,6 +2118,8 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             ELM_HIP_TRY(hipStreamWaitEvent(h->stream, ev, 0));
         }
         ELM_HIP_TRY(hipEventDestroy(ev));
+        for (int32_t e = 0; e < count; ++e)
+            if (info_all[e].escalations > 0) ++h->batch_report.escalations;
         if (infos) std::memcpy(infos, info_all.data(), (size_t)count * sizeof(elm_train_info));
         if (statuses) std::memcpy(statuses, st_all.data(), (size_t)count * sizeof(elm_status));
         for (int32_t e = 0; e < count; ++e)

@@ -103,7 +103,7 @@ struct Workspace {
     std::vector<std::pair<std::string, Buffer>> bufs;
     std::vector<std::string> tables;  // buffers holding an uploaded constant table
     // instantiated HIP graphs of fixed launch sequences, by a key naming
-    // everything their kernel arguments depend on (the most recent 16)
+    // everything their kernel arguments depend on (the most recent 32)
     std::vector<std::pair<std::string, hipGraphExec_t>> graphs;
     // K-split counts of the 16-bit Gram chosen by the autotuner, by (L, N, dtype)
     struct TunedSplits {
@@ -112,6 +112,9 @@ struct Workspace {
     };
     std::vector<TunedSplits> tuned_splits;
     Profiler* prof = nullptr;
+    // HIP graphs captured and launched through this workspace, and host
+    // synchronisations of the batched path's shared launches (counters)
+    int64_t graph_captures = 0, graph_launches = 0, host_syncs = 0;
     void* get(const std::string& name, size_t bytes);
     void release();
     int find_splits(int64_t L, int64_t N, int dt) const {
@@ -127,13 +130,29 @@ struct Workspace {
             }
         tuned_splits.push_back({L, N, dt, splits});
     }
+    // residual evaluations the last grouped refinement of a shape needed
+    std::vector<std::pair<std::string, int>> iters;
+    int find_iters(const std::string& key) const {
+        for (const auto& x : iters)
+            if (x.first == key) return x.second;
+        return 1 << 20;
+    }
+    void put_iters(const std::string& key, int n) {
+        for (auto& x : iters)
+            if (x.first == key) {
+                x.second = n;
+                return;
+            }
+        if (iters.size() >= 64) iters.erase(iters.begin());
+        iters.push_back({key, n});
+    }
     hipGraphExec_t find_graph(const std::string& key) const {
         for (const auto& g : graphs)
             if (g.first == key) return g.second;
         return nullptr;
     }
     void put_graph(const std::string& key, hipGraphExec_t g) {
-        if (graphs.size() >= 16) {
+        if (graphs.size() >= 32) {
             (void)hipGraphExecDestroy(graphs.front().second);
             graphs.erase(graphs.begin());
         }
@@ -180,6 +199,8 @@ struct elm_handle {
     // tuning options (elm_set_option)
     int64_t full_rank_min_order = elm::FULL_RANK_MIN_ORDER;
     int batch_workers = elm::BATCH_WORKERS;
+    // counters of the last elm_train_batched call (elm_batch_get_report)
+    elm_batch_report batch_report{};
 };
 
 struct elm_factor {
@@ -465,6 +486,9 @@ struct GroupSched {
     const int32_t* prob = nullptr;
     int count = 0;
     int64_t blocks = 0;
+    // optional device flags by descriptor index: the blocks of a problem whose
+    // flag is 0 return at once (refinement steps decided on the device)
+    const int32_t* live = nullptr;
 };
 // the problem of this block (a descriptor index) and its block index within it
 __device__ inline int group_problem(const GroupSched& g, int64_t& local) {
@@ -478,6 +502,7 @@ __device__ inline int group_problem(const GroupSched& g, int64_t& local) {
     local = b - g.start[lo];
     return g.prob[lo];
 }
+__device__ inline bool group_live(const GroupSched& g, int j) { return g.live == nullptr || g.live[j] != 0; }
 
 // A sequence of grouped launches: add() copies one launch's descriptors and
 // schedule (problems with no blocks left out) into a host blob, call() inserts
@@ -670,7 +695,36 @@ struct RefineDesc {
     double* g2 = nullptr;       // ||G||_F^2
     double* D = nullptr;        // L x m, ld m: the correction added to beta
     double* prev = nullptr;     // L x m, ld m: beta before the last correction
+    const double* z2 = nullptr; // ||H^T T||_F^2
 };
+// Refinement loop state of one problem, kept and decided on the device: the
+// rules of elm_pinv_solve (stop at ir_tol after at least one correction, at
+// ir_max_iter, or when a correction did not lower the residual).  A
+// correction after which the residual exceeds IR_RISE times the previous one
+// has diverged and is taken back.  Near the rounding floor the residuals of
+// successive iterates differ by small factors at random, and there a
+// correction that does not lower the residual is kept: the first corrections
+// after an FP64 factor of an ill-conditioned Gram remove a forward error of
+// about kappa^2 eps that the residual (already at its floor) does not show.
+constexpr double IR_RISE = 4.0;
+struct IrCtl {
+    int32_t active = 0;    // still iterating
+    int32_t it = 0;        // corrections kept
+    int32_t evals = 0;     // residuals evaluated
+    double prev = 0.0;     // residual before the last correction
+    double res = 0.0;      // residual of the current beta
+    double hist[32] = {};  // residual at each evaluation
+};
+// c[j] = iterating, flags cleared (P problems)
+void launch_ir_init(hipStream_t s, int P, IrCtl* c, int32_t* active, int32_t* rollback);
+// after the residual of every active problem: its decision.  g2 and z2 come
+// from d[j] (descriptor j of P); active[j] / rollback[j] gate the next
+// launches (rollback: this correction is taken back); *any = 1 while some
+// problem is still iterating.
+void launch_ir_decide(hipStream_t s, int P, IrCtl* c, const RefineDesc* d, int32_t* active,
+                      int32_t* rollback, int32_t* any, double ir_tol, int ir_max_iter);
+// beta = prev for the problems whose flag in g.live is set
+void launch_restore_grouped(hipStream_t s, const RefineDesc* d, const GroupSched& g);
 enum class RefinePass {
     ROWS_DOT,   // E = T - H beta
     COLS_DOT,   // part = column-chunk partials of H^T E

@@ -647,6 +647,7 @@ static const int4* gram_table(hipStream_t s, int64_t L, int nsplit_eff, Workspac
         if (tab.size() != nblocks) throw Error{ELM_ERR_HIP, "Gram work table size mismatch"};
         ELM_HIP_TRY(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int4), hipMemcpyHostToDevice, s));
         ELM_HIP_TRY(hipStreamSynchronize(s));  // tab is a host temporary
+        ++ws.host_syncs;
         ws.tables.push_back(key);
     }
     *nblocks_out = nblocks;

@@ -1044,8 +1044,10 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
             (void)hipGraphDestroy(graph);
             if (ie != hipSuccess) throw Error{ELM_ERR_HIP, "graph instantiation of the pivot steps failed"};
             ws.put_graph(key, exec);
+            ++ws.graph_captures;
         }
         ELM_HIP_TRY(hipGraphLaunch(exec, s));
+        ++ws.graph_launches;
     };
     if (nbig > 0) run_chain(dg, nbig, probs[order[0]].n, panel_width(probs[order[0]].n));
     if (nlarge > nbig)
@@ -1057,6 +1059,7 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
     ELM_HIP_TRY(hipMemcpyAsync(hstats.data(), stats, hstats.size() * sizeof(double),
                                hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));
+    ++ws.host_syncs;
     for (int i = 0; i < count; ++i) {
         PcholProblem& pr = probs[order[i]];
         pr.rank = hstate[(size_t)i * ST_N + ST_RANK];

@@ -420,7 +420,9 @@ template <int MM>
 __global__ __launch_bounds__(SB, 2) void rows_dot_grouped(const RefineDesc* __restrict__ d,
                                                        GroupSched g) {
     int64_t lb;
-    const RefineDesc& q = d[group_problem(g, lb)];
+    const int j = group_problem(g, lb);
+    if (!group_live(g, j)) return;
+    const RefineDesc& q = d[j];
     rows_dot_body<MM>(lb, q.N, q.L, q.m, q.H, q.ldh, q.beta, q.ldbeta, q.T, q.ldt, -1.0, q.E, q.m,
                       nullptr, nullptr, 0);
 }
@@ -429,7 +431,9 @@ template <int MM>
 __global__ __launch_bounds__(SB) void cols_dot_grouped(const RefineDesc* __restrict__ d,
                                                        GroupSched g) {
     int64_t lb;
-    const RefineDesc& q = d[group_problem(g, lb)];
+    const int j = group_problem(g, lb);
+    if (!group_live(g, j)) return;
+    const RefineDesc& q = d[j];
     const int64_t nbx = cdiv(q.L, SB);
     cols_dot_body<MM>(lb % nbx, lb / nbx, q.N, q.L, q.m, q.H, q.ldh, q.E, q.m, q.part);
 }
@@ -437,23 +441,108 @@ __global__ __launch_bounds__(SB) void cols_dot_grouped(const RefineDesc* __restr
 __global__ __launch_bounds__(NT) void ht_reduce_grouped(const RefineDesc* __restrict__ d,
                                                         GroupSched g) {
     int64_t lb;
-    const RefineDesc& q = d[group_problem(g, lb)];
+    const int j = group_problem(g, lb);
+    if (!group_live(g, j)) return;
+    const RefineDesc& q = d[j];
     ht_reduce_body(lb, q.L, q.m, (int)cdiv(q.N, CR_ROWS), q.part, q.G, q.m, q.sq);
 }
 
 __global__ __launch_bounds__(NT) void sum_grouped(const RefineDesc* __restrict__ d, GroupSched g) {
     int64_t lb;
-    const RefineDesc& q = d[group_problem(g, lb)];
+    const int j = group_problem(g, lb);
+    if (!group_live(g, j)) return;
+    const RefineDesc& q = d[j];
     sum_body(cdiv(q.L * q.m, NT), q.sq, q.g2);
 }
 
 __global__ void axpy_grouped(const RefineDesc* __restrict__ d, GroupSched g) {
     int64_t lb;
-    const RefineDesc& q = d[group_problem(g, lb)];
+    const int j = group_problem(g, lb);
+    if (!group_live(g, j)) return;
+    const RefineDesc& q = d[j];
     axpy_mat_body(lb, q.L, q.m, q.D, q.m, q.beta, q.ldbeta, q.prev);
 }
 
+__global__ void restore_grouped(const RefineDesc* __restrict__ d, GroupSched g) {
+    int64_t lb;
+    const int j = group_problem(g, lb);
+    if (!group_live(g, j)) return;
+    const RefineDesc& q = d[j];
+    const int64_t e = lb * blockDim.x + threadIdx.x;
+    if (e < q.L * q.m) {
+        const int64_t i = e / q.m, c = e % q.m;
+        q.beta[i * q.ldbeta + c] = q.prev[e];
+    }
+}
+
+__global__ void ir_init_kernel(int P, IrCtl* __restrict__ c, int32_t* __restrict__ active,
+                               int32_t* __restrict__ rollback) {
+    for (int j = threadIdx.x; j < P; j += blockDim.x) {
+        c[j] = IrCtl{};
+        c[j].active = 1;
+        active[j] = 1;
+        rollback[j] = 0;
+    }
+}
+
+// the single-problem loop's rules, one thread per problem
+__global__ __launch_bounds__(256) void ir_decide_kernel(int P, IrCtl* __restrict__ c,
+                                                        const RefineDesc* __restrict__ d,
+                                                        int32_t* __restrict__ active,
+                                                        int32_t* __restrict__ rollback,
+                                                        int32_t* __restrict__ any, double tol,
+                                                        int max_iter) {
+    __shared__ int32_t live;
+    if (threadIdx.x == 0) live = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < P; j += blockDim.x) {
+        rollback[j] = 0;
+        IrCtl& q = c[j];
+        if (!q.active) continue;
+        q.evals += 1;
+        const double g2 = *d[j].g2, z2 = *d[j].z2;
+        double res = z2 > 0 ? sqrt(g2 / z2) : sqrt(g2);
+        if (q.it < 32) q.hist[q.it] = res;
+        if (q.it >= 1 && !(res < q.prev)) {
+            // no progress: stop, and take a diverging correction back
+            if (!(res <= IR_RISE * q.prev)) {
+                rollback[j] = 1;
+                q.it -= 1;
+                res = q.prev;
+            }
+            q.active = 0;
+        } else if ((q.it >= 1 && !(res > tol)) || q.it >= max_iter) {
+            q.active = 0;
+        } else {
+            q.prev = res;   // a correction follows
+            q.it += 1;
+        }
+        q.res = res;
+        active[j] = q.active;
+        if (q.active) atomicOr(&live, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *any = live;
+}
+
 }  // namespace
+
+void launch_ir_init(hipStream_t s, int P, IrCtl* c, int32_t* active, int32_t* rollback) {
+    ir_init_kernel<<<1, 256, 0, s>>>(P, c, active, rollback);
+    ELM_LAUNCH_CHECK();
+}
+
+void launch_ir_decide(hipStream_t s, int P, IrCtl* c, const RefineDesc* d, int32_t* active,
+                      int32_t* rollback, int32_t* any, double ir_tol, int ir_max_iter) {
+    ir_decide_kernel<<<1, 256, 0, s>>>(P, c, d, active, rollback, any, ir_tol, ir_max_iter);
+    ELM_LAUNCH_CHECK();
+}
+
+void launch_restore_grouped(hipStream_t s, const RefineDesc* d, const GroupSched& g) {
+    if (g.count <= 0 || g.blocks <= 0) return;
+    restore_grouped<<<(unsigned)g.blocks, 256, 0, s>>>(d, g);
+    ELM_LAUNCH_CHECK();
+}
 
 int64_t refine_group_blocks(RefinePass pass, const RefineDesc& q, int maxm) {
     switch (pass) {

@@ -155,7 +155,9 @@ template <int MM>
 __global__ __launch_bounds__(256) void rowprod_grouped(const RowprodDesc* __restrict__ d,
                                                        GroupSched g) {
     int64_t lb;
-    const RowprodDesc& q = d[group_problem(g, lb)];
+    const int j = group_problem(g, lb);
+    if (!group_live(g, j)) return;
+    const RowprodDesc& q = d[j];
     rowprod_body<MM>(lb, q.M, q.K, q.m, q.alpha, q.A, q.lda, q.tri, q.B, q.ldb, q.beta, q.C, q.ldc);
 }
 
@@ -164,7 +166,9 @@ template <bool SCATTER>
 __global__ __launch_bounds__(256) void copy_rows_grouped(const CopyRowsDesc* __restrict__ d,
                                                          GroupSched g) {
     int64_t lb;
-    const CopyRowsDesc& q = d[group_problem(g, lb)];
+    const int jp = group_problem(g, lb);
+    if (!group_live(g, jp)) return;
+    const CopyRowsDesc& q = d[jp];
     const int64_t e = lb * 256 + threadIdx.x;
     if (e >= q.rows * q.cols) return;
     const int64_t i = e / q.cols, c = e % q.cols;
@@ -739,6 +743,7 @@ std::vector<int> build_factor_tails_grouped(hipStream_t s, const std::vector<elm
     std::vector<int> hf(P, 0);
     ELM_HIP_TRY(hipMemcpyAsync(hf.data(), flags, P * sizeof(int), hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));
+    ++ws.host_syncs;
     for (size_t p = 0; p < P; ++p) bad[p] = hf[p] ? 1 : 0;
     return bad;
 }

@@ -78,6 +78,16 @@ class Problem(ctypes.Structure):
 STAGES = ["hidden", "gram", "gram_reduce", "rank", "factor", "solve", "rhs", "residual", "predict"]
 
 
+class BatchReport(ctypes.Structure):
+    _fields_ = [("groups", ctypes.c_int32), ("grouped_problems", ctypes.c_int32),
+                ("worker_problems", ctypes.c_int32), ("escalations", ctypes.c_int32),
+                ("batch_stream_syncs", ctypes.c_int32), ("graph_captures", ctypes.c_int32),
+                ("graph_launches", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 class StageTimes(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 9), ("count", ctypes.c_int64 * 9)]
 
@@ -123,6 +133,7 @@ def _load():
         "elm_get_option": ([vp, i32, ctypes.POINTER(i64)], i32),
         "elm_profile_enable": ([vp, i32], i32),
         "elm_profile_read": ([vp, ctypes.POINTER(StageTimes)], i32),
+        "elm_batch_get_report": ([vp, ctypes.POINTER(BatchReport)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -137,7 +148,7 @@ EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", 
             "elm_factor_destroy", "elm_factor_get_info", "elm_train", "elm_train_streamed", "elm_train_batched",
             "elm_pinv_solve", "elm_block_solve", "elm_predict", "elm_predict_hidden",
             "elm_autotune_gram", "elm_set_option", "elm_get_option", "elm_profile_enable",
-            "elm_profile_read"]
+            "elm_profile_read", "elm_batch_get_report"]
 
 
 def _status_string(st: int) -> str:
@@ -458,6 +469,15 @@ def profile_read() -> dict:
     st = StageTimes()
     h.check(_lib.elm_profile_read(h.ptr, ctypes.byref(st)), "elm_profile_read")
     return {name: (float(st.ms[i]), int(st.count[i])) for i, name in enumerate(STAGES)}
+
+
+def batch_report() -> dict:
+    """How the last train_batched call ran (groups, grouped and worker
+    problems, escalations, batch-stream synchronisations, HIP graphs)."""
+    h = handle()
+    out = BatchReport()
+    h.check(_lib.elm_batch_get_report(h.ptr, ctypes.byref(out)), "elm_batch_get_report")
+    return out.as_dict()
 
 
 def elm_predict_hidden(H: torch.Tensor, beta: torch.Tensor, want_Y: bool = True,

@@ -150,22 +150,35 @@ def test_batched_escalation_matches_single_training(elm, batch):
     assert stats[0] == 0 and stats[2] == 0
 
 
-def test_batched_replays_are_identical(elm, mixed):
-    # the shared pivot-step launches of a batch are captured once as a HIP
-    # graph and replayed by later calls with the same shape: every replay,
-    # with other work and synchronisations between them, gives the first
-    # call's results, which equal the single trainings'
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_batched_replays_are_identical(elm, mixed, precision):
+    # the shared pivot-step launches and the whole refinement of a batch are
+    # captured once as HIP graphs and replayed by later calls with the same
+    # shape: every replay, with other work and synchronisations between them,
+    # gives the first call's results, which equal the single trainings'
     probs, refs = mixed
     dev = [_dev(p) for p in probs]
-    first, infos0, _ = elm.train_batched(dev, precision="fp64", ir_tol=1e-12)
+    first, infos0, st0 = elm.train_batched(dev, precision=precision, ir_tol=1e-12, check=False)
+    rep0 = elm.batch_report()
+    print(f"{precision} first call: {rep0}")
     for rep in range(3):
         X, W, b, T = dev[0]
         elm.train(X, W, b, T, precision="bf16", ir_tol=1e-10)  # unrelated eager work
         torch.cuda.synchronize()
-        again, infos, _ = elm.train_batched(dev, precision="fp64", ir_tol=1e-12)
+        again, infos, st = elm.train_batched(dev, precision=precision, ir_tol=1e-12, check=False)
+        report = elm.batch_report()
+        assert report["graph_captures"] == 0 and report["graph_launches"] >= 1, report
+        # one group: four host synchronisations with the batch stream
+        # (thresholds, ranks, the factors' flags, the refinement's final state)
+        assert report["groups"] == 1 and report["batch_stream_syncs"] == 4, report
+        assert st == st0
         for e in range(len(probs)):
             assert torch.equal(again[e], first[e]), (rep, e)
             assert infos[e]["rank"] == infos0[e]["rank"] == refs[e][1]
+            assert infos[e]["ne_history"] == infos0[e]["ne_history"], (rep, e)
+    for e, (X, W, b, T) in enumerate(dev):
+        one = elm.train(X, W, b, T, precision=precision, ir_tol=1e-12, check_convergence=False)
+        assert torch.equal(one.beta, first[e]), e
 
 
 def _solve_fields(info):
