@@ -126,6 +126,12 @@ def bench_batch(args, elm, torch, wl, dev):
     out = {"workload": "batch_sweep: 256 ELMs, N log-U[1000,50000], L log-U[64,2048], d=32, m=5, 10% duplicated nodes",
            "count": len(probs), "sum_N_L2": float(sum(p.N * p.L * p.L for p in probs))}
     for precision in ("bf16", "fp32", "fp64"):
+        # the library's batch autotuner picks the pivot panel width and the
+        # Grams' split/chunk counts for this batch (untimed; kept in the
+        # handle's table, which the timed batches then use)
+        t_before, t_after = elm.autotune_batch(dev_probs, precision=precision, ir_tol=1e-10, H64s=H64s,
+                                               betas=betas)
+        log(f"batch {precision} autotune: {t_before:.1f} ms -> {t_after:.1f} ms")
         _, infos, stats = elm.train_batched(dev_probs, precision=precision, ir_tol=1e-10, H64s=H64s,
                                             betas=betas, check=False)
         torch.cuda.synchronize()
@@ -151,7 +157,9 @@ def bench_batch(args, elm, torch, wl, dev):
             # how the last timed batch ran: host synchronisations with the batch
             # stream, HIP graph launches, problems in shared launches / alone
             "run": elm.batch_report(),
+            "autotune": {"ms_before": round(t_before, 2), "ms_after": round(t_after, 2)},
         }
+    out["tuned_table"] = elm.tune_table()
     del H64s, betas, dev_probs
     torch.cuda.empty_cache()
     return out

@@ -186,12 +186,17 @@ elm_status elm_gram_noalloc(elm_handle* h, int64_t N, int64_t L, const void* H, 
  * sums) of the caller's data with the default rule's split count and with
  * 1/2, 3/4, 3/2 and 2 times it (1 .. 48 splits, at least 2048 samples each),
  * and keeps the fastest (the default's count unless another is at least 2%
- * faster) for this (L, N, dtype) in the handle: later Grams of
- * that shape on this handle (elm_gram, elm_rank_factor, elm_train) use it.
+ * faster) as the handle's ELM_TUNE_GRAM_SPLITS row for the (dtype, L, N)
+ * buckets: later 16-bit Grams of shapes in those buckets on this handle
+ * (elm_gram, elm_rank_factor, elm_train, elm_train_batched) use it.  FP32
+ * node-major and FP64 sample-major copies tune the FP32/FP64 Gram's K chunks
+ * the same way (candidates 1/2, 3/4, 1, 3/2, 2 times the default count,
+ * ELM_TUNE_GRAM_CHUNKS rows).
  * splits_out and ms_out (host, may be NULL) receive the choice and its time
  * in milliseconds.  Synchronises the handle's stream; uses a scratch Gram of
  * L x L FP64 in the handle's workspace.
- * Errors: INVALID_ARG; SHAPE; UNSUPPORTED (FP32/FP64 copies, N < L). */
+ * Errors: INVALID_ARG; SHAPE; UNSUPPORTED (N < L; FP64 must be sample-major,
+ * the others node-major). */
 elm_status elm_autotune_gram(elm_handle* h, int64_t N, int64_t L, const void* Hn, int64_t ldn,
                              elm_dtype dt, int32_t* splits_out, double* ms_out);
 
@@ -223,6 +228,43 @@ elm_status elm_autotune_gram(elm_handle* h, int64_t N, int64_t L, const void* Hn
 elm_status elm_factor_grow(elm_handle* h, const elm_factor* f, int64_t N, int64_t L,
                            const double* H64, int64_t ldh64, double tau_rel,
                            elm_factor** out, int64_t* rank, int32_t* grown);
+
+/* The autotuners' table.  Each row holds a tile-schedule choice of the
+ * library for one kind of kernel, one operand dtype and the power-of-two
+ * buckets of the Gram's order and reduction length (n_log2 = ceil(log2 n),
+ * k_log2 = ceil(log2 K); -1 for "any"):
+ *   ELM_TUNE_GRAM_SPLITS  K splits of the 16-bit Gram (work items of one
+ *                         256 x 256 tile over N / splits samples);
+ *   ELM_TUNE_GRAM_CHUNKS  K chunks of the FP32/FP64 Gram (128 x 128 tiles);
+ *   ELM_TUNE_PANEL        panel width of the greedy pivoted Cholesky for
+ *                         orders up to 4096 (one value for all: the batched
+ *                         form shares panels across problems, and a single
+ *                         training must take the same width to give the same
+ *                         bits); dtype and buckets -1.
+ * A shape without a row takes the default rules.  The choices change speed
+ * and rounding order, never the rank decision's rule or the stopping rules. */
+typedef enum { ELM_TUNE_GRAM_SPLITS = 1, ELM_TUNE_GRAM_CHUNKS = 2, ELM_TUNE_PANEL = 3 } elm_tune_kind;
+typedef struct {
+    int32_t kind;     /* elm_tune_kind */
+    int32_t dtype;    /* elm_dtype of the Gram's operand, or -1 */
+    int32_t n_log2;   /* bucket of the Gram's order, or -1 */
+    int32_t k_log2;   /* bucket of the reduction length (samples), or -1 */
+    int32_t value;    /* splits, chunks or panel width */
+} elm_tune_entry;
+
+/* The handle's table: *count (host) receives the number of rows, and up to
+ * `capacity` rows are copied to out (host, may be NULL with capacity 0). */
+elm_status elm_tune_table_get(const elm_handle* h, elm_tune_entry* out, int32_t capacity,
+                              int32_t* count);
+/* Replace the handle's table by `count` rows (host array; count 0 clears it).
+ * Errors: INVALID_ARG for an unknown kind or a value out of range (splits and
+ * chunks 1..64, panel widths 32, 64, 128 or 256). */
+elm_status elm_tune_table_set(elm_handle* h, const elm_tune_entry* rows, int32_t count);
+/* Persist the table as text (one row per line: kind dtype n_log2 k_log2
+ * value) / read such a file back, replacing the table.  Errors: INVALID_ARG
+ * for a null path, a file that cannot be opened or a malformed row. */
+elm_status elm_tune_table_save(const elm_handle* h, const char* path);
+elm_status elm_tune_table_load(elm_handle* h, const char* path);
 
 /* r of a factor (host read, no synchronisation needed). */
 elm_status elm_factor_rank(const elm_factor* f, int64_t* rank);
@@ -453,6 +495,21 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
                              elm_dtype gram_dt, double tau_rel, double ir_tol,
                              int32_t ir_max_iter, elm_train_info* infos,
                              elm_status* statuses);
+
+/* Autotuner of a batch's shared tile schedule: runs elm_train_batched on the
+ * caller's problems (results are overwritten) with each candidate of a grid
+ * -- the greedy pivot panel width (32, 64, 128) times a scale of every
+ * grouped problem's Gram split or chunk count (1/2, 1, 2 times what the
+ * table or the default rule gives) -- after one untimed call, and keeps the
+ * fastest pair if it beats the current choice by at least 2%: the panel row
+ * and one split/chunk row per (dtype, order, length) bucket of the batch's
+ * Grams go to the handle's table, so later batches and single trainings of
+ * those shapes take them.  ms_before / ms_after (host, may be NULL): the
+ * batch's time with the table as it was, and with the choice kept.
+ * Synchronises.  Errors: those of elm_train_batched. */
+elm_status elm_autotune_batch(elm_handle* h, int32_t count, const elm_problem* probs,
+                              elm_dtype gram_dt, double tau_rel, double ir_tol, int32_t ir_max_iter,
+                              double* ms_before, double* ms_after);
 
 /* How the last elm_train_batched call on a handle ran (host struct, filled by
  * elm_batch_get_report; no synchronisation). */

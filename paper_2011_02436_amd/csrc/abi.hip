@@ -519,20 +519,27 @@ elm_status elm_autotune_gram(elm_handle* h, int64_t N, int64_t L, const void* Hn
     return elm::guarded(h, [&] {
         REQUIRE(N >= 1 && L >= 1, ELM_ERR_INVALID_ARG, "N and L must be >= 1");
         REQUIRE(Hn, ELM_ERR_INVALID_ARG, "Hn must be non-null");
-        REQUIRE(dt == ELM_BF16 || dt == ELM_F16, ELM_ERR_UNSUPPORTED,
-                "the autotuner covers the BF16/FP16 Gram");
-        REQUIRE(N >= L, ELM_ERR_UNSUPPORTED, "the 16-bit Gram needs N >= L");
-        REQUIRE(ldn >= N, ELM_ERR_SHAPE, "ldn < N");
+        REQUIRE(dt == ELM_BF16 || dt == ELM_F16 || dt == ELM_F32 || dt == ELM_F64, ELM_ERR_INVALID_ARG,
+                "unknown dtype");
+        REQUIRE(N >= L, ELM_ERR_UNSUPPORTED, "the autotuner covers the column Gram: N >= L");
+        REQUIRE(ldn >= (dt == ELM_F64 ? L : N), ELM_ERR_SHAPE, "leading dimension smaller than the row");
         elm::use_device(h);
-        const int base = elm::gram_default_splits(N, L);
+        const bool lp = dt == ELM_BF16 || dt == ELM_F16;
+        const int base = lp ? elm::gram_default_splits(N, L) : elm::gram16_default_chunks(L, N);
         std::vector<int> cand;
         for (double f : {1.0, 0.5, 0.75, 1.5, 2.0}) {
             int c = (int)std::lround(base * f);
-            c = std::max(1, std::min(48, c));
-            while (c > 1 && N / c < 2048) --c;
+            c = std::max(1, std::min(lp ? 48 : 64, c));
+            while (lp && c > 1 && N / c < 2048) --c;
             if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
         }
         double* M = (double*)h->ws.get("tune_M", (size_t)L * L * sizeof(double));
+        auto gram = [&](int c) {
+            if (dt == ELM_F64)
+                elm::launch_gram_f64_cols(h->stream, N, L, (const double*)Hn, ldn, M, L, h->ws, c);
+            else
+                elm::launch_gram_lp_nodes(h->stream, dt, N, L, Hn, ldn, M, L, h->ws, c);
+        };
         hipEvent_t e0 = nullptr, e1 = nullptr;
         ELM_HIP_TRY(hipEventCreate(&e0));
         ELM_HIP_TRY(hipEventCreate(&e1));
@@ -548,10 +555,9 @@ elm_status elm_autotune_gram(elm_handle* h, int64_t N, int64_t L, const void* Hn
         double best_ms = 1e300, base_ms = 0.0;
         for (int c : cand) {
             // one untimed run (tables, partial buffer), then the mean of two
-            elm::launch_gram_lp_nodes(h->stream, dt, N, L, Hn, ldn, M, L, h->ws, c);
+            gram(c);
             ELM_HIP_TRY(hipEventRecord(e0, h->stream));
-            for (int r = 0; r < 2; ++r)
-                elm::launch_gram_lp_nodes(h->stream, dt, N, L, Hn, ldn, M, L, h->ws, c);
+            for (int r = 0; r < 2; ++r) gram(c);
             ELM_HIP_TRY(hipEventRecord(e1, h->stream));
             ELM_HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -565,10 +571,70 @@ elm_status elm_autotune_gram(elm_handle* h, int64_t N, int64_t L, const void* Hn
                 best = c;
             }
         }
-        h->ws.put_splits(L, N, (int)dt, best);
+        h->ws.put_tune(lp ? ELM_TUNE_GRAM_SPLITS : ELM_TUNE_GRAM_CHUNKS, (int)dt, L, N, best);
         if (splits_out) *splits_out = best;
         if (ms_out) *ms_out = best_ms;
     });
+}
+
+elm_status elm_tune_table_get(const elm_handle* h, elm_tune_entry* out, int32_t capacity, int32_t* count) {
+    if (!h || !count || capacity < 0 || (capacity > 0 && !out)) return ELM_ERR_INVALID_ARG;
+    *count = (int32_t)h->ws.tune.size();
+    for (int32_t i = 0; i < *count && i < capacity; ++i) out[i] = h->ws.tune[(size_t)i];
+    return ELM_OK;
+}
+
+namespace elm {
+namespace {
+bool tune_row_ok(const elm_tune_entry& t) {
+    if (t.kind == ELM_TUNE_PANEL) return t.value == 32 || t.value == 64 || t.value == 128 || t.value == 256;
+    if (t.kind == ELM_TUNE_GRAM_SPLITS || t.kind == ELM_TUNE_GRAM_CHUNKS)
+        return t.value >= 1 && t.value <= 64 && t.dtype >= ELM_F64 && t.dtype <= ELM_F16;
+    return false;
+}
+}  // namespace
+}  // namespace elm
+
+elm_status elm_tune_table_set(elm_handle* h, const elm_tune_entry* rows, int32_t count) {
+    if (!h || count < 0 || (count > 0 && !rows)) return ELM_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < count; ++i)
+        if (!elm::tune_row_ok(rows[i])) return ELM_ERR_INVALID_ARG;
+    h->ws.tune.assign(rows, rows + count);
+    return ELM_OK;
+}
+
+elm_status elm_tune_table_save(const elm_handle* h, const char* path) {
+    if (!h || !path) return ELM_ERR_INVALID_ARG;
+    FILE* fp = std::fopen(path, "w");
+    if (!fp) return ELM_ERR_INVALID_ARG;
+    std::fprintf(fp, "# libelm tuning table: kind dtype n_log2 k_log2 value\n");
+    for (const elm_tune_entry& t : h->ws.tune)
+        std::fprintf(fp, "%d %d %d %d %d\n", t.kind, t.dtype, t.n_log2, t.k_log2, t.value);
+    const bool ok = std::fclose(fp) == 0;
+    return ok ? ELM_OK : ELM_ERR_INVALID_ARG;
+}
+
+elm_status elm_tune_table_load(elm_handle* h, const char* path) {
+    if (!h || !path) return ELM_ERR_INVALID_ARG;
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return ELM_ERR_INVALID_ARG;
+    std::vector<elm_tune_entry> rows;
+    char line[256];
+    bool ok = true;
+    while (std::fgets(line, sizeof(line), fp)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        elm_tune_entry t{};
+        if (std::sscanf(line, "%d %d %d %d %d", &t.kind, &t.dtype, &t.n_log2, &t.k_log2, &t.value) != 5 ||
+            !elm::tune_row_ok(t)) {
+            ok = false;
+            break;
+        }
+        rows.push_back(t);
+    }
+    std::fclose(fp);
+    if (!ok) return ELM_ERR_INVALID_ARG;
+    h->ws.tune = rows;
+    return ELM_OK;
 }
 
 elm_status elm_factor_rank(const elm_factor* f, int64_t* rank) {
@@ -1480,6 +1546,97 @@ elm_status elm_train_streamed(elm_handle* h, int64_t N, int64_t d, int64_t L, in
     return st;
 }
 
+elm_status elm_autotune_batch(elm_handle* h, int32_t count, const elm_problem* probs, elm_dtype gram_dt,
+                              double tau_rel, double ir_tol, int32_t ir_max_iter, double* ms_before,
+                              double* ms_after) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(count >= 1 && probs, ELM_ERR_INVALID_ARG, "count must be >= 1 and probs non-null");
+        elm::use_device(h);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ELM_HIP_TRY(hipEventCreate(&e0));
+        ELM_HIP_TRY(hipEventCreate(&e1));
+        struct Ev {
+            hipEvent_t a, b;
+            ~Ev() {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } ev{e0, e1};
+        // one batch; a problem that misses ir_tol or fails its guard does not
+        // stop the timing, a malformed argument does
+        auto time_batch = [&]() {
+            ELM_HIP_TRY(hipEventRecord(e0, h->stream));
+            const elm_status st = elm_train_batched(h, count, probs, gram_dt, tau_rel, ir_tol, ir_max_iter,
+                                                    nullptr, nullptr);
+            if (st == ELM_ERR_INVALID_ARG || st == ELM_ERR_SHAPE || st == ELM_ERR_ALLOC || st == ELM_ERR_HIP)
+                throw Error{st, h->last_error};
+            ELM_HIP_TRY(hipEventRecord(e1, h->stream));
+            ELM_HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            ELM_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            return (double)ms;
+        };
+        // the batch's Gram shapes, by bucket, each with its largest problem
+        struct Rep {
+            int kind, dt;
+            int64_t n, k;
+        };
+        std::vector<Rep> reps;
+        for (int32_t e = 0; e < count; ++e) {
+            const elm_problem& p = probs[e];
+            const bool tr = p.N < p.L;
+            const elm_dtype dt = tr ? ELM_F64 : gram_dt;
+            const bool lp = dt == ELM_BF16 || dt == ELM_F16;
+            Rep r{lp ? ELM_TUNE_GRAM_SPLITS : ELM_TUNE_GRAM_CHUNKS, (int)dt, tr ? p.N : p.L, tr ? p.L : p.N};
+            bool found = false;
+            for (Rep& q : reps)
+                if (q.kind == r.kind && q.dt == r.dt && elm::Workspace::bucket(q.n) == elm::Workspace::bucket(r.n) &&
+                    elm::Workspace::bucket(q.k) == elm::Workspace::bucket(r.k)) {
+                    if (r.n * r.n * r.k > q.n * q.n * q.k) q = r;
+                    found = true;
+                }
+            if (!found) reps.push_back(r);
+        }
+        const std::vector<elm_tune_entry> saved = h->ws.tune;
+        auto apply = [&](int panel, double scale) {
+            h->ws.tune = saved;
+            h->ws.put_tune(ELM_TUNE_PANEL, -1, -1, -1, panel);
+            for (const Rep& r : reps) {
+                const int def = r.kind == ELM_TUNE_GRAM_SPLITS ? elm::gram_default_splits(r.k, r.n)
+                                                               : elm::gram16_default_chunks(r.n, r.k);
+                const int v = std::max(1, std::min(r.kind == ELM_TUNE_GRAM_SPLITS ? 48 : 64,
+                                                   (int)std::lround(def * scale)));
+                h->ws.put_tune(r.kind, r.dt, r.n, r.k, v);
+            }
+        };
+        (void)time_batch();  // untimed: buffers, tables, graphs
+        const double before = time_batch();
+        double best_t = before;
+        int best_panel = 0;
+        double best_scale = 0.0;
+        for (int panel : {32, 64, 128})
+            for (double scale : {0.5, 1.0, 2.0}) {
+                apply(panel, scale);
+                (void)time_batch();  // untimed: the candidate's tables and graphs
+                const double t = time_batch();
+                if (t < best_t) {
+                    best_t = t;
+                    best_panel = panel;
+                    best_scale = scale;
+                }
+            }
+        if (best_panel > 0 && best_t < 0.98 * before) {
+            apply(best_panel, best_scale);
+        } else {
+            h->ws.tune = saved;
+            best_t = before;
+        }
+        if (ms_before) *ms_before = before;
+        if (ms_after) *ms_after = best_t;
+    });
+}
+
 elm_status elm_batch_get_report(const elm_handle* h, elm_batch_report* out) {
     if (!h || !out) return ELM_ERR_INVALID_ARG;
     *out = h->batch_report;
@@ -1535,7 +1692,12 @@ elm_status elm_train_batched(elm_handle* h, int32_t count, const elm_problem* pr
             w->owns_stream = true;
             h->workers.push_back(w);
         }
-        for (int w = 0; w < nw; ++w) h->workers[w]->full_rank_min_order = h->full_rank_min_order;
+        for (int w = 0; w < nw; ++w) {
+            // the workers take the handle's options and tuned schedules, so a
+            // problem gives the same bits wherever it runs
+            h->workers[w]->full_rank_min_order = h->full_rank_min_order;
+            h->workers[w]->ws.tune = h->ws.tune;
+        }
         // the workers start after the work already queued on the caller's stream
         hipEvent_t ev = nullptr;
         ELM_HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));

@@ -105,30 +105,36 @@ struct Workspace {
     // instantiated HIP graphs of fixed launch sequences, by a key naming
     // everything their kernel arguments depend on (the most recent 32)
     std::vector<std::pair<std::string, hipGraphExec_t>> graphs;
-    // K-split counts of the 16-bit Gram chosen by the autotuner, by (L, N, dtype)
-    struct TunedSplits {
-        int64_t L, N;
-        int dt, splits;
-    };
-    std::vector<TunedSplits> tuned_splits;
+    // the autotuners' table (elm_tune_entry rows): choices by kind, dtype and
+    // the power-of-two buckets of the Gram's order and reduction length
+    std::vector<elm_tune_entry> tune;
     Profiler* prof = nullptr;
     // HIP graphs captured and launched through this workspace, and host
     // synchronisations of the batched path's shared launches (counters)
     int64_t graph_captures = 0, graph_launches = 0, host_syncs = 0;
     void* get(const std::string& name, size_t bytes);
     void release();
-    int find_splits(int64_t L, int64_t N, int dt) const {
-        for (const auto& t : tuned_splits)
-            if (t.L == L && t.N == N && t.dt == dt) return t.splits;
+    static int bucket(int64_t x) {  // ceil(log2 x), -1 for "any"
+        if (x <= 0) return -1;
+        int b = 0;
+        while (((int64_t)1 << b) < x) ++b;
+        return b;
+    }
+    // the tuned value for (kind, dtype, order n, length k), 0 if none
+    int find_tune(int kind, int dt, int64_t n, int64_t k) const {
+        const int nb = bucket(n), kb = bucket(k);
+        for (const auto& t : tune)
+            if (t.kind == kind && t.dtype == dt && t.n_log2 == nb && t.k_log2 == kb) return t.value;
         return 0;
     }
-    void put_splits(int64_t L, int64_t N, int dt, int splits) {
-        for (auto& t : tuned_splits)
-            if (t.L == L && t.N == N && t.dt == dt) {
-                t.splits = splits;
+    void put_tune(int kind, int dt, int64_t n, int64_t k, int value) {
+        const int nb = bucket(n), kb = bucket(k);
+        for (auto& t : tune)
+            if (t.kind == kind && t.dtype == dt && t.n_log2 == nb && t.k_log2 == kb) {
+                t.value = value;
                 return;
             }
-        tuned_splits.push_back({L, N, dt, splits});
+        tune.push_back(elm_tune_entry{kind, dt, nb, kb, value});
     }
     // residual evaluations the last grouped refinement of a shape needed
     std::vector<std::pair<std::string, int>> iters;
@@ -281,7 +287,7 @@ int64_t hidden_row_tiles(int64_t N);
 // gram.hip: M (n x n FP64, full symmetric, ld = ldm)
 //   column Gram  M = H^T H  of sample-major FP64 H (N x L)
 void launch_gram_f64_cols(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
-                          double* M, int64_t ldm, Workspace& ws);
+                          double* M, int64_t ldm, Workspace& ws, int force_chunks = 0);
 //   row Gram     M = H H^T  of sample-major FP64 H (N x L, N < L)
 void launch_gram_f64_rows(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
                           double* M, int64_t ldm, Workspace& ws);
@@ -294,8 +300,10 @@ void launch_gram_f64_rows(hipStream_t s, int64_t N, int64_t L, const double* H, 
 int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
                              int64_t ldn, double* M, int64_t ldm, Workspace& ws,
                              int force_splits = 0);
-//   the default rule's K splits for a 16-bit Gram of L nodes over N samples
+//   the default rule's K splits for a 16-bit Gram of L nodes over N samples,
+//   and K chunks for an FP32/FP64 Gram of order n over K products
 int gram_default_splits(int64_t N, int64_t L);
+int gram16_default_chunks(int64_t n, int64_t K);
 //   the Gram of elm_gram with its partial tiles in a static device array of
 //   GRAM_NOALLOC_SCRATCH_BYTES per GPU instead of the workspace (no device
 //   allocation); K splits lowered until they fit, ELM_ERR_SHAPE if none does

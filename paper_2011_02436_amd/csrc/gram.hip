@@ -176,15 +176,28 @@ void plan_chunks(int64_t ntile, int64_t K, int64_t quantum, int64_t& kc_len, int
     nchunk = (int)cdiv(K, kc_len);
 }
 
+// K chunks of the FP32/FP64 Gram: force_chunks > 0, else the tuning table's
+// row for this shape, else plan_chunks' rule
+void gram16_chunks(int dt, int64_t n, int64_t ntile, int64_t K, int force_chunks, const Workspace& ws,
+                   int64_t& kc_len, int& nchunk) {
+    plan_chunks(ntile, K, 16, kc_len, nchunk);
+    int nc = force_chunks > 0 ? force_chunks : ws.find_tune(ELM_TUNE_GRAM_CHUNKS, dt, n, K);
+    if (nc > 0) {
+        nc = std::max(1, std::min(64, nc));
+        kc_len = cdiv(cdiv(K, nc), 16) * 16;
+        nchunk = (int)cdiv(K, kc_len);
+    }
+}
+
 // Returns the longest run of products accumulated in T before the FP64 sum.
 template <typename T, bool KCONTIG>
 int64_t run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, double* M,
-                   int64_t ldm, Workspace& ws) {
+                   int64_t ldm, Workspace& ws, int force_chunks = 0) {
     const int64_t nt = cdiv(n, TILE);
     const int64_t ntile = nt * (nt + 1) / 2;
     int64_t kc_len;
     int nchunk;
-    plan_chunks(ntile, K, 16, kc_len, nchunk);
+    gram16_chunks(sizeof(T) == 8 ? ELM_F64 : ELM_F32, n, ntile, K, force_chunks, ws, kc_len, nchunk);
     T* part = (T*)ws.get("gram_part", (size_t)ntile * nchunk * TILE * TILE * sizeof(T));
     {
         StageScope sc(ws.prof, ELM_STAGE_GRAM, s);
@@ -539,8 +552,8 @@ void launch_diag_max(hipStream_t s, int64_t n, const double* M, int64_t ldm, dou
 }
 
 void launch_gram_f64_cols(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
-                          double* M, int64_t ldm, Workspace& ws) {
-    run_gram16<double, false>(s, L, N, H, ldh, M, ldm, ws);
+                          double* M, int64_t ldm, Workspace& ws, int force_chunks) {
+    run_gram16<double, false>(s, L, N, H, ldh, M, ldm, ws, force_chunks);
 }
 
 void launch_gram_f64_rows(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
@@ -632,6 +645,14 @@ int gram_default_splits(int64_t N, int64_t L) {
     return pick_splits(nt * (nt + 1) / 2, N);
 }
 
+int gram16_default_chunks(int64_t n, int64_t K) {
+    const int64_t nt = cdiv(n, TILE);
+    int64_t kc_len;
+    int nchunk;
+    plan_chunks(nt * (nt + 1) / 2, K, 16, kc_len, nchunk);
+    return nchunk;
+}
+
 // the work table of a 16-bit Gram of L nodes in nsplit_eff splits: it depends
 // only on (L, splits), so it is built and uploaded once per workspace
 static const int4* gram_table(hipStream_t s, int64_t L, int nsplit_eff, Workspace& ws,
@@ -660,7 +681,7 @@ size_t gram_group_plan(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, GramDe
         const int64_t nt = cdiv(L, GT);
         const int64_t ntile = nt * (nt + 1) / 2;
         int nsplit = gram_splits_override();
-        if (nsplit <= 0) nsplit = ws.find_splits(L, N, (int)dt);
+        if (nsplit <= 0) nsplit = ws.find_tune(ELM_TUNE_GRAM_SPLITS, (int)dt, L, N);
         if (nsplit <= 0) nsplit = pick_splits(ntile, N);
         const int64_t kc_len = cdiv(cdiv(N, nsplit), GBK) * GBK;
         const int nsplit_eff = (int)cdiv(N, kc_len);
@@ -681,7 +702,7 @@ size_t gram_group_plan(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, GramDe
     const int64_t ntile = nt * (nt + 1) / 2;
     int64_t kc_len;
     int nchunk;
-    plan_chunks(ntile, N, 16, kc_len, nchunk);
+    gram16_chunks(dt == ELM_F32 ? ELM_F32 : ELM_F64, L, ntile, N, 0, ws, kc_len, nchunk);
     q.kind = dt == ELM_F32 ? GRAM_F32 : GRAM_F64;
     q.n = L;
     q.K = N;
@@ -729,12 +750,13 @@ void launch_gram_grouped(hipStream_t s, int stage, int kind, const GramDesc* d, 
 
 int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, const void* Hn,
                              int64_t ldn, double* M, int64_t ldm, Workspace& ws, int force_splits) {
-    if (dt == ELM_F32) return run_gram16<float, true>(s, L, N, (const float*)Hn, ldn, M, ldm, ws);
+    if (dt == ELM_F32)
+        return run_gram16<float, true>(s, L, N, (const float*)Hn, ldn, M, ldm, ws, force_splits);
     const int64_t nt = cdiv(L, GT);
     const int64_t ntile = nt * (nt + 1) / 2;
     int nsplit = force_splits;
     if (nsplit <= 0) nsplit = gram_splits_override();
-    if (nsplit <= 0) nsplit = ws.find_splits(L, N, (int)dt);
+    if (nsplit <= 0) nsplit = ws.find_tune(ELM_TUNE_GRAM_SPLITS, (int)dt, L, N);
     if (nsplit <= 0) nsplit = pick_splits(ntile, N);
     const int64_t kc_len = cdiv(cdiv(N, nsplit), GBK) * GBK;
     const int nsplit_eff = (int)cdiv(N, kc_len);

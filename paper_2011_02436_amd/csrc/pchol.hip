@@ -792,21 +792,23 @@ static int64_t finish_pivoted_cholesky(hipStream_t s, int64_t n, const int32_t* 
 // MID_MAX take narrow panels (the re-read rows of many factorisations sharing
 // the launches stay in the caches), larger ones NB.  ELM_MID_PANEL (32, 64,
 // 128 or 256) overrides the narrow width for tuning.
-static int panel_width(int64_t n) {
-    static const int mid = [] {
+static int panel_width(int64_t n, const Workspace& ws) {
+    static const int mid_env = [] {
         if (const char* e = std::getenv("ELM_MID_PANEL")) {
             const int v = std::atoi(e);
             if (v == 32 || v == 64 || v == 128 || v == 256) return v;
         }
         return 64;
     }();
-    return n <= MID_MAX ? mid : NB;
+    if (n > MID_MAX) return NB;
+    const int t = ws.find_tune(ELM_TUNE_PANEL, -1, -1, -1);   // the autotuner's width
+    return t > 0 ? t : mid_env;
 }
 
 int64_t pivoted_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm, double tau,
                          int32_t* piv, double** R_out, double* stats_out, Workspace& ws,
                          elm_factor* f) {
-    const int pw = panel_width(n);
+    const int pw = panel_width(n, ws);
     const int64_t nparts_max = cdiv(n, PT / 8);  // most blocks of any step launch
     int* state = (int*)ws.get("pc_state", ST_N * sizeof(int));
     double* pstats = (double*)ws.get("pc_stats", PS_N * sizeof(double));
@@ -917,7 +919,7 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
         off[i] = scratch;
         scratch += al(nn) + al(n * sizeof(int32_t));  // S0, piv
         if (n > SMALL_N)
-            scratch += al(nn) + al((size_t)panel_width(n) * n * sizeof(double)) + al(n * sizeof(double)) +
+            scratch += al(nn) + al((size_t)panel_width(n, ws) * n * sizeof(double)) + al(n * sizeof(double)) +
                        4 * al(n * sizeof(int)) + 2 * al(cdiv(n, PT / 8) * sizeof(Part));
         roff[i] = rbytes;
         rbytes += al(nn);
@@ -949,7 +951,7 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
         q.piv = (int32_t*)take(n * sizeof(int32_t));
         if (n > SMALL_N) {
             q.S[1] = (double*)take(nn);
-            q.P = (double*)take((size_t)panel_width(n) * n * sizeof(double));
+            q.P = (double*)take((size_t)panel_width(n, ws) * n * sizeof(double));
             q.d = (double*)take(n * sizeof(double));
             q.chosen = (int*)take(n * sizeof(int));
             q.rem0 = (int*)take(n * sizeof(int));
@@ -1049,9 +1051,9 @@ void pivoted_cholesky_grouped(hipStream_t s, std::vector<PcholProblem>& probs, W
         ELM_HIP_TRY(hipGraphLaunch(exec, s));
         ++ws.graph_launches;
     };
-    if (nbig > 0) run_chain(dg, nbig, probs[order[0]].n, panel_width(probs[order[0]].n));
+    if (nbig > 0) run_chain(dg, nbig, probs[order[0]].n, panel_width(probs[order[0]].n, ws));
     if (nlarge > nbig)
-        run_chain(dg + nbig, nlarge - nbig, probs[order[nbig]].n, panel_width(probs[order[nbig]].n));
+        run_chain(dg + nbig, nlarge - nbig, probs[order[nbig]].n, panel_width(probs[order[nbig]].n, ws));
     std::vector<int> hstate((size_t)count * ST_N);
     std::vector<double> hstats((size_t)count * PS_N);
     ELM_HIP_TRY(hipMemcpyAsync(hstate.data(), states, hstate.size() * sizeof(int),

@@ -88,6 +88,14 @@ class BatchReport(ctypes.Structure):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n_log2", ctypes.c_int32),
+                ("k_log2", ctypes.c_int32), ("value", ctypes.c_int32)]
+
+
+TUNE_KINDS = {1: "gram_splits", 2: "gram_chunks", 3: "panel"}
+
+
 class StageTimes(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 9), ("count", ctypes.c_int64 * 9)]
 
@@ -134,6 +142,12 @@ def _load():
         "elm_profile_enable": ([vp, i32], i32),
         "elm_profile_read": ([vp, ctypes.POINTER(StageTimes)], i32),
         "elm_batch_get_report": ([vp, ctypes.POINTER(BatchReport)], i32),
+        "elm_tune_table_get": ([vp, ctypes.POINTER(TuneEntry), i32, ctypes.POINTER(i32)], i32),
+        "elm_tune_table_set": ([vp, ctypes.POINTER(TuneEntry), i32], i32),
+        "elm_tune_table_save": ([vp, ctypes.c_char_p], i32),
+        "elm_tune_table_load": ([vp, ctypes.c_char_p], i32),
+        "elm_autotune_batch": ([vp, i32, ctypes.POINTER(Problem), i32, dbl, dbl, i32, ctypes.POINTER(dbl),
+                                ctypes.POINTER(dbl)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -148,7 +162,8 @@ EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", 
             "elm_factor_destroy", "elm_factor_get_info", "elm_train", "elm_train_streamed", "elm_train_batched",
             "elm_pinv_solve", "elm_block_solve", "elm_predict", "elm_predict_hidden",
             "elm_autotune_gram", "elm_set_option", "elm_get_option", "elm_profile_enable",
-            "elm_profile_read", "elm_batch_get_report"]
+            "elm_profile_read", "elm_batch_get_report", "elm_tune_table_get", "elm_tune_table_set",
+            "elm_tune_table_save", "elm_tune_table_load", "elm_autotune_batch"]
 
 
 def _status_string(st: int) -> str:
@@ -417,18 +432,26 @@ def elm_predict(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, beta: torch.T
     return Y, labels
 
 
-def autotune_gram(Hn: torch.Tensor) -> Tuple[int, float]:
-    """elm_autotune_gram on a node-major BF16/FP16 copy Hn (L x N): times the
-    Gram with several K-split counts and keeps the fastest for this shape in
-    the handle.  Returns (splits, milliseconds)."""
-    if Hn.dtype not in (torch.bfloat16, torch.float16) or Hn.dim() != 2 or Hn.stride(1) != 1:
-        raise ValueError("Hn must be a row-major 2-D bfloat16/float16 tensor (L x N)")
+def autotune_gram(H: torch.Tensor, layout: str = "node") -> Tuple[int, float]:
+    """elm_autotune_gram: times the Gram of H with several K-split (16-bit,
+    node-major L x N copy) or K-chunk (FP32 node-major, FP64 sample-major
+    N x L) counts and keeps the fastest as the handle's table row for this
+    shape's buckets.  Returns (count, milliseconds)."""
+    if H.dim() != 2 or H.stride(1) != 1:
+        raise ValueError("H must be a row-major 2-D tensor")
+    if layout == "sample":
+        if H.dtype != torch.float64:
+            raise ValueError("a sample-major H must be float64")
+        N, L = H.shape
+    else:
+        if H.dtype not in (torch.bfloat16, torch.float16, torch.float32):
+            raise ValueError("a node-major H must be bfloat16, float16 or float32")
+        L, N = H.shape
     h = handle()
-    L, N = Hn.shape
     sp = ctypes.c_int32()
     ms = ctypes.c_double()
-    h.check(_lib.elm_autotune_gram(h.ptr, N, L, ctypes.c_void_p(Hn.data_ptr()), Hn.stride(0),
-                                   _DT[Hn.dtype], ctypes.byref(sp), ctypes.byref(ms)),
+    h.check(_lib.elm_autotune_gram(h.ptr, N, L, ctypes.c_void_p(H.data_ptr()), H.stride(0),
+                                   _DT[H.dtype], ctypes.byref(sp), ctypes.byref(ms)),
             "elm_autotune_gram")
     return int(sp.value), float(ms.value)
 
@@ -469,6 +492,74 @@ def profile_read() -> dict:
     st = StageTimes()
     h.check(_lib.elm_profile_read(h.ptr, ctypes.byref(st)), "elm_profile_read")
     return {name: (float(st.ms[i]), int(st.count[i])) for i, name in enumerate(STAGES)}
+
+
+def tune_table() -> list:
+    """The handle's tuning table as a list of dicts."""
+    h = handle()
+    n = ctypes.c_int32()
+    h.check(_lib.elm_tune_table_get(h.ptr, None, 0, ctypes.byref(n)), "elm_tune_table_get")
+    rows = (TuneEntry * max(n.value, 1))()
+    h.check(_lib.elm_tune_table_get(h.ptr, rows, n.value, ctypes.byref(n)), "elm_tune_table_get")
+    return [{"kind": TUNE_KINDS.get(r.kind, r.kind), "dtype": _DT_NAME.get(r.dtype, "any"),
+             "n_log2": r.n_log2, "k_log2": r.k_log2, "value": r.value} for r in rows[:n.value]]
+
+
+def tune_table_set(rows: list) -> None:
+    """Replace the table (rows as returned by tune_table)."""
+    h = handle()
+    kinds = {v: k for k, v in TUNE_KINDS.items()}
+    dts = {v: k for k, v in _DT_NAME.items()}
+    arr = (TuneEntry * max(len(rows), 1))()
+    for i, r in enumerate(rows):
+        arr[i] = TuneEntry(kinds[r["kind"]], dts.get(r["dtype"], -1), r["n_log2"], r["k_log2"], r["value"])
+    h.check(_lib.elm_tune_table_set(h.ptr, arr, len(rows)), "elm_tune_table_set")
+
+
+def tune_table_save(path: str) -> None:
+    h = handle()
+    h.check(_lib.elm_tune_table_save(h.ptr, path.encode()), "elm_tune_table_save")
+
+
+def tune_table_load(path: str) -> None:
+    h = handle()
+    h.check(_lib.elm_tune_table_load(h.ptr, path.encode()), "elm_tune_table_load")
+
+
+def _problem_array(problems, H64s=None, betas=None):
+    count = len(problems)
+    arr = (Problem * max(count, 1))()
+    keep = []
+    for e, (X, W, b, T) in enumerate(problems):
+        N, d = X.shape
+        L = W.shape[1]
+        m = T.shape[1]
+        H64 = H64s[e] if H64s is not None else torch.empty((N, L), dtype=torch.float64, device=X.device)
+        beta = betas[e] if betas is not None else torch.empty((L, m), dtype=torch.float64, device=X.device)
+        keep += [H64, beta]
+        xp, ldx = _mat(X, "X")
+        wp, ldw = _mat(W, "W")
+        tp, ldt = _mat(T, "T")
+        hp, ldh = _mat(H64, "H64")
+        bp, ldb = _mat(beta, "beta")
+        arr[e] = Problem(N, d, L, m, xp.value, ldx, wp.value, ldw, _vec(b, "b").value, tp.value, ldt,
+                         hp.value, ldh, bp.value, ldb)
+    return arr, keep
+
+
+def autotune_batch(problems, precision: str = "bf16", ir_tol: float = 1e-10,
+                   ir_max_iter: Optional[int] = None, tau_rel: float = 0.0, H64s=None, betas=None):
+    """elm_autotune_batch over a list of (X, W, b, T): returns (ms before,
+    ms after); the choice goes to the handle's tuning table."""
+    h = handle()
+    arr, keep = _problem_array(problems, H64s, betas)
+    gdt = {"fp64": ELM_F64, "fp32": ELM_F32, "bf16": ELM_BF16, "fp16": ELM_F16}[precision]
+    its = (2 if precision == "fp64" else 30) if ir_max_iter is None else ir_max_iter
+    before, after = ctypes.c_double(), ctypes.c_double()
+    h.check(_lib.elm_autotune_batch(h.ptr, len(problems), arr, gdt, tau_rel, ir_tol, its, ctypes.byref(before),
+                                    ctypes.byref(after)), "elm_autotune_batch")
+    del keep
+    return before.value, after.value
 
 
 def batch_report() -> dict:
