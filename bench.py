@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--config-steps", type=int, default=3,
                     help="timed trainings per form of the other named workloads (0 = skip)")
     ap.add_argument("--stage", default=None,
-                    choices=["hidden", "gram", "gram64", "rank", "refine", "predict", "copy", "batch"],
+                    choices=["hidden", "gram", "gram64", "rank", "refine", "predict", "copy", "batch", "probes"],
                     help="run one stage alone (for profiling) instead of the benchmark")
     ap.add_argument("--reps", type=int, default=1, help="timed repetitions of --stage")
     return ap.parse_args()
@@ -237,6 +237,20 @@ def run_stage(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.stage == "probes":
+        # the device ceilings the kernels are held against (one JSON line)
+        buf = torch.empty(16 << 30, dtype=torch.uint8, device=dev)
+        buf.fill_(1)
+        res = {}
+        for dt in ("bf16", "fp64"):
+            for rnd in (False, True):
+                tf, ms = elm.probe_mfma(dt, rnd)
+                res[f"mfma_{dt}_{'random' if rnd else 'constant'}_tflops"] = round(tf, 1)
+        res["stream_read_gbs"] = round(elm.probe_stream(buf)[0], 1)
+        res["dma_stream_gbs"] = round(elm.probe_dma(buf, resident=False)[0], 1)
+        res["dma_l2_resident_gbs"] = round(elm.probe_dma(buf, resident=True)[0], 1)
+        print(json.dumps({"probes": res, "buffer_bytes": buf.numel()}), flush=True)
+        return
     if args.stage == "batch":
         probs = wl.batch_sweep()
         dp = [tuple(torch.from_numpy(a).to(dev) for a in (q.X, q.W, q.b, q.T)) for q in probs]

@@ -600,6 +600,31 @@ elm_status elm_profile_enable(elm_handle* h, int enable);
  * (host struct out).  Synchronises the handle's stream. */
 elm_status elm_profile_read(elm_handle* h, elm_stage_times* out);
 
+/* ------------------------------------------------------------------------ */
+/* Probes of the device's ceilings (not part of the method; for measurement). */
+/* ------------------------------------------------------------------------ */
+
+/* Sustained MFMA rate: 2 waves per SIMD on every CU issue independent
+ * 32x32x16 BF16 (dt = ELM_BF16) or 16x16x4 FP64 (ELM_F64) MFMAs from
+ * registers, 8 accumulator chains each; random_operands != 0 fills the
+ * operands with random values (the data-dependent power draw lowers the
+ * clock), else 1.0.  tflops (host) receives the rate, ms (host, may be
+ * NULL) the launch time.  Synchronises.  Errors: UNSUPPORTED dtype. */
+elm_status elm_probe_mfma(elm_handle* h, elm_dtype dt, int32_t random_operands, double* tflops,
+                          double* ms);
+/* Streaming read of `bytes` of the caller's device buffer (16-byte
+ * non-temporal loads, grid-stride): gbs (host) receives GB/s.  buf 16-byte
+ * aligned, bytes >= 1 MiB.  Synchronises. */
+elm_status elm_probe_stream(elm_handle* h, const void* buf, int64_t bytes, double* gbs, double* ms);
+/* Direct global->LDS loads as the 16-bit Gram stages its operands: 1024
+ * workgroups of 4 waves each stream 32 KB stages (16-byte loads, one stage
+ * in flight) into four LDS buffers, over consecutive parts of the caller's
+ * buffer (resident = 0) or re-reading each workgroup's first stage
+ * (resident != 0: L2 hits).  gbs (host) receives the aggregate GB/s.  buf
+ * 16-byte aligned, bytes >= 128 MiB.  Synchronises. */
+elm_status elm_probe_dma(elm_handle* h, const void* buf, int64_t bytes, int32_t resident, double* gbs,
+                         double* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libelm.so")
 OBJ_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["abi.hip", "hidden.hip", "gram.hip", "pchol.hip", "chol.hip", "gemm.hip", "solve.hip",
-           "refine.hip", "predict.hip", "block.hip", "grow.hip"]
+           "refine.hip", "predict.hip", "block.hip", "grow.hip", "probe.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1637,6 +1637,39 @@ elm_status elm_autotune_batch(elm_handle* h, int32_t count, const elm_problem* p
     });
 }
 
+elm_status elm_probe_mfma(elm_handle* h, elm_dtype dt, int32_t random_operands, double* tflops, double* ms) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(dt == ELM_BF16 || dt == ELM_F64, ELM_ERR_UNSUPPORTED, "probe dtypes: BF16, FP64");
+        REQUIRE(tflops, ELM_ERR_INVALID_ARG, "tflops must be non-null");
+        elm::use_device(h);
+        *tflops = elm::probe_mfma(h->stream, dt, random_operands ? 1 : 0, ms);
+    });
+}
+
+elm_status elm_probe_stream(elm_handle* h, const void* buf, int64_t bytes, double* gbs, double* ms) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(buf && gbs && bytes >= (int64_t)1 << 20, ELM_ERR_INVALID_ARG,
+                "a buffer of at least 1 MiB and gbs must be given");
+        REQUIRE(((uintptr_t)buf & 15) == 0, ELM_ERR_INVALID_ARG, "buf must be 16-byte aligned");
+        elm::use_device(h);
+        *gbs = elm::probe_stream(h->stream, buf, bytes, ms);
+    });
+}
+
+elm_status elm_probe_dma(elm_handle* h, const void* buf, int64_t bytes, int32_t resident, double* gbs,
+                         double* ms) {
+    if (!h) return ELM_ERR_INVALID_ARG;
+    return elm::guarded(h, [&] {
+        REQUIRE(buf && gbs, ELM_ERR_INVALID_ARG, "buf and gbs must be non-null");
+        REQUIRE(bytes >= (int64_t)1024 * 4 * 32768, ELM_ERR_SHAPE, "the buffer must hold 4 stages per block");
+        REQUIRE(((uintptr_t)buf & 15) == 0, ELM_ERR_INVALID_ARG, "buf must be 16-byte aligned");
+        elm::use_device(h);
+        *gbs = elm::probe_dma(h->stream, buf, bytes, resident ? 1 : 0, ms);
+    });
+}
+
 elm_status elm_batch_get_report(const elm_handle* h, elm_batch_report* out) {
     if (!h || !out) return ELM_ERR_INVALID_ARG;
     *out = h->batch_report;

@@ -448,6 +448,11 @@ void block_solve(hipStream_t s, int64_t L, int64_t m, int64_t split, const doubl
                  const double* Z, int64_t ldz, const int32_t* piv, double thr, double* beta, int64_t ldb,
                  Workspace& ws);
 
+// probe.hip: device ceilings (measurement only); each returns TFLOP/s or GB/s
+double probe_mfma(hipStream_t s, elm_dtype dt, int random_ops, double* ms_out);
+double probe_stream(hipStream_t s, const void* buf, int64_t bytes, double* ms_out);
+double probe_dma(hipStream_t s, const void* buf, int64_t bytes, int resident, double* ms_out);
+
 // grow.hip: the factor g of H' = [H Hn] (N x L2 FP64 sample-major, ld ldh, its
 // first f->n columns the H of factor f: FP64 Gram, N >= L2) from f and the new
 // Gram blocks, keeping f's accepted pivots first.  Returns false (g untouched

@@ -1,0 +1,199 @@
+// Measurement probes (not part of the method): the device ceilings the path's
+// kernels are held against.
+//   mfma    sustained rate of independent MFMAs issued from registers, with
+//           constant or random operands (the data-dependent power draw of
+//           random operands lowers the clock);
+//   stream  a streaming read of a caller's buffer (16-byte non-temporal
+//           loads, grid-stride), the refinement passes' ceiling;
+//   dma     direct global->LDS loads (global_load_lds_dwordx4) into 32 KB
+//           stages per workgroup, as the 16-bit Gram stages its operands,
+//           streaming a caller's buffer or re-reading one stage (L2 hits).
+#include "elm_internal.h"
+
+#include <algorithm>
+
+namespace elm {
+namespace {
+
+constexpr int PB = 256;  // threads per probe block
+
+__device__ inline uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+// 8 independent accumulator chains per wave; iters rounds of 8 MFMAs
+__global__ __launch_bounds__(PB) void mfma_bf16_probe(int iters, int random_ops, float* out) {
+    const uint32_t tid = blockIdx.x * PB + threadIdx.x;
+    bf8v a, b;
+    for (int e = 0; e < 8; ++e) {
+        // random: values in [0.5, 1) with random low mantissa bits; else 1.0
+        const uint32_t r = random_ops ? mix32(tid * 16 + e) : 0u;
+        const float fa = random_ops ? 0.5f + (float)(r & 0xFFFF) / 131072.0f : 1.0f;
+        const float fb = random_ops ? 0.5f + (float)(r >> 16) / 131072.0f : 1.0f;
+        a[e] = (__bf16)fa;
+        b[e] = (__bf16)fb;
+    }
+    f16v acc[8];
+    for (int c = 0; c < 8; ++c) acc[c] = f16v{};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[c], 0, 0, 0);
+    }
+    float s = 0.f;
+    for (int c = 0; c < 8; ++c)
+        for (int v = 0; v < 16; ++v) s += acc[c][v];
+    if (s == 12345.0f) out[tid] = s;  // keeps the chains live; never true in practice
+}
+
+__global__ __launch_bounds__(PB) void mfma_f64_probe(int iters, int random_ops, double* out) {
+    const uint32_t tid = blockIdx.x * PB + threadIdx.x;
+    const uint32_t r = random_ops ? mix32(tid) : 0u;
+    const double a = random_ops ? 0.5 + (double)(r & 0xFFFF) / 131072.0 : 1.0;
+    const double b = random_ops ? 0.5 + (double)(r >> 16) / 131072.0 : 1.0;
+    d4v acc[8];
+    for (int c = 0; c < 8; ++c) acc[c] = d4v{};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+    }
+    double s = 0.0;
+    for (int c = 0; c < 8; ++c)
+        for (int v = 0; v < 4; ++v) s += acc[c][v];
+    if (s == 12345.0) out[tid] = s;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(PB) void stream_probe(const u32x4* __restrict__ p, int64_t n16, double* out) {
+    int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * PB;
+    uint32_t acc = 0;
+    for (; i < n16; i += stride) {
+        const u32x4 v = __builtin_nontemporal_load(p + i);
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    if (acc == 0x9e3779b9u) out[0] = (double)acc;  // keeps the loads live
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// each block streams stages of 32 KB (32 loads of 1 KB) into 4 LDS buffers,
+// up to 2 stages in flight, like the Gram's operand loads
+__global__ __launch_bounds__(PB) void dma_probe(const unsigned char* __restrict__ p, int64_t stages_per_block,
+                                                int64_t stage_stride, int resident, double* out) {
+    __shared__ __attribute__((aligned(1024))) unsigned char smem[4 * 32768];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const unsigned char* base = p + (int64_t)blockIdx.x * stages_per_block * stage_stride;
+    for (int64_t st = 0; st < stages_per_block; ++st) {
+        const unsigned char* src = base + (resident ? 0 : st * stage_stride);
+        unsigned char* dst = smem + (st & 3) * 32768 + wave * 1024;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)(i * 4 + wave) * 1024 + lane * 16),
+                                             (lds_void_t*)(dst + i * 4096), 16, 0, 0);
+        __builtin_amdgcn_s_waitcnt((16 & 15) | ((16 >> 4) << 14) | (7 << 4) | (15 << 8));  // 2 stages in flight
+        __builtin_amdgcn_s_barrier();
+    }
+    __builtin_amdgcn_s_waitcnt(0 | (0 << 14) | (7 << 4) | (15 << 8));
+    __syncthreads();
+    if (tid == 0 && smem[5] == 0x5a && smem[77777] == 0xa5) out[blockIdx.x] = 1.0;
+}
+
+}  // namespace
+
+double probe_mfma(hipStream_t s, elm_dtype dt, int random_ops, double* ms_out) {
+    const int blocks = 256 * 4 * 2 / (PB / 64);   // 2 waves per SIMD on 256 CUs
+    const int iters = dt == ELM_BF16 ? 20000 : 20000;
+    void* out = nullptr;
+    ELM_HIP_TRY(hipMalloc(&out, (size_t)blocks * PB * sizeof(double)));
+    struct Free {
+        void* p;
+        ~Free() { (void)hipFree(p); }
+    } fr{out};
+    hipEvent_t e0, e1;
+    ELM_HIP_TRY(hipEventCreate(&e0));
+    ELM_HIP_TRY(hipEventCreate(&e1));
+    auto launch = [&] {
+        if (dt == ELM_BF16) mfma_bf16_probe<<<blocks, PB, 0, s>>>(iters, random_ops, (float*)out);
+        else mfma_f64_probe<<<blocks, PB, 0, s>>>(iters, random_ops, (double*)out);
+        ELM_LAUNCH_CHECK();
+    };
+    launch();
+    ELM_HIP_TRY(hipEventRecord(e0, s));
+    launch();
+    ELM_HIP_TRY(hipEventRecord(e1, s));
+    ELM_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    ELM_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const double waves = (double)blocks * (PB / 64);
+    const double flops_per = dt == ELM_BF16 ? 2.0 * 32 * 32 * 16 : 2.0 * 16 * 16 * 4;
+    if (ms_out) *ms_out = ms;
+    return waves * iters * 8 * flops_per / (ms * 1e-3) / 1e12;
+}
+
+double probe_stream(hipStream_t s, const void* buf, int64_t bytes, double* ms_out) {
+    const int64_t n16 = bytes / 16;
+    const int blocks = 256 * 32;
+    double* out = nullptr;
+    ELM_HIP_TRY(hipMalloc(&out, sizeof(double)));
+    struct Free {
+        void* p;
+        ~Free() { (void)hipFree(p); }
+    } fr{out};
+    hipEvent_t e0, e1;
+    ELM_HIP_TRY(hipEventCreate(&e0));
+    ELM_HIP_TRY(hipEventCreate(&e1));
+    stream_probe<<<blocks, PB, 0, s>>>((const u32x4*)buf, n16, out);
+    ELM_LAUNCH_CHECK();
+    ELM_HIP_TRY(hipEventRecord(e0, s));
+    stream_probe<<<blocks, PB, 0, s>>>((const u32x4*)buf, n16, out);
+    ELM_LAUNCH_CHECK();
+    ELM_HIP_TRY(hipEventRecord(e1, s));
+    ELM_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    ELM_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ms_out) *ms_out = ms;
+    return (double)(n16 * 16) / (ms * 1e-3) / 1e9;
+}
+
+double probe_dma(hipStream_t s, const void* buf, int64_t bytes, int resident, double* ms_out) {
+    // 4 blocks per CU would not fit their LDS; one 128 KB block per CU, 4 per
+    // XCD round, as many rounds as the buffer allows
+    const int blocks = 256 * 4;
+    const int64_t stage = 32768;
+    const int64_t per_block = bytes / ((int64_t)blocks * stage);
+    if (per_block < 4) throw Error{ELM_ERR_SHAPE, "dma probe: buffer too small"};
+    double* out = nullptr;
+    ELM_HIP_TRY(hipMalloc(&out, (size_t)blocks * sizeof(double)));
+    struct Free {
+        void* p;
+        ~Free() { (void)hipFree(p); }
+    } fr{out};
+    hipEvent_t e0, e1;
+    ELM_HIP_TRY(hipEventCreate(&e0));
+    ELM_HIP_TRY(hipEventCreate(&e1));
+    dma_probe<<<blocks, PB, 0, s>>>((const unsigned char*)buf, per_block, stage, resident, out);
+    ELM_LAUNCH_CHECK();
+    ELM_HIP_TRY(hipEventRecord(e0, s));
+    dma_probe<<<blocks, PB, 0, s>>>((const unsigned char*)buf, per_block, stage, resident, out);
+    ELM_LAUNCH_CHECK();
+    ELM_HIP_TRY(hipEventRecord(e1, s));
+    ELM_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    ELM_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ms_out) *ms_out = ms;
+    return (double)blocks * per_block * stage / (ms * 1e-3) / 1e9;
+}
+
+}  // namespace elm

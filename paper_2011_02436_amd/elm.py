@@ -143,6 +143,9 @@ def _load():
         "elm_profile_read": ([vp, ctypes.POINTER(StageTimes)], i32),
         "elm_batch_get_report": ([vp, ctypes.POINTER(BatchReport)], i32),
         "elm_tune_table_get": ([vp, ctypes.POINTER(TuneEntry), i32, ctypes.POINTER(i32)], i32),
+        "elm_probe_mfma": ([vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], i32),
+        "elm_probe_stream": ([vp, vp, i64, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], i32),
+        "elm_probe_dma": ([vp, vp, i64, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], i32),
         "elm_tune_table_set": ([vp, ctypes.POINTER(TuneEntry), i32], i32),
         "elm_tune_table_save": ([vp, ctypes.c_char_p], i32),
         "elm_tune_table_load": ([vp, ctypes.c_char_p], i32),
@@ -163,7 +166,8 @@ EXPORTED = ["elm_create", "elm_destroy", "elm_set_stream", "elm_status_string", 
             "elm_pinv_solve", "elm_block_solve", "elm_predict", "elm_predict_hidden",
             "elm_autotune_gram", "elm_set_option", "elm_get_option", "elm_profile_enable",
             "elm_profile_read", "elm_batch_get_report", "elm_tune_table_get", "elm_tune_table_set",
-            "elm_tune_table_save", "elm_tune_table_load", "elm_autotune_batch"]
+            "elm_tune_table_save", "elm_tune_table_load", "elm_autotune_batch", "elm_probe_mfma",
+            "elm_probe_stream", "elm_probe_dma"]
 
 
 def _status_string(st: int) -> str:
@@ -560,6 +564,33 @@ def autotune_batch(problems, precision: str = "bf16", ir_tol: float = 1e-10,
                                     ctypes.byref(after)), "elm_autotune_batch")
     del keep
     return before.value, after.value
+
+
+def probe_mfma(dtype: str = "bf16", random_operands: bool = True) -> Tuple[float, float]:
+    """Sustained MFMA rate from registers: (TFLOP/s, ms)."""
+    h = handle()
+    tf, ms = ctypes.c_double(), ctypes.c_double()
+    h.check(_lib.elm_probe_mfma(h.ptr, {"bf16": ELM_BF16, "fp64": ELM_F64}[dtype], 1 if random_operands else 0,
+                                ctypes.byref(tf), ctypes.byref(ms)), "elm_probe_mfma")
+    return tf.value, ms.value
+
+
+def probe_stream(buf: torch.Tensor) -> Tuple[float, float]:
+    """Streaming read of a device tensor: (GB/s, ms)."""
+    h = handle()
+    gbs, ms = ctypes.c_double(), ctypes.c_double()
+    h.check(_lib.elm_probe_stream(h.ptr, ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                                  ctypes.byref(gbs), ctypes.byref(ms)), "elm_probe_stream")
+    return gbs.value, ms.value
+
+
+def probe_dma(buf: torch.Tensor, resident: bool = False) -> Tuple[float, float]:
+    """Direct global->LDS staging as the 16-bit Gram does it: (GB/s, ms)."""
+    h = handle()
+    gbs, ms = ctypes.c_double(), ctypes.c_double()
+    h.check(_lib.elm_probe_dma(h.ptr, ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                               1 if resident else 0, ctypes.byref(gbs), ctypes.byref(ms)), "elm_probe_dma")
+    return gbs.value, ms.value
 
 
 def batch_report() -> dict:
