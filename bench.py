@@ -264,7 +264,9 @@ def run_stage(args):
     p = wl.smooth_regression(N=args.N, L=args.L)
     X, W, b, T = (torch.from_numpy(a).to(dev) for a in (p.X, p.W, p.b, p.T))
     H64 = torch.empty((p.N, p.L), dtype=torch.float64, device=dev)
-    Hb = torch.empty((p.L, p.N), dtype=torch.bfloat16, device=dev)
+    # the BF16 copy with the library's own padding: rows of a multiple of 64
+    # elements, as the training path lays it out
+    Hb = torch.empty((p.L, -(-p.N // 64) * 64), dtype=torch.bfloat16, device=dev)[:, :p.N]
     elm.elm_hidden(X, W, b, H=H64, Hlp=Hb)
     torch.cuda.synchronize()
 

@@ -786,8 +786,9 @@ void launch_predict(hipStream_t s, elm_dtype dt, int64_t N, int64_t d, int64_t L
                     Workspace& ws);
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-// leading dimension of an internal node-major low-precision copy of H: rows
-// start on 16-byte boundaries, so the 16-bit Gram takes its vector loads
-inline int64_t lp_ld(int64_t N) { return cdiv(N, 8) * 8; }
+// leading dimension of an internal node-major low-precision copy of H: a
+// multiple of 64 elements, so that the 16-bit Gram's 64-sample row segments
+// are whole 128-byte cache lines
+inline int64_t lp_ld(int64_t N) { return cdiv(N, 64) * 64; }
 
 }  // namespace elm

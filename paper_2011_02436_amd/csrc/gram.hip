@@ -218,35 +218,46 @@ int64_t run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, 
 // Each block owns one work item (split-K chunk, tile bi <= bj) from a table
 // built on the host.  4 waves in a 2 x 2 grid each accumulate a 128 x 128
 // sub-tile as 4 x 4 blocks of the 32x32x16 MFMA (256 FP32 accumulators per
-// lane, in AGPRs).  K is consumed in stages of 32 samples through GNS (4 or 5)
-// LDS buffers filled by direct global->LDS loads (global_load_lds_dwordx4)
-// issued GNS - 1 stages ahead: no staging registers, and the loads of later stages
-// stay in flight across the per-stage barrier (an explicit vmcnt wait plus a
-// bare s_barrier; a full __syncthreads would drain them).  Every stage issues
-// the same number of loads (past the last full stage they re-read it into a
-// buffer nobody reads again), so the wait count is static.
-// In LDS a tile row is 4 chunks of 16 B; chunk c of row r sits at position
-// c ^ ((r >> 2) & 3): a 64-byte row covers 16 of the 64 banks, r % 4 picks
-// which 16, and the swizzle spreads rows r, r + 4, r + 8, r + 12 over the
-// four 16-byte slots, so the 16 consecutive rows that one quarter-wave of an
-// operand read (ds_read_b128) touches hit 16 distinct 4-bank groups.  Ragged
-// tiles load clamped rows on the same path; the K tail and unaligned input
-// take a plain path.
+// lane, in AGPRs).  K is consumed in stages of 64 samples: a stage holds
+// 128 contiguous bytes of each of the 512 operand rows (64 KB), and two LDS
+// buffers alternate, filled by direct global->LDS loads
+// (global_load_lds_dwordx4) one stage ahead.  When the leading dimension is
+// a multiple of 64 elements (the library pads its own 16-bit copies so), a
+// row's stage segment is exactly one 128-byte cache line and a load
+// instruction moves 8 whole lines; unaligned rows straddle two lines and
+// cost about a tenth of the Gram's time.  The load path, not the MFMAs, sets
+// the pace of this kernel: each load instruction occupies the CU's address
+// unit for about 16 cycles, so a stage's 64 instructions are spread over the
+// MFMAs of two k16 steps rather than issued in a burst that stalls the
+// waves.  The loads stay in flight across the steps (explicit vmcnt and
+// lgkmcnt waits with bare s_barriers: a full __syncthreads would drain them).
+// Every stage issues the same number of loads (past the last full stage they
+// re-read it into a buffer nobody reads again), so the wait counts are
+// static.
+// In LDS a tile row is 8 chunks of 16 B; chunk c of row r sits at position
+// c ^ ((r >> 1) & 7): two rows share one 256-byte bank line, r % 2 picks the
+// half, and the swizzle spreads the 8 row pairs of 16 consecutive rows over
+// the 8 slots of a half, so the 16 rows that one quarter-wave of an operand
+// read (ds_read_b128) touches hit 16 distinct 4-bank groups.  Ragged tiles
+// load clamped rows on the same path; the K tail (fewer than 64 samples) and
+// unaligned input take a plain path, 32 samples at a time.
 // ---------------------------------------------------------------------------
 constexpr int GT = 256;    // tile
-constexpr int GBK = 32;    // samples per stage
-constexpr int G_OPB = GT * GBK * 2;            // bytes per operand per stage (16 KB)
-constexpr int G_STB = 2 * G_OPB;               // bytes per stage (32 KB)
+constexpr int GBK = 64;    // samples per stage of the load path (128-byte row segments)
+constexpr int G_OPB = GT * GBK * 2;            // bytes per operand per stage (32 KB)
+constexpr int G_STB = 2 * G_OPB;               // bytes per stage (64 KB)
+constexpr int GTK = 32;    // samples per step of the plain tail path
+constexpr int GT_OPB = GT * GTK * 2;           // bytes per operand per tail step (16 KB)
 #define G_VMCNT(N) (((N) & 15) | (((N) >> 4) << 14) | (7 << 4) | (15 << 8))
 #define G_LGKMCNT(N) (15 | (3 << 14) | (7 << 4) | ((N) << 8))
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <typename HT, int GNS>  // GNS: LDS stages, GNS - 2 of them in flight
+template <typename HT>
 __device__ __forceinline__ void gram_lp256_body(const int4 wk, int64_t n, int64_t K, int64_t kc_len,
                                                 const HT* __restrict__ A, int64_t ld,
                                                 float* __restrict__ part) {
-    __shared__ __attribute__((aligned(1024))) unsigned char smem[GNS * G_STB];
+    __shared__ __attribute__((aligned(1024))) unsigned char smem[2 * G_STB];
     typedef typename Mfma32<HT>::vec_t vec_t;
     if (wk.x < 0) return;
     const int64_t r0 = (int64_t)wk.y * GT, c0 = (int64_t)wk.z * GT;
@@ -262,41 +273,6 @@ __device__ __forceinline__ void gram_lp256_body(const int4 wk, int64_t n, int64_
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = f16v{};
 
-    // one stage from LDS buffer ST: read both k16 steps' fragments, then MFMAs
-#define GRAM_COMPUTE(ST)                                                                   \
-    do {                                                                                   \
-        const unsigned char* sA = smem + (ST) * G_STB;                                     \
-        const unsigned char* sB = sA + G_OPB;                                              \
-        vec_t a0[4], b0[4], a1[4], b1[4];                                                  \
-        _Pragma("unroll") for (int x = 0; x < 4; ++x) {                                    \
-            const int ra = wm * 128 + x * 32 + (lane & 31);                                \
-            const int rb = wn * 128 + x * 32 + (lane & 31);                                \
-            const int c = lane >> 5;                                                       \
-            a0[x] = *(const vec_t*)(sA + ra * 64 + ((c ^ ((ra >> 2) & 3)) << 4));          \
-            b0[x] = *(const vec_t*)(sB + rb * 64 + ((c ^ ((rb >> 2) & 3)) << 4));          \
-            a1[x] = *(const vec_t*)(sA + ra * 64 + (((c + 2) ^ ((ra >> 2) & 3)) << 4));    \
-            b1[x] = *(const vec_t*)(sB + rb * 64 + (((c + 2) ^ ((rb >> 2) & 3)) << 4));    \
-        }                                                                                  \
-        _Pragma("unroll") for (int x = 0; x < 4; ++x)                                      \
-            _Pragma("unroll") for (int y = 0; y < 4; ++y)                                  \
-                acc[x][y] = Mfma32<HT>::op(a0[x], b0[y], acc[x][y]);                       \
-        _Pragma("unroll") for (int x = 0; x < 4; ++x)                                      \
-            _Pragma("unroll") for (int y = 0; y < 4; ++y)                                  \
-                acc[x][y] = Mfma32<HT>::op(a1[x], b1[y], acc[x][y]);                       \
-    } while (0)
-    // fragments of one k16 half (H = 0: samples 0-15 of the stage, 1: 16-31)
-#define GRAM_READ(FA, FB, ST, H)                                                           \
-    do {                                                                                   \
-        const unsigned char* sA = smem + (ST) * G_STB;                                     \
-        const unsigned char* sB = sA + G_OPB;                                              \
-        _Pragma("unroll") for (int x = 0; x < 4; ++x) {                                    \
-            const int ra = wm * 128 + x * 32 + (lane & 31);                                \
-            const int rb = wn * 128 + x * 32 + (lane & 31);                                \
-            const int c = (lane >> 5) + 2 * (H);                                           \
-            FA[x] = *(const vec_t*)(sA + ra * 64 + ((c ^ ((ra >> 2) & 3)) << 4));          \
-            FB[x] = *(const vec_t*)(sB + rb * 64 + ((c ^ ((rb >> 2) & 3)) << 4));          \
-        }                                                                                  \
-    } while (0)
 #define GRAM_MMA(FA, FB)                                                                   \
     do {                                                                                   \
         _Pragma("unroll") for (int x = 0; x < 4; ++x)                                      \
@@ -309,74 +285,130 @@ __device__ __forceinline__ void gram_lp256_body(const int4 wk, int64_t n, int64_
     const bool interior = vec_ok;  // block-uniform
     const int64_t nfull = interior ? (kend - kbeg) / GBK : 0;
     if (nfull > 0) {
+        // fragments of k16 step S (0..3) of the stage in buffer BUF
+#define GRAM_READ(FA, FB, BUF, S)                                                          \
+    do {                                                                                   \
+        const unsigned char* sA = smem + (BUF) * G_STB;                                    \
+        const unsigned char* sB = sA + G_OPB;                                              \
+        _Pragma("unroll") for (int x = 0; x < 4; ++x) {                                    \
+            const int ra = wm * 128 + x * 32 + (lane & 31);                                \
+            const int rb = wn * 128 + x * 32 + (lane & 31);                                \
+            const int c = (lane >> 5) + 2 * (S);                                           \
+            FA[x] = *(const vec_t*)(sA + ra * 128 + ((c ^ ((ra >> 1) & 7)) << 4));         \
+            FB[x] = *(const vec_t*)(sB + rb * 128 + ((c ^ ((rb >> 1) & 7)) << 4));         \
+        }                                                                                  \
+    } while (0)
         // DMA lane mapping: instruction i of wave w fills LDS bytes
-        // [(4 i + w) * 1024, +1024) of an operand buffer = rows (4 i + w) * 16
-        // .. +16, lane l -> row (4 i + w) * 16 + l / 4, position l % 4, which
-        // holds global chunk (l % 4) ^ ((row >> 2) & 3).
-        const HT* asrc[4];
-        const HT* bsrc[4];
+        // [(4 i + w) * 1024, +1024) of an operand buffer = rows (4 i + w) * 8
+        // .. +8, lane l -> row (4 i + w) * 8 + l / 8, position l % 8, which
+        // holds global chunk (l % 8) ^ ((row >> 1) & 7).
+        const HT* asrc[8];
+        const HT* bsrc[8];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = (4 * i + wave) * 16 + (lane >> 2);
-            const int c = (lane & 3) ^ ((row >> 2) & 3);
+        for (int i = 0; i < 8; ++i) {
+            const int row = (4 * i + wave) * 8 + (lane >> 3);
+            const int c = (lane & 7) ^ ((row >> 1) & 7);
             asrc[i] = A + min(r0 + row, n - 1) * ld + c * 8;
             bsrc[i] = A + min(c0 + row, n - 1) * ld + c * 8;
         }
         const int64_t klast = kbeg + (nfull - 1) * GBK;
-#define GRAM_DMA(STG, K0)                                                                    \
+        // loads Q0 .. Q0 + NL - 1 of the 16 that fill stage buffer BUF with
+        // samples K0 .. K0 + 63 (clamped to the last full stage): load q is
+        // instruction q / 2 of operand q % 2 (A rows, then B rows)
+#define GRAM_LOADS(BUF, K0, Q0, NL)                                                          \
     do {                                                                                     \
         const int64_t k_ = min((int64_t)(K0), klast);                                        \
-        unsigned char* dA = smem + ((STG) % GNS) * G_STB + wave * 1024;                      \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                      \
-            __builtin_amdgcn_global_load_lds((const void*)(asrc[i] + k_),                    \
-                                             (lds_void*)(dA + i * 4096), 16, 0, 0);          \
-            __builtin_amdgcn_global_load_lds((const void*)(bsrc[i] + k_),                    \
-                                             (lds_void*)(dA + G_OPB + i * 4096), 16, 0, 0);  \
+        unsigned char* dA = smem + (BUF) * G_STB + wave * 1024;                              \
+        _Pragma("unroll") for (int q = (Q0); q < (Q0) + (NL); ++q) {                         \
+            const int i = q >> 1;                                                            \
+            if (q & 1)                                                                       \
+                __builtin_amdgcn_global_load_lds((const void*)(bsrc[i] + k_),                \
+                                                 (lds_void*)(dA + G_OPB + i * 4096), 16, 0, 0); \
+            else                                                                             \
+                __builtin_amdgcn_global_load_lds((const void*)(asrc[i] + k_),                \
+                                                 (lds_void*)(dA + i * 4096), 16, 0, 0);      \
         }                                                                                    \
     } while (0)
-        // Fragment reads are software-pipelined against the MFMAs: the second
-        // half of stage st is read while the first half multiplies, and the
-        // first half of stage st + 1 while the second half multiplies.  The
-        // barrier between the halves publishes stage st + 1 (every wave has
-        // waited for its own loads of it) and retires buffer (st - 1) % GNS,
-        // which the loads issued right after it refill.
+        // one k16 step's 16 MFMAs with 8 of the loads of stage buffer BUF
+        // interleaved, one after every second MFMA, so that the load issue
+        // (about 16 cycles of the address unit per instruction) overlaps the
+        // MFMAs instead of stalling the wave in a burst
+#define GRAM_MMA_LOADS(FA, FB, BUF, K0, Q0)                                                  \
+    do {                                                                                     \
+        const int64_t k_ = min((int64_t)(K0), klast);                                        \
+        unsigned char* dA = smem + (BUF) * G_STB + wave * 1024;                              \
+        _Pragma("unroll") for (int q = 0; q < 16; ++q) {                                     \
+            acc[q >> 2][q & 3] = Mfma32<HT>::op(FA[q >> 2], FB[q & 3], acc[q >> 2][q & 3]);  \
+            if (q & 1) {                                                                     \
+                const int l = (Q0) + (q >> 1), i = l >> 1;                                   \
+                if (l & 1)                                                                   \
+                    __builtin_amdgcn_global_load_lds((const void*)(bsrc[i] + k_),            \
+                                                     (lds_void*)(dA + G_OPB + i * 4096), 16, 0, 0); \
+                else                                                                         \
+                    __builtin_amdgcn_global_load_lds((const void*)(asrc[i] + k_),            \
+                                                     (lds_void*)(dA + i * 4096), 16, 0, 0);  \
+            }                                                                                \
+        }                                                                                    \
+        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0); /* the step's 8 fragment reads */ \
+        _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                      \
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0); /* 2 MFMAs */                 \
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0); /* 1 load */                  \
+        }                                                                                    \
+    } while (0)
+        // Fragment reads are software-pipelined against the MFMAs: step s + 1
+        // is read while step s multiplies, and step 0 of stage st + 1 while
+        // step 3 of stage st multiplies.  The barrier before that last read
+        // publishes stage st + 1 (every wave has waited for its own loads of
+        // it) and retires buffer st % 2 (every wave has read its four steps).
+        // The 16 loads of stage st + 2 into that buffer go out with the next
+        // two steps' MFMAs: 8 with step 3 of stage st, 8 with step 0 of
+        // stage st + 1, and land during steps 1-3.
         vec_t f0a[4], f0b[4], f1a[4], f1b[4];
-#pragma unroll
-        for (int p = 0; p < GNS - 1; ++p) GRAM_DMA(p, kbeg + p * GBK);
-        __builtin_amdgcn_s_waitcnt(G_VMCNT(8 * (GNS - 2)));  // stage 0 landed
+        GRAM_LOADS(0, kbeg, 0, 16);
+        GRAM_LOADS(1, kbeg + GBK, 0, 8);
+        __builtin_amdgcn_s_waitcnt(G_VMCNT(8));  // stage 0 landed
         __builtin_amdgcn_s_barrier();
         GRAM_READ(f0a, f0b, 0, 0);
-        // (The reads of the first half of stage st + 1 are issued in the last
-        // iteration too, from a buffer whose contents are then unused: the
-        // count of LDS operations per iteration stays static, so the
-        // compiler's wait counts stay exact across the back edge.  The
-        // scheduling barriers keep the MFMAs on their side of the s_barrier.)
+        // (Step 0 of stage st + 1 is read in the last iteration too, from a
+        // buffer whose contents are then unused, and the loads past the last
+        // stage re-read it: the counts of LDS and memory operations per
+        // iteration stay static, so the wait counts stay exact across the
+        // back edge.  The scheduling barriers keep the MFMAs on their side
+        // of the s_barrier.)
         for (int64_t st = 0; st < nfull; ++st) {
-            const int cur = (int)(st % GNS);
-            // the first half's fragments were read during the previous MFMAs
+            const int cur = (int)(st & 1);
             __builtin_amdgcn_s_waitcnt(G_LGKMCNT(0));
             GRAM_READ(f1a, f1b, cur, 1);
+            GRAM_MMA_LOADS(f0a, f0b, cur ^ 1, kbeg + (st + 1) * GBK, 8);
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_waitcnt(G_LGKMCNT(0));
+            GRAM_READ(f0a, f0b, cur, 2);
+            __builtin_amdgcn_sched_barrier(0);
+            GRAM_MMA(f1a, f1b);
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_waitcnt(G_LGKMCNT(0));
+            GRAM_READ(f1a, f1b, cur, 3);
             __builtin_amdgcn_sched_barrier(0);
             GRAM_MMA(f0a, f0b);
             __builtin_amdgcn_sched_barrier(0);
-            // the second half's fragments were read during those MFMAs
             __builtin_amdgcn_s_waitcnt(G_LGKMCNT(0));
-            __builtin_amdgcn_s_waitcnt(G_VMCNT(8 * (GNS - 3)));  // stage st + 1 landed
+            __builtin_amdgcn_s_waitcnt(G_VMCNT(0));  // stage st + 1 landed
             __builtin_amdgcn_s_barrier();
             __builtin_amdgcn_sched_barrier(0);
-            GRAM_DMA(st + GNS - 1, kbeg + (st + GNS - 1) * GBK);
-            GRAM_READ(f0a, f0b, (int)((st + 1) % GNS), 0);
-            __builtin_amdgcn_sched_barrier(0);
-            GRAM_MMA(f1a, f1b);
+            GRAM_READ(f0a, f0b, cur ^ 1, 0);
+            GRAM_MMA_LOADS(f1a, f1b, cur, kbeg + (st + 2) * GBK, 0);
             __builtin_amdgcn_sched_barrier(0);
         }
         __builtin_amdgcn_s_waitcnt(G_VMCNT(0));
         __builtin_amdgcn_s_barrier();
-#undef GRAM_DMA
+#undef GRAM_LOADS
+#undef GRAM_MMA_LOADS
+#undef GRAM_READ
     }
     // what the DMA path did not cover: the K tail of an interior item, or a
-    // whole ragged/unaligned item, one stage at a time through registers
-    for (int64_t k0 = kbeg + nfull * GBK; k0 < kend; k0 += GBK) {
+    // whole ragged/unaligned item, 32 samples at a time through registers
+    // (LDS rows of 64 bytes, chunk c of row r at position c ^ ((r >> 2) & 3))
+    for (int64_t k0 = kbeg + nfull * GBK; k0 < kend; k0 += GTK) {
         const uint16_t* A16 = (const uint16_t*)A;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -396,14 +428,26 @@ __device__ __forceinline__ void gram_lp256_body(const int4 wk, int64_t n, int64_
                 wb[e] = blo | (bhi << 16);
             }
             *(uint4*)(smem + q * 16) = make_uint4(wa[0], wa[1], wa[2], wa[3]);
-            *(uint4*)(smem + G_OPB + q * 16) = make_uint4(wb[0], wb[1], wb[2], wb[3]);
+            *(uint4*)(smem + GT_OPB + q * 16) = make_uint4(wb[0], wb[1], wb[2], wb[3]);
         }
         __syncthreads();
-        GRAM_COMPUTE(0);
+        vec_t a0[4], b0[4], a1[4], b1[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const int ra = wm * 128 + x * 32 + (lane & 31);
+            const int rb = wn * 128 + x * 32 + (lane & 31);
+            const int c = lane >> 5;
+            const unsigned char* sA = smem;
+            const unsigned char* sB = smem + GT_OPB;
+            a0[x] = *(const vec_t*)(sA + ra * 64 + ((c ^ ((ra >> 2) & 3)) << 4));
+            b0[x] = *(const vec_t*)(sB + rb * 64 + ((c ^ ((rb >> 2) & 3)) << 4));
+            a1[x] = *(const vec_t*)(sA + ra * 64 + (((c + 2) ^ ((ra >> 2) & 3)) << 4));
+            b1[x] = *(const vec_t*)(sB + rb * 64 + (((c + 2) ^ ((rb >> 2) & 3)) << 4));
+        }
+        GRAM_MMA(a0, b0);
+        GRAM_MMA(a1, b1);
         __syncthreads();
     }
-#undef GRAM_COMPUTE
-#undef GRAM_READ
 #undef GRAM_MMA
 
     float* out = part + (int64_t)wk.w * (GT * GT);
@@ -419,24 +463,24 @@ __device__ __forceinline__ void gram_lp256_body(const int4 wk, int64_t n, int64_
             }
 }
 
-template <typename HT, int GNS>
+template <typename HT>
 __global__ __launch_bounds__(256) void gram_lp256_kernel(int64_t n, int64_t K, int64_t kc_len,
                                                          const HT* __restrict__ A, int64_t ld,
                                                          float* __restrict__ part,
                                                          const int4* __restrict__ work) {
-    gram_lp256_body<HT, GNS>(work[blockIdx.x], n, K, kc_len, A, ld, part);
+    gram_lp256_body<HT>(work[blockIdx.x], n, K, kc_len, A, ld, part);
 }
 
 // The same work items without a table: block b is split b / ntile, upper tile
 // b % ntile, partial slot b (one launch covers every item in item order).
-template <typename HT, int GNS>
+template <typename HT>
 __global__ __launch_bounds__(256) void gram_lp256_direct_kernel(int64_t n, int64_t K, int64_t kc_len,
                                                                 const HT* __restrict__ A, int64_t ld,
                                                                 float* __restrict__ part, int64_t ntile) {
     const int64_t b = blockIdx.x;
     int bi, bj;
     tile_coords(b % ntile, bi, bj);
-    gram_lp256_body<HT, GNS>(int4{(int)(b / ntile), bi, bj, (int)b}, n, K, kc_len, A, ld, part);
+    gram_lp256_body<HT>(int4{(int)(b / ntile), bi, bj, (int)b}, n, K, kc_len, A, ld, part);
 }
 
 // M[i][j] = M[j][i] = sum over splits (in order, FP64) of the 256-tile partials;
@@ -512,12 +556,12 @@ __global__ __launch_bounds__(NT) void diag_max_kernel(int64_t n, const double* _
 // Grouped Grams of a batch (GramDesc): the blocks of a problem run over its
 // work items exactly as its single launches would.
 // ---------------------------------------------------------------------------
-template <typename HT, int GNS>
+template <typename HT>
 __global__ __launch_bounds__(256) void gram_lp256_grouped(const GramDesc* __restrict__ d,
                                                           GroupSched g) {
     int64_t lb;
     const GramDesc& q = d[group_problem(g, lb)];
-    gram_lp256_body<HT, GNS>(q.work[lb], q.n, q.K, q.kc_len, (const HT*)q.A, q.ld, (float*)q.part);
+    gram_lp256_body<HT>(q.work[lb], q.n, q.K, q.kc_len, (const HT*)q.A, q.ld, (float*)q.part);
 }
 
 template <typename T, bool KCONTIG>
@@ -621,15 +665,6 @@ static int pick_splits(int64_t ntile, int64_t K) {
     return (int)best;
 }
 
-// LDS stages of the 16-bit Gram pipeline (4 or 5; ELM_GRAM_STAGES overrides the default)
-static int gram_stages() {
-    static const int ns = [] {
-        const char* e = std::getenv("ELM_GRAM_STAGES");
-        return (e && std::atoi(e) == 5) ? 5 : 4;
-    }();
-    return ns;
-}
-
 // K splits of the 16-bit Gram (ELM_GRAM_SPLITS, 1..64, overrides the choice)
 static int gram_splits_override() {
     static const int v = [] {
@@ -725,16 +760,9 @@ void launch_gram_grouped(hipStream_t s, int stage, int kind, const GramDesc* d, 
     if (g.count <= 0 || g.blocks <= 0) return;
     const unsigned grid = (unsigned)g.blocks;
     if (stage == 0) {
-        const bool five = gram_stages() == 5;
         switch (kind) {
-            case GRAM_BF16:
-                if (five) gram_lp256_grouped<__bf16, 5><<<grid, 256, 0, s>>>(d, g);
-                else gram_lp256_grouped<__bf16, 4><<<grid, 256, 0, s>>>(d, g);
-                break;
-            case GRAM_F16:
-                if (five) gram_lp256_grouped<_Float16, 5><<<grid, 256, 0, s>>>(d, g);
-                else gram_lp256_grouped<_Float16, 4><<<grid, 256, 0, s>>>(d, g);
-                break;
+            case GRAM_BF16: gram_lp256_grouped<__bf16><<<grid, 256, 0, s>>>(d, g); break;
+            case GRAM_F16: gram_lp256_grouped<_Float16><<<grid, 256, 0, s>>>(d, g); break;
             case GRAM_F32: gram16_grouped<float, true><<<grid, NT, 0, s>>>(d, g); break;
             default: gram16_grouped<double, false><<<grid, NT, 0, s>>>(d, g); break;
         }
@@ -765,22 +793,12 @@ int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, 
     float* part = (float*)ws.get("gram_part", (size_t)ntile * nsplit_eff * GT * GT * sizeof(float));
     {
         StageScope sc(ws.prof, ELM_STAGE_GRAM, s);
-        const int ns = gram_stages();
-        if (dt == ELM_BF16) {
-            if (ns == 5)
-                gram_lp256_kernel<__bf16, 5><<<(unsigned)nblocks, 256, 0, s>>>(L, N, kc_len, (const __bf16*)Hn,
-                                                                             ldn, part, dtab);
-            else
-                gram_lp256_kernel<__bf16, 4><<<(unsigned)nblocks, 256, 0, s>>>(L, N, kc_len, (const __bf16*)Hn,
-                                                                             ldn, part, dtab);
-        } else {
-            if (ns == 5)
-                gram_lp256_kernel<_Float16, 5><<<(unsigned)nblocks, 256, 0, s>>>(
-                    L, N, kc_len, (const _Float16*)Hn, ldn, part, dtab);
-            else
-                gram_lp256_kernel<_Float16, 4><<<(unsigned)nblocks, 256, 0, s>>>(
-                    L, N, kc_len, (const _Float16*)Hn, ldn, part, dtab);
-        }
+        if (dt == ELM_BF16)
+            gram_lp256_kernel<__bf16><<<(unsigned)nblocks, 256, 0, s>>>(L, N, kc_len, (const __bf16*)Hn, ldn,
+                                                                        part, dtab);
+        else
+            gram_lp256_kernel<_Float16><<<(unsigned)nblocks, 256, 0, s>>>(L, N, kc_len, (const _Float16*)Hn, ldn,
+                                                                          part, dtab);
         ELM_LAUNCH_CHECK();
     }
     StageScope sc(ws.prof, ELM_STAGE_GRAM_REDUCE, s);
@@ -887,20 +905,10 @@ void launch_gram_noalloc(hipStream_t s, int device, elm_dtype dt, int64_t N, int
         throw Error{ELM_ERR_SHAPE, "Gram order too large for the static scratch of elm_gram_noalloc"};
     float* part = (float*)scr;
     const unsigned grid = (unsigned)(ntile * nsplit_eff);
-    const bool five = gram_stages() == 5;
-    if (dt == ELM_BF16) {
-        if (five)
-            gram_lp256_direct_kernel<__bf16, 5><<<grid, 256, 0, s>>>(L, N, kc_len, (const __bf16*)H, ldh, part, ntile);
-        else
-            gram_lp256_direct_kernel<__bf16, 4><<<grid, 256, 0, s>>>(L, N, kc_len, (const __bf16*)H, ldh, part, ntile);
-    } else {
-        if (five)
-            gram_lp256_direct_kernel<_Float16, 5><<<grid, 256, 0, s>>>(L, N, kc_len, (const _Float16*)H, ldh, part,
-                                                                       ntile);
-        else
-            gram_lp256_direct_kernel<_Float16, 4><<<grid, 256, 0, s>>>(L, N, kc_len, (const _Float16*)H, ldh, part,
-                                                                       ntile);
-    }
+    if (dt == ELM_BF16)
+        gram_lp256_direct_kernel<__bf16><<<grid, 256, 0, s>>>(L, N, kc_len, (const __bf16*)H, ldh, part, ntile);
+    else
+        gram_lp256_direct_kernel<_Float16><<<grid, 256, 0, s>>>(L, N, kc_len, (const _Float16*)H, ldh, part, ntile);
     ELM_LAUNCH_CHECK();
     gram_reduce256_kernel<<<dim3((unsigned)ntile, RSUBS), NT, 0, s>>>(L, part, ntile, nsplit_eff, M, ldm);
     ELM_LAUNCH_CHECK();
