@@ -16,9 +16,10 @@
 // Organisation, per diagonal block of CB positions:
 //   strip         the block rows take the updates of the earlier block rows
 //                 of their group of GB rows            (FP64 MFMA GEMM)
-//   potrf_block   one workgroup: the block's Cholesky factor (held in
-//                 registers), written to U, then its inverse (in LDS), written
-//                 to W
+//   potrf_block   one workgroup: the block's Cholesky factor, panel by
+//                 panel in LDS (one wave's register steps per 16 x 16
+//                 diagonal block, MFMA tiles for the rest), written to U,
+//                 then its inverse, written to W
 //   copy          the block rows right of the diagonal block into T
 //   product       U12 = W^T T                           (FP64 MFMA GEMM)
 // and per group: S -= U_g^T U_g on the trailing matrix's upper tiles, with
@@ -66,159 +67,278 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
     return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
-// Steps j = 32 JH .. 32 JH + 31 of the block Cholesky below (JH: the slice of
-// the pivot rows, a compile-time index into the thread's registers).
-// Returns true when a pivot is <= thr (every thread alike).
-template <int JH>
-__device__ __forceinline__ bool potrf_slice(double (&u)[4][4], double (*rowb)[CB], int* stop, int nb,
-                                            double thr, int tx, int ty) {
-    for (int jl = 0; jl < 32; ++jl) {
-        const int j = 32 * JH + jl, pb = j & 1;
-        if (j >= nb) return false;
-        if (ty == jl) {
-            // the pivot (j, j): slot (JH, JH) of lane 32 (jl % 2) + jl of this wave
-            const double d = readlane_f64(u[JH][JH], 32 * (jl & 1) + jl);
-            const bool ok = d > thr;
-            const double dd = ok ? d : 1.0;
-            // 1 / sqrt(dd): the hardware estimate (about 23 bits) and two
-            // Newton-Raphson steps y <- y (3 - dd y^2) / 2, a short dependent
-            // chain on the step's critical path; the root is dd y
-            const double hd = 0.5 * dd;
-            double y = __builtin_amdgcn_rsq(dd);
-            y = y * fma(-hd, y * y, 1.5);
-            y = y * fma(-hd, y * y, 1.5);
-            const double rj = dd * y, inv = y;
+// acc += A(r, k) B(k, c) over k in [0, K) for one 16 x 16 tile, with A and B
+// read through accessors (all operand reads issued before the MFMAs); in the
+// result, register v of lane l is row 4 v + l / 16, column l % 16
+// (Mfma16<double>)
+template <int K, typename FA, typename FB>
+__device__ __forceinline__ d4v mma16_f64(d4v acc, int lane, FA fa, FB fb) {
+    const int r = lane & 15, kq = lane >> 4;
+    double av[K / 4], bv[K / 4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int c = tx + 32 * b;
-                const double x = c > j ? u[JH][b] * inv : (c == j ? rj : 0.0);
-                rowb[pb][c] = x;
-                u[JH][b] = x;
-            }
-            if (tx == 0) stop[pb] = ok ? 0 : 1;
-        }
-        __syncthreads();
-        if (stop[pb]) return true;  // the same value for every thread
-#pragma unroll
-        for (int a = JH; a < 4; ++a) {  // slices a < JH hold final rows only
-            if (a == JH && jl == 31) continue;  // nor does slice JH after its last step
-            const int i = ty + 32 * a;
-            const double ri = rowb[pb][i];
-#pragma unroll
-            for (int b = a; b < 4; ++b) {  // b < a: below the diagonal
-                const int c = tx + 32 * b;
-                if (i > j && c >= i) u[a][b] -= ri * rowb[pb][c];
-            }
-        }
+    for (int s = 0; s < K / 4; ++s) {
+        av[s] = fa(r, 4 * s + kq);
+        bv[s] = fb(4 * s + kq, r);
     }
-    return false;
+#pragma unroll
+    for (int s = 0; s < K / 4; ++s) acc = Mfma16<double>::op(av[s], bv[s], acc);
+    return acc;
 }
 
-// The CB x CB block lives in registers: thread (ty, tx) of a 32 x 32 grid
-// holds the 4 x 4 elements (ty + 32 a, tx + 32 b), so the 32 owners of a row
-// are one half of a wave.  Step j: the owners of row j read its pivot from
-// the diagonal owner's lane (readlane), scale the row and publish it in LDS
-// (with the stop decision); after one block barrier every thread applies
-// the row to its elements.  Row and pivot buffers alternate between steps,
-// so one barrier per step suffices.  A step's work is issue-bound, so the
-// element slices a step cannot change are skipped by block-uniform tests:
-// slices below the diagonal (b < a) and slices whose rows are all final.
-// The inverse is then formed in LDS by recursive doubling (log2 CB levels of
-// two small products each) rather than by CB more dependent steps.
+constexpr int PW = 16;      // panel of the block factorisation
+typedef double d2v __attribute__((ext_vector_type(2)));
+constexpr int TS = PW / 8;  // elements per side of a lane's tile in the panel wave
+
+// The CB x CB block is factored in LDS, one panel of PW rows at a time:
+//   1. one wave factors the panel's PW x PW diagonal block D = U_pp^T U_pp
+//      in registers (lane (rg, cg) of an 8 x 8 grid holds the TS x TS
+//      elements rows TS rg .., columns TS cg ..), PW dependent steps with no
+//      block barrier: step j reads its pivot from the diagonal owner
+//      (readlane), publishes row j of U_pp in LDS and applies it to the
+//      trailing elements.  The same steps build W_pp = U_pp^-1 by columns:
+//      with S[i][c] = sum_{k < j} W[i][k] U[k][c] kept up to date, column j
+//      of W is (e_j - S[:, j]) / U[j][j], and S then takes W[:, j] U[j][c].
+//   2. the panel's rows right of D: U_pq = W_pp^T A_pq (FP64 MFMA tiles);
+//   3. the trailing block: A_qq -= U_pq^T U_pq (FP64 MFMA tiles).
+// The block's inverse then comes from the diagonal blocks' W_pp by
+// recursive doubling over 16, 32 and 64: the inverse of [A B; 0 C] has the
+// off-diagonal block -A^-1 (B C^-1).  W_pp waits in the lower triangle of
+// its diagonal block (the diagonal in wdiag).  Positions past nb carry an
+// identity (no threshold test), so they add exact zeros.  The panel wave's
+// step is a short dependent chain (pivot, root, LDS round trip, FMAs); the
+// panel width keeps its per-step work small, and the rest of the block runs
+// on all 16 waves.
+template <int SZ>
+__device__ __forceinline__ void inverse_doubling_level(double (*Us)[CB + 1], int wave, int lane) {
+    constexpr int ts = SZ / 16;            // tiles per side of an SZ x SZ block
+    constexpr int per = ts * ts;           // tiles per pair of diagonal blocks
+    constexpr int pairs = CB / (2 * SZ);
+    static_assert(pairs * per <= CPT / 64, "one tile per wave");
+    const bool has = wave < pairs * per;
+    const int i0 = has ? 2 * SZ * (wave / per) : 0;
+    const int ra = 16 * ((wave % per) / ts), cb = 16 * (wave % ts);  // tile within the block
+    // T = B C^-1, staged across a barrier into B
+    d4v acc = d4v{0.0, 0.0, 0.0, 0.0};
+    if (has)
+        acc = mma16_f64<SZ>(
+            acc, lane, [&](int r, int k) { return Us[i0 + ra + r][i0 + SZ + k]; },
+            [&](int k, int c) { return Us[i0 + SZ + k][i0 + SZ + cb + c]; });
+    __syncthreads();
+    if (has)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Us[i0 + ra + Mfma16<double>::row(lane, v)][i0 + SZ + cb + (lane & 15)] = acc[v];
+    __syncthreads();
+    // -A^-1 T, likewise
+    acc = d4v{0.0, 0.0, 0.0, 0.0};
+    if (has)
+        acc = mma16_f64<SZ>(
+            acc, lane, [&](int r, int k) { return -Us[i0 + ra + r][i0 + k]; },
+            [&](int k, int c) { return Us[i0 + k][i0 + SZ + cb + c]; });
+    __syncthreads();
+    if (has)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Us[i0 + ra + Mfma16<double>::row(lane, v)][i0 + SZ + cb + (lane & 15)] = acc[v];
+    __syncthreads();
+}
+
 __device__ __forceinline__ void potrf_block_body(double* __restrict__ U, int64_t ldu, int64_t k0,
                                                  int nb, double thr, double* __restrict__ W,
                                                  int64_t ldw, int* flag) {
-    static_assert(CB == 128 && CPT == 1024, "4 x 4 elements per thread of a 32 x 32 grid");
-    __shared__ double rowb[2][CB];
-    __shared__ int stop[2];
-    __shared__ double Us[CB][CB + 1];  // the factor, for the inverse's columns
+    static_assert(CB == 128 && CPT == 1024 && PW == 16 && TS == 2, "8 panels of 16, 16 waves");
+    __shared__ double Us[CB][CB + 1];
+    __shared__ __attribute__((aligned(16))) double rowb[PW];
+    __shared__ __attribute__((aligned(16))) double colb[PW];
+    __shared__ double wdiag[CB];
+    __shared__ int stop;
     if (*flag) return;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    double u[4][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    {
+        double x[CB * CB / CPT];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = ty + 32 * a, c = tx + 32 * b;
-            u[a][b] = (i < nb && c < nb && c >= i) ? U[(k0 + i) * ldu + k0 + c] : 0.0;
+        for (int q = 0; q < CB * CB / CPT; ++q) {  // all loads in flight, then the stores
+            const int e = tid + q * CPT, i = e >> 7, c = e & (CB - 1);
+            x[q] = (i < nb && c < nb && c >= i) ? U[(k0 + i) * ldu + k0 + c] : (i == c && i >= nb ? 1.0 : 0.0);
         }
-    // right-looking Cholesky: row j scaled by the root of its pivot, then
-    // u[i][c] -= U[j][i] U[j][c] for j < i <= c
-    if (potrf_slice<0>(u, rowb, stop, nb, thr, tx, ty) || potrf_slice<1>(u, rowb, stop, nb, thr, tx, ty) ||
-        potrf_slice<2>(u, rowb, stop, nb, thr, tx, ty) || potrf_slice<3>(u, rowb, stop, nb, thr, tx, ty)) {
-        if (threadIdx.x == 0) *flag = 1;  // the block leaves together
-        return;
+#pragma unroll
+        for (int q = 0; q < CB * CB / CPT; ++q) {
+            const int e = tid + q * CPT;
+            Us[e >> 7][e & (CB - 1)] = x[q];
+        }
     }
+    if (tid < CB) wdiag[tid] = 1.0;
+    if (tid == 0) stop = 0;
+    __syncthreads();
+
+    for (int P0 = 0; P0 < nb; P0 += PW) {
+        if (wave == 0) {
+            const int rg = lane >> 3, cg = lane & 7;
+            const bool act = cg >= rg;  // tiles on or above the diagonal
+            double u[TS][TS], sw[TS][TS];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < TS; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = ty + 32 * a, c = tx + 32 * b;
-            const double x = c >= i ? u[a][b] : 0.0;
-            Us[i][c] = x;
-            if (i < nb && c < nb) U[(k0 + i) * ldu + k0 + c] = x;
+                for (int b = 0; b < TS; ++b) {
+                    const int i = TS * rg + a, c = TS * cg + b;
+                    u[a][b] = (act && c >= i) ? Us[P0 + i][P0 + c] : 0.0;
+                    sw[a][b] = 0.0;
+                }
+            // rowb needs no clearing: at step j its entries <= j hold zeros
+            // (each entry's last write, at a step >= its index, is a zero);
+            // colb starts the panel at zero, and its entries > j stay zero
+            if (lane < PW) colb[lane] = 0.0;
+            bool bad = false;
+            for (int jr = 0; jr < PW / TS && !bad; ++jr) {
+#pragma unroll
+                for (int ja = 0; ja < TS; ++ja) {
+                    const int j = TS * jr + ja;
+                    const double d = readlane_f64(u[ja][ja], 9 * jr);  // lane (jr, jr)
+                    const bool pad = P0 + j >= nb;                      // identity position
+                    if (!pad && !(d > thr)) {
+                        bad = true;
+                        break;
+                    }
+                    const double dd = pad ? 1.0 : d;
+                    // 1 / sqrt(dd): the hardware estimate (about 23 bits) and
+                    // two Newton-Raphson steps y <- y (3 - dd y^2) / 2; the
+                    // root is dd y
+                    const double hd = 0.5 * dd;
+                    double y = __builtin_amdgcn_rsq(dd);
+                    y = y * fma(-hd, y * y, 1.5);
+                    y = y * fma(-hd, y * y, 1.5);
+                    const double rj = dd * y, inv = y;
+                    if (rg == jr && act) {  // row j of U_pp; rowb gets zero at j and left of it
+                        d2v x;
+#pragma unroll
+                        for (int b = 0; b < TS; ++b) {
+                            const int c = TS * cg + b;
+                            const double v = c > j ? u[ja][b] * inv : 0.0;
+                            u[ja][b] = c == j ? rj : v;
+                            x[b] = v;
+                        }
+                        *(d2v*)&rowb[TS * cg] = x;
+                    }
+                    if (cg == jr && act) {  // column j of W_pp (zero below j)
+                        d2v x;
+#pragma unroll
+                        for (int a = 0; a < TS; ++a) {
+                            const int i = TS * rg + a;
+                            const double w = i <= j ? ((i == j ? 1.0 : 0.0) - sw[a][ja]) * inv : 0.0;
+                            sw[a][ja] = w;
+                            x[a] = w;
+                        }
+                        *(d2v*)&colb[TS * rg] = x;
+                    }
+                    // One wave: its LDS operations complete in order, so a
+                    // wavefront-scope fence (no instruction; it keeps the
+                    // compiler from moving the reads above the other lanes'
+                    // writes) makes the row and column just written visible.
+                    // The zeros in them leave rows <= j of U and columns
+                    // <= j of W unchanged.
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    const d2v ri = *(const d2v*)&rowb[TS * rg];
+                    const d2v wi = *(const d2v*)&colb[TS * rg];
+                    const d2v rc = *(const d2v*)&rowb[TS * cg];
+#pragma unroll
+                    for (int a2 = 0; a2 < TS; ++a2)
+#pragma unroll
+                        for (int b2 = 0; b2 < TS; ++b2) {
+                            u[a2][b2] = fma(-ri[a2], rc[b2], u[a2][b2]);
+                            sw[a2][b2] = fma(wi[a2], rc[b2], sw[a2][b2]);
+                        }
+                }
+            }
+            if (bad) {
+                if (lane == 0) stop = 1;
+            } else if (act) {
+#pragma unroll
+                for (int a = 0; a < TS; ++a)
+#pragma unroll
+                    for (int b = 0; b < TS; ++b) {
+                        const int i = TS * rg + a, c = TS * cg + b;
+                        if (c >= i) Us[P0 + i][P0 + c] = u[a][b];
+                        if (c > i) Us[P0 + c][P0 + i] = sw[a][b];  // W_pp, transposed below
+                        if (c == i) wdiag[P0 + i] = sw[a][b];
+                    }
+            }
         }
-    // W = U^-1 in place in Us by recursive doubling: first the inverted
-    // diagonal, then for s = 1, 2, ..., CB / 2 each pair of inverted s x s
-    // diagonal blocks A^-1, C^-1 and the block B of U between them give the
-    // inverse's block -A^-1 (B C^-1): two products whose entries are staged in
-    // registers across a barrier before they overwrite B.  Each entry is a sum
-    // over k in increasing order (the triangular factors' zeros bound k).  Rows
-    // past nb carry an identity, so they add exact zeros.
-    __syncthreads();  // Us complete
-    if (threadIdx.x < CB) {
-        const int i = threadIdx.x;
-        Us[i][i] = i < nb ? 1.0 / Us[i][i] : 1.0;
+        __syncthreads();
+        if (stop) {
+            if (tid == 0) *flag = 1;  // the block leaves together
+            return;
+        }
+        const int Q0 = P0 + PW, nq = CB - Q0;
+        if (Q0 >= nb) break;  // the rest is identity
+        // U_pq = W_pp^T A_pq: nq / 16 tiles, one per wave
+        const int tq = nq / 16;
+        d4v acc = d4v{0.0, 0.0, 0.0, 0.0};
+        const bool has = wave < tq;
+        if (has)
+            acc = mma16_f64<PW>(
+                acc, lane,
+                [&](int r, int k) {  // W_pp^T (r, k) = W_pp (k, r), zero for k > r
+                    const double x = Us[P0 + r][P0 + k];
+                    return k < r ? x : (k == r ? wdiag[P0 + r] : 0.0);
+                },
+                [&](int k, int c) { return Us[P0 + k][Q0 + 16 * wave + c]; });
+        __syncthreads();
+        if (has)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                Us[P0 + Mfma16<double>::row(lane, v)][Q0 + 16 * wave + (lane & 15)] = acc[v];
+        __syncthreads();
+        // A_qq -= U_pq^T U_pq on the upper tiles (tq (tq + 1) / 2 of them)
+        for (int t = wave; t < tq * (tq + 1) / 2; t += CPT / 64) {
+            int ta = 0, rem = t;
+            while (rem >= tq - ta) {
+                rem -= tq - ta;
+                ++ta;
+            }
+            const int tb = ta + rem;  // tile (ta, tb), ta <= tb
+            d4v c;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                c[v] = Us[Q0 + 16 * ta + Mfma16<double>::row(lane, v)][Q0 + 16 * tb + (lane & 15)];
+            c = mma16_f64<PW>(
+                c, lane, [&](int r, int k) { return -Us[P0 + k][Q0 + 16 * ta + r]; },
+                [&](int k, int cc) { return Us[P0 + k][Q0 + 16 * tb + cc]; });
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * ta + Mfma16<double>::row(lane, v), cc = 16 * tb + (lane & 15);
+                if (cc >= r) Us[Q0 + r][Q0 + cc] = c[v];
+            }
+        }
+        __syncthreads();
+    }
+
+    // the factor
+#pragma unroll
+    for (int q = 0; q < CB * CB / CPT; ++q) {
+        const int e = tid + q * CPT, i = e >> 7, c = e & (CB - 1);
+        if (i < nb && c < nb) U[(k0 + i) * ldu + k0 + c] = c >= i ? Us[i][c] : 0.0;
+    }
+    __syncthreads();  // U read out of Us before its diagonal blocks turn into W_pp
+    // diagonal blocks: W_pp (upper, from the lower triangle), zero below
+#pragma unroll
+    for (int q = 0; q < CB * PW / CPT; ++q) {
+        const int e = tid + q * CPT;
+        const int P0 = PW * (e / (PW * PW)), i = (e / PW) % PW, c = e % PW;
+        if (c > i) {
+            const double w = Us[P0 + c][P0 + i];
+            Us[P0 + c][P0 + i] = 0.0;
+            Us[P0 + i][P0 + c] = w;
+        } else if (c == i) {
+            Us[P0 + i][P0 + i] = wdiag[P0 + i];
+        }
     }
     __syncthreads();
-    for (int s = 1; s < CB; s *= 2) {
-        const int E = s >= 16 ? s / 16 : 1;  // entries per thread: a 1 x E row piece
-        const int groups = s / E;            // row pieces per row
-        const int t = threadIdx.x;
-        const bool act = t < (CB / (2 * s)) * s * groups;  // pairs x rows x pieces
-        const int pg = s * groups;
-        const int i0 = act ? 2 * s * (t / pg) : 0, i = act ? (t % pg) / groups : 0;
-        const int j0 = act ? (t % groups) * E : 0;   // first column of the piece within C
-        const int ra = i0 + i, cb = i0 + s + j0;     // row in A, first column in C
-        double acc[4];
-        // T = B C^-1: row ra of B times columns cb .. cb + E - 1 of C^-1 (rows k <= column)
+    inverse_doubling_level<16>(Us, wave, lane);
+    inverse_doubling_level<32>(Us, wave, lane);
+    inverse_doubling_level<64>(Us, wave, lane);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = 0.0;
-        if (act)
-            for (int k = 0; k < j0 + E; ++k) {
-                const double bik = Us[ra][i0 + s + k];
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (e < E) acc[e] += bik * Us[i0 + s + k][cb + e];
-            }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (act && e < E) Us[ra][cb + e] = acc[e];
-        __syncthreads();
-        // -A^-1 T: row i of A^-1 (columns k >= i) times the same columns of T
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = 0.0;
-        if (act)
-            for (int k = i; k < s; ++k) {
-                const double aik = Us[ra][i0 + k];
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (e < E) acc[e] += aik * Us[i0 + k][cb + e];
-            }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (act && e < E) Us[ra][cb + e] = -acc[e];
-        __syncthreads();
+    for (int q = 0; q < CB * CB / CPT; ++q) {
+        const int e = tid + q * CPT, i = e >> 7, c = e & (CB - 1);
+        if (i < nb && c < nb) W[i * ldw + c] = c >= i ? Us[i][c] : 0.0;
     }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = ty + 32 * a, c = tx + 32 * b;
-            if (i < nb && c < nb) W[i * ldw + c] = c >= i ? Us[i][c] : 0.0;
-        }
 }
 
 __global__ __launch_bounds__(CPT) void potrf_block_kernel(double* __restrict__ U, int64_t ldu,
