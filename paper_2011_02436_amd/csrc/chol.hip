@@ -35,7 +35,7 @@ namespace elm {
 namespace {
 
 constexpr int CB = 128;    // diagonal block
-constexpr int GB = 4 * CB; // block rows per trailing update
+constexpr int GB = 2 * CB; // block rows per trailing update
 constexpr int CPT = 1024;  // threads of the block kernel
 
 __global__ void clear_flag_kernel(int* flag) {
