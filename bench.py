@@ -246,6 +246,9 @@ def run_stage(args):
             for rnd in (False, True):
                 tf, ms = elm.probe_mfma(dt, rnd)
                 res[f"mfma_{dt}_{'random' if rnd else 'constant'}_tflops"] = round(tf, 1)
+        for rnd in (False, True):
+            tf, _ = elm.probe_mfma("fp64", rnd, shape=1)
+            res[f"mfma_fp64_4x4x4_four_block_{'random' if rnd else 'constant'}_tflops"] = round(tf, 1)
         res["stream_read_gbs"] = round(elm.probe_stream(buf)[0], 1)
         res["dma_stream_gbs"] = round(elm.probe_dma(buf, resident=False)[0], 1)
         res["dma_l2_resident_gbs"] = round(elm.probe_dma(buf, resident=True)[0], 1)

@@ -605,12 +605,13 @@ elm_status elm_profile_read(elm_handle* h, elm_stage_times* out);
 /* ------------------------------------------------------------------------ */
 
 /* Sustained MFMA rate: 2 waves per SIMD on every CU issue independent
- * 32x32x16 BF16 (dt = ELM_BF16) or 16x16x4 FP64 (ELM_F64) MFMAs from
- * registers, 8 accumulator chains each; random_operands != 0 fills the
+ * MFMAs from registers, 8 accumulator chains each: with shape 0, 32x32x16
+ * BF16 (dt = ELM_BF16) or 16x16x4 FP64 (ELM_F64); with shape 1 (FP64 only),
+ * the four-block 4x4x4 FP64 instruction.  random_operands != 0 fills the
  * operands with random values (the data-dependent power draw lowers the
- * clock), else 1.0.  tflops (host) receives the rate, ms (host, may be
- * NULL) the launch time.  Synchronises.  Errors: UNSUPPORTED dtype. */
-elm_status elm_probe_mfma(elm_handle* h, elm_dtype dt, int32_t random_operands, double* tflops,
+ * clock), else 1.0.  tflops (host) receives the rate, ms (host, may be NULL)
+ * the launch time.  Synchronises.  Errors: UNSUPPORTED dtype or shape. */
+elm_status elm_probe_mfma(elm_handle* h, elm_dtype dt, int32_t shape, int32_t random_operands, double* tflops,
                           double* ms);
 /* Streaming read of `bytes` of the caller's device buffer (16-byte
  * non-temporal loads, grid-stride): gbs (host) receives GB/s.  buf 16-byte

@@ -1637,13 +1637,16 @@ elm_status elm_autotune_batch(elm_handle* h, int32_t count, const elm_problem* p
     });
 }
 
-elm_status elm_probe_mfma(elm_handle* h, elm_dtype dt, int32_t random_operands, double* tflops, double* ms) {
+elm_status elm_probe_mfma(elm_handle* h, elm_dtype dt, int32_t shape, int32_t random_operands, double* tflops,
+                          double* ms) {
     if (!h) return ELM_ERR_INVALID_ARG;
     return elm::guarded(h, [&] {
         REQUIRE(dt == ELM_BF16 || dt == ELM_F64, ELM_ERR_UNSUPPORTED, "probe dtypes: BF16, FP64");
+        REQUIRE(shape == 0 || (shape == 1 && dt == ELM_F64), ELM_ERR_UNSUPPORTED,
+                "probe shapes: 0, and 1 (four-block 4x4x4) for FP64");
         REQUIRE(tflops, ELM_ERR_INVALID_ARG, "tflops must be non-null");
         elm::use_device(h);
-        *tflops = elm::probe_mfma(h->stream, dt, random_operands ? 1 : 0, ms);
+        *tflops = elm::probe_mfma(h->stream, dt, shape, random_operands ? 1 : 0, ms);
     });
 }
 

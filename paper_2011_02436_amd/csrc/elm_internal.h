@@ -41,22 +41,6 @@ template <> struct Mfma16<double> {
     }
     static __device__ inline int row(int lane, int v) { return 4 * v + (lane >> 4); }
 };
-// The same 16 x 16 x 4 FP64 step on the 4x4x4 four-block FP64 MFMA, which on
-// gfx950 sustains about 1.5 times the FP64 rate of the 16x16x4 instruction:
-// four instructions, one per 4-row group g of the tile, whose four blocks take
-// the step's four 4-column groups.  B as for Mfma16<double> (lane l holds
-// B[l / 16][l % 16]); A for group g: lane l holds A[4 g + l % 4][l / 16]; the
-// result is laid out as Mfma16<double>'s (register g of lane l: row
-// 4 g + l / 16, column l % 16).  (Block b's operands sit in lanes
-// 16 k + 4 b + y and its result in lanes 16 i + 4 b + j, measured on gfx950.)
-struct Mfma4x4F64 {
-    static __device__ inline int a_row(int lane, int g) { return 4 * g + (lane & 3); }
-    static __device__ inline d4v op(const double (&a)[4], double b, d4v c) {
-#pragma unroll
-        for (int g = 0; g < 4; ++g) c[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[g], b, c[g], 0, 0, 0);
-        return c;
-    }
-};
 template <> struct Mfma16<float> {
     typedef f4v acc_t;
     static __device__ inline acc_t op(float a, float b, acc_t c) {
@@ -465,7 +449,7 @@ void block_solve(hipStream_t s, int64_t L, int64_t m, int64_t split, const doubl
                  Workspace& ws);
 
 // probe.hip: device ceilings (measurement only); each returns TFLOP/s or GB/s
-double probe_mfma(hipStream_t s, elm_dtype dt, int random_ops, double* ms_out);
+double probe_mfma(hipStream_t s, elm_dtype dt, int shape, int random_ops, double* ms_out);
 double probe_stream(hipStream_t s, const void* buf, int64_t bytes, double* ms_out);
 double probe_dma(hipStream_t s, const void* buf, int64_t bytes, int resident, double* ms_out);
 

@@ -67,6 +67,23 @@ __global__ __launch_bounds__(PB) void mfma_f64_probe(int iters, int random_ops, 
     if (s == 12345.0) out[tid] = s;
 }
 
+// the four-block 4x4x4 FP64 instruction: 256 FMAs per instruction
+__global__ __launch_bounds__(PB) void mfma_f64_4b_probe(int iters, int random_ops, double* out) {
+    const uint32_t tid = blockIdx.x * PB + threadIdx.x;
+    const uint32_t r = random_ops ? mix32(tid) : 0u;
+    const double a = random_ops ? 0.5 + (double)(r & 0xFFFF) / 131072.0 : 1.0;
+    const double b = random_ops ? 0.5 + (double)(r >> 16) / 131072.0 : 1.0;
+    double acc[8];
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, acc[c], 0, 0, 0);
+    }
+    double s = 0.0;
+    for (int c = 0; c < 8; ++c) s += acc[c];
+    if (s == 12345.0) out[tid] = s;
+}
+
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(PB) void stream_probe(const u32x4* __restrict__ p, int64_t n16, double* out) {
@@ -106,9 +123,9 @@ __global__ __launch_bounds__(PB) void dma_probe(const unsigned char* __restrict_
 
 }  // namespace
 
-double probe_mfma(hipStream_t s, elm_dtype dt, int random_ops, double* ms_out) {
+double probe_mfma(hipStream_t s, elm_dtype dt, int shape, int random_ops, double* ms_out) {
     const int blocks = 256 * 4 * 2 / (PB / 64);   // 2 waves per SIMD on 256 CUs
-    const int iters = dt == ELM_BF16 ? 20000 : 20000;
+    const int iters = shape == 1 ? 40000 : 20000;
     void* out = nullptr;
     ELM_HIP_TRY(hipMalloc(&out, (size_t)blocks * PB * sizeof(double)));
     struct Free {
@@ -120,6 +137,7 @@ double probe_mfma(hipStream_t s, elm_dtype dt, int random_ops, double* ms_out) {
     ELM_HIP_TRY(hipEventCreate(&e1));
     auto launch = [&] {
         if (dt == ELM_BF16) mfma_bf16_probe<<<blocks, PB, 0, s>>>(iters, random_ops, (float*)out);
+        else if (shape == 1) mfma_f64_4b_probe<<<blocks, PB, 0, s>>>(iters, random_ops, (double*)out);
         else mfma_f64_probe<<<blocks, PB, 0, s>>>(iters, random_ops, (double*)out);
         ELM_LAUNCH_CHECK();
     };
@@ -133,7 +151,7 @@ double probe_mfma(hipStream_t s, elm_dtype dt, int random_ops, double* ms_out) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const double waves = (double)blocks * (PB / 64);
-    const double flops_per = dt == ELM_BF16 ? 2.0 * 32 * 32 * 16 : 2.0 * 16 * 16 * 4;
+    const double flops_per = dt == ELM_BF16 ? 2.0 * 32 * 32 * 16 : (shape == 1 ? 2.0 * 4 * 4 * 4 * 4 : 2.0 * 16 * 16 * 4);
     if (ms_out) *ms_out = ms;
     return waves * iters * 8 * flops_per / (ms * 1e-3) / 1e12;
 }

@@ -143,7 +143,7 @@ def _load():
         "elm_profile_read": ([vp, ctypes.POINTER(StageTimes)], i32),
         "elm_batch_get_report": ([vp, ctypes.POINTER(BatchReport)], i32),
         "elm_tune_table_get": ([vp, ctypes.POINTER(TuneEntry), i32, ctypes.POINTER(i32)], i32),
-        "elm_probe_mfma": ([vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], i32),
+        "elm_probe_mfma": ([vp, i32, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], i32),
         "elm_probe_stream": ([vp, vp, i64, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], i32),
         "elm_probe_dma": ([vp, vp, i64, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], i32),
         "elm_tune_table_set": ([vp, ctypes.POINTER(TuneEntry), i32], i32),
@@ -566,12 +566,14 @@ def autotune_batch(problems, precision: str = "bf16", ir_tol: float = 1e-10,
     return before.value, after.value
 
 
-def probe_mfma(dtype: str = "bf16", random_operands: bool = True) -> Tuple[float, float]:
-    """Sustained MFMA rate from registers: (TFLOP/s, ms)."""
+def probe_mfma(dtype: str = "bf16", random_operands: bool = True, shape: int = 0) -> Tuple[float, float]:
+    """Sustained MFMA rate from registers: (TFLOP/s, ms).  shape 0: 32x32x16
+    BF16 or 16x16x4 FP64; shape 1 (FP64): the four-block 4x4x4 instruction."""
     h = handle()
     tf, ms = ctypes.c_double(), ctypes.c_double()
-    h.check(_lib.elm_probe_mfma(h.ptr, {"bf16": ELM_BF16, "fp64": ELM_F64}[dtype], 1 if random_operands else 0,
-                                ctypes.byref(tf), ctypes.byref(ms)), "elm_probe_mfma")
+    h.check(_lib.elm_probe_mfma(h.ptr, {"bf16": ELM_BF16, "fp64": ELM_F64}[dtype], int(shape),
+                                1 if random_operands else 0, ctypes.byref(tf), ctypes.byref(ms)),
+            "elm_probe_mfma")
     return tf.value, ms.value
 
 

@@ -24,6 +24,11 @@ def test_probes(elm):
             tf, ms = elm.probe_mfma(dt, rnd)
             print(f"mfma {dt} random={rnd}: {tf:.1f} TFLOP/s ({ms:.3f} ms)")
             assert ms > 0 and 0 < tf <= 1.05 * peak
+    tf, ms = elm.probe_mfma("fp64", True, shape=1)
+    print(f"mfma fp64 four-block 4x4x4: {tf:.1f} TFLOP/s ({ms:.3f} ms)")
+    assert ms > 0 and 0 < tf <= 1.05 * 78.6
+    with pytest.raises(elm.ElmError):
+        elm.probe_mfma("bf16", True, shape=1)
     buf = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     gbs, ms = elm.probe_stream(buf)
     print(f"stream read: {gbs:.0f} GB/s ({ms:.3f} ms)")
