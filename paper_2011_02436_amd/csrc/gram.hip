@@ -228,7 +228,7 @@ int64_t run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, 
 // cost about a tenth of the Gram's time.  The load path, not the MFMAs, sets
 // the pace of this kernel: each load instruction occupies the CU's address
 // unit for about 16 cycles, so a stage's 64 instructions are spread over the
-// MFMAs of two k16 steps rather than issued in a burst that stalls the
+// MFMAs of three k16 steps rather than issued in a burst that stalls the
 // waves.  The loads stay in flight across the steps (explicit vmcnt and
 // lgkmcnt waits with bare s_barriers: a full __syncthreads would drain them).
 // Every stage issues the same number of loads (past the last full stage they
@@ -329,30 +329,28 @@ __device__ __forceinline__ void gram_lp256_body(const int4 wk, int64_t n, int64_
                                                  (lds_void*)(dA + i * 4096), 16, 0, 0);      \
         }                                                                                    \
     } while (0)
-        // one k16 step's 16 MFMAs with 8 of the loads of stage buffer BUF
-        // interleaved, one after every second MFMA, so that the load issue
-        // (about 16 cycles of the address unit per instruction) overlaps the
-        // MFMAs instead of stalling the wave in a burst
-#define GRAM_MMA_LOADS(FA, FB, BUF, K0, Q0)                                                  \
+        // one k16 step's 16 MFMAs with loads Q0 .. Q0 + NL - 1 of stage buffer
+        // BUF interleaved, evenly spaced (load t after MFMA 16 t / NL), so
+        // that the load issue (about 16 cycles of the address unit per
+        // instruction) overlaps the MFMAs instead of stalling the wave in a
+        // burst
+#define GRAM_MMA_LOADS(FA, FB, BUF, K0, Q0, NL)                                              \
     do {                                                                                     \
         const int64_t k_ = min((int64_t)(K0), klast);                                        \
         unsigned char* dA = smem + (BUF) * G_STB + wave * 1024;                              \
         _Pragma("unroll") for (int q = 0; q < 16; ++q) {                                     \
             acc[q >> 2][q & 3] = Mfma32<HT>::op(FA[q >> 2], FB[q & 3], acc[q >> 2][q & 3]);  \
-            if (q & 1) {                                                                     \
-                const int l = (Q0) + (q >> 1), i = l >> 1;                                   \
-                if (l & 1)                                                                   \
-                    __builtin_amdgcn_global_load_lds((const void*)(bsrc[i] + k_),            \
-                                                     (lds_void*)(dA + G_OPB + i * 4096), 16, 0, 0); \
-                else                                                                         \
-                    __builtin_amdgcn_global_load_lds((const void*)(asrc[i] + k_),            \
-                                                     (lds_void*)(dA + i * 4096), 16, 0, 0);  \
+            _Pragma("unroll") for (int t = 0; t < (NL); ++t) {                               \
+                if ((t * 16) / (NL) == q) {                                                  \
+                    const int l = (Q0) + t, i = l >> 1;                                      \
+                    if (l & 1)                                                               \
+                        __builtin_amdgcn_global_load_lds((const void*)(bsrc[i] + k_),        \
+                                                         (lds_void*)(dA + G_OPB + i * 4096), 16, 0, 0); \
+                    else                                                                     \
+                        __builtin_amdgcn_global_load_lds((const void*)(asrc[i] + k_),        \
+                                                         (lds_void*)(dA + i * 4096), 16, 0, 0); \
+                }                                                                            \
             }                                                                                \
-        }                                                                                    \
-        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0); /* the step's 8 fragment reads */ \
-        _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                      \
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0); /* 2 MFMAs */                 \
-            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0); /* 1 load */                  \
         }                                                                                    \
     } while (0)
         // Fragment reads are software-pipelined against the MFMAs: step s + 1
@@ -361,12 +359,14 @@ __device__ __forceinline__ void gram_lp256_body(const int4 wk, int64_t n, int64_
         // publishes stage st + 1 (every wave has waited for its own loads of
         // it) and retires buffer st % 2 (every wave has read its four steps).
         // The 16 loads of stage st + 2 into that buffer go out with the next
-        // two steps' MFMAs: 8 with step 3 of stage st, 8 with step 0 of
-        // stage st + 1, and land during steps 1-3.
+        // three steps' MFMAs: 6 with step 3 of stage st, 5 with each of steps
+        // 0 and 1 of stage st + 1, and land during steps 1-3.
+        constexpr int LD3 = 6, LD0 = 5, LD1 = 5;
+        static_assert(LD3 + LD0 + LD1 == 16, "a stage is 16 loads per wave");
         vec_t f0a[4], f0b[4], f1a[4], f1b[4];
         GRAM_LOADS(0, kbeg, 0, 16);
-        GRAM_LOADS(1, kbeg + GBK, 0, 8);
-        __builtin_amdgcn_s_waitcnt(G_VMCNT(8));  // stage 0 landed
+        GRAM_LOADS(1, kbeg + GBK, 0, LD3);
+        __builtin_amdgcn_s_waitcnt(G_VMCNT(LD3));  // stage 0 landed
         __builtin_amdgcn_s_barrier();
         GRAM_READ(f0a, f0b, 0, 0);
         // (Step 0 of stage st + 1 is read in the last iteration too, from a
@@ -379,12 +379,13 @@ __device__ __forceinline__ void gram_lp256_body(const int4 wk, int64_t n, int64_
             const int cur = (int)(st & 1);
             __builtin_amdgcn_s_waitcnt(G_LGKMCNT(0));
             GRAM_READ(f1a, f1b, cur, 1);
-            GRAM_MMA_LOADS(f0a, f0b, cur ^ 1, kbeg + (st + 1) * GBK, 8);
+            __builtin_amdgcn_sched_barrier(0);
+            GRAM_MMA_LOADS(f0a, f0b, cur ^ 1, kbeg + (st + 1) * GBK, LD3, LD0);
             __builtin_amdgcn_sched_barrier(0);
             __builtin_amdgcn_s_waitcnt(G_LGKMCNT(0));
             GRAM_READ(f0a, f0b, cur, 2);
             __builtin_amdgcn_sched_barrier(0);
-            GRAM_MMA(f1a, f1b);
+            GRAM_MMA_LOADS(f1a, f1b, cur ^ 1, kbeg + (st + 1) * GBK, LD3 + LD0, LD1);
             __builtin_amdgcn_sched_barrier(0);
             __builtin_amdgcn_s_waitcnt(G_LGKMCNT(0));
             GRAM_READ(f1a, f1b, cur, 3);
@@ -396,7 +397,8 @@ __device__ __forceinline__ void gram_lp256_body(const int4 wk, int64_t n, int64_
             __builtin_amdgcn_s_barrier();
             __builtin_amdgcn_sched_barrier(0);
             GRAM_READ(f0a, f0b, cur ^ 1, 0);
-            GRAM_MMA_LOADS(f1a, f1b, cur, kbeg + (st + 2) * GBK, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            GRAM_MMA_LOADS(f1a, f1b, cur, kbeg + (st + 2) * GBK, 0, LD3);
             __builtin_amdgcn_sched_barrier(0);
         }
         __builtin_amdgcn_s_waitcnt(G_VMCNT(0));
