@@ -143,6 +143,22 @@ def test_full_size_precision_form(elm):
         assert np.max(np.abs(res.Y[int(i)].cpu().numpy() - want)) <= 1e-12 * max(1.0, np.abs(want).max())
 
 
+def test_full_size_precision_form_fp16(elm):
+    """The same workload in the FP16 form (FP16 Gram of the library's own
+    node-major copy, FP64 rank decision and refinement to 1e-10): rank and beta
+    against the oracle's stored result, within the mixed-path bar."""
+    p = wl.smooth_regression()
+    X, W, b, T = to_dev(p.X), to_dev(p.W), to_dev(p.b), to_dev(p.T)
+    res = elm.train(X, W, b, T, precision="fp16", ir_tol=1e-10)
+    torch.cuda.synchronize()
+    print(f"C4 fp16: rank {res.rank}, gram {res.info['gram_dtype']}, NE {res.info['ne_residual']:.3e}, "
+          f"corrections {res.info['iterations']}")
+    assert res.rank == p.structural_rank == 10000
+    assert res.info["gram_dtype"] == "fp16" and res.info["escalations"] == 0
+    assert res.info["ne_residual"] <= 1e-10
+    check_against_golden("C4 fp16", res.beta.cpu().numpy(), res.rank, golden("smooth_regression"), 1e-6)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_full_size_rank_deficient_mixture(elm, precision):
     """N=100000, d=54, L=5000 with 500 duplicated nodes (rank 4500), 7 classes."""
