@@ -296,7 +296,9 @@ elm_status elm_factor_pivots(elm_handle* h, const elm_factor* f, int32_t* piv_ho
  * greedy rule provably keeps every position (r = n), the identity order is
  * used, certified_full_rank is 1 and last_pivot reports lambda (a lower bound
  * on the greedy rule's smallest pivot).  Otherwise the greedy factorisation
- * runs as usual. */
+ * runs as usual.  A Gram whose diagonal holds some value twice (the mark of
+ * duplicated nodes: equal columns of H give bitwise-equal Gram rows) goes to
+ * the greedy factorisation without the attempt. */
 typedef struct {
     int64_t rank;          /* r */
     int64_t n;             /* order of the Gram, min(N, L) */
@@ -465,9 +467,11 @@ typedef struct {
 
 /* elm_train on each of `count` independent problems (e.g. a sweep over
  * hidden-layer sizes or seeds), with one precision form and tolerances for
- * all, and the same results as elm_train gives each problem alone (problems of
- * order >= ELM_OPT_FULL_RANK_MIN_ORDER take the greedy rank rule here, not
- * the certified full-rank path, so their beta agrees to rounding).  Each step
+ * all, and the same results as elm_train gives each problem alone, bit for
+ * bit, except that a problem elm_train would certify full rank (see
+ * elm_factor_info) takes the greedy rank rule here: its rank is the same and
+ * its beta agrees to rounding (the grouped greedy steps serve every order of
+ * the group at once; certified factorisations one by one would not).  Each step
  * is one launch for all problems (each block runs the single-problem kernel's
  * arithmetic for its problem), on a batch stream owned by the handle, in
  * three phases: (1) the hidden layer, Z = H^T T and the Gram of every problem
@@ -582,7 +586,7 @@ typedef struct {
  * rounding).
  *   ELM_OPT_FULL_RANK_MIN_ORDER  Grams of at least this order try the
  *       certified full-rank path before the greedy steps (see
- *       elm_factor_info); <= 0 disables it.  Default 4097.
+ *       elm_factor_info); <= 0 disables it.  Default 64.
  *   ELM_OPT_BATCH_WORKERS  worker streams of elm_train_batched, 1..16.
  *       Default 8.
  * Errors: INVALID_ARG for an unknown option or a value out of range. */

@@ -285,6 +285,16 @@ static void factor_gram(elm_handle* h, elm_factor* f, double* M, int64_t kc, dou
     elm::launch_diag_max(h->stream, n, M, n, dmax);
     double hdmax = 0;
     ELM_HIP_TRY(hipMemcpyAsync(&hdmax, dmax, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    // an order the certified path may take: its diagonal too, in the same read
+    const bool cert_order = h->full_rank_min_order > 0 && n >= h->full_rank_min_order;
+    std::vector<double> hdiag;
+    if (cert_order) {
+        double* dg = (double*)h->ws.get("gram_diag", (size_t)n * sizeof(double));
+        elm::launch_diag_copy(h->stream, n, M, n, dg);
+        hdiag.resize((size_t)n);
+        ELM_HIP_TRY(hipMemcpyAsync(hdiag.data(), dg, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
+                                   h->stream));
+    }
     ELM_HIP_TRY(hipStreamSynchronize(h->stream));
     if (!std::isfinite(hdmax)) throw Error{ELM_ERR_NOT_PSD, "Gram has a non-finite diagonal entry"};
     // default threshold: 16 (n + K) 2^-53 max diag, K = products summed per
@@ -295,7 +305,9 @@ static void factor_gram(elm_handle* h, elm_factor* f, double* M, int64_t kc, dou
     f->max_diag = hdmax;
     f->noise_floor = elm::schur_noise_floor(h_dt, n, N > L ? N : L, kc) * hdmax;
     bool done = false;
-    if (h->full_rank_min_order > 0 && n >= h->full_rank_min_order) {
+    // a repeated diagonal entry (duplicated nodes) sends the Gram to the
+    // greedy rule at once: the certificate would fail on it after its work
+    if (cert_order && !elm::diag_repeats(std::move(hdiag))) {
         // certified full rank: every greedy pivot is at least
         // 1 / max_j (M^-1)_jj, read off the rows of the inverse factor
         const double need = std::max(64.0 * f->tau, 2.0 * f->noise_floor);

@@ -178,8 +178,11 @@ namespace elm {
 // default (more than the runtime's four hardware queues per process: the
 // streams also hide each other's host synchronisations).
 constexpr int BATCH_WORKERS = 8;
-// Grams of at least this order try the certified full-rank path first
-constexpr int64_t FULL_RANK_MIN_ORDER = 4097;
+// Grams of at least this order try the certified full-rank path first: from
+// order ~48 up its blocked factorisation beats the n dependent greedy steps
+// (0.07 against 0.24 ms at 64, 1.6 against 12.2 ms at 2000); below, the two
+// are within launch overheads of each other
+constexpr int64_t FULL_RANK_MIN_ORDER = 64;
 // device memory for the Grams and factorisation scratch of one group of a
 // batched training (larger batches run group after group)
 constexpr size_t BATCH_GROUP_BYTES = (size_t)16 << 30;
@@ -315,6 +318,12 @@ void launch_gram_noalloc(hipStream_t s, int device, elm_dtype dt, int64_t N, int
 void* noalloc_scratch(int device);
 //   *out = max_i M[i][i]  (NaN if any diagonal entry is NaN)
 void launch_diag_max(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
+// the diagonal of M into out (n values, device)
+void launch_diag_copy(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
+// true when two of the values are equal: on a Gram's diagonal, the mark of
+// duplicated hidden nodes (the Gram rows of equal columns are bitwise equal),
+// whose Gram the certified full-rank path would only reject after work
+bool diag_repeats(std::vector<double> d);
 
 // pchol.hip: greedy pivoted Cholesky of M (n x n FP64, full symmetric, ld = ldm).
 // Writes piv (n), allocates *R_out = R (r x n in pivot order, ld n, by factor_alloc,

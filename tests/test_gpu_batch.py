@@ -21,6 +21,15 @@ def elm():
     return mod
 
 
+@pytest.fixture(autouse=True)
+def greedy_singles(elm):
+    """The batch takes the greedy rank rule at every order; the single
+    trainings compared with it bit for bit take that rule too."""
+    old = elm.set_option("full_rank_min_order", 0)
+    yield
+    elm.set_option("full_rank_min_order", old)
+
+
 @pytest.fixture(scope="module")
 def batch():
     probs = wl.batch_sweep(seed=21, count=12, L_range=(24, 400), N_range=(200, 3000))
@@ -291,3 +300,24 @@ def test_batched_wide_targets_match_oracle_and_single(elm, precision):
         X, W, b, T = dev[e]
         one = elm.train(X, W, b, T, precision=precision, ir_tol=1e-12)
         assert torch.equal(one.beta, betas[e]), e
+
+
+def test_batched_agrees_with_a_certified_single_training(elm):
+    # with the default order threshold a single training certifies these
+    # full-rank problems; the batch takes the greedy rule: the same rank, beta
+    # equal to rounding
+    elm.set_option("full_rank_min_order", 64)
+    probs = [wl.random_problem(70 + i, N, 16, L, 3) for i, (N, L) in enumerate([(3000, 300), (600, 900), (2000, 150)])]
+    dev = [_dev(p) for p in probs]
+    betas, infos, _ = elm.train_batched(dev, precision="fp64", ir_tol=1e-12)
+    for e, (X, W, b, T) in enumerate(dev):
+        one = elm.train(X, W, b, T, precision="fp64", ir_tol=1e-12)
+        assert one.info["factor"]["certified_full_rank"]
+        assert not infos[e]["factor"]["certified_full_rank"]
+        assert one.rank == infos[e]["rank"] == min(probs[e].N, probs[e].L)
+        err = O.rel_err(betas[e].cpu().numpy(), one.beta.cpu().numpy())
+        # two correct normal-equation solvers differ by up to kappa^2 eps
+        s = np.linalg.svd(O.hidden(probs[e].X, probs[e].W, probs[e].b), compute_uv=False)
+        bar = max(1e-10, (s[0] / s[-1]) ** 2 * EPS)
+        print(f"[{e}] N={probs[e].N} L={probs[e].L}: batch vs certified single {err:.1e} (bar {bar:.1e})")
+        assert err <= bar

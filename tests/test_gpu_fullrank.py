@@ -4,11 +4,14 @@ oracle's greedy pivoted Cholesky.  The order threshold is lowered so that
 small problems take the path.  Covered: ragged last blocks (300 = 2 x 128 +
 44, 1000 = 7 x 128 + 104, single rows at 129 and 1153), one block (128),
 look-ahead updates on a second stream (1300, 1153), the
-N < L route, a rank-deficient Gram (the unpivoted factorisation stops and the
-greedy rule runs) and a threshold the certificate cannot clear (the greedy
-rule runs, full rank)."""
+N < L route, duplicated nodes (a repeated Gram diagonal value: the greedy rule
+at once), dependent columns with no repeated value (the unpivoted
+factorisation stops and the greedy rule runs), a threshold the certificate
+cannot clear (the greedy rule runs, full rank) and the default order
+threshold on both sides."""
 import numpy as np
 import pytest
+import torch
 
 import elm_workloads as wl
 import oracle as O
@@ -84,7 +87,9 @@ def test_certified_full_rank_matches_oracle(elm, low_threshold, shape, precision
     assert err <= tol, (err, tol)
 
 
-def test_rank_deficient_gram_falls_back_to_greedy(elm, low_threshold):
+def test_duplicated_nodes_take_the_greedy_path_at_once(elm, low_threshold):
+    # equal columns give equal Gram diagonal entries: the greedy rule at
+    # once, with the rank and beta of the oracle
     p = wl.random_problem(54, 3000, 64, 700, 3, n_dup=70)
     beta_ref, r, _, _, k2 = _reference(p)
     res = elm.train(*_dev(p), precision="fp64", ir_tol=1e-12)
@@ -109,7 +114,42 @@ def test_threshold_above_certificate_falls_back_to_greedy(elm, low_threshold):
 
 
 def test_default_threshold_keeps_small_grams_on_the_greedy_path(elm):
-    assert elm.get_option("full_rank_min_order") == 4097
-    p = wl.random_problem(50, 6000, 64, 300, 3)
+    assert elm.get_option("full_rank_min_order") == 64
+    p = wl.random_problem(50, 6000, 64, 48, 3)
     res = elm.train(*_dev(p), precision="fp64", ir_tol=1e-12)
     assert not res.info["factor"]["certified_full_rank"]
+    assert res.rank == 48
+
+
+def test_default_threshold_certifies_full_rank_grams(elm):
+    p = wl.random_problem(50, 6000, 64, 300, 3)
+    beta_ref, r, _, lam, _ = _reference(p)
+    res = elm.train(*_dev(p), precision="fp64", ir_tol=1e-12)
+    fi = res.info["factor"]
+    assert fi["certified_full_rank"]
+    assert res.rank == r == 300
+    assert abs(fi["last_pivot"] - lam) <= 1e-8 * lam
+    assert O.rel_err(res.beta.cpu().numpy(), beta_ref) <= 1e-10
+
+
+def test_dependent_columns_without_repeats_stop_the_certificate(elm):
+    # columns that are mixtures of two others (no repeated Gram diagonal
+    # value): the unpivoted factorisation meets a pivot below its bound, stops,
+    # and the greedy rule finds the oracle's rank
+    rng = np.random.default_rng(61)
+    p = wl.random_problem(61, 3000, 64, 700, 3)
+    H = O.hidden(p.X, p.W, p.b)
+    dep = rng.choice(np.arange(100, 700), size=35, replace=False)
+    src = np.setdiff1d(np.arange(700), dep)
+    for j in dep:
+        a, b_ = rng.choice(src, size=2, replace=False)
+        w = rng.uniform(0.2, 0.8)
+        H[:, j] = w * H[:, a] + (1.0 - w) * H[:, b_]
+    M = H.T @ H
+    assert np.unique(M.diagonal()).size == 700
+    _, _, r = O.pivoted_cholesky(M, K=3000)
+    assert r == 665
+    f = elm.elm_rank_factor(torch.from_numpy(H).to("cuda:0"))
+    fi = f.info()
+    assert not fi["certified_full_rank"]
+    assert f.rank == r

@@ -27,6 +27,15 @@ def elm():
     return mod
 
 
+@pytest.fixture(autouse=True)
+def greedy_singles(elm):
+    """The batch takes the greedy rank rule at every order; the single
+    trainings compared with it bit for bit take that rule too."""
+    old = elm.set_option("full_rank_min_order", 0)
+    yield
+    elm.set_option("full_rank_min_order", old)
+
+
 @pytest.fixture()
 def clean_table(elm):
     saved = elm.tune_table()
