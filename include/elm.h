@@ -296,8 +296,8 @@ elm_status elm_factor_pivots(elm_handle* h, const elm_factor* f, int32_t* piv_ho
  * greedy rule provably keeps every position (r = n), the identity order is
  * used, certified_full_rank is 1 and last_pivot reports lambda (a lower bound
  * on the greedy rule's smallest pivot).  Otherwise the greedy factorisation
- * runs as usual.  A Gram whose diagonal holds some value twice (the mark of
- * duplicated nodes: equal columns of H give bitwise-equal Gram rows) goes to
+ * runs as usual.  A Gram with duplicated nodes (some i != j with
+ * M_ij = M_ii = M_jj bitwise, which equal columns of H always give) goes to
  * the greedy factorisation without the attempt. */
 typedef struct {
     int64_t rank;          /* r */

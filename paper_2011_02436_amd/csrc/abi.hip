@@ -305,9 +305,9 @@ static void factor_gram(elm_handle* h, elm_factor* f, double* M, int64_t kc, dou
     f->max_diag = hdmax;
     f->noise_floor = elm::schur_noise_floor(h_dt, n, N > L ? N : L, kc) * hdmax;
     bool done = false;
-    // a repeated diagonal entry (duplicated nodes) sends the Gram to the
-    // greedy rule at once: the certificate would fail on it after its work
-    if (cert_order && !elm::diag_repeats(std::move(hdiag))) {
+    // duplicated nodes send the Gram to the greedy rule at once: the
+    // certificate would fail on it after its work
+    if (cert_order && !elm::has_duplicate_nodes(h->stream, n, M, n, hdiag, h->ws)) {
         // certified full rank: every greedy pivot is at least
         // 1 / max_j (M^-1)_jj, read off the rows of the inverse factor
         const double need = std::max(64.0 * f->tau, 2.0 * f->noise_floor);

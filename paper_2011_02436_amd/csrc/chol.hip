@@ -408,6 +408,18 @@ __global__ __launch_bounds__(1024) void max_kernel(int64_t n, const double* __re
     }
 }
 
+__global__ void diag_copy_kernel(int64_t n, const double* __restrict__ M, int64_t ldm,
+                                 double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = M[i * ldm + i];
+}
+
+__global__ void gather_entries_kernel(int64_t count, const int64_t* __restrict__ off,
+                                      const double* __restrict__ M, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = M[off[i]];
+}
+
 __global__ void iota_kernel(int64_t n, int32_t* piv) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) piv[i] = (int32_t)i;
@@ -527,6 +539,46 @@ double inv_max_row_sumsq(hipStream_t s, int64_t n, const double* X, int64_t ldx,
     ELM_HIP_TRY(hipMemcpyAsync(&h, mx, sizeof(double), hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));
     return h > 0.0 ? 1.0 / h : 0.0;
+}
+
+void launch_diag_copy(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out) {
+    if (n <= 0) return;
+    diag_copy_kernel<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(n, M, ldm, out);
+    ELM_LAUNCH_CHECK();
+}
+
+bool has_duplicate_nodes(hipStream_t s, int64_t n, const double* M, int64_t ldm,
+                         const std::vector<double>& diag, Workspace& ws) {
+    // candidate pairs: equal diagonal values (indices sorted by value)
+    std::vector<int64_t> idx((size_t)n);
+    for (int64_t i = 0; i < n; ++i) idx[(size_t)i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return diag[(size_t)a] < diag[(size_t)b]; });
+    constexpr size_t MAX_PAIRS = 1 << 16;
+    std::vector<int64_t> off;
+    for (size_t a = 0; a < idx.size();) {
+        size_t b = a + 1;
+        while (b < idx.size() && diag[(size_t)idx[b]] == diag[(size_t)idx[a]]) ++b;
+        for (size_t p = a; p < b; ++p)
+            for (size_t q = p + 1; q < b; ++q) {
+                if (off.size() >= MAX_PAIRS) return true;  // too many equal values to check
+                const int64_t i = std::min(idx[p], idx[q]), j = std::max(idx[p], idx[q]);
+                off.push_back(i * ldm + j);  // the upper triangle holds the Gram
+            }
+        a = b;
+    }
+    if (off.empty()) return false;
+    const int64_t cnt = (int64_t)off.size();
+    int64_t* doff = (int64_t*)ws.get("dup_off", off.size() * sizeof(int64_t));
+    double* dval = (double*)ws.get("dup_val", off.size() * sizeof(double));
+    ELM_HIP_TRY(hipMemcpyAsync(doff, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    gather_entries_kernel<<<(unsigned)cdiv(cnt, 256), 256, 0, s>>>(cnt, doff, M, dval);
+    ELM_LAUNCH_CHECK();
+    std::vector<double> val(off.size());
+    ELM_HIP_TRY(hipMemcpyAsync(val.data(), dval, off.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipStreamSynchronize(s));
+    for (size_t k = 0; k < off.size(); ++k)
+        if (val[k] == diag[(size_t)(off[k] % ldm)]) return true;  // M_ij = M_jj = M_ii
+    return false;
 }
 
 void launch_iota(hipStream_t s, int64_t n, int32_t* piv) {

@@ -318,12 +318,6 @@ void launch_gram_noalloc(hipStream_t s, int device, elm_dtype dt, int64_t N, int
 void* noalloc_scratch(int device);
 //   *out = max_i M[i][i]  (NaN if any diagonal entry is NaN)
 void launch_diag_max(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
-// the diagonal of M into out (n values, device)
-void launch_diag_copy(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
-// true when two of the values are equal: on a Gram's diagonal, the mark of
-// duplicated hidden nodes (the Gram rows of equal columns are bitwise equal),
-// whose Gram the certified full-rank path would only reject after work
-bool diag_repeats(std::vector<double> d);
 
 // pchol.hip: greedy pivoted Cholesky of M (n x n FP64, full symmetric, ld = ldm).
 // Writes piv (n), allocates *R_out = R (r x n in pivot order, ld n, by factor_alloc,
@@ -417,6 +411,18 @@ void cholesky_inverse_small(hipStream_t s, int64_t q, double* A, int64_t lda, do
 double inv_max_row_sumsq(hipStream_t s, int64_t n, const double* X, int64_t ldx, Workspace& ws);
 // piv[i] = i
 void launch_iota(hipStream_t s, int64_t n, int32_t* piv);
+// the diagonal of M into out (n values, device)
+void launch_diag_copy(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
+// Duplicated hidden nodes in a Gram M (n x n, upper triangle valid, diagonal
+// diag on the host): true when some pair i != j has M_ij = M_ii = M_jj
+// bitwise.  Equal columns of H give bitwise-equal Gram rows, so they always
+// show so; two distinct columns with equal norms cannot (|M_ij| < M_ii by
+// Cauchy-Schwarz unless they are parallel).  The candidates are the pairs of
+// equal diagonal values; their cross terms are read back (one
+// synchronisation, only when there are candidates; more than 65536 pairs
+// count as duplicates).
+bool has_duplicate_nodes(hipStream_t s, int64_t n, const double* M, int64_t ldm,
+                         const std::vector<double>& diag, Workspace& ws);
 
 // solve.hip: dense FP64 helpers for the factor and the pseudoinverse apply
 //   C (M x m, ld ldc) = alpha A B + beta C for A (M x K, ld lda) and a thin B

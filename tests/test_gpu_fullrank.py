@@ -4,11 +4,11 @@ oracle's greedy pivoted Cholesky.  The order threshold is lowered so that
 small problems take the path.  Covered: ragged last blocks (300 = 2 x 128 +
 44, 1000 = 7 x 128 + 104, single rows at 129 and 1153), one block (128),
 look-ahead updates on a second stream (1300, 1153), the
-N < L route, duplicated nodes (a repeated Gram diagonal value: the greedy rule
-at once), dependent columns with no repeated value (the unpivoted
-factorisation stops and the greedy rule runs), a threshold the certificate
-cannot clear (the greedy rule runs, full rank) and the default order
-threshold on both sides."""
+N < L route, duplicated nodes (M_ij = M_ii = M_jj: the greedy rule at once),
+dependent columns with no repeated value (the unpivoted factorisation stops
+and the greedy rule runs), distinct columns with equal norms (certified), a
+threshold the certificate cannot clear (the greedy rule runs, full rank) and
+the default order threshold on both sides."""
 import numpy as np
 import pytest
 import torch
@@ -88,8 +88,8 @@ def test_certified_full_rank_matches_oracle(elm, low_threshold, shape, precision
 
 
 def test_duplicated_nodes_take_the_greedy_path_at_once(elm, low_threshold):
-    # equal columns give equal Gram diagonal entries: the greedy rule at
-    # once, with the rank and beta of the oracle
+    # equal columns give bitwise-equal Gram rows: the greedy rule at once,
+    # with the rank and beta of the oracle
     p = wl.random_problem(54, 3000, 64, 700, 3, n_dup=70)
     beta_ref, r, _, _, k2 = _reference(p)
     res = elm.train(*_dev(p), precision="fp64", ir_tol=1e-12)
@@ -153,3 +153,18 @@ def test_dependent_columns_without_repeats_stop_the_certificate(elm):
     fi = f.info()
     assert not fi["certified_full_rank"]
     assert f.rank == r
+
+
+def test_equal_norms_without_duplicates_are_certified(elm):
+    # two pairs of distinct columns with bitwise-equal norms (integer entries:
+    # every sum is exact, so reversing a column keeps its norm): equal Gram
+    # diagonal values alone do not send a Gram to the greedy rule
+    rng = np.random.default_rng(62)
+    H = rng.integers(-8, 9, size=(2000, 300)).astype(np.float64)
+    H[:, 1] = H[::-1, 0]
+    H[:, 7] = H[::-1, 3]
+    M = H.T @ H
+    assert M[1, 1] == M[0, 0] and M[7, 7] == M[3, 3] and M[0, 1] != M[0, 0]
+    f = elm.elm_rank_factor(torch.from_numpy(H).to("cuda:0"))
+    assert f.info()["certified_full_rank"]
+    assert f.rank == np.linalg.matrix_rank(H) == 300
