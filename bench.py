@@ -181,19 +181,24 @@ def bench_configs(args, elm, torch, wl, dev):
       tiny_fp64        N=2000, d=20, L=200 (rank 160), m=2, FP64 form;
       digits_like      N=60000, d=784 (80% zeros), L=2000, m=10, FP32 form;
       mixture_rankdef  N=100000, d=54, L=5000 (rank 4500), m=7, FP64 and FP32
-                       forms (rank-deficient: the greedy pivoted Cholesky,
-                       256-wide panels at this order, is what the rank stage
-                       times here)."""
+                       forms (rank-deficient by 500 duplicated nodes: the
+                       copies set aside, the distinct nodes certified), and
+                       the FP64 form again with the certified path off
+                       ("fp64_greedy": the greedy pivoted Cholesky, 256-wide
+                       panels at this order)."""
     specs = [("tiny_fp64", wl.tiny_fp64, ("fp64",), 20),
              ("digits_like", wl.digits_like, ("fp32",), args.config_steps),
-             ("mixture_rankdef", wl.mixture_rankdef, ("fp64", "fp32"), args.config_steps)]
+             ("mixture_rankdef", wl.mixture_rankdef, ("fp64", "fp32", "fp64_greedy"), args.config_steps)]
     out = {}
     for name, gen, forms, reps in specs:
         p = gen()
         X, W, b, T = (torch.from_numpy(a).to(dev) for a in (p.X, p.W, p.b, p.T))
         H64 = torch.empty((p.N, p.L), dtype=torch.float64, device=dev)
         entry = {"N": p.N, "d": p.d, "L": p.L, "m": p.m}
-        for form in forms:
+        for key in forms:
+            form = key.split("_")[0]
+            greedy = key.endswith("_greedy")
+            old_order = elm.set_option("full_rank_min_order", 0) if greedy else None
             Hlp = None if form == "fp64" else torch.empty((p.L, p.N), dtype=torch.float32, device=dev)
             res = elm.train(X, W, b, T, precision=form, ir_tol=1e-10, H64=H64, Hlp=Hlp, check_convergence=False)
             torch.cuda.synchronize()
@@ -207,14 +212,16 @@ def bench_configs(args, elm, torch, wl, dev):
                 ts.append(time.perf_counter() - t0)
             stages = elm.profile_read()
             elm.profile_enable(False)
+            if greedy:
+                elm.set_option("full_rank_min_order", old_order)
             ms = _median(ts) * 1e3
             fi = res.info["factor"]
-            entry[form] = {"ms_per_training": round(ms, 3), "trainings_per_s": round(1e3 / ms, 2),
+            entry[key] = {"ms_per_training": round(ms, 3), "trainings_per_s": round(1e3 / ms, 2),
                            "rank": res.rank, "certified_full_rank": fi["certified_full_rank"],
                            "gram_dtype_used": res.info["gram_dtype"], "ne_residual": res.info["ne_residual"],
                            "refine_iterations": res.info["iterations"],
                            "stage_ms_per_training": _stage_ms(stages, len(ts))}
-            log(f"{name} {form}: {ms:.2f} ms, rank {res.rank}, NE {res.info['ne_residual']:.1e}, "
+            log(f"{name} {key}: {ms:.2f} ms, rank {res.rank}, NE {res.info['ne_residual']:.1e}, "
                 f"its {res.info['iterations']}")
             del Hlp
         out[name] = entry
@@ -532,9 +539,12 @@ def main():
         cpu = cpu_baseline(prob, min(args.cpu_rows, N), min(args.cpu_nodes, L))
         log(f"cpu baseline {time.perf_counter() - t0:.1f} s: {cpu['sample']}")
 
-    certified = bool(info_lp["factor"]["certified_full_rank"])
-    rank_path = ("certified full rank: unpivoted blocked Cholesky whose inverse-factor rows bound every "
-                 "greedy pivot above the threshold" if certified else "greedy diagonally pivoted Cholesky")
+    certified = int(info_lp["factor"]["certified_full_rank"])
+    rank_path = {1: "certified full rank: unpivoted blocked Cholesky whose inverse-factor rows bound every "
+                    "greedy pivot above the threshold",
+                 2: "duplicated nodes set aside, the distinct nodes certified full rank (unpivoted blocked "
+                    "Cholesky whose inverse-factor rows bound every greedy pivot above the threshold)"}.get(
+                     certified, "greedy diagonally pivoted Cholesky")
     out = {
         "metric": METRIC,
         "value": round(1e3 / ms_per_step, 4),

@@ -296,9 +296,16 @@ elm_status elm_factor_pivots(elm_handle* h, const elm_factor* f, int32_t* piv_ho
  * greedy rule provably keeps every position (r = n), the identity order is
  * used, certified_full_rank is 1 and last_pivot reports lambda (a lower bound
  * on the greedy rule's smallest pivot).  Otherwise the greedy factorisation
- * runs as usual.  A Gram with duplicated nodes (some i != j with
- * M_ij = M_ii = M_jj bitwise, which equal columns of H always give) goes to
- * the greedy factorisation without the attempt. */
+ * runs as usual.  Duplicated nodes (Gram rows i != j bitwise equal, which
+ * equal columns of H always give; found from the pairs of equal diagonal
+ * values with M_ij = M_ii) are set aside first: the greedy rule never pivots
+ * a copy after its original (the copy's Schur diagonal is then zero up to
+ * rounding), so on the remaining distinct nodes it is the greedy rule on
+ * their Gram, which the certificate decides.  On success the order is the
+ * distinct nodes ascending, then the copies ascending; r is the number of
+ * distinct nodes, certified_full_rank is 2, last_pivot is lambda of their
+ * Gram and first_rejected 0 (the copies' R12 columns are their originals'
+ * columns of R11). */
 typedef struct {
     int64_t rank;          /* r */
     int64_t n;             /* order of the Gram, min(N, L) */
@@ -310,7 +317,8 @@ typedef struct {
     double tau;            /* absolute stopping threshold */
     double noise_floor;    /* absolute noise scale of the Schur diagonals */
     int32_t reliable;      /* see above */
-    int32_t certified_full_rank; /* 1: rank n certified without the greedy steps */
+    int32_t certified_full_rank; /* 1: rank n certified without the greedy steps; 2: the
+                                    distinct nodes certified after setting aside copies */
 } elm_factor_info;
 
 elm_status elm_factor_get_info(const elm_factor* f, elm_factor_info* out);

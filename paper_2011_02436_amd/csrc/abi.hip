@@ -305,44 +305,60 @@ static void factor_gram(elm_handle* h, elm_factor* f, double* M, int64_t kc, dou
     f->max_diag = hdmax;
     f->noise_floor = elm::schur_noise_floor(h_dt, n, N > L ? N : L, kc) * hdmax;
     bool done = false;
-    // duplicated nodes send the Gram to the greedy rule at once: the
-    // certificate would fail on it after its work
-    if (cert_order && !elm::has_duplicate_nodes(h->stream, n, M, n, hdiag, h->ws)) {
-        // certified full rank: every greedy pivot is at least
-        // 1 / max_j (M^-1)_jj, read off the rows of the inverse factor
-        const double need = std::max(64.0 * f->tau, 2.0 * f->noise_floor);
-        if (!h->side) {  // the look-ahead stream (default priority, non-blocking)
-            ELM_HIP_TRY(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-            for (auto& e : h->side_ev) ELM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        }
-        bool ok;
-        {
-            elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
-            ok = elm::unpivoted_cholesky(h->stream, n, M, n, need, &f->R, f, h->ws, h->side,
-                                         h->side_ev[0], h->side_ev[1]);
-        }
-        if (ok) {
-            f->r = n;
-            f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
-            elm::launch_iota(h->stream, n, f->piv);
+    if (cert_order) {
+        // Duplicated nodes (bitwise-equal Gram rows) are set aside: the greedy
+        // rule never pivots a copy after its original (its Schur diagonal
+        // is then zero up to rounding), so on the distinct nodes it is the
+        // greedy rule on their Gram, which the certificate below decides.
+        std::vector<int32_t> rep;
+        const int64_t ndup = elm::duplicate_nodes(h->stream, n, M, n, hdiag, h->ws, rep);
+        if (ndup >= 0) {
+            // certified full rank: every greedy pivot is at least
+            // 1 / max_j (M^-1)_jj, read off the rows of the inverse factor
+            const double need = std::max(64.0 * f->tau, 2.0 * f->noise_floor);
+            if (!h->side) {  // the look-ahead stream (default priority, non-blocking)
+                ELM_HIP_TRY(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+                for (auto& e : h->side_ev) ELM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            }
+            bool ok;
             {
-                elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
-                elm::build_factor_tail(h->stream, f, h->ws);
+                elm::StageScope sc(&h->prof, ELM_STAGE_RANK, h->stream);
+                if (ndup == 0) {
+                    ok = elm::unpivoted_cholesky(h->stream, n, M, n, need, &f->R, f, h->ws, h->side,
+                                                 h->side_ev[0], h->side_ev[1]);
+                } else {
+                    f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
+                    ok = elm::dedup_cholesky(h->stream, n, M, n, rep, need, &f->R, f, h->ws, h->side,
+                                             h->side_ev[0], h->side_ev[1]);
+                }
             }
-            const double lam = elm::inv_max_row_sumsq(h->stream, n, f->Rinv, n, h->ws);
-            if (lam >= need) {
-                f->last_pivot = lam;
-                f->first_rejected = -INFINITY;
-                f->reliable = true;
-                f->certified_full_rank = true;
-                done = true;
+            if (ok) {
+                const int64_t r = n - ndup;
+                f->r = r;
+                if (ndup == 0) {
+                    f->piv = (int32_t*)elm::factor_alloc(f, "piv", (size_t)n * sizeof(int32_t));
+                    elm::launch_iota(h->stream, n, f->piv);
+                }
+                {
+                    elm::StageScope sc(&h->prof, ELM_STAGE_FACTOR, h->stream);
+                    elm::build_factor_tail(h->stream, f, h->ws);
+                }
+                const double lam = elm::inv_max_row_sumsq(h->stream, r, f->Rinv, r, h->ws);
+                if (lam >= need) {
+                    f->last_pivot = lam;
+                    // a copy's Schur diagonal after its original is zero
+                    f->first_rejected = ndup > 0 ? 0.0 : -INFINITY;
+                    f->reliable = true;
+                    f->certified_full_rank = ndup > 0 ? 2 : 1;
+                    done = true;
+                }
             }
-        }
-        if (!done) {  // not certified: the greedy rule decides
-            elm::free_factor_buffers(f);
-            f->r = 0;
-            f->q = 0;
-            f->woodbury = false;
+            if (!done) {  // not certified: the greedy rule decides
+                elm::free_factor_buffers(f);
+                f->r = 0;
+                f->q = 0;
+                f->woodbury = false;
+            }
         }
     }
     if (!done) {
@@ -667,7 +683,7 @@ elm_status elm_factor_get_info(const elm_factor* f, elm_factor_info* out) {
     out->tau = f->tau;
     out->noise_floor = f->noise_floor;
     out->reliable = f->reliable ? 1 : 0;
-    out->certified_full_rank = f->certified_full_rank ? 1 : 0;
+    out->certified_full_rank = f->certified_full_rank;
     return ELM_OK;
 }
 

@@ -29,6 +29,7 @@
 #include "elm_internal.h"
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 
 namespace elm {
@@ -420,6 +421,52 @@ __global__ void gather_entries_kernel(int64_t count, const int64_t* __restrict__
     if (i < count) out[i] = M[off[i]];
 }
 
+// eq[p] = 1 when rows a = pr[2 p] and b = pr[2 p + 1] of the symmetric M
+// (upper triangle read) are bitwise equal, one block per pair
+__global__ __launch_bounds__(256) void rows_equal_kernel(int64_t n, const int32_t* __restrict__ pr,
+                                                         const double* __restrict__ M, int64_t ldm,
+                                                         int32_t* __restrict__ eq) {
+    __shared__ int differ;
+    if (threadIdx.x == 0) differ = 0;
+    __syncthreads();
+    const int64_t a = pr[2 * blockIdx.x], b = pr[2 * blockIdx.x + 1];
+    bool d = false;
+    for (int64_t k = threadIdx.x; k < n; k += 256) {
+        const double x = k >= a ? M[a * ldm + k] : M[k * ldm + a];
+        const double y = k >= b ? M[b * ldm + k] : M[k * ldm + b];
+        d |= __double_as_longlong(x) != __double_as_longlong(y);
+    }
+    if (d) differ = 1;  // benign race: every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0) eq[blockIdx.x] = differ ? 0 : 1;
+}
+
+// U (r x r, ld ldu) = upper triangle of M[S][:, S] (M's upper triangle read),
+// zero below the diagonal
+__global__ void gather_upper_kernel(int64_t r, const int32_t* __restrict__ S,
+                                    const double* __restrict__ M, int64_t ldm,
+                                    double* __restrict__ U, int64_t ldu) {
+    for (int64_t i = blockIdx.y; i < r; i += gridDim.y) {
+        const int64_t si = S[i];
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < r;
+             c += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t sc = S[c];  // S ascending: sc >= si when c >= i
+            U[i * ldu + c] = c >= i ? M[si * ldm + sc] : 0.0;
+        }
+    }
+}
+
+// U[:, r + t] = U[:, src[t]] on rows 0 .. r - 1 (U upper triangular there)
+__global__ void gather_cols_kernel(int64_t r, int64_t c, const int32_t* __restrict__ src,
+                                   double* __restrict__ U, int64_t ldu) {
+    for (int64_t i = blockIdx.y; i < r; i += gridDim.y)
+        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < c;
+             t += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t j = src[t];
+            U[i * ldu + r + t] = i <= j ? U[i * ldu + j] : 0.0;
+        }
+}
+
 __global__ void iota_kernel(int64_t n, int32_t* piv) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) piv[i] = (int32_t)i;
@@ -547,26 +594,33 @@ void launch_diag_copy(hipStream_t s, int64_t n, const double* M, int64_t ldm, do
     ELM_LAUNCH_CHECK();
 }
 
-bool has_duplicate_nodes(hipStream_t s, int64_t n, const double* M, int64_t ldm,
-                         const std::vector<double>& diag, Workspace& ws) {
+int64_t duplicate_nodes(hipStream_t s, int64_t n, const double* M, int64_t ldm,
+                        const std::vector<double>& diag, Workspace& ws, std::vector<int32_t>& rep) {
+    rep.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) rep[(size_t)i] = (int32_t)i;
     // candidate pairs: equal diagonal values (indices sorted by value)
-    std::vector<int64_t> idx((size_t)n);
-    for (int64_t i = 0; i < n; ++i) idx[(size_t)i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return diag[(size_t)a] < diag[(size_t)b]; });
+    std::vector<int32_t> idx((size_t)n);
+    for (int64_t i = 0; i < n; ++i) idx[(size_t)i] = (int32_t)i;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int32_t a, int32_t b) { return diag[(size_t)a] < diag[(size_t)b]; });
     constexpr size_t MAX_PAIRS = 1 << 16;
     std::vector<int64_t> off;
+    std::vector<int32_t> pr;
     for (size_t a = 0; a < idx.size();) {
         size_t b = a + 1;
         while (b < idx.size() && diag[(size_t)idx[b]] == diag[(size_t)idx[a]]) ++b;
         for (size_t p = a; p < b; ++p)
             for (size_t q = p + 1; q < b; ++q) {
-                if (off.size() >= MAX_PAIRS) return true;  // too many equal values to check
-                const int64_t i = std::min(idx[p], idx[q]), j = std::max(idx[p], idx[q]);
-                off.push_back(i * ldm + j);  // the upper triangle holds the Gram
+                if (off.size() >= MAX_PAIRS) return -1;  // too many equal values to check
+                const int32_t i = std::min(idx[p], idx[q]), j = std::max(idx[p], idx[q]);
+                off.push_back((int64_t)i * ldm + j);  // the upper triangle holds the Gram
+                pr.push_back(i);
+                pr.push_back(j);
             }
         a = b;
     }
-    if (off.empty()) return false;
+    if (off.empty()) return 0;
+    // the cross terms of the candidates: M_ij = M_ii (= M_jj) marks a pair
     const int64_t cnt = (int64_t)off.size();
     int64_t* doff = (int64_t*)ws.get("dup_off", off.size() * sizeof(int64_t));
     double* dval = (double*)ws.get("dup_val", off.size() * sizeof(double));
@@ -576,9 +630,89 @@ bool has_duplicate_nodes(hipStream_t s, int64_t n, const double* M, int64_t ldm,
     std::vector<double> val(off.size());
     ELM_HIP_TRY(hipMemcpyAsync(val.data(), dval, off.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     ELM_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> cand;
     for (size_t k = 0; k < off.size(); ++k)
-        if (val[k] == diag[(size_t)(off[k] % ldm)]) return true;  // M_ij = M_jj = M_ii
-    return false;
+        if (val[k] == diag[(size_t)pr[2 * k]]) {
+            cand.push_back(pr[2 * k]);
+            cand.push_back(pr[2 * k + 1]);
+        }
+    if (cand.empty()) return 0;
+    // and their whole rows, bitwise
+    const int64_t np = (int64_t)cand.size() / 2;
+    int32_t* dpr = (int32_t*)ws.get("dup_pairs", cand.size() * sizeof(int32_t));
+    int32_t* deq = (int32_t*)ws.get("dup_eq", (size_t)np * sizeof(int32_t));
+    ELM_HIP_TRY(hipMemcpyAsync(dpr, cand.data(), cand.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    rows_equal_kernel<<<(unsigned)np, 256, 0, s>>>(n, dpr, M, ldm, deq);
+    ELM_LAUNCH_CHECK();
+    std::vector<int32_t> eq((size_t)np);
+    ELM_HIP_TRY(hipMemcpyAsync(eq.data(), deq, (size_t)np * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipStreamSynchronize(s));
+    // groups of equal rows (union-find), each represented by its lowest index
+    std::function<int32_t(int32_t)> find = [&](int32_t x) {
+        while (rep[(size_t)x] != x) x = rep[(size_t)x] = rep[(size_t)rep[(size_t)x]];
+        return x;
+    };
+    for (int64_t p = 0; p < np; ++p) {
+        if (!eq[(size_t)p]) continue;
+        const int32_t x = find(cand[2 * p]), y = find(cand[2 * p + 1]);
+        if (x != y) rep[(size_t)std::max(x, y)] = std::min(x, y);
+    }
+    int64_t dup = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        rep[(size_t)i] = find((int32_t)i);
+        dup += rep[(size_t)i] != i;
+    }
+    return dup;
+}
+
+bool dedup_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
+                    const std::vector<int32_t>& rep, double thr, double** R_out, elm_factor* f,
+                    Workspace& ws, hipStream_t side, hipEvent_t ev_main, hipEvent_t ev_side) {
+    *R_out = nullptr;
+    std::vector<int32_t> S, D, pos((size_t)n, -1);
+    for (int64_t j = 0; j < n; ++j)
+        if (rep[(size_t)j] == j) {
+            pos[(size_t)j] = (int32_t)S.size();
+            S.push_back((int32_t)j);
+        } else {
+            D.push_back((int32_t)j);
+        }
+    const int64_t r = (int64_t)S.size(), c = (int64_t)D.size();
+    std::vector<int32_t> src((size_t)c), piv((size_t)n);
+    for (int64_t t = 0; t < c; ++t) src[(size_t)t] = pos[(size_t)rep[(size_t)D[(size_t)t]]];
+    std::copy(S.begin(), S.end(), piv.begin());
+    std::copy(D.begin(), D.end(), piv.begin() + r);
+    int32_t* dS = (int32_t*)ws.get("dd_S", (size_t)std::max<int64_t>(r, 1) * sizeof(int32_t));
+    int32_t* dsrc = (int32_t*)ws.get("dd_src", (size_t)std::max<int64_t>(c, 1) * sizeof(int32_t));
+    ELM_HIP_TRY(hipMemcpyAsync(dS, S.data(), (size_t)r * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (c > 0)
+        ELM_HIP_TRY(hipMemcpyAsync(dsrc, src.data(), (size_t)c * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    ELM_HIP_TRY(hipMemcpyAsync(f->piv, piv.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // R = [R11 R12] (r x n, ld n) in the order S, D
+    double* U = (double*)factor_alloc(f, "R", (size_t)r * n * sizeof(double));
+    int* flag = (int*)ws.get("fr_flag", sizeof(int));
+    clear_flag_kernel<<<1, 64, 0, s>>>(flag);
+    ELM_LAUNCH_CHECK();
+    gather_upper_kernel<<<dim3((unsigned)cdiv(r, 256), (unsigned)std::min<int64_t>(r, 65535)), 256, 0, s>>>(
+        r, dS, M, ldm, U, n);
+    ELM_LAUNCH_CHECK();
+    cholesky_blocked(s, r, U, n, thr, flag, ws, side, ev_main, ev_side);
+    int hflag = 0;
+    ELM_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    ELM_HIP_TRY(hipStreamSynchronize(s));
+    if (hflag) {
+        if (!f->pool) (void)hipFree(U);
+        return false;
+    }
+    // a copy's Gram column is its original's: R12 column t = U^-T M[S, D_t] =
+    // column src[t] of U
+    if (c > 0) {
+        gather_cols_kernel<<<dim3((unsigned)cdiv(c, 256), (unsigned)std::min<int64_t>(r, 65535)), 256, 0,
+                             s>>>(r, c, dsrc, U, n);
+        ELM_LAUNCH_CHECK();
+    }
+    *R_out = U;
+    return true;
 }
 
 void launch_iota(hipStream_t s, int64_t n, int32_t* piv) {

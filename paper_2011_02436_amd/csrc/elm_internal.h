@@ -223,7 +223,9 @@ struct elm_factor {
     double max_diag = 0, last_pivot = 0, first_rejected = 0;
     double noise_floor = 0;   // absolute rounding-noise scale of the Schur diagonals
     bool reliable = true;
-    bool certified_full_rank = false;  // rank n by the certificate, identity order
+    // 1: rank n by the certificate, identity order; 2: duplicated nodes set
+    // aside, the distinct ones certified (rank = their count)
+    int certified_full_rank = 0;
     // device buffers: hipMalloc'd and owned by the factor, or, when pool is
     // set, named buffers of that workspace (a factor used only inside a call)
     elm::Workspace* pool = nullptr;
@@ -413,16 +415,26 @@ double inv_max_row_sumsq(hipStream_t s, int64_t n, const double* X, int64_t ldx,
 void launch_iota(hipStream_t s, int64_t n, int32_t* piv);
 // the diagonal of M into out (n values, device)
 void launch_diag_copy(hipStream_t s, int64_t n, const double* M, int64_t ldm, double* out);
-// Duplicated hidden nodes in a Gram M (n x n, upper triangle valid, diagonal
-// diag on the host): true when some pair i != j has M_ij = M_ii = M_jj
-// bitwise.  Equal columns of H give bitwise-equal Gram rows, so they always
-// show so; two distinct columns with equal norms cannot (|M_ij| < M_ii by
-// Cauchy-Schwarz unless they are parallel).  The candidates are the pairs of
-// equal diagonal values; their cross terms are read back (one
-// synchronisation, only when there are candidates; more than 65536 pairs
-// count as duplicates).
-bool has_duplicate_nodes(hipStream_t s, int64_t n, const double* M, int64_t ldm,
-                         const std::vector<double>& diag, Workspace& ws);
+// Duplicated hidden nodes in a Gram M (n x n, upper triangle read, diagonal
+// diag on the host): rep[j] = the lowest index whose Gram row equals row j
+// bitwise (j itself when none).  Equal columns of H give bitwise-equal Gram
+// rows; the candidates are the pairs of equal diagonal values whose cross
+// term equals them too (two distinct columns with equal norms cannot show it:
+// |M_ij| < M_ii by Cauchy-Schwarz unless they are parallel), and their whole
+// rows are then compared (a synchronisation each, only when there are
+// candidates).  Returns the number of columns j with rep[j] != j, or -1 when
+// more than 65536 candidate pairs would have to be read.
+int64_t duplicate_nodes(hipStream_t s, int64_t n, const double* M, int64_t ldm,
+                        const std::vector<double>& diag, Workspace& ws, std::vector<int32_t>& rep);
+// The unpivoted blocked Cholesky of the Gram of the distinct nodes (S: the j
+// with rep[j] == j, ascending) stopping, like unpivoted_cholesky, at a pivot
+// <= thr (false, nothing kept).  On success R_out = [R11 R12] (r x n, ld n,
+// allocated for f) in the order S then the copies D (ascending), whose R12
+// columns are their originals' columns of R11, and f->piv (allocated by the
+// caller, n entries) holds that order.
+bool dedup_cholesky(hipStream_t s, int64_t n, const double* M, int64_t ldm,
+                    const std::vector<int32_t>& rep, double thr, double** R_out, elm_factor* f,
+                    Workspace& ws, hipStream_t side, hipEvent_t ev_main, hipEvent_t ev_side);
 
 // solve.hip: dense FP64 helpers for the factor and the pseudoinverse apply
 //   C (M x m, ld ldc) = alpha A B + beta C for A (M x K, ld lda) and a thin B

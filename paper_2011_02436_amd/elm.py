@@ -59,7 +59,7 @@ class FactorInfo(ctypes.Structure):
                 "gram_dtype": _DT_NAME.get(int(self.gram_dtype), "?"), "max_diag": float(self.max_diag),
                 "last_pivot": float(self.last_pivot), "first_rejected": float(self.first_rejected),
                 "tau": float(self.tau), "noise_floor": float(self.noise_floor),
-                "reliable": bool(self.reliable), "certified_full_rank": bool(self.certified_full_rank)}
+                "reliable": bool(self.reliable), "certified_full_rank": int(self.certified_full_rank)}
 
 
 class TrainInfo(ctypes.Structure):

@@ -4,7 +4,8 @@ oracle's greedy pivoted Cholesky.  The order threshold is lowered so that
 small problems take the path.  Covered: ragged last blocks (300 = 2 x 128 +
 44, 1000 = 7 x 128 + 104, single rows at 129 and 1153), one block (128),
 look-ahead updates on a second stream (1300, 1153), the
-N < L route, duplicated nodes (M_ij = M_ii = M_jj: the greedy rule at once),
+N < L route, duplicated nodes (bitwise-equal Gram rows: set aside, the
+distinct nodes certified; the greedy rule with the path off),
 dependent columns with no repeated value (the unpivoted factorisation stops
 and the greedy rule runs), distinct columns with equal norms (certified), a
 threshold the certificate cannot clear (the greedy rule runs, full rank) and
@@ -87,18 +88,45 @@ def test_certified_full_rank_matches_oracle(elm, low_threshold, shape, precision
     assert err <= tol, (err, tol)
 
 
-def test_duplicated_nodes_take_the_greedy_path_at_once(elm, low_threshold):
-    # equal columns give bitwise-equal Gram rows: the greedy rule at once,
-    # with the rank and beta of the oracle
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_duplicated_nodes_set_aside_then_certified(elm, low_threshold, precision):
+    # equal columns give bitwise-equal Gram rows: the copies are set aside,
+    # the distinct nodes certified (mode 2), with the oracle's rank, last
+    # greedy pivot and beta; the order is the distinct nodes, then the copies
     p = wl.random_problem(54, 3000, 64, 700, 3, n_dup=70)
-    beta_ref, r, _, _, k2 = _reference(p)
-    res = elm.train(*_dev(p), precision="fp64", ir_tol=1e-12)
+    beta_ref, r, last, _, k2 = _reference(p)
+    res = elm.train(*_dev(p), precision=precision, ir_tol=1e-12)
     fi = res.info["factor"]
-    assert not fi["certified_full_rank"]
+    assert fi["certified_full_rank"] == 2
     assert res.rank == r == p.structural_rank == 630
+    assert fi["first_rejected"] == 0.0
+    if precision == "fp64":
+        assert abs(fi["last_pivot"] - last) <= 1e-8 * last
+    piv = res.factor.pivots()
+    assert sorted(piv.tolist()) == list(range(p.L))
+    keep, rest = piv[:r], piv[r:]
+    assert np.all(np.diff(keep) > 0) and np.all(np.diff(rest) > 0)
+    assert len(set(p.groups[keep])) == r                   # one node per group
+    assert set(p.groups[rest]) <= set(p.groups[keep])      # the rest are copies
     err = O.rel_err(res.beta.cpu().numpy(), beta_ref)
-    print(f"beta err {err:.2e} (bar 1e-10; kappa^2 eps {k2 * EPS:.1e})")
-    assert err <= 1e-10
+    bar = 1e-10 if precision == "fp64" else 1e-6
+    print(f"{precision}: beta err {err:.2e} (bar {bar:.0e}; kappa^2 eps {k2 * EPS:.1e})")
+    assert err <= bar
+
+
+def test_duplicated_nodes_greedy_rule_when_disabled(elm):
+    # the same problem with the certified path off: the greedy rule, the same
+    # rank and beta
+    old = elm.set_option("full_rank_min_order", 0)
+    try:
+        p = wl.random_problem(54, 3000, 64, 700, 3, n_dup=70)
+        beta_ref, r, _, _, _ = _reference(p)
+        res = elm.train(*_dev(p), precision="fp64", ir_tol=1e-12)
+        assert res.info["factor"]["certified_full_rank"] == 0
+        assert res.rank == r == 630
+        assert O.rel_err(res.beta.cpu().numpy(), beta_ref) <= 1e-10
+    finally:
+        elm.set_option("full_rank_min_order", old)
 
 
 def test_threshold_above_certificate_falls_back_to_greedy(elm, low_threshold):

@@ -175,12 +175,28 @@ def test_full_size_rank_deficient_mixture(elm, precision):
     assert res.rank == p.structural_rank == 4500
     check_against_golden(f"C3 {precision}", beta, res.rank, golden("mixture_rankdef"),
                          1e-10 if precision == "fp64" else 1e-6)
-    assert not res.info["factor"]["certified_full_rank"]
+    # the 500 copies set aside, the 4500 distinct nodes certified
+    assert res.info["factor"]["certified_full_rank"] == 2
     assert ne <= 1e-10
     assert spread <= 1e-9
     rng = np.random.default_rng(7)
     _, _, got, ref, bound = _sampled_h(p, H64, rng)
     assert np.all(np.abs(got - ref) <= bound)
+
+
+def test_full_size_rank_deficient_mixture_greedy_rule(elm):
+    """C3 (FP64 form) with the certified path off: the greedy pivoted Cholesky
+    (256-wide panels) at order 5000, against the oracle's stored beta."""
+    p = wl.mixture_rankdef()
+    X, W, b, T = to_dev(p.X), to_dev(p.W), to_dev(p.b), to_dev(p.T)
+    old = elm.set_option("full_rank_min_order", 0)
+    try:
+        res = elm.train(X, W, b, T, precision="fp64", ir_tol=1e-10)
+    finally:
+        elm.set_option("full_rank_min_order", old)
+    assert res.info["factor"]["certified_full_rank"] == 0
+    assert res.rank == p.structural_rank == 4500
+    check_against_golden("C3 fp64 greedy", res.beta.cpu().numpy(), res.rank, golden("mixture_rankdef"), 1e-10)
 
 
 def test_full_size_digits_fp32_form(elm):
