@@ -10,7 +10,10 @@
 // that to send the Schur diagonal of a duplicated hidden node to ~0.
 //
 // Kernels:
-//   gram16_kernel<T, KCONTIG>  FP64 or FP32, 16x16x4 MFMA, 128 x 128 tiles.
+//   FP64 (single problems): the FP64 GEMM's upper tiles per K chunk, then
+//     gram_sum_mirror_kernel (chunk sum in FP64, mirrored).
+//   gram16_kernel<T, KCONTIG>  FP32, and FP64 in the batches' grouped launches
+//     (the same products in the same order), 16x16x4 MFMA, 128 x 128 tiles.
 //     KCONTIG=false: operand element (row, k) at base[k*ld + row] (columns of
 //       a sample-major H: the column Gram H^T H).
 //     KCONTIG=true:  element (row, k) at base[row*ld + k] (rows of a
@@ -157,6 +160,45 @@ __device__ __forceinline__ void gram_reduce_body(int64_t bx, int64_t n, const PT
     }
 }
 
+// M = the sum over chunks (in chunk order, FP64) of the upper triangles of
+// the chunk products P[c] (n x n, ld ldp, c_bs apart), written to (i, j) and
+// (j, i): one 32 x 32 tile of the upper block triangle per block, its
+// transpose written from LDS so both stores are whole rows
+constexpr int MT = 32;
+__global__ __launch_bounds__(256) void gram_sum_mirror_kernel(int64_t n, const double* __restrict__ P,
+                                                              int64_t ldp, int64_t c_bs, int nchunk,
+                                                              double* __restrict__ M, int64_t ldm) {
+    __shared__ double t[MT][MT + 1];
+    int bi, bj;
+    tile_coords(blockIdx.x, bi, bj);
+    const int tx = threadIdx.x & (MT - 1), ty = threadIdx.x / MT;  // 32 x 8
+    const int64_t i0 = (int64_t)bi * MT, j0 = (int64_t)bj * MT;
+#pragma unroll
+    for (int q = 0; q < MT / 8; ++q) {
+        const int li = ty + 8 * q;
+        int64_t i = i0 + li, j = j0 + tx;
+        if (i < n && j < n) {
+            if (i > j) {  // lower half of a diagonal tile: the upper entry
+                const int64_t x = i;
+                i = j;
+                j = x;
+            }
+            double v = 0.0;
+            for (int c = 0; c < nchunk; ++c) v += P[(int64_t)c * c_bs + i * ldp + j];
+            M[(i0 + li) * ldm + j0 + tx] = v;
+            t[li][tx] = v;
+        }
+    }
+    if (bi == bj) return;  // block-uniform: the tile is its own transpose
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MT / 8; ++q) {
+        const int lj = ty + 8 * q;
+        const int64_t j = j0 + lj, i = i0 + tx;
+        if (i < n && j < n) M[j * ldm + i] = t[tx][lj];
+    }
+}
+
 template <typename PT>
 __global__ __launch_bounds__(NT) void gram_reduce_kernel(int64_t n, const PT* __restrict__ part,
                                                          int64_t ntile, int nchunk,
@@ -211,6 +253,48 @@ int64_t run_gram16(hipStream_t s, int64_t n, int64_t K, const T* A, int64_t ld, 
     return kc_len;
 }
 
+// The FP64 Gram on the library's FP64 GEMM (its tiles and MFMA steps take
+// the products of each element in the order gram16_kernel does: K chunks of
+// kc_len, steps of 16 and of 4 inside them): the chunks' upper tiles in one
+// batched launch (a shorter last chunk in a second), then their sum in chunk
+// order and the mirror.  kcontig: operand element (row, k) at A[row * ld + k]
+// (H H^T of a sample-major H); else at A[k * ld + row] (H^T H).  (On the FP32
+// node-major copy the same route took twice gram16_kernel's time: the FP32
+// Gram stays there.)
+static void run_gram_f64(hipStream_t s, int64_t n, int64_t K, const double* A, int64_t ld, bool kcontig,
+                         double* M, int64_t ldm, Workspace& ws, int force_chunks) {
+    const int64_t nt = cdiv(n, TILE);
+    const int64_t ntile = nt * (nt + 1) / 2;
+    int64_t kc_len;
+    int nchunk;
+    gram16_chunks(ELM_F64, n, ntile, K, force_chunks, ws, kc_len, nchunk);
+    const int64_t a_rs = kcontig ? ld : 1, a_cs = kcontig ? 1 : ld;   // A(i, k)
+    const int64_t b_rs = kcontig ? 1 : ld, b_cs = kcontig ? ld : 1;   // B(k, j) = A(j, k)
+    const int64_t kstep = kcontig ? 1 : ld;                           // one k further
+    // a single chunk goes straight to M
+    double* P = M;
+    int64_t ldp = ldm, c_bs = 0;
+    if (nchunk > 1) {
+        P = (double*)ws.get("gram_part64", (size_t)nchunk * n * n * sizeof(double));
+        ldp = n;
+        c_bs = n * n;
+    }
+    auto gemm = [&](int64_t batch, int64_t kl, const double* Ak, double* C) {
+        gemm_f64_batched(s, batch, n, n, kl, 1.0, Ak, a_rs, a_cs, kl * kstep, Ak, b_rs, b_cs, kl * kstep,
+                         0.0, C, ldp, c_bs, false, false, true, nullptr);
+    };
+    const int64_t last = K - (int64_t)(nchunk - 1) * kc_len;
+    const int nfull = last == kc_len ? nchunk : nchunk - 1;
+    {
+        StageScope sc(ws.prof, ELM_STAGE_GRAM, s);
+        if (nfull > 0) gemm(nfull, kc_len, A, P);
+        if (nfull < nchunk) gemm(1, last, A + (int64_t)nfull * kc_len * kstep, P + (int64_t)nfull * c_bs);
+    }
+    StageScope sc(ws.prof, ELM_STAGE_GRAM_REDUCE, s);
+    const int64_t mt = cdiv(n, MT);
+    gram_sum_mirror_kernel<<<(unsigned)(mt * (mt + 1) / 2), 256, 0, s>>>(n, P, ldp, c_bs, nchunk, M, ldm);
+    ELM_LAUNCH_CHECK();
+}
 
 // ---------------------------------------------------------------------------
 // 16-bit node-major Gram, 256 x 256 tiles (the high-throughput path).
@@ -599,12 +683,12 @@ void launch_diag_max(hipStream_t s, int64_t n, const double* M, int64_t ldm, dou
 
 void launch_gram_f64_cols(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
                           double* M, int64_t ldm, Workspace& ws, int force_chunks) {
-    run_gram16<double, false>(s, L, N, H, ldh, M, ldm, ws, force_chunks);
+    run_gram_f64(s, L, N, H, ldh, false, M, ldm, ws, force_chunks);
 }
 
 void launch_gram_f64_rows(hipStream_t s, int64_t N, int64_t L, const double* H, int64_t ldh,
                           double* M, int64_t ldm, Workspace& ws) {
-    run_gram16<double, true>(s, N, L, H, ldh, M, ldm, ws);
+    run_gram_f64(s, N, L, H, ldh, true, M, ldm, ws, 0);
 }
 
 // Work table for the 256-tile Gram: items (split, bi, bj, slot) ordered by
@@ -734,7 +818,7 @@ size_t gram_group_plan(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, GramDe
         *kc_out = kc_len;
         return (size_t)ntile * nsplit_eff * GT * GT * sizeof(float);
     }
-    // run_gram16: FP32 node-major (n = L, K = N) or FP64 sample-major columns
+    // run_gram16's tiles and chunks (the FP64 route chunks alike)
     const int64_t nt = cdiv(L, TILE);
     const int64_t ntile = nt * (nt + 1) / 2;
     int64_t kc_len;

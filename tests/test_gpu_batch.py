@@ -251,7 +251,7 @@ def tails():
     return probs, refs
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "bf16", "fp32"])
 def test_batched_tail_shapes_match_oracle_and_single(elm, tails, precision):
     probs, refs = tails
     dev = [_dev(p) for p in probs]
