@@ -48,9 +48,11 @@ template <typename T, bool KCONTIG>
 __device__ __forceinline__ void gram16_body(int64_t bx, int64_t by, int64_t n, int64_t K,
                                             int64_t kc_len, const T* __restrict__ A, int64_t ld,
                                             T* __restrict__ part, int64_t ntile) {
-    constexpr int BK = 16;
-    __shared__ T As[BK][TILE + 1];
-    __shared__ T Bs[BK][TILE + 1];
+    constexpr int BK = 16;  // samples per stage (32 for FP32 measured no faster)
+    constexpr int EL = (BK * TILE) / NT;  // staged elements per thread and operand
+    // two stages: the next chunk's loads are in flight while this one multiplies
+    __shared__ T As[2][BK][TILE + 1];
+    __shared__ T Bs[2][BK][TILE + 1];
 
     int bi, bj;
     tile_coords(bx, bi, bj);
@@ -67,39 +69,64 @@ __device__ __forceinline__ void gram16_body(int64_t bx, int64_t by, int64_t n, i
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = typename Mfma16<T>::acc_t{};
 
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    T va[EL], vb[EL];
+    auto load = [&](int64_t k0) {
 #pragma unroll
-        for (int it = 0; it < (BK * TILE) / NT; ++it) {
+        for (int it = 0; it < EL; ++it) {
             const int e = tid + it * NT;
             int row, k;
             if (KCONTIG) { row = e / BK; k = e % BK; }
             else         { k = e / TILE; row = e % TILE; }
             const int64_t gk = k0 + k;
             const int64_t ga = r0 + row, gb = c0 + row;
-            T va = T(0), vb = T(0);
+            T x = T(0), y = T(0);
             if (gk < kend) {
-                if (ga < n) va = KCONTIG ? A[ga * ld + gk] : A[gk * ld + ga];
-                if (gb < n) vb = KCONTIG ? A[gb * ld + gk] : A[gk * ld + gb];
+                if (ga < n) x = KCONTIG ? A[ga * ld + gk] : A[gk * ld + ga];
+                if (gb < n) y = KCONTIG ? A[gb * ld + gk] : A[gk * ld + gb];
             }
-            As[k][row] = va;
-            Bs[k][row] = vb;
+            va[it] = x;
+            vb[it] = y;
         }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int it = 0; it < EL; ++it) {
+            const int e = tid + it * NT;
+            int row, k;
+            if (KCONTIG) { row = e / BK; k = e % BK; }
+            else         { k = e / TILE; row = e % TILE; }
+            As[buf][k][row] = va[it];
+            Bs[buf][k][row] = vb[it];
+        }
+    };
+
+    if (kbeg < kend) {
+        load(kbeg);
+        store(0);
         __syncthreads();
+        int buf = 0;
+        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+            const bool more = k0 + BK < kend;  // block-uniform
+            if (more) load(k0 + BK);
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            const int k = kk + (lane >> 4);
-            T a[4], b[4];
+            for (int kk = 0; kk < BK; kk += 4) {
+                const int k = kk + (lane >> 4);
+                T a[4], b[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[k][wm * 64 + q * 16 + (lane & 15)];
-                b[q] = Bs[k][wn * 64 + q * 16 + (lane & 15)];
+                for (int q = 0; q < 4; ++q) {
+                    a[q] = As[buf][k][wm * 64 + q * 16 + (lane & 15)];
+                    b[q] = Bs[buf][k][wn * 64 + q * 16 + (lane & 15)];
+                }
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = Mfma16<T>::op(a[x], b[y], acc[x][y]);
             }
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = Mfma16<T>::op(a[x], b[y], acc[x][y]);
+            // the other buffer was last read before the previous barrier
+            if (more) store(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
         }
-        __syncthreads();
     }
 
     T* out = part + (by * ntile + bx) * (TILE * TILE);
