@@ -181,7 +181,9 @@ __global__ __launch_bounds__(NT) void ht_kernel(int64_t N, int64_t L, int m,
 //   beta (re-read by every wave) and the partials out of the caches.
 //   With labels, also the arg-max of each row (lowest index on ties).
 // cols_dot_kernel: part[chunk][col][o] = sum over the chunk's rows of
-//   H[row][col] E[row][o]; thread per column, the chunk's E rows in LDS.
+//   H[row][col] E[row][o], row by row; CPT columns per thread (more for wide
+//   m, so that each E value read from LDS serves several columns), the
+//   chunk's E rows in LDS.
 // ---------------------------------------------------------------------------
 constexpr int SB = 256;   // threads per block
 constexpr int CR_ROWS = 1024;  // rows per chunk, cols_dot_kernel
@@ -279,14 +281,26 @@ __device__ __forceinline__ void rows_dot_body(int64_t bx, int64_t N, int64_t L, 
     }
 }
 
+// columns per thread of cols_dot_kernel: each E value read from LDS serves
+// CPT columns, so that a row costs about four LDS reads per H element
+template <int MM>
+struct ColsDot {
+    static constexpr int CPT = MM >= 8 ? MM / 4 : 1;
+    static constexpr int CB = SB * CPT;  // columns per block
+};
+
 template <int MM>
 __device__ __forceinline__ void cols_dot_body(int64_t bx, int64_t by, int64_t N, int64_t L, int m,
                                      const double* __restrict__ H, int64_t ldh,
                                      const double* __restrict__ E, int64_t lde,
                                      double* __restrict__ part) {
+    constexpr int CPT = ColsDot<MM>::CPT;
+    constexpr int RU = CPT > 2 ? 4 : 8;  // rows per unrolled step
     __shared__ double Es[CR_ROWS * MM];
     const int tid = threadIdx.x;
-    const int64_t col = bx * SB + tid;
+    // thread columns col0 + j SB, j < CPT (each load instruction reads 64
+    // consecutive columns); a column past L reads column L - 1, unstored
+    const int64_t col0 = bx * ColsDot<MM>::CB + tid;
     const int64_t rbeg = by * CR_ROWS;
     const int nrows = (int)min<int64_t>(CR_ROWS, N - rbeg);
     for (int e = tid; e < CR_ROWS * MM; e += SB) {
@@ -294,30 +308,47 @@ __device__ __forceinline__ void cols_dot_body(int64_t bx, int64_t by, int64_t N,
         Es[e] = (r < nrows && c < m) ? E[(rbeg + r) * lde + c] : 0.0;
     }
     __syncthreads();
-    double acc[MM];
+    if (col0 >= L) return;  // no barrier follows
+    double acc[CPT][MM];
+    const double* __restrict__ hp[CPT];
 #pragma unroll
-    for (int c = 0; c < MM; ++c) acc[c] = 0.0;
-    if (col < L) {
-        const double* __restrict__ hp = H + rbeg * ldh + col;
-        int r = 0;
-        for (; r + 8 <= nrows; r += 8) {
-            double h[8];
+    for (int j = 0; j < CPT; ++j) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) h[u] = __builtin_nontemporal_load(&hp[(int64_t)(r + u) * ldh]);
+        for (int c = 0; c < MM; ++c) acc[j][c] = 0.0;
+        hp[j] = H + rbeg * ldh + min(col0 + (int64_t)j * SB, L - 1);
+    }
+    int r = 0;
+    for (; r + RU <= nrows; r += RU) {
+        double h[RU][CPT];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < RU; ++u)
 #pragma unroll
-                for (int c = 0; c < MM; ++c) acc[c] += h[u] * Es[(r + u) * MM + c];
+            for (int j = 0; j < CPT; ++j) h[u][j] = __builtin_nontemporal_load(&hp[j][(int64_t)(r + u) * ldh]);
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+            for (int c = 0; c < MM; ++c) {
+                const double e = Es[(r + u) * MM + c];
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) acc[j][c] += h[u][j] * e;
+            }
+    }
+    for (; r < nrows; ++r) {
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const double hv = __builtin_nontemporal_load(&hp[j][(int64_t)r * ldh]);
+#pragma unroll
+            for (int c = 0; c < MM; ++c) acc[j][c] += hv * Es[r * MM + c];
         }
-        for (; r < nrows; ++r) {
-            const double hv = __builtin_nontemporal_load(&hp[(int64_t)r * ldh]);
+    }
 #pragma unroll
-            for (int c = 0; c < MM; ++c) acc[c] += hv * Es[r * MM + c];
-        }
+    for (int j = 0; j < CPT; ++j) {
+        const int64_t col = col0 + (int64_t)j * SB;
+        if (col >= L) continue;
         double* o = part + by * L * m + col * m;
 #pragma unroll
         for (int c = 0; c < MM; ++c)
-            if (c < m) o[c] = acc[c];
+            if (c < m) o[c] = acc[j][c];
     }
 }
 
@@ -434,7 +465,7 @@ __global__ __launch_bounds__(SB) void cols_dot_grouped(const RefineDesc* __restr
     const int j = group_problem(g, lb);
     if (!group_live(g, j)) return;
     const RefineDesc& q = d[j];
-    const int64_t nbx = cdiv(q.L, SB);
+    const int64_t nbx = cdiv(q.L, ColsDot<MM>::CB);
     cols_dot_body<MM>(lb % nbx, lb / nbx, q.N, q.L, q.m, q.H, q.ldh, q.E, q.m, q.part);
 }
 
@@ -550,7 +581,10 @@ int64_t refine_group_blocks(RefinePass pass, const RefineDesc& q, int maxm) {
             return cdiv(q.N, maxm <= 2 ? RowsDot<2>::RB
                              : maxm <= 4 ? RowsDot<4>::RB
                              : maxm <= 8 ? RowsDot<8>::RB : RowsDot<16>::RB);
-        case RefinePass::COLS_DOT: return cdiv(q.L, SB) * cdiv(q.N, CR_ROWS);
+        case RefinePass::COLS_DOT:
+            return cdiv(q.L, maxm <= 2 ? ColsDot<2>::CB
+                             : maxm <= 4 ? ColsDot<4>::CB
+                             : maxm <= 8 ? ColsDot<8>::CB : ColsDot<16>::CB) * cdiv(q.N, CR_ROWS);
         case RefinePass::HT_REDUCE: return cdiv(q.L * q.m, NT);
         case RefinePass::SUM: return 1;
         case RefinePass::AXPY: return cdiv(q.L * q.m, 256);
@@ -733,15 +767,18 @@ void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
     if (m <= 16) {
         nchunk = (int)cdiv(N, CR_ROWS);
         part = (double*)ws.get("ht_part", (size_t)nchunk * L * m * sizeof(double));
-        dim3 grid((unsigned)cdiv(L, SB), (unsigned)nchunk);
+#define ELM_CD(MM)                                                                               \
+    cols_dot_kernel<MM><<<dim3((unsigned)cdiv(L, ColsDot<MM>::CB), (unsigned)nchunk), SB, 0, s>>>(      \
+        N, L, mi, H, ldh, E, lde, part)
         if (m <= 2)
-            cols_dot_kernel<2><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
+            ELM_CD(2);
         else if (m <= 4)
-            cols_dot_kernel<4><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
+            ELM_CD(4);
         else if (m <= 8)
-            cols_dot_kernel<8><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
+            ELM_CD(8);
         else
-            cols_dot_kernel<16><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, E, lde, part);
+            ELM_CD(16);
+#undef ELM_CD
     } else {
         nchunk = (int)cdiv(N, HT_ROWS);
         part = (double*)ws.get("ht_part", (size_t)nchunk * L * m * sizeof(double));
