@@ -289,6 +289,21 @@ struct ColsDot {
     static constexpr int CB = SB * CPT;  // columns per block
 };
 
+// Rows per chunk of the column pass: CR_ROWS, halved (down to 128) while
+// the pass would have fewer than 512 blocks (a function of the problem's own
+// N, L and m, so a batch chunks each problem as its single training does).
+// On N = 60000, L = 2000, m = 10 (118 blocks of 1024 rows) four passes took
+// 2.0 ms, 1.65 in chunks of 128 rows; a 1024-block bar also split
+// N = 100000, L = 5000, m = 7 (980 blocks), whose partial sums then cost more
+// than the blocks gained.
+__host__ __device__ inline int cols_rows(int64_t N, int64_t L, int m) {
+    const int64_t cb = (int64_t)SB * (m > 8 ? 4 : m > 4 ? 2 : 1);
+    const int64_t nbx = (L + cb - 1) / cb;
+    int cr = CR_ROWS;
+    while (cr > 128 && nbx * ((N + cr - 1) / cr) < 512) cr >>= 1;
+    return cr;
+}
+
 template <int MM>
 __device__ __forceinline__ void cols_dot_body(int64_t bx, int64_t by, int64_t N, int64_t L, int m,
                                      const double* __restrict__ H, int64_t ldh,
@@ -301,9 +316,10 @@ __device__ __forceinline__ void cols_dot_body(int64_t bx, int64_t by, int64_t N,
     // thread columns col0 + j SB, j < CPT (each load instruction reads 64
     // consecutive columns); a column past L reads column L - 1, unstored
     const int64_t col0 = bx * ColsDot<MM>::CB + tid;
-    const int64_t rbeg = by * CR_ROWS;
-    const int nrows = (int)min<int64_t>(CR_ROWS, N - rbeg);
-    for (int e = tid; e < CR_ROWS * MM; e += SB) {
+    const int cr = cols_rows(N, L, m);
+    const int64_t rbeg = by * cr;
+    const int nrows = (int)min<int64_t>(cr, N - rbeg);
+    for (int e = tid; e < cr * MM; e += SB) {
         const int r = e / MM, c = e % MM;
         Es[e] = (r < nrows && c < m) ? E[(rbeg + r) * lde + c] : 0.0;
     }
@@ -475,7 +491,7 @@ __global__ __launch_bounds__(NT) void ht_reduce_grouped(const RefineDesc* __rest
     const int j = group_problem(g, lb);
     if (!group_live(g, j)) return;
     const RefineDesc& q = d[j];
-    ht_reduce_body(lb, q.L, q.m, (int)cdiv(q.N, CR_ROWS), q.part, q.G, q.m, q.sq);
+    ht_reduce_body(lb, q.L, q.m, (int)cdiv(q.N, cols_rows(q.N, q.L, q.m)), q.part, q.G, q.m, q.sq);
 }
 
 __global__ __launch_bounds__(NT) void sum_grouped(const RefineDesc* __restrict__ d, GroupSched g) {
@@ -584,7 +600,8 @@ int64_t refine_group_blocks(RefinePass pass, const RefineDesc& q, int maxm) {
         case RefinePass::COLS_DOT:
             return cdiv(q.L, maxm <= 2 ? ColsDot<2>::CB
                              : maxm <= 4 ? ColsDot<4>::CB
-                             : maxm <= 8 ? ColsDot<8>::CB : ColsDot<16>::CB) * cdiv(q.N, CR_ROWS);
+                             : maxm <= 8 ? ColsDot<8>::CB : ColsDot<16>::CB) *
+                   cdiv(q.N, cols_rows(q.N, q.L, (int)q.m));
         case RefinePass::HT_REDUCE: return cdiv(q.L * q.m, NT);
         case RefinePass::SUM: return 1;
         case RefinePass::AXPY: return cdiv(q.L * q.m, 256);
@@ -592,7 +609,9 @@ int64_t refine_group_blocks(RefinePass pass, const RefineDesc& q, int maxm) {
     return 0;
 }
 
-size_t refine_part_doubles(int64_t N, int64_t L, int64_t m) { return (size_t)cdiv(N, CR_ROWS) * L * m; }
+size_t refine_part_doubles(int64_t N, int64_t L, int64_t m) {
+    return (size_t)cdiv(N, cols_rows(N, L, (int)m)) * L * m;
+}
 size_t refine_sq_doubles(int64_t L, int64_t m) { return (size_t)cdiv(L * m, NT); }
 
 void launch_refine_grouped(hipStream_t s, RefinePass pass, const RefineDesc* d, const GroupSched& g,
@@ -765,7 +784,7 @@ void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
     int nchunk;
     double* part;
     if (m <= 16) {
-        nchunk = (int)cdiv(N, CR_ROWS);
+        nchunk = (int)cdiv(N, cols_rows(N, L, mi));
         part = (double*)ws.get("ht_part", (size_t)nchunk * L * m * sizeof(double));
 #define ELM_CD(MM)                                                                               \
     cols_dot_kernel<MM><<<dim3((unsigned)cdiv(L, ColsDot<MM>::CB), (unsigned)nchunk), SB, 0, s>>>(      \
