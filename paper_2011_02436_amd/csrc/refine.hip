@@ -281,41 +281,127 @@ __device__ __forceinline__ void rows_dot_body(int64_t bx, int64_t N, int64_t L, 
     }
 }
 
+// Rows of a problem with 4 < m <= 16 on the FP64 16x16x4 MFMA (the wave
+// form above reloads m values of beta per column and row group and then
+// spends its time in the lane exchange).  A wave takes 16 rows and the 16
+// output columns (beta's columns past m read as zeros); lane (r, q) =
+// (lane % 16, lane / 16) reads H[row r][8 g + 2 q .. 8 g + 2 q + 1] as one
+// 16-byte pair and feeds the two values to two steps, so every sum runs over
+// the columns 8 g + 2 q, then 8 g + 2 q + 1, group after group, whatever the
+// launch.  Row arg-max (lowest index on ties) over the 16 lanes of the row.
+typedef double d2v __attribute__((ext_vector_type(2)));
+constexpr int RMB = 16 * (SB / 64);  // rows per block
+__device__ __forceinline__ void rows_mfma_body(int64_t bx, int64_t N, int64_t L, int m,
+                                               const double* __restrict__ H, int64_t ldh,
+                                               const double* __restrict__ beta, int64_t ldb,
+                                               const double* __restrict__ T, int64_t ldt, double sign,
+                                               double* __restrict__ out, int64_t ldo,
+                                               int32_t* __restrict__ labels, double* __restrict__ y,
+                                               int64_t ldy) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t r0 = bx * RMB + (int64_t)wave * 16;
+    if (r0 >= N) return;
+    const int q = lane >> 4, c = lane & 15;
+    const double* __restrict__ hrow = H + min(r0 + c, N - 1) * ldh;  // A row: lane % 16
+    const bool cv = c < m;
+    d4v acc = d4v{};
+    const int64_t L8 = L & ~(int64_t)7;
+    // 16-byte pairs when every row starts 16-byte aligned (block-uniform)
+    const bool pairs = ((((uintptr_t)H) | (uintptr_t)(ldh * 8)) & 15) == 0;
+    int64_t k = 0;
+    if (pairs) {
+#pragma unroll 4
+        for (; k < L8; k += 8) {
+            const d2v h = *(const d2v*)(hrow + k + 2 * q);
+            const double b0 = cv ? beta[(k + 2 * q) * ldb + c] : 0.0;
+            const double b1 = cv ? beta[(k + 2 * q + 1) * ldb + c] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h.x, b0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h.y, b1, acc, 0, 0, 0);
+        }
+    } else {
+#pragma unroll 4
+        for (; k < L8; k += 8) {
+            const double h0 = hrow[k + 2 * q], h1 = hrow[k + 2 * q + 1];
+            const double b0 = cv ? beta[(k + 2 * q) * ldb + c] : 0.0;
+            const double b1 = cv ? beta[(k + 2 * q + 1) * ldb + c] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h0, b0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h1, b1, acc, 0, 0, 0);
+        }
+    }
+    if (k < L) {  // the last group, fewer than 8 columns (wave-uniform)
+        const int64_t k0 = k + 2 * q, k1 = k0 + 1;
+        const double h0 = k0 < L ? hrow[k0] : 0.0, h1 = k1 < L ? hrow[k1] : 0.0;
+        const double b0 = (cv && k0 < L) ? beta[k0 * ldb + c] : 0.0;
+        const double b1 = (cv && k1 < L) ? beta[k1 * ldb + c] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h0, b0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h1, b1, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + Mfma16<double>::row(lane, v);  // column c = lane % 16
+        const double val = acc[v];
+        if (row < N && cv) {
+            if (out) out[row * ldo + c] = sign * val + (T ? T[row * ldt + c] : 0.0);
+            if (y) y[row * ldy + c] = val;
+        }
+        if (labels) {
+            double bv = cv ? val : -INFINITY;
+            int bi = c;
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o);
+                const int oi = __shfl_xor(bi, o);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            if (c == 0 && row < N) labels[row] = bi;
+        }
+    }
+}
+
 // columns per thread of cols_dot_kernel: each E value read from LDS serves
-// CPT columns, so that a row costs about four LDS reads per H element
+// CPT columns, so that a row costs about four LDS reads per H element (the
+// batches' grouped launches keep one column per thread: their narrow
+// problems would leave most of a wider block idle; a column's sum does not
+// depend on it)
 template <int MM>
 struct ColsDot {
     static constexpr int CPT = MM >= 8 ? MM / 4 : 1;
     static constexpr int CB = SB * CPT;  // columns per block
 };
 
-// Rows per chunk of the column pass: CR_ROWS, halved (down to 128) while
-// the pass would have fewer than 512 blocks (a function of the problem's own
-// N, L and m, so a batch chunks each problem as its single training does).
-// On N = 60000, L = 2000, m = 10 (118 blocks of 1024 rows) four passes took
-// 2.0 ms, 1.65 in chunks of 128 rows; a 1024-block bar also split
-// N = 100000, L = 5000, m = 7 (980 blocks), whose partial sums then cost more
-// than the blocks gained.
+// Rows per chunk of the column pass: CR_ROWS, and for an H of at least 2^26
+// elements halved (down to 128) while the pass would have fewer than 512
+// blocks (a function of the problem's own N, L and m, so a batch chunks each
+// problem as its single training does).  On N = 60000, L = 2000, m = 10
+// (118 blocks of 1024 rows) four passes took 2.0 ms, 1.65 in chunks of 128
+// rows; a 1024-block bar also split N = 100000, L = 5000, m = 7 (980 blocks),
+// whose partial sums then cost more than the blocks gained, and without the
+// size floor the batch's small problems took their column passes from 12.6
+// to 14.8 ms per 256 trainings.
 __host__ __device__ inline int cols_rows(int64_t N, int64_t L, int m) {
+    int cr = CR_ROWS;
+    if (N * L < ((int64_t)1 << 26)) return cr;
     const int64_t cb = (int64_t)SB * (m > 8 ? 4 : m > 4 ? 2 : 1);
     const int64_t nbx = (L + cb - 1) / cb;
-    int cr = CR_ROWS;
     while (cr > 128 && nbx * ((N + cr - 1) / cr) < 512) cr >>= 1;
     return cr;
 }
 
-template <int MM>
+template <int MM, int CPT = ColsDot<MM>::CPT>
 __device__ __forceinline__ void cols_dot_body(int64_t bx, int64_t by, int64_t N, int64_t L, int m,
                                      const double* __restrict__ H, int64_t ldh,
                                      const double* __restrict__ E, int64_t lde,
                                      double* __restrict__ part) {
-    constexpr int CPT = ColsDot<MM>::CPT;
     constexpr int RU = CPT > 2 ? 4 : 8;  // rows per unrolled step
     __shared__ double Es[CR_ROWS * MM];
     const int tid = threadIdx.x;
     // thread columns col0 + j SB, j < CPT (each load instruction reads 64
     // consecutive columns); a column past L reads column L - 1, unstored
-    const int64_t col0 = bx * ColsDot<MM>::CB + tid;
+    const int64_t col0 = bx * (SB * CPT) + tid;
     const int cr = cols_rows(N, L, m);
     const int64_t rbeg = by * cr;
     const int nrows = (int)min<int64_t>(cr, N - rbeg);
@@ -427,8 +513,11 @@ __global__ __launch_bounds__(SB, 2) void rows_dot_kernel(int64_t N, int64_t L, i
                                                       double sign, double* __restrict__ out,
                                                       int64_t ldo, int32_t* __restrict__ labels,
                                                       double* __restrict__ y, int64_t ldy) {
-    rows_dot_body<MM>(blockIdx.x, N, L, m, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y,
-                      ldy);
+    if constexpr (MM > 4)
+        rows_mfma_body(blockIdx.x, N, L, m, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy);
+    else
+        rows_dot_body<MM>(blockIdx.x, N, L, m, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y,
+                          ldy);
 }
 
 template <int MM>
@@ -470,8 +559,13 @@ __global__ __launch_bounds__(SB, 2) void rows_dot_grouped(const RefineDesc* __re
     const int j = group_problem(g, lb);
     if (!group_live(g, j)) return;
     const RefineDesc& q = d[j];
-    rows_dot_body<MM>(lb, q.N, q.L, q.m, q.H, q.ldh, q.beta, q.ldbeta, q.T, q.ldt, -1.0, q.E, q.m,
-                      nullptr, nullptr, 0);
+    // the form of the problem's own m (that of its single training)
+    if (MM > 4 && q.m > 4)
+        rows_mfma_body(lb, q.N, q.L, q.m, q.H, q.ldh, q.beta, q.ldbeta, q.T, q.ldt, -1.0, q.E, q.m,
+                       nullptr, nullptr, 0);
+    else
+        rows_dot_body<MM>(lb, q.N, q.L, q.m, q.H, q.ldh, q.beta, q.ldbeta, q.T, q.ldt, -1.0, q.E, q.m,
+                          nullptr, nullptr, 0);
 }
 
 template <int MM>
@@ -481,8 +575,8 @@ __global__ __launch_bounds__(SB) void cols_dot_grouped(const RefineDesc* __restr
     const int j = group_problem(g, lb);
     if (!group_live(g, j)) return;
     const RefineDesc& q = d[j];
-    const int64_t nbx = cdiv(q.L, ColsDot<MM>::CB);
-    cols_dot_body<MM>(lb % nbx, lb / nbx, q.N, q.L, q.m, q.H, q.ldh, q.E, q.m, q.part);
+    const int64_t nbx = cdiv(q.L, SB);
+    cols_dot_body<MM, 1>(lb % nbx, lb / nbx, q.N, q.L, q.m, q.H, q.ldh, q.E, q.m, q.part);
 }
 
 __global__ __launch_bounds__(NT) void ht_reduce_grouped(const RefineDesc* __restrict__ d,
@@ -594,14 +688,11 @@ void launch_restore_grouped(hipStream_t s, const RefineDesc* d, const GroupSched
 int64_t refine_group_blocks(RefinePass pass, const RefineDesc& q, int maxm) {
     switch (pass) {
         case RefinePass::ROWS_DOT:
+            if (q.m > 4) return cdiv(q.N, RMB);
             return cdiv(q.N, maxm <= 2 ? RowsDot<2>::RB
                              : maxm <= 4 ? RowsDot<4>::RB
                              : maxm <= 8 ? RowsDot<8>::RB : RowsDot<16>::RB);
-        case RefinePass::COLS_DOT:
-            return cdiv(q.L, maxm <= 2 ? ColsDot<2>::CB
-                             : maxm <= 4 ? ColsDot<4>::CB
-                             : maxm <= 8 ? ColsDot<8>::CB : ColsDot<16>::CB) *
-                   cdiv(q.N, cols_rows(q.N, q.L, (int)q.m));
+        case RefinePass::COLS_DOT: return cdiv(q.L, SB) * cdiv(q.N, cols_rows(q.N, q.L, (int)q.m));
         case RefinePass::HT_REDUCE: return cdiv(q.L * q.m, NT);
         case RefinePass::SUM: return 1;
         case RefinePass::AXPY: return cdiv(q.L * q.m, 256);
@@ -649,7 +740,7 @@ static void launch_rows_dot(hipStream_t s, int64_t N, int64_t L, int64_t m, cons
                             double* y = nullptr, int64_t ldy = 0) {
     const int mi = (int)m;
 #define ELM_RD(MM)                                                                                  \
-    rows_dot_kernel<MM><<<(unsigned)cdiv(N, RowsDot<MM>::RB), SB, 0, s>>>(                          \
+    rows_dot_kernel<MM><<<(unsigned)cdiv(N, MM > 4 ? RMB : RowsDot<MM>::RB), SB, 0, s>>>(           \
         N, L, mi, H, ldh, beta, ldb, T, ldt, sign, out, ldo, labels, y, ldy)
     if (m <= 2)
         ELM_RD(2);
