@@ -142,7 +142,8 @@ elm_status elm_hidden(elm_handle* h, int64_t N, int64_t d, int64_t L,
  *
  * *out receives a library-owned factor (free with elm_factor_destroy).
  * rank (host, may be NULL) receives r.  This call synchronises the stream
- * once (the rank sizes the later steps).
+ * (the rank sizes the later steps; the duplicate check and the certified
+ * path below read a few values back each).
  * Errors: INVALID_ARG / SHAPE / UNSUPPORTED as above; NOT_PSD if the Gram has
  * a non-finite diagonal; ALLOC; HIP. */
 elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L,
@@ -158,7 +159,9 @@ elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t 
 
 /* elm_gram for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc).
- * Same arguments, accepted inputs, kernels and result as elm_gram; the
+ * Same arguments, accepted inputs and result as elm_gram (its FP64 Gram on
+ * the 128 x 128 Gram tiles, which take each element's products in the order
+ * of elm_gram's FP64 GEMM route); the
  * split-K partial tiles go to a static device array of 64 MiB per GPU
  * (allocated with the library's code on each device it runs on and held
  * until the process ends) instead of the handle's workspace, and this call
