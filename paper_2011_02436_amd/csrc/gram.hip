@@ -245,17 +245,14 @@ void plan_chunks(int64_t ntile, int64_t K, int64_t quantum, int64_t& kc_len, int
     nchunk = (int)cdiv(K, kc_len);
 }
 
-// K chunks of the FP32/FP64 Gram: force_chunks > 0, else the tuning table's
-// row for this shape, else plan_chunks' rule
-void gram16_chunks(int dt, int64_t n, int64_t ntile, int64_t K, int force_chunks, const Workspace& ws,
-                   int64_t& kc_len, int& nchunk) {
+// The default K chunks of the FP32/FP64 Gram: plan_chunks' rule, and for
+// FP64 chunks of about 16384 samples (within 16 GiB of partial products),
+// which keep the blocks that share a panel in step (L2 reuse).  On N = 500000,
+// L = 10000 the Gram took 1109 ms in one chunk, 1029 in 8, 1013 in 16 and
+// 1000 in 32; on N = 100000, L = 5000 58.9 ms in 2, 56.9 in 8 and 55.2 in 32.
+static void default_chunks(int dt, int64_t n, int64_t ntile, int64_t K, int64_t& kc_len, int& nchunk) {
     plan_chunks(ntile, K, 16, kc_len, nchunk);
     if (dt == ELM_F64) {
-        // FP64: chunks of about 16384 samples keep the blocks that share a
-        // panel in step (L2 reuse), within 16 GiB of partial products.  On
-        // N = 500000, L = 10000 the Gram took 1109 ms in one chunk, 1029 in
-        // 8, 1013 in 16 and 1000 in 32; on N = 100000, L = 5000 58.9 ms in
-        // 2, 56.9 in 8 and 55.2 in 32.
         const int64_t cap = std::max<int64_t>(1, ((int64_t)16 << 30) / (8 * n * n));
         const int64_t want = std::min<int64_t>(std::min<int64_t>(cdiv(K, 16384), 32), cap);
         if (want > nchunk) {
@@ -263,6 +260,13 @@ void gram16_chunks(int dt, int64_t n, int64_t ntile, int64_t K, int force_chunks
             nchunk = (int)cdiv(K, kc_len);
         }
     }
+}
+
+// K chunks of the FP32/FP64 Gram: force_chunks > 0, else the tuning table's
+// row for this shape, else the default rule
+void gram16_chunks(int dt, int64_t n, int64_t ntile, int64_t K, int force_chunks, const Workspace& ws,
+                   int64_t& kc_len, int& nchunk) {
+    default_chunks(dt, n, ntile, K, kc_len, nchunk);
     int nc = force_chunks > 0 ? force_chunks : ws.find_tune(ELM_TUNE_GRAM_CHUNKS, dt, n, K);
     if (nc > 0) {
         nc = std::max(1, std::min(64, nc));
@@ -950,10 +954,11 @@ constexpr int MAX_DEVICES = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[MAX_DEVICES] = {};
 
-// chunks of K for the 128-tile FP64/FP32 Gram: plan_chunks' count, lowered
-// until ntile * nchunk partial tiles of `tile_bytes` fit in the scratch
-bool fit_chunks(int64_t ntile, int64_t K, size_t tile_bytes, int64_t& kc_len, int& nchunk) {
-    plan_chunks(ntile, K, 16, kc_len, nchunk);
+// chunks of K for the 128-tile FP64/FP32 Gram: elm_gram's default count,
+// lowered until ntile * nchunk partial tiles of `tile_bytes` fit in the scratch
+bool fit_chunks(int dt, int64_t n, int64_t ntile, int64_t K, size_t tile_bytes, int64_t& kc_len,
+                int& nchunk) {
+    default_chunks(dt, n, ntile, K, kc_len, nchunk);
     for (int64_t nc = nchunk; nc >= 1; --nc) {
         kc_len = cdiv(cdiv(K, nc), 16) * 16;
         nchunk = (int)cdiv(K, kc_len);
@@ -992,7 +997,7 @@ void launch_gram_noalloc(hipStream_t s, int device, elm_dtype dt, int64_t N, int
         const size_t tb = (size_t)TILE * TILE * (dt == ELM_F64 ? sizeof(double) : sizeof(float));
         int64_t kc_len;
         int nchunk;
-        if (!fit_chunks(ntile, K, tb, kc_len, nchunk))
+        if (!fit_chunks(dt, n, ntile, K, tb, kc_len, nchunk))
             throw Error{ELM_ERR_SHAPE, "Gram order too large for the static scratch of elm_gram_noalloc"};
         dim3 grid((unsigned)ntile, (unsigned)nchunk);
         if (dt == ELM_F64) {
