@@ -5,7 +5,8 @@ small problems take the path.  Covered: ragged last blocks (300 = 2 x 128 +
 44, 1000 = 7 x 128 + 104, single rows at 129 and 1153), one block (128),
 look-ahead updates on a second stream (1300, 1153), the
 N < L route, duplicated nodes (bitwise-equal Gram rows: set aside, the
-distinct nodes certified; the greedy rule with the path off),
+distinct nodes certified; the greedy rule with the path off), duplicated
+samples on the N < L route,
 dependent columns with no repeated value (the unpivoted factorisation stops
 and the greedy rule runs), distinct columns with equal norms (certified), a
 threshold the certificate cannot clear (the greedy rule runs, full rank) and
@@ -196,3 +197,24 @@ def test_equal_norms_without_duplicates_are_certified(elm):
     f = elm.elm_rank_factor(torch.from_numpy(H).to("cuda:0"))
     assert f.info()["certified_full_rank"]
     assert f.rank == np.linalg.matrix_rank(H) == 300
+
+
+def test_duplicated_samples_on_the_transposed_route(elm):
+    # N < L (the Gram H H^T): 60 of 600 samples repeat others, so 60 rows of
+    # H and of the Gram repeat: set aside, the 540 distinct samples certified,
+    # with the oracle's rank and beta
+    rng = np.random.default_rng(63)
+    p = wl.random_problem(63, 600, 32, 900, 3)
+    X = p.X.copy()
+    rows = rng.choice(600, size=60, replace=False)
+    X[rows] = X[rng.choice(np.setdiff1d(np.arange(600), rows), size=60)]
+    H = O.hidden(X, p.W, p.b)
+    beta_ref, F = O.solve(H, p.T)
+    assert F.r == len(np.unique(X, axis=0)) == 540
+    res = elm.train(to_dev(X), to_dev(p.W), to_dev(p.b), to_dev(p.T), precision="fp64", ir_tol=1e-12)
+    fi = res.info["factor"]
+    assert fi["transposed"] and fi["certified_full_rank"] == 2
+    assert res.rank == 540
+    err = O.rel_err(res.beta.cpu().numpy(), beta_ref)
+    print(f"beta err {err:.2e} (bar 1e-10)")
+    assert err <= 1e-10
