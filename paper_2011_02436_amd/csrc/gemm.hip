@@ -131,8 +131,23 @@ __device__ __forceinline__ void gemm_body(int64_t bx, int64_t by, int64_t bz, in
             buf ^= 1;
         }
     }
+    // With beta != 0 a block row's C values are read together (clamped
+    // addresses, all in range) before its stores: read, wait and store per
+    // element had put 32 memory round trips after every tile.
+    const bool use_c = beta != 0.0;  // block-uniform
 #pragma unroll
-    for (int x = 0; x < WBI; ++x)
+    for (int x = 0; x < WBI; ++x) {
+        double cold[WBJ][4];
+        if (use_c) {
+#pragma unroll
+            for (int y = 0; y < WBJ; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t gi = i0 + wm * (TS / 2) + x * 16 + Mfma16<double>::row(lane, v);
+                    const int64_t gj = j0 + wn * (TS / WGN) + y * 16 + (lane & 15);
+                    cold[y][v] = C[(gi < M ? gi : M - 1) * ldc + (gj < N ? gj : N - 1)];
+                }
+        }
 #pragma unroll
         for (int y = 0; y < WBJ; ++y)
 #pragma unroll
@@ -141,9 +156,10 @@ __device__ __forceinline__ void gemm_body(int64_t bx, int64_t by, int64_t bz, in
                 const int64_t gj = j0 + wn * (TS / WGN) + y * 16 + (lane & 15);
                 if (gi >= M || gj >= N) continue;
                 double c = alpha * acc[x][y][v];
-                if (beta != 0.0) c += beta * C[gi * ldc + gj];
+                if (use_c) c += beta * cold[y][v];
                 C[gi * ldc + gj] = c;
             }
+    }
 }
 
 template <int TS, int NTH>
