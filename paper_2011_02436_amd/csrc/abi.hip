@@ -1008,7 +1008,7 @@ void refine_grouped(elm_handle* h, hipStream_t s, std::vector<GroupedSolve>& gs,
         nblk[(size_t)K_SCU * P + j] = copy_rows_group_blocks(cp[(size_t)2 * P + j]);
         nblk[(size_t)K_SCB * P + j] = copy_rows_group_blocks(cp[(size_t)4 * P + j]);
         for (int k = 0; k < 7; ++k)
-            nblk[(size_t)(K_P0 + k) * P + j] = rowprod_group_blocks(rp[(size_t)k * P + j]);
+            nblk[(size_t)(K_P0 + k) * P + j] = rowprod_group_blocks(rp[(size_t)k * P + j], maxm);
     }
     const size_t per = (size_t)2 * P + 1;
     std::vector<int32_t> hs((size_t)NK * per);

@@ -801,7 +801,7 @@ struct CopyRowsDesc {
     double* dst = nullptr;
     int64_t ldd = 0;
 };
-int64_t rowprod_group_blocks(const RowprodDesc& q);
+int64_t rowprod_group_blocks(const RowprodDesc& q, int maxm);
 int64_t copy_rows_group_blocks(const CopyRowsDesc& q);
 void launch_rowprod_grouped(hipStream_t s, const RowprodDesc* d, const GroupSched& g, int maxm);
 void launch_copy_rows_grouped(hipStream_t s, bool scatter, const CopyRowsDesc* d, const GroupSched& g);

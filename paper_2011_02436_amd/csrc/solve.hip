@@ -87,56 +87,83 @@ __global__ void zero_mat_kernel(int64_t rows, int64_t cols, double* __restrict__
 }
 
 // C[i][c] = alpha * sum_k A[i][k] B[k][c] + beta * C[i][c] for thin B (m <= MM
-// columns): one wave per output row, lanes striding over k (coalesced reads
-// of A's row and of B's rows), fixed-order lane reduction.  tri restricts k
-// to the nonzero part of a triangular A (1: k >= i, 2: k <= i).
+// columns): a wave takes RP rows (so that each B value read serves RP rows),
+// lane l the columns k = l (mod 64) of every row, fixed-order lane reduction.
+// tri restricts k to the nonzero part of a triangular A (1: k >= i, 2:
+// k <= i); a row's columns outside its range are masked, so its lane sums,
+// and by the halving exchange its whole sum, do not depend on which rows
+// share its wave (the batch's launches may take another MM than a single
+// problem's).
+template <int MM>
+struct Rowprod {
+    static constexpr int RP = MM <= 16 ? 4 : 1;  // rows per wave
+    static constexpr int RB = 4 * RP;             // rows per block
+};
+
 template <int MM>
 __device__ __forceinline__ void rowprod_body(int64_t bx, int64_t M, int64_t K, int m, double alpha,
                                     const double* __restrict__ A, int64_t lda, int tri,
                                     const double* __restrict__ B, int64_t ldb, double beta,
                                     double* C, int64_t ldc) {
+    constexpr int RP = Rowprod<MM>::RP;
     const int lane = threadIdx.x & 63;
-    const int64_t i = bx * 4 + (threadIdx.x >> 6);
-    if (i >= M) return;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t i0 = (bx * 4 + wave) * RP;
+    if (i0 >= M) return;
+    // the wave's columns: the union of its rows' ranges, from a multiple of 64
     int64_t kb = 0, ke = K;
-    if (tri == 1) kb = i;
-    if (tri == 2) ke = min(K, i + 1);
-    double acc[MM];
+    if (tri == 1) kb = i0 & ~(int64_t)63;
+    if (tri == 2) ke = min(K, min(i0 + RP, M));
+    double acc[RP][MM];
+    const double* __restrict__ arow[RP];
+    int64_t klo[RP], khi[RP];
 #pragma unroll
-    for (int c = 0; c < MM; ++c) acc[c] = 0.0;
-    const double* __restrict__ arow = A + i * lda;
-    for (int64_t k = kb + lane; k < ke; k += 64) {
-        const double a = arow[k];
-        const double* __restrict__ brow = B + k * ldb;
+    for (int r = 0; r < RP; ++r) {
 #pragma unroll
-        for (int c = 0; c < MM; ++c)
-            if (c < m) acc[c] += a * brow[c];
+        for (int c = 0; c < MM; ++c) acc[r][c] = 0.0;
+        const int64_t i = min(i0 + r, M - 1);
+        arow[r] = A + i * lda;
+        klo[r] = tri == 1 ? i0 + r : 0;                   // rows past M: empty range
+        khi[r] = i0 + r >= M ? 0 : tri == 2 ? min(K, i0 + r + 1) : K;
     }
-    // the MM sums by a halving exchange across the lanes: at offset o a lane
-    // keeps half of its partial sums (the upper half when lane & o) and adds
-    // its partner's values of that half, so each sum is formed by a
-    // butterfly's pairwise tree with MM/2 + MM/4 + ... shuffles instead of
-    // 6 MM; sum c ends in lane c * (64 / MM)
-    static_assert(MM <= 64 && (MM & (MM - 1)) == 0, "a power-of-two count of sums");
-    constexpr int DUP = 64 / MM;
+    for (int64_t k = kb + lane; k < ke; k += 64) {
+        double bv[MM];
+#pragma unroll
+        for (int c = 0; c < MM; ++c) bv[c] = c < m ? B[k * ldb + c] : 0.0;
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            const double a = (k >= klo[r] && k < khi[r]) ? arow[r][k] : 0.0;
+#pragma unroll
+            for (int c = 0; c < MM; ++c) acc[r][c] += a * bv[c];
+        }
+    }
+    // the RP MM sums by a halving exchange across the lanes: at offset o a
+    // lane keeps half of its partial sums (the upper half when lane & o) and
+    // adds its partner's values of that half, so each sum is formed by a
+    // butterfly's pairwise tree; value r MM + c ends in lane (r MM + c) DUP
+    constexpr int V = RP * MM;
+    static_assert(V <= 64 && (V & (V - 1)) == 0, "a power-of-two count of sums");
+    constexpr int DUP = 64 / V;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const int o = 32 >> k, n = MM >> k;
+        const int o = 32 >> k, n = V >> k;
         if (n > 1) {
             const bool up = (lane & o) != 0;
 #pragma unroll
-            for (int c = 0; c < n / 2; ++c) {
-                const double lo = acc[c], hi = acc[c + n / 2];
+            for (int q = 0; q < n / 2; ++q) {
+                double& lo = acc[q / MM][q % MM];
+                const double hi = acc[(q + n / 2) / MM][(q + n / 2) % MM];
                 const double send = up ? lo : hi, keep = up ? hi : lo;
-                acc[c] = keep + __shfl_xor(send, o);
+                lo = keep + __shfl_xor(send, o);
             }
         } else {
-            acc[0] += __shfl_xor(acc[0], o);
+            acc[0][0] += __shfl_xor(acc[0][0], o);
         }
     }
-    const int c = lane / DUP;
-    if (lane % DUP == 0 && c < m) {
-        double v = alpha * acc[0];
+    const int idx = lane / DUP, r = idx / MM, c = idx % MM;
+    const int64_t i = i0 + r;
+    if (lane % DUP == 0 && c < m && i < M) {
+        double v = alpha * acc[0][0];
         if (beta != 0.0) v += beta * C[i * ldc + c];
         C[i * ldc + c] = v;
     }
@@ -229,16 +256,19 @@ __global__ __launch_bounds__(256) void mat_grouped(const MatDesc* __restrict__ d
 void rowprod(hipStream_t s, int64_t M, int64_t K, int64_t m, double alpha, const double* A, int64_t lda,
              int tri, const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
     if (M <= 0) return;
-    const unsigned grid = (unsigned)cdiv(M, 4);
     const int mi = (int)m;
+#define ELM_RP(MM)                                                                                  \
+    rowprod_kernel<MM><<<(unsigned)cdiv(M, Rowprod<MM>::RB), 256, 0, s>>>(M, K, mi, alpha, A, lda, tri, B, \
+                                                                         ldb, beta, C, ldc)
     if (m <= 4)
-        rowprod_kernel<4><<<grid, 256, 0, s>>>(M, K, mi, alpha, A, lda, tri, B, ldb, beta, C, ldc);
+        ELM_RP(4);
     else if (m <= 8)
-        rowprod_kernel<8><<<grid, 256, 0, s>>>(M, K, mi, alpha, A, lda, tri, B, ldb, beta, C, ldc);
+        ELM_RP(8);
     else if (m <= 16)
-        rowprod_kernel<16><<<grid, 256, 0, s>>>(M, K, mi, alpha, A, lda, tri, B, ldb, beta, C, ldc);
+        ELM_RP(16);
     else
-        rowprod_kernel<64><<<grid, 256, 0, s>>>(M, K, mi, alpha, A, lda, tri, B, ldb, beta, C, ldc);
+        ELM_RP(64);
+#undef ELM_RP
     ELM_LAUNCH_CHECK();
 }
 
@@ -374,7 +404,10 @@ void launch_mat_grouped(hipStream_t s, MatOp op, const MatDesc* d, const GroupSc
     ELM_LAUNCH_CHECK();
 }
 
-int64_t rowprod_group_blocks(const RowprodDesc& q) { return q.M > 0 ? cdiv(q.M, 4) : 0; }
+int64_t rowprod_group_blocks(const RowprodDesc& q, int maxm) {
+    const int64_t rb = maxm <= 16 ? Rowprod<16>::RB : Rowprod<64>::RB;  // the launch's template
+    return q.M > 0 ? cdiv(q.M, rb) : 0;
+}
 
 int64_t copy_rows_group_blocks(const CopyRowsDesc& q) { return cdiv(q.rows * q.cols, 256); }
 
