@@ -628,20 +628,34 @@ __device__ __forceinline__ void gram_reduce256_body(int64_t bx, int64_t by, int6
     tile_coords(bx, bi, bj);
     const int sr = (int)(by / (GT / RS)), sc = (int)(by % (GT / RS));
     const int64_t r0 = (int64_t)bi * GT + sr * RS, c0 = (int64_t)bj * GT + sc * RS;
-    const int tx = threadIdx.x % RS, ty = threadIdx.x / RS;  // 32 x 8 threads
-    for (int k = 0; k < RS; k += NT / RS) {
-        const int row = ty + k;
-        const int64_t gi = r0 + row, gj = c0 + tx;
-        double s = 0.0;
-        const bool on = gi < n && gj < n && gi <= gj;
-        if (on) {
-            const int64_t e = (int64_t)(sr * RS + row) * GT + sc * RS + tx;  // element within the tile
-            for (int c = 0; c < nsplit; ++c) s += (double)part[((int64_t)c * ntile + bx) * (GT * GT) + e];
-            M[gi * ldm + gj] = s;
+    // thread (row, quad): 4 consecutive columns of one row, read as 16 bytes
+    // per split (the partial tiles are whole 256 x 256 arrays, so the quad is
+    // in range even where the Gram is ragged); each element summed over the
+    // splits in order, in FP64
+    {
+        const int row = threadIdx.x / (RS / 4), q4 = threadIdx.x % (RS / 4);  // 32 x 8 threads
+        const int64_t gi = r0 + row;
+        const int64_t e = (int64_t)(sr * RS + row) * GT + sc * RS + 4 * q4;  // first element within the tile
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        if (gi < n && gi <= c0 + 4 * q4 + 3) {  // some column of the quad is kept
+            for (int c = 0; c < nsplit; ++c) {
+                const float4 v = *(const float4*)&part[((int64_t)c * ntile + bx) * (GT * GT) + e];
+                s[0] += (double)v.x;
+                s[1] += (double)v.y;
+                s[2] += (double)v.z;
+                s[3] += (double)v.w;
+            }
         }
-        sm[row][tx] = s;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t gj = c0 + 4 * q4 + u;
+            const bool on = gi < n && gj < n && gi <= gj;
+            if (on) M[gi * ldm + gj] = s[u];
+            sm[row][4 * q4 + u] = on ? s[u] : 0.0;
+        }
     }
     __syncthreads();
+    const int tx = threadIdx.x % RS, ty = threadIdx.x / RS;  // 32 x 8 threads
     for (int k = 0; k < RS; k += NT / RS) {
         const int col = ty + k;                 // sub-tile column: the mirrored row
         const int64_t gi = r0 + tx, gj = c0 + col;
