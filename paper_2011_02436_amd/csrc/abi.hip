@@ -553,7 +553,7 @@ elm_status elm_autotune_gram(elm_handle* h, int64_t N, int64_t L, const void* Hn
         REQUIRE(ldn >= (dt == ELM_F64 ? L : N), ELM_ERR_SHAPE, "leading dimension smaller than the row");
         elm::use_device(h);
         const bool lp = dt == ELM_BF16 || dt == ELM_F16;
-        const int base = lp ? elm::gram_default_splits(N, L) : elm::gram16_default_chunks(L, N);
+        const int base = lp ? elm::gram_default_splits(N, L) : elm::gram16_default_chunks(dt, L, N);
         std::vector<int> cand;
         for (double f : {1.0, 0.5, 0.75, 1.5, 2.0}) {
             int c = (int)std::lround(base * f);
@@ -1632,7 +1632,7 @@ elm_status elm_autotune_batch(elm_handle* h, int32_t count, const elm_problem* p
             h->ws.put_tune(ELM_TUNE_PANEL, -1, -1, -1, panel);
             for (const Rep& r : reps) {
                 const int def = r.kind == ELM_TUNE_GRAM_SPLITS ? elm::gram_default_splits(r.k, r.n)
-                                                               : elm::gram16_default_chunks(r.n, r.k);
+                                                               : elm::gram16_default_chunks(r.dt, r.n, r.k);
                 const int v = std::max(1, std::min(r.kind == ELM_TUNE_GRAM_SPLITS ? 48 : 64,
                                                    (int)std::lround(def * scale)));
                 h->ws.put_tune(r.kind, r.dt, r.n, r.k, v);

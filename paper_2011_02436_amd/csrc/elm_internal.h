@@ -308,7 +308,7 @@ int64_t launch_gram_lp_nodes(hipStream_t s, elm_dtype dt, int64_t N, int64_t L, 
 //   the default rule's K splits for a 16-bit Gram of L nodes over N samples,
 //   and K chunks for an FP32/FP64 Gram of order n over K products
 int gram_default_splits(int64_t N, int64_t L);
-int gram16_default_chunks(int64_t n, int64_t K);
+int gram16_default_chunks(int dt, int64_t n, int64_t K);
 //   the Gram of elm_gram with its partial tiles in a static device array of
 //   GRAM_NOALLOC_SCRATCH_BYTES per GPU instead of the workspace (no device
 //   allocation); K splits lowered until they fit, ELM_ERR_SHAPE if none does

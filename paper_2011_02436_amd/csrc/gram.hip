@@ -824,11 +824,11 @@ int gram_default_splits(int64_t N, int64_t L) {
     return pick_splits(nt * (nt + 1) / 2, N);
 }
 
-int gram16_default_chunks(int64_t n, int64_t K) {
+int gram16_default_chunks(int dt, int64_t n, int64_t K) {
     const int64_t nt = cdiv(n, TILE);
     int64_t kc_len;
     int nchunk;
-    plan_chunks(nt * (nt + 1) / 2, K, 16, kc_len, nchunk);
+    default_chunks(dt, n, nt * (nt + 1) / 2, K, kc_len, nchunk);
     return nchunk;
 }
 
