@@ -391,13 +391,13 @@ __host__ __device__ inline int cols_rows(int64_t N, int64_t L, int m) {
     return cr;
 }
 
-template <int MM, int CPT = ColsDot<MM>::CPT>
+template <int MM, int CPT = ColsDot<MM>::CPT, int CRCAP = CR_ROWS>
 __device__ __forceinline__ void cols_dot_body(int64_t bx, int64_t by, int64_t N, int64_t L, int m,
                                      const double* __restrict__ H, int64_t ldh,
                                      const double* __restrict__ E, int64_t lde,
                                      double* __restrict__ part) {
     constexpr int RU = CPT > 2 ? 4 : 8;  // rows per unrolled step
-    __shared__ double Es[CR_ROWS * MM];
+    __shared__ double Es[CRCAP * MM];  // the chunk's rows of E (cr <= CRCAP)
     const int tid = threadIdx.x;
     // thread columns col0 + j SB, j < CPT (each load instruction reads 64
     // consecutive columns); a column past L reads column L - 1, unstored
@@ -520,12 +520,14 @@ __global__ __launch_bounds__(SB, 2) void rows_dot_kernel(int64_t N, int64_t L, i
                           ldy);
 }
 
-template <int MM>
+// CRCAP: the largest chunk the launch may take; a launch whose chunks are
+// 128 rows reserves that much LDS, so more blocks share a CU
+template <int MM, int CRCAP>
 __global__ __launch_bounds__(SB) void cols_dot_kernel(int64_t N, int64_t L, int m,
                                                       const double* __restrict__ H, int64_t ldh,
                                                       const double* __restrict__ E, int64_t lde,
                                                       double* __restrict__ part) {
-    cols_dot_body<MM>(blockIdx.x, blockIdx.y, N, L, m, H, ldh, E, lde, part);
+    cols_dot_body<MM, ColsDot<MM>::CPT, CRCAP>(blockIdx.x, blockIdx.y, N, L, m, H, ldh, E, lde, part);
 }
 
 __global__ __launch_bounds__(NT) void ht_reduce_kernel(int64_t L, int m, int nchunk,
@@ -875,11 +877,17 @@ void launch_ht_times(hipStream_t s, int64_t N, int64_t L, int64_t m, const doubl
     int nchunk;
     double* part;
     if (m <= 16) {
-        nchunk = (int)cdiv(N, cols_rows(N, L, mi));
+        const int cr = cols_rows(N, L, mi);
+        nchunk = (int)cdiv(N, cr);
         part = (double*)ws.get("ht_part", (size_t)nchunk * L * m * sizeof(double));
 #define ELM_CD(MM)                                                                               \
-    cols_dot_kernel<MM><<<dim3((unsigned)cdiv(L, ColsDot<MM>::CB), (unsigned)nchunk), SB, 0, s>>>(      \
-        N, L, mi, H, ldh, E, lde, part)
+    do {                                                                                         \
+        const dim3 grid((unsigned)cdiv(L, ColsDot<MM>::CB), (unsigned)nchunk);                   \
+        if (cr <= 128)                                                                           \
+            cols_dot_kernel<MM, 128><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, E, lde, part);        \
+        else                                                                                     \
+            cols_dot_kernel<MM, CR_ROWS><<<grid, SB, 0, s>>>(N, L, mi, H, ldh, E, lde, part);    \
+    } while (0)
         if (m <= 2)
             ELM_CD(2);
         else if (m <= 4)
