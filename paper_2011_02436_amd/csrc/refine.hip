@@ -283,14 +283,16 @@ __device__ __forceinline__ void rows_dot_body(int64_t bx, int64_t N, int64_t L, 
 
 // Rows of a problem with 4 < m <= 16 on the FP64 16x16x4 MFMA (the wave
 // form above reloads m values of beta per column and row group and then
-// spends its time in the lane exchange).  A wave takes 16 rows and the 16
-// output columns (beta's columns past m read as zeros); lane (r, q) =
+// spends its time in the lane exchange).  A wave takes two groups of 16 rows
+// (each beta value read serves both) and the 16 output columns (beta's
+// columns past m read as zeros); in each group lane (r, q) =
 // (lane % 16, lane / 16) reads H[row r][8 g + 2 q .. 8 g + 2 q + 1] as one
 // 16-byte pair and feeds the two values to two steps, so every sum runs over
 // the columns 8 g + 2 q, then 8 g + 2 q + 1, group after group, whatever the
 // launch.  Row arg-max (lowest index on ties) over the 16 lanes of the row.
 typedef double d2v __attribute__((ext_vector_type(2)));
-constexpr int RMB = 16 * (SB / 64);  // rows per block
+constexpr int RMG = 2;                     // groups of 16 rows per wave (sharing beta's reads)
+constexpr int RMB = 16 * RMG * (SB / 64);  // rows per block
 __device__ __forceinline__ void rows_mfma_body(int64_t bx, int64_t N, int64_t L, int m,
                                                const double* __restrict__ H, int64_t ldh,
                                                const double* __restrict__ beta, int64_t ldb,
@@ -300,66 +302,89 @@ __device__ __forceinline__ void rows_mfma_body(int64_t bx, int64_t N, int64_t L,
                                                int64_t ldy) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t r0 = bx * RMB + (int64_t)wave * 16;
+    const int64_t r0 = bx * RMB + (int64_t)wave * 16 * RMG;
     if (r0 >= N) return;
     const int q = lane >> 4, c = lane & 15;
-    const double* __restrict__ hrow = H + min(r0 + c, N - 1) * ldh;  // A row: lane % 16
+    const double* __restrict__ hrow[RMG];  // A rows: lane % 16 of each group
+    d4v acc[RMG];
+#pragma unroll
+    for (int g = 0; g < RMG; ++g) {
+        hrow[g] = H + min(r0 + 16 * g + c, N - 1) * ldh;
+        acc[g] = d4v{};
+    }
     const bool cv = c < m;
-    d4v acc = d4v{};
     const int64_t L8 = L & ~(int64_t)7;
     // 16-byte pairs when every row starts 16-byte aligned (block-uniform)
     const bool pairs = ((((uintptr_t)H) | (uintptr_t)(ldh * 8)) & 15) == 0;
     int64_t k = 0;
     if (pairs) {
-#pragma unroll 4
+#pragma unroll 2
         for (; k < L8; k += 8) {
-            const d2v h = *(const d2v*)(hrow + k + 2 * q);
+            d2v h[RMG];
+#pragma unroll
+            for (int g = 0; g < RMG; ++g) h[g] = *(const d2v*)(hrow[g] + k + 2 * q);
             const double b0 = cv ? beta[(k + 2 * q) * ldb + c] : 0.0;
             const double b1 = cv ? beta[(k + 2 * q + 1) * ldb + c] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h.x, b0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h.y, b1, acc, 0, 0, 0);
+#pragma unroll
+            for (int g = 0; g < RMG; ++g) {
+                acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[g].x, b0, acc[g], 0, 0, 0);
+                acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[g].y, b1, acc[g], 0, 0, 0);
+            }
         }
     } else {
-#pragma unroll 4
+#pragma unroll 2
         for (; k < L8; k += 8) {
-            const double h0 = hrow[k + 2 * q], h1 = hrow[k + 2 * q + 1];
+            double h0[RMG], h1[RMG];
+#pragma unroll
+            for (int g = 0; g < RMG; ++g) {
+                h0[g] = hrow[g][k + 2 * q];
+                h1[g] = hrow[g][k + 2 * q + 1];
+            }
             const double b0 = cv ? beta[(k + 2 * q) * ldb + c] : 0.0;
             const double b1 = cv ? beta[(k + 2 * q + 1) * ldb + c] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h0, b0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h1, b1, acc, 0, 0, 0);
+#pragma unroll
+            for (int g = 0; g < RMG; ++g) {
+                acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(h0[g], b0, acc[g], 0, 0, 0);
+                acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(h1[g], b1, acc[g], 0, 0, 0);
+            }
         }
     }
     if (k < L) {  // the last group, fewer than 8 columns (wave-uniform)
         const int64_t k0 = k + 2 * q, k1 = k0 + 1;
-        const double h0 = k0 < L ? hrow[k0] : 0.0, h1 = k1 < L ? hrow[k1] : 0.0;
         const double b0 = (cv && k0 < L) ? beta[k0 * ldb + c] : 0.0;
         const double b1 = (cv && k1 < L) ? beta[k1 * ldb + c] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h0, b0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(h1, b1, acc, 0, 0, 0);
+#pragma unroll
+        for (int g = 0; g < RMG; ++g) {
+            const double h0 = k0 < L ? hrow[g][k0] : 0.0, h1 = k1 < L ? hrow[g][k1] : 0.0;
+            acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(h0, b0, acc[g], 0, 0, 0);
+            acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(h1, b1, acc[g], 0, 0, 0);
+        }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + Mfma16<double>::row(lane, v);  // column c = lane % 16
-        const double val = acc[v];
-        if (row < N && cv) {
-            if (out) out[row * ldo + c] = sign * val + (T ? T[row * ldt + c] : 0.0);
-            if (y) y[row * ldy + c] = val;
-        }
-        if (labels) {
-            double bv = cv ? val : -INFINITY;
-            int bi = c;
+    for (int g = 0; g < RMG; ++g)
 #pragma unroll
-            for (int o = 8; o > 0; o >>= 1) {
-                const double ov = __shfl_xor(bv, o);
-                const int oi = __shfl_xor(bi, o);
-                if (ov > bv || (ov == bv && oi < bi)) {
-                    bv = ov;
-                    bi = oi;
-                }
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = r0 + 16 * g + Mfma16<double>::row(lane, v);  // column c = lane % 16
+            const double val = acc[g][v];
+            if (row < N && cv) {
+                if (out) out[row * ldo + c] = sign * val + (T ? T[row * ldt + c] : 0.0);
+                if (y) y[row * ldy + c] = val;
             }
-            if (c == 0 && row < N) labels[row] = bi;
+            if (labels) {
+                double bv = cv ? val : -INFINITY;
+                int bi = c;
+#pragma unroll
+                for (int o = 8; o > 0; o >>= 1) {
+                    const double ov = __shfl_xor(bv, o);
+                    const int oi = __shfl_xor(bi, o);
+                    if (ov > bv || (ov == bv && oi < bi)) {
+                        bv = ov;
+                        bi = oi;
+                    }
+                }
+                if (c == 0 && row < N) labels[row] = bi;
+            }
         }
-    }
 }
 
 // columns per thread of cols_dot_kernel: each E value read from LDS serves
