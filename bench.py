@@ -69,6 +69,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def node_major(L, N, dtype, dev):
+    """An L x N node-major copy laid out as the library lays out its own: rows
+    padded to a multiple of 64 elements, so each 64-sample stage of a row the
+    16-bit Gram loads is whole cache lines."""
+    import torch
+    return torch.empty((L, -(-N // 64) * 64), dtype=dtype, device=dev)[:, :N]
+
+
 def cpu_baseline(prob, rows, nodes):
     """The FP64 oracle on a bounded sample of the workload, scaled to
     trainings/s of the full workload:
@@ -199,7 +207,7 @@ def bench_configs(args, elm, torch, wl, dev):
             form = key.split("_")[0]
             greedy = key.endswith("_greedy")
             old_order = elm.set_option("full_rank_min_order", 0) if greedy else None
-            Hlp = None if form == "fp64" else torch.empty((p.L, p.N), dtype=torch.float32, device=dev)
+            Hlp = None if form == "fp64" else node_major(p.L, p.N, torch.float32, dev)
             res = elm.train(X, W, b, T, precision=form, ir_tol=1e-10, H64=H64, Hlp=Hlp, check_convergence=False)
             torch.cuda.synchronize()
             elm.profile_enable(True)
@@ -274,9 +282,7 @@ def run_stage(args):
     p = wl.smooth_regression(N=args.N, L=args.L)
     X, W, b, T = (torch.from_numpy(a).to(dev) for a in (p.X, p.W, p.b, p.T))
     H64 = torch.empty((p.N, p.L), dtype=torch.float64, device=dev)
-    # the BF16 copy with the library's own padding: rows of a multiple of 64
-    # elements, as the training path lays it out
-    Hb = torch.empty((p.L, -(-p.N // 64) * 64), dtype=torch.bfloat16, device=dev)[:, :p.N]
+    Hb = node_major(p.L, p.N, torch.bfloat16, dev)
     elm.elm_hidden(X, W, b, H=H64, Hlp=Hb)
     torch.cuda.synchronize()
 
@@ -389,7 +395,7 @@ def main():
     N, L, m = prob.N, prob.L, prob.m
     lp_dtype = {"bf16": torch.bfloat16, "fp16": torch.float16, "fp32": torch.float32}[args.precision]
     H64 = torch.empty((N, L), dtype=torch.float64, device=dev)
-    Hlp = torch.empty((L, N), dtype=lp_dtype, device=dev)
+    Hlp = node_major(L, N, lp_dtype, dev)
     torch.cuda.synchronize()
 
     def step():
@@ -469,7 +475,7 @@ def main():
     # FP16 form on the same workload (FP16 copy of H in the BF16 copy's memory)
     fp16 = None
     if args.fp16_steps > 0 and args.precision != "fp16":
-        Hh = torch.empty((L, N), dtype=torch.float16, device=dev)
+        Hh = node_major(L, N, torch.float16, dev)
         r16 = elm.train(X, W, b, T, precision="fp16", ir_tol=1e-10, H64=H64, Hlp=Hh, check_convergence=False)
         torch.cuda.synchronize()
         elm.profile_enable(True)

@@ -111,7 +111,11 @@ const char* elm_last_error(const elm_handle* h);
  * H (optional, may be NULL): sample-major N x L of dtype `dt`, ld ldh >= L.
  * Hlp (optional, may be NULL): node-major L x N copy, ld ldlp >= N, of dtype
  *   lp_dt (ELM_BF16, ELM_F16 or ELM_F32), rounded to nearest even from the
- *   same `dt` value written to H.  It feeds the low-precision Gram.
+ *   same `dt` value written to H.  It feeds the low-precision Gram.  With
+ *   ldlp a multiple of 64 elements and Hlp 16-byte aligned (the layout the
+ *   library gives its own copies), every 64-sample stage of a row that the
+ *   16-bit Gram loads is whole 128-byte lines; other leading dimensions give
+ *   the same Gram, about 5% more slowly.
  * At least one of H and Hlp must be non-NULL.  N, d, L >= 1. */
 elm_status elm_hidden(elm_handle* h, int64_t N, int64_t d, int64_t L,
                       const void* X, int64_t ldx, const void* W, int64_t ldw,
@@ -153,7 +157,8 @@ elm_status elm_rank_factor(elm_handle* h, int64_t N, int64_t L,
 /* The Gram step alone (eq. 8): M = H^T H (N >= L) or H H^T (N < L), n x n
  * FP64 with n = min(N, L), written in full (both triangles, exactly
  * symmetric) to the caller's M (ld ldm >= n).  Same accepted inputs and the
- * same kernels as elm_rank_factor; asynchronous. */
+ * same kernels as elm_rank_factor; asynchronous.  A node-major 16-bit H is
+ * read fastest with ldh a multiple of 64 elements (see elm_hidden's Hlp). */
 elm_status elm_gram(elm_handle* h, int64_t N, int64_t L, const void* H, int64_t ldh,
                     elm_dtype h_dt, elm_layout layout, double* M, int64_t ldm);
 
@@ -416,7 +421,8 @@ typedef struct {
  * gram_dt selects the form: ELM_F64 factors the FP64 Gram of H64 (plain form);
  * ELM_F32 / ELM_BF16 / ELM_F16 factor the Gram of a node-major copy of H
  * rounded to that type (precision form), written to Hlp (L x N, ld ldlp >= N,
- * of type gram_dt) or, when Hlp is NULL, to library workspace.  When N < L the
+ * of type gram_dt; a multiple of 64 elements for the fastest Gram, as for
+ * elm_hidden) or, when Hlp is NULL, to library workspace.  When N < L the
  * FP64 form is used whatever gram_dt says (the low-precision Gram needs N >= L).
  * Precision policy: if the rank decision on a low-precision Gram is within its
  * rounding noise (elm_factor_info.reliable = 0) or the refinement does not

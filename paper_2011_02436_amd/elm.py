@@ -649,8 +649,10 @@ def train(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor, T: torch.Tensor, pr
     node-major low-precision copy; the rank decision and the refinement
     residual stay in FP64, and a failed guard moves the Gram one precision
     up).  X, W, b, T must be float64; H64 (N x L float64) and Hlp (L x N of
-    the precision's dtype) may be passed preallocated to keep allocation out
-    of timed regions.  info holds the solve report plus 'factor' (rank
+    the precision's dtype; for the fastest Gram a view of rows padded to a
+    multiple of 64 elements, e.g. torch.empty((L, -(-N // 64) * 64))[:, :N])
+    may be passed preallocated to keep allocation out of timed regions.  info
+    holds the solve report plus 'factor' (rank
     diagnostics), 'gram_dtype', 'escalations' and 'guard'."""
     if precision not in ("fp64", "fp32", "bf16", "fp16"):
         raise ValueError("precision must be one of fp64, fp32, bf16, fp16")
