@@ -263,6 +263,32 @@ def test_gram_lowprec_matches_fp64_of_rounded_input(elm, lp, N, L):
     assert np.array_equal(M[5], M[3])
 
 
+@pytest.mark.parametrize("lp", ["bf16", "fp16"])
+def test_gram_16bit_same_for_every_leading_dimension(elm, lp):
+    """The node-major 16-bit Gram takes 64-sample stages of whole 128-byte
+    lines when rows start on 64-element boundaries, stages that straddle lines
+    when the leading dimension is only a multiple of 8, and 32-sample register
+    steps otherwise; every path multiplies the same 16-sample steps in the same
+    order, so the three layouts of the same values give bitwise-equal Grams
+    (N = 20000: the last split ends in half a stage; L = 600: a ragged last
+    tile)."""
+    N, L = 20000, 600
+    rng = np.random.default_rng(77)
+    dt = {"bf16": torch.bfloat16, "fp16": torch.float16}[lp]
+    vals = to_dev(rng.uniform(0, 1, (L, N))).to(dt)
+    Ms = []
+    for ld in (-(-N // 64) * 64, N, N + 3):
+        assert (ld % 64 == 0) or ld == N or ld % 8 != 0
+        Hn = torch.empty((L, ld), dtype=dt, device=vals.device)[:, :N]
+        Hn.copy_(vals)
+        Ms.append(elm.elm_gram(Hn, "node").cpu().numpy())
+    ref = vals.double().cpu().numpy()
+    ref = ref @ ref.T
+    assert np.max(np.abs(Ms[0] - ref)) <= 2e-6 * np.max(np.abs(ref))
+    assert np.array_equal(Ms[0], Ms[1])
+    assert np.array_equal(Ms[0], Ms[2])
+
+
 def test_predict_hidden_matches_numpy(elm):
     rng = np.random.default_rng(2)
     H = rng.uniform(0, 1, (1000, 130))
