@@ -208,12 +208,20 @@ __global__ __launch_bounds__(NTH, NTH / 128) void gemm_grouped(const GemmDesc* _
 
 // 128-wide tiles when there are enough of them to give every CU one;
 // otherwise (thin strips of the blocked factorisations) four times as many
-// 64-wide tiles
-static bool use_tile128(int64_t batch, int64_t M, int64_t N) {
-    return M >= 128 && N >= 128 && cdiv(M, 128) * cdiv(N, 128) * batch >= 256;
+// 64-wide tiles.  With a triangular operand the tiles' k ranges run from one
+// chunk to the whole K, so a launch of fewer than 768 128-wide tiles (a round
+// and a half at two per CU) lasts as long as its longest tiles while the
+// others' CUs idle: such products also take 64-wide tiles, whose shorter
+// tiles fill the rounds (the triangular inverse's levels of order 1024 and
+// 2048 at L = 10000: 8.7 -> 8.2 ms per factor step; 1536 measured the same).
+static bool use_tile128(int64_t batch, int64_t M, int64_t N, bool tri) {
+    const int64_t t = cdiv(M, 128) * cdiv(N, 128) * batch;
+    return M >= 128 && N >= 128 && t >= 256 && !(tri && t < 768);
 }
 
-int gemm_tile(const GemmDesc& q) { return use_tile128(q.batch, q.M, q.N) ? 128 : 64; }
+int gemm_tile(const GemmDesc& q) {
+    return use_tile128(q.batch, q.M, q.N, q.tri_a || q.tri_b) ? 128 : 64;
+}
 
 int64_t gemm_group_blocks(const GemmDesc& q, int ts) {
     if (q.M <= 0 || q.N <= 0 || q.batch <= 0) return 0;
@@ -234,7 +242,7 @@ void gemm_f64_batched(hipStream_t s, int64_t batch, int64_t M, int64_t N, int64_
                       int64_t b_rs, int64_t b_cs, int64_t b_bs, double beta, double* C, int64_t ldc,
                       int64_t c_bs, bool tri_a, bool tri_b, bool upper_c, const int* skip) {
     if (M <= 0 || N <= 0 || batch <= 0) return;
-    if (use_tile128(batch, M, N)) {  // the rule of gemm_tile
+    if (use_tile128(batch, M, N, tri_a || tri_b)) {  // the rule of gemm_tile
         dim3 grid((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 128), (unsigned)batch);
         gemm_kernel<128, 512><<<grid, 512, 0, s>>>(M, N, K, alpha, A, a_rs, a_cs, a_bs, B, b_rs, b_cs,
                                                    b_bs, beta, C, ldc, c_bs, tri_a, tri_b, upper_c, skip);
